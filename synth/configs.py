@@ -1,0 +1,203 @@
+"""Named synthetic workloads.
+
+Each generator returns a :class:`Workload`: a lattice domain, the bodies to
+release in it, the relaxation time, the characteristic velocity u_max (used
+by the inter-body repulsion), the population precision and the number of
+steps.  Sizes and parameters follow the configurations the build is measured
+on; random draws use ``numpy.random.default_rng(seed)`` in the documented
+order.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .geometry import Domain, bifurcation, periodic_box, pipe
+from .mesh import Body, icosphere
+
+
+@dataclass
+class Workload:
+    name: str
+    domain: Domain
+    bodies: list
+    tau: float
+    u_max: float
+    precision: str          # "f64" | "f32" | "f16s"
+    steps: int
+    meta: dict = field(default_factory=dict)
+
+
+def pipe_sphere(precision="f64", steps=200):
+    """Straight pipe D = 16 on a 48x20x20 grid, tau = 0.8, Poiseuille inlet
+    u_max = 0.05, outlet rho = 1, one rigid icosphere (subdivision 2, 162
+    vertices) of radius 4 released at rest on the axis at x = 12, density
+    ratio 1.1.  No random draws."""
+    tau, u_max = 0.8, 0.05
+    dom = pipe(48, 20, 20, 8.0, u_max=u_max, tau=tau, init="poiseuille")
+    X, F = icosphere(2, 4.0, (12.0, 9.5, 9.5))
+    body = Body(X, F, rigid=True, rho_ratio=1.1, r_ref=4.0, u_ref=u_max)
+    return Workload("pipe_sphere", dom, [body], tau, u_max, precision, steps)
+
+
+def bifurcation_capsule(seed=0, precision="f32", steps=5000, nx=256, ny=128, nz=40,
+                        D=32.0, subdiv=4, occlusion=0.5, ca=0.01):
+    """Symmetric Y-bifurcation, main diameter D = 32, daughters 0.8 D at a
+    60 degree semi-aperture, fillet radius 4, grid 256x128x40, Re = 10 with
+    tau = 0.7 (so u_max = Re*nu/D), one deformable icosphere capsule
+    (subdivision 4, 2562 vertices) at occlusion ratio 0.5 with Ca = 0.01,
+    Eb = 0.001, density ratio 1.1, released at x = 1.16 D with a lateral
+    offset drawn first from U[-0.1 D, 0.1 D]."""
+    rng = np.random.default_rng(seed)
+    tau = 0.7
+    nu = (tau - 0.5) / 3.0
+    u_max = 10.0 * nu / D
+    dom = bifurcation(nx, ny, nz, D, 0.8, 60.0, 4.0, u_max=u_max)
+    rp = occlusion * D / 2.0
+    dy = rng.uniform(-0.1 * D, 0.1 * D)
+    c = (1.16 * D, (ny - 1) / 2.0 + dy, (nz - 1) / 2.0)
+    X, F = icosphere(subdiv, rp, c)
+    body = Body(X, F, rigid=False, ca=ca, eb=0.001, rho_ratio=1.1, r_ref=rp, u_ref=u_max)
+    return Workload("bifurcation_capsule", dom, [body], tau, u_max, precision, steps,
+                    meta={"offset": dy, "seed": seed})
+
+
+def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_choices,
+                    x_inlet_clear, face_clear, u_max, max_tries=100000):
+    """Rejection sampling of non-overlapping capsules inside the fluid.
+    Draw order per capsule: occlusion ratio, log10 Ca, mesh choice, then
+    centre candidates (x, y, z) until one fits."""
+    nx, ny, nz = box
+    bodies, centres, radii = [], [], []
+    tries = 0
+    while len(bodies) < n:
+        occ = rng.uniform(occl_lo, occl_hi)
+        ca = 10.0 ** rng.uniform(np.log10(ca_lo), np.log10(ca_hi))
+        sub = subdiv_choices[rng.integers(len(subdiv_choices))]
+        rp = occ * D / 2.0
+        placed = False
+        while tries < max_tries:
+            tries += 1
+            c = np.array([rng.uniform(x_inlet_clear, nx - 1 - face_clear),
+                          rng.uniform(face_clear, ny - 1 - face_clear),
+                          rng.uniform(0, nz - 1)])
+            if sdf(c[None, :])[0] > -(rp + 1.5):
+                continue
+            if any(np.linalg.norm(c - cc) < rp + rr + 2.0 for cc, rr in zip(centres, radii)):
+                continue
+            placed = True
+            break
+        if not placed:
+            break
+        X, F = icosphere(sub, rp, c)
+        bodies.append(Body(X, F, rigid=False, ca=ca, eb=0.001, rho_ratio=1.1, r_ref=rp, u_ref=u_max))
+        centres.append(c)
+        radii.append(rp)
+    return bodies
+
+
+def precision_form(seed=0, precision="f16s", steps=2000, n_capsules=16):
+    """Bifurcation with a 90 degree semi-aperture on 512x256x64, D = 48,
+    fillet 4, Re = 10 with tau = 0.7, 16 deformable capsules (2562 vertices)
+    with occlusion ratio ~ U[0.3, 0.8] and Ca log-uniform in [1e-3, 1e-1],
+    placed without overlap at least 1 D from the inlet and the outlet faces."""
+    rng = np.random.default_rng(seed)
+    tau = 0.7
+    nu = (tau - 0.5) / 3.0
+    D = 48.0
+    u_max = 10.0 * nu / D
+    dom = bifurcation(512, 256, 64, D, 0.8, 90.0, 4.0, u_max=u_max)
+    bodies = _place_capsules(rng, dom.meta["sdf"], (512, 256, 64), D, n_capsules,
+                             0.3, 0.8, 1e-3, 1e-1, (4,), D, D, u_max)
+    return Workload("precision_form", dom, bodies, tau, u_max, precision, steps,
+                    meta={"seed": seed})
+
+
+def batch_instances(seed=0, n_instances=64):
+    """Independent bifurcation instances of uneven size: per instance, in
+    draw order, D from {16, 24, 32, 48}, semi-aperture U[30, 120] degrees,
+    fillet U[0, 0.25 D], then 1-4 capsules (occlusion U[0.3, 0.9], Ca
+    log-uniform [1e-3, 1e-1], 642 or 2562 vertices) on an 8D x 4D x 1.25D
+    grid, Re = 10, tau = 0.7."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_instances):
+        D = float(rng.choice([16, 24, 32, 48]))
+        th = rng.uniform(30.0, 120.0)
+        fil = rng.uniform(0.0, 0.25 * D)
+        ncap = int(rng.integers(1, 5))
+        nx, ny, nz = int(8 * D), int(4 * D), int(1.25 * D)
+        tau = 0.7
+        nu = (tau - 0.5) / 3.0
+        u_max = 10.0 * nu / D
+        dom = bifurcation(nx, ny, nz, D, 0.8, th, fil, x_junction=4 * D, u_max=u_max)
+        bodies = _place_capsules(rng, dom.meta["sdf"], (nx, ny, nz), D, ncap, 0.3, 0.9,
+                                 1e-3, 1e-1, (3, 4), D, 0.5 * D, u_max)
+        out.append(Workload(f"batch_{k}", dom, bodies, tau, u_max, "f32", 1000,
+                            meta={"D": D, "theta": th, "fillet": fil}))
+    return out
+
+
+def periodic_r0(n=256, precision="f32", steps=100):
+    """All-fluid periodic n^3 box driven by a uniform body force 1e-6 along
+    x, tau = 0.8 (the stream-collide bandwidth ceiling workload)."""
+    dom = periodic_box(n, n, n, body_force=(1e-6, 0.0, 0.0))
+    return Workload(f"periodic_{n}", dom, [], 0.8, 0.0, precision, steps)
+
+
+def pipe_r1(precision="f32", steps=100):
+    """Straight pipe D = 96 in a 768x100x100 box, Poiseuille inlet u_max =
+    0.05, outlet rho = 1, tau = 0.8 (walls + open faces at scale)."""
+    dom = pipe(768, 100, 100, 48.0, u_max=0.05, tau=0.8, init="poiseuille")
+    return Workload("pipe_r1", dom, [], 0.8, 0.05, precision, steps)
+
+
+def tiny_pipe(precision="f64", steps=20, with_body=True, rigid=True, nx=24, ny=12, nz=12,
+              radius=4.5, body_radius=2.5, subdiv=2):
+    """Small pipe for quick parity checks (several tiles, ragged rows)."""
+    tau, u_max = 0.8, 0.05
+    dom = pipe(nx, ny, nz, radius, u_max=u_max, tau=tau, init="poiseuille")
+    bodies = []
+    if with_body:
+        X, F = icosphere(subdiv, body_radius, (7.3, (ny - 1) / 2.0 + 0.21, (nz - 1) / 2.0 - 0.13))
+        bodies.append(Body(X, F, rigid=rigid, ca=0.05, eb=0.001, rho_ratio=1.1,
+                           r_ref=body_radius, u_ref=u_max))
+    return Workload("tiny_pipe", dom, bodies, tau, u_max, precision, steps)
+
+
+def tiny_bifurcation(seed=0, precision="f64", steps=20, n_bodies=1, subdiv=2):
+    """Small Y-bifurcation (D = 12 on 64x40x16, 60 degrees, fillet 2) with
+    one or two deformable capsules; draw order as in bifurcation_capsule."""
+    rng = np.random.default_rng(seed)
+    tau = 0.7
+    nu = (tau - 0.5) / 3.0
+    D = 12.0
+    u_max = 0.02
+    dom = bifurcation(64, 40, 16, D, 0.8, 60.0, 2.0, x_junction=32.0, u_max=u_max)
+    bodies = []
+    for k in range(n_bodies):
+        dy = rng.uniform(-0.1 * D, 0.1 * D)
+        rp = 2.6
+        c = (10.0 + 5.4 * k, 19.5 + dy, 7.5 + (0.3 if k else 0.0))
+        X, F = icosphere(subdiv, rp, c)
+        bodies.append(Body(X, F, rigid=False, ca=0.05, eb=0.001, rho_ratio=1.1, r_ref=rp,
+                           u_ref=u_max))
+    del nu
+    return Workload("tiny_bifurcation", dom, bodies, tau, u_max, precision, steps,
+                    meta={"seed": seed})
+
+
+_REGISTRY = {
+    "pipe_sphere": pipe_sphere,
+    "bifurcation_capsule": bifurcation_capsule,
+    "precision_form": precision_form,
+    "periodic_r0": periodic_r0,
+    "pipe_r1": pipe_r1,
+    "tiny_pipe": tiny_pipe,
+    "tiny_bifurcation": tiny_bifurcation,
+}
+
+
+def get(name, **kw):
+    return _REGISTRY[name](**kw)
