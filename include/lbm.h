@@ -1,0 +1,201 @@
+/*
+ * lbm.h - C interface of the MI355X (gfx950) library for the coupled
+ * lattice-Boltzmann / dynamic immersed-boundary step of Coclite, de Tullio,
+ * Pascazio and Politi, "Characterization of micro-Capsules Deformation in
+ * Branching Channels" (arXiv 2207.06043), Section "Numerical method and
+ * computational procedure".
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice units: dx = dt = 1.  Node (x, y, z) sits at position (x, y, z) and
+ * has the linear index n = x + nx*(y + ny*z) (x fastest); N = nx*ny*nz.
+ * Per-node scalar fields are [N]; per-node vector fields are component-major
+ * [3][N]; populations are [19][N] in the order of the D3Q19 velocity set
+ * printed in the paper's fluid-evolution section (Eq. e_i).  Point lists
+ * (markers, vertices) are [n][3].  All floating-point arguments are double.
+ *
+ * Ownership: every pointer in lbm_desc / lbm_body_desc is host memory that is
+ * copied during the call.  Arguments named d_* are caller-owned device
+ * pointers on the context's device; they must stay valid until the work the
+ * call enqueued on the context's stream has completed.  The library never
+ * frees or retains them.
+ *
+ * Errors: every call returns an lbm_status and never throws.
+ * lbm_last_error() gives a message for the last failure on a context.  A HIP
+ * runtime failure is sticky: the call returns LBM_E_HIP and every later call
+ * on the context returns LBM_E_STATE.  LBM_E_UNSTABLE and LBM_E_DAMAGED are
+ * reported by lbm_sync() (and the calls that synchronise) once the device
+ * has seen them; the state is then left at the last completed step and
+ * further steps do nothing.
+ *
+ * Threads: one context per host thread; no internal locking.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVAL = 1,       /* bad argument, size, geometry or mesh            */
+  LBM_E_NOMEM = 2,       /* device or host allocation failed               */
+  LBM_E_HIP = 3,         /* HIP runtime error (sticky)                      */
+  LBM_E_UNSTABLE = 4,    /* |u| > 0.3 or NaN in the fluid or a body         */
+  LBM_E_DAMAGED = 5,     /* a membrane link reached twice its rest length   */
+  LBM_E_STATE = 6,       /* context unusable after an earlier HIP error     */
+  LBM_E_UNSUPPORTED = 7  /* feature not available in this build            */
+} lbm_status;
+
+typedef enum {
+  LBM_F64 = 0,  /* populations stored and collided in double                  */
+  LBM_F32 = 1,  /* populations stored as float deviations f_i - w_i, float math */
+  LBM_F16S = 2  /* populations stored as half deviations f_i - w_i, float math  */
+} lbm_precision;
+
+enum { LBM_NODE_FLUID = 0, LBM_NODE_SOLID = 1, LBM_NODE_INLET = 2, LBM_NODE_OUTLET = 3 };
+
+/* The fluid problem (sections "Fluid evolution", "Dirichlet conditions for
+ * external boundaries" and "No-slip boundary conditions for stationary
+ * immersed boundaries").
+ *  node_type [N]: LBM_NODE_*.  INLET nodes carry a velocity Dirichlet
+ *    condition, OUTLET nodes a density Dirichlet condition (Zou-He); both
+ *    must lie on exactly one non-periodic face of the box.  Every other
+ *    non-solid node must have all its neighbours inside the box (or across
+ *    a periodic face).
+ *  Wall links (link_node[k], link_dir[k], link_q[k]): link_node + e_dir is a
+ *    solid node and the wall crosses that link at fraction q in [0, 1]
+ *    (Eq. qbouzidi).  Every solid neighbour of a non-solid node needs one.
+ *  inlet_u [n_inlet][3]: wall velocity of the INLET nodes in increasing
+ *    linear index order.  outlet_rho: density imposed on OUTLET nodes.
+ *  init_rho [N], init_u [3][N]: initial fields (NULL: rho = 1, u = 0); the
+ *    populations start at the equilibrium (Eq. eqfunc) of these fields.
+ *  tau > 1/2: BGK relaxation time (nu = (tau - 1/2)/3).
+ *  body_force [3]: uniform force density added to the immersed-boundary
+ *    force on every non-solid node (Eq. forcing).
+ *  u_max: characteristic flow velocity used by the inter-body repulsion
+ *    (Eq. collision). */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t periodic[3];
+  double tau;
+  double u_max;
+  double body_force[3];
+  int32_t precision; /* lbm_precision */
+  const uint8_t *node_type;
+  int64_t n_links;
+  const int64_t *link_node;
+  const uint8_t *link_dir;
+  const double *link_q;
+  const double *inlet_u;
+  double outlet_rho;
+  const double *init_rho;
+  const double *init_u;
+} lbm_desc;
+
+/* A capsule (section "Immersed-Structure Transport"): a closed triangle mesh
+ * with counter-clockwise faces seen from outside.  Its face centroids are
+ * the Lagrangian markers of the direct forcing.
+ *  rigid: Newton-Euler motion of the whole body; fixed: held at rest.
+ *  ca: capillary number Ca = rho nu u_ref / k_s0 (rho = 1) giving the
+ *    membrane modulus; eb: bending number Eb = k_b / (k_s,l r_ref^2);
+ *  kv: volume-penalty constant (<= 0: 10 k_s0 / r_ref);
+ *  rho_ratio: solid-to-fluid density ratio (mass = rho_ratio * enclosed volume);
+ *  v0 [nv][3]: initial vertex velocities (NULL: at rest). */
+typedef struct {
+  int32_t nv, nf;
+  const double *x;
+  const int32_t *faces;
+  int32_t rigid, fixed;
+  double ca, eb, kv, rho_ratio, r_ref, u_ref;
+  const double *v0;
+} lbm_body_desc;
+
+/* Sizes and counters of a context. */
+typedef struct {
+  int64_t n_nodes, n_fluid, n_bulk, n_general, n_links;
+  int64_t n_bodies, n_vertices, n_faces;
+  int64_t steps_done;
+  int64_t bytes_per_step_alg;   /* 2 * 19 * sizeof(stored population) * n_fluid */
+  int32_t precision;
+  int32_t mls_singular;         /* markers whose moment matrix was singular */
+} lbm_info_t;
+
+/* Create a context on the current HIP device; work is enqueued on
+ * hip_stream (a hipStream_t; NULL = the default stream).  Validates the
+ * geometry (LBM_E_INVAL with a message on failure). */
+lbm_status lbm_create(const lbm_desc *desc, void *hip_stream, lbm_ctx **out);
+lbm_status lbm_destroy(lbm_ctx *ctx);
+const char *lbm_last_error(const lbm_ctx *ctx);
+lbm_status lbm_info(lbm_ctx *ctx, lbm_info_t *out);
+
+/* Add a capsule (host data copied).  Rest lengths, areas, angles and volume
+ * are taken from the given positions.  LBM_E_INVAL for an open or
+ * inconsistently oriented mesh. */
+lbm_status lbm_add_body(lbm_ctx *ctx, const lbm_body_desc *body, int32_t *body_id);
+
+/* Advance n_steps coupled steps (asynchronous on the context's stream):
+ * streaming with interpolated bounce-back and Zou-He, dynamic-IB direct
+ * forcing, forced BGK collision, membrane and hydrodynamic forces, body
+ * motion.  The step is replayed from a captured HIP graph. */
+lbm_status lbm_step(lbm_ctx *ctx, int32_t n_steps);
+
+/* Wait for the context's stream and report LBM_E_UNSTABLE / LBM_E_DAMAGED
+ * if the device raised them. */
+lbm_status lbm_sync(lbm_ctx *ctx);
+
+/* Macroscopic fields of the last completed step: d_rho [N], d_u [3][N]
+ * (u = (sum f e + F/2)/rho with the step's total force F); solid nodes 0. */
+lbm_status lbm_get_fields(lbm_ctx *ctx, double *d_rho, double *d_u);
+/* Post-collision populations [19][N] (solid nodes 0). */
+lbm_status lbm_get_populations(lbm_ctx *ctx, double *d_f);
+/* Immersed-boundary force density [3][N] of the last completed step. */
+lbm_status lbm_get_force(lbm_ctx *ctx, double *d_fib);
+/* Vertex positions and velocities [nv][3] of a body. */
+lbm_status lbm_get_body(lbm_ctx *ctx, int32_t body_id, double *d_x, double *d_v);
+
+/* Moving-least-squares interpolation (Eqs. uLag, l2norm, intKernel) of the
+ * vector field d_field [3][N] at n points d_pts [n][3] into d_u [n][3].
+ * d_field = NULL interpolates the fluid velocity of the last completed step.
+ * Support: the 3x3x3 nodes around the nearest node, solid nodes and nodes
+ * outside a non-periodic face excluded.  A point whose support is
+ * degenerate gets 0. */
+lbm_status ib_interpolate(lbm_ctx *ctx, int64_t n, const double *d_pts, const double *d_field,
+                          double *d_u);
+
+/* Spreading (Eq. bodyforce): d_fib [3][N] += sum_l c_l phi_k^l F_l for the
+ * n points d_pts [n][3] with forces d_F [n][3] and weights d_c [n].  The sum
+ * is accumulated in 64-bit fixed point (2^-52), so it is bitwise
+ * reproducible whatever the thread order. */
+lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double *d_F,
+                     const double *d_c, double *d_fib);
+
+/* Discrete adjoint of the step: not available in this build
+ * (LBM_E_UNSUPPORTED). */
+lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t n_steps, const double *d_dJ_dstate,
+                            double *d_grad_params);
+
+/* Checkpoint / restart of the full state (populations, force field, body
+ * state) to a binary file; lbm_load requires a context created with the
+ * same geometry and bodies. */
+lbm_status lbm_save(lbm_ctx *ctx, const char *path);
+lbm_status lbm_load(lbm_ctx *ctx, const char *path);
+
+/* Timing support: average duration in milliseconds of the fused
+ * stream-collide kernel over n_steps full steps, measured with HIP events
+ * around each launch on the context's stream (the steps are launched one
+ * kernel at a time instead of from the graph). */
+lbm_status lbm_time_fluid_kernel(lbm_ctx *ctx, int32_t n_steps, double *avg_ms);
+
+/* Replay steps from captured HIP graphs (default 1) or launch kernels one by one (0). */
+lbm_status lbm_set_graph(lbm_ctx *ctx, int32_t enable);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

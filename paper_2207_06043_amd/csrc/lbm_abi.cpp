@@ -1,0 +1,1064 @@
+// Host side of the C ABI declared in include/lbm.h: validation, node
+// classification, boundary records, body set-up, graph capture and the
+// ABI entry points.  All per-step arithmetic runs in lbm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+// D3Q19 velocity set (order of the paper's Eq. e_i).
+const int HX[19] = {0, 1, -1, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0};
+const int HY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1};
+const int HZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, -1};
+const int HOPP[19] = {0, 2, 1, 4, 3, 6, 5, 12, 11, 14, 13, 8, 7, 10, 9, 18, 17, 16, 15};
+
+struct HostBody {
+  int nv, nf, rigid, fixed;
+  std::vector<double> x0, v0;
+  std::vector<int> faces;  // local ids
+  std::vector<int> edges;  // local ids [ne][2]
+  std::vector<double> l0, kl;
+  std::vector<int> hinges;  // local [nh][4]
+  std::vector<double> theta0, kb;
+  double V0, S0, ks0, kv, m_v, mass;
+  double cm[3], Ibody[9];
+  std::vector<double> Xbody;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  std::string err;
+  bool broken = false;
+  Grid g{};
+  int prec = 0;
+  size_t ssize = 8;
+  double tau = 0.8, umax = 0.0, gfx = 0, gfy = 0, gfz = 0;
+  int64_t n_fluid = 0, n_bulk = 0, n_general = 0, n_links = 0;
+  // fluid device state
+  void* f[2] = {nullptr, nullptr};
+  uint8_t* ncls = nullptr;
+  int32_t* rec_of = nullptr;
+  int nrec = 0;
+  int32_t* rec_node = nullptr;
+  uint32_t* rec_mask = nullptr;
+  int32_t* rec_link0 = nullptr;
+  uint8_t* rec_face = nullptr;
+  double* rec_bc = nullptr;
+  uint8_t* lk_dm = nullptr;
+  double* lk_q = nullptr;
+  int32_t* tile_list = nullptr;
+  int nbulk_blocks = 0;
+  long long ntiles = 0;
+  long long* fx[2] = {nullptr, nullptr};
+  uint8_t* tf[2] = {nullptr, nullptr};
+  long long* fx_api = nullptr;
+  DevFlags* flags = nullptr;  // followed by the block counter
+  // bodies
+  std::vector<HostBody> bodies;
+  int nv = 0, nf = 0, ne = 0, nh = 0, nsoft_v = 0;
+  std::vector<void*> bod_alloc;
+  BodyArgs bargs[2]{};
+  double* X[2] = {nullptr, nullptr};
+  double* Vel = nullptr;
+  int32_t* base[2] = {nullptr, nullptr};
+  double* b_rig = nullptr;
+  double* b_diag = nullptr;
+  // graphs
+  bool use_graph = true;
+  bool graph_valid = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int64_t enq = 0;
+};
+
+#define CHK(expr)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ctx->broken = true;                                                            \
+      ctx->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " + #expr; \
+      return LBM_E_HIP;                                                              \
+    }                                                                                \
+  } while (0)
+
+static lbm_status fail(lbm_ctx* ctx, lbm_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+template <class T>
+static hipError_t dalloc(T** p, size_t n) {
+  if (n == 0) n = 1;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+template <class T>
+static hipError_t upload(T** p, const std::vector<T>& v) {
+  hipError_t e = dalloc(p, v.size());
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+static void free_graphs(lbm_ctx* ctx) {
+  for (int p = 0; p < 2; p++)
+    if (ctx->gexec[p]) {
+      (void)hipGraphExecDestroy(ctx->gexec[p]);
+      ctx->gexec[p] = nullptr;
+    }
+  ctx->graph_valid = false;
+}
+
+static void free_bodies(lbm_ctx* ctx) {
+  for (void* p : ctx->bod_alloc) (void)hipFree(p);
+  ctx->bod_alloc.clear();
+}
+
+// ------------------------------------------------------------------ create
+extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** out) {
+  if (!out) return LBM_E_INVAL;
+  *out = nullptr;
+  if (!d || !d->node_type) return LBM_E_INVAL;
+  lbm_ctx* ctx = new lbm_ctx();
+  auto bad = [&](const std::string& m) {
+    *out = ctx;  // hand back the context so the caller can read the message
+    return fail(ctx, LBM_E_INVAL, m);
+  };
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return bad("grid sizes must be >= 1");
+  if (!(d->tau > 0.5)) return bad("tau must be > 1/2");
+  if (d->precision < 0 || d->precision > 2) return bad("unknown precision");
+  if ((long long)d->nx * d->ny * d->nz > (1LL << 31) - (1LL << 20)) return bad("grid too large");
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->prec = d->precision;
+  ctx->ssize = d->precision == 0 ? 8 : (d->precision == 1 ? 4 : 2);
+  ctx->tau = d->tau;
+  ctx->umax = d->u_max;
+  ctx->gfx = d->body_force[0];
+  ctx->gfy = d->body_force[1];
+  ctx->gfz = d->body_force[2];
+  Grid& G = ctx->g;
+  G.nx = d->nx;
+  G.ny = d->ny;
+  G.nz = d->nz;
+  for (int a = 0; a < 3; a++) G.per[a] = d->periodic[a] ? 1 : 0;
+  G.px = (d->nx + 7) / 8 * 8;
+  G.Np = (long long)G.px * G.ny * G.nz;
+  G.plane = (G.Np + 64 + 63) / 64 * 64;
+  const long long N = (long long)d->nx * d->ny * d->nz;
+  const int nx = d->nx, ny = d->ny, nz = d->nz;
+  auto lin = [&](int x, int y, int z) { return x + (long long)nx * (y + (long long)ny * z); };
+  auto pad = [&](int x, int y, int z) { return x + (long long)G.px * (y + (long long)G.ny * z); };
+  const int dim[3] = {nx, ny, nz};
+  // neighbour with periodic wrap; false if it leaves through a closed face
+  auto nb = [&](int x, int y, int z, int dx, int dy, int dz, int* c) {
+    c[0] = x + dx;
+    c[1] = y + dy;
+    c[2] = z + dz;
+    for (int a = 0; a < 3; a++) {
+      if (c[a] < 0 || c[a] >= dim[a]) {
+        if (!G.per[a]) return false;
+        c[a] = ((c[a] % dim[a]) + dim[a]) % dim[a];
+      }
+    }
+    return true;
+  };
+  const uint8_t* nt = d->node_type;
+  for (long long n = 0; n < N; n++)
+    if (nt[n] > 3) return bad("node_type values must be 0..3");
+  // wall links, keyed by (node, pulled direction j = opposite of the link direction)
+  std::map<std::pair<long long, int>, double> links;
+  for (int64_t k = 0; k < d->n_links; k++) {
+    const long long n = d->link_node[k];
+    const int i = d->link_dir[k];
+    const double q = d->link_q[k];
+    if (n < 0 || n >= N || i < 1 || i > 18 || !(q >= 0.0 && q <= 1.0))
+      return bad("wall link " + std::to_string(k) + " out of range");
+    if (nt[n] == LBM_NODE_SOLID) return bad("wall link " + std::to_string(k) + " starts on a solid node");
+    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((long long)nx * ny));
+    int c[3];
+    if (!nb(x, y, z, HX[i], HY[i], HZ[i], c) || nt[lin(c[0], c[1], c[2])] != LBM_NODE_SOLID)
+      return bad("wall link " + std::to_string(k) + " does not point at a solid node");
+    if (!links.emplace(std::make_pair(n, HOPP[i]), q).second)
+      return bad("duplicate wall link " + std::to_string(k));
+  }
+  ctx->n_links = d->n_links;
+  // classify
+  std::vector<uint8_t> ncls(G.Np, CLS_SOLID);
+  std::vector<int32_t> rec_of(G.Np, -1);
+  std::vector<int32_t> r_node;
+  std::vector<uint32_t> r_mask;
+  std::vector<int32_t> r_link0;
+  std::vector<uint8_t> r_face;
+  std::vector<double> r_bc;  // 4 per record, transposed later
+  std::vector<uint8_t> l_dm;
+  std::vector<double> l_q;
+  long long n_inlet_seen = 0;
+  for (int z = 0; z < nz; z++)
+    for (int y = 0; y < ny; y++)
+      for (int x = 0; x < nx; x++) {
+        const long long n = lin(x, y, z);
+        const uint8_t t = nt[n];
+        if (t == LBM_NODE_SOLID) continue;
+        ctx->n_fluid++;
+        const bool open = t == LBM_NODE_INLET || t == LBM_NODE_OUTLET;
+        int face = -1, nfaces = 0;
+        const int cc[3] = {x, y, z};
+        for (int a = 0; a < 3; a++) {
+          if (G.per[a]) continue;
+          if (cc[a] == 0) { face = 2 * a; nfaces++; }
+          if (cc[a] == dim[a] - 1) { face = 2 * a + 1; nfaces++; }
+        }
+        if (open && nfaces != 1)
+          return bad("open node " + std::to_string(n) + " must lie on exactly one non-periodic face");
+        bool general = open;
+        uint32_t mask = 0;
+        for (int j = 1; j < 19; j++) {
+          int c[3];
+          const bool in = nb(x, y, z, -HX[j], -HY[j], -HZ[j], c);
+          if (!in) {
+            if (!open) return bad("fluid node " + std::to_string(n) + " on a closed box face");
+            continue;
+          }
+          const bool wrapped = (c[0] != x - HX[j]) || (c[1] != y - HY[j]) || (c[2] != z - HZ[j]);
+          if (wrapped) general = true;
+          if (nt[lin(c[0], c[1], c[2])] == LBM_NODE_SOLID) {
+            if (!links.count(std::make_pair(n, j)))
+              return bad("node " + std::to_string(n) + " has a solid neighbour in direction " +
+                         std::to_string(HOPP[j]) + " without a wall link");
+            mask |= 1u << j;
+            general = true;
+          }
+        }
+        const long long p = pad(x, y, z);
+        if (!general) {
+          ncls[p] = CLS_BULK;
+          ctx->n_bulk++;
+          continue;
+        }
+        ncls[p] = CLS_GENERAL;
+        ctx->n_general++;
+        rec_of[p] = (int32_t)r_node.size();
+        r_node.push_back((int32_t)p);
+        r_mask.push_back(mask);
+        r_link0.push_back((int32_t)l_q.size());
+        uint8_t fc = 0xff;
+        double bc[4] = {0, 0, 0, 0};
+        if (open) {
+          fc = (uint8_t)(face | (t == LBM_NODE_OUTLET ? 0x10 : 0));
+          if (t == LBM_NODE_INLET) {
+            if (d->inlet_u)
+              for (int a = 0; a < 3; a++) bc[a] = d->inlet_u[3 * n_inlet_seen + a];
+            n_inlet_seen++;
+          } else {
+            bc[3] = d->outlet_rho;
+          }
+        }
+        r_face.push_back(fc);
+        for (int a = 0; a < 4; a++) r_bc.push_back(bc[a]);
+        for (int j = 1; j < 19; j++) {
+          if (!(mask & (1u << j))) continue;
+          const double q = links[std::make_pair(n, j)];
+          // availability of x - e_i = x + e_j and x - 2e_i = x + 2e_j (i = opposite of j)
+          int c1[3], c2[3];
+          const bool a1 = nb(x, y, z, HX[j], HY[j], HZ[j], c1) && nt[lin(c1[0], c1[1], c1[2])] != LBM_NODE_SOLID;
+          const bool a2 = nb(x, y, z, 2 * HX[j], 2 * HY[j], 2 * HZ[j], c2) &&
+                          nt[lin(c2[0], c2[1], c2[2])] != LBM_NODE_SOLID;
+          uint8_t mode;
+          if (q < 0.5) mode = (a1 && a2) ? BFL_QUAD_LO : (a1 ? BFL_LIN_LO : BFL_BB);
+          else mode = a1 ? BFL_QUAD_HI : BFL_LIN_HI;
+          l_dm.push_back((uint8_t)(j | (mode << 5)));
+          l_q.push_back(q);
+        }
+      }
+  for (const auto& kv : links)
+    if (!(nt[kv.first.first] != LBM_NODE_SOLID)) return bad("wall link on a solid node");
+  ctx->nrec = (int)r_node.size();
+  std::vector<double> bcT(4 * (size_t)ctx->nrec);
+  for (int r = 0; r < ctx->nrec; r++)
+    for (int a = 0; a < 4; a++) bcT[(size_t)a * ctx->nrec + r] = r_bc[4 * (size_t)r + a];
+  // bulk tiles: blocks of 256 threads x V nodes holding at least one bulk node
+  const int V = ctx->prec == 0 ? 2 : (ctx->prec == 1 ? 4 : 8);
+  const long long tnodes = 256LL * V;
+  std::vector<int32_t> tiles;
+  for (long long t = 0; t * tnodes < G.Np; t++) {
+    bool any = false;
+    for (long long k = t * tnodes; k < std::min(G.Np, (t + 1) * tnodes) && !any; k++)
+      any = ncls[k] == CLS_BULK;
+    if (any) tiles.push_back((int32_t)t);
+  }
+  ctx->nbulk_blocks = (int)tiles.size();
+  ctx->ntiles = (G.Np >> TILE_SHIFT) + 1;
+  // device allocations
+  CHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+  const size_t fbytes = (size_t)19 * G.plane * ctx->ssize;
+  for (int p = 0; p < 2; p++) {
+    CHK(hipMalloc(&ctx->f[p], fbytes));
+    CHK(hipMemset(ctx->f[p], 0, fbytes));
+  }
+  CHK(upload(&ctx->ncls, ncls));
+  CHK(upload(&ctx->rec_of, rec_of));
+  CHK(upload(&ctx->rec_node, r_node));
+  CHK(upload(&ctx->rec_mask, r_mask));
+  CHK(upload(&ctx->rec_link0, r_link0));
+  CHK(upload(&ctx->rec_face, r_face));
+  CHK(upload(&ctx->rec_bc, bcT));
+  CHK(upload(&ctx->lk_dm, l_dm));
+  CHK(upload(&ctx->lk_q, l_q));
+  CHK(upload(&ctx->tile_list, tiles));
+  CHK(hipMalloc(&ctx->flags, sizeof(DevFlags) + 64));
+  CHK(hipMemset(ctx->flags, 0, sizeof(DevFlags) + 64));
+  // initial populations: equilibrium of the given fields
+  double *drho = nullptr, *du = nullptr;
+  if (d->init_rho) {
+    CHK(hipMalloc(&drho, N * sizeof(double)));
+    CHK(hipMemcpy(drho, d->init_rho, N * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (d->init_u) {
+    CHK(hipMalloc(&du, 3 * N * sizeof(double)));
+    CHK(hipMemcpy(du, d->init_u, 3 * N * sizeof(double), hipMemcpyHostToDevice));
+  }
+  CHK(launch_init(ctx->prec, G, ctx->f[0], ctx->ncls, drho, du, ctx->cap));
+  CHK(hipStreamSynchronize(ctx->cap));
+  if (drho) CHK(hipFree(drho));
+  if (du) CHK(hipFree(du));
+  *out = ctx;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return LBM_OK;
+  (void)hipDeviceSynchronize();
+  free_graphs(ctx);
+  free_bodies(ctx);
+  void* ptrs[] = {ctx->f[0], ctx->f[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
+                  ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_dm, ctx->lk_q,
+                  ctx->tile_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
+                  ctx->flags};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  delete ctx;
+  return LBM_OK;
+}
+
+extern "C" const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static lbm_status read_flags(lbm_ctx* ctx, DevFlags* h) {
+  CHK(hipStreamSynchronize(ctx->stream));
+  CHK(hipMemcpy(h, ctx->flags, sizeof(DevFlags), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_info(lbm_ctx* ctx, lbm_info_t* o) {
+  if (!ctx || !o) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  DevFlags h;
+  lbm_status st = read_flags(ctx, &h);
+  if (st) return st;
+  o->n_nodes = (int64_t)ctx->g.nx * ctx->g.ny * ctx->g.nz;
+  o->n_fluid = ctx->n_fluid;
+  o->n_bulk = ctx->n_bulk;
+  o->n_general = ctx->n_general;
+  o->n_links = ctx->n_links;
+  o->n_bodies = (int64_t)ctx->bodies.size();
+  o->n_vertices = ctx->nv;
+  o->n_faces = ctx->nf;
+  o->steps_done = h.steps_done;
+  o->bytes_per_step_alg = 2 * 19 * (int64_t)ctx->ssize * ctx->n_fluid;
+  o->precision = ctx->prec;
+  o->mls_singular = h.mls_singular;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ bodies
+static void cross(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dihedral_host(const double* X, const int* h) {
+  const double *a = X + 3 * h[0], *b = X + 3 * h[1], *c = X + 3 * h[2], *d = X + 3 * h[3];
+  double e[3], ca[3], ab[3], db[3], n1[3], n2[3], t[3];
+  for (int k = 0; k < 3; k++) {
+    e[k] = b[k] - a[k];
+    ca[k] = c[k] - a[k];
+    ab[k] = a[k] - b[k];
+    db[k] = d[k] - b[k];
+  }
+  cross(e, ca, n1);
+  cross(ab, db, n2);
+  double l1 = std::sqrt(n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+  double l2 = std::sqrt(n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2]);
+  double le = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  for (int k = 0; k < 3; k++) {
+    n1[k] /= l1;
+    n2[k] /= l2;
+  }
+  cross(n1, n2, t);
+  return std::atan2((t[0] * e[0] + t[1] * e[1] + t[2] * e[2]) / le,
+                    n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2]);
+}
+
+static double tri_area(const double* X, int a, int b, int c) {
+  double u[3], v[3], n[3];
+  for (int k = 0; k < 3; k++) {
+    u[k] = X[3 * b + k] - X[3 * a + k];
+    v[k] = X[3 * c + k] - X[3 * a + k];
+  }
+  cross(u, v, n);
+  return 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+}
+
+// Upload all bodies (host rest data + current dynamic state) into fresh
+// device arrays; dyn_* hold the dynamic state of the bodies already present.
+static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<double>& Xc,
+                                    const std::vector<double>& Xp, const std::vector<double>& Vl,
+                                    const std::vector<double>& rig, const std::vector<int32_t>& b_other,
+                                    const std::vector<int32_t>& b_last) {
+  free_bodies(ctx);
+  const int nb = (int)ctx->bodies.size();
+  std::vector<int32_t> faces, face_body, vert_body, edges, hinges, soft;
+  std::vector<double> l0, kl, th0, kb, Xbody, param(8 * (size_t)nb + 9 * (size_t)nb);
+  std::vector<int32_t> bf0, bnf, bv0, bnv, be0, bne, brig, bfix;
+  int v0 = 0, f0 = 0, e0 = 0;
+  for (int b = 0; b < nb; b++) {
+    const HostBody& B = ctx->bodies[b];
+    bf0.push_back(f0);
+    bnf.push_back(B.nf);
+    bv0.push_back(v0);
+    bnv.push_back(B.nv);
+    be0.push_back(e0);
+    bne.push_back((int)B.l0.size());
+    brig.push_back(B.rigid || B.fixed);
+    bfix.push_back(B.fixed);
+    for (int k = 0; k < 3 * B.nf; k++) faces.push_back(B.faces[k] + v0);
+    for (int f = 0; f < B.nf; f++) face_body.push_back(b);
+    for (int v = 0; v < B.nv; v++) {
+      vert_body.push_back(b);
+      if (!(B.rigid || B.fixed)) soft.push_back(v0 + v);
+    }
+    for (size_t k = 0; k < B.edges.size(); k++) edges.push_back(B.edges[k] + v0);
+    for (size_t k = 0; k < B.hinges.size(); k++) hinges.push_back(B.hinges[k] + v0);
+    l0.insert(l0.end(), B.l0.begin(), B.l0.end());
+    kl.insert(kl.end(), B.kl.begin(), B.kl.end());
+    th0.insert(th0.end(), B.theta0.begin(), B.theta0.end());
+    kb.insert(kb.end(), B.kb.begin(), B.kb.end());
+    Xbody.insert(Xbody.end(), B.Xbody.begin(), B.Xbody.end());
+    double* pp = param.data() + 8 * b;
+    pp[0] = B.V0;
+    pp[1] = B.S0;
+    pp[2] = B.kv;
+    pp[3] = B.m_v;
+    pp[4] = B.mass;
+    pp[5] = B.ks0;
+    for (int k = 0; k < 9; k++) param[8 * (size_t)nb + 9 * b + k] = B.Ibody[k];
+    v0 += B.nv;
+    f0 += B.nf;
+    e0 += (int)B.l0.size();
+  }
+  ctx->nv = v0;
+  ctx->nf = f0;
+  ctx->ne = e0;
+  ctx->nh = e0;
+  ctx->nsoft_v = (int)soft.size();
+  // incidence CSR
+  std::vector<std::vector<int32_t>> ve(v0), vh(v0), vf(v0);
+  for (int e = 0; e < e0; e++) {
+    ve[edges[2 * e]].push_back(e);
+    ve[edges[2 * e + 1]].push_back(e);
+  }
+  for (int h = 0; h < e0; h++)
+    for (int r = 0; r < 4; r++) vh[hinges[4 * h + r]].push_back(4 * h + r);
+  for (int f = 0; f < f0; f++)
+    for (int r = 0; r < 3; r++) vf[faces[3 * f + r]].push_back(f);
+  auto csr = [&](const std::vector<std::vector<int32_t>>& L, std::vector<int32_t>& ptr,
+                 std::vector<int32_t>& idx) {
+    ptr.assign(1, 0);
+    for (const auto& l : L) {
+      idx.insert(idx.end(), l.begin(), l.end());
+      ptr.push_back((int32_t)idx.size());
+    }
+  };
+  std::vector<int32_t> veP, veI, vhP, vhI, vfP, vfI;
+  csr(ve, veP, veI);
+  csr(vh, vhP, vhI);
+  csr(vf, vfP, vfI);
+  auto up = [&](auto** p, const auto& v) -> hipError_t {
+    hipError_t e = upload(p, v);
+    ctx->bod_alloc.push_back((void*)*p);
+    return e;
+  };
+  BodyArgs B{};
+  B.nbody = nb;
+  B.nv = v0;
+  B.nf = f0;
+  B.ne = e0;
+  B.nh = e0;
+  B.nsoft_v = ctx->nsoft_v;
+  int32_t *d_soft, *d_faces, *d_fb, *d_vb, *d_edges, *d_hinges, *d_veP, *d_veI, *d_vhP, *d_vhI,
+      *d_vfP, *d_vfI, *d_bf0, *d_bnf, *d_bv0, *d_bnv, *d_be0, *d_bne, *d_brig, *d_bfix;
+  double *d_l0, *d_kl, *d_th0, *d_kb, *d_param, *d_Xbody;
+  CHK(up(&d_soft, soft));
+  CHK(up(&d_faces, faces));
+  CHK(up(&d_fb, face_body));
+  CHK(up(&d_vb, vert_body));
+  CHK(up(&d_edges, edges));
+  CHK(up(&d_hinges, hinges));
+  CHK(up(&d_veP, veP));
+  CHK(up(&d_veI, veI));
+  CHK(up(&d_vhP, vhP));
+  CHK(up(&d_vhI, vhI));
+  CHK(up(&d_vfP, vfP));
+  CHK(up(&d_vfI, vfI));
+  CHK(up(&d_bf0, bf0));
+  CHK(up(&d_bnf, bnf));
+  CHK(up(&d_bv0, bv0));
+  CHK(up(&d_bnv, bnv));
+  CHK(up(&d_be0, be0));
+  CHK(up(&d_bne, bne));
+  CHK(up(&d_brig, brig));
+  CHK(up(&d_bfix, bfix));
+  CHK(up(&d_l0, l0));
+  CHK(up(&d_kl, kl));
+  CHK(up(&d_th0, th0));
+  CHK(up(&d_kb, kb));
+  CHK(up(&d_param, param));
+  CHK(up(&d_Xbody, Xbody));
+  // dynamic state
+  std::vector<double> X0(Xc), X1(Xp);
+  CHK(up(&ctx->X[cur], X0));
+  CHK(up(&ctx->X[cur ^ 1], X1));
+  CHK(up(&ctx->Vel, Vl));
+  CHK(up(&ctx->b_rig, rig));
+  std::vector<double> diag(16 * (size_t)nb, 0.0);
+  CHK(up(&ctx->b_diag, diag));
+  // the next step has parity cur: it writes base[cur] and clears the spread
+  // of the last completed step, whose stencil bases are in base[cur ^ 1]
+  CHK(up(&ctx->base[cur ^ 1], b_last));
+  CHK(up(&ctx->base[cur], b_other));
+  std::vector<double> zf(3 * (size_t)f0, 0.0), zv(3 * (size_t)v0, 0.0);
+  double *d_cen, *d_fext, *d_u0v;
+  CHK(up(&d_cen, zf));
+  CHK(up(&d_fext, zf));
+  CHK(up(&d_u0v, zv));
+  B.soft_vlist = d_soft;
+  B.Vel = ctx->Vel;
+  B.faces = d_faces;
+  B.face_body = d_fb;
+  B.vert_body = d_vb;
+  B.edges = d_edges;
+  B.l0 = d_l0;
+  B.kl = d_kl;
+  B.hinges = d_hinges;
+  B.theta0 = d_th0;
+  B.kb = d_kb;
+  B.ve_ptr = d_veP;
+  B.ve_idx = d_veI;
+  B.vh_ptr = d_vhP;
+  B.vh_idx = d_vhI;
+  B.vf_ptr = d_vfP;
+  B.vf_idx = d_vfI;
+  B.b_face0 = d_bf0;
+  B.b_nf = d_bnf;
+  B.b_vert0 = d_bv0;
+  B.b_nv = d_bnv;
+  B.b_edge0 = d_be0;
+  B.b_ne = d_bne;
+  B.b_rigid = d_brig;
+  B.b_fixed = d_bfix;
+  B.b_param = d_param;
+  B.b_rig = ctx->b_rig;
+  B.Xbody = d_Xbody;
+  B.b_diag = ctx->b_diag;
+  B.centroid = d_cen;
+  B.fext = d_fext;
+  B.u0v = d_u0v;
+  B.nu = (ctx->tau - 0.5) / 3.0;
+  B.umax = ctx->umax;
+  for (int p = 0; p < 2; p++) {
+    ctx->bargs[p] = B;
+    ctx->bargs[p].Xcur = ctx->X[p];
+    ctx->bargs[p].Xnext = ctx->X[p ^ 1];
+    ctx->bargs[p].base_cur = ctx->base[p];
+    ctx->bargs[p].base_prev = ctx->base[p ^ 1];
+  }
+  // force buffers (once)
+  if (!ctx->fx[0]) {
+    const size_t fxb = 3 * (size_t)ctx->g.Np * sizeof(long long);
+    for (int p = 0; p < 2; p++) {
+      CHK(hipMalloc(&ctx->fx[p], fxb));
+      CHK(hipMemset(ctx->fx[p], 0, fxb));
+      CHK(hipMalloc(&ctx->tf[p], ctx->ntiles));
+      CHK(hipMemset(ctx->tf[p], 0, ctx->ntiles));
+    }
+  }
+  // diagnostics of the current positions (no step counted)
+  CHK(launch_end(ctx->bargs[cur], ctx->X[cur], ctx->flags, 0, ctx->stream));
+  CHK(hipStreamSynchronize(ctx->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_add_body(lbm_ctx* ctx, const lbm_body_desc* bd, int32_t* body_id) {
+  if (!ctx || !bd) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (bd->nv < 4 || bd->nf < 4 || !bd->x || !bd->faces) return fail(ctx, LBM_E_INVAL, "mesh too small");
+  HostBody B;
+  B.nv = bd->nv;
+  B.nf = bd->nf;
+  B.rigid = bd->rigid || bd->fixed;
+  B.fixed = bd->fixed ? 1 : 0;
+  B.x0.assign(bd->x, bd->x + 3 * (size_t)bd->nv);
+  B.faces.assign(bd->faces, bd->faces + 3 * (size_t)bd->nf);
+  for (int k = 0; k < 3 * bd->nf; k++)
+    if (B.faces[k] < 0 || B.faces[k] >= bd->nv) return fail(ctx, LBM_E_INVAL, "face index out of range");
+  // closed, consistently oriented: each directed edge once, with its reverse
+  std::map<std::pair<int, int>, int> dir_edge;  // (a, b) -> face
+  for (int f = 0; f < bd->nf; f++)
+    for (int k = 0; k < 3; k++) {
+      const int a = B.faces[3 * f + k], b = B.faces[3 * f + (k + 1) % 3];
+      if (a == b) return fail(ctx, LBM_E_INVAL, "degenerate face");
+      if (!dir_edge.emplace(std::make_pair(a, b), f).second)
+        return fail(ctx, LBM_E_INVAL, "mesh is not consistently oriented");
+    }
+  std::vector<double> Af(bd->nf);
+  for (int f = 0; f < bd->nf; f++) Af[f] = tri_area(bd->x, B.faces[3 * f], B.faces[3 * f + 1], B.faces[3 * f + 2]);
+  double V0 = 0.0, S0 = 0.0;
+  for (int f = 0; f < bd->nf; f++) {
+    const double *a = bd->x + 3 * B.faces[3 * f], *b = bd->x + 3 * B.faces[3 * f + 1], *c = bd->x + 3 * B.faces[3 * f + 2];
+    double bc[3];
+    cross(b, c, bc);
+    V0 += (a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2]) / 6.0;
+    S0 += Af[f];
+  }
+  if (!(V0 > 0.0)) return fail(ctx, LBM_E_INVAL, "mesh encloses no volume (inward faces?)");
+  const double nu = (ctx->tau - 0.5) / 3.0;
+  B.ks0 = bd->ca > 0.0 ? nu * bd->u_ref / bd->ca : 0.0;
+  B.kv = bd->kv > 0.0 ? bd->kv : 10.0 * B.ks0 / bd->r_ref;
+  B.V0 = V0;
+  B.S0 = S0;
+  B.mass = bd->rho_ratio * V0;
+  B.m_v = B.mass / bd->nv;
+  for (const auto& kv : dir_edge) {
+    const int a = kv.first.first, b = kv.first.second;
+    auto it = dir_edge.find(std::make_pair(b, a));
+    if (it == dir_edge.end()) return fail(ctx, LBM_E_INVAL, "mesh is not closed");
+    if (a > b) continue;  // each undirected edge once, oriented as in its first face
+    const int f1 = kv.second, f2 = it->second;
+    int c = -1, d = -1;
+    for (int k = 0; k < 3; k++) {
+      if (B.faces[3 * f1 + k] != a && B.faces[3 * f1 + k] != b) c = B.faces[3 * f1 + k];
+      if (B.faces[3 * f2 + k] != a && B.faces[3 * f2 + k] != b) d = B.faces[3 * f2 + k];
+    }
+    B.edges.push_back(a);
+    B.edges.push_back(b);
+    const double* xa = bd->x + 3 * a;
+    const double* xb = bd->x + 3 * b;
+    const double l = std::sqrt((xa[0] - xb[0]) * (xa[0] - xb[0]) + (xa[1] - xb[1]) * (xa[1] - xb[1]) +
+                               (xa[2] - xb[2]) * (xa[2] - xb[2]));
+    B.l0.push_back(l);
+    // k_s,l = k_s0 T (A1 + A2) / l0^2 with T = 1
+    const double k = B.ks0 * (Af[f1] + Af[f2]) / (l * l);
+    B.kl.push_back(k);
+    const int h[4] = {a, b, c, d};
+    for (int r = 0; r < 4; r++) B.hinges.push_back(h[r]);
+    B.theta0.push_back(dihedral_host(bd->x, h));
+    B.kb.push_back(bd->eb * k * bd->r_ref * bd->r_ref);
+  }
+  // centre of mass and inertia of the enclosed uniform solid (rigid bodies)
+  {
+    double vol = 0.0, cm[3] = {0, 0, 0}, C[9] = {0};
+    for (int f = 0; f < bd->nf; f++) {
+      const double* P[3] = {bd->x + 3 * B.faces[3 * f], bd->x + 3 * B.faces[3 * f + 1],
+                            bd->x + 3 * B.faces[3 * f + 2]};
+      double bc[3];
+      cross(P[1], P[2], bc);
+      const double vt = (P[0][0] * bc[0] + P[0][1] * bc[1] + P[0][2] * bc[2]) / 6.0;
+      vol += vt;
+      for (int a = 0; a < 3; a++) cm[a] += vt * (P[0][a] + P[1][a] + P[2][a]) / 4.0;
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          double sp = 0, si = 0, sj = 0;
+          for (int k = 0; k < 3; k++) {
+            sp += P[k][i] * P[k][j];
+            si += P[k][i];
+            sj += P[k][j];
+          }
+          C[3 * i + j] += vt / 20.0 * (sp + si * sj);
+        }
+    }
+    for (int a = 0; a < 3; a++) cm[a] /= vol;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) C[3 * i + j] -= vol * cm[i] * cm[j];
+    const double tr = C[0] + C[4] + C[8];
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) B.Ibody[3 * i + j] = bd->rho_ratio * ((i == j ? tr : 0.0) - C[3 * i + j]);
+    for (int a = 0; a < 3; a++) B.cm[a] = cm[a];
+    B.Xbody.resize(3 * (size_t)bd->nv);
+    for (int v = 0; v < bd->nv; v++)
+      for (int a = 0; a < 3; a++) B.Xbody[3 * v + a] = bd->x[3 * v + a] - cm[a];
+  }
+  // current dynamic state of the existing bodies
+  DevFlags h;
+  lbm_status st = read_flags(ctx, &h);
+  if (st) return st;
+  const int cur = (int)(h.steps_done & 1);
+  const int nb_old = (int)ctx->bodies.size();
+  std::vector<double> Xc(3 * (size_t)ctx->nv), Xp(3 * (size_t)ctx->nv), Vl(3 * (size_t)ctx->nv),
+      rig(32 * (size_t)nb_old);
+  std::vector<int32_t> bprev(3 * (size_t)ctx->nf), blast(3 * (size_t)ctx->nf);
+  if (nb_old > 0) {
+    CHK(hipMemcpy(Xc.data(), ctx->X[cur], Xc.size() * 8, hipMemcpyDeviceToHost));
+    CHK(hipMemcpy(Xp.data(), ctx->X[cur ^ 1], Xp.size() * 8, hipMemcpyDeviceToHost));
+    CHK(hipMemcpy(Vl.data(), ctx->Vel, Vl.size() * 8, hipMemcpyDeviceToHost));
+    CHK(hipMemcpy(rig.data(), ctx->b_rig, rig.size() * 8, hipMemcpyDeviceToHost));
+    // base[cur^1] was written by the last completed step (parity cur^1)
+    CHK(hipMemcpy(blast.data(), ctx->base[cur ^ 1], blast.size() * 4, hipMemcpyDeviceToHost));
+    CHK(hipMemcpy(bprev.data(), ctx->base[cur], bprev.size() * 4, hipMemcpyDeviceToHost));
+  }
+  // append the new body: x^n = x, x^{n-1} = x - v0 (soft), velocities v0
+  std::vector<double> v0(3 * (size_t)bd->nv, 0.0);
+  if (bd->v0 && !bd->fixed) v0.assign(bd->v0, bd->v0 + 3 * (size_t)bd->nv);
+  double rs[32] = {0};
+  for (int a = 0; a < 3; a++) rs[a] = B.cm[a];
+  rs[15] = rs[19] = rs[23] = 1.0;
+  if (B.rigid && !B.fixed && bd->v0) {
+    for (int a = 0; a < 3; a++) {
+      double m = 0.0;
+      for (int v = 0; v < bd->nv; v++) m += v0[3 * v + a];
+      rs[3 + a] = rs[6 + a] = m / bd->nv;
+    }
+    for (int v = 0; v < bd->nv; v++)
+      for (int a = 0; a < 3; a++) v0[3 * v + a] = rs[3 + a];
+  }
+  for (int v = 0; v < bd->nv; v++)
+    for (int a = 0; a < 3; a++) {
+      Xc.push_back(bd->x[3 * v + a]);
+      Xp.push_back(bd->x[3 * v + a] - (B.rigid ? 0.0 : v0[3 * v + a]));
+      Vl.push_back(v0[3 * v + a]);
+    }
+  rig.insert(rig.end(), rs, rs + 32);
+  for (int k = 0; k < 3 * bd->nf; k++) {
+    bprev.push_back(INT_MIN);
+    blast.push_back(INT_MIN);
+  }
+  ctx->bodies.push_back(std::move(B));
+  free_graphs(ctx);
+  st = build_body_arrays(ctx, cur, Xc, Xp, Vl, rig, bprev, blast);
+  if (st) return st;
+  if (body_id) *body_id = (int32_t)ctx->bodies.size() - 1;
+  return LBM_OK;
+}
+
+// -------------------------------------------------------------------- step
+static FluidArgs fluid_args(lbm_ctx* ctx, int p) {
+  FluidArgs a{};
+  a.g = ctx->g;
+  a.A = ctx->f[p];
+  a.B = ctx->f[p ^ 1];
+  a.ncls = ctx->ncls;
+  a.rec_of = ctx->rec_of;
+  a.nrec = ctx->nrec;
+  a.rec_node = ctx->rec_node;
+  a.rec_mask = ctx->rec_mask;
+  a.rec_link0 = ctx->rec_link0;
+  a.rec_face = ctx->rec_face;
+  a.rec_bc = ctx->rec_bc;
+  a.lk_dm = ctx->lk_dm;
+  a.lk_q = ctx->lk_q;
+  a.tile_list = ctx->tile_list;
+  a.nbulk_blocks = ctx->nbulk_blocks;
+  a.omega = 1.0 / ctx->tau;
+  a.gx = ctx->gfx;
+  a.gy = ctx->gfy;
+  a.gz = ctx->gfz;
+  const bool ib = ctx->nf > 0;
+  a.fx = ib ? ctx->fx[p] : nullptr;
+  a.tflag = ib ? ctx->tf[p] : nullptr;
+  a.flags = ctx->flags;
+  return a;
+}
+
+static BodyArgs empty_body_args() {
+  BodyArgs b{};
+  return b;
+}
+
+// The launches of one step of parity p; if ev is given, HIP events bracket
+// the fused stream-collide kernel.
+static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  hipError_t e;
+  const FluidArgs a = fluid_args(ctx, p);
+  const bool ib = ctx->nf > 0;
+  const BodyArgs b = ib ? ctx->bargs[p] : empty_body_args();
+  if (ib) {
+    e = launch_ib_force(ctx->prec, a, b, ctx->fx[p], ctx->tf[p], ctx->fx[p ^ 1], ctx->tf[p ^ 1], s);
+    if (e != hipSuccess) return e;
+  }
+  if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
+  if ((e = launch_fluid(ctx->prec, a, s)) != hipSuccess) return e;
+  if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
+  if (ib) {
+    if ((e = launch_mls_post(ctx->prec, a, b, s)) != hipSuccess) return e;
+    if ((e = launch_body_post(b, ctx->flags, s)) != hipSuccess) return e;
+  }
+  return launch_end(b, ib ? ctx->X[p ^ 1] : nullptr, ctx->flags, 1, s);
+}
+
+static lbm_status build_graphs(lbm_ctx* ctx) {
+  free_graphs(ctx);
+  for (int p = 0; p < 2; p++) {
+    hipGraph_t g;
+    CHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_step(ctx, p, ctx->cap, nullptr, nullptr);
+    hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
+    CHK(e);
+    CHK(e2);
+    CHK(hipGraphInstantiate(&ctx->gexec[p], g, nullptr, nullptr, 0));
+    CHK(hipGraphDestroy(g));
+  }
+  ctx->graph_valid = true;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_ctx* ctx, int32_t n) {
+  if (!ctx || n < 0) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (ctx->use_graph && !ctx->graph_valid) {
+    lbm_status st = build_graphs(ctx);
+    if (st) return st;
+  }
+  for (int32_t k = 0; k < n; k++) {
+    const int p = (int)(ctx->enq & 1);
+    if (ctx->use_graph) CHK(hipGraphLaunch(ctx->gexec[p], ctx->stream));
+    else CHK(enqueue_step(ctx, p, ctx->stream, nullptr, nullptr));
+    ctx->enq++;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_graph(lbm_ctx* ctx, int32_t enable) {
+  if (!ctx) return LBM_E_INVAL;
+  ctx->use_graph = enable != 0;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_sync(lbm_ctx* ctx) {
+  if (!ctx) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  DevFlags h;
+  lbm_status st = read_flags(ctx, &h);
+  if (st) return st;
+  // the host's step counter follows the device once it has stopped
+  if (h.stop & ST_DAMAGED) return fail(ctx, LBM_E_DAMAGED, "a membrane link reached twice its rest length");
+  if (h.stop & ST_UNSTABLE) return fail(ctx, LBM_E_UNSTABLE, "|u| > 0.3 or NaN");
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_time_fluid_kernel(lbm_ctx* ctx, int32_t n, double* avg_ms) {
+  if (!ctx || n <= 0 || !avg_ms) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  std::vector<hipEvent_t> e0(n), e1(n);
+  for (int k = 0; k < n; k++) {
+    CHK(hipEventCreate(&e0[k]));
+    CHK(hipEventCreate(&e1[k]));
+  }
+  for (int k = 0; k < n; k++) {
+    const int p = (int)(ctx->enq & 1);
+    CHK(enqueue_step(ctx, p, ctx->stream, e0[k], e1[k]));
+    ctx->enq++;
+  }
+  CHK(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (int k = 0; k < n; k++) {
+    float ms = 0.f;
+    CHK(hipEventElapsedTime(&ms, e0[k], e1[k]));
+    tot += ms;
+    CHK(hipEventDestroy(e0[k]));
+    CHK(hipEventDestroy(e1[k]));
+  }
+  *avg_ms = tot / n;
+  return LBM_OK;
+}
+
+// ----------------------------------------------------------------- outputs
+static lbm_status fields_common(lbm_ctx* ctx, double* rho, double* u, double* pops, double* fib) {
+  if (!ctx) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  CHK(launch_get_fields(ctx->prec, ctx->g, ctx->f[0], ctx->f[1], ctx->ncls, ctx->fx[0], ctx->fx[1],
+                        ctx->tf[0], ctx->tf[1], ctx->gfx, ctx->gfy, ctx->gfz, ctx->flags, rho, u, pops,
+                        fib, ctx->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_fields(lbm_ctx* ctx, double* d_rho, double* d_u) {
+  return fields_common(ctx, d_rho, d_u, nullptr, nullptr);
+}
+extern "C" lbm_status lbm_get_populations(lbm_ctx* ctx, double* d_f) {
+  if (!d_f) return LBM_E_INVAL;
+  return fields_common(ctx, nullptr, nullptr, d_f, nullptr);
+}
+extern "C" lbm_status lbm_get_force(lbm_ctx* ctx, double* d_fib) {
+  if (!d_fib) return LBM_E_INVAL;
+  return fields_common(ctx, nullptr, nullptr, nullptr, d_fib);
+}
+
+extern "C" lbm_status lbm_get_body(lbm_ctx* ctx, int32_t id, double* d_x, double* d_v) {
+  if (!ctx) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (id < 0 || id >= (int)ctx->bodies.size()) return fail(ctx, LBM_E_INVAL, "no such body");
+  DevFlags h;
+  lbm_status st = read_flags(ctx, &h);
+  if (st) return st;
+  const int cur = (int)(h.steps_done & 1);
+  int v0 = 0;
+  for (int b = 0; b < id; b++) v0 += ctx->bodies[b].nv;
+  const size_t bytes = 3 * sizeof(double) * ctx->bodies[id].nv;
+  if (d_x) CHK(hipMemcpyAsync(d_x, ctx->X[cur] + 3 * (size_t)v0, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (d_v) CHK(hipMemcpyAsync(d_v, ctx->Vel + 3 * (size_t)v0, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status ib_interpolate(lbm_ctx* ctx, int64_t n, const double* d_pts,
+                                     const double* d_field, double* d_u) {
+  if (!ctx || n < 0 || (n > 0 && (!d_pts || !d_u))) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  CHK(launch_interp(ctx->prec, ctx->g, ctx->f[0], ctx->f[1], ctx->ncls, ctx->fx[0], ctx->fx[1],
+                    ctx->tf[0], ctx->tf[1], ctx->gfx, ctx->gfy, ctx->gfz, ctx->flags, n, d_pts,
+                    d_field, d_u, ctx->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status ib_spread(lbm_ctx* ctx, int64_t n, const double* d_pts, const double* d_F,
+                                const double* d_c, double* d_fib) {
+  if (!ctx || n < 0 || !d_fib || (n > 0 && (!d_pts || !d_F || !d_c))) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (!ctx->fx_api) {
+    const size_t b = 3 * (size_t)ctx->g.Np * sizeof(long long);
+    CHK(hipMalloc(&ctx->fx_api, b));
+    CHK(hipMemset(ctx->fx_api, 0, b));
+  }
+  CHK(launch_spread_api(ctx->g, ctx->ncls, n, d_pts, d_F, d_c, ctx->fx_api, ctx->flags, ctx->stream));
+  CHK(launch_flush_fx(ctx->g, ctx->fx_api, d_fib, ctx->stream));
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t, const double*, double*) {
+  if (!ctx) return LBM_E_INVAL;
+  return fail(ctx, LBM_E_UNSUPPORTED, "the discrete adjoint is not available in this build");
+}
+
+// ------------------------------------------------------- checkpoint / restart
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int32_t nx, ny, nz, prec, nbody, nv, nf, pad;
+  int64_t steps_done;
+};
+}  // namespace
+
+extern "C" lbm_status lbm_save(lbm_ctx* ctx, const char* path) {
+  if (!ctx || !path) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  DevFlags h;
+  lbm_status st = read_flags(ctx, &h);
+  if (st) return st;
+  CkptHeader hd{};
+  memcpy(hd.magic, "LBMIB01", 8);
+  hd.nx = ctx->g.nx;
+  hd.ny = ctx->g.ny;
+  hd.nz = ctx->g.nz;
+  hd.prec = ctx->prec;
+  hd.nbody = (int)ctx->bodies.size();
+  hd.nv = ctx->nv;
+  hd.nf = ctx->nf;
+  hd.steps_done = h.steps_done;
+  FILE* fp = fopen(path, "wb");
+  if (!fp) return fail(ctx, LBM_E_INVAL, std::string("cannot open ") + path);
+  fwrite(&hd, sizeof hd, 1, fp);
+  fwrite(&h, sizeof h, 1, fp);
+  auto dump = [&](const void* d, size_t bytes) -> hipError_t {
+    std::vector<char> buf(bytes);
+    hipError_t e = hipMemcpy(buf.data(), d, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) fwrite(buf.data(), 1, bytes, fp);
+    return e;
+  };
+  const size_t fbytes = (size_t)19 * ctx->g.plane * ctx->ssize;
+  hipError_t e = hipSuccess;
+  for (int p = 0; p < 2 && e == hipSuccess; p++) e = dump(ctx->f[p], fbytes);
+  if (e == hipSuccess && ctx->nf > 0) {
+    const size_t fxb = 3 * (size_t)ctx->g.Np * sizeof(long long);
+    for (int p = 0; p < 2 && e == hipSuccess; p++) {
+      e = dump(ctx->fx[p], fxb);
+      if (e == hipSuccess) e = dump(ctx->tf[p], ctx->ntiles);
+      if (e == hipSuccess) e = dump(ctx->X[p], 3 * sizeof(double) * ctx->nv);
+      if (e == hipSuccess) e = dump(ctx->base[p], 3 * sizeof(int32_t) * ctx->nf);
+    }
+    if (e == hipSuccess) e = dump(ctx->Vel, 3 * sizeof(double) * ctx->nv);
+    if (e == hipSuccess) e = dump(ctx->b_rig, 32 * sizeof(double) * ctx->bodies.size());
+    if (e == hipSuccess) e = dump(ctx->b_diag, 16 * sizeof(double) * ctx->bodies.size());
+  }
+  fclose(fp);
+  CHK(e);
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_load(lbm_ctx* ctx, const char* path) {
+  if (!ctx || !path) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  CHK(hipStreamSynchronize(ctx->stream));
+  FILE* fp = fopen(path, "rb");
+  if (!fp) return fail(ctx, LBM_E_INVAL, std::string("cannot open ") + path);
+  CkptHeader hd{};
+  DevFlags h{};
+  bool ok = fread(&hd, sizeof hd, 1, fp) == 1 && fread(&h, sizeof h, 1, fp) == 1;
+  ok = ok && memcmp(hd.magic, "LBMIB01", 8) == 0 && hd.nx == ctx->g.nx && hd.ny == ctx->g.ny &&
+       hd.nz == ctx->g.nz && hd.prec == ctx->prec && hd.nbody == (int)ctx->bodies.size() &&
+       hd.nv == ctx->nv && hd.nf == ctx->nf;
+  if (!ok) {
+    fclose(fp);
+    return fail(ctx, LBM_E_INVAL, "checkpoint does not match this context");
+  }
+  auto load = [&](void* d, size_t bytes) -> hipError_t {
+    std::vector<char> buf(bytes);
+    if (fread(buf.data(), 1, bytes, fp) != bytes) return hipErrorInvalidValue;
+    return hipMemcpy(d, buf.data(), bytes, hipMemcpyHostToDevice);
+  };
+  const size_t fbytes = (size_t)19 * ctx->g.plane * ctx->ssize;
+  hipError_t e = hipSuccess;
+  for (int p = 0; p < 2 && e == hipSuccess; p++) e = load(ctx->f[p], fbytes);
+  if (e == hipSuccess && ctx->nf > 0) {
+    const size_t fxb = 3 * (size_t)ctx->g.Np * sizeof(long long);
+    for (int p = 0; p < 2 && e == hipSuccess; p++) {
+      e = load(ctx->fx[p], fxb);
+      if (e == hipSuccess) e = load(ctx->tf[p], ctx->ntiles);
+      if (e == hipSuccess) e = load(ctx->X[p], 3 * sizeof(double) * ctx->nv);
+      if (e == hipSuccess) e = load(ctx->base[p], 3 * sizeof(int32_t) * ctx->nf);
+    }
+    if (e == hipSuccess) e = load(ctx->Vel, 3 * sizeof(double) * ctx->nv);
+    if (e == hipSuccess) e = load(ctx->b_rig, 32 * sizeof(double) * ctx->bodies.size());
+    if (e == hipSuccess) e = load(ctx->b_diag, 16 * sizeof(double) * ctx->bodies.size());
+  }
+  fclose(fp);
+  if (e == hipErrorInvalidValue) return fail(ctx, LBM_E_INVAL, "truncated checkpoint");
+  CHK(e);
+  CHK(hipMemcpy(ctx->flags, &h, sizeof h, hipMemcpyHostToDevice));
+  ctx->enq = h.steps_done;
+  return LBM_OK;
+}

@@ -1,0 +1,136 @@
+// Internal declarations shared by the host side (lbm_abi.cpp) and the
+// kernels (lbm_kernels.hip) of the gfx950 library.  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Node classes used by the fused stream-collide kernel.
+enum : uint8_t { CLS_SOLID = 0, CLS_BULK = 1, CLS_GENERAL = 2 };
+
+// Wall-link interpolation modes, chosen on the host from q and from which of
+// x - e_i, x - 2 e_i are fluid (i = link direction into the wall).
+enum : uint8_t {
+  BFL_QUAD_LO = 1,  // q < 1/2, quadratic through x, x - e_i, x - 2e_i
+  BFL_LIN_LO = 2,   // q < 1/2, x - 2e_i unavailable: linear
+  BFL_BB = 3,       // q < 1/2, x - e_i unavailable: plain bounce-back
+  BFL_QUAD_HI = 4,  // q >= 1/2, quadratic (needs x - e_i)
+  BFL_LIN_HI = 5    // q >= 1/2, x - e_i unavailable: linear
+};
+
+// Status bits raised on the device.
+enum : uint32_t { ST_UNSTABLE = 1u, ST_DAMAGED = 2u };
+
+// Fixed-point scale of the spread force: 2^52 (range +-2048 per node).
+constexpr double FX_SCALE = 4503599627370496.0;
+constexpr double FX_INV = 1.0 / 4503599627370496.0;
+
+constexpr int TILE_SHIFT = 10;  // force-flag granularity: 1024 nodes
+
+struct DevFlags {
+  uint32_t stop;      // sticky stop bits (checked at every kernel entry)
+  uint32_t pending;   // bits raised during the current step
+  uint32_t overflow;  // a single spread contribution exceeded +-1
+  uint32_t pad;
+  long long steps_done;
+  int mls_singular;
+  int pad2;
+};
+
+struct Grid {
+  int nx, ny, nz;  // logical sizes
+  int px;          // padded row pitch (multiple of 8)
+  int per[3];
+  long long Np;    // px*ny*nz
+  long long plane; // distance between population planes (elements)
+};
+
+// Everything the fluid and IB kernels need (passed by value).
+struct FluidArgs {
+  Grid g;
+  const void* A;  // populations read this step
+  void* B;        // populations written this step
+  const uint8_t* ncls;
+  const int32_t* rec_of;     // [Np] -> record or -1
+  int nrec;
+  const int32_t* rec_node;   // padded index
+  const uint32_t* rec_mask;  // bit j: pulled direction j comes from a wall link
+  const int32_t* rec_link0;
+  const uint8_t* rec_face;   // 0xff: none; else face | (kind << 4) (kind 1 = density)
+  const double* rec_bc;      // [4][nrec]: ux, uy, uz, rho
+  const uint8_t* lk_dm;      // dir | mode << 5
+  const double* lk_q;
+  const int32_t* tile_list;  // blocks of the bulk part
+  int nbulk_blocks;
+  double omega;              // 1/tau
+  double gx, gy, gz;         // uniform body force
+  const long long* fx;       // fixed-point IB force [3][Np] of this step (may be null)
+  const uint8_t* tflag;      // tile flags of this step (may be null)
+  DevFlags* flags;
+};
+
+// Bodies (all concatenated).
+struct BodyArgs {
+  int nbody, nv, nf, ne, nh;
+  int nsoft_v;                 // number of soft vertices
+  const int32_t* soft_vlist;   // [nsoft_v] global vertex ids of soft bodies
+  const double* Xcur;          // [nv][3] x^n
+  double* Xnext;               // [nv][3] x^{n+1} (holds x^{n-1} on entry)
+  double* Vel;                 // [nv][3]
+  const int32_t* faces;        // [nf][3] global vertex ids
+  const int32_t* face_body;    // [nf]
+  const int32_t* vert_body;    // [nv]
+  const int32_t* edges;        // [ne][2]
+  const double* l0;            // [ne]
+  const double* kl;            // [ne]
+  const int32_t* hinges;       // [nh][4]
+  const double* theta0;        // [nh]
+  const double* kb;            // [nh]
+  // vertex incidence CSR
+  const int32_t* ve_ptr; const int32_t* ve_idx;   // edges
+  const int32_t* vh_ptr; const int32_t* vh_idx;   // hinge*4 + role
+  const int32_t* vf_ptr; const int32_t* vf_idx;   // faces
+  // per body tables
+  const int32_t* b_face0; const int32_t* b_nf;
+  const int32_t* b_vert0; const int32_t* b_nv;
+  const int32_t* b_edge0; const int32_t* b_ne;
+  const int32_t* b_rigid; const int32_t* b_fixed;
+  const double* b_param;       // [nbody][8]: V0, S0, kv, m_v, mass, ks0, unused...
+  double* b_rig;               // [nbody][32]: xc3 u3 uprev3 w3 wprev3 R9 Ibody9 (rigid state)
+  const double* Xbody;         // [nv][3] body-frame offsets (rigid)
+  double* b_diag;              // [nbody][16]: V S bbox(6) max_strain ...
+  // per face / vertex work arrays
+  double* centroid;            // [nf][3]
+  double* fext;                // [nf][3] hydrodynamic + repulsion force
+  double* u0v;                 // [nv][3] interpolated velocity at vertices
+  int32_t* base_cur;           // [nf][3] stencil base written this step
+  const int32_t* base_prev;    // [nf][3] stencil base of the previous step
+  double nu, umax;
+};
+
+// Launchers (lbm_kernels.hip)
+hipError_t launch_init(int prec, const Grid& g, void* f, const uint8_t* ncls, const double* rho,
+                       const double* u, hipStream_t s);
+hipError_t launch_fluid(int prec, const FluidArgs& a, hipStream_t s);
+hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fx_cur,
+                           uint8_t* tf_cur, long long* fx_prev, uint8_t* tf_prev, hipStream_t s);
+hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s);
+hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s);
+hipError_t launch_end(const BodyArgs& b, const double* X, DevFlags* flags, int count, hipStream_t s);
+hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,
+                             const uint8_t* ncls, const long long* fx0, const long long* fx1,
+                             const uint8_t* tf0, const uint8_t* tf1, double gx, double gy,
+                             double gz, const DevFlags* flags, double* rho, double* u,
+                             double* pops, double* fib, hipStream_t s);
+hipError_t launch_interp(int prec, const Grid& g, const void* f0, const void* f1,
+                         const uint8_t* ncls, const long long* fx0, const long long* fx1,
+                         const uint8_t* tf0, const uint8_t* tf1, double gx, double gy, double gz,
+                         const DevFlags* flags, long long n, const double* pts,
+                         const double* field, double* out, hipStream_t s);
+hipError_t launch_spread_api(const Grid& g, const uint8_t* ncls, long long n, const double* pts,
+                             const double* F, const double* c, long long* fx, DevFlags* flags,
+                             hipStream_t s);
+hipError_t launch_flush_fx(const Grid& g, long long* fx, double* fib, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Error measures (relative to the oracle):
+  e_u = max |u_gpu - u_orc| / max |u_orc|       (all non-solid nodes)
+  e_x = max |x_gpu - x_orc| / max |x_orc^N - x_orc^0|   (vertex positions)
+Bounds: 1e-12 for the FP64 path, 2e-5 for the FP32 path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2207_06043_amd as P
+    P.load_library()
+    return P
+
+
+def _run_pair(P, w, precision, steps, bodies=True):
+    _say(f"[parity] {w.name} {precision} steps={steps} bodies={len(w.bodies) if bodies else 0}")
+    lat = P.from_workload(w, precision=precision, with_bodies=bodies)
+    lat.step(steps)
+    st = lat.sync(raise_on_stop=False)
+    orc = oracle.from_workload(w, with_bodies=bodies)
+    so = orc.step(steps)
+    return lat, orc, st, so
+
+
+def _compare(lat, orc, w, tol, bodies=True):
+    rho_g, u_g = (t.cpu().numpy() for t in lat.fields())
+    rho_o, u_o = orc.fields()
+    fl = w.domain.node_type != 1
+    e_u = np.abs(u_g[:, fl] - u_o[:, fl]).max() / np.abs(u_o[:, fl]).max()
+    e_r = np.abs(rho_g[fl] - rho_o[fl]).max()
+    out = {"e_u": e_u, "e_rho": e_r}
+    if bodies:
+        ex = []
+        for b in range(len(w.bodies)):
+            xg = lat.body(b)[0].cpu().numpy()
+            xo = orc.body(b)[0]
+            disp = np.abs(xo - w.bodies[b].x).max()
+            ex.append(np.abs(xg - xo).max() / max(disp, 1e-300))
+        out["e_x"] = max(ex) if ex else 0.0
+    _say(f"    {out}")
+    assert e_u <= tol, out
+    assert e_r <= tol * 10, out
+    if bodies and w.bodies:
+        assert out["e_x"] <= tol, out
+    return out
+
+
+# ------------------------------------------------------------ fluid only
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_periodic_box_forced(lib, precision):
+    g = (1e-5, -2e-6, 3e-6)
+    d = synth.periodic_box(20, 13, 11, body_force=g)
+    rng = np.random.default_rng(1)
+    d.init_rho = 1 + 0.01 * rng.standard_normal(d.n_nodes)
+    d.init_u = 0.02 * rng.standard_normal(3 * d.n_nodes)
+    w = synth.Workload("periodic_box", d, [], 0.9, 0.0, precision, 7)
+    lat, orc, st, so = _run_pair(lib, w, precision, 7, bodies=False)
+    assert st == 0 and so == 0
+    _compare(lat, orc, w, TOL[precision], bodies=False)
+    fg = lat.populations().cpu().numpy()
+    fo = orc.populations()
+    assert np.abs(fg - fo).max() < (1e-15 if precision == "f64" else 2e-7)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pipe_open_ends_and_curved_walls(lib, precision):
+    w = synth.tiny_pipe(precision=precision, with_body=False)
+    lat, orc, st, so = _run_pair(lib, w, precision, 40, bodies=False)
+    _compare(lat, orc, w, TOL[precision], bodies=False)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_bifurcation_outlets(lib, precision):
+    w = synth.tiny_bifurcation(precision=precision, n_bodies=0)
+    lat, orc, st, so = _run_pair(lib, w, precision, 40, bodies=False)
+    _compare(lat, orc, w, TOL[precision], bodies=False)
+
+
+# ------------------------------------------------------------ with bodies
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pipe_rigid_sphere(lib, precision):
+    w = synth.tiny_pipe(precision=precision, rigid=True)
+    lat, orc, st, so = _run_pair(lib, w, precision, 30)
+    assert st == 0 and so == 0
+    _compare(lat, orc, w, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pipe_soft_capsule(lib, precision):
+    w = synth.tiny_pipe(precision=precision, rigid=False)
+    lat, orc, st, so = _run_pair(lib, w, precision, 30)
+    assert st == 0 and so == 0
+    _compare(lat, orc, w, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_bifurcation_two_soft_capsules(lib, precision):
+    w = synth.tiny_bifurcation(precision=precision, n_bodies=2)
+    lat, orc, st, so = _run_pair(lib, w, precision, 30)
+    assert st == 0 and so == 0
+    _compare(lat, orc, w, TOL[precision])
+
+
+def test_force_field_matches(lib):
+    w = synth.tiny_pipe(precision="f64", rigid=False)
+    lat, orc, _, _ = _run_pair(lib, w, "f64", 5)
+    fg = lat.force().cpu().numpy()
+    fo = orc.force()
+    assert np.abs(fg - fo).max() <= 1e-12 * np.abs(fo).max()
+
+
+# ------------------------------------------------------ interface operators
+def test_ib_interpolate_and_spread_match_oracle(lib):
+    import torch
+    d = synth.pipe(16, 14, 14, 5.6, periodic_x=True, init="rest")
+    w = synth.Workload("pipe_ops", d, [], 0.8, 0.0, "f64", 0)
+    lat = lib.from_workload(w)
+    orc = oracle.from_workload(w)
+    rng = np.random.default_rng(4)
+    n = 300
+    r = rng.uniform(0, 5.5, n)
+    t = rng.uniform(0, 2 * np.pi, n)
+    pts = np.stack([rng.uniform(-3, 19, n), 6.5 + r * np.cos(t), 6.5 + r * np.sin(t)], 1)
+    field = rng.normal(size=(3, d.n_nodes))
+    _say("[ops] ib_interpolate / ib_spread")
+    ug = lat.ib_interpolate(torch.from_numpy(pts), torch.from_numpy(field)).cpu().numpy()
+    uo = orc.ib_interpolate(pts, field)
+    assert np.abs(ug - uo).max() < 1e-12
+    F = rng.normal(size=(n, 3)) * 1e-3
+    c = rng.uniform(0.1, 1.0, n)
+    fg = lat.ib_spread(torch.from_numpy(pts), torch.from_numpy(F), torch.from_numpy(c)).cpu().numpy()
+    fo = orc.ib_spread(pts, F, c)
+    assert np.abs(fg - fo).max() < 1e-15
+    # the current-velocity path equals interpolating the exported field
+    lat.step(3)
+    lat.sync()
+    _, u = lat.fields()
+    a = lat.ib_interpolate(torch.from_numpy(pts)).cpu().numpy()
+    b = lat.ib_interpolate(torch.from_numpy(pts), u).cpu().numpy()
+    assert np.abs(a - b).max() < 1e-15
+
+
+# --------------------------------------------------------- full config 1
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pipe_sphere_config(lib, precision):
+    """Straight pipe D = 16 on 48x20x20, rigid icosphere (162 vertices), 200 steps."""
+    w = synth.pipe_sphere(precision=precision)
+    lat, orc, st, so = _run_pair(lib, w, precision, w.steps)
+    assert st == 0 and so == 0
+    _compare(lat, orc, w, TOL[precision])
+
+
+# ----------------------------------------------------------- determinism
+def test_bitwise_reproducible_and_graph_equals_eager(lib):
+    w = synth.tiny_bifurcation(precision="f32", n_bodies=2)
+    outs = []
+    for graph in (True, True, False):
+        _say(f"[determinism] graph={graph}")
+        lat = lib.from_workload(w)
+        lat.set_graph(graph)
+        lat.step(15)
+        lat.sync()
+        outs.append((lat.populations().cpu().numpy(), lat.body(0)[0].cpu().numpy(),
+                     lat.force().cpu().numpy()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+# -------------------------------------------------------- failure handling
+def test_damage_stops_on_device(lib):
+    d = synth.pipe(24, 24, 24, 3.0, periodic_x=True, init="rest")
+    X, Fc = synth.icosphere(2, 3.0, (12.0, 4.0, 4.0))
+    v0 = -3.0 * (X - np.array([12.0, 4.0, 4.0]))
+    b = synth.Body(X, Fc, rigid=False, ca=0.05, r_ref=3.0, u_ref=0.02, v0=v0)
+    w = synth.Workload("damage", d, [b], 0.8, 0.02, "f64", 3)
+    _say("[failure] damage")
+    lat = lib.from_workload(w)
+    lat.step(3)
+    assert lat.sync(raise_on_stop=False) == lib.LBM_E_DAMAGED
+    assert lat.info()["steps_done"] == 1
+    x1 = lat.body(0)[0].cpu().numpy()
+    assert np.abs(x1 - (X + 1.5 * (X - [12.0, 4.0, 4.0]))).max() < 1e-12
+    lat.step(2)
+    assert np.array_equal(lat.body(0)[0].cpu().numpy(), x1)
+
+
+def test_unstable_flow_stops_on_device(lib):
+    d = synth.periodic_box(8, 8, 8)
+    d.init_u = np.full(3 * d.n_nodes, 0.4)
+    w = synth.Workload("unstable", d, [], 0.8, 0.0, "f64", 2)
+    _say("[failure] unstable")
+    lat = lib.from_workload(w)
+    lat.step(3)
+    assert lat.sync(raise_on_stop=False) == lib.LBM_E_UNSTABLE
+    assert lat.info()["steps_done"] == 1
+
+
+def test_invalid_geometry_is_rejected(lib):
+    d = synth.pipe(8, 12, 12, 4.0, init="rest")
+    d.node_type = d.node_type.copy()
+    d.node_type[d.node_type == 2] = 0  # inlet nodes retagged as plain fluid on a closed face
+    with pytest.raises(lib.LbmError) as e:
+        lib.Lattice(d, 0.8)
+    assert e.value.status == 1
+
+
+def test_adjoint_reports_unsupported(lib):
+    lat = lib.Lattice(synth.periodic_box(8, 8, 8), 0.8)
+    with pytest.raises(lib.LbmError) as e:
+        lat.adjoint_step(1)
+    assert e.value.status == 7
+
+
+def test_checkpoint_roundtrip(lib, tmp_path):
+    w = synth.tiny_pipe(precision="f32", rigid=False)
+    a = lib.from_workload(w)
+    a.step(6)
+    a.sync()
+    a.save(tmp_path / "ck.bin")
+    a.step(5)
+    a.sync()
+    ref = a.populations().cpu().numpy()
+    b = lib.from_workload(w)
+    b.load(tmp_path / "ck.bin")
+    b.step(5)
+    b.sync()
+    assert np.array_equal(b.populations().cpu().numpy(), ref)
