@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -44,6 +45,8 @@ struct HostBody {
 struct lbm_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
+  hipStream_t side = nullptr;      // boundary-record kernel (forked from the step stream)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   bool broken = false;
   Grid g{};
@@ -52,7 +55,8 @@ struct lbm_ctx {
   double tau = 0.8, umax = 0.0, gfx = 0, gfy = 0, gfz = 0;
   int64_t n_fluid = 0, n_bulk = 0, n_general = 0, n_links = 0;
   // fluid device state
-  void* f[2] = {nullptr, nullptr};
+  void* f[2] = {nullptr, nullptr};        // first element of plane 0
+  void* f_alloc[2] = {nullptr, nullptr};  // allocations (with guard regions)
   uint8_t* ncls = nullptr;
   int32_t* rec_of = nullptr;
   int nrec = 0;
@@ -82,8 +86,9 @@ struct lbm_ctx {
   double* b_diag = nullptr;
   // graphs
   bool use_graph = true;
+  int rec_lanes = 0;
   bool graph_valid = false;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   int64_t enq = 0;
 };
 
@@ -96,6 +101,10 @@ struct lbm_ctx {
       return LBM_E_HIP;                                                              \
     }                                                                                \
   } while (0)
+
+// Block counters live after the flags word: 0 k_ib_force, 1 k_body_post,
+// 2 k_fluid (fluid-only steps), 3 k_check.
+static unsigned int* counter(lbm_ctx* ctx, int k) { return (unsigned int*)(ctx->flags + 1) + k; }
 
 static lbm_status fail(lbm_ctx* ctx, lbm_status st, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -117,7 +126,7 @@ static hipError_t upload(T** p, const std::vector<T>& v) {
 }
 
 static void free_graphs(lbm_ctx* ctx) {
-  for (int p = 0; p < 2; p++)
+  for (int p = 0; p < 3; p++)
     if (ctx->gexec[p]) {
       (void)hipGraphExecDestroy(ctx->gexec[p]);
       ctx->gexec[p] = nullptr;
@@ -146,6 +155,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   if ((long long)d->nx * d->ny * d->nz > (1LL << 31) - (1LL << 20)) return bad("grid too large");
   ctx->stream = (hipStream_t)hip_stream;
   ctx->prec = d->precision;
+  if (const char* ev = getenv("LBM_RECORD_LANES")) ctx->rec_lanes = atoi(ev) != 0;
   ctx->ssize = d->precision == 0 ? 8 : (d->precision == 1 ? 4 : 2);
   ctx->tau = d->tau;
   ctx->umax = d->u_max;
@@ -160,6 +170,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   G.px = (d->nx + 7) / 8 * 8;
   G.Np = (long long)G.px * G.ny * G.nz;
   G.plane = (G.Np + 64 + 63) / 64 * 64;
+  G.guard = ((long long)G.px * G.ny + G.px + 16 + 63) / 64 * 64;
   const long long N = (long long)d->nx * d->ny * d->nz;
   const int nx = d->nx, ny = d->ny, nz = d->nz;
   auto lin = [&](int x, int y, int z) { return x + (long long)nx * (y + (long long)ny * z); };
@@ -235,8 +246,6 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
             if (!open) return bad("fluid node " + std::to_string(n) + " on a closed box face");
             continue;
           }
-          const bool wrapped = (c[0] != x - HX[j]) || (c[1] != y - HY[j]) || (c[2] != z - HZ[j]);
-          if (wrapped) general = true;
           if (nt[lin(c[0], c[1], c[2])] == LBM_NODE_SOLID) {
             if (!links.count(std::make_pair(n, j)))
               return bad("node " + std::to_string(n) + " has a solid neighbour in direction " +
@@ -306,10 +315,14 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   ctx->ntiles = (G.Np >> TILE_SHIFT) + 1;
   // device allocations
   CHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
-  const size_t fbytes = (size_t)19 * G.plane * ctx->ssize;
+  CHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  CHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  CHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  const size_t fbytes = ((size_t)19 * G.plane + 2 * (size_t)G.guard) * ctx->ssize;
   for (int p = 0; p < 2; p++) {
-    CHK(hipMalloc(&ctx->f[p], fbytes));
-    CHK(hipMemset(ctx->f[p], 0, fbytes));
+    CHK(hipMalloc(&ctx->f_alloc[p], fbytes));
+    CHK(hipMemset(ctx->f_alloc[p], 0, fbytes));
+    ctx->f[p] = (char*)ctx->f_alloc[p] + (size_t)G.guard * ctx->ssize;
   }
   CHK(upload(&ctx->ncls, ncls));
   CHK(upload(&ctx->rec_of, rec_of));
@@ -346,13 +359,16 @@ extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
   (void)hipDeviceSynchronize();
   free_graphs(ctx);
   free_bodies(ctx);
-  void* ptrs[] = {ctx->f[0], ctx->f[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
+  void* ptrs[] = {ctx->f_alloc[0], ctx->f_alloc[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
                   ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_dm, ctx->lk_q,
                   ctx->tile_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
                   ctx->flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
   return LBM_OK;
 }
@@ -478,28 +494,26 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   ctx->ne = e0;
   ctx->nh = e0;
   ctx->nsoft_v = (int)soft.size();
-  // incidence CSR
-  std::vector<std::vector<int32_t>> ve(v0), vh(v0), vf(v0);
+  // vertex incidence tables, slot-major [VT_SLOTS][nv]
+  std::vector<int32_t> vtab((size_t)VT_SLOTS * v0, 0);
+  std::vector<int> ne_cnt(v0, 0), nh_cnt(v0, 0), nf_cnt(v0, 0);
+  auto put = [&](int v, int slot0, int width, std::vector<int>& cnt, int32_t val) {
+    if (cnt[v] >= width) return false;
+    vtab[(size_t)(slot0 + cnt[v]++) * v0 + v] = val;
+    return true;
+  };
   for (int e = 0; e < e0; e++) {
-    ve[edges[2 * e]].push_back(e);
-    ve[edges[2 * e + 1]].push_back(e);
+    if (!put(edges[2 * e], 0, VT_E, ne_cnt, e + 1) || !put(edges[2 * e + 1], 0, VT_E, ne_cnt, -(e + 1)))
+      return fail(ctx, LBM_E_INVAL, "vertex valence above 10");
   }
   for (int h = 0; h < e0; h++)
-    for (int r = 0; r < 4; r++) vh[hinges[4 * h + r]].push_back(4 * h + r);
+    for (int r = 0; r < 4; r++)
+      if (!put(hinges[4 * h + r], VT_E, VT_H, nh_cnt, 4 * h + r + 1))
+        return fail(ctx, LBM_E_INVAL, "vertex in more than 20 hinges");
   for (int f = 0; f < f0; f++)
-    for (int r = 0; r < 3; r++) vf[faces[3 * f + r]].push_back(f);
-  auto csr = [&](const std::vector<std::vector<int32_t>>& L, std::vector<int32_t>& ptr,
-                 std::vector<int32_t>& idx) {
-    ptr.assign(1, 0);
-    for (const auto& l : L) {
-      idx.insert(idx.end(), l.begin(), l.end());
-      ptr.push_back((int32_t)idx.size());
-    }
-  };
-  std::vector<int32_t> veP, veI, vhP, vhI, vfP, vfI;
-  csr(ve, veP, veI);
-  csr(vh, vhP, vhI);
-  csr(vf, vfP, vfI);
+    for (int r = 0; r < 3; r++)
+      if (!put(faces[3 * f + r], VT_E + VT_H, VT_F, nf_cnt, f + 1))
+        return fail(ctx, LBM_E_INVAL, "vertex valence above 10");
   auto up = [&](auto** p, const auto& v) -> hipError_t {
     hipError_t e = upload(p, v);
     ctx->bod_alloc.push_back((void*)*p);
@@ -512,8 +526,8 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.ne = e0;
   B.nh = e0;
   B.nsoft_v = ctx->nsoft_v;
-  int32_t *d_soft, *d_faces, *d_fb, *d_vb, *d_edges, *d_hinges, *d_veP, *d_veI, *d_vhP, *d_vhI,
-      *d_vfP, *d_vfI, *d_bf0, *d_bnf, *d_bv0, *d_bnv, *d_be0, *d_bne, *d_brig, *d_bfix;
+  int32_t *d_soft, *d_faces, *d_fb, *d_vb, *d_edges, *d_hinges, *d_vtab, *d_bf0, *d_bnf, *d_bv0,
+      *d_bnv, *d_be0, *d_bne, *d_brig, *d_bfix;
   double *d_l0, *d_kl, *d_th0, *d_kb, *d_param, *d_Xbody;
   CHK(up(&d_soft, soft));
   CHK(up(&d_faces, faces));
@@ -521,12 +535,7 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   CHK(up(&d_vb, vert_body));
   CHK(up(&d_edges, edges));
   CHK(up(&d_hinges, hinges));
-  CHK(up(&d_veP, veP));
-  CHK(up(&d_veI, veI));
-  CHK(up(&d_vhP, vhP));
-  CHK(up(&d_vhI, vhI));
-  CHK(up(&d_vfP, vfP));
-  CHK(up(&d_vfI, vfI));
+  CHK(up(&d_vtab, vtab));
   CHK(up(&d_bf0, bf0));
   CHK(up(&d_bnf, bnf));
   CHK(up(&d_bv0, bv0));
@@ -547,17 +556,42 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   CHK(up(&ctx->X[cur ^ 1], X1));
   CHK(up(&ctx->Vel, Vl));
   CHK(up(&ctx->b_rig, rig));
-  std::vector<double> diag(16 * (size_t)nb, 0.0);
+  // diagnostics blocks: one thread per face, vertex and edge of a body
+  std::vector<int32_t> dblk0(1, 0), dblk_body;
+  for (int b = 0; b < nb; b++) {
+    const HostBody& HB = ctx->bodies[b];
+    const int items = std::max(HB.nf, std::max(HB.nv, (int)HB.l0.size()));
+    const int nblk = (items + 255) / 256;
+    for (int k = 0; k < nblk; k++) dblk_body.push_back(b);
+    dblk0.push_back(dblk0.back() + nblk);
+  }
+  std::vector<double> diag(16 * (size_t)nb, 0.0), dpart(12 * dblk_body.size(), 0.0);
   CHK(up(&ctx->b_diag, diag));
+  double* d_dpart;
+  int32_t *d_dblk0, *d_dblkb;
+  CHK(up(&d_dpart, dpart));
+  CHK(up(&d_dblk0, dblk0));
+  CHK(up(&d_dblkb, dblk_body));
+  B.diag_part = d_dpart;
+  B.b_dblk0 = d_dblk0;
+  B.dblk_body = d_dblkb;
+  B.n_diag_blocks = (int)dblk_body.size();
+  B.n_marker_blocks = (f0 + 7) / 8;
+  B.n_elem_blocks = (2 * e0 + 255) / 256;
   // the next step has parity cur: it writes base[cur] and clears the spread
   // of the last completed step, whose stencil bases are in base[cur ^ 1]
   CHK(up(&ctx->base[cur ^ 1], b_last));
   CHK(up(&ctx->base[cur], b_other));
   std::vector<double> zf(3 * (size_t)f0, 0.0), zv(3 * (size_t)v0, 0.0);
-  double *d_cen, *d_fext, *d_u0v;
+  double *d_cen, *d_fext, *d_u0v, *d_fedge, *d_fhinge;
   CHK(up(&d_cen, zf));
   CHK(up(&d_fext, zf));
   CHK(up(&d_u0v, zv));
+  std::vector<double> ze(3 * (size_t)e0, 0.0), zh(12 * (size_t)e0, 0.0);
+  CHK(up(&d_fedge, ze));
+  CHK(up(&d_fhinge, zh));
+  B.f_edge = d_fedge;
+  B.f_hinge = d_fhinge;
   B.soft_vlist = d_soft;
   B.Vel = ctx->Vel;
   B.faces = d_faces;
@@ -569,12 +603,7 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.hinges = d_hinges;
   B.theta0 = d_th0;
   B.kb = d_kb;
-  B.ve_ptr = d_veP;
-  B.ve_idx = d_veI;
-  B.vh_ptr = d_vhP;
-  B.vh_idx = d_vhI;
-  B.vf_ptr = d_vfP;
-  B.vf_idx = d_vfI;
+  B.vtab = d_vtab;
   B.b_face0 = d_bf0;
   B.b_nf = d_bnf;
   B.b_vert0 = d_bv0;
@@ -609,8 +638,8 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
       CHK(hipMemset(ctx->tf[p], 0, ctx->ntiles));
     }
   }
-  // diagnostics of the current positions (no step counted)
-  CHK(launch_end(ctx->bargs[cur], ctx->X[cur], ctx->flags, 0, ctx->stream));
+  // diagnostics of the current positions
+  CHK(launch_check(ctx->bargs[cur], ctx->X[0], ctx->X[1], ctx->flags, counter(ctx, 3), ctx->stream));
   CHK(hipStreamSynchronize(ctx->stream));
   return LBM_OK;
 }
@@ -792,6 +821,7 @@ static FluidArgs fluid_args(lbm_ctx* ctx, int p) {
   a.fx = ib ? ctx->fx[p] : nullptr;
   a.tflag = ib ? ctx->tf[p] : nullptr;
   a.flags = ctx->flags;
+  a.rec_lanes = ctx->rec_lanes;
   return a;
 }
 
@@ -802,35 +832,56 @@ static BodyArgs empty_body_args() {
 
 // The launches of one step of parity p; if ev is given, HIP events bracket
 // the fused stream-collide kernel.
+// The launches of one step of parity p on stream s.  The boundary-record
+// kernel runs on a second stream (fork/join with events) concurrently with
+// the bulk stream-collide kernel.  If ev0/ev1 are given they bracket the
+// stream-collide pair.
 static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   hipError_t e;
-  const FluidArgs a = fluid_args(ctx, p);
+  FluidArgs a = fluid_args(ctx, p);
   const bool ib = ctx->nf > 0;
-  const BodyArgs b = ib ? ctx->bargs[p] : empty_body_args();
   if (ib) {
-    e = launch_ib_force(ctx->prec, a, b, ctx->fx[p], ctx->tf[p], ctx->fx[p ^ 1], ctx->tf[p ^ 1], s);
-    if (e != hipSuccess) return e;
+    const BodyArgs& b = ctx->bargs[p];
+    if ((e = launch_ib_force(ctx->prec, a, b, ctx->fx[p], ctx->tf[p], counter(ctx, 0), s)) != hipSuccess) return e;
   }
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-  if ((e = launch_fluid(ctx->prec, a, s)) != hipSuccess) return e;
+  if (ctx->nrec > 0) {
+    if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0)) != hipSuccess) return e;
+    if ((e = launch_fluid_rec(ctx->prec, a, ctx->side)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ctx->ev_join, ctx->side)) != hipSuccess) return e;
+  }
+  if ((e = launch_fluid_bulk(ctx->prec, a, s)) != hipSuccess) return e;
+  if (ctx->nrec > 0 && (e = hipStreamWaitEvent(s, ctx->ev_join, 0)) != hipSuccess) return e;
   if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
   if (ib) {
-    if ((e = launch_mls_post(ctx->prec, a, b, s)) != hipSuccess) return e;
-    if ((e = launch_body_post(b, ctx->flags, s)) != hipSuccess) return e;
+    const BodyArgs& b = ctx->bargs[p];
+    if ((e = launch_mls_post(ctx->prec, a, b, ctx->fx[p ^ 1], ctx->tf[p ^ 1], s)) != hipSuccess) return e;
+    if ((e = launch_body_post(b, ctx->flags, counter(ctx, 1), s)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_close(ctx->flags, s)) != hipSuccess) return e;
   }
-  return launch_end(b, ib ? ctx->X[p ^ 1] : nullptr, ctx->flags, 1, s);
+  return hipSuccess;
 }
+
+// Graphs: one step of each parity, and a chunk of GRAPH_CHUNK steps (even,
+// starting at parity 0) so that the launch gap between graphs is paid once
+// per chunk.
+static const int GRAPH_CHUNK = 16;
 
 static lbm_status build_graphs(lbm_ctx* ctx) {
   free_graphs(ctx);
-  for (int p = 0; p < 2; p++) {
+  for (int k = 0; k < 3; k++) {
     hipGraph_t g;
     CHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_step(ctx, p, ctx->cap, nullptr, nullptr);
+    hipError_t e = hipSuccess;
+    if (k < 2) e = enqueue_step(ctx, k, ctx->cap, nullptr, nullptr);
+    else
+      for (int q = 0; q < GRAPH_CHUNK && e == hipSuccess; q++) e = enqueue_step(ctx, q & 1, ctx->cap, nullptr, nullptr);
     hipError_t e2 = hipStreamEndCapture(ctx->cap, &g);
     CHK(e);
     CHK(e2);
-    CHK(hipGraphInstantiate(&ctx->gexec[p], g, nullptr, nullptr, 0));
+    CHK(hipGraphInstantiate(&ctx->gexec[k], g, nullptr, nullptr, 0));
     CHK(hipGraphDestroy(g));
   }
   ctx->graph_valid = true;
@@ -844,11 +895,19 @@ extern "C" lbm_status lbm_step(lbm_ctx* ctx, int32_t n) {
     lbm_status st = build_graphs(ctx);
     if (st) return st;
   }
-  for (int32_t k = 0; k < n; k++) {
+  int32_t k = 0;
+  while (k < n) {
     const int p = (int)(ctx->enq & 1);
+    if (ctx->use_graph && p == 0 && n - k >= GRAPH_CHUNK) {
+      CHK(hipGraphLaunch(ctx->gexec[2], ctx->stream));
+      ctx->enq += GRAPH_CHUNK;
+      k += GRAPH_CHUNK;
+      continue;
+    }
     if (ctx->use_graph) CHK(hipGraphLaunch(ctx->gexec[p], ctx->stream));
     else CHK(enqueue_step(ctx, p, ctx->stream, nullptr, nullptr));
     ctx->enq++;
+    k++;
   }
   return LBM_OK;
 }
@@ -862,6 +921,9 @@ extern "C" lbm_status lbm_set_graph(lbm_ctx* ctx, int32_t enable) {
 extern "C" lbm_status lbm_sync(lbm_ctx* ctx) {
   if (!ctx) return LBM_E_INVAL;
   if (ctx->broken) return LBM_E_STATE;
+  // damage or non-finite positions of the last completed step
+  if (ctx->nf > 0)
+    CHK(launch_check(ctx->bargs[0], ctx->X[0], ctx->X[1], ctx->flags, counter(ctx, 3), ctx->stream));
   DevFlags h;
   lbm_status st = read_flags(ctx, &h);
   if (st) return st;

@@ -28,6 +28,9 @@ constexpr double FX_INV = 1.0 / 4503599627370496.0;
 
 constexpr int TILE_SHIFT = 10;  // force-flag granularity: 1024 nodes
 
+// Vertex incidence table widths (largest vertex valence accepted: 10).
+constexpr int VT_E = 10, VT_H = 20, VT_F = 10, VT_SLOTS = VT_E + VT_H + VT_F;
+
 struct DevFlags {
   uint32_t stop;      // sticky stop bits (checked at every kernel entry)
   uint32_t pending;   // bits raised during the current step
@@ -44,6 +47,7 @@ struct Grid {
   int per[3];
   long long Np;    // px*ny*nz
   long long plane; // distance between population planes (elements)
+  long long guard; // elements allocated before plane 0 and after plane 18
 };
 
 // Everything the fluid and IB kernels need (passed by value).
@@ -68,6 +72,9 @@ struct FluidArgs {
   const long long* fx;       // fixed-point IB force [3][Np] of this step (may be null)
   const uint8_t* tflag;      // tile flags of this step (may be null)
   DevFlags* flags;
+  unsigned int* counter;     // block counter used when this launch closes the step
+  int close_step;            // 1: no bodies, this launch is the whole step
+  int rec_lanes;             // boundary records: 1 = 32 lanes per record, 0 = one thread
 };
 
 // Bodies (all concatenated).
@@ -87,10 +94,12 @@ struct BodyArgs {
   const int32_t* hinges;       // [nh][4]
   const double* theta0;        // [nh]
   const double* kb;            // [nh]
-  // vertex incidence CSR
-  const int32_t* ve_ptr; const int32_t* ve_idx;   // edges
-  const int32_t* vh_ptr; const int32_t* vh_idx;   // hinge*4 + role
-  const int32_t* vf_ptr; const int32_t* vf_idx;   // faces
+  // vertex incidence, slot-major [VT_SLOTS][nv]: VT_E edge slots (+-(e+1),
+  // sign + when the vertex is the edge's first end), VT_H hinge slots
+  // (4 h + role + 1), VT_F face slots (f + 1); 0 = empty
+  const int32_t* vtab;
+  double* f_edge;              // [ne][3] stretching force on the edge's first vertex
+  double* f_hinge;             // [nh][4][3] bending force on the hinge's four vertices
   // per body tables
   const int32_t* b_face0; const int32_t* b_nf;
   const int32_t* b_vert0; const int32_t* b_nv;
@@ -100,6 +109,10 @@ struct BodyArgs {
   double* b_rig;               // [nbody][32]: xc3 u3 uprev3 w3 wprev3 R9 Ibody9 (rigid state)
   const double* Xbody;         // [nv][3] body-frame offsets (rigid)
   double* b_diag;              // [nbody][16]: V S bbox(6) max_strain ...
+  double* diag_part;           // [n_diag_blocks][12] partial diagnostics
+  const int32_t* dblk_body;    // [n_diag_blocks] body of each diagnostics block
+  const int32_t* b_dblk0;      // [nbody + 1] first diagnostics block of each body
+  int n_marker_blocks, n_elem_blocks, n_diag_blocks;
   // per face / vertex work arrays
   double* centroid;            // [nf][3]
   double* fext;                // [nf][3] hydrodynamic + repulsion force
@@ -112,12 +125,16 @@ struct BodyArgs {
 // Launchers (lbm_kernels.hip)
 hipError_t launch_init(int prec, const Grid& g, void* f, const uint8_t* ncls, const double* rho,
                        const double* u, hipStream_t s);
-hipError_t launch_fluid(int prec, const FluidArgs& a, hipStream_t s);
+hipError_t launch_fluid_bulk(int prec, const FluidArgs& a, hipStream_t s);
+hipError_t launch_fluid_rec(int prec, const FluidArgs& a, hipStream_t s);
+hipError_t launch_close(DevFlags* flags, hipStream_t s);
 hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fx_cur,
-                           uint8_t* tf_cur, long long* fx_prev, uint8_t* tf_prev, hipStream_t s);
-hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s);
-hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s);
-hipError_t launch_end(const BodyArgs& b, const double* X, DevFlags* flags, int count, hipStream_t s);
+                           uint8_t* tf_cur, unsigned int* counter, hipStream_t s);
+hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, long long* fx_prev,
+                           uint8_t* tf_prev, hipStream_t s);
+hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter, hipStream_t s);
+hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
+                        unsigned int* counter, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,
                              const uint8_t* ncls, const long long* fx0, const long long* fx1,
                              const uint8_t* tf0, const uint8_t* tf1, double gx, double gy,

@@ -80,10 +80,11 @@ __device__ __forceinline__ long long nbr(const Grid& G, int x, int y, int z, int
 }
 
 __device__ __forceinline__ void coords(const Grid& G, long long n, int& x, int& y, int& z) {
-  x = (int)(n % G.px);
-  long long t = n / G.px;
-  y = (int)(t % G.ny);
-  z = (int)(t / G.ny);
+  const unsigned int u = (unsigned int)n;  // padded index < 2^31
+  const unsigned int t = u / (unsigned int)G.px;
+  x = (int)(u - t * (unsigned int)G.px);
+  z = (int)(t / (unsigned int)G.ny);
+  y = (int)(t - (unsigned int)z * (unsigned int)G.ny);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; give every XCD a
@@ -194,55 +195,65 @@ __device__ void zouhe(C (&g)[19], int face, int kind, C bx, C by, C bz, C brho) 
 // Streamed populations of a boundary record: plain pulls (periodic wrap),
 // interpolated bounce-back on wall links (Eq. bbouzidi, modes fixed on the
 // host), Zou-He for the populations entering through an open face.
+// Addresses are formed with periodic wrap, so they lie in the box even for
+// sources the record does not use: all loads are issued first (plain pulls
+// unconditionally, link data and bounce-back neighbours under the link
+// mask) and the arithmetic follows, so one thread waits for memory once.
 template <class S>
 __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19]) {
   typedef typename Store<S>::C C;
   const Grid& G = a.g;
   const long long node = a.rec_node[r];
+  const uint32_t mask = a.rec_mask[r];
+  const int lk0 = a.rec_link0[r];
+  const int fc = a.rec_face[r];
   int x, y, z;
   coords(G, node, x, y, z);
-  const uint32_t mask = a.rec_mask[r];
-  int lk = a.rec_link0[r];
-  const int fc = a.rec_face[r];
   const int face = fc & 7, kind = (fc >> 4) & 1;
   const int ax = face >> 1, s = (face & 1) ? -1 : 1;
-  g[0] = ldA<S>(a, 0, node);
+  C self[19], pl[19], b1[19], b2[19], b3[19], q[19];
+  int md[19];
+#pragma unroll
+  for (int i = 0; i < 19; i++) self[i] = ldA<S>(a, i, node);
+#pragma unroll
+  for (int j = 1; j < 19; j++) pl[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
+  int lk = lk0;
 #pragma unroll
   for (int j = 1; j < 19; j++) {
-    if (mask & (1u << j)) {
+    md[j] = 0;
+    q[j] = b1[j] = b2[j] = b3[j] = C(0);
+    if ((mask >> j) & 1u) {
       const int i = OPP[j];
-      const uint8_t dm = a.lk_dm[lk];
-      const C q = (C)a.lk_q[lk];
+      md[j] = a.lk_dm[lk] >> 5;
+      q[j] = (C)a.lk_q[lk];
       ++lk;
-      const int mode = dm >> 5;
-      const C fi_x = ldA<S>(a, i, node);
-      C v;
-      if (mode == BFL_BB) {
-        v = fi_x;
-      } else if (mode == BFL_LIN_HI) {
-        v = fi_x / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * ldA<S>(a, j, node);
-      } else {
-        const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
-        if (mode == BFL_QUAD_LO) {
-          const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
-          v = q * (C(1) + C(2) * q) * fi_x + (C(1) - C(4) * q * q) * ldA<S>(a, i, n1) -
-              q * (C(1) - C(2) * q) * ldA<S>(a, i, n2);
-        } else if (mode == BFL_LIN_LO) {
-          v = C(2) * q * fi_x + (C(1) - C(2) * q) * ldA<S>(a, i, n1);
-        } else {  // BFL_QUAD_HI
-          v = fi_x / (q * (C(2) * q + C(1))) + (C(2) * q - C(1)) / q * ldA<S>(a, j, node) +
-              (C(1) - C(2) * q) / (C(1) + C(2) * q) * ldA<S>(a, j, n1);
-        }
-      }
-      g[j] = v;
-    } else {
-      int e[3] = {EX[j], EY[j], EZ[j]};
-      if (fc != 0xff && s * e[ax] == 1) {
-        g[j] = 0;  // unknown: Zou-He below
-      } else {
-        g[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
-      }
+      const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
+      const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
+      b1[j] = ldA<S>(a, i, n1);
+      b2[j] = ldA<S>(a, i, n2);
+      b3[j] = ldA<S>(a, j, n1);
     }
+  }
+  g[0] = self[0];
+#pragma unroll
+  for (int j = 1; j < 19; j++) {
+    const int i = OPP[j];
+    const int e[3] = {EX[j], EY[j], EZ[j]};
+    const C fi_x = self[i], fj_x = self[j], qq = q[j];
+    C v;
+    if (md[j] == 0) v = (fc != 0xff && s * e[ax] == 1) ? C(0) : pl[j];  // unknowns: Zou-He below
+    else if (md[j] == BFL_QUAD_LO)
+      v = qq * (C(1) + C(2) * qq) * fi_x + (C(1) - C(4) * qq * qq) * b1[j] - qq * (C(1) - C(2) * qq) * b2[j];
+    else if (md[j] == BFL_LIN_LO)
+      v = C(2) * qq * fi_x + (C(1) - C(2) * qq) * b1[j];
+    else if (md[j] == BFL_BB)
+      v = fi_x;
+    else if (md[j] == BFL_QUAD_HI)
+      v = fi_x / (qq * (C(2) * qq + C(1))) + (C(2) * qq - C(1)) / qq * fj_x +
+          (C(1) - C(2) * qq) / (C(1) + C(2) * qq) * b3[j];
+    else  // BFL_LIN_HI
+      v = fi_x / (C(2) * qq) + (C(2) * qq - C(1)) / (C(2) * qq) * fj_x;
+    g[j] = v;
   }
   if (fc != 0xff) {
     zouhe<C>(g, face, kind, (C)a.rec_bc[r], (C)a.rec_bc[a.nrec + r], (C)a.rec_bc[2 * a.nrec + r],
@@ -256,11 +267,10 @@ __device__ __forceinline__ void pull_node(const FluidArgs& a, long long node,
                                           typename Store<S>::C (&g)[19]) {
   if (a.ncls[node] == CLS_BULK) {
     const Grid& G = a.g;
+    int x, y, z;
+    coords(G, node, x, y, z);
 #pragma unroll
-    for (int j = 0; j < 19; j++) {
-      long long off = EX[j] + (long long)G.px * (EY[j] + (long long)G.ny * EZ[j]);
-      g[j] = ldA<S>(a, j, node - off);
-    }
+    for (int j = 0; j < 19; j++) g[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
   } else {
     pull_general<S>(a, a.rec_of[node], g);
   }
@@ -280,7 +290,67 @@ __device__ __forceinline__ void node_force(const FluidArgs& a, long long node, b
   Fz = (C)fz;
 }
 
+// ------------------------------------------------------------ step closing
+// Blocks of a kernel that closes a piece of work count themselves on a
+// device counter; the last one to arrive combines the kernel's results.
+// No agent-scope fence (on gfx950 that writes back the whole L2): the few
+// values the last block reads are written with device-coherent atomic
+// stores or read-modify-writes, and each writing wave waits for them to
+// complete before its block is counted.
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ void store_coherent(double* p, double v) {
+  __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_coherent(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ void raise_pending(DevFlags* flags, unsigned int bits) {
+  atomicOr(&flags->pending, bits);
+  wait_mem();
+}
+
+__device__ __forceinline__ bool last_block(unsigned int* counter, unsigned int nblocks) {
+  __shared__ int is_last;
+  wait_mem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int done = atomicAdd(counter, 1u);
+    is_last = (done == nblocks - 1);
+  }
+  __syncthreads();
+  return is_last != 0;
+}
+
+// steps_done += 1 and the bits raised during the step become sticky.
+__device__ __forceinline__ void close_step(DevFlags* flags, unsigned int* counter) {
+  if (threadIdx.x == 0) {
+    const unsigned int pend =
+        __hip_atomic_load(&flags->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    flags->steps_done += 1;
+    flags->stop |= pend;
+    flags->pending = 0u;
+    *counter = 0u;
+  }
+}
+
 // ------------------------------------------------------------- k_fluid
+template <class S>
+struct ClsVec;
+template <>
+struct ClsVec<double> { typedef uint16_t T; };
+template <>
+struct ClsVec<float> { typedef uint32_t T; };
+template <>
+struct ClsVec<_Float16> { typedef uint64_t T; };
+
+// One thread = V consecutive nodes of a row.  The populations carry guard
+// regions of one z-plane plus one row on both sides, so the 19 vector loads
+// stay inside the allocation for any group; values pulled for solid or
+// boundary-record nodes are computed and discarded.
 template <class S>
 __device__ void fluid_bulk(const FluidArgs& a, int blk) {
   typedef typename Store<S>::C C;
@@ -291,68 +361,204 @@ __device__ void fluid_bulk(const FluidArgs& a, int blk) {
   const long long tile = a.tile_list[blk];
   const long long base = tile * (256LL * V) + (long long)threadIdx.x * V;
   if (base >= G.Np) return;
-  uint8_t cls[V];
+  const typename ClsVec<S>::T cw = *(const typename ClsVec<S>::T*)(a.ncls + base);
+  bool isb[V];
   bool all = true, any = false;
 #pragma unroll
   for (int k = 0; k < V; k++) {
-    cls[k] = a.ncls[base + k];
-    all = all && cls[k] == CLS_BULK;
-    any = any || cls[k] == CLS_BULK;
+    isb[k] = ((cw >> (8 * k)) & 0xff) == CLS_BULK;
+    all = all && isb[k];
+    any = any || isb[k];
   }
   if (!any) return;
   const bool flagged = a.tflag && a.tflag[base >> TILE_SHIFT];
   const S* A = (const S*)a.A;
   S* B = (S*)a.B;
   const C omega = (C)a.omega;
+  int x0, y, z;
+  coords(G, base, x0, y, z);
+  // periodic x: groups touching x = 0 or x = nx-1 gather element by element
+  const bool xedge = G.per[0] && (x0 == 0 || x0 + V > G.nx - 1);
+  vec in[19];
+#pragma unroll
+  for (int j = 0; j < 19; j++) {
+    const int sy = (G.per[1] ? wrapc(y - EY[j], G.ny) : y - EY[j]);
+    const int sz = (G.per[2] ? wrapc(z - EZ[j], G.nz) : z - EZ[j]);
+    const long long row = (long long)G.px * (sy + (long long)G.ny * sz);
+    const S* pl = A + (long long)j * G.plane + row;
+    if (EX[j] == 0) {
+      in[j] = *(const vec*)(pl + x0);
+    } else if (!xedge) {
+      in[j] = *(const vecu*)(pl + x0 - EX[j]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; k++) in[j][k] = pl[wrapc(x0 + k - EX[j], G.nx)];
+    }
+  }
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < V; k++) {
+    C g[19];
+#pragma unroll
+    for (int j = 0; j < 19; j++) g[j] = to_c(in[j][k]);
+    C Fx, Fy, Fz, rho, ux, uy, uz;
+    node_force<C>(a, base + k, flagged && isb[k], Fx, Fy, Fz);
+    collide<C>(g, Fx, Fy, Fz, omega, rho, ux, uy, uz);
+    bad = bad || (isb[k] && !(ux * ux + uy * uy + uz * uz <= C(0.09)));
+#pragma unroll
+    for (int j = 0; j < 19; j++) in[j][k] = (S)g[j];
+  }
   if (all) {
-    vec in[19];
-#pragma unroll
-    for (int j = 0; j < 19; j++) {
-      const long long off = EX[j] + (long long)G.px * (EY[j] + (long long)G.ny * EZ[j]);
-      const S* p = A + (long long)j * G.plane + base - off;
-      if (EX[j] == 0) in[j] = *(const vec*)p;
-      else in[j] = *(const vecu*)p;
-    }
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < V; k++) {
-      C g[19];
-#pragma unroll
-      for (int j = 0; j < 19; j++) g[j] = to_c(in[j][k]);
-      C Fx, Fy, Fz, rho, ux, uy, uz;
-      node_force<C>(a, base + k, flagged, Fx, Fy, Fz);
-      collide<C>(g, Fx, Fy, Fz, omega, rho, ux, uy, uz);
-      bad = bad || !(ux * ux + uy * uy + uz * uz <= C(0.09));
-#pragma unroll
-      for (int j = 0; j < 19; j++) in[j][k] = (S)g[j];
-    }
 #pragma unroll
     for (int j = 0; j < 19; j++) *(vec*)(B + (long long)j * G.plane + base) = in[j];
-    if (bad) atomicOr(&a.flags->pending, ST_UNSTABLE);
   } else {
-    bool bad = false;
-    for (int k = 0; k < V; k++) {
-      if (cls[k] != CLS_BULK) continue;
-      const long long node = base + k;
-      C g[19];
 #pragma unroll
-      for (int j = 0; j < 19; j++) {
-        const long long off = EX[j] + (long long)G.px * (EY[j] + (long long)G.ny * EZ[j]);
-        g[j] = to_c(A[(long long)j * G.plane + node - off]);
-      }
-      C Fx, Fy, Fz, rho, ux, uy, uz;
-      node_force<C>(a, node, flagged, Fx, Fy, Fz);
-      collide<C>(g, Fx, Fy, Fz, omega, rho, ux, uy, uz);
-      bad = bad || !(ux * ux + uy * uy + uz * uz <= C(0.09));
+    for (int j = 0; j < 19; j++)
 #pragma unroll
-      for (int j = 0; j < 19; j++) B[(long long)j * G.plane + node] = (S)g[j];
-    }
-    if (bad) atomicOr(&a.flags->pending, ST_UNSTABLE);
+      for (int k = 0; k < V; k++)
+        if (isb[k]) B[(long long)j * G.plane + base + k] = in[j][k];
   }
+  if (bad) raise_pending(a.flags, ST_UNSTABLE);
 }
 
+// Direction tables as bit masks, for lanes that own one direction each.
+constexpr uint32_t bits_of(const int (&v)[19], int val) {
+  uint32_t m = 0;
+  for (int i = 0; i < 19; i++)
+    if (v[i] == val) m |= 1u << i;
+  return m;
+}
+constexpr uint32_t PXM = bits_of(EX, 1), NXM = bits_of(EX, -1);
+constexpr uint32_t PYM = bits_of(EY, 1), NYM = bits_of(EY, -1);
+constexpr uint32_t PZM = bits_of(EZ, 1), NZM = bits_of(EZ, -1);
+__device__ __forceinline__ int ecomp(uint32_t pm, uint32_t nm, int j) {
+  return (int)((pm >> j) & 1u) - (int)((nm >> j) & 1u);
+}
+__device__ __forceinline__ int opp_of(int j) {
+  // 1<->2, 3<->4, 5<->6, 7<->12, 8<->11, 9<->14, 10<->13, 15<->18, 16<->17
+  if (j == 0) return 0;
+  if (j <= 6) return (j & 1) ? j + 1 : j - 1;
+  if (j <= 14) return ((j - 7) & 2) ? 23 - j : 19 - j;
+  return 33 - j;
+}
+
+template <class C>
+__device__ __forceinline__ C seg_sum(C v) {
+#pragma unroll
+  for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
+  return v;
+}
+
+// Boundary record (32 lanes; lane j < 19 owns direction j): pull or
+// interpolated bounce-back for its direction, Zou-He and moments by segment
+// reductions, then the forced BGK collision of its own population.
 template <class S>
-__device__ void fluid_record(const FluidArgs& a, int r) {
+__device__ void fluid_record_lanes(const FluidArgs& a, int r, int j) {
+  typedef typename Store<S>::C C;
+  const Grid& G = a.g;
+  const long long node = a.rec_node[r];
+  const uint32_t mask = a.rec_mask[r];
+  const int lk0 = a.rec_link0[r];
+  const int fc = a.rec_face[r];
+  int x, y, z;
+  coords(G, node, x, y, z);
+  const bool act = j < 19;
+  const int jj = act ? j : 0;
+  const int ex = ecomp(PXM, NXM, jj), ey = ecomp(PYM, NYM, jj), ez = ecomp(PZM, NZM, jj);
+  const int i = opp_of(jj);
+  const bool linked = act && ((mask >> jj) & 1u);
+  // loads
+  const C self_j = ldA<S>(a, jj, node);
+  const C pulled = ldA<S>(a, jj, nbr(G, x, y, z, -ex, -ey, -ez));
+  C fi_x = 0, b1 = 0, b2 = 0, b3 = 0, q = 0;
+  int md = 0;
+  if (linked) {
+    const int lk = lk0 + __popc(mask & ((1u << jj) - 2u));
+    md = a.lk_dm[lk] >> 5;
+    q = (C)a.lk_q[lk];
+    const long long n1 = nbr(G, x, y, z, ex, ey, ez);  // x - e_i
+    const long long n2 = nbr(G, x, y, z, 2 * ex, 2 * ey, 2 * ez);
+    fi_x = ldA<S>(a, i, node);
+    b1 = ldA<S>(a, i, n1);
+    b2 = ldA<S>(a, i, n2);
+    b3 = ldA<S>(a, jj, n1);
+  }
+  C gj;
+  if (jj == 0) gj = self_j;
+  else if (!linked) gj = pulled;
+  else if (md == BFL_QUAD_LO)
+    gj = q * (C(1) + C(2) * q) * fi_x + (C(1) - C(4) * q * q) * b1 - q * (C(1) - C(2) * q) * b2;
+  else if (md == BFL_LIN_LO)
+    gj = C(2) * q * fi_x + (C(1) - C(2) * q) * b1;
+  else if (md == BFL_BB)
+    gj = fi_x;
+  else if (md == BFL_QUAD_HI)
+    gj = fi_x / (q * (C(2) * q + C(1))) + (C(2) * q - C(1)) / q * self_j +
+         (C(1) - C(2) * q) / (C(1) + C(2) * q) * b3;
+  else
+    gj = fi_x / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * self_j;
+  if (!act) gj = C(0);
+  const int seg = threadIdx.x & 32;  // first lane of this segment within the wave
+  if (fc != 0xff) {
+    // Zou-He (Eq. extbound) on deviations, inward normal n = s e_ax
+    const int face = fc & 7, kind = (fc >> 4) & 1;
+    const int ax = face >> 1, s = (face & 1) ? -1 : 1;
+    const int e_ax = ax == 0 ? ex : (ax == 1 ? ey : ez);
+    const int en = act ? s * e_ax : 2;
+    if (en == 1) gj = C(0);
+    const C G0 = seg_sum<C>(en == 0 ? gj : C(0));
+    const C Gout = seg_sum<C>(en == -1 ? gj : C(0));
+    // tangential axes t1, t2 (the two axes other than ax)
+    const int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+    const int e1 = a1 == 0 ? ex : (a1 == 1 ? ey : ez);
+    const int e2 = a2 == 0 ? ex : (a2 == 1 ? ey : ez);
+    const C T1 = seg_sum<C>(en == 0 ? C(e1) * gj : C(0));
+    const C T2 = seg_sum<C>(en == 0 ? C(e2) * gj : C(0));
+    C u[3] = {(C)a.rec_bc[r], (C)a.rec_bc[a.nrec + r], (C)a.rec_bc[2 * a.nrec + r]};
+    C rho, un;
+    if (kind == 0) {
+      un = C(s) * u[ax];
+      rho = (C(1) + G0 + C(2) * Gout) / (C(1) - un);
+    } else {
+      rho = (C)a.rec_bc[3 * a.nrec + r];
+      un = (rho - C(1) - G0 - C(2) * Gout) / rho;
+      u[0] = u[1] = u[2] = C(0);
+      u[ax] = C(s) * un;
+    }
+    const C N1 = C(0.5) * T1 - rho / C(3) * u[a1];
+    const C N2 = C(0.5) * T2 - rho / C(3) * u[a2];
+    const C g_opp = __shfl(gj, seg + i, 64);
+    if (en == 1) {
+      if (e1 == 0 && e2 == 0) gj = g_opp + rho / C(3) * un;
+      else if (e1 != 0) gj = g_opp + rho / C(6) * (un + C(e1) * u[a1]) - C(e1) * N1;
+      else gj = g_opp + rho / C(6) * (un + C(e2) * u[a2]) - C(e2) * N2;
+    }
+  }
+  // moments and forced collision
+  const C drho = seg_sum<C>(gj);
+  const C mx = seg_sum<C>(C(ex) * gj), my = seg_sum<C>(C(ey) * gj), mz = seg_sum<C>(C(ez) * gj);
+  const bool flagged = a.tflag && a.tflag[node >> TILE_SHIFT];
+  C Fx, Fy, Fz;
+  node_force<C>(a, node, flagged, Fx, Fy, Fz);
+  const C rho = C(1) + drho, ir = C(1) / rho;
+  const C ux = (mx + C(0.5) * Fx) * ir, uy = (my + C(0.5) * Fy) * ir, uz = (mz + C(0.5) * Fz) * ir;
+  const C usq = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
+  const C omega = (C)a.omega, kf = C(1) - C(0.5) * omega;
+  const C w = jj == 0 ? C(1.0 / 3) : (jj <= 6 ? C(1.0 / 18) : C(1.0 / 36));
+  const C eu = C(ex) * ux + C(ey) * uy + C(ez) * uz;
+  const C eF = C(ex) * Fx + C(ey) * Fy + C(ez) * Fz;
+  const C geq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * usq));
+  const C Gi = kf * w * (C(3) * (eF - uF) + C(9) * eu * eF);
+  const C out = gj - omega * (gj - geq) + Gi;
+  if (act) ((S*)a.B)[(long long)jj * G.plane + node] = (S)out;
+  if (j == 0 && !(usq <= C(0.09))) raise_pending(a.flags, ST_UNSTABLE);
+}
+
+// Boundary record, one thread: all loads in one batch (pull_general), then
+// the forced collision; consecutive records are consecutive nodes, so the
+// loads of a wave are coalesced along x.
+template <class S>
+__device__ void fluid_record_thread(const FluidArgs& a, int r) {
   typedef typename Store<S>::C C;
   C g[19];
   pull_general<S>(a, r, g);
@@ -364,19 +570,39 @@ __device__ void fluid_record(const FluidArgs& a, int r) {
   S* B = (S*)a.B;
 #pragma unroll
   for (int j = 0; j < 19; j++) B[(long long)j * a.g.plane + node] = (S)g[j];
-  if (!(ux * ux + uy * uy + uz * uz <= C(0.09))) atomicOr(&a.flags->pending, ST_UNSTABLE);
+  if (!(ux * ux + uy * uy + uz * uz <= C(0.09))) raise_pending(a.flags, ST_UNSTABLE);
+}
+
+// The bulk tiles and the boundary records are two kernels: the records
+// need several times the registers of the bulk path, and sharing one kernel
+// would cap the occupancy of the bandwidth-bound part.  The two launches
+// read A and write disjoint nodes of B and may run concurrently.
+template <class S>
+__global__ __launch_bounds__(256) void k_fluid_bulk(FluidArgs a) {
+  if (a.flags->stop) return;
+  fluid_bulk<S>(a, xcd_remap(blockIdx.x, a.nbulk_blocks));
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_fluid(FluidArgs a) {
+__global__ __launch_bounds__(256) void k_fluid_rec(FluidArgs a) {
   if (a.flags->stop) return;
-  const int b = blockIdx.x;
-  if (b < a.nbulk_blocks) {
-    fluid_bulk<S>(a, xcd_remap(b, a.nbulk_blocks));
+  if (a.rec_lanes) {
+    const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
+    if (r < a.nrec) fluid_record_lanes<S>(a, r, threadIdx.x & 31);
   } else {
-    const int r = (b - a.nbulk_blocks) * 256 + threadIdx.x;
-    if (r < a.nrec) fluid_record<S>(a, r);
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < a.nrec) fluid_record_thread<S>(a, r);
   }
+}
+
+// Closes a fluid-only step (one thread).
+__global__ void k_close(DevFlags* flags) {
+  if (flags->stop) return;
+  const unsigned int pend =
+      __hip_atomic_load(&flags->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  flags->steps_done += 1;
+  flags->stop |= pend;
+  flags->pending = 0u;
 }
 
 // ---------------------------------------------------------------- init
@@ -563,42 +789,205 @@ __device__ __forceinline__ void face_geom(const double* X, const int32_t* faces,
   area = 0.5 * l;
 }
 
-// ---------------------------------------------------------- k_ib_force
-// Direct forcing at the face centroids: U = sum phi u* with u* = sum f e / rho
-// of the streamed populations (no force), F_l = U_b - U, spread of
-// c_l phi_k F_l with c_l the face area.
-template <class S>
-__global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long long* fxc,
-                                                  uint8_t* tfc, long long* fxp, uint8_t* tfp) {
-  typedef typename Store<S>::C C;
-  if (a.flags->stop) return;
-  const int lane = threadIdx.x & 31;
-  const int m = (blockIdx.x * 256 + threadIdx.x) >> 5;
-  if (m >= b.nf) return;
-  const Grid& G = a.g;
-  // clear the previous step's spread buffer at the previous stencil
-  const int pbx = b.base_prev[3 * m];
-  if (pbx != INT_MIN && lane < 27) {
-    int c[3] = {pbx + lane % 3 - 1, b.base_prev[3 * m + 1] + (lane / 3) % 3 - 1,
-                b.base_prev[3 * m + 2] + lane / 9 - 1};
-    const int dim[3] = {G.nx, G.ny, G.nz};
-    bool ok = true;
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Signed dihedral angle of hinge (a, b, c, d) (faces (a,b,c) and (b,a,d),
+// outward normals, positive for a convex fold) and its gradient with
+// respect to the four vertices: the wing gradients are -|e| n/|n|^2; the
+// edge-end gradients follow from translation and rotation invariance.
+__device__ void hinge_all(const double* X, const int32_t* h, double& theta, double (&gr)[4][3]) {
+  const double* pa = X + 3 * h[0];
+  const double* pb = X + 3 * h[1];
+  const double* pc = X + 3 * h[2];
+  const double* pd = X + 3 * h[3];
+  double e[3], ca[3], da[3], ab[3], db[3], n1[3], n2[3];
+  for (int k = 0; k < 3; k++) {
+    e[k] = pb[k] - pa[k];
+    ca[k] = pc[k] - pa[k];
+    da[k] = pd[k] - pa[k];
+    ab[k] = pa[k] - pb[k];
+    db[k] = pd[k] - pb[k];
+  }
+  cross3(e, ca, n1);
+  cross3(ab, db, n2);
+  const double q1 = n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2];
+  const double q2 = n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2];
+  const double le2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+  const double le = sqrt(le2);
+  const double l1 = sqrt(q1), l2 = sqrt(q2);
+  double m1[3], m2[3], t[3];
+  for (int k = 0; k < 3; k++) {
+    m1[k] = n1[k] / l1;
+    m2[k] = n2[k] / l2;
+  }
+  cross3(m1, m2, t);
+  theta = atan2((t[0] * e[0] + t[1] * e[1] + t[2] * e[2]) / le,
+                m1[0] * m2[0] + m1[1] * m2[1] + m1[2] * m2[2]);
+  const double al_c = (ca[0] * e[0] + ca[1] * e[1] + ca[2] * e[2]) / le2;
+  const double al_d = (da[0] * e[0] + da[1] * e[1] + da[2] * e[2]) / le2;
+  for (int k = 0; k < 3; k++) {
+    const double gc = -le * n1[k] / q1;
+    const double gd = -le * n2[k] / q2;
+    gr[0][k] = -((1.0 - al_c) * gc + (1.0 - al_d) * gd);
+    gr[1][k] = -(al_c * gc + al_d * gd);
+    gr[2][k] = gc;
+    gr[3][k] = gd;
+  }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // deterministic: fixed lane tree in each wave, then fixed order over waves
+  v = red64(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); k++) t += sh[k];
+  return t;
+}
+
+// ------------------------------------------------------------ diagnostics
+// One block of one body (one face, vertex and edge per thread): partial
+// volume sum a.(b x c)/6, area, bounding box, NaN and largest stretch
+// l/l0 of the positions X, written to diag_part[dblk].
+__device__ void diag_block(const BodyArgs& b, const double* X, int dblk) {
+  __shared__ double sh[8];
+  __shared__ double shm[4][8];
+  const int body = b.dblk_body[dblk];
+  const int i = (dblk - b.b_dblk0[body]) * 256 + threadIdx.x;
+  double V = 0.0, S = 0.0, strain = 0.0, nan = 0.0;
+  double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+  if (i < b.b_nf[body]) {
+    const int f = b.b_face0[body] + i;
+    const int* F = b.faces + 3 * f;
+    double bc[3];
+    cross3(X + 3 * F[1], X + 3 * F[2], bc);
+    const double* pa = X + 3 * F[0];
+    V = (pa[0] * bc[0] + pa[1] * bc[1] + pa[2] * bc[2]) / 6.0;
+    double c[3], n[3];
+    face_geom(X, b.faces, f, c, n, S);
+  }
+  if (i < b.b_nv[body]) {
+    const int v = b.b_vert0[body] + i;
     for (int k = 0; k < 3; k++) {
-      if (c[k] < 0 || c[k] >= dim[k]) {
-        if (G.per[k]) c[k] = ((c[k] % dim[k]) + dim[k]) % dim[k];
-        else ok = false;
-      }
-    }
-    if (ok) {
-      long long node = c[0] + (long long)G.px * (c[1] + (long long)G.ny * c[2]);
-      fxp[node] = 0;
-      fxp[G.Np + node] = 0;
-      fxp[2 * G.Np + node] = 0;
-      tfp[node >> TILE_SHIFT] = 0;
+      const double c = X[3 * v + k];
+      if (!(c == c)) nan = 1.0;
+      lo[k] = c;
+      hi[k] = c;
     }
   }
+  if (i < b.b_ne[body]) {
+    const int e = b.b_edge0[body] + i;
+    const int p = b.edges[2 * e], c = b.edges[2 * e + 1];
+    const double r[3] = {X[3 * p] - X[3 * c], X[3 * p + 1] - X[3 * c + 1], X[3 * p + 2] - X[3 * c + 2]};
+    strain = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) / b.l0[e];
+  }
+  V = block_sum(V, sh);
+  S = block_sum(S, sh);
+  for (int k = 0; k < 3; k++)
+    for (int m = 32; m >= 1; m >>= 1) {
+      lo[k] = fmin(lo[k], __shfl_xor(lo[k], m, 64));
+      hi[k] = fmax(hi[k], __shfl_xor(hi[k], m, 64));
+    }
+  for (int m = 32; m >= 1; m >>= 1) {
+    strain = fmax(strain, __shfl_xor(strain, m, 64));
+    nan = fmax(nan, __shfl_xor(nan, m, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    for (int k = 0; k < 3; k++) {
+      shm[w][k] = lo[k];
+      shm[w][3 + k] = hi[k];
+    }
+    shm[w][6] = strain;
+    shm[w][7] = nan;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* P = b.diag_part + 12 * (long long)dblk;
+    store_coherent(P, V);
+    store_coherent(P + 1, S);
+    for (int k = 0; k < 8; k++) {
+      double m = shm[0][k];
+      for (int q = 1; q < (int)(blockDim.x >> 6); q++) m = (k < 3) ? fmin(m, shm[q][k]) : fmax(m, shm[q][k]);
+      store_coherent(P + 2 + k, m);
+    }
+  }
+}
+
+// Combine the partials of every body in block order (run by the last
+// block); returns the DAMAGED / UNSTABLE bits found by this thread.
+__device__ unsigned int diag_finalize(const BodyArgs& b) {
+  unsigned int raised = 0u;
+  for (int body = threadIdx.x; body < b.nbody; body += blockDim.x) {
+    double V = 0.0, S = 0.0, lo[3], hi[3], strain = 0.0, nan = 0.0;
+    for (int k = 0; k < 3; k++) {
+      lo[k] = DBL_MAX;
+      hi[k] = -DBL_MAX;
+    }
+    for (int q = b.b_dblk0[body]; q < b.b_dblk0[body + 1]; q++) {
+      const double* P = b.diag_part + 12 * (long long)q;
+      V += load_coherent(P);
+      S += load_coherent(P + 1);
+      for (int k = 0; k < 3; k++) {
+        lo[k] = fmin(lo[k], load_coherent(P + 2 + k));
+        hi[k] = fmax(hi[k], load_coherent(P + 5 + k));
+      }
+      strain = fmax(strain, load_coherent(P + 8));
+      nan = fmax(nan, load_coherent(P + 9));
+    }
+    double* d = b.b_diag + 16 * body;
+    d[0] = V;
+    d[1] = S;
+    for (int k = 0; k < 3; k++) {
+      d[2 + k] = lo[k];
+      d[5 + k] = hi[k];
+    }
+    d[8] = strain;
+    // a link whose length doubles its rest length is damaged (computation stops)
+    if (!b.b_rigid[body] && strain >= 2.0) raised |= ST_DAMAGED;
+    if (nan > 0.0) raised |= ST_UNSTABLE;
+  }
+  return raised;
+}
+
+// ---------------------------------------------------------- k_ib_force
+// First launch of a coupled step, three kinds of blocks:
+//  markers   direct forcing at the face centroids (Eqs. uLag, the direct
+//            forcing equation, bodyforce): U = sum phi u* with u* = sum f e
+//            / rho of the streamed populations (no force), F_l = U_b - U,
+//            spread of c_l phi_k F_l (c_l = face area) in fixed point;
+//  elements  stretching force per edge (Eq. strainFor) and bending force per
+//            hinge, F = -k_b sin(theta - theta0) dtheta/dx (soft bodies);
+//  diag      volume, area, bounding box and stretch of x^n; the last block
+//            combines them and stops the computation before anything of
+//            this step is written when x^n is damaged or not finite.
+template <class S>
+__device__ void ib_marker(const FluidArgs& a, const BodyArgs& b, long long* fxc, uint8_t* tfc,
+                          int m, int lane) {
+  typedef typename Store<S>::C C;
+  const Grid& G = a.g;
   double cen[3], nrm[3], area;
   face_geom(b.Xcur, b.faces, m, cen, nrm, area);
+  const int body = b.face_body[m];
+  double Ub[3];
+  if (b.b_rigid[body]) {
+    const double* rs = b.b_rig + 32 * body;
+    const double r[3] = {cen[0] - rs[0], cen[1] - rs[1], cen[2] - rs[2]};
+    const double* w = rs + 9;
+    Ub[0] = rs[3] + (w[1] * r[2] - w[2] * r[1]);
+    Ub[1] = rs[4] + (w[2] * r[0] - w[0] * r[2]);
+    Ub[2] = rs[5] + (w[0] * r[1] - w[1] * r[0]);
+  } else {
+    const int v0 = b.faces[3 * m], v1 = b.faces[3 * m + 1], v2 = b.faces[3 * m + 2];
+#pragma unroll
+    for (int k = 0; k < 3; k++) Ub[k] = (b.Vel[3 * v0 + k] + b.Vel[3 * v1 + k] + b.Vel[3 * v2 + k]) / 3.0;
+  }
   if (lane == 0) {
     b.centroid[3 * m] = cen[0];
     b.centroid[3 * m + 1] = cen[1];
@@ -618,33 +1007,16 @@ __global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long 
     C mx = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
     C my = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
     C mz = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
-    double rho = 1.0 + (double)drho;
+    const double rho = 1.0 + (double)drho;
     us[0] = (double)mx / rho;
     us[1] = (double)my / rho;
     us[2] = (double)mz / rho;
   }
   double psi[4];
-  const bool ok = mls_psi(s, psi);
-  if (!ok && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
+  if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
   double U[3];
 #pragma unroll
   for (int k = 0; k < 3; k++) U[k] = red32(psi[0] * us[k]);
-  // marker velocity
-  const int body = b.face_body[m];
-  double Ub[3];
-  if (b.b_rigid[body]) {
-    const double* rs = b.b_rig + 32 * body;
-    double r[3] = {cen[0] - rs[0], cen[1] - rs[1], cen[2] - rs[2]};
-    const double* w = rs + 9;
-    Ub[0] = rs[3] + (w[1] * r[2] - w[2] * r[1]);
-    Ub[1] = rs[4] + (w[2] * r[0] - w[0] * r[2]);
-    Ub[2] = rs[5] + (w[0] * r[1] - w[1] * r[0]);
-  } else {
-    const int v0 = b.faces[3 * m], v1 = b.faces[3 * m + 1], v2 = b.faces[3 * m + 2];
-#pragma unroll
-    for (int k = 0; k < 3; k++)
-      Ub[k] = (b.Vel[3 * v0 + k] + b.Vel[3 * v1 + k] + b.Vel[3 * v2 + k]) / 3.0;
-  }
   if (s.valid && psi[0] != 0.0) {
     const double cp = area * psi[0];
     fx_add(fxc + s.node, cp * (Ub[0] - U[0]), a.flags);
@@ -654,14 +1026,80 @@ __global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long 
   }
 }
 
+__device__ void membrane_element(const BodyArgs& b, int idx) {
+  if (idx < b.ne) {
+    const int e = idx;
+    const int va = b.edges[2 * e], vb = b.edges[2 * e + 1];
+    if (b.b_rigid[b.vert_body[va]]) return;
+    // F_a = -k (l - l0) (x_a - x_b) / l
+    const double r[3] = {b.Xcur[3 * va] - b.Xcur[3 * vb], b.Xcur[3 * va + 1] - b.Xcur[3 * vb + 1],
+                         b.Xcur[3 * va + 2] - b.Xcur[3 * vb + 2]};
+    const double l = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double c = -b.kl[e] * (l - b.l0[e]) / l;
+#pragma unroll
+    for (int k = 0; k < 3; k++) b.f_edge[3 * e + k] = c * r[k];
+  } else if (idx < b.ne + b.nh) {
+    const int h = idx - b.ne;
+    const int32_t* H = b.hinges + 4 * h;
+    if (b.b_rigid[b.vert_body[H[0]]]) return;
+    double th, gr[4][3];
+    hinge_all(b.Xcur, H, th, gr);
+    const double amp = -b.kb[h] * sin(th - b.theta0[h]);
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) b.f_hinge[12 * h + 3 * r + k] = amp * gr[r][k];
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long long* fxc,
+                                                  uint8_t* tfc, unsigned int* counter) {
+  if (a.flags->stop) return;
+  const int blk = blockIdx.x;
+  if (blk < b.n_marker_blocks) {
+    const int m = blk * 8 + (threadIdx.x >> 5);
+    if (m < b.nf) ib_marker<S>(a, b, fxc, tfc, m, threadIdx.x & 31);
+  } else if (blk < b.n_marker_blocks + b.n_elem_blocks) {
+    membrane_element(b, (blk - b.n_marker_blocks) * 256 + threadIdx.x);
+  } else {
+    diag_block(b, b.Xcur, blk - b.n_marker_blocks - b.n_elem_blocks);
+    // the diagnostics blocks count themselves; the last one combines them
+    if (last_block(counter, b.n_diag_blocks)) {
+      const unsigned int raised = diag_finalize(b);
+      if (raised) atomicOr(&a.flags->stop, raised);
+      __syncthreads();
+      if (threadIdx.x == 0) *counter = 0u;
+    }
+  }
+}
+
+// Diagnostics of the current positions only (set-up and synchronisation
+// points): fills the body table and stops on damage or non-finite values.
+__global__ __launch_bounds__(256) void k_check(BodyArgs b, const double* X0, const double* X1,
+                                               DevFlags* flags, unsigned int* counter) {
+  if (flags->stop) return;
+  const double* X = (flags->steps_done & 1) ? X1 : X0;
+  if ((int)blockIdx.x < b.n_diag_blocks) diag_block(b, X, blockIdx.x);
+  if (last_block(counter, gridDim.x)) {
+    const unsigned int raised = diag_finalize(b);
+    if (raised) atomicOr(&flags->stop, raised);
+    __syncthreads();
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+}
+
 // ---------------------------------------------------------- k_mls_post
 // Faces (one wave each; lanes 0-31 the outer probe, 32-63 the inner one):
 // pressure p = rho/3 and viscous stress rho nu (grad u + grad u^T) from MLS
-// fits 1.2 dx along +-n (Eqs. hydroForP, hydroForNu), plus the repulsion of
-// centroids of other bodies closer than dx (Eq. collision).  Soft vertices
-// (two per wave): MLS velocity u_v,0 at x_v^n.
+// fits 1.2 dx along +-n (Eqs. hydroForP, hydroForNu), the repulsion of
+// centroids of other bodies closer than dx (Eq. collision) and, for soft
+// bodies, the volume penalty k_v (1 - V/V0) A n (Eq. volFor, outward n).
+// The same waves clear the previous step's spread buffer at the previous
+// stencils.  Soft vertices (two per wave): MLS velocity u_v,0 at x_v^n.
 template <class S>
-__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
+__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b, long long* fxp,
+                                                  uint8_t* tfp) {
   if (a.flags->stop) return;
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
   const int l64 = threadIdx.x & 63, half = l64 >> 5, lane = l64 & 31;
@@ -669,6 +1107,26 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
   const S* f = (const S*)a.B;
   if (wave < b.nf) {
     const int m = wave;
+    const int pbx = b.base_prev[3 * m];
+    if (half == 0 && pbx != INT_MIN && lane < 27) {
+      int c[3] = {pbx + lane % 3 - 1, b.base_prev[3 * m + 1] + (lane / 3) % 3 - 1,
+                  b.base_prev[3 * m + 2] + lane / 9 - 1};
+      const int dim[3] = {G.nx, G.ny, G.nz};
+      bool ok = true;
+      for (int k = 0; k < 3; k++) {
+        if (c[k] < 0 || c[k] >= dim[k]) {
+          if (G.per[k]) c[k] = ((c[k] % dim[k]) + dim[k]) % dim[k];
+          else ok = false;
+        }
+      }
+      if (ok) {
+        const long long node = c[0] + (long long)G.px * (c[1] + (long long)G.ny * c[2]);
+        fxp[node] = 0;
+        fxp[G.Np + node] = 0;
+        fxp[2 * G.Np + node] = 0;
+        tfp[node >> TILE_SHIFT] = 0;
+      }
+    }
     double cen[3], nrm[3], area;
     face_geom(b.Xcur, b.faces, m, cen, nrm, area);
     const double sg = half == 0 ? 1.2 : -1.2;
@@ -678,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
     if (s.valid) macro_at<S>(G, f, a.fx, a.tflag, a.gx, a.gy, a.gz, s.node, rho, u[0], u[1], u[2]);
     double psi[4];
     if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
-    double rfit = red32(psi[0] * rho);
+    const double rfit = red32(psi[0] * rho);
     double Gm[3][3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
@@ -691,7 +1149,6 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
     for (int i = 0; i < 3; i++)
 #pragma unroll
       for (int c = 0; c < 3; c++) Gin[i][c] = __shfl(Gm[i][c], 32, 64);
-    // repulsion from the other bodies
     const int body = b.face_body[m];
     double acc = 0.0;
     if (b.nbody > 1) {
@@ -730,92 +1187,36 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
         F[i] = (-dp * nrm[i] + tn) * area;
       }
       const double pref = b.umax / (8.0 * sqrt(2.0));
+      double cv = 0.0;
+      if (!b.b_rigid[body]) {
+        const double V0 = b.b_param[8 * body], kv = b.b_param[8 * body + 2];
+        cv = kv * (1.0 - b.b_diag[16 * body] / V0) * area;
+      }
 #pragma unroll
-      for (int i = 0; i < 3; i++) b.fext[3 * m + i] = F[i] - pref * acc * nrm[i];
+      for (int i = 0; i < 3; i++) b.fext[3 * m + i] = F[i] - pref * acc * nrm[i] + cv * nrm[i];
     }
-  } else {
-    const int idx = (wave - b.nf) * 2 + half;
-    if (idx >= b.nsoft_v) return;
-    const int v = b.soft_vlist[idx];
-    const double X = b.Xcur[3 * v], Y = b.Xcur[3 * v + 1], Z = b.Xcur[3 * v + 2];
-    const Slot s = stencil_slot(G, a.ncls, X, Y, Z, lane);
-    double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
-    if (s.valid) macro_at<S>(G, f, a.fx, a.tflag, a.gx, a.gy, a.gz, s.node, rho, u[0], u[1], u[2]);
-    double psi[4];
-    if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
-    double U[3];
+    return;
+  }
+  const int idx = (wave - b.nf) * 2 + half;
+  if (idx >= b.nsoft_v) return;
+  const int v = b.soft_vlist[idx];
+  const double X = b.Xcur[3 * v], Y = b.Xcur[3 * v + 1], Z = b.Xcur[3 * v + 2];
+  const Slot s = stencil_slot(G, a.ncls, X, Y, Z, lane);
+  double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
+  if (s.valid) macro_at<S>(G, f, a.fx, a.tflag, a.gx, a.gy, a.gz, s.node, rho, u[0], u[1], u[2]);
+  double psi[4];
+  if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
+  double U[3];
 #pragma unroll
-    for (int k = 0; k < 3; k++) U[k] = red32(psi[0] * u[k]);
-    if (lane == 0) {
-      b.u0v[3 * v] = U[0];
-      b.u0v[3 * v + 1] = U[1];
-      b.u0v[3 * v + 2] = U[2];
-    }
+  for (int k = 0; k < 3; k++) U[k] = red32(psi[0] * u[k]);
+  if (lane == 0) {
+    b.u0v[3 * v] = U[0];
+    b.u0v[3 * v + 1] = U[1];
+    b.u0v[3 * v + 2] = U[2];
   }
 }
 
 // ----------------------------------------------------------- k_body_post
-__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
-  c[0] = a[1] * b[2] - a[2] * b[1];
-  c[1] = a[2] * b[0] - a[0] * b[2];
-  c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-// Gradient of the signed dihedral angle of hinge (a, b, c, d) (faces (a,b,c)
-// and (b,a,d), outward normals) with respect to the vertex in `role`.
-__device__ void hinge_grad(const double* X, const int32_t* h, int role, double& theta,
-                           double (&gr)[3]) {
-  const double* pa = X + 3 * h[0];
-  const double* pb = X + 3 * h[1];
-  const double* pc = X + 3 * h[2];
-  const double* pd = X + 3 * h[3];
-  double e[3], ca[3], da[3], ab[3], db[3], n1[3], n2[3];
-  for (int k = 0; k < 3; k++) {
-    e[k] = pb[k] - pa[k];
-    ca[k] = pc[k] - pa[k];
-    da[k] = pd[k] - pa[k];
-    ab[k] = pa[k] - pb[k];
-    db[k] = pd[k] - pb[k];
-  }
-  cross3(e, ca, n1);
-  cross3(ab, db, n2);
-  const double q1 = n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2];
-  const double q2 = n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2];
-  const double le2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
-  const double le = sqrt(le2);
-  const double l1 = sqrt(q1), l2 = sqrt(q2);
-  double m1[3], m2[3], t[3];
-  for (int k = 0; k < 3; k++) {
-    m1[k] = n1[k] / l1;
-    m2[k] = n2[k] / l2;
-  }
-  cross3(m1, m2, t);
-  theta = atan2((t[0] * e[0] + t[1] * e[1] + t[2] * e[2]) / le,
-                m1[0] * m2[0] + m1[1] * m2[1] + m1[2] * m2[2]);
-  const double al_c = (ca[0] * e[0] + ca[1] * e[1] + ca[2] * e[2]) / le2;
-  const double al_d = (da[0] * e[0] + da[1] * e[1] + da[2] * e[2]) / le2;
-  for (int k = 0; k < 3; k++) {
-    const double gc = -le * n1[k] / q1;
-    const double gd = -le * n2[k] / q2;
-    if (role == 0) gr[k] = -((1.0 - al_c) * gc + (1.0 - al_d) * gd);
-    else if (role == 1) gr[k] = -(al_c * gc + al_d * gd);
-    else if (role == 2) gr[k] = gc;
-    else gr[k] = gd;
-  }
-}
-
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  // deterministic: fixed lane tree in each wave, then fixed order over waves
-  v = red64(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int k = 0; k < (int)(blockDim.x >> 6); k++) t += sh[k];
-  return t;
-}
-
 __device__ void rodrigues(const double* phi, double* R) {
   const double th = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
   if (th == 0.0) {
@@ -835,253 +1236,160 @@ __device__ double det3(const double* A) {
          A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 
-__global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags) {
-  if (flags->stop) return;
+// Rigid body (one block): total force and moment about the centre of mass
+// from one third of each face force at its vertices, second-order backward
+// update of u and omega (Eq. angularVelRig with the Newton-Euler system,
+// inertia rotated with the body), x_c += u, rotation by omega (Rodrigues).
+__device__ void rigid_block(const BodyArgs& b, int body) {
   __shared__ double sh[8];
   __shared__ double rs[32];
-  const int blk = blockIdx.x;
-  if (blk < b.nbody) {
-    // rigid (or fixed) body: one block
-    if (!b.b_rigid[blk]) return;
-    const int v0 = b.b_vert0[blk], nv = b.b_nv[blk];
-    double* st = b.b_rig + 32 * blk;
-    if (b.b_fixed[blk]) {
-      for (int v = threadIdx.x; v < nv; v += blockDim.x)
-        for (int k = 0; k < 3; k++) {
-          b.Xnext[3 * (v0 + v) + k] = b.Xcur[3 * (v0 + v) + k];
-          b.Vel[3 * (v0 + v) + k] = 0.0;
-        }
-      return;
-    }
-    const int f0 = b.b_face0[blk], nf = b.b_nf[blk];
-    double F[3] = {0, 0, 0}, M[3] = {0, 0, 0};
-    const double xc[3] = {st[0], st[1], st[2]};
-    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
-      const double* Ff = b.fext + 3 * (f0 + f);
-      for (int k = 0; k < 3; k++) F[k] += Ff[k];
-      for (int c = 0; c < 3; c++) {
-        const int v = b.faces[3 * (f0 + f) + c];
-        double r[3] = {b.Xcur[3 * v] - xc[0], b.Xcur[3 * v + 1] - xc[1], b.Xcur[3 * v + 2] - xc[2]};
-        double t[3];
-        double Fv[3] = {Ff[0] / 3.0, Ff[1] / 3.0, Ff[2] / 3.0};
-        cross3(r, Fv, t);
-        for (int k = 0; k < 3; k++) M[k] += t[k];
-      }
-    }
-    for (int k = 0; k < 3; k++) {
-      F[k] = block_sum(F[k], sh);
-      M[k] = block_sum(M[k], sh);
-    }
-    if (threadIdx.x == 0) {
-      // state: x_c 0-2, u 3-5, u_prev 6-8, omega 9-11, omega_prev 12-14, R 15-23
-      const double* R = st + 15;
-      const double mass = b.b_param[8 * blk + 4];
-      double RI[9], Iw[9];
-      double Ibm[9];  // body-frame inertia tensor, stored after the [nbody][8] parameters
-      for (int k = 0; k < 9; k++) Ibm[k] = b.b_param[8 * b.nbody + 9 * blk + k];
-      for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) {
-          double v = 0.0;
-          for (int k = 0; k < 3; k++) v += R[3 * i + k] * Ibm[3 * k + j];
-          RI[3 * i + j] = v;
-        }
-      for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) {
-          double v = 0.0;
-          for (int k = 0; k < 3; k++) v += RI[3 * i + k] * R[3 * j + k];
-          Iw[3 * i + j] = v;
-        }
-      double al[3];
-      const double dI = det3(Iw);
-      for (int c = 0; c < 3; c++) {
-        double Mm[9];
-        for (int k = 0; k < 9; k++) Mm[k] = Iw[k];
-        for (int r = 0; r < 3; r++) Mm[3 * r + c] = M[r];
-        al[c] = det3(Mm) / dI;
-      }
-      double un[3], wn[3];
+  const int v0 = b.b_vert0[body], nv = b.b_nv[body];
+  double* st = b.b_rig + 32 * body;
+  if (b.b_fixed[body]) {
+    for (int v = threadIdx.x; v < nv; v += blockDim.x)
       for (int k = 0; k < 3; k++) {
-        un[k] = 2.0 / 3.0 * (2.0 * st[3 + k] - 0.5 * st[6 + k] + F[k] / mass);
-        wn[k] = 2.0 / 3.0 * (2.0 * st[9 + k] - 0.5 * st[12 + k] + al[k]);
+        b.Xnext[3 * (v0 + v) + k] = b.Xcur[3 * (v0 + v) + k];
+        b.Vel[3 * (v0 + v) + k] = 0.0;
       }
-      for (int k = 0; k < 3; k++) {
-        st[6 + k] = st[3 + k];
-        st[3 + k] = un[k];
-        st[12 + k] = st[9 + k];
-        st[9 + k] = wn[k];
-        st[k] += un[k];
-      }
-      double Rr[9], Rn[9];
-      rodrigues(wn, Rr);
-      for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) {
-          double v = 0.0;
-          for (int k = 0; k < 3; k++) v += Rr[3 * i + k] * R[3 * k + j];
-          Rn[3 * i + j] = v;
-        }
-      for (int k = 0; k < 9; k++) st[15 + k] = Rn[k];
-      for (int k = 0; k < 24; k++) rs[k] = st[k];
-    }
-    __syncthreads();
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-      const double* Xb = b.Xbody + 3 * (v0 + v);
-      double r[3], wr[3];
-      for (int i = 0; i < 3; i++) r[i] = rs[15 + 3 * i] * Xb[0] + rs[15 + 3 * i + 1] * Xb[1] + rs[15 + 3 * i + 2] * Xb[2];
-      cross3(rs + 9, r, wr);
-      for (int k = 0; k < 3; k++) {
-        b.Xnext[3 * (v0 + v) + k] = rs[k] + r[k];
-        b.Vel[3 * (v0 + v) + k] = rs[3 + k] + wr[k];
-      }
-    }
     return;
   }
-  // soft vertices: membrane forces + Verlet (Eqs. verletPos, verletVel, verletPosC)
-  const int idx = (blk - b.nbody) * 256 + threadIdx.x;
-  if (idx >= b.nsoft_v) return;
+  const int f0 = b.b_face0[body], nf = b.b_nf[body];
+  double F[3] = {0, 0, 0}, M[3] = {0, 0, 0};
+  const double xc[3] = {st[0], st[1], st[2]};
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+    const double* Ff = b.fext + 3 * (f0 + f);
+    for (int k = 0; k < 3; k++) F[k] += Ff[k];
+    const double Fv[3] = {Ff[0] / 3.0, Ff[1] / 3.0, Ff[2] / 3.0};
+    for (int c = 0; c < 3; c++) {
+      const int v = b.faces[3 * (f0 + f) + c];
+      const double r[3] = {b.Xcur[3 * v] - xc[0], b.Xcur[3 * v + 1] - xc[1], b.Xcur[3 * v + 2] - xc[2]};
+      double t[3];
+      cross3(r, Fv, t);
+      for (int k = 0; k < 3; k++) M[k] += t[k];
+    }
+  }
+  for (int k = 0; k < 3; k++) {
+    F[k] = block_sum(F[k], sh);
+    M[k] = block_sum(M[k], sh);
+  }
+  if (threadIdx.x == 0) {
+    // state: x_c 0-2, u 3-5, u_prev 6-8, omega 9-11, omega_prev 12-14, R 15-23
+    const double* R = st + 15;
+    const double mass = b.b_param[8 * body + 4];
+    double Ibm[9];  // body-frame inertia tensor, stored after the [nbody][8] parameters
+    for (int k = 0; k < 9; k++) Ibm[k] = b.b_param[8 * b.nbody + 9 * body + k];
+    double RI[9], Iw[9];
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double v = 0.0;
+        for (int k = 0; k < 3; k++) v += R[3 * i + k] * Ibm[3 * k + j];
+        RI[3 * i + j] = v;
+      }
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double v = 0.0;
+        for (int k = 0; k < 3; k++) v += RI[3 * i + k] * R[3 * j + k];
+        Iw[3 * i + j] = v;
+      }
+    double al[3];
+    const double dI = det3(Iw);
+    for (int c = 0; c < 3; c++) {
+      double Mm[9];
+      for (int k = 0; k < 9; k++) Mm[k] = Iw[k];
+      for (int r = 0; r < 3; r++) Mm[3 * r + c] = M[r];
+      al[c] = det3(Mm) / dI;
+    }
+    double un[3], wn[3];
+    for (int k = 0; k < 3; k++) {
+      un[k] = 2.0 / 3.0 * (2.0 * st[3 + k] - 0.5 * st[6 + k] + F[k] / mass);
+      wn[k] = 2.0 / 3.0 * (2.0 * st[9 + k] - 0.5 * st[12 + k] + al[k]);
+    }
+    for (int k = 0; k < 3; k++) {
+      st[6 + k] = st[3 + k];
+      st[3 + k] = un[k];
+      st[12 + k] = st[9 + k];
+      st[9 + k] = wn[k];
+      st[k] += un[k];
+    }
+    double Rr[9], Rn[9];
+    rodrigues(wn, Rr);
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double v = 0.0;
+        for (int k = 0; k < 3; k++) v += Rr[3 * i + k] * R[3 * k + j];
+        Rn[3 * i + j] = v;
+      }
+    for (int k = 0; k < 9; k++) st[15 + k] = Rn[k];
+    for (int k = 0; k < 24; k++) rs[k] = st[k];
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    const double* Xb = b.Xbody + 3 * (v0 + v);
+    double r[3], wr[3];
+    for (int i = 0; i < 3; i++) r[i] = rs[15 + 3 * i] * Xb[0] + rs[15 + 3 * i + 1] * Xb[1] + rs[15 + 3 * i + 2] * Xb[2];
+    cross3(rs + 9, r, wr);
+    for (int k = 0; k < 3; k++) {
+      b.Xnext[3 * (v0 + v) + k] = rs[k] + r[k];
+      b.Vel[3 * (v0 + v) + k] = rs[3 + k] + wr[k];
+    }
+  }
+}
+
+// Soft vertex: gather the element forces (stretching per edge, bending per
+// hinge, one third of each face's volume + hydrodynamic + repulsion force),
+// then the Verlet update with the MLS tentative velocity (Eqs. verletPos,
+// verletVel, verletPosC, dt = 1).
+__device__ void soft_vertex(const BodyArgs& b, int idx) {
   const int v = b.soft_vlist[idx];
   const int body = b.vert_body[v];
   const double* x = b.Xcur;
   const double xv[3] = {x[3 * v], x[3 * v + 1], x[3 * v + 2]};
   double F[3] = {0.0, 0.0, 0.0};
-  // stretching: F_v = -k (l - l0) (x_v - x_w) / l
-  for (int p = b.ve_ptr[v]; p < b.ve_ptr[v + 1]; p++) {
-    const int e = b.ve_idx[p];
-    const int w = b.edges[2 * e] == v ? b.edges[2 * e + 1] : b.edges[2 * e];
-    double r[3] = {xv[0] - x[3 * w], xv[1] - x[3 * w + 1], xv[2] - x[3 * w + 2]};
-    const double l = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    const double c = -b.kl[e] * (l - b.l0[e]) / l;
-    for (int k = 0; k < 3; k++) F[k] += c * r[k];
+  int32_t t[VT_SLOTS];
+#pragma unroll
+  for (int k = 0; k < VT_SLOTS; k++) t[k] = b.vtab[(long long)k * b.nv + v];
+#pragma unroll
+  for (int k = 0; k < VT_E; k++) {
+    if (t[k] == 0) continue;
+    const int e = (t[k] > 0 ? t[k] : -t[k]) - 1;
+    const double sg = t[k] > 0 ? 1.0 : -1.0;
+    for (int c = 0; c < 3; c++) F[c] += sg * b.f_edge[3 * e + c];
   }
-  // bending: F = -k_b sin(theta - theta0) dtheta/dx
-  for (int p = b.vh_ptr[v]; p < b.vh_ptr[v + 1]; p++) {
-    const int hr = b.vh_idx[p];
-    const int h = hr >> 2, role = hr & 3;
-    double th, gr[3];
-    hinge_grad(x, b.hinges + 4 * h, role, th, gr);
-    const double amp = -b.kb[h] * sin(th - b.theta0[h]);
-    for (int k = 0; k < 3; k++) F[k] += amp * gr[k];
+#pragma unroll
+  for (int k = VT_E; k < VT_E + VT_H; k++) {
+    if (t[k] == 0) continue;
+    const int hr = t[k] - 1;
+    for (int c = 0; c < 3; c++) F[c] += b.f_hinge[3 * hr + c];
   }
-  // volume penalty k_v (1 - V/V0) A n / 3 and one third of each face's
-  // hydrodynamic + repulsion force
-  const double V0 = b.b_param[8 * body], kv = b.b_param[8 * body + 2];
-  const double Vc = b.b_diag[16 * body];
-  const double cv = kv * (1.0 - Vc / V0);
-  for (int p = b.vf_ptr[v]; p < b.vf_ptr[v + 1]; p++) {
-    const int f = b.vf_idx[p];
-    double c[3], n[3], area;
-    face_geom(x, b.faces, f, c, n, area);
-    for (int k = 0; k < 3; k++) F[k] += (cv * area * n[k] + b.fext[3 * f + k]) / 3.0;
+#pragma unroll
+  for (int k = VT_E + VT_H; k < VT_SLOTS; k++) {
+    if (t[k] == 0) continue;
+    const int f = t[k] - 1;
+    for (int c = 0; c < 3; c++) F[c] += b.fext[3 * f + c] / 3.0;
   }
   const double mv = b.b_param[8 * body + 3];
   for (int k = 0; k < 3; k++) {
     const double acc = 0.5 * F[k] / mv;
-    const double xt = xv[k] + b.u0v[3 * v + k] + acc;
-    const double un = 1.5 * xt - 2.0 * xv[k] + 0.5 * b.Xnext[3 * v + k];
-    b.Xnext[3 * v + k] = xv[k] + un + acc;
+    const double xt = xv[k] + b.u0v[3 * v + k] + acc;                  // predictor
+    const double un = 1.5 * xt - 2.0 * xv[k] + 0.5 * b.Xnext[3 * v + k];  // velocity
+    b.Xnext[3 * v + k] = xv[k] + un + acc;                             // corrector
     b.Vel[3 * v + k] = un;
   }
 }
 
-// --------------------------------------------------------------- k_diag
-// Per body (one block): volume, area, bounding box, largest stretch of the
-// new positions; a soft link at twice its rest length raises DAMAGED.  The
-// last block to finish closes the step: steps_done += 1 and the bits raised
-// during the step become sticky.
-__global__ __launch_bounds__(256) void k_diag(BodyArgs b, const double* X, DevFlags* flags,
-                                              unsigned int* counter, int count) {
+// Last launch of a coupled step: rigid blocks, then soft-vertex blocks; the
+// last block to finish closes the step.
+__global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags,
+                                                   unsigned int* counter) {
   if (flags->stop) return;
-  __shared__ double sh[8];
-  __shared__ int last;
   const int blk = blockIdx.x;
   if (blk < b.nbody) {
-    const int f0 = b.b_face0[blk], nf = b.b_nf[blk];
-    double V = 0.0, S = 0.0;
-    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
-      const int* F = b.faces + 3 * (f0 + f);
-      const double* pa = X + 3 * F[0];
-      const double* pb = X + 3 * F[1];
-      const double* pc = X + 3 * F[2];
-      double bc[3];
-      cross3(pb, pc, bc);
-      V += (pa[0] * bc[0] + pa[1] * bc[1] + pa[2] * bc[2]) / 6.0;
-      double c[3], n[3], area;
-      face_geom(X, b.faces, f0 + f, c, n, area);
-      S += area;
-    }
-    V = block_sum(V, sh);
-    S = block_sum(S, sh);
-    const int v0 = b.b_vert0[blk], nv = b.b_nv[blk];
-    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
-    bool nan = false;
-    for (int v = threadIdx.x; v < nv; v += blockDim.x)
-      for (int k = 0; k < 3; k++) {
-        const double c = X[3 * (v0 + v) + k];
-        nan = nan || !(c == c);
-        lo[k] = fmin(lo[k], c);
-        hi[k] = fmax(hi[k], c);
-      }
-    double strain = 0.0;
-    const int e0 = b.b_edge0[blk], ne = b.b_ne[blk];
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-      const int a = b.edges[2 * (e0 + e)], c = b.edges[2 * (e0 + e) + 1];
-      double r[3] = {X[3 * a] - X[3 * c], X[3 * a + 1] - X[3 * c + 1], X[3 * a + 2] - X[3 * c + 2]};
-      strain = fmax(strain, sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) / b.l0[e0 + e]);
-    }
-    // min/max reductions (order independent)
-    for (int k = 0; k < 3; k++) {
-      for (int m = 32; m >= 1; m >>= 1) {
-        lo[k] = fmin(lo[k], __shfl_xor(lo[k], m, 64));
-        hi[k] = fmax(hi[k], __shfl_xor(hi[k], m, 64));
-      }
-    }
-    for (int m = 32; m >= 1; m >>= 1) strain = fmax(strain, __shfl_xor(strain, m, 64));
-    __shared__ double shm[4][7];
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-      for (int k = 0; k < 3; k++) {
-        shm[w][k] = lo[k];
-        shm[w][3 + k] = hi[k];
-      }
-      shm[w][6] = strain;
-    }
-    if (nan) atomicOr(&flags->pending, ST_UNSTABLE);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double* d = b.b_diag + 16 * blk;
-      for (int k = 0; k < 3; k++) {
-        double l = shm[0][k], h = shm[0][3 + k];
-        for (int q = 1; q < (int)(blockDim.x >> 6); q++) {
-          l = fmin(l, shm[q][k]);
-          h = fmax(h, shm[q][3 + k]);
-        }
-        d[2 + k] = l;
-        d[5 + k] = h;
-      }
-      double s = shm[0][6];
-      for (int q = 1; q < (int)(blockDim.x >> 6); q++) s = fmax(s, shm[q][6]);
-      d[0] = V;
-      d[1] = S;
-      d[8] = s;
-      if (!b.b_rigid[blk] && s >= 2.0) atomicOr(&flags->pending, ST_DAMAGED);
-    }
+    if (b.b_rigid[blk]) rigid_block(b, blk);
+  } else {
+    const int idx = (blk - b.nbody) * 256 + threadIdx.x;
+    if (idx < b.nsoft_v) soft_vertex(b, idx);
   }
-  // step bookkeeping by the last block to finish
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned int done = atomicAdd(counter, 1u);
-    last = (done == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    const unsigned int pend = __hip_atomic_load(&flags->pending, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (count) flags->steps_done += 1;
-    flags->stop |= pend;
-    flags->pending = 0u;
-    *counter = 0u;
-  }
+  if (last_block(counter, gridDim.x)) close_step(flags, counter);
 }
 
 // ------------------------------------------------------------ API kernels
@@ -1221,53 +1529,69 @@ hipError_t launch_init(int prec, const Grid& g, void* f, const uint8_t* ncls, co
   return hipGetLastError();
 }
 
-hipError_t launch_fluid(int prec, const FluidArgs& a, hipStream_t s) {
-  const unsigned grid = (unsigned)a.nbulk_blocks + cdiv(a.nrec, 256);
-  if (grid == 0) return hipSuccess;
+hipError_t launch_fluid_bulk(int prec, const FluidArgs& a, hipStream_t s) {
+  if (a.nbulk_blocks == 0) return hipSuccess;
+  const unsigned grid = (unsigned)a.nbulk_blocks;
   switch (prec) {
-    case 0: k_fluid<double><<<grid, 256, 0, s>>>(a); break;
-    case 1: k_fluid<float><<<grid, 256, 0, s>>>(a); break;
-    default: k_fluid<_Float16><<<grid, 256, 0, s>>>(a); break;
+    case 0: k_fluid_bulk<double><<<grid, 256, 0, s>>>(a); break;
+    case 1: k_fluid_bulk<float><<<grid, 256, 0, s>>>(a); break;
+    default: k_fluid_bulk<_Float16><<<grid, 256, 0, s>>>(a); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fluid_rec(int prec, const FluidArgs& a, hipStream_t s) {
+  if (a.nrec == 0) return hipSuccess;
+  const unsigned grid = cdiv(a.nrec, a.rec_lanes ? 8 : 256);
+  switch (prec) {
+    case 0: k_fluid_rec<double><<<grid, 256, 0, s>>>(a); break;
+    case 1: k_fluid_rec<float><<<grid, 256, 0, s>>>(a); break;
+    default: k_fluid_rec<_Float16><<<grid, 256, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_close(DevFlags* flags, hipStream_t s) {
+  k_close<<<1, 1, 0, s>>>(flags);
   return hipGetLastError();
 }
 
 hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fxc,
-                           uint8_t* tfc, long long* fxp, uint8_t* tfp, hipStream_t s) {
-  if (b.nf == 0) return hipSuccess;
-  const unsigned grid = cdiv((long long)b.nf * 32, 256);
+                           uint8_t* tfc, unsigned int* counter, hipStream_t s) {
+  const unsigned grid = (unsigned)(b.n_marker_blocks + b.n_elem_blocks + b.n_diag_blocks);
+  if (grid == 0) return hipSuccess;
   switch (prec) {
-    case 0: k_ib_force<double><<<grid, 256, 0, s>>>(a, b, fxc, tfc, fxp, tfp); break;
-    case 1: k_ib_force<float><<<grid, 256, 0, s>>>(a, b, fxc, tfc, fxp, tfp); break;
-    default: k_ib_force<_Float16><<<grid, 256, 0, s>>>(a, b, fxc, tfc, fxp, tfp); break;
+    case 0: k_ib_force<double><<<grid, 256, 0, s>>>(a, b, fxc, tfc, counter); break;
+    case 1: k_ib_force<float><<<grid, 256, 0, s>>>(a, b, fxc, tfc, counter); break;
+    default: k_ib_force<_Float16><<<grid, 256, 0, s>>>(a, b, fxc, tfc, counter); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s) {
+hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, long long* fxp,
+                           uint8_t* tfp, hipStream_t s) {
   const long long waves = (long long)b.nf + (b.nsoft_v + 1) / 2;
   if (waves == 0) return hipSuccess;
   const unsigned grid = cdiv(waves * 64, 256);
   switch (prec) {
-    case 0: k_mls_post<double><<<grid, 256, 0, s>>>(a, b); break;
-    case 1: k_mls_post<float><<<grid, 256, 0, s>>>(a, b); break;
-    default: k_mls_post<_Float16><<<grid, 256, 0, s>>>(a, b); break;
+    case 0: k_mls_post<double><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
+    case 1: k_mls_post<float><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
+    default: k_mls_post<_Float16><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s) {
+hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter,
+                            hipStream_t s) {
   const unsigned grid = (unsigned)b.nbody + cdiv(b.nsoft_v, 256);
-  if (grid == 0) return hipSuccess;
-  k_body_post<<<grid, 256, 0, s>>>(b, flags);
+  k_body_post<<<grid, 256, 0, s>>>(b, flags, counter);
   return hipGetLastError();
 }
 
-hipError_t launch_end(const BodyArgs& b, const double* X, DevFlags* flags, int count,
-                      hipStream_t s) {
-  const unsigned grid = b.nbody > 0 ? (unsigned)b.nbody : 1u;
-  // the block counter lives right after the flags word
-  k_diag<<<grid, 256, 0, s>>>(b, X, flags, (unsigned int*)(flags + 1), count);
+hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
+                        unsigned int* counter, hipStream_t s) {
+  if (b.nbody == 0) return hipSuccess;
+  k_check<<<(unsigned)b.n_diag_blocks, 256, 0, s>>>(b, X0, X1, flags, counter);
   return hipGetLastError();
 }
 
