@@ -24,9 +24,9 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(HERE, "csrc", os.path.basename(src) + ".o")
         cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"),
-                   "-c", src, "-o", obj]
+        if src.endswith(".cpp"):  # host code only
+            cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+                   "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -14,7 +14,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "lbm_internal.h"
 
 using namespace lbm;
@@ -65,8 +65,8 @@ struct lbm_ctx {
   int32_t* rec_link0 = nullptr;
   uint8_t* rec_face = nullptr;
   double* rec_bc = nullptr;
-  uint8_t* lk_dm = nullptr;
-  double* lk_q = nullptr;
+  double* lk_c = nullptr;
+  int nlinks_rec = 0;
   int32_t* tile_list = nullptr;
   int nbulk_blocks = 0;
   long long ntiles = 0;
@@ -87,6 +87,9 @@ struct lbm_ctx {
   // graphs
   bool use_graph = true;
   int rec_lanes = 0;
+  int rec_block = 64;
+  int bulk_v = 4;
+  int bulk_block = 256;
   bool graph_valid = false;
   hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   int64_t enq = 0;
@@ -155,7 +158,25 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   if ((long long)d->nx * d->ny * d->nz > (1LL << 31) - (1LL << 20)) return bad("grid too large");
   ctx->stream = (hipStream_t)hip_stream;
   ctx->prec = d->precision;
+  // launch shape (defaults; overridable for tuning)
+  // small (cache-resident, latency-bound) grids: one node per thread and
+  // 64-thread blocks; large (HBM-bound) grids: 16-byte accesses per thread
+  const bool large = (long long)d->nx * d->ny * d->nz >= (4LL << 20);
+  ctx->bulk_v = large ? (d->precision == 0 ? 2 : (d->precision == 1 ? 4 : 8)) : (d->precision == 2 ? 2 : 1);
+  ctx->bulk_block = large ? 256 : 64;
   if (const char* ev = getenv("LBM_RECORD_LANES")) ctx->rec_lanes = atoi(ev) != 0;
+  if (const char* ev = getenv("LBM_RECORD_BLOCK")) ctx->rec_block = atoi(ev);
+  if (const char* ev = getenv("LBM_BULK_V")) ctx->bulk_v = atoi(ev);
+  if (const char* ev = getenv("LBM_BULK_BLOCK")) ctx->bulk_block = atoi(ev);
+  {
+    const int pv = d->precision;
+    const bool vok = (pv == 0 && (ctx->bulk_v == 1 || ctx->bulk_v == 2)) ||
+                     (pv == 1 && (ctx->bulk_v == 1 || ctx->bulk_v == 2 || ctx->bulk_v == 4)) ||
+                     (pv == 2 && (ctx->bulk_v == 2 || ctx->bulk_v == 4 || ctx->bulk_v == 8));
+    if (!vok || (ctx->bulk_block != 64 && ctx->bulk_block != 128 && ctx->bulk_block != 256) ||
+        (ctx->rec_block != 64 && ctx->rec_block != 128 && ctx->rec_block != 256))
+      return bad("unsupported launch shape");
+  }
   ctx->ssize = d->precision == 0 ? 8 : (d->precision == 1 ? 4 : 2);
   ctx->tau = d->tau;
   ctx->umax = d->u_max;
@@ -217,8 +238,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   std::vector<int32_t> r_link0;
   std::vector<uint8_t> r_face;
   std::vector<double> r_bc;  // 4 per record, transposed later
-  std::vector<uint8_t> l_dm;
-  std::vector<double> l_q;
+  std::vector<double> l_c;  // 5 per link, transposed below
   long long n_inlet_seen = 0;
   for (int z = 0; z < nz; z++)
     for (int y = 0; y < ny; y++)
@@ -265,7 +285,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
         rec_of[p] = (int32_t)r_node.size();
         r_node.push_back((int32_t)p);
         r_mask.push_back(mask);
-        r_link0.push_back((int32_t)l_q.size());
+        r_link0.push_back((int32_t)(l_c.size() / 5));
         uint8_t fc = 0xff;
         double bc[4] = {0, 0, 0, 0};
         if (open) {
@@ -288,11 +308,29 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
           const bool a1 = nb(x, y, z, HX[j], HY[j], HZ[j], c1) && nt[lin(c1[0], c1[1], c1[2])] != LBM_NODE_SOLID;
           const bool a2 = nb(x, y, z, 2 * HX[j], 2 * HY[j], 2 * HZ[j], c2) &&
                           nt[lin(c2[0], c2[1], c2[2])] != LBM_NODE_SOLID;
-          uint8_t mode;
-          if (q < 0.5) mode = (a1 && a2) ? BFL_QUAD_LO : (a1 ? BFL_LIN_LO : BFL_BB);
-          else mode = a1 ? BFL_QUAD_HI : BFL_LIN_HI;
-          l_dm.push_back((uint8_t)(j | (mode << 5)));
-          l_q.push_back(q);
+          // Eq. bbouzidi as c0 f*_i(x) + c1 f*_i(x-e_i) + c2 f*_i(x-2e_i) + c3 f*_j(x)
+          // + c4 f*_j(x-e_i); linear / plain bounce-back where neighbours are missing
+          double c[5] = {0, 0, 0, 0, 0};
+          if (q < 0.5) {
+            if (a1 && a2) {
+              c[0] = q * (1.0 + 2.0 * q);
+              c[1] = 1.0 - 4.0 * q * q;
+              c[2] = -q * (1.0 - 2.0 * q);
+            } else if (a1) {
+              c[0] = 2.0 * q;
+              c[1] = 1.0 - 2.0 * q;
+            } else {
+              c[0] = 1.0;
+            }
+          } else if (a1) {
+            c[0] = 1.0 / (q * (2.0 * q + 1.0));
+            c[3] = (2.0 * q - 1.0) / q;
+            c[4] = (1.0 - 2.0 * q) / (1.0 + 2.0 * q);
+          } else {
+            c[0] = 1.0 / (2.0 * q);
+            c[3] = (2.0 * q - 1.0) / (2.0 * q);
+          }
+          for (int k = 0; k < 5; k++) l_c.push_back(c[k]);
         }
       }
   for (const auto& kv : links)
@@ -302,8 +340,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   for (int r = 0; r < ctx->nrec; r++)
     for (int a = 0; a < 4; a++) bcT[(size_t)a * ctx->nrec + r] = r_bc[4 * (size_t)r + a];
   // bulk tiles: blocks of 256 threads x V nodes holding at least one bulk node
-  const int V = ctx->prec == 0 ? 2 : (ctx->prec == 1 ? 4 : 8);
-  const long long tnodes = 256LL * V;
+  const long long tnodes = (long long)ctx->bulk_block * ctx->bulk_v;
   std::vector<int32_t> tiles;
   for (long long t = 0; t * tnodes < G.Np; t++) {
     bool any = false;
@@ -331,8 +368,12 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   CHK(upload(&ctx->rec_link0, r_link0));
   CHK(upload(&ctx->rec_face, r_face));
   CHK(upload(&ctx->rec_bc, bcT));
-  CHK(upload(&ctx->lk_dm, l_dm));
-  CHK(upload(&ctx->lk_q, l_q));
+  const size_t nl = l_c.size() / 5;
+  std::vector<double> lcT(l_c.size());
+  for (size_t k = 0; k < nl; k++)
+    for (int c = 0; c < 5; c++) lcT[c * nl + k] = l_c[5 * k + c];
+  ctx->nlinks_rec = (int)nl;
+  CHK(upload(&ctx->lk_c, lcT));
   CHK(upload(&ctx->tile_list, tiles));
   CHK(hipMalloc(&ctx->flags, sizeof(DevFlags) + 64));
   CHK(hipMemset(ctx->flags, 0, sizeof(DevFlags) + 64));
@@ -360,7 +401,7 @@ extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
   free_graphs(ctx);
   free_bodies(ctx);
   void* ptrs[] = {ctx->f_alloc[0], ctx->f_alloc[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
-                  ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_dm, ctx->lk_q,
+                  ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_c,
                   ctx->tile_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
                   ctx->flags};
   for (void* p : ptrs)
@@ -809,8 +850,8 @@ static FluidArgs fluid_args(lbm_ctx* ctx, int p) {
   a.rec_link0 = ctx->rec_link0;
   a.rec_face = ctx->rec_face;
   a.rec_bc = ctx->rec_bc;
-  a.lk_dm = ctx->lk_dm;
-  a.lk_q = ctx->lk_q;
+  a.lk_c = ctx->lk_c;
+  a.nlinks = ctx->nlinks_rec;
   a.tile_list = ctx->tile_list;
   a.nbulk_blocks = ctx->nbulk_blocks;
   a.omega = 1.0 / ctx->tau;
@@ -822,6 +863,9 @@ static FluidArgs fluid_args(lbm_ctx* ctx, int p) {
   a.tflag = ib ? ctx->tf[p] : nullptr;
   a.flags = ctx->flags;
   a.rec_lanes = ctx->rec_lanes;
+  a.rec_block = ctx->rec_block;
+  a.bulk_v = ctx->bulk_v;
+  a.bulk_block = ctx->bulk_block;
   return a;
 }
 

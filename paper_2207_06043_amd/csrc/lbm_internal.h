@@ -9,16 +9,6 @@ namespace lbm {
 // Node classes used by the fused stream-collide kernel.
 enum : uint8_t { CLS_SOLID = 0, CLS_BULK = 1, CLS_GENERAL = 2 };
 
-// Wall-link interpolation modes, chosen on the host from q and from which of
-// x - e_i, x - 2 e_i are fluid (i = link direction into the wall).
-enum : uint8_t {
-  BFL_QUAD_LO = 1,  // q < 1/2, quadratic through x, x - e_i, x - 2e_i
-  BFL_LIN_LO = 2,   // q < 1/2, x - 2e_i unavailable: linear
-  BFL_BB = 3,       // q < 1/2, x - e_i unavailable: plain bounce-back
-  BFL_QUAD_HI = 4,  // q >= 1/2, quadratic (needs x - e_i)
-  BFL_LIN_HI = 5    // q >= 1/2, x - e_i unavailable: linear
-};
-
 // Status bits raised on the device.
 enum : uint32_t { ST_UNSTABLE = 1u, ST_DAMAGED = 2u };
 
@@ -63,8 +53,8 @@ struct FluidArgs {
   const int32_t* rec_link0;
   const uint8_t* rec_face;   // 0xff: none; else face | (kind << 4) (kind 1 = density)
   const double* rec_bc;      // [4][nrec]: ux, uy, uz, rho
-  const uint8_t* lk_dm;      // dir | mode << 5
-  const double* lk_q;
+  const double* lk_c;        // [5][nlinks] interpolated bounce-back coefficients
+  int nlinks;
   const int32_t* tile_list;  // blocks of the bulk part
   int nbulk_blocks;
   double omega;              // 1/tau
@@ -75,6 +65,9 @@ struct FluidArgs {
   unsigned int* counter;     // block counter used when this launch closes the step
   int close_step;            // 1: no bodies, this launch is the whole step
   int rec_lanes;             // boundary records: 1 = 32 lanes per record, 0 = one thread
+  int rec_block;             // threads per block of the record kernel (one-thread mode)
+  int bulk_v;                // nodes per thread of the bulk kernel
+  int bulk_block;            // threads per block of the bulk kernel
 };
 
 // Bodies (all concatenated).

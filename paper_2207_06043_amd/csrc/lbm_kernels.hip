@@ -44,38 +44,42 @@ struct Store;
 template <>
 struct Store<double> {
   typedef double C;
-  static constexpr int V = 2;
-  typedef double vec __attribute__((ext_vector_type(2)));
-  typedef double vecu __attribute__((ext_vector_type(2), aligned(8)));
 };
 template <>
 struct Store<float> {
   typedef float C;
-  static constexpr int V = 4;
-  typedef float vec __attribute__((ext_vector_type(4)));
-  typedef float vecu __attribute__((ext_vector_type(4), aligned(4)));
 };
 template <>
 struct Store<_Float16> {
   typedef float C;
-  static constexpr int V = 8;
-  typedef _Float16 vec __attribute__((ext_vector_type(8)));
-  typedef _Float16 vecu __attribute__((ext_vector_type(8), aligned(2)));
 };
+// V consecutive populations of one plane: aligned and element-aligned forms.
+template <class S, int V>
+struct Vec {
+  typedef S a __attribute__((ext_vector_type(V)));
+  typedef S u __attribute__((ext_vector_type(V), aligned(sizeof(S))));
+};
+template <int V>
+struct ClsWord;
+template <>
+struct ClsWord<1> { typedef uint8_t T; };
+template <>
+struct ClsWord<2> { typedef uint16_t T; };
+template <>
+struct ClsWord<4> { typedef uint32_t T; };
+template <>
+struct ClsWord<8> { typedef uint64_t T; };
 
 // ------------------------------------------------------------ index helpers
-__device__ __forceinline__ int wrapc(int c, int n) {
-  if (c < 0 || c >= n) c = ((c % n) + n) % n;
-  return c;
+__device__ __forceinline__ int wrap2(int c, int n) {  // |c| excursion <= 2 cells
+  c = c < 0 ? c + n : (c >= n ? c - n : c);
+  return c < 0 ? c + n : (c >= n ? c - n : c);
 }
-
-// Node at (x,y,z)+(dx,dy,dz) with periodic wrap (the host guarantees the
-// target is inside the box or across a periodic face).
 __device__ __forceinline__ long long nbr(const Grid& G, int x, int y, int z, int dx, int dy,
                                          int dz) {
-  x = wrapc(x + dx, G.nx);
-  y = wrapc(y + dy, G.ny);
-  z = wrapc(z + dz, G.nz);
+  x = wrap2(x + dx, G.nx);
+  y = wrap2(y + dy, G.ny);
+  z = wrap2(z + dz, G.nz);
   return x + (long long)G.px * (y + (long long)G.ny * z);
 }
 
@@ -142,63 +146,64 @@ __device__ __forceinline__ typename Store<S>::C ldA(const FluidArgs& a, int j, l
 
 // Zou-He on an open face (Eq. extbound, general inward normal n = s e_ax),
 // on deviations: rho_w = (1 + G0 + 2 Gout)/(1 - u_n) for a velocity face,
-// u_n = (rho_w - 1 - G0 - 2 Gout)/rho_w for a density face (tangential u = 0).
+// u_n = (rho_w - 1 - G0 - 2 Gout)/rho_w for a density face (tangential u = 0);
+// unknowns (e.n = +1): axis  g = g_opp + rho_w/3 u_n,
+// diagonal e = n + t: g = g_opp + rho_w/6 (u_n + u.t) - N_t with
+// N_t = 1/2 sum_{e.n = 0} g (e.t) - rho_w/3 u.t.  Written with selects on the
+// runtime face so that the code stays small.
 template <class C>
 __device__ void zouhe(C (&g)[19], int face, int kind, C bx, C by, C bz, C brho) {
   const int ax = face >> 1;
   const int s = (face & 1) ? -1 : 1;
-  C G0 = 0, Gout = 0;
+  C G0 = 0, Gout = 0, T[3] = {0, 0, 0};
 #pragma unroll
   for (int j = 0; j < 19; j++) {
-    int e = ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]);
-    int en = s * e;
-    if (en == 0) G0 += g[j];
-    else if (en == -1) Gout += g[j];
+    const int e_ax = ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]);
+    const int en = s * e_ax;
+    G0 += en == 0 ? g[j] : C(0);
+    Gout += en == -1 ? g[j] : C(0);
+    if (EX[j]) T[0] += en == 0 ? C(EX[j]) * g[j] : C(0);
+    if (EY[j]) T[1] += en == 0 ? C(EY[j]) * g[j] : C(0);
+    if (EZ[j]) T[2] += en == 0 ? C(EZ[j]) * g[j] : C(0);
   }
   C u[3] = {bx, by, bz};
   C rho, un;
   if (kind == 0) {
-    un = C(s) * u[ax];
+    un = C(s) * (ax == 0 ? u[0] : (ax == 1 ? u[1] : u[2]));
     rho = (C(1) + G0 + C(2) * Gout) / (C(1) - un);
   } else {
     rho = brho;
     un = (rho - C(1) - G0 - C(2) * Gout) / rho;
-    u[0] = u[1] = u[2] = 0;
-    u[ax] = C(s) * un;
+    u[0] = ax == 0 ? C(s) * un : C(0);
+    u[1] = ax == 1 ? C(s) * un : C(0);
+    u[2] = ax == 2 ? C(s) * un : C(0);
+  }
+  C N[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) N[k] = C(0.5) * T[k] - rho / C(3) * u[k];
+  C out[19];
+#pragma unroll
+  for (int j = 0; j < 19; j++) {
+    const int e_ax = ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]);
+    // tangential part t = e_j - n (zero on the normal axis)
+    const C tx = ax == 0 ? C(0) : C(EX[j]), ty = ax == 1 ? C(0) : C(EY[j]), tz = ax == 2 ? C(0) : C(EZ[j]);
+    const C ut = u[0] * tx + u[1] * ty + u[2] * tz;
+    const C Nt = N[0] * tx + N[1] * ty + N[2] * tz;
+    const bool axis = tx == C(0) && ty == C(0) && tz == C(0);
+    const C fill = axis ? g[OPP[j]] + rho / C(3) * un : g[OPP[j]] + rho / C(6) * (un + ut) - Nt;
+    out[j] = (s * e_ax == 1) ? fill : g[j];
   }
 #pragma unroll
-  for (int j = 1; j < 19; j++) {
-    int e[3] = {EX[j], EY[j], EZ[j]};
-    if (s * e[ax] != 1) continue;
-    int t[3] = {e[0], e[1], e[2]};
-    t[ax] -= s;
-    C val;
-    if (t[0] == 0 && t[1] == 0 && t[2] == 0) {
-      val = g[OPP[j]] + rho / C(3) * un;
-    } else {
-      C ut = u[0] * C(t[0]) + u[1] * C(t[1]) + u[2] * C(t[2]);
-      C Nt = 0;
-#pragma unroll
-      for (int k = 0; k < 19; k++) {
-        int ek[3] = {EX[k], EY[k], EZ[k]};
-        if (ek[ax] != 0) continue;
-        int et = ek[0] * t[0] + ek[1] * t[1] + ek[2] * t[2];
-        if (et != 0) Nt += C(et) * g[k];
-      }
-      Nt = C(0.5) * Nt - rho / C(3) * ut;
-      val = g[OPP[j]] + rho / C(6) * (un + ut) - Nt;
-    }
-    g[j] = val;
-  }
+  for (int j = 0; j < 19; j++) g[j] = out[j];
 }
 
 // Streamed populations of a boundary record: plain pulls (periodic wrap),
-// interpolated bounce-back on wall links (Eq. bbouzidi, modes fixed on the
-// host), Zou-He for the populations entering through an open face.
-// Addresses are formed with periodic wrap, so they lie in the box even for
-// sources the record does not use: all loads are issued first (plain pulls
-// unconditionally, link data and bounce-back neighbours under the link
-// mask) and the arithmetic follows, so one thread waits for memory once.
+// interpolated bounce-back on wall links (Eq. bbouzidi) as
+// c0 f*_i(x) + c1 f*_i(x - e_i) + c2 f*_i(x - 2e_i) + c3 f*_j(x) + c4 f*_j(x - e_i)
+// with coefficients fixed on the host from q and the fluid neighbours, and
+// Zou-He for the populations entering through an open face.  Addresses are
+// formed with periodic wrap, so they lie in the box even where a coefficient
+// is zero: all loads are issued in one batch, then the arithmetic follows.
 template <class S>
 __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19]) {
   typedef typename Store<S>::C C;
@@ -211,8 +216,7 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
   coords(G, node, x, y, z);
   const int face = fc & 7, kind = (fc >> 4) & 1;
   const int ax = face >> 1, s = (face & 1) ? -1 : 1;
-  C self[19], pl[19], b1[19], b2[19], b3[19], q[19];
-  int md[19];
+  C self[19], pl[19], b1[19], b2[19], b3[19], cf[19][5];
 #pragma unroll
   for (int i = 0; i < 19; i++) self[i] = ldA<S>(a, i, node);
 #pragma unroll
@@ -220,12 +224,12 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
   int lk = lk0;
 #pragma unroll
   for (int j = 1; j < 19; j++) {
-    md[j] = 0;
-    q[j] = b1[j] = b2[j] = b3[j] = C(0);
+    cf[j][0] = cf[j][1] = cf[j][2] = cf[j][3] = cf[j][4] = C(0);
+    b1[j] = b2[j] = b3[j] = C(0);
     if ((mask >> j) & 1u) {
       const int i = OPP[j];
-      md[j] = a.lk_dm[lk] >> 5;
-      q[j] = (C)a.lk_q[lk];
+#pragma unroll
+      for (int c = 0; c < 5; c++) cf[j][c] = (C)a.lk_c[(long long)c * a.nlinks + lk];
       ++lk;
       const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
       const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
@@ -237,23 +241,12 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
   g[0] = self[0];
 #pragma unroll
   for (int j = 1; j < 19; j++) {
-    const int i = OPP[j];
     const int e[3] = {EX[j], EY[j], EZ[j]};
-    const C fi_x = self[i], fj_x = self[j], qq = q[j];
-    C v;
-    if (md[j] == 0) v = (fc != 0xff && s * e[ax] == 1) ? C(0) : pl[j];  // unknowns: Zou-He below
-    else if (md[j] == BFL_QUAD_LO)
-      v = qq * (C(1) + C(2) * qq) * fi_x + (C(1) - C(4) * qq * qq) * b1[j] - qq * (C(1) - C(2) * qq) * b2[j];
-    else if (md[j] == BFL_LIN_LO)
-      v = C(2) * qq * fi_x + (C(1) - C(2) * qq) * b1[j];
-    else if (md[j] == BFL_BB)
-      v = fi_x;
-    else if (md[j] == BFL_QUAD_HI)
-      v = fi_x / (qq * (C(2) * qq + C(1))) + (C(2) * qq - C(1)) / qq * fj_x +
-          (C(1) - C(2) * qq) / (C(1) + C(2) * qq) * b3[j];
-    else  // BFL_LIN_HI
-      v = fi_x / (C(2) * qq) + (C(2) * qq - C(1)) / (C(2) * qq) * fj_x;
-    g[j] = v;
+    const bool linked = (mask >> j) & 1u;
+    const C bfl = cf[j][0] * self[OPP[j]] + cf[j][1] * b1[j] + cf[j][2] * b2[j] + cf[j][3] * self[j] +
+                  cf[j][4] * b3[j];
+    const bool unknown = fc != 0xff && s * (ax == 0 ? e[0] : (ax == 1 ? e[1] : e[2])) == 1;
+    g[j] = linked ? bfl : (unknown ? C(0) : pl[j]);
   }
   if (fc != 0xff) {
     zouhe<C>(g, face, kind, (C)a.rec_bc[r], (C)a.rec_bc[a.nrec + r], (C)a.rec_bc[2 * a.nrec + r],
@@ -338,30 +331,20 @@ __device__ __forceinline__ void close_step(DevFlags* flags, unsigned int* counte
 }
 
 // ------------------------------------------------------------- k_fluid
-template <class S>
-struct ClsVec;
-template <>
-struct ClsVec<double> { typedef uint16_t T; };
-template <>
-struct ClsVec<float> { typedef uint32_t T; };
-template <>
-struct ClsVec<_Float16> { typedef uint64_t T; };
-
 // One thread = V consecutive nodes of a row.  The populations carry guard
 // regions of one z-plane plus one row on both sides, so the 19 vector loads
 // stay inside the allocation for any group; values pulled for solid or
 // boundary-record nodes are computed and discarded.
-template <class S>
+template <class S, int V, bool PERX>
 __device__ void fluid_bulk(const FluidArgs& a, int blk) {
   typedef typename Store<S>::C C;
-  constexpr int V = Store<S>::V;
-  typedef typename Store<S>::vec vec;
-  typedef typename Store<S>::vecu vecu;
+  typedef typename Vec<S, V>::a vec;
+  typedef typename Vec<S, V>::u vecu;
   const Grid& G = a.g;
   const long long tile = a.tile_list[blk];
-  const long long base = tile * (256LL * V) + (long long)threadIdx.x * V;
+  const long long base = tile * ((long long)blockDim.x * V) + (long long)threadIdx.x * V;
   if (base >= G.Np) return;
-  const typename ClsVec<S>::T cw = *(const typename ClsVec<S>::T*)(a.ncls + base);
+  const typename ClsWord<V>::T cw = *(const typename ClsWord<V>::T*)(a.ncls + base);
   bool isb[V];
   bool all = true, any = false;
 #pragma unroll
@@ -378,21 +361,21 @@ __device__ void fluid_bulk(const FluidArgs& a, int blk) {
   int x0, y, z;
   coords(G, base, x0, y, z);
   // periodic x: groups touching x = 0 or x = nx-1 gather element by element
-  const bool xedge = G.per[0] && (x0 == 0 || x0 + V > G.nx - 1);
+  const bool xedge = PERX && (x0 == 0 || x0 + V > G.nx - 1);
   vec in[19];
 #pragma unroll
   for (int j = 0; j < 19; j++) {
-    const int sy = (G.per[1] ? wrapc(y - EY[j], G.ny) : y - EY[j]);
-    const int sz = (G.per[2] ? wrapc(z - EZ[j], G.nz) : z - EZ[j]);
+    const int sy = (G.per[1] ? wrap2(y - EY[j], G.ny) : y - EY[j]);
+    const int sz = (G.per[2] ? wrap2(z - EZ[j], G.nz) : z - EZ[j]);
     const long long row = (long long)G.px * (sy + (long long)G.ny * sz);
     const S* pl = A + (long long)j * G.plane + row;
     if (EX[j] == 0) {
       in[j] = *(const vec*)(pl + x0);
-    } else if (!xedge) {
+    } else if (!PERX || !xedge) {
       in[j] = *(const vecu*)(pl + x0 - EX[j]);
     } else {
 #pragma unroll
-      for (int k = 0; k < V; k++) in[j][k] = pl[wrapc(x0 + k - EX[j], G.nx)];
+      for (int k = 0; k < V; k++) in[j][k] = pl[wrap2(x0 + k - EX[j], G.nx)];
     }
   }
   bool bad = false;
@@ -470,12 +453,14 @@ __device__ void fluid_record_lanes(const FluidArgs& a, int r, int j) {
   // loads
   const C self_j = ldA<S>(a, jj, node);
   const C pulled = ldA<S>(a, jj, nbr(G, x, y, z, -ex, -ey, -ez));
-  C fi_x = 0, b1 = 0, b2 = 0, b3 = 0, q = 0;
-  int md = 0;
+  C fi_x = 0, b1 = 0, b2 = 0, b3 = 0, c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
   if (linked) {
     const int lk = lk0 + __popc(mask & ((1u << jj) - 2u));
-    md = a.lk_dm[lk] >> 5;
-    q = (C)a.lk_q[lk];
+    c0 = (C)a.lk_c[lk];
+    c1 = (C)a.lk_c[(long long)a.nlinks + lk];
+    c2 = (C)a.lk_c[2LL * a.nlinks + lk];
+    c3 = (C)a.lk_c[3LL * a.nlinks + lk];
+    c4 = (C)a.lk_c[4LL * a.nlinks + lk];
     const long long n1 = nbr(G, x, y, z, ex, ey, ez);  // x - e_i
     const long long n2 = nbr(G, x, y, z, 2 * ex, 2 * ey, 2 * ez);
     fi_x = ldA<S>(a, i, node);
@@ -486,17 +471,7 @@ __device__ void fluid_record_lanes(const FluidArgs& a, int r, int j) {
   C gj;
   if (jj == 0) gj = self_j;
   else if (!linked) gj = pulled;
-  else if (md == BFL_QUAD_LO)
-    gj = q * (C(1) + C(2) * q) * fi_x + (C(1) - C(4) * q * q) * b1 - q * (C(1) - C(2) * q) * b2;
-  else if (md == BFL_LIN_LO)
-    gj = C(2) * q * fi_x + (C(1) - C(2) * q) * b1;
-  else if (md == BFL_BB)
-    gj = fi_x;
-  else if (md == BFL_QUAD_HI)
-    gj = fi_x / (q * (C(2) * q + C(1))) + (C(2) * q - C(1)) / q * self_j +
-         (C(1) - C(2) * q) / (C(1) + C(2) * q) * b3;
-  else
-    gj = fi_x / (C(2) * q) + (C(2) * q - C(1)) / (C(2) * q) * self_j;
+  else gj = c0 * fi_x + c1 * b1 + c2 * b2 + c3 * self_j + c4 * b3;
   if (!act) gj = C(0);
   const int seg = threadIdx.x & 32;  // first lane of this segment within the wave
   if (fc != 0xff) {
@@ -577,10 +552,10 @@ __device__ void fluid_record_thread(const FluidArgs& a, int r) {
 // need several times the registers of the bulk path, and sharing one kernel
 // would cap the occupancy of the bandwidth-bound part.  The two launches
 // read A and write disjoint nodes of B and may run concurrently.
-template <class S>
+template <class S, int V, bool PERX>
 __global__ __launch_bounds__(256) void k_fluid_bulk(FluidArgs a) {
   if (a.flags->stop) return;
-  fluid_bulk<S>(a, xcd_remap(blockIdx.x, a.nbulk_blocks));
+  fluid_bulk<S, V, PERX>(a, xcd_remap(blockIdx.x, a.nbulk_blocks));
 }
 
 template <class S>
@@ -590,7 +565,7 @@ __global__ __launch_bounds__(256) void k_fluid_rec(FluidArgs a) {
     const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
     if (r < a.nrec) fluid_record_lanes<S>(a, r, threadIdx.x & 31);
   } else {
-    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < a.nrec) fluid_record_thread<S>(a, r);
   }
 }
@@ -1529,24 +1504,37 @@ hipError_t launch_init(int prec, const Grid& g, void* f, const uint8_t* ncls, co
   return hipGetLastError();
 }
 
+template <class S, int V>
+static void bulk_launch(const FluidArgs& a, unsigned grid, hipStream_t s) {
+  if (a.g.per[0]) k_fluid_bulk<S, V, true><<<grid, a.bulk_block, 0, s>>>(a);
+  else k_fluid_bulk<S, V, false><<<grid, a.bulk_block, 0, s>>>(a);
+}
+
 hipError_t launch_fluid_bulk(int prec, const FluidArgs& a, hipStream_t s) {
   if (a.nbulk_blocks == 0) return hipSuccess;
   const unsigned grid = (unsigned)a.nbulk_blocks;
-  switch (prec) {
-    case 0: k_fluid_bulk<double><<<grid, 256, 0, s>>>(a); break;
-    case 1: k_fluid_bulk<float><<<grid, 256, 0, s>>>(a); break;
-    default: k_fluid_bulk<_Float16><<<grid, 256, 0, s>>>(a); break;
+  switch (prec * 16 + a.bulk_v) {
+    case 0 * 16 + 1: bulk_launch<double, 1>(a, grid, s); break;
+    case 0 * 16 + 2: bulk_launch<double, 2>(a, grid, s); break;
+    case 1 * 16 + 1: bulk_launch<float, 1>(a, grid, s); break;
+    case 1 * 16 + 2: bulk_launch<float, 2>(a, grid, s); break;
+    case 1 * 16 + 4: bulk_launch<float, 4>(a, grid, s); break;
+    case 2 * 16 + 2: bulk_launch<_Float16, 2>(a, grid, s); break;
+    case 2 * 16 + 4: bulk_launch<_Float16, 4>(a, grid, s); break;
+    case 2 * 16 + 8: bulk_launch<_Float16, 8>(a, grid, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_fluid_rec(int prec, const FluidArgs& a, hipStream_t s) {
   if (a.nrec == 0) return hipSuccess;
-  const unsigned grid = cdiv(a.nrec, a.rec_lanes ? 8 : 256);
+  const unsigned grid = cdiv(a.nrec, a.rec_lanes ? 8 : a.rec_block);
+  const unsigned blk = a.rec_lanes ? 256u : (unsigned)a.rec_block;
   switch (prec) {
-    case 0: k_fluid_rec<double><<<grid, 256, 0, s>>>(a); break;
-    case 1: k_fluid_rec<float><<<grid, 256, 0, s>>>(a); break;
-    default: k_fluid_rec<_Float16><<<grid, 256, 0, s>>>(a); break;
+    case 0: k_fluid_rec<double><<<grid, blk, 0, s>>>(a); break;
+    case 1: k_fluid_rec<float><<<grid, blk, 0, s>>>(a); break;
+    default: k_fluid_rec<_Float16><<<grid, blk, 0, s>>>(a); break;
   }
   return hipGetLastError();
 }
