@@ -26,11 +26,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "MLUPS (D3Q19 LBM+IB step), % HBM roofline; batched & adjoint vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fluid_kernel_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_06043_amd", "csrc", "lbm_kernels.hip")
+# sources that decide what the fluid kernels read and write (code and launch shapes)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_06043_amd", "csrc", n)
+               for n in ("lbm_kernels.hip", "lbm_abi.cpp", "lbm_internal.h")]
+FLUID_KERNELS = ("k_fluid_bulk", "k_fluid_rec")
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, precision):
@@ -45,6 +51,61 @@ def measured_traffic(workload, precision):
     if not e or e.get("kernel_sha") != kernel_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def _counter_medians(run_dir, counter):
+    """Median per-dispatch value (KiB) of a rocprofv3 --pmc counter for each
+    kernel name in run_dir/run_counter_collection.csv."""
+    import csv
+    import statistics
+    vals = {}
+    with open(os.path.join(run_dir, "run_counter_collection.csv")) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: statistics.median(v) for k, v in vals.items()}
+
+
+def summarize_counters(args):
+    """Writes the HBM traffic of one launch of the fluid kernels (bulk +
+    boundary records, the span the roofline times) into TRAFFIC_FILE, from
+    FETCH_SIZE and WRITE_SIZE runs of the workload and of the plain-copy
+    calibration (--copy-calibration-mb), each scaled so the copy reads and
+    writes its known size."""
+    wl_f, wl_w, cp_f, cp_w = args.summarize_counters
+    copy_bytes = args.calibration_bytes
+
+    def only(d, key):
+        hits = [v for k, v in d.items() if key in k]
+        if len(hits) != 1:
+            raise SystemExit(f"expected one kernel matching {key}, found {len(hits)}")
+        return hits[0]
+
+    kf = copy_bytes / (only(_counter_medians(cp_f, "FETCH_SIZE"), "copyBuffer") * 1024.0)
+    kw = copy_bytes / (only(_counter_medians(cp_w, "WRITE_SIZE"), "copyBuffer") * 1024.0)
+    fetch = _counter_medians(wl_f, "FETCH_SIZE")
+    write = _counter_medians(wl_w, "WRITE_SIZE")
+    rd = sum(1024.0 * kf * v for k, v in fetch.items() if any(n in k for n in FLUID_KERNELS))
+    wr = sum(1024.0 * kw * v for k, v in write.items() if any(n in k for n in FLUID_KERNELS))
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        d = {}
+    d[f"{args.workload}:{args.precision}"] = {
+        "kernel_sha": kernel_hash(),
+        "bytes_per_launch": round(rd + wr),
+        "read_bytes": round(rd),
+        "write_bytes": round(wr),
+        "fetch_scale": round(kf, 5),
+        "write_scale": round(kw, 5),
+        "kernels": {k: {"FETCH_SIZE_KiB": fetch.get(k), "WRITE_SIZE_KiB": write.get(k)}
+                    for k in sorted(set(fetch) | set(write)) if any(n in k for n in FLUID_KERNELS)},
+    }
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(d[f"{args.workload}:{args.precision}"]))
 
 
 def build_workload(name, precision):
@@ -94,7 +155,28 @@ def main():
                     help="steps whose fused stream-collide launches are timed with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="only run plain device copies of this size (calibrates HBM counters)")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR",
+                    "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="turn rocprofv3 --pmc runs into the fluid-kernel traffic entry (no GPU)")
+    ap.add_argument("--calibration-bytes", type=float, default=1.024e9,
+                    help="bytes read and written by one calibration copy")
     args = ap.parse_args()
+    if args.summarize_counters:
+        args.precision = args.precision or ("f64" if args.workload == "pipe_sphere" else "f32")
+        summarize_counters(args)
+        return
+    if args.copy_calibration_mb > 0:
+        import torch
+        n = int(args.copy_calibration_mb * 1e6 / 4)
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: the build has no multi-GPU path "
               "(use --gpus 1)", file=sys.stderr)

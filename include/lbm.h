@@ -170,8 +170,11 @@ lbm_status ib_interpolate(lbm_ctx *ctx, int64_t n, const double *d_pts, const do
 
 /* Spreading (Eq. bodyforce): d_fib [3][N] += sum_l c_l phi_k^l F_l for the
  * n points d_pts [n][3] with forces d_F [n][3] and weights d_c [n].  The sum
- * is accumulated in 64-bit fixed point (2^-52), so it is bitwise
- * reproducible whatever the thread order. */
+ * is accumulated in 64-bit fixed point (unit 2^-57, up to +-64 per node), so
+ * it is bitwise reproducible whatever the thread order.  Each contribution
+ * c_l phi_k^l F_l must lie in [-1, 1]: one that does not is dropped and the
+ * call returns LBM_E_INVAL after the rest was added.  Synchronises the
+ * context's stream. */
 lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double *d_F,
                      const double *d_c, double *d_fib);
 

@@ -12,19 +12,45 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+DEFAULT_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+LIB_PATH = DEFAULT_LIB_PATH
 _lib = None
 
 
-def build(verbose=False):
-    """Compile the oracle with the host compiler (gcc, OpenMP)."""
+# Measurement builds of the same source, used only to gauge how far a
+# trajectory moves under other rounding: "fma" lets the compiler fuse
+# multiply-adds, "reassoc" lets it reorder sums (vectorised reductions),
+# "store_f32" rounds the stored populations to FP32.
+VARIANT_FLAGS = {
+    "plain": [],
+    "fma": ["-mfma", "-ffp-contract=fast"],
+    "reassoc": ["-O3", "-mavx2", "-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math"],
+    "store_f32": ["-DORC_STORE_F32"],
+}
+
+
+def build(verbose=False, variant="plain", path=None):
+    """Compile the oracle with the host compiler (gcc, OpenMP).  The default
+    build is the oracle; a named variant goes to ``path``."""
+    out = path or DEFAULT_LIB_PATH
+    if variant != "plain" and path is None:
+        raise ValueError("a measurement variant needs its own path")
     cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-           os.path.join(_HERE, "oracle.c"), "-o", LIB_PATH + ".tmp", "-lm"]
+           *VARIANT_FLAGS[variant], os.path.join(_HERE, "oracle.c"), "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def use_library(path):
+    """Load the oracle from ``path`` (a measurement build) in this process;
+    must be called before the first use."""
+    global LIB_PATH
+    if _lib is not None:
+        raise RuntimeError("oracle library already loaded")
+    LIB_PATH = path
 
 
 def _P(t):
@@ -36,6 +62,8 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
+        if LIB_PATH != DEFAULT_LIB_PATH:
+            raise FileNotFoundError(LIB_PATH)
         build()
     L = C.CDLL(LIB_PATH)
     d, i32, i64, u8 = C.c_double, C.c_int32, C.c_int64, C.c_uint8

@@ -30,6 +30,16 @@
  *      (Eq. angularVelRig).
  * Where the paper is silent or garbled, the reading taken is stated at the
  * point of use.
+ *
+ * Storage: populations are kept as deviations d_i = f_i - w_i from the rest
+ * weights.  This is an exact change of variables: streaming, the
+ * interpolated bounce-back (its coefficients add up to 1 and link directions
+ * of equal weight) and the Zou-He rule map deviations to deviations, and the
+ * moments are rho = 1 + sum d, rho u = sum d e.  Full populations (about
+ * 1/3) lose about 3e-17 to rounding at every store; in a steady flow that
+ * loss has the same sign step after step and adds up to about 1e-12 of the
+ * velocity scale within a few thousand steps, which the deviations (about
+ * 1e-3) avoid.
  */
 #include "oracle.h"
 
@@ -97,8 +107,8 @@ struct orc_sim {
   double *lk_q;
   double *uin;             /* [N*3], inlet nodes only */
   double rho_out;
-  double *fs;              /* post-collision populations [N*19] (the state) */
-  double *f;               /* streamed populations [N*19] (work) */
+  double *fs;              /* post-collision populations, as f - w [N*19] (the state) */
+  double *f;               /* streamed populations, as f - w [N*19] (work) */
   double *rho, *u;         /* outputs of the last step [N], [N*3] */
   double *mom;             /* pre-collision momentum sum_i f_i e_i [N*3] */
   double *ustar;           /* pre-force velocity m/rho [N*3] */
@@ -166,6 +176,14 @@ static double feq_i(int i, double rho, const double *u) {
   return Wt[i] * rho * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
 }
 
+/* f^eq_i - w_i, the same expansion written as a deviation from the rest
+ * weights (the form the populations are stored in, below). */
+static double feq_dev_i(int i, double rho, const double *u) {
+  double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+  double uu = dot(u, u);
+  return Wt[i] * ((rho - 1.0) + rho * (eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2)));
+}
+
 /* Eq. forcing: the discrete forcing term projected on direction i. */
 static double guo_i(int i, double tau, const double *u, const double *F) {
   double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
@@ -197,7 +215,9 @@ void orc_guo(double tau, const double *u, const double *F, double *out19) {
  * the two opposite populations behind x, as in the q < 1/2 branch.
  * Reading where the paper is silent (x - e_i or x - 2e_i solid or outside):
  * drop to the linear interpolation through the points that remain, and to
- * the plain bounce-back f*_i(x) when none remains (q < 1/2). */
+ * the plain bounce-back f*_i(x) when none remains (q < 1/2).
+ * Every branch's coefficients add up to 1, so the rule applies unchanged to
+ * deviations f - w (w_i = w_j for a link and its opposite). */
 double orc_bfl(double q, double fi_x, double fi_xm1, double fi_xm2, double fj_x,
                double fj_xm1, int avail1, int avail2) {
   if (q < 0.5) {
@@ -225,22 +245,24 @@ static void face_normal(int face, int *n) {
  * than Eq. e_i, so it is applied through direction vectors; its 1/6 terms
  * carry the wall density rho_w, which the momentum balance requires.
  * Fills the unknowns of f19 in place and returns rho_w. */
-double orc_zouhe(double *f, int face, int kind, const double *u_w_in, double rho_w) {
+static double zouhe_dev(double *d, int face, int kind, const double *u_w_in, double rho_w) {
   int n[3];
   face_normal(face, n);
-  double S0 = 0.0, Sout = 0.0;
+  /* with d = f - w: sum_{e.n=0} f + 2 sum_{e.n=-1} f = 1 + D0 + 2 Dout, since
+   * the rest weights of those sets add up to 2/3 and 1/6 */
+  double D0 = 0.0, Dout = 0.0;
   for (int j = 0; j < 19; j++) {
     int en = E[j][0] * n[0] + E[j][1] * n[1] + E[j][2] * n[2];
-    if (en == 0) S0 += f[j];
-    else if (en == -1) Sout += f[j];
+    if (en == 0) D0 += d[j];
+    else if (en == -1) Dout += d[j];
   }
   double uw[3];
   if (kind == 0) {
     for (int a = 0; a < 3; a++) uw[a] = u_w_in[a];
     double un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
-    rho_w = (S0 + 2.0 * Sout) / (1.0 - un);
+    rho_w = (1.0 + D0 + 2.0 * Dout) / (1.0 - un);
   } else {
-    double un = 1.0 - (S0 + 2.0 * Sout) / rho_w;
+    double un = (rho_w - 1.0 - D0 - 2.0 * Dout) / rho_w;
     for (int a = 0; a < 3; a++) uw[a] = un * n[a];
   }
   double un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
@@ -250,19 +272,29 @@ double orc_zouhe(double *f, int face, int kind, const double *u_w_in, double rho
     int jb = opposite(j);
     int t[3] = {E[j][0] - n[0], E[j][1] - n[1], E[j][2] - n[2]};
     if (t[0] == 0 && t[1] == 0 && t[2] == 0) {
-      f[j] = f[jb] + rho_w / 3.0 * un;
+      d[j] = d[jb] + rho_w / 3.0 * un;
     } else {
       double ut = uw[0] * t[0] + uw[1] * t[1] + uw[2] * t[2];
+      /* the rest weights cancel in this sum (symmetric pairs) */
       double Nt = 0.0;
       for (int k = 0; k < 19; k++) {
         int ek = E[k][0] * n[0] + E[k][1] * n[1] + E[k][2] * n[2];
-        if (ek == 0) Nt += f[k] * (E[k][0] * t[0] + E[k][1] * t[1] + E[k][2] * t[2]);
+        if (ek == 0) Nt += d[k] * (E[k][0] * t[0] + E[k][1] * t[1] + E[k][2] * t[2]);
       }
       Nt = 0.5 * Nt - rho_w / 3.0 * ut;
-      f[j] = f[jb] + rho_w / 6.0 * (un + ut) - Nt;
+      d[j] = d[jb] + rho_w / 6.0 * (un + ut) - Nt;
     }
   }
   return rho_w;
+}
+
+/* The same condition on full populations f (public entry). */
+double orc_zouhe(double *f, int face, int kind, const double *u_w_in, double rho_w) {
+  double d[19];
+  for (int j = 0; j < 19; j++) d[j] = f[j] - Wt[j];
+  double r = zouhe_dev(d, face, kind, u_w_in, rho_w);
+  for (int j = 0; j < 19; j++) f[j] = Wt[j] + d[j];
+  return r;
 }
 
 /* Box face on which an open node lies (the face whose outside its unknown
@@ -391,7 +423,7 @@ orc_sim *orc_create(int nx, int ny, int nz, const int32_t *periodic, double tau,
       n_in++;
     }
   }
-  /* initial state: f = f^eq(rho0, u0) on non-solid nodes */
+  /* initial state: f = f^eq(rho0, u0) on non-solid nodes (stored as f - w) */
   for (long n = 0; n < N; n++) {
     double r = init_rho ? init_rho[n] : 1.0;
     double uu[3] = {0, 0, 0};
@@ -401,7 +433,7 @@ orc_sim *orc_create(int nx, int ny, int nz, const int32_t *periodic, double tau,
       for (int i = 0; i < 19; i++) s->fs[19 * n + i] = 0.0;
       continue;
     }
-    for (int i = 0; i < 19; i++) s->fs[19 * n + i] = feq_i(i, r, uu);
+    for (int i = 0; i < 19; i++) s->fs[19 * n + i] = feq_dev_i(i, r, uu);
     s->rho[n] = r;
     for (int a = 0; a < 3; a++) s->u[3 * n + a] = uu[a];
   }
@@ -776,14 +808,16 @@ static void stream_node(orc_sim *s, long n) {
   }
   if (s->type[n] == T_INLET || s->type[n] == T_OUTLET) {
     int face = open_face(s, n);
-    if (s->type[n] == T_INLET) orc_zouhe(f, face, 0, s->uin + 3 * n, 0.0);
-    else orc_zouhe(f, face, 1, NULL, s->rho_out);
+    if (s->type[n] == T_INLET) zouhe_dev(f, face, 0, s->uin + 3 * n, 0.0);
+    else zouhe_dev(f, face, 1, NULL, s->rho_out);
   }
-  double rho = 0.0, m[3] = {0, 0, 0};
+  /* moments of f = w + d: the weights add up to 1 and carry no momentum */
+  double dsum = 0.0, m[3] = {0, 0, 0};
   for (int i = 0; i < 19; i++) {
-    rho += f[i];
+    dsum += f[i];
     for (int a = 0; a < 3; a++) m[a] += f[i] * E[i][a];
   }
+  double rho = 1.0 + dsum;
   s->rho[n] = rho;
   for (int a = 0; a < 3; a++) {
     s->mom[3 * n + a] = m[a];
@@ -801,8 +835,15 @@ static int collide_node(orc_sim *s, long n) {
     /* rho u = sum f e + (dt/2) f_ib */
     u[a] = (s->mom[3 * n + a] + 0.5 * F[a]) / rho;
   }
-  for (int i = 0; i < 19; i++)
-    s->fs[19 * n + i] = f[i] - (f[i] - feq_i(i, rho, u)) / s->tau + guo_i(i, s->tau, u, F);
+  for (int i = 0; i < 19; i++) {
+    double v = f[i] - (f[i] - feq_dev_i(i, rho, u)) / s->tau + guo_i(i, s->tau, u, F);
+#ifdef ORC_STORE_F32
+    /* measurement build only: the state rounded to FP32 at every store, to
+     * gauge how far FP32 storage alone moves a trajectory */
+    v = (double)(float)v;
+#endif
+    s->fs[19 * n + i] = v;
+  }
   for (int a = 0; a < 3; a++) s->u[3 * n + a] = u[a];
   double uu = dot(u, u);
   return !(uu <= 0.09) || !(rho == rho);
@@ -1229,7 +1270,8 @@ void orc_get_fields(const orc_sim *s, double *rho, double *u) {
 
 void orc_get_populations(const orc_sim *s, double *f) {
   for (long n = 0; n < s->N; n++)
-    for (int i = 0; i < 19; i++) f[(long)i * s->N + n] = s->type[n] == T_SOLID ? 0.0 : s->fs[19 * n + i];
+    for (int i = 0; i < 19; i++)
+      f[(long)i * s->N + n] = s->type[n] == T_SOLID ? 0.0 : Wt[i] + s->fs[19 * n + i];
 }
 
 void orc_get_force(const orc_sim *s, double *fib) {

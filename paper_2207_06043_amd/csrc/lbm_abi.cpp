@@ -73,6 +73,7 @@ struct lbm_ctx {
   long long* fx[2] = {nullptr, nullptr};
   uint8_t* tf[2] = {nullptr, nullptr};
   long long* fx_api = nullptr;
+  DevFlags* api_flags = nullptr;  // range flags of ib_spread (kept apart from the run's)
   DevFlags* flags = nullptr;  // followed by the block counter
   // bodies
   std::vector<HostBody> bodies;
@@ -403,7 +404,7 @@ extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
   void* ptrs[] = {ctx->f_alloc[0], ctx->f_alloc[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
                   ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_c,
                   ctx->tile_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
-                  ctx->flags};
+                  ctx->api_flags, ctx->flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -973,7 +974,9 @@ extern "C" lbm_status lbm_sync(lbm_ctx* ctx) {
   if (st) return st;
   // the host's step counter follows the device once it has stopped
   if (h.stop & ST_DAMAGED) return fail(ctx, LBM_E_DAMAGED, "a membrane link reached twice its rest length");
-  if (h.stop & ST_UNSTABLE) return fail(ctx, LBM_E_UNSTABLE, "|u| > 0.3 or NaN");
+  if (h.stop & ST_UNSTABLE)
+    return fail(ctx, LBM_E_UNSTABLE, h.overflow ? "a spread force contribution exceeded +-1 (IB unstable)"
+                                                : "|u| > 0.3 or NaN");
   return LBM_OK;
 }
 
@@ -1059,9 +1062,19 @@ extern "C" lbm_status ib_spread(lbm_ctx* ctx, int64_t n, const double* d_pts, co
     const size_t b = 3 * (size_t)ctx->g.Np * sizeof(long long);
     CHK(hipMalloc(&ctx->fx_api, b));
     CHK(hipMemset(ctx->fx_api, 0, b));
+    CHK(hipMalloc(&ctx->api_flags, sizeof(DevFlags)));
+    CHK(hipMemset(ctx->api_flags, 0, sizeof(DevFlags)));
   }
-  CHK(launch_spread_api(ctx->g, ctx->ncls, n, d_pts, d_F, d_c, ctx->fx_api, ctx->flags, ctx->stream));
+  CHK(launch_spread_api(ctx->g, ctx->ncls, n, d_pts, d_F, d_c, ctx->fx_api, ctx->api_flags, ctx->stream));
   CHK(launch_flush_fx(ctx->g, ctx->fx_api, d_fib, ctx->stream));
+  // contributions beyond the fixed-point range were dropped: report them
+  DevFlags h;
+  CHK(hipStreamSynchronize(ctx->stream));
+  CHK(hipMemcpy(&h, ctx->api_flags, sizeof(DevFlags), hipMemcpyDeviceToHost));
+  if (h.overflow) {
+    CHK(hipMemset(ctx->api_flags, 0, sizeof(DevFlags)));
+    return fail(ctx, LBM_E_INVAL, "ib_spread: a contribution c*phi*F exceeded +-1 (dropped)");
+  }
   return LBM_OK;
 }
 

@@ -12,9 +12,12 @@ enum : uint8_t { CLS_SOLID = 0, CLS_BULK = 1, CLS_GENERAL = 2 };
 // Status bits raised on the device.
 enum : uint32_t { ST_UNSTABLE = 1u, ST_DAMAGED = 2u };
 
-// Fixed-point scale of the spread force: 2^52 (range +-2048 per node).
-constexpr double FX_SCALE = 4503599627370496.0;
-constexpr double FX_INV = 1.0 / 4503599627370496.0;
+// Fixed-point scale of the spread force: 2^57, so one unit is 2^-57 (the
+// rounding of a contribution at most 2^-58 ~ 3.5e-18) and a node holds
+// +-64.  A single contribution beyond +-1 stops the run as unstable, which
+// keeps node totals in range up to 64 such contributions per node.
+constexpr double FX_SCALE = 144115188075855872.0;
+constexpr double FX_INV = 1.0 / 144115188075855872.0;
 
 constexpr int TILE_SHIFT = 10;  // force-flag granularity: 1024 nodes
 
@@ -24,7 +27,7 @@ constexpr int VT_E = 10, VT_H = 20, VT_F = 10, VT_SLOTS = VT_E + VT_H + VT_F;
 struct DevFlags {
   uint32_t stop;      // sticky stop bits (checked at every kernel entry)
   uint32_t pending;   // bits raised during the current step
-  uint32_t overflow;  // a single spread contribution exceeded +-1
+  uint32_t overflow;  // a spread contribution exceeded +-1 (also raises ST_UNSTABLE)
   uint32_t pad;
   long long steps_done;
   int mls_singular;

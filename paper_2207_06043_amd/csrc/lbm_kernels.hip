@@ -100,12 +100,30 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 }
 
 __device__ __forceinline__ void fx_add(long long* p, double v, DevFlags* fl) {
-  if (!(fabs(v) <= 1.0)) atomicOr(&fl->overflow, 1u);
+  if (!(fabs(v) <= 1.0)) {
+    // out of the fixed-point range: dropped and flagged
+    atomicOr(&fl->overflow, 1u);
+    atomicOr(&fl->pending, ST_UNSTABLE);
+    v = 0.0;
+  }
   long long q = __double2ll_rn(v * FX_SCALE);
   atomicAdd((unsigned long long*)p, (unsigned long long)q);
 }
 
 // ---------------------------------------------------------------- collision
+// Sum of the 19 deviations (the density deviation rho - 1).  The deviations
+// of a direction and its opposite are close to +-3 w e.u and nearly cancel,
+// so they are added pairwise first: those sums are exact or nearly so, and
+// the density deviation keeps its relative precision in float as well,
+// instead of carrying rounding of the size of the large terms.
+template <class C>
+__device__ __forceinline__ C dev_sum(const C (&g)[19]) {
+  const C ax = ((g[1] + g[2]) + (g[3] + g[4])) + (g[5] + g[6]);
+  const C d1 = ((g[7] + g[12]) + (g[8] + g[11])) + ((g[9] + g[14]) + (g[10] + g[13]));
+  const C d2 = (g[15] + g[18]) + (g[16] + g[17]);
+  return g[0] + ((ax + d1) + d2);
+}
+
 // BGK with the forcing term on deviations g = f - w (Eqs. evoleq, eqfunc,
 // forcing): rho = 1 + sum g, rho u = sum g e + F/2,
 // g^eq_i = w_i (drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)),
@@ -113,9 +131,7 @@ __device__ __forceinline__ void fx_add(long long* p, double v, DevFlags* fl) {
 template <class C>
 __device__ __forceinline__ void collide(C (&g)[19], C Fx, C Fy, C Fz, C omega, C& rho, C& ux,
                                         C& uy, C& uz) {
-  C drho = 0;
-#pragma unroll
-  for (int i = 0; i < 19; i++) drho += g[i];
+  const C drho = dev_sum(g);
   C mx = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
   C my = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
   C mz = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
@@ -135,6 +151,24 @@ __device__ __forceinline__ void collide(C (&g)[19], C Fx, C Fy, C Fz, C omega, C
     C geq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * usq));
     C Gi = kf * w * (C(3) * (eF - uF) + C(9) * eu * eF);
     g[i] = g[i] - omega * (g[i] - geq) + Gi;
+  }
+  if constexpr (sizeof(C) < sizeof(double)) {
+    // The collision keeps the mass (rho - 1) and turns the momentum m into
+    // m + F exactly; with the weights rounded to float it does not (their
+    // sums are off by ~1e-8, the same sign at every node and step), so the
+    // residuals are put back: mass on the rest population, momentum on the
+    // axis pairs.
+    const C mx1 = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
+    const C my1 = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
+    const C mz1 = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
+    const C rx = C(0.5) * ((mx + Fx) - mx1), ry = C(0.5) * ((my + Fy) - my1), rz = C(0.5) * ((mz + Fz) - mz1);
+    g[1] += rx;
+    g[2] -= rx;
+    g[3] += ry;
+    g[4] -= ry;
+    g[5] += rz;
+    g[6] -= rz;
+    g[0] += drho - dev_sum(g);
   }
 }
 
@@ -252,6 +286,85 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
     zouhe<C>(g, face, kind, (C)a.rec_bc[r], (C)a.rec_bc[a.nrec + r], (C)a.rec_bc[2 * a.nrec + r],
              (C)a.rec_bc[3 * a.nrec + r]);
   }
+}
+
+// Moments of the streamed populations at any non-solid node (what the
+// forcing step interpolates), in double: drho = sum g, m = sum g e.  A
+// boundary record accumulates them direction by direction (plain pull,
+// interpolated bounce-back, or nothing for a population from outside an
+// open face) without holding all of its populations; on an open face the
+// Zou-He rule fixes the completed node's moments in closed form:
+// rho = rho_w and rho u = rho_w u_w, with rho_w = (1 + G0 + 2 Gout)/(1 - u_n)
+// on a velocity face and u_n = (rho_w - 1 - G0 - 2 Gout)/rho_w (tangential
+// u = 0) on a density face.
+template <class S>
+__device__ void streamed_moments(const FluidArgs& a, long long node, double& drho, double (&m)[3]) {
+  const Grid& G = a.g;
+  int x, y, z;
+  coords(G, node, x, y, z);
+  double g[19];
+  if (a.ncls[node] == CLS_BULK) {
+#pragma unroll
+    for (int j = 0; j < 19; j++) g[j] = (double)ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
+  } else {
+    const int r = a.rec_of[node];
+    const uint32_t mask = a.rec_mask[r];
+    const int fc = a.rec_face[r];
+    const int face = fc & 7, ax = face >> 1, sgn = (face & 1) ? -1 : 1;
+    int lk = a.rec_link0[r];
+    g[0] = (double)ldA<S>(a, 0, node);
+#pragma unroll
+    for (int j = 1; j < 19; j++) {
+      const int en = sgn * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]));
+      double v;
+      if ((mask >> j) & 1u) {
+        const int i = OPP[j];
+        const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);
+        const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
+        double c[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) c[k] = a.lk_c[(long long)k * a.nlinks + lk];
+        ++lk;
+        v = c[0] * (double)ldA<S>(a, i, node) + c[1] * (double)ldA<S>(a, i, n1) +
+            c[2] * (double)ldA<S>(a, i, n2) + c[3] * (double)ldA<S>(a, j, node) +
+            c[4] * (double)ldA<S>(a, j, n1);
+      } else if (fc != 0xff && en == 1) {
+        v = 0.0;  // enters through the open face: the Zou-He rule fills it
+      } else {
+        v = (double)ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
+      }
+      g[j] = v;
+    }
+    if (fc != 0xff) {
+      double G0 = 0.0, Gout = 0.0;
+#pragma unroll
+      for (int j = 0; j < 19; j++) {
+        const int en = sgn * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]));
+        G0 += en == 0 ? g[j] : 0.0;
+        Gout += en == -1 ? g[j] : 0.0;
+      }
+      const int kind = (fc >> 4) & 1;
+      double rw, un, ut[3] = {0.0, 0.0, 0.0};
+      if (kind == 0) {
+        const double bu[3] = {a.rec_bc[r], a.rec_bc[a.nrec + r], a.rec_bc[2 * a.nrec + r]};
+        un = sgn * bu[ax];
+        rw = (1.0 + G0 + 2.0 * Gout) / (1.0 - un);
+#pragma unroll
+        for (int k = 0; k < 3; k++) ut[k] = k == ax ? 0.0 : bu[k];
+      } else {
+        rw = a.rec_bc[3 * a.nrec + r];
+        un = (rw - 1.0 - G0 - 2.0 * Gout) / rw;
+      }
+      drho = rw - 1.0;
+#pragma unroll
+      for (int k = 0; k < 3; k++) m[k] = rw * (k == ax ? sgn * un : ut[k]);
+      return;
+    }
+  }
+  drho = dev_sum(g);
+  m[0] = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
+  m[1] = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
+  m[2] = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
 }
 
 // Streamed populations at any non-solid node.
@@ -609,6 +722,7 @@ __global__ void k_init(Grid G, S* f, const uint8_t* ncls, const double* rho0, co
 struct Slot {
   long long node;
   double W, dx, dy, dz;
+  int cx, cy, cz;  // node coordinates before periodic wrap
   bool valid;
 };
 
@@ -622,6 +736,9 @@ __device__ __forceinline__ Slot stencil_slot(const Grid& G, const uint8_t* ncls,
   if (k >= 27) return s;
   const int bx = (int)floor(X + 0.5), by = (int)floor(Y + 0.5), bz = (int)floor(Z + 0.5);
   int c[3] = {bx + k % 3 - 1, by + (k / 3) % 3 - 1, bz + k / 9 - 1};
+  s.cx = c[0];
+  s.cy = c[1];
+  s.cz = c[2];
   s.dx = c[0] - X;
   s.dy = c[1] - Y;
   s.dz = c[2] - Z;
@@ -720,16 +837,14 @@ __device__ __forceinline__ void macro_at(const Grid& G, const S* f, const long l
                                          const uint8_t* tf, double gx, double gy, double gz,
                                          long long node, double& rho, double& ux, double& uy,
                                          double& uz) {
-  typedef typename Store<S>::C C;
-  C g[19];
+  // moments in double whatever the storage (off the bandwidth-bound path)
+  double g[19];
 #pragma unroll
-  for (int j = 0; j < 19; j++) g[j] = to_c(f[(long long)j * G.plane + node]);
-  C drho = 0;
-#pragma unroll
-  for (int j = 0; j < 19; j++) drho += g[j];
-  C mx = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
-  C my = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
-  C mz = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
+  for (int j = 0; j < 19; j++) g[j] = (double)to_c(f[(long long)j * G.plane + node]);
+  const double drho = dev_sum(g);
+  const double mx = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
+  const double my = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
+  const double mz = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
   double Fx = gx, Fy = gy, Fz = gz;
   if (fx && tf && tf[node >> TILE_SHIFT]) {
     Fx += (double)fx[node] * FX_INV;
@@ -899,23 +1014,40 @@ __device__ void diag_block(const BodyArgs& b, const double* X, int dblk) {
 // block); returns the DAMAGED / UNSTABLE bits found by this thread.
 __device__ unsigned int diag_finalize(const BodyArgs& b) {
   unsigned int raised = 0u;
-  for (int body = threadIdx.x; body < b.nbody; body += blockDim.x) {
+  // one wave per body; its lanes take the partial blocks (all loads in
+  // flight at once), then a fixed-order xor reduction
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int body = wv; body < b.nbody; body += nw) {
     double V = 0.0, S = 0.0, lo[3], hi[3], strain = 0.0, nan = 0.0;
     for (int k = 0; k < 3; k++) {
       lo[k] = DBL_MAX;
       hi[k] = -DBL_MAX;
     }
-    for (int q = b.b_dblk0[body]; q < b.b_dblk0[body + 1]; q++) {
+    for (int q = b.b_dblk0[body] + ln; q < b.b_dblk0[body + 1]; q += 64) {
       const double* P = b.diag_part + 12 * (long long)q;
-      V += load_coherent(P);
-      S += load_coherent(P + 1);
+      double p[10];
+#pragma unroll
+      for (int k = 0; k < 10; k++) p[k] = load_coherent(P + k);
+      V += p[0];
+      S += p[1];
       for (int k = 0; k < 3; k++) {
-        lo[k] = fmin(lo[k], load_coherent(P + 2 + k));
-        hi[k] = fmax(hi[k], load_coherent(P + 5 + k));
+        lo[k] = fmin(lo[k], p[2 + k]);
+        hi[k] = fmax(hi[k], p[5 + k]);
       }
-      strain = fmax(strain, load_coherent(P + 8));
-      nan = fmax(nan, load_coherent(P + 9));
+      strain = fmax(strain, p[8]);
+      nan = fmax(nan, p[9]);
     }
+    V = red64(V);
+    S = red64(S);
+    for (int m = 32; m >= 1; m >>= 1) {
+      for (int k = 0; k < 3; k++) {
+        lo[k] = fmin(lo[k], __shfl_xor(lo[k], m, 64));
+        hi[k] = fmax(hi[k], __shfl_xor(hi[k], m, 64));
+      }
+      strain = fmax(strain, __shfl_xor(strain, m, 64));
+      nan = fmax(nan, __shfl_xor(nan, m, 64));
+    }
+    if (ln != 0) continue;
     double* d = b.b_diag + 16 * body;
     d[0] = V;
     d[1] = S;
@@ -942,9 +1074,26 @@ __device__ unsigned int diag_finalize(const BodyArgs& b) {
 //  diag      volume, area, bounding box and stretch of x^n; the last block
 //            combines them and stops the computation before anything of
 //            this step is written when x^n is damaged or not finite.
+// Result of one lane of a marker: the fixed-point contribution to one node.
+struct Contrib {
+  long long node;
+  int cx, cy, cz;
+  long long q[3];
+  bool valid;
+};
+
+__device__ __forceinline__ long long fx_quant(double v, DevFlags* fl) {
+  if (!(fabs(v) <= 1.0)) {
+    // out of the fixed-point range: the step ends as unstable
+    atomicOr(&fl->overflow, 1u);
+    atomicOr(&fl->pending, ST_UNSTABLE);
+    v = 0.0;
+  }
+  return __double2ll_rn(v * FX_SCALE);
+}
+
 template <class S>
-__device__ void ib_marker(const FluidArgs& a, const BodyArgs& b, long long* fxc, uint8_t* tfc,
-                          int m, int lane) {
+__device__ void ib_marker(const FluidArgs& a, const BodyArgs& b, int m, int lane, Contrib& out) {
   typedef typename Store<S>::C C;
   const Grid& G = a.g;
   double cen[3], nrm[3], area;
@@ -974,30 +1123,85 @@ __device__ void ib_marker(const FluidArgs& a, const BodyArgs& b, long long* fxc,
   const Slot s = stencil_slot(G, a.ncls, cen[0], cen[1], cen[2], lane);
   double us[3] = {0.0, 0.0, 0.0};
   if (s.valid) {
-    C g[19];
-    pull_node<S>(a, s.node, g);
-    C drho = 0;
-#pragma unroll
-    for (int j = 0; j < 19; j++) drho += g[j];
-    C mx = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
-    C my = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
-    C mz = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
-    const double rho = 1.0 + (double)drho;
-    us[0] = (double)mx / rho;
-    us[1] = (double)my / rho;
-    us[2] = (double)mz / rho;
+    double drho, mm[3];
+    streamed_moments<S>(a, s.node, drho, mm);
+    const double rho = 1.0 + drho;
+    us[0] = mm[0] / rho;
+    us[1] = mm[1] / rho;
+    us[2] = mm[2] / rho;
   }
   double psi[4];
   if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
   double U[3];
 #pragma unroll
   for (int k = 0; k < 3; k++) U[k] = red32(psi[0] * us[k]);
-  if (s.valid && psi[0] != 0.0) {
+  out.valid = s.valid && psi[0] != 0.0;
+  if (out.valid) {
     const double cp = area * psi[0];
-    fx_add(fxc + s.node, cp * (Ub[0] - U[0]), a.flags);
-    fx_add(fxc + G.Np + s.node, cp * (Ub[1] - U[1]), a.flags);
-    fx_add(fxc + 2 * G.Np + s.node, cp * (Ub[2] - U[2]), a.flags);
-    tfc[s.node >> TILE_SHIFT] = 1;
+    out.node = s.node;
+    out.cx = s.cx;
+    out.cy = s.cy;
+    out.cz = s.cz;
+#pragma unroll
+    for (int k = 0; k < 3; k++) out.q[k] = fx_quant(cp * (Ub[k] - U[k]), a.flags);
+  }
+}
+
+// Spread of the 8 markers of a block: the integer contributions are summed
+// per node in LDS over the block's bounding box of support nodes, then one
+// device atomic per node and component is issued (integer sums, so the
+// result does not depend on the order).  A box larger than SPREAD_CELLS
+// falls back to one device atomic per contribution.
+constexpr int SPREAD_CELLS = 512;
+
+__device__ void spread_block(const Grid& G, const Contrib& o, long long* fxc, uint8_t* tfc) {
+  __shared__ long long acc[3][SPREAD_CELLS];
+  __shared__ long long nid[SPREAD_CELLS];
+  __shared__ int box[6];
+  if (threadIdx.x < 6) box[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
+  __syncthreads();
+  if (o.valid) {
+    atomicMin(&box[0], o.cx);
+    atomicMin(&box[1], o.cy);
+    atomicMin(&box[2], o.cz);
+    atomicMax(&box[3], o.cx);
+    atomicMax(&box[4], o.cy);
+    atomicMax(&box[5], o.cz);
+  }
+  __syncthreads();
+  const int x0 = box[0], y0 = box[1], z0 = box[2];
+  const bool any = box[3] >= x0;
+  const int ex = box[3] - x0 + 1, ey = box[4] - y0 + 1, ez = box[5] - z0 + 1;
+  const bool fits = any && (long long)ex * ey * ez <= SPREAD_CELLS;
+  if (!fits) {
+    if (o.valid) {
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+        atomicAdd((unsigned long long*)(fxc + k * G.Np + o.node), (unsigned long long)o.q[k]);
+      tfc[o.node >> TILE_SHIFT] = 1;
+    }
+    return;
+  }
+  const int ncell = ex * ey * ez;
+  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+    acc[0][c] = acc[1][c] = acc[2][c] = 0;
+    nid[c] = -1;
+  }
+  __syncthreads();
+  if (o.valid) {
+    const int c = (o.cx - x0) + ex * ((o.cy - y0) + ey * (o.cz - z0));
+#pragma unroll
+    for (int k = 0; k < 3; k++) atomicAdd((unsigned long long*)&acc[k][c], (unsigned long long)o.q[k]);
+    nid[c] = o.node;  // every lane that writes a cell writes the same node
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+    const long long node = nid[c];
+    if (node < 0) continue;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+      if (acc[k][c] != 0) atomicAdd((unsigned long long*)(fxc + k * G.Np + node), (unsigned long long)acc[k][c]);
+    tfc[node >> TILE_SHIFT] = 1;
   }
 }
 
@@ -1034,7 +1238,10 @@ __global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long 
   const int blk = blockIdx.x;
   if (blk < b.n_marker_blocks) {
     const int m = blk * 8 + (threadIdx.x >> 5);
-    if (m < b.nf) ib_marker<S>(a, b, fxc, tfc, m, threadIdx.x & 31);
+    Contrib o;
+    o.valid = false;
+    if (m < b.nf) ib_marker<S>(a, b, m, threadIdx.x & 31, o);
+    spread_block(a.g, o, fxc, tfc);
   } else if (blk < b.n_marker_blocks + b.n_elem_blocks) {
     membrane_element(b, (blk - b.n_marker_blocks) * 256 + threadIdx.x);
   } else {
@@ -1323,24 +1530,26 @@ __device__ void soft_vertex(const BodyArgs& b, int idx) {
   int32_t t[VT_SLOTS];
 #pragma unroll
   for (int k = 0; k < VT_SLOTS; k++) t[k] = b.vtab[(long long)k * b.nv + v];
+  // Branch-free gather: every slot loads from a valid address (entry 0 for
+  // an empty slot) and adds its value only when the slot is used, so all
+  // the loads go out together instead of one slot at a time.
+  double val[VT_SLOTS][3];
 #pragma unroll
-  for (int k = 0; k < VT_E; k++) {
-    if (t[k] == 0) continue;
-    const int e = (t[k] > 0 ? t[k] : -t[k]) - 1;
-    const double sg = t[k] > 0 ? 1.0 : -1.0;
-    for (int c = 0; c < 3; c++) F[c] += sg * b.f_edge[3 * e + c];
+  for (int k = 0; k < VT_SLOTS; k++) {
+    const int a = t[k] > 0 ? t[k] - 1 : (t[k] < 0 ? -t[k] - 1 : 0);
+    const double* src = k < VT_E ? b.f_edge : (k < VT_E + VT_H ? b.f_hinge : b.fext);
+#pragma unroll
+    for (int c = 0; c < 3; c++) val[k][c] = src[3 * a + c];
   }
 #pragma unroll
-  for (int k = VT_E; k < VT_E + VT_H; k++) {
-    if (t[k] == 0) continue;
-    const int hr = t[k] - 1;
-    for (int c = 0; c < 3; c++) F[c] += b.f_hinge[3 * hr + c];
-  }
+  for (int k = 0; k < VT_SLOTS; k++) {
+    const bool used = t[k] != 0;
 #pragma unroll
-  for (int k = VT_E + VT_H; k < VT_SLOTS; k++) {
-    if (t[k] == 0) continue;
-    const int f = t[k] - 1;
-    for (int c = 0; c < 3; c++) F[c] += b.fext[3 * f + c] / 3.0;
+    for (int c = 0; c < 3; c++) {
+      double x = k < VT_E ? (t[k] > 0 ? val[k][c] : -val[k][c])
+                          : (k < VT_E + VT_H ? val[k][c] : val[k][c] / 3.0);
+      F[c] += used ? x : 0.0;
+    }
   }
   const double mv = b.b_param[8 * body + 3];
   for (int k = 0; k < 3; k++) {
@@ -1352,8 +1561,9 @@ __device__ void soft_vertex(const BodyArgs& b, int idx) {
   }
 }
 
-// Last launch of a coupled step: rigid blocks, then soft-vertex blocks; the
-// last block to finish closes the step.
+// Last launch of a coupled step: rigid blocks, then soft-vertex blocks (one
+// vertex per thread, 64-thread blocks); the last block to finish closes the
+// step.
 __global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags,
                                                    unsigned int* counter) {
   if (flags->stop) return;
@@ -1361,7 +1571,7 @@ __global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags,
   if (blk < b.nbody) {
     if (b.b_rigid[blk]) rigid_block(b, blk);
   } else {
-    const int idx = (blk - b.nbody) * 256 + threadIdx.x;
+    const int idx = (blk - b.nbody) * (int)blockDim.x + threadIdx.x;
     if (idx < b.nsoft_v) soft_vertex(b, idx);
   }
   if (last_block(counter, gridDim.x)) close_step(flags, counter);
@@ -1571,8 +1781,9 @@ hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, long
 
 hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter,
                             hipStream_t s) {
-  const unsigned grid = (unsigned)b.nbody + cdiv(b.nsoft_v, 256);
-  k_body_post<<<grid, 256, 0, s>>>(b, flags, counter);
+  // small blocks: the vertex gathers are spread over many CUs' load pipelines
+  const unsigned grid = (unsigned)b.nbody + cdiv(b.nsoft_v, 64);
+  k_body_post<<<grid, 64, 0, s>>>(b, flags, counter);
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .geometry import Domain, bifurcation, periodic_box, pipe
-from .mesh import Body, icosphere
+from .mesh import Body, icosphere, off_switch_planes
 
 
 @dataclass
@@ -32,11 +32,12 @@ class Workload:
 def pipe_sphere(precision="f64", steps=200):
     """Straight pipe D = 16 on a 48x20x20 grid, tau = 0.8, Poiseuille inlet
     u_max = 0.05, outlet rho = 1, one rigid icosphere (subdivision 2, 162
-    vertices) of radius 4 released at rest on the axis at x = 12, density
-    ratio 1.1.  No random draws."""
+    vertices, in the fixed tilted orientation) of radius 4 released at rest on
+    the axis at x = 12, density ratio 1.1.  No random draws."""
     tau, u_max = 0.8, 0.05
     dom = pipe(48, 20, 20, 8.0, u_max=u_max, tau=tau, init="poiseuille")
-    X, F = icosphere(2, 4.0, (12.0, 9.5, 9.5))
+    X, F = icosphere(2, 4.0, (12.0, 9.5, 9.5), tilt=True)
+    assert off_switch_planes(X, F)
     body = Body(X, F, rigid=True, rho_ratio=1.1, r_ref=4.0, u_ref=u_max)
     return Workload("pipe_sphere", dom, [body], tau, u_max, precision, steps)
 
@@ -48,7 +49,9 @@ def bifurcation_capsule(seed=0, precision="f32", steps=5000, nx=256, ny=128, nz=
     tau = 0.7 (so u_max = Re*nu/D), one deformable icosphere capsule
     (subdivision 4, 2562 vertices) at occlusion ratio 0.5 with Ca = 0.01,
     density ratio 1.1, released at x = 1.16 D with a lateral offset drawn
-    first from U[-0.1 D, 0.1 D].
+    first from U[-0.1 D, 0.1 D].  The mesh is in the fixed tilted orientation
+    so that no marker starts on the mid-plane z = (nz - 1)/2, a half-integer
+    plane where the support of the 3x3x3 stencil would be chosen by rounding.
 
     Bending number: 1e-4 instead of the paper's 1e-3.  For this mesh (rest
     edge ~0.6 lu, vertex mass ~0.92) the largest bending mode of the rest
@@ -63,7 +66,8 @@ def bifurcation_capsule(seed=0, precision="f32", steps=5000, nx=256, ny=128, nz=
     rp = occlusion * D / 2.0
     dy = rng.uniform(-0.1 * D, 0.1 * D)
     c = (1.16 * D, (ny - 1) / 2.0 + dy, (nz - 1) / 2.0)
-    X, F = icosphere(subdiv, rp, c)
+    X, F = icosphere(subdiv, rp, c, tilt=True)
+    assert off_switch_planes(X, F)
     body = Body(X, F, rigid=False, ca=ca, eb=eb, rho_ratio=1.1, r_ref=rp, u_ref=u_max)
     return Workload("bifurcation_capsule", dom, [body], tau, u_max, precision, steps,
                     meta={"offset": dy, "seed": seed})
@@ -96,7 +100,9 @@ def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_
             break
         if not placed:
             break
-        X, F = icosphere(sub, rp, c)
+        X, F = icosphere(sub, rp, c, tilt=True)
+        if not off_switch_planes(X, F):
+            continue
         bodies.append(Body(X, F, rigid=False, ca=ca, eb=0.001, rho_ratio=1.1, r_ref=rp, u_ref=u_max))
         centres.append(c)
         radii.append(rp)
@@ -186,7 +192,8 @@ def tiny_bifurcation(seed=0, precision="f64", steps=20, n_bodies=1, subdiv=2):
         dy = rng.uniform(-0.1 * D, 0.1 * D)
         rp = 2.6
         c = (10.0 + 5.4 * k, 19.5 + dy, 7.5 + (0.3 if k else 0.0))
-        X, F = icosphere(subdiv, rp, c)
+        X, F = icosphere(subdiv, rp, c, tilt=True)
+        assert off_switch_planes(X, F)
         bodies.append(Body(X, F, rigid=False, ca=0.05, eb=0.001, rho_ratio=1.1, r_ref=rp,
                            u_ref=u_max))
     del nu

@@ -14,7 +14,20 @@ from dataclasses import dataclass
 import numpy as np
 
 
-def icosphere(subdiv: int, radius: float = 1.0, center=(0.0, 0.0, 0.0)):
+# Fixed generic orientation (rotations of 1.1, 0.7 and 0.3 rad about x, y
+# and z, in that order) applied by ``icosphere(..., tilt=True)``.  It keeps
+# mesh vertices and face centroids of a sphere centred on a half-integer
+# lattice coordinate off the planes where the nearest-node stencil base
+# floor(x + 1/2) changes.
+def _tilt_matrix():
+    ax, ay, az = 1.1, 0.7, 0.3
+    rx = np.array([[1, 0, 0], [0, np.cos(ax), -np.sin(ax)], [0, np.sin(ax), np.cos(ax)]])
+    ry = np.array([[np.cos(ay), 0, np.sin(ay)], [0, 1, 0], [-np.sin(ay), 0, np.cos(ay)]])
+    rz = np.array([[np.cos(az), -np.sin(az), 0], [np.sin(az), np.cos(az), 0], [0, 0, 1]])
+    return rz @ ry @ rx
+
+
+def icosphere(subdiv: int, radius: float = 1.0, center=(0.0, 0.0, 0.0), tilt: bool = False):
     phi = (1.0 + 5.0 ** 0.5) / 2.0
     v = [(-1, phi, 0), (1, phi, 0), (-1, -phi, 0), (1, -phi, 0),
          (0, -1, phi), (0, 1, phi), (0, -1, -phi), (0, 1, -phi),
@@ -47,7 +60,20 @@ def icosphere(subdiv: int, radius: float = 1.0, center=(0.0, 0.0, 0.0)):
     a, b, c = X[F[:, 0]], X[F[:, 1]], X[F[:, 2]]
     flip = np.einsum("ij,ij->i", np.cross(b - a, c - a), a + b + c) < 0
     F[flip] = F[flip][:, [0, 2, 1]]
+    if tilt:
+        X = X @ _tilt_matrix().T
     return X * radius + np.asarray(center, np.float64), F
+
+
+def off_switch_planes(X, F, eps=1e-6):
+    """True when no vertex and no face centroid lies within eps of a plane
+    x_a = k + 1/2, where the 3x3x3 support base floor(x + 1/2) jumps: a marker
+    released on such a plane has a support chosen by rounding."""
+    for P in (X, X[F].mean(1)):
+        fr = (P + 0.5) - np.floor(P + 0.5)
+        if np.any((fr < eps) | (fr > 1.0 - eps)):
+            return False
+    return True
 
 
 @dataclass

@@ -162,6 +162,29 @@ def test_ib_interpolate_and_spread_match_oracle(lib):
     assert np.abs(a - b).max() < 1e-15
 
 
+def test_ib_spread_out_of_range_is_reported(lib):
+    """A contribution c phi F beyond the fixed-point range is dropped and
+    reported; the rest of the call is still added, and the run's own flags
+    are untouched."""
+    import torch
+    d = synth.periodic_box(12, 12, 12)
+    w = synth.Workload("box_range", d, [], 0.8, 0.0, "f64", 0)
+    lat = lib.from_workload(w)
+    orc = oracle.from_workload(w)
+    pts = np.array([[5.2, 6.1, 4.7], [3.3, 3.9, 8.2]])
+    F = np.array([[1e-3, -2e-3, 5e-4], [0.0, 0.0, 1e6]])
+    c = np.array([0.5, 1.0])
+    _say("[ops] ib_spread out of range")
+    fib = torch.zeros(3, d.n_nodes, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.LbmError):
+        lat.ib_spread(torch.from_numpy(pts), torch.from_numpy(F), torch.from_numpy(c), fib)
+    # the in-range point went in: compare with the oracle on that point alone
+    fo = orc.ib_spread(pts[:1], F[:1], c[:1])
+    assert np.abs(fib.cpu().numpy() - fo).max() < 1e-15
+    lat.step(2)
+    assert lat.sync(raise_on_stop=False) == lib.LBM_OK
+
+
 # --------------------------------------------------------- full config 1
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_pipe_sphere_config(lib, precision):
