@@ -72,6 +72,7 @@ struct lbm_ctx {
   long long ntiles = 0;
   long long* fx[2] = {nullptr, nullptr};
   uint8_t* tf[2] = {nullptr, nullptr};
+  void* mac = nullptr;  // [Np][4] rho - 1, u of the step in the compute type (bodies only)
   long long* fx_api = nullptr;
   DevFlags* api_flags = nullptr;  // range flags of ib_spread (kept apart from the run's)
   DevFlags* flags = nullptr;  // followed by the block counter
@@ -87,7 +88,6 @@ struct lbm_ctx {
   double* b_diag = nullptr;
   // graphs
   bool use_graph = true;
-  int rec_lanes = 0;
   int rec_block = 64;
   int bulk_v = 4;
   int bulk_block = 256;
@@ -165,7 +165,6 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   const bool large = (long long)d->nx * d->ny * d->nz >= (4LL << 20);
   ctx->bulk_v = large ? (d->precision == 0 ? 2 : (d->precision == 1 ? 4 : 8)) : (d->precision == 2 ? 2 : 1);
   ctx->bulk_block = large ? 256 : 64;
-  if (const char* ev = getenv("LBM_RECORD_LANES")) ctx->rec_lanes = atoi(ev) != 0;
   if (const char* ev = getenv("LBM_RECORD_BLOCK")) ctx->rec_block = atoi(ev);
   if (const char* ev = getenv("LBM_BULK_V")) ctx->bulk_v = atoi(ev);
   if (const char* ev = getenv("LBM_BULK_BLOCK")) ctx->bulk_block = atoi(ev);
@@ -404,7 +403,7 @@ extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
   void* ptrs[] = {ctx->f_alloc[0], ctx->f_alloc[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
                   ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_c,
                   ctx->tile_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
-                  ctx->api_flags, ctx->flags};
+                  ctx->api_flags, ctx->mac, ctx->flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -679,6 +678,9 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
       CHK(hipMalloc(&ctx->tf[p], ctx->ntiles));
       CHK(hipMemset(ctx->tf[p], 0, ctx->ntiles));
     }
+    const size_t macb = 4 * (size_t)ctx->g.Np * (ctx->prec == 0 ? sizeof(double) : sizeof(float));
+    CHK(hipMalloc(&ctx->mac, macb));
+    CHK(hipMemset(ctx->mac, 0, macb));
   }
   // diagnostics of the current positions
   CHK(launch_check(ctx->bargs[cur], ctx->X[0], ctx->X[1], ctx->flags, counter(ctx, 3), ctx->stream));
@@ -862,8 +864,8 @@ static FluidArgs fluid_args(lbm_ctx* ctx, int p) {
   const bool ib = ctx->nf > 0;
   a.fx = ib ? ctx->fx[p] : nullptr;
   a.tflag = ib ? ctx->tf[p] : nullptr;
+  a.mac = ib ? ctx->mac : nullptr;
   a.flags = ctx->flags;
-  a.rec_lanes = ctx->rec_lanes;
   a.rec_block = ctx->rec_block;
   a.bulk_v = ctx->bulk_v;
   a.bulk_block = ctx->bulk_block;

@@ -64,11 +64,11 @@ struct FluidArgs {
   double gx, gy, gz;         // uniform body force
   const long long* fx;       // fixed-point IB force [3][Np] of this step (may be null)
   const uint8_t* tflag;      // tile flags of this step (may be null)
+  void* mac;                 // [Np][4] rho - 1, u of this step in the compute type (null: not kept)
   DevFlags* flags;
   unsigned int* counter;     // block counter used when this launch closes the step
   int close_step;            // 1: no bodies, this launch is the whole step
-  int rec_lanes;             // boundary records: 1 = 32 lanes per record, 0 = one thread
-  int rec_block;             // threads per block of the record kernel (one-thread mode)
+  int rec_block;             // threads per block of the record kernel
   int bulk_v;                // nodes per thread of the bulk kernel
   int bulk_block;            // threads per block of the bulk kernel
 };

@@ -129,13 +129,14 @@ __device__ __forceinline__ C dev_sum(const C (&g)[19]) {
 // g^eq_i = w_i (drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)),
 // F_i = (1 - 1/(2 tau)) w_i (3 (e_i - u) + 9 (e_i.u) e_i).F.
 template <class C>
-__device__ __forceinline__ void collide(C (&g)[19], C Fx, C Fy, C Fz, C omega, C& rho, C& ux,
+__device__ __forceinline__ void collide(C (&g)[19], C Fx, C Fy, C Fz, C omega, C& drho_out, C& ux,
                                         C& uy, C& uz) {
   const C drho = dev_sum(g);
+  drho_out = drho;
   C mx = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
   C my = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
   C mz = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
-  rho = C(1) + drho;
+  const C rho = C(1) + drho;
   C ir = C(1) / rho;
   ux = (mx + C(0.5) * Fx) * ir;
   uy = (my + C(0.5) * Fy) * ir;
@@ -497,9 +498,10 @@ __device__ void fluid_bulk(const FluidArgs& a, int blk) {
     C g[19];
 #pragma unroll
     for (int j = 0; j < 19; j++) g[j] = to_c(in[j][k]);
-    C Fx, Fy, Fz, rho, ux, uy, uz;
+    C Fx, Fy, Fz, drho, ux, uy, uz;
     node_force<C>(a, base + k, flagged && isb[k], Fx, Fy, Fz);
-    collide<C>(g, Fx, Fy, Fz, omega, rho, ux, uy, uz);
+    collide<C>(g, Fx, Fy, Fz, omega, drho, ux, uy, uz);
+    if (a.mac && isb[k]) store_mac<C>(a, base + k, drho, ux, uy, uz);
     bad = bad || (isb[k] && !(ux * ux + uy * uy + uz * uz <= C(0.09)));
 #pragma unroll
     for (int j = 0; j < 19; j++) in[j][k] = (S)g[j];
@@ -517,129 +519,29 @@ __device__ void fluid_bulk(const FluidArgs& a, int blk) {
   if (bad) raise_pending(a.flags, ST_UNSTABLE);
 }
 
-// Direction tables as bit masks, for lanes that own one direction each.
-constexpr uint32_t bits_of(const int (&v)[19], int val) {
-  uint32_t m = 0;
-  for (int i = 0; i < 19; i++)
-    if (v[i] == val) m |= 1u << i;
-  return m;
-}
-constexpr uint32_t PXM = bits_of(EX, 1), NXM = bits_of(EX, -1);
-constexpr uint32_t PYM = bits_of(EY, 1), NYM = bits_of(EY, -1);
-constexpr uint32_t PZM = bits_of(EZ, 1), NZM = bits_of(EZ, -1);
-__device__ __forceinline__ int ecomp(uint32_t pm, uint32_t nm, int j) {
-  return (int)((pm >> j) & 1u) - (int)((nm >> j) & 1u);
-}
-__device__ __forceinline__ int opp_of(int j) {
-  // 1<->2, 3<->4, 5<->6, 7<->12, 8<->11, 9<->14, 10<->13, 15<->18, 16<->17
-  if (j == 0) return 0;
-  if (j <= 6) return (j & 1) ? j + 1 : j - 1;
-  if (j <= 14) return ((j - 7) & 2) ? 23 - j : 19 - j;
-  return 33 - j;
-}
-
+// This step's rho - 1 and u at a node (what the probes and the vertex
+// velocities interpolate), [Np][4] in the compute type.
 template <class C>
-__device__ __forceinline__ C seg_sum(C v) {
-#pragma unroll
-  for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
-  return v;
+__device__ __forceinline__ void store_mac(const FluidArgs& a, long long node, C drho, C ux, C uy, C uz) {
+  typedef C C4 __attribute__((ext_vector_type(4)));
+  C4 v;
+  v.x = drho;
+  v.y = ux;
+  v.z = uy;
+  v.w = uz;
+  ((C4*)a.mac)[node] = v;
 }
 
-// Boundary record (32 lanes; lane j < 19 owns direction j): pull or
-// interpolated bounce-back for its direction, Zou-He and moments by segment
-// reductions, then the forced BGK collision of its own population.
 template <class S>
-__device__ void fluid_record_lanes(const FluidArgs& a, int r, int j) {
+__device__ __forceinline__ void load_mac(const FluidArgs& a, long long node, double& drho, double& ux,
+                                         double& uy, double& uz) {
   typedef typename Store<S>::C C;
-  const Grid& G = a.g;
-  const long long node = a.rec_node[r];
-  const uint32_t mask = a.rec_mask[r];
-  const int lk0 = a.rec_link0[r];
-  const int fc = a.rec_face[r];
-  int x, y, z;
-  coords(G, node, x, y, z);
-  const bool act = j < 19;
-  const int jj = act ? j : 0;
-  const int ex = ecomp(PXM, NXM, jj), ey = ecomp(PYM, NYM, jj), ez = ecomp(PZM, NZM, jj);
-  const int i = opp_of(jj);
-  const bool linked = act && ((mask >> jj) & 1u);
-  // loads
-  const C self_j = ldA<S>(a, jj, node);
-  const C pulled = ldA<S>(a, jj, nbr(G, x, y, z, -ex, -ey, -ez));
-  C fi_x = 0, b1 = 0, b2 = 0, b3 = 0, c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
-  if (linked) {
-    const int lk = lk0 + __popc(mask & ((1u << jj) - 2u));
-    c0 = (C)a.lk_c[lk];
-    c1 = (C)a.lk_c[(long long)a.nlinks + lk];
-    c2 = (C)a.lk_c[2LL * a.nlinks + lk];
-    c3 = (C)a.lk_c[3LL * a.nlinks + lk];
-    c4 = (C)a.lk_c[4LL * a.nlinks + lk];
-    const long long n1 = nbr(G, x, y, z, ex, ey, ez);  // x - e_i
-    const long long n2 = nbr(G, x, y, z, 2 * ex, 2 * ey, 2 * ez);
-    fi_x = ldA<S>(a, i, node);
-    b1 = ldA<S>(a, i, n1);
-    b2 = ldA<S>(a, i, n2);
-    b3 = ldA<S>(a, jj, n1);
-  }
-  C gj;
-  if (jj == 0) gj = self_j;
-  else if (!linked) gj = pulled;
-  else gj = c0 * fi_x + c1 * b1 + c2 * b2 + c3 * self_j + c4 * b3;
-  if (!act) gj = C(0);
-  const int seg = threadIdx.x & 32;  // first lane of this segment within the wave
-  if (fc != 0xff) {
-    // Zou-He (Eq. extbound) on deviations, inward normal n = s e_ax
-    const int face = fc & 7, kind = (fc >> 4) & 1;
-    const int ax = face >> 1, s = (face & 1) ? -1 : 1;
-    const int e_ax = ax == 0 ? ex : (ax == 1 ? ey : ez);
-    const int en = act ? s * e_ax : 2;
-    if (en == 1) gj = C(0);
-    const C G0 = seg_sum<C>(en == 0 ? gj : C(0));
-    const C Gout = seg_sum<C>(en == -1 ? gj : C(0));
-    // tangential axes t1, t2 (the two axes other than ax)
-    const int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
-    const int e1 = a1 == 0 ? ex : (a1 == 1 ? ey : ez);
-    const int e2 = a2 == 0 ? ex : (a2 == 1 ? ey : ez);
-    const C T1 = seg_sum<C>(en == 0 ? C(e1) * gj : C(0));
-    const C T2 = seg_sum<C>(en == 0 ? C(e2) * gj : C(0));
-    C u[3] = {(C)a.rec_bc[r], (C)a.rec_bc[a.nrec + r], (C)a.rec_bc[2 * a.nrec + r]};
-    C rho, un;
-    if (kind == 0) {
-      un = C(s) * u[ax];
-      rho = (C(1) + G0 + C(2) * Gout) / (C(1) - un);
-    } else {
-      rho = (C)a.rec_bc[3 * a.nrec + r];
-      un = (rho - C(1) - G0 - C(2) * Gout) / rho;
-      u[0] = u[1] = u[2] = C(0);
-      u[ax] = C(s) * un;
-    }
-    const C N1 = C(0.5) * T1 - rho / C(3) * u[a1];
-    const C N2 = C(0.5) * T2 - rho / C(3) * u[a2];
-    const C g_opp = __shfl(gj, seg + i, 64);
-    if (en == 1) {
-      if (e1 == 0 && e2 == 0) gj = g_opp + rho / C(3) * un;
-      else if (e1 != 0) gj = g_opp + rho / C(6) * (un + C(e1) * u[a1]) - C(e1) * N1;
-      else gj = g_opp + rho / C(6) * (un + C(e2) * u[a2]) - C(e2) * N2;
-    }
-  }
-  // moments and forced collision
-  const C drho = seg_sum<C>(gj);
-  const C mx = seg_sum<C>(C(ex) * gj), my = seg_sum<C>(C(ey) * gj), mz = seg_sum<C>(C(ez) * gj);
-  const bool flagged = a.tflag && a.tflag[node >> TILE_SHIFT];
-  C Fx, Fy, Fz;
-  node_force<C>(a, node, flagged, Fx, Fy, Fz);
-  const C rho = C(1) + drho, ir = C(1) / rho;
-  const C ux = (mx + C(0.5) * Fx) * ir, uy = (my + C(0.5) * Fy) * ir, uz = (mz + C(0.5) * Fz) * ir;
-  const C usq = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
-  const C omega = (C)a.omega, kf = C(1) - C(0.5) * omega;
-  const C w = jj == 0 ? C(1.0 / 3) : (jj <= 6 ? C(1.0 / 18) : C(1.0 / 36));
-  const C eu = C(ex) * ux + C(ey) * uy + C(ez) * uz;
-  const C eF = C(ex) * Fx + C(ey) * Fy + C(ez) * Fz;
-  const C geq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * usq));
-  const C Gi = kf * w * (C(3) * (eF - uF) + C(9) * eu * eF);
-  const C out = gj - omega * (gj - geq) + Gi;
-  if (act) ((S*)a.B)[(long long)jj * G.plane + node] = (S)out;
-  if (j == 0 && !(usq <= C(0.09))) raise_pending(a.flags, ST_UNSTABLE);
+  typedef C C4 __attribute__((ext_vector_type(4)));
+  const C4 v = ((const C4*)a.mac)[node];
+  drho = (double)v.x;
+  ux = (double)v.y;
+  uy = (double)v.z;
+  uz = (double)v.w;
 }
 
 // Boundary record, one thread: all loads in one batch (pull_general), then
@@ -652,9 +554,10 @@ __device__ void fluid_record_thread(const FluidArgs& a, int r) {
   pull_general<S>(a, r, g);
   const long long node = a.rec_node[r];
   const bool flagged = a.tflag && a.tflag[node >> TILE_SHIFT];
-  C Fx, Fy, Fz, rho, ux, uy, uz;
+  C Fx, Fy, Fz, drho, ux, uy, uz;
   node_force<C>(a, node, flagged, Fx, Fy, Fz);
-  collide<C>(g, Fx, Fy, Fz, (C)a.omega, rho, ux, uy, uz);
+  collide<C>(g, Fx, Fy, Fz, (C)a.omega, drho, ux, uy, uz);
+  if (a.mac) store_mac<C>(a, node, drho, ux, uy, uz);
   S* B = (S*)a.B;
 #pragma unroll
   for (int j = 0; j < 19; j++) B[(long long)j * a.g.plane + node] = (S)g[j];
@@ -674,13 +577,8 @@ __global__ __launch_bounds__(256) void k_fluid_bulk(FluidArgs a) {
 template <class S>
 __global__ __launch_bounds__(256) void k_fluid_rec(FluidArgs a) {
   if (a.flags->stop) return;
-  if (a.rec_lanes) {
-    const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
-    if (r < a.nrec) fluid_record_lanes<S>(a, r, threadIdx.x & 31);
-  } else {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < a.nrec) fluid_record_thread<S>(a, r);
-  }
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < a.nrec) fluid_record_thread<S>(a, r);
 }
 
 // Closes a fluid-only step (one thread).
@@ -1314,11 +1212,12 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b, long 
     const double sg = half == 0 ? 1.2 : -1.2;
     const Slot s = stencil_slot(G, a.ncls, cen[0] + sg * nrm[0], cen[1] + sg * nrm[1],
                                 cen[2] + sg * nrm[2], lane);
-    double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
-    if (s.valid) macro_at<S>(G, f, a.fx, a.tflag, a.gx, a.gy, a.gz, s.node, rho, u[0], u[1], u[2]);
+    double drho = 0.0, u[3] = {0.0, 0.0, 0.0};
+    if (s.valid) load_mac<S>(a, s.node, drho, u[0], u[1], u[2]);
     double psi[4];
     if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
-    const double rfit = red32(psi[0] * rho);
+    // the weights add up to 1, so the fit of rho is 1 + the fit of rho - 1
+    const double rfit = 1.0 + red32(psi[0] * drho);
     double Gm[3][3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
@@ -1384,8 +1283,8 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b, long 
   const int v = b.soft_vlist[idx];
   const double X = b.Xcur[3 * v], Y = b.Xcur[3 * v + 1], Z = b.Xcur[3 * v + 2];
   const Slot s = stencil_slot(G, a.ncls, X, Y, Z, lane);
-  double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
-  if (s.valid) macro_at<S>(G, f, a.fx, a.tflag, a.gx, a.gy, a.gz, s.node, rho, u[0], u[1], u[2]);
+  double drho = 0.0, u[3] = {0.0, 0.0, 0.0};
+  if (s.valid) load_mac<S>(a, s.node, drho, u[0], u[1], u[2]);
   double psi[4];
   if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
   double U[3];
@@ -1739,8 +1638,8 @@ hipError_t launch_fluid_bulk(int prec, const FluidArgs& a, hipStream_t s) {
 
 hipError_t launch_fluid_rec(int prec, const FluidArgs& a, hipStream_t s) {
   if (a.nrec == 0) return hipSuccess;
-  const unsigned grid = cdiv(a.nrec, a.rec_lanes ? 8 : a.rec_block);
-  const unsigned blk = a.rec_lanes ? 256u : (unsigned)a.rec_block;
+  const unsigned grid = cdiv(a.nrec, a.rec_block);
+  const unsigned blk = (unsigned)a.rec_block;
   switch (prec) {
     case 0: k_fluid_rec<double><<<grid, blk, 0, s>>>(a); break;
     case 1: k_fluid_rec<float><<<grid, blk, 0, s>>>(a); break;
