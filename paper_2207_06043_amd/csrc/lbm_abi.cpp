@@ -83,7 +83,6 @@ struct lbm_ctx {
   BodyArgs bargs[2]{};
   double* X[2] = {nullptr, nullptr};
   double* Vel = nullptr;
-  int32_t* base[2] = {nullptr, nullptr};
   double* b_rig = nullptr;
   double* b_diag = nullptr;
   // graphs
@@ -487,8 +486,7 @@ static double tri_area(const double* X, int a, int b, int c) {
 // device arrays; dyn_* hold the dynamic state of the bodies already present.
 static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<double>& Xc,
                                     const std::vector<double>& Xp, const std::vector<double>& Vl,
-                                    const std::vector<double>& rig, const std::vector<int32_t>& b_other,
-                                    const std::vector<int32_t>& b_last) {
+                                    const std::vector<double>& rig) {
   free_bodies(ctx);
   const int nb = (int)ctx->bodies.size();
   std::vector<int32_t> faces, face_body, vert_body, edges, hinges, soft;
@@ -537,23 +535,27 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   ctx->nsoft_v = (int)soft.size();
   // vertex incidence tables, slot-major [VT_SLOTS][nv]
   std::vector<int32_t> vtab((size_t)VT_SLOTS * v0, 0);
+  // and the slot each (element, vertex role) writes its force into
   std::vector<int> ne_cnt(v0, 0), nh_cnt(v0, 0), nf_cnt(v0, 0);
-  auto put = [&](int v, int slot0, int width, std::vector<int>& cnt, int32_t val) {
+  std::vector<int32_t> sl_edge(2 * (size_t)e0), sl_hinge(4 * (size_t)e0), sl_face(3 * (size_t)f0);
+  auto put = [&](int v, int slot0, int width, std::vector<int>& cnt, int32_t val, int32_t& slot) {
     if (cnt[v] >= width) return false;
-    vtab[(size_t)(slot0 + cnt[v]++) * v0 + v] = val;
+    slot = slot0 + cnt[v]++;
+    vtab[(size_t)slot * v0 + v] = val;
     return true;
   };
   for (int e = 0; e < e0; e++) {
-    if (!put(edges[2 * e], 0, VT_E, ne_cnt, e + 1) || !put(edges[2 * e + 1], 0, VT_E, ne_cnt, -(e + 1)))
+    if (!put(edges[2 * e], 0, VT_E, ne_cnt, e + 1, sl_edge[2 * e]) ||
+        !put(edges[2 * e + 1], 0, VT_E, ne_cnt, -(e + 1), sl_edge[2 * e + 1]))
       return fail(ctx, LBM_E_INVAL, "vertex valence above 10");
   }
   for (int h = 0; h < e0; h++)
     for (int r = 0; r < 4; r++)
-      if (!put(hinges[4 * h + r], VT_E, VT_H, nh_cnt, 4 * h + r + 1))
+      if (!put(hinges[4 * h + r], VT_E, VT_H, nh_cnt, 4 * h + r + 1, sl_hinge[4 * h + r]))
         return fail(ctx, LBM_E_INVAL, "vertex in more than 20 hinges");
   for (int f = 0; f < f0; f++)
     for (int r = 0; r < 3; r++)
-      if (!put(faces[3 * f + r], VT_E + VT_H, VT_F, nf_cnt, f + 1))
+      if (!put(faces[3 * f + r], VT_E + VT_H, VT_F, nf_cnt, f + 1, sl_face[3 * f + r]))
         return fail(ctx, LBM_E_INVAL, "vertex valence above 10");
   auto up = [&](auto** p, const auto& v) -> hipError_t {
     hipError_t e = upload(p, v);
@@ -567,7 +569,7 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.ne = e0;
   B.nh = e0;
   B.nsoft_v = ctx->nsoft_v;
-  int32_t *d_soft, *d_faces, *d_fb, *d_vb, *d_edges, *d_hinges, *d_vtab, *d_bf0, *d_bnf, *d_bv0,
+  int32_t *d_soft, *d_faces, *d_fb, *d_vb, *d_edges, *d_hinges, *d_bf0, *d_bnf, *d_bv0,
       *d_bnv, *d_be0, *d_bne, *d_brig, *d_bfix;
   double *d_l0, *d_kl, *d_th0, *d_kb, *d_param, *d_Xbody;
   CHK(up(&d_soft, soft));
@@ -576,7 +578,6 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   CHK(up(&d_vb, vert_body));
   CHK(up(&d_edges, edges));
   CHK(up(&d_hinges, hinges));
-  CHK(up(&d_vtab, vtab));
   CHK(up(&d_bf0, bf0));
   CHK(up(&d_bnf, bnf));
   CHK(up(&d_bv0, bv0));
@@ -617,22 +618,25 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.b_dblk0 = d_dblk0;
   B.dblk_body = d_dblkb;
   B.n_diag_blocks = (int)dblk_body.size();
-  B.n_marker_blocks = (f0 + 7) / 8;
+  B.n_marker_blocks = (f0 + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
   B.n_elem_blocks = (2 * e0 + 255) / 256;
-  // the next step has parity cur: it writes base[cur] and clears the spread
-  // of the last completed step, whose stencil bases are in base[cur ^ 1]
-  CHK(up(&ctx->base[cur ^ 1], b_last));
-  CHK(up(&ctx->base[cur], b_other));
+  // one flag per thread: blocks of 256 threads cover 256 tiles each
+  B.n_clear_blocks = (int)std::min<long long>(64, ((ctx->g.Np >> TILE_SHIFT) + 1 + 255) / 256);
   std::vector<double> zf(3 * (size_t)f0, 0.0), zv(3 * (size_t)v0, 0.0);
-  double *d_cen, *d_fext, *d_u0v, *d_fedge, *d_fhinge;
+  double *d_cen, *d_fext, *d_u0v, *d_fslot;
+  int32_t *d_sle, *d_slh, *d_slf;
   CHK(up(&d_cen, zf));
   CHK(up(&d_fext, zf));
   CHK(up(&d_u0v, zv));
-  std::vector<double> ze(3 * (size_t)e0, 0.0), zh(12 * (size_t)e0, 0.0);
-  CHK(up(&d_fedge, ze));
-  CHK(up(&d_fhinge, zh));
-  B.f_edge = d_fedge;
-  B.f_hinge = d_fhinge;
+  // slots nobody writes stay zero
+  CHK(up(&d_fslot, std::vector<double>((size_t)VT_SLOTS * 3 * v0, 0.0)));
+  CHK(up(&d_sle, sl_edge));
+  CHK(up(&d_slh, sl_hinge));
+  CHK(up(&d_slf, sl_face));
+  B.f_slot = d_fslot;
+  B.sl_edge = d_sle;
+  B.sl_hinge = d_slh;
+  B.sl_face = d_slf;
   B.soft_vlist = d_soft;
   B.Vel = ctx->Vel;
   B.faces = d_faces;
@@ -644,7 +648,6 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.hinges = d_hinges;
   B.theta0 = d_th0;
   B.kb = d_kb;
-  B.vtab = d_vtab;
   B.b_face0 = d_bf0;
   B.b_nf = d_bnf;
   B.b_vert0 = d_bv0;
@@ -666,8 +669,6 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
     ctx->bargs[p] = B;
     ctx->bargs[p].Xcur = ctx->X[p];
     ctx->bargs[p].Xnext = ctx->X[p ^ 1];
-    ctx->bargs[p].base_cur = ctx->base[p];
-    ctx->bargs[p].base_prev = ctx->base[p ^ 1];
   }
   // force buffers (once)
   if (!ctx->fx[0]) {
@@ -795,15 +796,11 @@ extern "C" lbm_status lbm_add_body(lbm_ctx* ctx, const lbm_body_desc* bd, int32_
   const int nb_old = (int)ctx->bodies.size();
   std::vector<double> Xc(3 * (size_t)ctx->nv), Xp(3 * (size_t)ctx->nv), Vl(3 * (size_t)ctx->nv),
       rig(32 * (size_t)nb_old);
-  std::vector<int32_t> bprev(3 * (size_t)ctx->nf), blast(3 * (size_t)ctx->nf);
   if (nb_old > 0) {
     CHK(hipMemcpy(Xc.data(), ctx->X[cur], Xc.size() * 8, hipMemcpyDeviceToHost));
     CHK(hipMemcpy(Xp.data(), ctx->X[cur ^ 1], Xp.size() * 8, hipMemcpyDeviceToHost));
     CHK(hipMemcpy(Vl.data(), ctx->Vel, Vl.size() * 8, hipMemcpyDeviceToHost));
     CHK(hipMemcpy(rig.data(), ctx->b_rig, rig.size() * 8, hipMemcpyDeviceToHost));
-    // base[cur^1] was written by the last completed step (parity cur^1)
-    CHK(hipMemcpy(blast.data(), ctx->base[cur ^ 1], blast.size() * 4, hipMemcpyDeviceToHost));
-    CHK(hipMemcpy(bprev.data(), ctx->base[cur], bprev.size() * 4, hipMemcpyDeviceToHost));
   }
   // append the new body: x^n = x, x^{n-1} = x - v0 (soft), velocities v0
   std::vector<double> v0(3 * (size_t)bd->nv, 0.0);
@@ -827,13 +824,9 @@ extern "C" lbm_status lbm_add_body(lbm_ctx* ctx, const lbm_body_desc* bd, int32_
       Vl.push_back(v0[3 * v + a]);
     }
   rig.insert(rig.end(), rs, rs + 32);
-  for (int k = 0; k < 3 * bd->nf; k++) {
-    bprev.push_back(INT_MIN);
-    blast.push_back(INT_MIN);
-  }
   ctx->bodies.push_back(std::move(B));
   free_graphs(ctx);
-  st = build_body_arrays(ctx, cur, Xc, Xp, Vl, rig, bprev, blast);
+  st = build_body_arrays(ctx, cur, Xc, Xp, Vl, rig);
   if (st) return st;
   if (body_id) *body_id = (int32_t)ctx->bodies.size() - 1;
   return LBM_OK;
@@ -889,7 +882,9 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
   const bool ib = ctx->nf > 0;
   if (ib) {
     const BodyArgs& b = ctx->bargs[p];
-    if ((e = launch_ib_force(ctx->prec, a, b, ctx->fx[p], ctx->tf[p], counter(ctx, 0), s)) != hipSuccess) return e;
+    if ((e = launch_ib_force(ctx->prec, a, b, ctx->fx[p], ctx->tf[p], ctx->fx[p ^ 1], ctx->tf[p ^ 1],
+                             counter(ctx, 0), s)) != hipSuccess)
+      return e;
   }
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
   if (ctx->nrec > 0) {
@@ -903,8 +898,9 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
   if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
   if (ib) {
     const BodyArgs& b = ctx->bargs[p];
-    if ((e = launch_mls_post(ctx->prec, a, b, ctx->fx[p ^ 1], ctx->tf[p ^ 1], s)) != hipSuccess) return e;
-    if ((e = launch_body_post(b, ctx->flags, counter(ctx, 1), s)) != hipSuccess) return e;
+    if ((e = launch_mls_post(ctx->prec, a, b, s)) != hipSuccess) return e;
+    if ((e = launch_body_post(b, ctx->flags, s)) != hipSuccess) return e;
+    if ((e = launch_close(ctx->flags, s)) != hipSuccess) return e;
   } else {
     if ((e = launch_close(ctx->flags, s)) != hipSuccess) return e;
   }
@@ -1129,7 +1125,6 @@ extern "C" lbm_status lbm_save(lbm_ctx* ctx, const char* path) {
       e = dump(ctx->fx[p], fxb);
       if (e == hipSuccess) e = dump(ctx->tf[p], ctx->ntiles);
       if (e == hipSuccess) e = dump(ctx->X[p], 3 * sizeof(double) * ctx->nv);
-      if (e == hipSuccess) e = dump(ctx->base[p], 3 * sizeof(int32_t) * ctx->nf);
     }
     if (e == hipSuccess) e = dump(ctx->Vel, 3 * sizeof(double) * ctx->nv);
     if (e == hipSuccess) e = dump(ctx->b_rig, 32 * sizeof(double) * ctx->bodies.size());
@@ -1170,7 +1165,6 @@ extern "C" lbm_status lbm_load(lbm_ctx* ctx, const char* path) {
       e = load(ctx->fx[p], fxb);
       if (e == hipSuccess) e = load(ctx->tf[p], ctx->ntiles);
       if (e == hipSuccess) e = load(ctx->X[p], 3 * sizeof(double) * ctx->nv);
-      if (e == hipSuccess) e = load(ctx->base[p], 3 * sizeof(int32_t) * ctx->nf);
     }
     if (e == hipSuccess) e = load(ctx->Vel, 3 * sizeof(double) * ctx->nv);
     if (e == hipSuccess) e = load(ctx->b_rig, 32 * sizeof(double) * ctx->bodies.size());

@@ -21,6 +21,12 @@ constexpr double FX_INV = 1.0 / 144115188075855872.0;
 
 constexpr int TILE_SHIFT = 10;  // force-flag granularity: 1024 nodes
 
+// Forcing markers per block of the first IB launch (one per lane of its
+// first wave), and the most support nodes a block's bounding box may hold
+// in LDS (larger boxes take the direct path).
+constexpr int MARKERS_PER_BLOCK = 64;
+constexpr int BOX_CELLS = 729;
+
 // Vertex incidence table widths (largest vertex valence accepted: 10).
 constexpr int VT_E = 10, VT_H = 20, VT_F = 10, VT_SLOTS = VT_E + VT_H + VT_F;
 
@@ -90,12 +96,13 @@ struct BodyArgs {
   const int32_t* hinges;       // [nh][4]
   const double* theta0;        // [nh]
   const double* kb;            // [nh]
-  // vertex incidence, slot-major [VT_SLOTS][nv]: VT_E edge slots (+-(e+1),
-  // sign + when the vertex is the edge's first end), VT_H hinge slots
-  // (4 h + role + 1), VT_F face slots (f + 1); 0 = empty
-  const int32_t* vtab;
-  double* f_edge;              // [ne][3] stretching force on the edge's first vertex
-  double* f_hinge;             // [nh][4][3] bending force on the hinge's four vertices
+  // Forces on vertices by incidence slot, [VT_SLOTS][3][nv]: VT_E edge slots,
+  // VT_H hinge slots, VT_F face slots per vertex (unused slots hold 0); the
+  // element of slot-major index sl_*[...] writes there.
+  double* f_slot;
+  const int32_t* sl_edge;      // [ne][2] slot of the edge's force at its two ends
+  const int32_t* sl_hinge;     // [nh][4] slot of the hinge's force at its four vertices
+  const int32_t* sl_face;      // [nf][3] slot of a third of the face force at its vertices
   // per body tables
   const int32_t* b_face0; const int32_t* b_nf;
   const int32_t* b_vert0; const int32_t* b_nv;
@@ -113,8 +120,7 @@ struct BodyArgs {
   double* centroid;            // [nf][3]
   double* fext;                // [nf][3] hydrodynamic + repulsion force
   double* u0v;                 // [nv][3] interpolated velocity at vertices
-  int32_t* base_cur;           // [nf][3] stencil base written this step
-  const int32_t* base_prev;    // [nf][3] stencil base of the previous step
+  int n_clear_blocks;          // blocks clearing the previous step's force tiles
   double nu, umax;
 };
 
@@ -125,10 +131,10 @@ hipError_t launch_fluid_bulk(int prec, const FluidArgs& a, hipStream_t s);
 hipError_t launch_fluid_rec(int prec, const FluidArgs& a, hipStream_t s);
 hipError_t launch_close(DevFlags* flags, hipStream_t s);
 hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fx_cur,
-                           uint8_t* tf_cur, unsigned int* counter, hipStream_t s);
-hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, long long* fx_prev,
-                           uint8_t* tf_prev, hipStream_t s);
-hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter, hipStream_t s);
+                           uint8_t* tf_cur, long long* fx_prev, uint8_t* tf_prev,
+                           unsigned int* counter, hipStream_t s);
+hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s);
+hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s);
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,

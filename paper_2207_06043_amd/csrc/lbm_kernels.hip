@@ -298,8 +298,15 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
 // rho = rho_w and rho u = rho_w u_w, with rho_w = (1 + G0 + 2 Gout)/(1 - u_n)
 // on a velocity face and u_n = (rho_w - 1 - G0 - 2 Gout)/rho_w (tangential
 // u = 0) on a density face.
+struct Moments {
+  double drho, m[3];
+};
+
 template <class S>
-__device__ void streamed_moments(const FluidArgs& a, long long node, double& drho, double (&m)[3]) {
+__device__ __forceinline__ Moments streamed_moments(const FluidArgs& a, long long node) {
+  Moments out;
+  double& drho = out.drho;
+  double (&m)[3] = out.m;
   const Grid& G = a.g;
   int x, y, z;
   coords(G, node, x, y, z);
@@ -359,13 +366,14 @@ __device__ void streamed_moments(const FluidArgs& a, long long node, double& drh
       drho = rw - 1.0;
 #pragma unroll
       for (int k = 0; k < 3; k++) m[k] = rw * (k == ax ? sgn * un : ut[k]);
-      return;
+      return out;
     }
   }
   drho = dev_sum(g);
   m[0] = (g[1] - g[2]) + (g[7] + g[8]) + (g[9] + g[10]) - (g[11] + g[12]) - (g[13] + g[14]);
   m[1] = (g[3] - g[4]) + (g[7] - g[8]) + (g[11] - g[12]) + (g[15] + g[16]) - (g[17] + g[18]);
   m[2] = (g[5] - g[6]) + (g[9] - g[10]) + (g[13] - g[14]) + (g[15] - g[16]) + (g[17] - g[18]);
+  return out;
 }
 
 // Streamed populations at any non-solid node.
@@ -430,18 +438,6 @@ __device__ __forceinline__ bool last_block(unsigned int* counter, unsigned int n
   }
   __syncthreads();
   return is_last != 0;
-}
-
-// steps_done += 1 and the bits raised during the step become sticky.
-__device__ __forceinline__ void close_step(DevFlags* flags, unsigned int* counter) {
-  if (threadIdx.x == 0) {
-    const unsigned int pend =
-        __hip_atomic_load(&flags->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    flags->steps_done += 1;
-    flags->stop |= pend;
-    flags->pending = 0u;
-    *counter = 0u;
-  }
 }
 
 // ------------------------------------------------------------- k_fluid
@@ -972,14 +968,6 @@ __device__ unsigned int diag_finalize(const BodyArgs& b) {
 //  diag      volume, area, bounding box and stretch of x^n; the last block
 //            combines them and stops the computation before anything of
 //            this step is written when x^n is damaged or not finite.
-// Result of one lane of a marker: the fixed-point contribution to one node.
-struct Contrib {
-  long long node;
-  int cx, cy, cz;
-  long long q[3];
-  bool valid;
-};
-
 __device__ __forceinline__ long long fx_quant(double v, DevFlags* fl) {
   if (!(fabs(v) <= 1.0)) {
     // out of the fixed-point range: the step ends as unstable
@@ -990,116 +978,324 @@ __device__ __forceinline__ long long fx_quant(double v, DevFlags* fl) {
   return __double2ll_rn(v * FX_SCALE);
 }
 
-template <class S>
-__device__ void ib_marker(const FluidArgs& a, const BodyArgs& b, int m, int lane, Contrib& out) {
-  typedef typename Store<S>::C C;
-  const Grid& G = a.g;
-  double cen[3], nrm[3], area;
-  face_geom(b.Xcur, b.faces, m, cen, nrm, area);
-  const int body = b.face_body[m];
-  double Ub[3];
-  if (b.b_rigid[body]) {
-    const double* rs = b.b_rig + 32 * body;
-    const double r[3] = {cen[0] - rs[0], cen[1] - rs[1], cen[2] - rs[2]};
-    const double* w = rs + 9;
-    Ub[0] = rs[3] + (w[1] * r[2] - w[2] * r[1]);
-    Ub[1] = rs[4] + (w[2] * r[0] - w[0] * r[2]);
-    Ub[2] = rs[5] + (w[0] * r[1] - w[1] * r[0]);
-  } else {
-    const int v0 = b.faces[3 * m], v1 = b.faces[3 * m + 1], v2 = b.faces[3 * m + 2];
+// ---------------------------------------------- MLS, one point per lane
+// Support k (0..26) of a point with stencil base bs = floor(p + 1/2) is the
+// node bs + (k%3-1, (k/3)%3-1, k/9-1); it is used when it lies in the box
+// (periodic faces wrap) and is not solid.
+__device__ __forceinline__ bool support_node(const Grid& G, const uint8_t* ncls, int cx, int cy,
+                                             int cz, long long& node) {
+  int c[3] = {cx, cy, cz};
+  const int dim[3] = {G.nx, G.ny, G.nz};
 #pragma unroll
-    for (int k = 0; k < 3; k++) Ub[k] = (b.Vel[3 * v0 + k] + b.Vel[3 * v1 + k] + b.Vel[3 * v2 + k]) / 3.0;
+  for (int k = 0; k < 3; k++) {
+    if (c[k] < 0 || c[k] >= dim[k]) {
+      if (!G.per[k]) return false;
+      c[k] = ((c[k] % dim[k]) + dim[k]) % dim[k];
+    }
   }
-  if (lane == 0) {
-    b.centroid[3 * m] = cen[0];
-    b.centroid[3 * m + 1] = cen[1];
-    b.centroid[3 * m + 2] = cen[2];
-    b.base_cur[3 * m] = (int)floor(cen[0] + 0.5);
-    b.base_cur[3 * m + 1] = (int)floor(cen[1] + 0.5);
-    b.base_cur[3 * m + 2] = (int)floor(cen[2] + 0.5);
-  }
-  const Slot s = stencil_slot(G, a.ncls, cen[0], cen[1], cen[2], lane);
-  double us[3] = {0.0, 0.0, 0.0};
-  if (s.valid) {
-    double drho, mm[3];
-    streamed_moments<S>(a, s.node, drho, mm);
-    const double rho = 1.0 + drho;
-    us[0] = mm[0] / rho;
-    us[1] = mm[1] / rho;
-    us[2] = mm[2] / rho;
-  }
-  double psi[4];
-  if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
-  double U[3];
+  node = c[0] + (long long)G.px * (c[1] + (long long)G.ny * c[2]);
+  return ncls[node] != CLS_SOLID;
+}
+
+// W = exp(-(r/0.3)^2), r = |x_k - p| / 2.6 (Eqs. l2norm, intKernel).  On
+// the 3x3x3 stencil around floor(p + 1/2) every |x_k - p| <= 1.5 sqrt(3)
+// < 2.6, so r <= 1 always holds and W factors into one term per axis:
+// W = w(dx) w(dy) w(dz) with w(d) = exp(-d^2 / (2.6^2 0.09)); the nine
+// per-axis terms of a point are computed once.
+constexpr double MLS_K = 1.0 / (2.6 * 2.6 * 0.09);
+
+__device__ __forceinline__ void axis_weights(double p, int base, double (&w)[3]) {
 #pragma unroll
-  for (int k = 0; k < 3; k++) U[k] = red32(psi[0] * us[k]);
-  out.valid = s.valid && psi[0] != 0.0;
-  if (out.valid) {
-    const double cp = area * psi[0];
-    out.node = s.node;
-    out.cx = s.cx;
-    out.cy = s.cy;
-    out.cz = s.cz;
-#pragma unroll
-    for (int k = 0; k < 3; k++) out.q[k] = fx_quant(cp * (Ub[k] - U[k]), a.flags);
+  for (int i = 0; i < 3; i++) {
+    const double d = (double)(base + i - 1) - p;
+    w[i] = exp(-(d * d) * MLS_K);
   }
 }
 
-// Spread of the 8 markers of a block: the integer contributions are summed
-// per node in LDS over the block's bounding box of support nodes, then one
-// device atomic per node and component is issued (integer sums, so the
-// result does not depend on the order).  A box larger than SPREAD_CELLS
-// falls back to one device atomic per contribution.
-constexpr int SPREAD_CELLS = 512;
+// A += W p p^T with p = (1, dx, dy, dz); A packed a00 a01 a02 a03 a11 a12
+// a13 a22 a23 a33.
+__device__ __forceinline__ void mls_add(double (&A)[10], double W, double dx, double dy, double dz) {
+  const double wx = W * dx, wy = W * dy, wz = W * dz;
+  A[0] += W;
+  A[1] += wx;
+  A[2] += wy;
+  A[3] += wz;
+  A[4] += wx * dx;
+  A[5] += wx * dy;
+  A[6] += wx * dz;
+  A[7] += wy * dy;
+  A[8] += wy * dz;
+  A[9] += wz * dz;
+}
 
-__device__ void spread_block(const Grid& G, const Contrib& o, long long* fxc, uint8_t* tfc) {
-  __shared__ long long acc[3][SPREAD_CELLS];
-  __shared__ long long nid[SPREAD_CELLS];
-  __shared__ int box[6];
-  if (threadIdx.x < 6) box[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
-  __syncthreads();
-  if (o.valid) {
-    atomicMin(&box[0], o.cx);
-    atomicMin(&box[1], o.cy);
-    atomicMin(&box[2], o.cz);
-    atomicMax(&box[3], o.cx);
-    atomicMax(&box[4], o.cy);
-    atomicMax(&box[5], o.cz);
-  }
-  __syncthreads();
-  const int x0 = box[0], y0 = box[1], z0 = box[2];
-  const bool any = box[3] >= x0;
-  const int ex = box[3] - x0 + 1, ey = box[4] - y0 + 1, ez = box[5] - z0 + 1;
-  const bool fits = any && (long long)ex * ey * ez <= SPREAD_CELLS;
-  if (!fits) {
-    if (o.valid) {
+// b += W p f
+__device__ __forceinline__ void mls_rhs(double (&bf)[4], double W, double dx, double dy, double dz,
+                                        double f) {
+  const double wf = W * f;
+  bf[0] += wf;
+  bf[1] += wf * dx;
+  bf[2] += wf * dy;
+  bf[3] += wf * dz;
+}
+
+// Cholesky A = L L^T; singular (a pivot below 1e-10 of the largest
+// diagonal) returns false.  r holds 1/L_ii.
+struct Chol4 {
+  double L[4][4];
+  double r[4];
+};
+
+__device__ __forceinline__ bool chol4(const double (&A)[10], Chol4& c) {
+  const double M[4][4] = {{A[0], A[1], A[2], A[3]},
+                          {A[1], A[4], A[5], A[6]},
+                          {A[2], A[5], A[7], A[8]},
+                          {A[3], A[6], A[8], A[9]}};
+  const double dmax = fmax(fmax(A[0], A[4]), fmax(A[7], A[9]));
+  bool ok = dmax > 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; k++)
-        atomicAdd((unsigned long long*)(fxc + k * G.Np + o.node), (unsigned long long)o.q[k]);
-      tfc[o.node >> TILE_SHIFT] = 1;
+  for (int j = 0; j < 4; j++) {
+    double d = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; k++) d -= c.L[j][k] * c.L[j][k];
+    if (!(d > 1e-10 * dmax)) ok = false;
+    c.L[j][j] = ok ? sqrt(d) : 1.0;
+    c.r[j] = 1.0 / c.L[j][j];
+#pragma unroll
+    for (int i = j + 1; i < 4; i++) {
+      double v = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; k++) v -= c.L[i][k] * c.L[j][k];
+      c.L[i][j] = v * c.r[j];
     }
-    return;
   }
-  const int ncell = ex * ey * ez;
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-    acc[0][c] = acc[1][c] = acc[2][c] = 0;
-    nid[c] = -1;
-  }
-  __syncthreads();
-  if (o.valid) {
-    const int c = (o.cx - x0) + ex * ((o.cy - y0) + ey * (o.cz - z0));
+  return ok;
+}
+
+// x = A^{-1} b
+__device__ __forceinline__ void chol_solve(const Chol4& c, const double (&b)[4], double (&x)[4]) {
+  double y[4];
 #pragma unroll
-    for (int k = 0; k < 3; k++) atomicAdd((unsigned long long*)&acc[k][c], (unsigned long long)o.q[k]);
-    nid[c] = o.node;  // every lane that writes a cell writes the same node
+  for (int i = 0; i < 4; i++) {
+    double v = b[i];
+#pragma unroll
+    for (int k = 0; k < i; k++) v -= c.L[i][k] * y[k];
+    y[i] = v * c.r[i];
+  }
+#pragma unroll
+  for (int i = 3; i >= 0; i--) {
+    double v = y[i];
+#pragma unroll
+    for (int k = i + 1; k < 4; k++) v -= c.L[k][i] * x[k];
+    x[i] = v * c.r[i];
+  }
+}
+
+// ------------------------------------------------ forcing markers (S4)
+// A block takes MARKERS_PER_BLOCK consecutive faces (neighbouring faces of
+// the mesh), one per lane of its first wave:
+//  1. centroid, area and marker velocity U_b of each face;
+//  2. the block's bounding box of support nodes; all its threads compute
+//     u* = sum f e / rho of the streamed populations (no force) at every
+//     node of the box into LDS;
+//  3. per marker: A = sum W p p^T and sum W p u* over the 27 supports, one
+//     Cholesky, U = e0 . A^{-1} sum W p u*, F_l = U_b - U (Eqs. uLag and
+//     the direct-forcing equation);
+//  4. spreading (Eq. bodyforce): c_l phi_k F_l with c_l = face area and
+//     phi_k = W_k p_k . A^{-1} e0, in fixed point, summed per node in LDS,
+//     then one device atomic per node and component (integer sums: the
+//     result does not depend on the order).
+// A box larger than BOX_CELLS takes the direct path: u* per support from
+// global memory and one device atomic per contribution.
+template <class S>
+__device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, long long* fxc,
+                             uint8_t* tfc) {
+  __shared__ double s_u[3][BOX_CELLS];
+  __shared__ long long s_acc[3][BOX_CELLS];
+  __shared__ long long s_node[BOX_CELLS];
+  __shared__ int s_box[6];
+  const Grid& G = a.g;
+  const int t = threadIdx.x;
+  const int m = blk * MARKERS_PER_BLOCK + t;
+  const bool mk = t < MARKERS_PER_BLOCK && m < b.nf;
+  if (t < 6) s_box[t] = t < 3 ? INT_MAX : INT_MIN;
+  __syncthreads();
+  double cen[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0}, area = 0.0;
+  int bs[3] = {0, 0, 0};
+  if (mk) {
+    double nrm[3];
+    face_geom(b.Xcur, b.faces, m, cen, nrm, area);
+    const int body = b.face_body[m];
+    if (b.b_rigid[body]) {
+      const double* rs = b.b_rig + 32 * body;
+      const double r[3] = {cen[0] - rs[0], cen[1] - rs[1], cen[2] - rs[2]};
+      const double* w = rs + 9;
+      Ub[0] = rs[3] + (w[1] * r[2] - w[2] * r[1]);
+      Ub[1] = rs[4] + (w[2] * r[0] - w[0] * r[2]);
+      Ub[2] = rs[5] + (w[0] * r[1] - w[1] * r[0]);
+    } else {
+      const int v0 = b.faces[3 * m], v1 = b.faces[3 * m + 1], v2 = b.faces[3 * m + 2];
+#pragma unroll
+      for (int k = 0; k < 3; k++) Ub[k] = (b.Vel[3 * v0 + k] + b.Vel[3 * v1 + k] + b.Vel[3 * v2 + k]) / 3.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      b.centroid[3 * m + k] = cen[k];
+      bs[k] = (int)floor(cen[k] + 0.5);
+    }
+    atomicMin(&s_box[0], bs[0]);
+    atomicMin(&s_box[1], bs[1]);
+    atomicMin(&s_box[2], bs[2]);
+    atomicMax(&s_box[3], bs[0]);
+    atomicMax(&s_box[4], bs[1]);
+    atomicMax(&s_box[5], bs[2]);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-    const long long node = nid[c];
+  const int x0 = s_box[0] - 1, y0 = s_box[1] - 1, z0 = s_box[2] - 1;
+  const int ex = s_box[3] - s_box[0] + 3, ey = s_box[4] - s_box[1] + 3, ez = s_box[5] - s_box[2] + 3;
+  const bool fits = s_box[3] >= s_box[0] && (long long)ex * ey * ez <= BOX_CELLS;
+  const int ncell = fits ? ex * ey * ez : 0;
+  for (int c = t; c < ncell; c += blockDim.x) {
+    long long node = -1;
+    double u3[3] = {0.0, 0.0, 0.0};
+    if (support_node(G, a.ncls, x0 + c % ex, y0 + (c / ex) % ey, z0 + c / (ex * ey), node)) {
+      const Moments mo = streamed_moments<S>(a, node);
+      const double rho = 1.0 + mo.drho;
+#pragma unroll
+      for (int k = 0; k < 3; k++) u3[k] = mo.m[k] / rho;
+    } else {
+      node = -1;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      s_u[k][c] = u3[k];
+      s_acc[k][c] = 0;
+    }
+    s_node[c] = node;
+  }
+  __syncthreads();
+  if (mk) {
+    double A[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, bu[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    double wx[3], wy[3], wz[3];
+    axis_weights(cen[0], bs[0], wx);
+    axis_weights(cen[1], bs[1], wy);
+    axis_weights(cen[2], bs[2], wz);
+    if (fits) {
+#pragma unroll
+      for (int k = 0; k < 27; k++) {
+        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
+        const int c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
+        const double W = s_node[c] >= 0 ? wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] : 0.0;
+        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+        mls_add(A, W, dx, dy, dz);
+#pragma unroll
+        for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, s_u[q][c]);
+      }
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < 27; k++) {
+        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
+        long long node;
+        double u3[3] = {0.0, 0.0, 0.0};
+        const bool ok = support_node(G, a.ncls, cx, cy, cz, node);
+        if (ok) {
+          const Moments mo = streamed_moments<S>(a, node);
+#pragma unroll
+          for (int q = 0; q < 3; q++) u3[q] = mo.m[q] / (1.0 + mo.drho);
+        }
+        const double W = ok ? wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] : 0.0;
+        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+        mls_add(A, W, dx, dy, dz);
+#pragma unroll
+        for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, u3[q]);
+      }
+    }
+    Chol4 ch;
+    double cc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (chol4(A, ch)) {
+      const double e0[4] = {1.0, 0.0, 0.0, 0.0};
+      chol_solve(ch, e0, cc);
+    } else {
+      atomicAdd(&a.flags->mls_singular, 1);
+    }
+    double F[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      F[q] = Ub[q] - (cc[0] * bu[q][0] + cc[1] * bu[q][1] + cc[2] * bu[q][2] + cc[3] * bu[q][3]);
+    if (fits) {
+#pragma unroll
+      for (int k = 0; k < 27; k++) {
+        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
+        const int c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
+        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+        const double phi = wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
+        if (s_node[c] >= 0 && phi != 0.0) {
+          const double cp = area * phi;
+#pragma unroll
+          for (int q = 0; q < 3; q++)
+            atomicAdd((unsigned long long*)&s_acc[q][c], (unsigned long long)fx_quant(cp * F[q], a.flags));
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < 27; k++) {
+        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
+        long long node;
+        if (!support_node(G, a.ncls, cx, cy, cz, node)) continue;
+        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+        const double phi = wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
+        if (phi == 0.0) continue;
+        const double cp = area * phi;
+#pragma unroll
+        for (int q = 0; q < 3; q++)
+          atomicAdd((unsigned long long*)(fxc + q * G.Np + node), (unsigned long long)fx_quant(cp * F[q], a.flags));
+        tfc[node >> TILE_SHIFT] = 1;
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = t; c < ncell; c += blockDim.x) {
+    const long long node = s_node[c];
     if (node < 0) continue;
+    bool any = false;
 #pragma unroll
-    for (int k = 0; k < 3; k++)
-      if (acc[k][c] != 0) atomicAdd((unsigned long long*)(fxc + k * G.Np + node), (unsigned long long)acc[k][c]);
-    tfc[node >> TILE_SHIFT] = 1;
+    for (int q = 0; q < 3; q++) {
+      const long long v = s_acc[q][c];
+      if (v != 0) {
+        atomicAdd((unsigned long long*)(fxc + q * G.Np + node), (unsigned long long)v);
+        any = true;
+      }
+    }
+    if (any) tfc[node >> TILE_SHIFT] = 1;
+  }
+}
+
+// Zeroes the spread force of the previous step in the tiles it flagged, and
+// the flags.  That buffer is not read again once this step has started, and
+// the next step adds into it.  Block cb of ncb reads the flags of its tiles
+// cb, cb + ncb, ... all at once (one per thread), lists the set ones in LDS,
+// then clears them one after the other with all its threads.
+__device__ void clear_tiles(const Grid& G, long long* fxp, uint8_t* tfp, int cb, int ncb) {
+  __shared__ int s_n;
+  __shared__ int s_list[256];
+  const long long ntiles = (G.Np >> TILE_SHIFT) + 1;
+  for (long long first = cb; first < ntiles; first += (long long)ncb * blockDim.x) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const long long tl = first + (long long)threadIdx.x * ncb;
+    if (tl < ntiles && tfp[tl]) s_list[atomicAdd(&s_n, 1)] = (int)tl;
+    __syncthreads();
+    const int n = s_n;
+    for (int i = 0; i < n; i++) {
+      const long long n0 = (long long)s_list[i] << TILE_SHIFT;
+      const long long n1 = n0 + (1LL << TILE_SHIFT) < G.Np ? n0 + (1LL << TILE_SHIFT) : G.Np;
+      for (long long q = n0 + threadIdx.x; q < n1; q += blockDim.x) {
+        fxp[q] = 0;
+        fxp[G.Np + q] = 0;
+        fxp[2 * G.Np + q] = 0;
+      }
+    }
+    if ((int)threadIdx.x < n) tfp[s_list[threadIdx.x]] = 0;
+    __syncthreads();
   }
 }
 
@@ -1113,8 +1309,12 @@ __device__ void membrane_element(const BodyArgs& b, int idx) {
                          b.Xcur[3 * va + 2] - b.Xcur[3 * vb + 2]};
     const double l = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
     const double c = -b.kl[e] * (l - b.l0[e]) / l;
+    const int sa = b.sl_edge[2 * e], sb = b.sl_edge[2 * e + 1];
 #pragma unroll
-    for (int k = 0; k < 3; k++) b.f_edge[3 * e + k] = c * r[k];
+    for (int k = 0; k < 3; k++) {
+      b.f_slot[((long long)sa * 3 + k) * b.nv + va] = c * r[k];
+      b.f_slot[((long long)sb * 3 + k) * b.nv + vb] = -(c * r[k]);
+    }
   } else if (idx < b.ne + b.nh) {
     const int h = idx - b.ne;
     const int32_t* H = b.hinges + 4 * h;
@@ -1123,27 +1323,29 @@ __device__ void membrane_element(const BodyArgs& b, int idx) {
     hinge_all(b.Xcur, H, th, gr);
     const double amp = -b.kb[h] * sin(th - b.theta0[h]);
 #pragma unroll
-    for (int r = 0; r < 4; r++)
+    for (int r = 0; r < 4; r++) {
+      const long long sl = b.sl_hinge[4 * h + r];
 #pragma unroll
-      for (int k = 0; k < 3; k++) b.f_hinge[12 * h + 3 * r + k] = amp * gr[r][k];
+      for (int k = 0; k < 3; k++) b.f_slot[(sl * 3 + k) * b.nv + H[r]] = amp * gr[r][k];
+    }
   }
 }
 
 template <class S>
 __global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long long* fxc,
-                                                  uint8_t* tfc, unsigned int* counter) {
+                                                  uint8_t* tfc, long long* fxp, uint8_t* tfp,
+                                                  unsigned int* counter) {
   if (a.flags->stop) return;
   const int blk = blockIdx.x;
-  if (blk < b.n_marker_blocks) {
-    const int m = blk * 8 + (threadIdx.x >> 5);
-    Contrib o;
-    o.valid = false;
-    if (m < b.nf) ib_marker<S>(a, b, m, threadIdx.x & 31, o);
-    spread_block(a.g, o, fxc, tfc);
-  } else if (blk < b.n_marker_blocks + b.n_elem_blocks) {
-    membrane_element(b, (blk - b.n_marker_blocks) * 256 + threadIdx.x);
+  const int nmk = b.n_marker_blocks, nel = b.n_elem_blocks, ncl = b.n_clear_blocks;
+  if (blk < nmk) {
+    marker_block<S>(a, b, blk, fxc, tfc);
+  } else if (blk < nmk + nel) {
+    membrane_element(b, (blk - nmk) * 256 + threadIdx.x);
+  } else if (blk < nmk + nel + ncl) {
+    clear_tiles(a.g, fxp, tfp, blk - nmk - nel, ncl);
   } else {
-    diag_block(b, b.Xcur, blk - b.n_marker_blocks - b.n_elem_blocks);
+    diag_block(b, b.Xcur, blk - nmk - nel - ncl);
     // the diagnostics blocks count themselves; the last one combines them
     if (last_block(counter, b.n_diag_blocks)) {
       const unsigned int raised = diag_finalize(b);
@@ -1170,89 +1372,138 @@ __global__ __launch_bounds__(256) void k_check(BodyArgs b, const double* X0, con
 }
 
 // ---------------------------------------------------------- k_mls_post
-// Faces (one wave each; lanes 0-31 the outer probe, 32-63 the inner one):
-// pressure p = rho/3 and viscous stress rho nu (grad u + grad u^T) from MLS
-// fits 1.2 dx along +-n (Eqs. hydroForP, hydroForNu), the repulsion of
-// centroids of other bodies closer than dx (Eq. collision) and, for soft
-// bodies, the volume penalty k_v (1 - V/V0) A n (Eq. volFor, outward n).
-// The same waves clear the previous step's spread buffer at the previous
-// stencils.  Soft vertices (two per wave): MLS velocity u_v,0 at x_v^n.
+// One MLS point per lane, supports read from this step's rho - 1 and u.
+// Face waves (32 faces each): lanes 0-31 take the probe 1.2 dx outside
+// their face, lanes 32-63 the probe inside the same face; each fits rho
+// (value) and u (gradient) by moving least squares (the linear-fit
+// coefficients), then the outer lane forms the traction: pressure p = rho/3
+// and viscous stress rho nu (grad u + grad u^T) (Eqs. hydroForP,
+// hydroForNu), the repulsion of centroids of other bodies closer than dx
+// (Eq. collision) and, for soft bodies, the volume penalty
+// k_v (1 - V/V0) A n (Eq. volFor, outward n).  A singular fit gives 0.
+// Vertex waves (64 soft vertices each): the MLS velocity u_v,0 at x_v^n.
 template <class S>
-__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b, long long* fxp,
-                                                  uint8_t* tfp) {
-  if (a.flags->stop) return;
-  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
-  const int l64 = threadIdx.x & 63, half = l64 >> 5, lane = l64 & 31;
+__device__ __forceinline__ void fit_point(const FluidArgs& a, double px, double py, double pz,
+                                          bool want_grad, double& rfit, double (&val)[3],
+                                          double (&grad)[3][3]) {
+  typedef typename Store<S>::C C;
+  typedef C C4 __attribute__((ext_vector_type(4)));
   const Grid& G = a.g;
-  const S* f = (const S*)a.B;
-  if (wave < b.nf) {
-    const int m = wave;
-    const int pbx = b.base_prev[3 * m];
-    if (half == 0 && pbx != INT_MIN && lane < 27) {
-      int c[3] = {pbx + lane % 3 - 1, b.base_prev[3 * m + 1] + (lane / 3) % 3 - 1,
-                  b.base_prev[3 * m + 2] + lane / 9 - 1};
-      const int dim[3] = {G.nx, G.ny, G.nz};
-      bool ok = true;
-      for (int k = 0; k < 3; k++) {
-        if (c[k] < 0 || c[k] >= dim[k]) {
-          if (G.per[k]) c[k] = ((c[k] % dim[k]) + dim[k]) % dim[k];
-          else ok = false;
-        }
+  const int bx = (int)floor(px + 0.5), by = (int)floor(py + 0.5), bz = (int)floor(pz + 0.5);
+  // all 27 support loads go out together (out-of-box supports read node 0
+  // and are not used; solid nodes hold zeros and get W = 0)
+  bool inb[27];
+  C4 mv[27];
+  uint8_t cls[27];
+#pragma unroll
+  for (int k = 0; k < 27; k++) {
+    long long node = 0;
+    int c[3] = {bx + k % 3 - 1, by + (k / 3) % 3 - 1, bz + k / 9 - 1};
+    const int dim[3] = {G.nx, G.ny, G.nz};
+    bool in = true;
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      if (c[q] < 0 || c[q] >= dim[q]) {
+        if (G.per[q]) c[q] = ((c[q] % dim[q]) + dim[q]) % dim[q];
+        else in = false;
       }
-      if (ok) {
-        const long long node = c[0] + (long long)G.px * (c[1] + (long long)G.ny * c[2]);
-        fxp[node] = 0;
-        fxp[G.Np + node] = 0;
-        fxp[2 * G.Np + node] = 0;
-        tfp[node >> TILE_SHIFT] = 0;
-      }
-    }
+    if (in) node = c[0] + (long long)G.px * (c[1] + (long long)G.ny * c[2]);
+    inb[k] = in;
+    cls[k] = a.ncls[node];
+    mv[k] = ((const C4*)a.mac)[node];
+  }
+  double wx[3], wy[3], wz[3];
+  axis_weights(px, bx, wx);
+  axis_weights(py, by, wy);
+  axis_weights(pz, bz, wz);
+  double A[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, br[4] = {0, 0, 0, 0};
+  double bu[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+  for (int k = 0; k < 27; k++) {
+    const double dx = (bx + k % 3 - 1) - px, dy = (by + (k / 3) % 3 - 1) - py, dz = (bz + k / 9 - 1) - pz;
+    const bool use = inb[k] && cls[k] != CLS_SOLID;
+    const double W = use ? wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] : 0.0;
+    const double dr = use ? (double)mv[k].x : 0.0;
+    const double u3[3] = {use ? (double)mv[k].y : 0.0, use ? (double)mv[k].z : 0.0, use ? (double)mv[k].w : 0.0};
+    mls_add(A, W, dx, dy, dz);
+    mls_rhs(br, W, dx, dy, dz, dr);
+#pragma unroll
+    for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, u3[q]);
+  }
+  Chol4 ch;
+  const bool ok = chol4(A, ch);
+  if (!ok) atomicAdd(&a.flags->mls_singular, 1);
+  double cc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (ok) {
+    const double e0[4] = {1.0, 0.0, 0.0, 0.0};
+    chol_solve(ch, e0, cc);
+  }
+  // the weights add up to 1, so the fit of rho is 1 + the fit of rho - 1
+  rfit = ok ? 1.0 + (cc[0] * br[0] + cc[1] * br[1] + cc[2] * br[2] + cc[3] * br[3]) : 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    val[q] = cc[0] * bu[q][0] + cc[1] * bu[q][1] + cc[2] * bu[q][2] + cc[3] * bu[q][3];
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    if (ok && want_grad) chol_solve(ch, bu[q], x);
+#pragma unroll
+    for (int c = 0; c < 3; c++) grad[q][c] = x[1 + c];
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
+  if (a.flags->stop) return;
+  const int gw = (blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int l = threadIdx.x & 63;
+  const int nfw = (b.nf + 31) / 32;
+  if (gw < nfw) {
+    const int f = gw * 32 + (l & 31);
+    const bool valid = f < b.nf;
+    const int fv = valid ? f : b.nf - 1;  // spare lanes repeat a face and write nothing
     double cen[3], nrm[3], area;
-    face_geom(b.Xcur, b.faces, m, cen, nrm, area);
-    const double sg = half == 0 ? 1.2 : -1.2;
-    const Slot s = stencil_slot(G, a.ncls, cen[0] + sg * nrm[0], cen[1] + sg * nrm[1],
-                                cen[2] + sg * nrm[2], lane);
-    double drho = 0.0, u[3] = {0.0, 0.0, 0.0};
-    if (s.valid) load_mac<S>(a, s.node, drho, u[0], u[1], u[2]);
-    double psi[4];
-    if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
-    // the weights add up to 1, so the fit of rho is 1 + the fit of rho - 1
-    const double rfit = 1.0 + red32(psi[0] * drho);
-    double Gm[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-      for (int c = 0; c < 3; c++) Gm[i][c] = red32(psi[1 + c] * u[i]);
-    // outer minus inner, on lane 0
-    const double r_in = __shfl(rfit, 32, 64);
+    face_geom(b.Xcur, b.faces, fv, cen, nrm, area);
+    const double sg = l < 32 ? 1.2 : -1.2;
+    double rfit, val[3], G[3][3];
+    fit_point<S>(a, cen[0] + sg * nrm[0], cen[1] + sg * nrm[1], cen[2] + sg * nrm[2], true, rfit,
+                 val, G);
+    // the inner probe of this lane's face
+    const double r_in = __shfl(rfit, l + 32, 64);
     double Gin[3][3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
-      for (int c = 0; c < 3; c++) Gin[i][c] = __shfl(Gm[i][c], 32, 64);
-    const int body = b.face_body[m];
+      for (int c = 0; c < 3; c++) Gin[i][c] = __shfl(G[i][c], l + 32, 64);
+    const int body = b.face_body[fv];
     double acc = 0.0;
     if (b.nbody > 1) {
-      const double* bb = b.b_diag + 16 * body + 2;
-      for (int o = 0; o < b.nbody; o++) {
-        if (o == body) continue;
-        const double* ob = b.b_diag + 16 * o + 2;
-        bool far = false;
+      // repulsion: for each face of the wave in turn, all lanes scan the
+      // centroids of the other bodies whose bounding boxes come within dx
+      for (int q = 0; q < 32; q++) {
+        const double qx = __shfl(cen[0], q, 64), qy = __shfl(cen[1], q, 64), qz = __shfl(cen[2], q, 64);
+        const int qb = __shfl(body, q, 64);
+        const double* bb = b.b_diag + 16 * qb + 2;
+        double part = 0.0;
+        for (int o = 0; o < b.nbody; o++) {
+          if (o == qb) continue;
+          const double* ob = b.b_diag + 16 * o + 2;
+          bool far = false;
 #pragma unroll
-        for (int k = 0; k < 3; k++)
-          if (bb[k] > ob[3 + k] + 1.0 || ob[k] > bb[3 + k] + 1.0) far = true;
-        if (far) continue;
-        const int f0 = b.b_face0[o], nf = b.b_nf[o];
-        for (int g2 = l64; g2 < nf; g2 += 64) {
-          const double* cj = b.centroid + 3 * (f0 + g2);
-          const double dx = cen[0] - cj[0], dy = cen[1] - cj[1], dz = cen[2] - cj[2];
-          const double d = sqrt(dx * dx + dy * dy + dz * dz);
-          if (d < 1.0 && d > 0.0) acc += 1.0 / sqrt(d * d * d * d * d);
+          for (int k = 0; k < 3; k++)
+            if (bb[k] > ob[3 + k] + 1.0 || ob[k] > bb[3 + k] + 1.0) far = true;
+          if (far) continue;
+          const int f0 = b.b_face0[o], nfo = b.b_nf[o];
+          for (int g2 = l; g2 < nfo; g2 += 64) {
+            const double* cj = b.centroid + 3 * (f0 + g2);
+            const double ddx = qx - cj[0], ddy = qy - cj[1], ddz = qz - cj[2];
+            const double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            if (d < 1.0 && d > 0.0) part += 1.0 / sqrt(d * d * d * d * d);
+          }
         }
+        part = red64(part);
+        if (l == q) acc = part;
       }
-      acc = red64(acc);
     }
-    if (l64 == 0) {
+    if (l < 32 && valid) {
       const double nu = b.nu;
       const double dp = (rfit - r_in) / 3.0;
       double F[3];
@@ -1261,7 +1512,7 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b, long 
         double tn = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-          const double tp = rfit * nu * (Gm[i][c] + Gm[c][i]);
+          const double tp = rfit * nu * (G[i][c] + G[c][i]);
           const double tm = r_in * nu * (Gin[i][c] + Gin[c][i]);
           tn += (tp - tm) * nrm[c];
         }
@@ -1273,24 +1524,30 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b, long 
         const double V0 = b.b_param[8 * body], kv = b.b_param[8 * body + 2];
         cv = kv * (1.0 - b.b_diag[16 * body] / V0) * area;
       }
+      double Ft[3];
 #pragma unroll
-      for (int i = 0; i < 3; i++) b.fext[3 * m + i] = F[i] - pref * acc * nrm[i] + cv * nrm[i];
+      for (int i = 0; i < 3; i++) {
+        Ft[i] = F[i] - pref * acc * nrm[i] + cv * nrm[i];
+        b.fext[3 * f + i] = Ft[i];
+      }
+      // a third of the face force at each of its vertices
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        const long long sl = b.sl_face[3 * f + r];
+        const int vr = b.faces[3 * f + r];
+#pragma unroll
+        for (int i = 0; i < 3; i++) b.f_slot[(sl * 3 + i) * b.nv + vr] = Ft[i] / 3.0;
+      }
     }
     return;
   }
-  const int idx = (wave - b.nf) * 2 + half;
-  if (idx >= b.nsoft_v) return;
-  const int v = b.soft_vlist[idx];
-  const double X = b.Xcur[3 * v], Y = b.Xcur[3 * v + 1], Z = b.Xcur[3 * v + 2];
-  const Slot s = stencil_slot(G, a.ncls, X, Y, Z, lane);
-  double drho = 0.0, u[3] = {0.0, 0.0, 0.0};
-  if (s.valid) load_mac<S>(a, s.node, drho, u[0], u[1], u[2]);
-  double psi[4];
-  if (!mls_psi(s, psi) && lane == 0) atomicAdd(&a.flags->mls_singular, 1);
-  double U[3];
-#pragma unroll
-  for (int k = 0; k < 3; k++) U[k] = red32(psi[0] * u[k]);
-  if (lane == 0) {
+  if (b.nsoft_v == 0) return;
+  const int idx = (gw - nfw) * 64 + l;
+  const bool valid = idx < b.nsoft_v;
+  const int v = b.soft_vlist[valid ? idx : b.nsoft_v - 1];
+  double rfit, U[3], G[3][3];
+  fit_point<S>(a, b.Xcur[3 * v], b.Xcur[3 * v + 1], b.Xcur[3 * v + 2], false, rfit, U, G);
+  if (valid) {
     b.u0v[3 * v] = U[0];
     b.u0v[3 * v + 1] = U[1];
     b.u0v[3 * v + 2] = U[2];
@@ -1425,31 +1682,19 @@ __device__ void soft_vertex(const BodyArgs& b, int idx) {
   const int body = b.vert_body[v];
   const double* x = b.Xcur;
   const double xv[3] = {x[3 * v], x[3 * v + 1], x[3 * v + 2]};
+  // sum of the element forces written into this vertex's slots (stretching,
+  // bending, a third of each incident face's force), in slot order; the
+  // slot-major layout makes every load coalesced across the wave
   double F[3] = {0.0, 0.0, 0.0};
-  int32_t t[VT_SLOTS];
-#pragma unroll
-  for (int k = 0; k < VT_SLOTS; k++) t[k] = b.vtab[(long long)k * b.nv + v];
-  // Branch-free gather: every slot loads from a valid address (entry 0 for
-  // an empty slot) and adds its value only when the slot is used, so all
-  // the loads go out together instead of one slot at a time.
   double val[VT_SLOTS][3];
 #pragma unroll
-  for (int k = 0; k < VT_SLOTS; k++) {
-    const int a = t[k] > 0 ? t[k] - 1 : (t[k] < 0 ? -t[k] - 1 : 0);
-    const double* src = k < VT_E ? b.f_edge : (k < VT_E + VT_H ? b.f_hinge : b.fext);
+  for (int k = 0; k < VT_SLOTS; k++)
 #pragma unroll
-    for (int c = 0; c < 3; c++) val[k][c] = src[3 * a + c];
-  }
+    for (int c = 0; c < 3; c++) val[k][c] = b.f_slot[((long long)k * 3 + c) * b.nv + v];
 #pragma unroll
-  for (int k = 0; k < VT_SLOTS; k++) {
-    const bool used = t[k] != 0;
+  for (int k = 0; k < VT_SLOTS; k++)
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      double x = k < VT_E ? (t[k] > 0 ? val[k][c] : -val[k][c])
-                          : (k < VT_E + VT_H ? val[k][c] : val[k][c] / 3.0);
-      F[c] += used ? x : 0.0;
-    }
-  }
+    for (int c = 0; c < 3; c++) F[c] += val[k][c];
   const double mv = b.b_param[8 * body + 3];
   for (int k = 0; k < 3; k++) {
     const double acc = 0.5 * F[k] / mv;
@@ -1460,11 +1705,9 @@ __device__ void soft_vertex(const BodyArgs& b, int idx) {
   }
 }
 
-// Last launch of a coupled step: rigid blocks, then soft-vertex blocks (one
-// vertex per thread, 64-thread blocks); the last block to finish closes the
-// step.
-__global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags,
-                                                   unsigned int* counter) {
+// Last IB launch of a coupled step: rigid blocks, then soft-vertex blocks
+// (one vertex per thread, 64-thread blocks); k_close follows.
+__global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags) {
   if (flags->stop) return;
   const int blk = blockIdx.x;
   if (blk < b.nbody) {
@@ -1473,7 +1716,6 @@ __global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags,
     const int idx = (blk - b.nbody) * (int)blockDim.x + threadIdx.x;
     if (idx < b.nsoft_v) soft_vertex(b, idx);
   }
-  if (last_block(counter, gridDim.x)) close_step(flags, counter);
 }
 
 // ------------------------------------------------------------ API kernels
@@ -1654,35 +1896,35 @@ hipError_t launch_close(DevFlags* flags, hipStream_t s) {
 }
 
 hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fxc,
-                           uint8_t* tfc, unsigned int* counter, hipStream_t s) {
-  const unsigned grid = (unsigned)(b.n_marker_blocks + b.n_elem_blocks + b.n_diag_blocks);
+                           uint8_t* tfc, long long* fxp, uint8_t* tfp, unsigned int* counter,
+                           hipStream_t s) {
+  const unsigned grid =
+      (unsigned)(b.n_marker_blocks + b.n_elem_blocks + b.n_clear_blocks + b.n_diag_blocks);
   if (grid == 0) return hipSuccess;
   switch (prec) {
-    case 0: k_ib_force<double><<<grid, 256, 0, s>>>(a, b, fxc, tfc, counter); break;
-    case 1: k_ib_force<float><<<grid, 256, 0, s>>>(a, b, fxc, tfc, counter); break;
-    default: k_ib_force<_Float16><<<grid, 256, 0, s>>>(a, b, fxc, tfc, counter); break;
+    case 0: k_ib_force<double><<<grid, 256, 0, s>>>(a, b, fxc, tfc, fxp, tfp, counter); break;
+    case 1: k_ib_force<float><<<grid, 256, 0, s>>>(a, b, fxc, tfc, fxp, tfp, counter); break;
+    default: k_ib_force<_Float16><<<grid, 256, 0, s>>>(a, b, fxc, tfc, fxp, tfp, counter); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, long long* fxp,
-                           uint8_t* tfp, hipStream_t s) {
-  const long long waves = (long long)b.nf + (b.nsoft_v + 1) / 2;
-  if (waves == 0) return hipSuccess;
+hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s) {
+  const long long waves = (long long)(b.nf + 31) / 32 + (b.nsoft_v + 63) / 64;
+  if (b.nf == 0) return hipSuccess;
   const unsigned grid = cdiv(waves * 64, 256);
   switch (prec) {
-    case 0: k_mls_post<double><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
-    case 1: k_mls_post<float><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
-    default: k_mls_post<_Float16><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
+    case 0: k_mls_post<double><<<grid, 256, 0, s>>>(a, b); break;
+    case 1: k_mls_post<float><<<grid, 256, 0, s>>>(a, b); break;
+    default: k_mls_post<_Float16><<<grid, 256, 0, s>>>(a, b); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter,
-                            hipStream_t s) {
+hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s) {
   // small blocks: the vertex gathers are spread over many CUs' load pipelines
   const unsigned grid = (unsigned)b.nbody + cdiv(b.nsoft_v, 64);
-  k_body_post<<<grid, 64, 0, s>>>(b, flags, counter);
+  k_body_post<<<grid, 64, 0, s>>>(b, flags);
   return hipGetLastError();
 }
 
