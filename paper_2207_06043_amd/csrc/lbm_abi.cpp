@@ -65,7 +65,8 @@ struct lbm_ctx {
   int32_t* rec_link0 = nullptr;
   uint8_t* rec_face = nullptr;
   double* rec_bc = nullptr;
-  double* lk_c = nullptr;
+  void* lk_c = nullptr;        // [5][nlinks] in the compute type
+  uint32_t* rec_mb = nullptr;  // [4][nrec] bounce-back inputs each linked direction needs
   int nlinks_rec = 0;
   int32_t* tile_list = nullptr;
   int nbulk_blocks = 0;
@@ -368,11 +369,32 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   CHK(upload(&ctx->rec_face, r_face));
   CHK(upload(&ctx->rec_bc, bcT));
   const size_t nl = l_c.size() / 5;
-  std::vector<double> lcT(l_c.size());
+  // at least one entry: the kernels read entry 0 for directions without a link
+  std::vector<double> lcT(std::max<size_t>(l_c.size(), 5), 0.0);
   for (size_t k = 0; k < nl; k++)
     for (int c = 0; c < 5; c++) lcT[c * nl + k] = l_c[5 * k + c];
   ctx->nlinks_rec = (int)nl;
-  CHK(upload(&ctx->lk_c, lcT));
+  if (ctx->prec == 0) {
+    CHK(upload((double**)&ctx->lk_c, lcT));
+  } else {
+    std::vector<float> lcf(lcT.begin(), lcT.end());
+    CHK(upload((float**)&ctx->lk_c, lcf));
+  }
+  // per record and linked direction j (bit j): which of the terms
+  // c1 f_i(x-e_i), c2 f_i(x-2e_i), c4 f_j(x-e_i), c3 f_j(x) are present
+  std::vector<uint32_t> mb(4 * (size_t)ctx->nrec, 0u);
+  for (int r = 0; r < ctx->nrec; r++) {
+    int lk = r_link0[r];
+    for (int j = 1; j < 19; j++) {
+      if (!((r_mask[r] >> j) & 1u)) continue;
+      const double* c = &l_c[5 * (size_t)lk++];
+      if (c[1] != 0.0) mb[r] |= 1u << j;
+      if (c[2] != 0.0) mb[(size_t)ctx->nrec + r] |= 1u << j;
+      if (c[4] != 0.0) mb[2 * (size_t)ctx->nrec + r] |= 1u << j;
+      if (c[3] != 0.0) mb[3 * (size_t)ctx->nrec + r] |= 1u << j;
+    }
+  }
+  CHK(upload(&ctx->rec_mb, mb));
   CHK(upload(&ctx->tile_list, tiles));
   CHK(hipMalloc(&ctx->flags, sizeof(DevFlags) + 64));
   CHK(hipMemset(ctx->flags, 0, sizeof(DevFlags) + 64));
@@ -400,7 +422,7 @@ extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
   free_graphs(ctx);
   free_bodies(ctx);
   void* ptrs[] = {ctx->f_alloc[0], ctx->f_alloc[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
-                  ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_c,
+                  ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_c, ctx->rec_mb,
                   ctx->tile_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
                   ctx->api_flags, ctx->mac, ctx->flags};
   for (void* p : ptrs)
@@ -847,6 +869,7 @@ static FluidArgs fluid_args(lbm_ctx* ctx, int p) {
   a.rec_face = ctx->rec_face;
   a.rec_bc = ctx->rec_bc;
   a.lk_c = ctx->lk_c;
+  a.rec_mb = ctx->rec_mb;
   a.nlinks = ctx->nlinks_rec;
   a.tile_list = ctx->tile_list;
   a.nbulk_blocks = ctx->nbulk_blocks;

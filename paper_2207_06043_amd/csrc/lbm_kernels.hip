@@ -239,12 +239,24 @@ __device__ void zouhe(C (&g)[19], int face, int kind, C bx, C by, C bz, C brho) 
 // Zou-He for the populations entering through an open face.  Addresses are
 // formed with periodic wrap, so they lie in the box even where a coefficient
 // is zero: all loads are issued in one batch, then the arithmetic follows.
+// Streamed populations of a boundary record: plain pulls (periodic wrap),
+// interpolated bounce-back on wall links (Eq. bbouzidi) as
+// c0 f*_i(x) + c1 f*_i(x - e_i) + c2 f*_i(x - 2e_i) + c3 f*_j(x) + c4 f*_j(x - e_i)
+// with coefficients fixed on the host from q and the fluid neighbours, and
+// Zou-He for the populations entering through an open face.  Addresses are
+// formed with periodic wrap, so they lie in the box even where a coefficient
+// is zero; all loads are issued in one batch, then the arithmetic follows.
+// A neighbour term whose coefficient is zero (record masks) reads the
+// node's own value instead, which is loaded anyway: no extra traffic.
 template <class S>
 __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19]) {
   typedef typename Store<S>::C C;
   const Grid& G = a.g;
+  const C* lc = (const C*)a.lk_c;
+  const long long nl = a.nlinks;
   const long long node = a.rec_node[r];
   const uint32_t mask = a.rec_mask[r];
+  const uint32_t m1 = a.rec_mb[r], m2 = a.rec_mb[a.nrec + r], m4 = a.rec_mb[2 * a.nrec + r];
   const int lk0 = a.rec_link0[r];
   const int fc = a.rec_face[r];
   int x, y, z;
@@ -264,13 +276,13 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
     if ((mask >> j) & 1u) {
       const int i = OPP[j];
 #pragma unroll
-      for (int c = 0; c < 5; c++) cf[j][c] = (C)a.lk_c[(long long)c * a.nlinks + lk];
+      for (int c = 0; c < 5; c++) cf[j][c] = lc[c * nl + lk];
       ++lk;
       const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
       const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
-      b1[j] = ldA<S>(a, i, n1);
-      b2[j] = ldA<S>(a, i, n2);
-      b3[j] = ldA<S>(a, j, n1);
+      b1[j] = ldA<S>(a, i, ((m1 >> j) & 1u) ? n1 : node);
+      b2[j] = ldA<S>(a, i, ((m2 >> j) & 1u) ? n2 : node);
+      b3[j] = ldA<S>(a, ((m4 >> j) & 1u) ? j : i, ((m4 >> j) & 1u) ? n1 : node);
     }
   }
   g[0] = self[0];
@@ -289,15 +301,6 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
   }
 }
 
-// Moments of the streamed populations at any non-solid node (what the
-// forcing step interpolates), in double: drho = sum g, m = sum g e.  A
-// boundary record accumulates them direction by direction (plain pull,
-// interpolated bounce-back, or nothing for a population from outside an
-// open face) without holding all of its populations; on an open face the
-// Zou-He rule fixes the completed node's moments in closed form:
-// rho = rho_w and rho u = rho_w u_w, with rho_w = (1 + G0 + 2 Gout)/(1 - u_n)
-// on a velocity face and u_n = (rho_w - 1 - G0 - 2 Gout)/rho_w (tangential
-// u = 0) on a density face.
 struct Moments {
   double drho, m[3];
 };
@@ -317,6 +320,9 @@ __device__ __forceinline__ Moments streamed_moments(const FluidArgs& a, long lon
   } else {
     const int r = a.rec_of[node];
     const uint32_t mask = a.rec_mask[r];
+    typedef typename Store<S>::C C;
+    const C* lc = (const C*)a.lk_c;
+    const long long nl = a.nlinks;
     const int fc = a.rec_face[r];
     const int face = fc & 7, ax = face >> 1, sgn = (face & 1) ? -1 : 1;
     int lk = a.rec_link0[r];
@@ -331,7 +337,7 @@ __device__ __forceinline__ Moments streamed_moments(const FluidArgs& a, long lon
         const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
         double c[5];
 #pragma unroll
-        for (int k = 0; k < 5; k++) c[k] = a.lk_c[(long long)k * a.nlinks + lk];
+        for (int k = 0; k < 5; k++) c[k] = (double)lc[k * nl + lk];
         ++lk;
         v = c[0] * (double)ldA<S>(a, i, node) + c[1] * (double)ldA<S>(a, i, n1) +
             c[2] * (double)ldA<S>(a, i, n2) + c[3] * (double)ldA<S>(a, j, node) +
@@ -573,7 +579,7 @@ __global__ __launch_bounds__(256) void k_fluid_bulk(FluidArgs a) {
 template <class S>
 __global__ __launch_bounds__(256) void k_fluid_rec(FluidArgs a) {
   if (a.flags->stop) return;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (r < a.nrec) fluid_record_thread<S>(a, r);
 }
 
@@ -1092,20 +1098,31 @@ __device__ __forceinline__ void chol_solve(const Chol4& c, const double (&b)[4],
 
 // ------------------------------------------------ forcing markers (S4)
 // A block takes MARKERS_PER_BLOCK consecutive faces (neighbouring faces of
-// the mesh), one per lane of its first wave:
-//  1. centroid, area and marker velocity U_b of each face;
+// the mesh); four lanes (a quad) serve each marker:
+//  1. centroid, area and marker velocity U_b of the face;
 //  2. the block's bounding box of support nodes; all its threads compute
 //     u* = sum f e / rho of the streamed populations (no force) at every
 //     node of the box into LDS;
-//  3. per marker: A = sum W p p^T and sum W p u* over the 27 supports, one
-//     Cholesky, U = e0 . A^{-1} sum W p u*, F_l = U_b - U (Eqs. uLag and
-//     the direct-forcing equation);
+//  3. per marker: A = sum W p p^T and sum W p u* over the 27 supports, split
+//     over the quad (lane q takes supports q, q+4, ...) and combined by a
+//     fixed xor tree, one Cholesky, U = e0 . A^{-1} sum W p u*,
+//     F_l = U_b - U (Eqs. uLag and the direct-forcing equation);
 //  4. spreading (Eq. bodyforce): c_l phi_k F_l with c_l = face area and
 //     phi_k = W_k p_k . A^{-1} e0, in fixed point, summed per node in LDS,
 //     then one device atomic per node and component (integer sums: the
 //     result does not depend on the order).
 // A box larger than BOX_CELLS takes the direct path: u* per support from
 // global memory and one device atomic per contribution.
+__device__ __forceinline__ double sel3(int i, const double (&w)[3]) {
+  return i == 0 ? w[0] : (i == 1 ? w[1] : w[2]);
+}
+
+__device__ __forceinline__ double quad_sum(double v) {
+  v += __shfl_xor(v, 1, 4);
+  v += __shfl_xor(v, 2, 4);
+  return v;
+}
+
 template <class S>
 __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, long long* fxc,
                              uint8_t* tfc) {
@@ -1114,9 +1131,9 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
   __shared__ long long s_node[BOX_CELLS];
   __shared__ int s_box[6];
   const Grid& G = a.g;
-  const int t = threadIdx.x;
-  const int m = blk * MARKERS_PER_BLOCK + t;
-  const bool mk = t < MARKERS_PER_BLOCK && m < b.nf;
+  const int t = threadIdx.x, sub = t & 3;
+  const int m = blk * MARKERS_PER_BLOCK + (t >> 2);
+  const bool mk = (t >> 2) < MARKERS_PER_BLOCK && m < b.nf;
   if (t < 6) s_box[t] = t < 3 ? INT_MAX : INT_MIN;
   __syncthreads();
   double cen[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0}, area = 0.0;
@@ -1138,16 +1155,17 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
       for (int k = 0; k < 3; k++) Ub[k] = (b.Vel[3 * v0 + k] + b.Vel[3 * v1 + k] + b.Vel[3 * v2 + k]) / 3.0;
     }
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-      b.centroid[3 * m + k] = cen[k];
-      bs[k] = (int)floor(cen[k] + 0.5);
+    for (int k = 0; k < 3; k++) bs[k] = (int)floor(cen[k] + 0.5);
+    if (sub == 0) {
+#pragma unroll
+      for (int k = 0; k < 3; k++) b.centroid[3 * m + k] = cen[k];
+      atomicMin(&s_box[0], bs[0]);
+      atomicMin(&s_box[1], bs[1]);
+      atomicMin(&s_box[2], bs[2]);
+      atomicMax(&s_box[3], bs[0]);
+      atomicMax(&s_box[4], bs[1]);
+      atomicMax(&s_box[5], bs[2]);
     }
-    atomicMin(&s_box[0], bs[0]);
-    atomicMin(&s_box[1], bs[1]);
-    atomicMin(&s_box[2], bs[2]);
-    atomicMax(&s_box[3], bs[0]);
-    atomicMax(&s_box[4], bs[1]);
-    atomicMax(&s_box[5], bs[2]);
   }
   __syncthreads();
   const int x0 = s_box[0] - 1, y0 = s_box[1] - 1, z0 = s_box[2] - 1;
@@ -1173,82 +1191,93 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
     s_node[c] = node;
   }
   __syncthreads();
-  if (mk) {
-    double A[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, bu[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    double wx[3], wy[3], wz[3];
-    axis_weights(cen[0], bs[0], wx);
-    axis_weights(cen[1], bs[1], wy);
-    axis_weights(cen[2], bs[2], wz);
-    if (fits) {
+  // a quad always holds one marker (or none), so the quad sums below see
+  // four lanes that agree on mk
+  double wx[3], wy[3], wz[3];
+  axis_weights(cen[0], bs[0], wx);
+  axis_weights(cen[1], bs[1], wy);
+  axis_weights(cen[2], bs[2], wz);
+  double A[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, bu[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  if (mk && fits) {
 #pragma unroll
-      for (int k = 0; k < 27; k++) {
-        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
-        const int c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
-        const double W = s_node[c] >= 0 ? wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] : 0.0;
-        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
-        mls_add(A, W, dx, dy, dz);
+    for (int i = 0; i < 7; i++) {
+      const int k = sub + 4 * i;
+      if (k >= 27) break;
+      const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+      const int cx = bs[0] + kx - 1, cy = bs[1] + ky - 1, cz = bs[2] + kz - 1;
+      const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+      const int c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
+      const double W = s_node[c] >= 0 ? sel3(kx, wx) * sel3(ky, wy) * sel3(kz, wz) : 0.0;
+      mls_add(A, W, dx, dy, dz);
 #pragma unroll
-        for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, s_u[q][c]);
-      }
-    } else {
-#pragma unroll 1
-      for (int k = 0; k < 27; k++) {
-        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
-        long long node;
-        double u3[3] = {0.0, 0.0, 0.0};
-        const bool ok = support_node(G, a.ncls, cx, cy, cz, node);
-        if (ok) {
-          const Moments mo = streamed_moments<S>(a, node);
-#pragma unroll
-          for (int q = 0; q < 3; q++) u3[q] = mo.m[q] / (1.0 + mo.drho);
-        }
-        const double W = ok ? wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] : 0.0;
-        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
-        mls_add(A, W, dx, dy, dz);
-#pragma unroll
-        for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, u3[q]);
-      }
+      for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, s_u[q][c]);
     }
+  } else if (mk) {
+#pragma unroll 1
+    for (int k = sub; k < 27; k += 4) {
+      const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+      const int cx = bs[0] + kx - 1, cy = bs[1] + ky - 1, cz = bs[2] + kz - 1;
+      const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+      long long node;
+      double u3[3] = {0.0, 0.0, 0.0};
+      const bool ok = support_node(G, a.ncls, cx, cy, cz, node);
+      if (ok) {
+        const Moments mo = streamed_moments<S>(a, node);
+#pragma unroll
+        for (int q = 0; q < 3; q++) u3[q] = mo.m[q] / (1.0 + mo.drho);
+      }
+      const double W = ok ? sel3(kx, wx) * sel3(ky, wy) * sel3(kz, wz) : 0.0;
+      mls_add(A, W, dx, dy, dz);
+#pragma unroll
+      for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, u3[q]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 10; k++) A[k] = quad_sum(A[k]);
+#pragma unroll
+  for (int q = 0; q < 3; q++)
+#pragma unroll
+    for (int k = 0; k < 4; k++) bu[q][k] = quad_sum(bu[q][k]);
+  if (mk) {
     Chol4 ch;
     double cc[4] = {0.0, 0.0, 0.0, 0.0};
     if (chol4(A, ch)) {
       const double e0[4] = {1.0, 0.0, 0.0, 0.0};
       chol_solve(ch, e0, cc);
-    } else {
+    } else if (sub == 0) {
       atomicAdd(&a.flags->mls_singular, 1);
     }
     double F[3];
 #pragma unroll
     for (int q = 0; q < 3; q++)
       F[q] = Ub[q] - (cc[0] * bu[q][0] + cc[1] * bu[q][1] + cc[2] * bu[q][2] + cc[3] * bu[q][3]);
-    if (fits) {
 #pragma unroll
-      for (int k = 0; k < 27; k++) {
-        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
-        const int c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
-        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
-        const double phi = wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
-        if (s_node[c] >= 0 && phi != 0.0) {
-          const double cp = area * phi;
-#pragma unroll
-          for (int q = 0; q < 3; q++)
-            atomicAdd((unsigned long long*)&s_acc[q][c], (unsigned long long)fx_quant(cp * F[q], a.flags));
-        }
+    for (int i = 0; i < 7; i++) {
+      const int k = sub + 4 * i;
+      if (k >= 27) break;
+      const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+      const int cx = bs[0] + kx - 1, cy = bs[1] + ky - 1, cz = bs[2] + kz - 1;
+      const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+      long long node;
+      int c = 0;
+      bool ok;
+      if (fits) {
+        c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
+        node = s_node[c];
+        ok = node >= 0;
+      } else {
+        ok = support_node(G, a.ncls, cx, cy, cz, node);
       }
-    } else {
-#pragma unroll 1
-      for (int k = 0; k < 27; k++) {
-        const int cx = bs[0] + k % 3 - 1, cy = bs[1] + (k / 3) % 3 - 1, cz = bs[2] + k / 9 - 1;
-        long long node;
-        if (!support_node(G, a.ncls, cx, cy, cz, node)) continue;
-        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
-        const double phi = wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
-        if (phi == 0.0) continue;
+      const double phi = sel3(kx, wx) * sel3(ky, wy) * sel3(kz, wz) * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
+      if (ok && phi != 0.0) {
         const double cp = area * phi;
 #pragma unroll
-        for (int q = 0; q < 3; q++)
-          atomicAdd((unsigned long long*)(fxc + q * G.Np + node), (unsigned long long)fx_quant(cp * F[q], a.flags));
-        tfc[node >> TILE_SHIFT] = 1;
+        for (int q = 0; q < 3; q++) {
+          const long long v = fx_quant(cp * F[q], a.flags);
+          if (fits) atomicAdd((unsigned long long*)&s_acc[q][c], (unsigned long long)v);
+          else atomicAdd((unsigned long long*)(fxc + q * G.Np + node), (unsigned long long)v);
+        }
+        if (!fits) tfc[node >> TILE_SHIFT] = 1;
       }
     }
   }
