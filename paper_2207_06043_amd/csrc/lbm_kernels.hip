@@ -1412,24 +1412,26 @@ __global__ __launch_bounds__(256) void k_check(BodyArgs b, const double* X0, con
 // k_v (1 - V/V0) A n (Eq. volFor, outward n).  A singular fit gives 0.
 // Vertex waves (64 soft vertices each): the MLS velocity u_v,0 at x_v^n.
 template <class S>
-__device__ __forceinline__ void fit_point(const FluidArgs& a, double px, double py, double pz,
+__device__ __forceinline__ void fit_point(const FluidArgs& a, int sub, double px, double py, double pz,
                                           bool want_grad, double& rfit, double (&val)[3],
                                           double (&grad)[3][3]) {
   typedef typename Store<S>::C C;
   typedef C C4 __attribute__((ext_vector_type(4)));
   const Grid& G = a.g;
   const int bx = (int)floor(px + 0.5), by = (int)floor(py + 0.5), bz = (int)floor(pz + 0.5);
-  // all 27 support loads go out together (out-of-box supports read node 0
-  // and are not used; solid nodes hold zeros and get W = 0)
-  bool inb[27];
-  C4 mv[27];
-  uint8_t cls[27];
+  // this lane's supports k = sub, sub + 4, ... : loads first, all together
+  // (out-of-box supports read node 0 and are not used; solid nodes hold
+  // zeros and get W = 0)
+  bool use[7];
+  C4 mv[7];
+  uint8_t cls[7];
 #pragma unroll
-  for (int k = 0; k < 27; k++) {
+  for (int i = 0; i < 7; i++) {
+    const int k = sub + 4 * i;
     long long node = 0;
     int c[3] = {bx + k % 3 - 1, by + (k / 3) % 3 - 1, bz + k / 9 - 1};
     const int dim[3] = {G.nx, G.ny, G.nz};
-    bool in = true;
+    bool in = k < 27;
 #pragma unroll
     for (int q = 0; q < 3; q++)
       if (c[q] < 0 || c[q] >= dim[q]) {
@@ -1437,9 +1439,9 @@ __device__ __forceinline__ void fit_point(const FluidArgs& a, double px, double 
         else in = false;
       }
     if (in) node = c[0] + (long long)G.px * (c[1] + (long long)G.ny * c[2]);
-    inb[k] = in;
-    cls[k] = a.ncls[node];
-    mv[k] = ((const C4*)a.mac)[node];
+    use[i] = in;
+    cls[i] = a.ncls[node];
+    mv[i] = ((const C4*)a.mac)[node];
   }
   double wx[3], wy[3], wz[3];
   axis_weights(px, bx, wx);
@@ -1448,20 +1450,31 @@ __device__ __forceinline__ void fit_point(const FluidArgs& a, double px, double 
   double A[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, br[4] = {0, 0, 0, 0};
   double bu[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-  for (int k = 0; k < 27; k++) {
-    const double dx = (bx + k % 3 - 1) - px, dy = (by + (k / 3) % 3 - 1) - py, dz = (bz + k / 9 - 1) - pz;
-    const bool use = inb[k] && cls[k] != CLS_SOLID;
-    const double W = use ? wx[k % 3] * wy[(k / 3) % 3] * wz[k / 9] : 0.0;
-    const double dr = use ? (double)mv[k].x : 0.0;
-    const double u3[3] = {use ? (double)mv[k].y : 0.0, use ? (double)mv[k].z : 0.0, use ? (double)mv[k].w : 0.0};
+  for (int i = 0; i < 7; i++) {
+    const int k = sub + 4 * i;
+    const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+    const double dx = (bx + kx - 1) - px, dy = (by + ky - 1) - py, dz = (bz + kz - 1) - pz;
+    const bool u = use[i] && cls[i] != CLS_SOLID;
+    const double W = u ? sel3(kx, wx) * sel3(ky, wy) * sel3(kz, wz) : 0.0;
+    const double dr = u ? (double)mv[i].x : 0.0;
+    const double u3[3] = {u ? (double)mv[i].y : 0.0, u ? (double)mv[i].z : 0.0, u ? (double)mv[i].w : 0.0};
     mls_add(A, W, dx, dy, dz);
     mls_rhs(br, W, dx, dy, dz, dr);
 #pragma unroll
     for (int q = 0; q < 3; q++) mls_rhs(bu[q], W, dx, dy, dz, u3[q]);
   }
+  // the quad's four partial sums, in a fixed order
+#pragma unroll
+  for (int k = 0; k < 10; k++) A[k] = quad_sum(A[k]);
+#pragma unroll
+  for (int k = 0; k < 4; k++) br[k] = quad_sum(br[k]);
+#pragma unroll
+  for (int q = 0; q < 3; q++)
+#pragma unroll
+    for (int k = 0; k < 4; k++) bu[q][k] = quad_sum(bu[q][k]);
   Chol4 ch;
   const bool ok = chol4(A, ch);
-  if (!ok) atomicAdd(&a.flags->mls_singular, 1);
+  if (!ok && sub == 0) atomicAdd(&a.flags->mls_singular, 1);
   double cc[4] = {0.0, 0.0, 0.0, 0.0};
   if (ok) {
     const double e0[4] = {1.0, 0.0, 0.0, 0.0};
@@ -1479,21 +1492,26 @@ __device__ __forceinline__ void fit_point(const FluidArgs& a, double px, double 
   }
 }
 
+// Face waves take 8 faces: the quad of lanes 4f..4f+3 (f < 8) fits the probe
+// outside face f, lanes 32 + 4f.. the probe inside; vertex waves take 16
+// soft vertices, one quad each.
+constexpr int MLS_FACES_PER_WAVE = 8, MLS_VERTS_PER_WAVE = 16;
+
 template <class S>
 __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
   if (a.flags->stop) return;
   const int gw = (blockIdx.x * 256 + threadIdx.x) >> 6;
-  const int l = threadIdx.x & 63;
-  const int nfw = (b.nf + 31) / 32;
+  const int l = threadIdx.x & 63, sub = l & 3;
+  const int nfw = (b.nf + MLS_FACES_PER_WAVE - 1) / MLS_FACES_PER_WAVE;
   if (gw < nfw) {
-    const int f = gw * 32 + (l & 31);
+    const int f = gw * MLS_FACES_PER_WAVE + ((l & 31) >> 2);
     const bool valid = f < b.nf;
     const int fv = valid ? f : b.nf - 1;  // spare lanes repeat a face and write nothing
     double cen[3], nrm[3], area;
     face_geom(b.Xcur, b.faces, fv, cen, nrm, area);
     const double sg = l < 32 ? 1.2 : -1.2;
     double rfit, val[3], G[3][3];
-    fit_point<S>(a, cen[0] + sg * nrm[0], cen[1] + sg * nrm[1], cen[2] + sg * nrm[2], true, rfit,
+    fit_point<S>(a, sub, cen[0] + sg * nrm[0], cen[1] + sg * nrm[1], cen[2] + sg * nrm[2], true, rfit,
                  val, G);
     // the inner probe of this lane's face
     const double r_in = __shfl(rfit, l + 32, 64);
@@ -1507,9 +1525,9 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
     if (b.nbody > 1) {
       // repulsion: for each face of the wave in turn, all lanes scan the
       // centroids of the other bodies whose bounding boxes come within dx
-      for (int q = 0; q < 32; q++) {
-        const double qx = __shfl(cen[0], q, 64), qy = __shfl(cen[1], q, 64), qz = __shfl(cen[2], q, 64);
-        const int qb = __shfl(body, q, 64);
+      for (int q = 0; q < MLS_FACES_PER_WAVE; q++) {
+        const double qx = __shfl(cen[0], 4 * q, 64), qy = __shfl(cen[1], 4 * q, 64), qz = __shfl(cen[2], 4 * q, 64);
+        const int qb = __shfl(body, 4 * q, 64);
         const double* bb = b.b_diag + 16 * qb + 2;
         double part = 0.0;
         for (int o = 0; o < b.nbody; o++) {
@@ -1529,10 +1547,10 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
           }
         }
         part = red64(part);
-        if (l == q) acc = part;
+        if ((l >> 2) == q) acc = part;
       }
     }
-    if (l < 32 && valid) {
+    if (l < 32 && sub == 0 && valid) {
       const double nu = b.nu;
       const double dp = (rfit - r_in) / 3.0;
       double F[3];
@@ -1571,12 +1589,12 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
     return;
   }
   if (b.nsoft_v == 0) return;
-  const int idx = (gw - nfw) * 64 + l;
+  const int idx = (gw - nfw) * MLS_VERTS_PER_WAVE + (l >> 2);
   const bool valid = idx < b.nsoft_v;
   const int v = b.soft_vlist[valid ? idx : b.nsoft_v - 1];
   double rfit, U[3], G[3][3];
-  fit_point<S>(a, b.Xcur[3 * v], b.Xcur[3 * v + 1], b.Xcur[3 * v + 2], false, rfit, U, G);
-  if (valid) {
+  fit_point<S>(a, sub, b.Xcur[3 * v], b.Xcur[3 * v + 1], b.Xcur[3 * v + 2], false, rfit, U, G);
+  if (valid && sub == 0) {
     b.u0v[3 * v] = U[0];
     b.u0v[3 * v + 1] = U[1];
     b.u0v[3 * v + 2] = U[2];
@@ -1939,8 +1957,9 @@ hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long
 }
 
 hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s) {
-  const long long waves = (long long)(b.nf + 31) / 32 + (b.nsoft_v + 63) / 64;
   if (b.nf == 0) return hipSuccess;
+  const long long waves = (long long)(b.nf + MLS_FACES_PER_WAVE - 1) / MLS_FACES_PER_WAVE +
+                          (b.nsoft_v + MLS_VERTS_PER_WAVE - 1) / MLS_VERTS_PER_WAVE;
   const unsigned grid = cdiv(waves * 64, 256);
   switch (prec) {
     case 0: k_mls_post<double><<<grid, 256, 0, s>>>(a, b); break;
