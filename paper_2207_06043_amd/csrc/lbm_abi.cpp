@@ -91,6 +91,7 @@ struct lbm_ctx {
   int rec_block = 64;
   int bulk_v = 4;
   int bulk_block = 256;
+  bool fluid_merged = false;  // records and bulk tiles in one launch (small grids)
   bool graph_valid = false;
   hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   int64_t enq = 0;
@@ -165,9 +166,14 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   const bool large = (long long)d->nx * d->ny * d->nz >= (4LL << 20);
   ctx->bulk_v = large ? (d->precision == 0 ? 2 : (d->precision == 1 ? 4 : 8)) : (d->precision == 2 ? 2 : 1);
   ctx->bulk_block = large ? 256 : 64;
+  // small grids: one fluid launch (no fork/join between streams) with the
+  // record blocks in the same 64-thread shape as the bulk tiles
+  ctx->fluid_merged = !large;
   if (const char* ev = getenv("LBM_RECORD_BLOCK")) ctx->rec_block = atoi(ev);
   if (const char* ev = getenv("LBM_BULK_V")) ctx->bulk_v = atoi(ev);
   if (const char* ev = getenv("LBM_BULK_BLOCK")) ctx->bulk_block = atoi(ev);
+  if (const char* ev = getenv("LBM_FLUID_SPLIT")) ctx->fluid_merged = atoi(ev) == 0;
+  if (ctx->fluid_merged) ctx->rec_block = ctx->bulk_block;
   {
     const int pv = d->precision;
     const bool vok = (pv == 0 && (ctx->bulk_v == 1 || ctx->bulk_v == 2)) ||
@@ -910,14 +916,19 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
       return e;
   }
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-  if (ctx->nrec > 0) {
-    if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0)) != hipSuccess) return e;
-    if ((e = launch_fluid_rec(ctx->prec, a, ctx->side)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ctx->ev_join, ctx->side)) != hipSuccess) return e;
+  if (ctx->fluid_merged) {
+    if ((e = launch_fluid_all(ctx->prec, a, s)) != hipSuccess) return e;
+  } else {
+    // large grids: records on the side stream, bulk tiles on this one
+    if (ctx->nrec > 0) {
+      if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0)) != hipSuccess) return e;
+      if ((e = launch_fluid_rec(ctx->prec, a, ctx->side)) != hipSuccess) return e;
+      if ((e = hipEventRecord(ctx->ev_join, ctx->side)) != hipSuccess) return e;
+    }
+    if ((e = launch_fluid_bulk(ctx->prec, a, s)) != hipSuccess) return e;
+    if (ctx->nrec > 0 && (e = hipStreamWaitEvent(s, ctx->ev_join, 0)) != hipSuccess) return e;
   }
-  if ((e = launch_fluid_bulk(ctx->prec, a, s)) != hipSuccess) return e;
-  if (ctx->nrec > 0 && (e = hipStreamWaitEvent(s, ctx->ev_join, 0)) != hipSuccess) return e;
   if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
   if (ib) {
     const BodyArgs& b = ctx->bargs[p];

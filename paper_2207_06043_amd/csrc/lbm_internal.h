@@ -130,6 +130,7 @@ hipError_t launch_init(int prec, const Grid& g, void* f, const uint8_t* ncls, co
                        const double* u, hipStream_t s);
 hipError_t launch_fluid_bulk(int prec, const FluidArgs& a, hipStream_t s);
 hipError_t launch_fluid_rec(int prec, const FluidArgs& a, hipStream_t s);
+hipError_t launch_fluid_all(int prec, const FluidArgs& a, hipStream_t s);
 hipError_t launch_close(DevFlags* flags, hipStream_t s);
 hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fx_cur,
                            uint8_t* tf_cur, long long* fx_prev, uint8_t* tf_prev,

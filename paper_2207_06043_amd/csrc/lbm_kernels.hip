@@ -583,6 +583,22 @@ __global__ __launch_bounds__(256) void k_fluid_rec(FluidArgs a) {
   if (r < a.nrec) fluid_record_thread<S>(a, r);
 }
 
+// Small (cache-resident, latency-bound) grids: records and bulk tiles in one
+// launch, the record blocks first (they take longest), so that a step has
+// no fork and join between two streams.  Both parts use blocks of the same
+// size.
+template <class S, int V, bool PERX>
+__global__ __launch_bounds__(256) void k_fluid_all(FluidArgs a, int nrb) {
+  if (a.flags->stop) return;
+  const int b = blockIdx.x;
+  if (b < nrb) {
+    const int r = xcd_remap(b, nrb) * blockDim.x + threadIdx.x;
+    if (r < a.nrec) fluid_record_thread<S>(a, r);
+  } else {
+    fluid_bulk<S, V, PERX>(a, xcd_remap(b - nrb, a.nbulk_blocks));
+  }
+}
+
 // Closes a fluid-only step (one thread).
 __global__ void k_close(DevFlags* flags) {
   if (flags->stop) return;
@@ -1933,6 +1949,25 @@ hipError_t launch_fluid_rec(int prec, const FluidArgs& a, hipStream_t s) {
     case 0: k_fluid_rec<double><<<grid, blk, 0, s>>>(a); break;
     case 1: k_fluid_rec<float><<<grid, blk, 0, s>>>(a); break;
     default: k_fluid_rec<_Float16><<<grid, blk, 0, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+template <class S, int V>
+static void all_launch(const FluidArgs& a, int nrb, unsigned grid, hipStream_t s) {
+  if (a.g.per[0]) k_fluid_all<S, V, true><<<grid, a.bulk_block, 0, s>>>(a, nrb);
+  else k_fluid_all<S, V, false><<<grid, a.bulk_block, 0, s>>>(a, nrb);
+}
+
+hipError_t launch_fluid_all(int prec, const FluidArgs& a, hipStream_t s) {
+  const int nrb = a.nrec > 0 ? (int)cdiv(a.nrec, a.bulk_block) : 0;
+  const unsigned grid = (unsigned)(nrb + a.nbulk_blocks);
+  if (grid == 0) return hipSuccess;
+  switch (prec * 16 + a.bulk_v) {
+    case 0 * 16 + 1: all_launch<double, 1>(a, nrb, grid, s); break;
+    case 1 * 16 + 1: all_launch<float, 1>(a, nrb, grid, s); break;
+    case 2 * 16 + 2: all_launch<_Float16, 2>(a, nrb, grid, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
