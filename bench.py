@@ -29,7 +29,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fluid_kernel_traffic.json")
 # sources that decide what the fluid kernels read and write (code and launch shapes)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_06043_amd", "csrc", n)
                for n in ("lbm_kernels.hip", "lbm_abi.cpp", "lbm_internal.h")]
-FLUID_KERNELS = ("k_fluid_bulk", "k_fluid_rec")
+FLUID_KERNELS = ("k_fluid_all", "k_fluid_bulk", "k_fluid_rec")
 
 
 def kernel_hash():
@@ -249,7 +249,10 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_fluid (fused pull-stream + BCs + forced BGK collide)",
+            "kernel": ("k_fluid_all (fused pull-stream + bounce-back + Zou-He + forced BGK collide, "
+                       "boundary records and bulk tiles in one launch)" if info["fluid_launch"] == 1 else
+                       "k_fluid_bulk || k_fluid_rec (fused pull-stream + BCs + forced BGK collide, "
+                       "bulk tiles and boundary records on two streams)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -124,6 +124,9 @@ typedef struct {
   int64_t bytes_per_step_alg;   /* 2 * 19 * sizeof(stored population) * n_fluid */
   int32_t precision;
   int32_t mls_singular;         /* markers whose moment matrix was singular */
+  int32_t fluid_launch;         /* 1: one fused fluid kernel per step (small grids);
+                                   2: bulk and boundary-record kernels on two streams */
+  int32_t pad;
 } lbm_info_t;
 
 /* Create a context on the current HIP device; work is enqueued on

@@ -57,7 +57,7 @@ class LbmInfo(C.Structure):
                 ("n_general", C.c_int64), ("n_links", C.c_int64), ("n_bodies", C.c_int64),
                 ("n_vertices", C.c_int64), ("n_faces", C.c_int64), ("steps_done", C.c_int64),
                 ("bytes_per_step_alg", C.c_int64), ("precision", C.c_int32),
-                ("mls_singular", C.c_int32)]
+                ("mls_singular", C.c_int32), ("fluid_launch", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None

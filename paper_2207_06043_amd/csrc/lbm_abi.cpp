@@ -65,8 +65,8 @@ struct lbm_ctx {
   int32_t* rec_link0 = nullptr;
   uint8_t* rec_face = nullptr;
   double* rec_bc = nullptr;
-  void* lk_c = nullptr;        // [5][nlinks] in the compute type
-  uint32_t* rec_mb = nullptr;  // [4][nrec] bounce-back inputs each linked direction needs
+  void* lk_c = nullptr;        // [3][nlinks] in the compute type
+  uint32_t* rec_mb = nullptr;  // [nrec] bit j: link j has q >= 1/2
   int nlinks_rec = 0;
   int32_t* tile_list = nullptr;
   int nbulk_blocks = 0;
@@ -374,31 +374,32 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   CHK(upload(&ctx->rec_link0, r_link0));
   CHK(upload(&ctx->rec_face, r_face));
   CHK(upload(&ctx->rec_bc, bcT));
+  // Each branch of the rule has three terms: q < 1/2 uses c0 f_i(x),
+  // c1 f_i(x-e_i), c2 f_i(x-2e_i); q >= 1/2 uses c0 f_i(x), c3 f_j(x),
+  // c4 f_j(x-e_i).  Stored per link as k0, k1, k2 (in that order, [3][nl],
+  // compute type) with one bit per record and direction saying which branch.
   const size_t nl = l_c.size() / 5;
-  // at least one entry: the kernels read entry 0 for directions without a link
-  std::vector<double> lcT(std::max<size_t>(l_c.size(), 5), 0.0);
-  for (size_t k = 0; k < nl; k++)
-    for (int c = 0; c < 5; c++) lcT[c * nl + k] = l_c[5 * k + c];
+  std::vector<double> lcT(std::max<size_t>(3 * nl, 3), 0.0);  // entry 0 always exists
+  std::vector<uint32_t> mb((size_t)std::max(ctx->nrec, 1), 0u);
+  for (int r = 0; r < ctx->nrec; r++) {
+    int lk = r_link0[r];
+    for (int j = 1; j < 19; j++) {
+      if (!((r_mask[r] >> j) & 1u)) continue;
+      const double* c = &l_c[5 * (size_t)lk];
+      const bool hq = c[1] == 0.0 && c[2] == 0.0 && (c[3] != 0.0 || c[4] != 0.0);
+      if (hq) mb[r] |= 1u << j;
+      lcT[lk] = c[0];
+      lcT[nl + lk] = hq ? c[3] : c[1];
+      lcT[2 * nl + lk] = hq ? c[4] : c[2];
+      ++lk;
+    }
+  }
   ctx->nlinks_rec = (int)nl;
   if (ctx->prec == 0) {
     CHK(upload((double**)&ctx->lk_c, lcT));
   } else {
     std::vector<float> lcf(lcT.begin(), lcT.end());
     CHK(upload((float**)&ctx->lk_c, lcf));
-  }
-  // per record and linked direction j (bit j): which of the terms
-  // c1 f_i(x-e_i), c2 f_i(x-2e_i), c4 f_j(x-e_i), c3 f_j(x) are present
-  std::vector<uint32_t> mb(4 * (size_t)ctx->nrec, 0u);
-  for (int r = 0; r < ctx->nrec; r++) {
-    int lk = r_link0[r];
-    for (int j = 1; j < 19; j++) {
-      if (!((r_mask[r] >> j) & 1u)) continue;
-      const double* c = &l_c[5 * (size_t)lk++];
-      if (c[1] != 0.0) mb[r] |= 1u << j;
-      if (c[2] != 0.0) mb[(size_t)ctx->nrec + r] |= 1u << j;
-      if (c[4] != 0.0) mb[2 * (size_t)ctx->nrec + r] |= 1u << j;
-      if (c[3] != 0.0) mb[3 * (size_t)ctx->nrec + r] |= 1u << j;
-    }
   }
   CHK(upload(&ctx->rec_mb, mb));
   CHK(upload(&ctx->tile_list, tiles));
@@ -467,6 +468,8 @@ extern "C" lbm_status lbm_info(lbm_ctx* ctx, lbm_info_t* o) {
   o->bytes_per_step_alg = 2 * 19 * (int64_t)ctx->ssize * ctx->n_fluid;
   o->precision = ctx->prec;
   o->mls_singular = h.mls_singular;
+  o->fluid_launch = ctx->fluid_merged ? 1 : 2;
+  o->pad = 0;
   return LBM_OK;
 }
 

@@ -62,8 +62,8 @@ struct FluidArgs {
   const int32_t* rec_link0;
   const uint8_t* rec_face;   // 0xff: none; else face | (kind << 4) (kind 1 = density)
   const double* rec_bc;      // [4][nrec]: ux, uy, uz, rho
-  const void* lk_c;          // [5][nlinks] interpolated bounce-back coefficients (compute type)
-  const uint32_t* rec_mb;    // [4][nrec] bit j: linked direction j uses c1, c2, c4, c3 (in that order)
+  const void* lk_c;          // [3][nlinks] interpolated bounce-back coefficients (compute type)
+  const uint32_t* rec_mb;    // [nrec] bit j: the link of direction j has q >= 1/2
   int nlinks;
   const int32_t* tile_list;  // blocks of the bulk part
   int nbulk_blocks;

@@ -232,68 +232,84 @@ __device__ void zouhe(C (&g)[19], int face, int kind, C bx, C by, C bz, C brho) 
   for (int j = 0; j < 19; j++) g[j] = out[j];
 }
 
-// Streamed populations of a boundary record: plain pulls (periodic wrap),
-// interpolated bounce-back on wall links (Eq. bbouzidi) as
-// c0 f*_i(x) + c1 f*_i(x - e_i) + c2 f*_i(x - 2e_i) + c3 f*_j(x) + c4 f*_j(x - e_i)
-// with coefficients fixed on the host from q and the fluid neighbours, and
-// Zou-He for the populations entering through an open face.  Addresses are
-// formed with periodic wrap, so they lie in the box even where a coefficient
-// is zero: all loads are issued in one batch, then the arithmetic follows.
-// Streamed populations of a boundary record: plain pulls (periodic wrap),
-// interpolated bounce-back on wall links (Eq. bbouzidi) as
-// c0 f*_i(x) + c1 f*_i(x - e_i) + c2 f*_i(x - 2e_i) + c3 f*_j(x) + c4 f*_j(x - e_i)
-// with coefficients fixed on the host from q and the fluid neighbours, and
-// Zou-He for the populations entering through an open face.  Addresses are
-// formed with periodic wrap, so they lie in the box even where a coefficient
-// is zero; all loads are issued in one batch, then the arithmetic follows.
-// A neighbour term whose coefficient is zero (record masks) reads the
-// node's own value instead, which is loaded anyway: no extra traffic.
+// Interpolated bounce-back of the linked direction j at node x (Eq.
+// bbouzidi): k0 f*_i(x) + k1 t1 + k2 t2 with i the opposite of j and, by the
+// link's branch, t1 = f*_i(x - e_i), t2 = f*_i(x - 2e_i) (q < 1/2) or
+// t1 = f*_j(x), t2 = f*_j(x - e_i) (q >= 1/2); k1, k2 are zero where the
+// fluid neighbours are missing.  The loads carry no branch (they go out in
+// one batch with the rest of the node's loads); for a direction without a
+// link they read the node's own values (no traffic) and the caller drops
+// the result.
 template <class S>
-__device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19]) {
+struct Bfl {
+  typename Store<S>::C k0, k1, k2, s, t1, t2;
+};
+
+template <class S>
+__device__ __forceinline__ Bfl<S> bfl_load(const FluidArgs& a, int j, bool linked, int lk, bool hq,
+                                           long long node, int x, int y, int z) {
   typedef typename Store<S>::C C;
   const Grid& G = a.g;
   const C* lc = (const C*)a.lk_c;
   const long long nl = a.nlinks;
+  const int i = OPP[j];
+  const int l = linked ? lk : 0;
+  const long long n1 = linked ? nbr(G, x, y, z, EX[j], EY[j], EZ[j]) : node;  // x - e_i
+  const long long n2 = linked ? nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]) : node;
+  Bfl<S> r;
+  r.k0 = lc[l];
+  r.k1 = lc[nl + l];
+  r.k2 = lc[2 * nl + l];
+  r.s = ldA<S>(a, i, node);
+  r.t1 = ldA<S>(a, hq ? j : i, hq ? node : n1);
+  r.t2 = ldA<S>(a, hq ? j : i, hq ? n1 : n2);
+  return r;
+}
+
+template <class S>
+__device__ __forceinline__ typename Store<S>::C bfl_value(const Bfl<S>& b) {
+  return b.k0 * b.s + b.k1 * b.t1 + b.k2 * b.t2;
+}
+
+// Streamed populations of a boundary record: plain pulls (periodic wrap),
+// interpolated bounce-back on wall links, and Zou-He for the populations
+// entering through an open face.  Addresses are formed with periodic wrap,
+// so they lie in the box; after the record's header every load is issued
+// in one batch, then the arithmetic follows.  A pull from a solid node or
+// from outside the box reads the node's own rest value (no traffic) and is
+// not used.
+template <class S>
+__device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19]) {
+  typedef typename Store<S>::C C;
+  const Grid& G = a.g;
   const long long node = a.rec_node[r];
   const uint32_t mask = a.rec_mask[r];
-  const uint32_t m1 = a.rec_mb[r], m2 = a.rec_mb[a.nrec + r], m4 = a.rec_mb[2 * a.nrec + r];
+  const uint32_t hqm = a.rec_mb[r];
   const int lk0 = a.rec_link0[r];
   const int fc = a.rec_face[r];
   int x, y, z;
   coords(G, node, x, y, z);
   const int face = fc & 7, kind = (fc >> 4) & 1;
   const int ax = face >> 1, s = (face & 1) ? -1 : 1;
-  C self[19], pl[19], b1[19], b2[19], b3[19], cf[19][5];
-#pragma unroll
-  for (int i = 0; i < 19; i++) self[i] = ldA<S>(a, i, node);
-#pragma unroll
-  for (int j = 1; j < 19; j++) pl[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
-  int lk = lk0;
-#pragma unroll
-  for (int j = 1; j < 19; j++) {
-    cf[j][0] = cf[j][1] = cf[j][2] = cf[j][3] = cf[j][4] = C(0);
-    b1[j] = b2[j] = b3[j] = C(0);
-    if ((mask >> j) & 1u) {
-      const int i = OPP[j];
-#pragma unroll
-      for (int c = 0; c < 5; c++) cf[j][c] = lc[c * nl + lk];
-      ++lk;
-      const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
-      const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
-      b1[j] = ldA<S>(a, i, ((m1 >> j) & 1u) ? n1 : node);
-      b2[j] = ldA<S>(a, i, ((m2 >> j) & 1u) ? n2 : node);
-      b3[j] = ldA<S>(a, ((m4 >> j) & 1u) ? j : i, ((m4 >> j) & 1u) ? n1 : node);
-    }
-  }
-  g[0] = self[0];
+  C pl[19];
+  Bfl<S> bb[19];
+  pl[0] = ldA<S>(a, 0, node);
 #pragma unroll
   for (int j = 1; j < 19; j++) {
     const int e[3] = {EX[j], EY[j], EZ[j]};
     const bool linked = (mask >> j) & 1u;
-    const C bfl = cf[j][0] * self[OPP[j]] + cf[j][1] * b1[j] + cf[j][2] * b2[j] + cf[j][3] * self[j] +
-                  cf[j][4] * b3[j];
     const bool unknown = fc != 0xff && s * (ax == 0 ? e[0] : (ax == 1 ? e[1] : e[2])) == 1;
-    g[j] = linked ? bfl : (unknown ? C(0) : pl[j]);
+    const bool plain = !linked && !unknown;
+    pl[j] = ldA<S>(a, plain ? j : 0, plain ? nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]) : node);
+    bb[j] = bfl_load<S>(a, j, linked, lk0 + __popc(mask & ((1u << j) - 1u)), (hqm >> j) & 1u, node, x, y, z);
+  }
+  g[0] = pl[0];
+#pragma unroll
+  for (int j = 1; j < 19; j++) {
+    const int e[3] = {EX[j], EY[j], EZ[j]};
+    const bool linked = (mask >> j) & 1u;
+    const bool unknown = fc != 0xff && s * (ax == 0 ? e[0] : (ax == 1 ? e[1] : e[2])) == 1;
+    g[j] = linked ? bfl_value<S>(bb[j]) : (unknown ? C(0) : pl[j]);
   }
   if (fc != 0xff) {
     zouhe<C>(g, face, kind, (C)a.rec_bc[r], (C)a.rec_bc[a.nrec + r], (C)a.rec_bc[2 * a.nrec + r],
@@ -320,34 +336,29 @@ __device__ __forceinline__ Moments streamed_moments(const FluidArgs& a, long lon
   } else {
     const int r = a.rec_of[node];
     const uint32_t mask = a.rec_mask[r];
-    typedef typename Store<S>::C C;
-    const C* lc = (const C*)a.lk_c;
-    const long long nl = a.nlinks;
+    const uint32_t hqm = a.rec_mb[r];
+    const int lk0 = a.rec_link0[r];
     const int fc = a.rec_face[r];
     const int face = fc & 7, ax = face >> 1, sgn = (face & 1) ? -1 : 1;
-    int lk = a.rec_link0[r];
-    g[0] = (double)ldA<S>(a, 0, node);
+    typedef typename Store<S>::C C;
+    C pl[19];
+    Bfl<S> bb[19];
+    pl[0] = ldA<S>(a, 0, node);
 #pragma unroll
     for (int j = 1; j < 19; j++) {
       const int en = sgn * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]));
-      double v;
-      if ((mask >> j) & 1u) {
-        const int i = OPP[j];
-        const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);
-        const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
-        double c[5];
+      const bool linked = (mask >> j) & 1u;
+      const bool plain = !linked && !(fc != 0xff && en == 1);
+      pl[j] = ldA<S>(a, plain ? j : 0, plain ? nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]) : node);
+      bb[j] = bfl_load<S>(a, j, linked, lk0 + __popc(mask & ((1u << j) - 1u)), (hqm >> j) & 1u, node, x, y, z);
+    }
+    g[0] = (double)pl[0];
 #pragma unroll
-        for (int k = 0; k < 5; k++) c[k] = (double)lc[k * nl + lk];
-        ++lk;
-        v = c[0] * (double)ldA<S>(a, i, node) + c[1] * (double)ldA<S>(a, i, n1) +
-            c[2] * (double)ldA<S>(a, i, n2) + c[3] * (double)ldA<S>(a, j, node) +
-            c[4] * (double)ldA<S>(a, j, n1);
-      } else if (fc != 0xff && en == 1) {
-        v = 0.0;  // enters through the open face: the Zou-He rule fills it
-      } else {
-        v = (double)ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
-      }
-      g[j] = v;
+    for (int j = 1; j < 19; j++) {
+      const int en = sgn * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]));
+      const bool linked = (mask >> j) & 1u;
+      const bool unknown = fc != 0xff && en == 1;  // the Zou-He rule fills it
+      g[j] = linked ? (double)bfl_value<S>(bb[j]) : (unknown ? 0.0 : (double)pl[j]);
     }
     if (fc != 0xff) {
       double G0 = 0.0, Gout = 0.0;
