@@ -74,20 +74,28 @@ def bifurcation_capsule(seed=0, precision="f32", steps=5000, nx=256, ny=128, nz=
 
 
 def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_choices,
-                    x_inlet_clear, face_clear, u_max, max_tries=100000):
+                    x_inlet_clear, face_clear, u_max, max_tries=100000, tries_per_capsule=2000):
     """Rejection sampling of non-overlapping capsules inside the fluid.
     Draw order per capsule: occlusion ratio, log10 Ca, mesh choice, then
-    centre candidates (x, y, z) until one fits."""
+    centre candidates (x, y, z) until one fits: wall clearance >= r_p + 1.5
+    (signed distance), centre distance >= r_i + r_j + 2 to the capsules
+    already placed, at least x_inlet_clear from the inlet and face_clear from
+    the other faces.  A capsule that finds no centre within
+    tries_per_capsule candidates has its radius (and Ca, mesh) drawn again
+    from the same stream; the redraws are counted.  Returns (bodies,
+    redraws); stops early once max_tries candidates have been spent."""
     nx, ny, nz = box
     bodies, centres, radii = [], [], []
-    tries = 0
-    while len(bodies) < n:
+    tries = redraws = 0
+    while len(bodies) < n and tries < max_tries:
         occ = rng.uniform(occl_lo, occl_hi)
         ca = 10.0 ** rng.uniform(np.log10(ca_lo), np.log10(ca_hi))
         sub = subdiv_choices[rng.integers(len(subdiv_choices))]
         rp = occ * D / 2.0
-        placed = False
-        while tries < max_tries:
+        placed = None
+        for _ in range(tries_per_capsule):
+            if tries >= max_tries:
+                break
             tries += 1
             c = np.array([rng.uniform(x_inlet_clear, nx - 1 - face_clear),
                           rng.uniform(face_clear, ny - 1 - face_clear),
@@ -96,17 +104,19 @@ def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_
                 continue
             if any(np.linalg.norm(c - cc) < rp + rr + 2.0 for cc, rr in zip(centres, radii)):
                 continue
-            placed = True
+            placed = c
             break
-        if not placed:
-            break
-        X, F = icosphere(sub, rp, c, tilt=True)
+        if placed is None:
+            redraws += 1
+            continue
+        X, F = icosphere(sub, rp, placed, tilt=True)
         if not off_switch_planes(X, F):
+            redraws += 1
             continue
         bodies.append(Body(X, F, rigid=False, ca=ca, eb=0.001, rho_ratio=1.1, r_ref=rp, u_ref=u_max))
-        centres.append(c)
+        centres.append(placed)
         radii.append(rp)
-    return bodies
+    return bodies, redraws
 
 
 def precision_form(seed=0, precision="f16s", steps=2000, n_capsules=16):
@@ -120,10 +130,10 @@ def precision_form(seed=0, precision="f16s", steps=2000, n_capsules=16):
     D = 48.0
     u_max = 10.0 * nu / D
     dom = bifurcation(512, 256, 64, D, 0.8, 90.0, 4.0, u_max=u_max)
-    bodies = _place_capsules(rng, dom.meta["sdf"], (512, 256, 64), D, n_capsules,
-                             0.3, 0.8, 1e-3, 1e-1, (4,), D, D, u_max)
+    bodies, redraws = _place_capsules(rng, dom.meta["sdf"], (512, 256, 64), D, n_capsules,
+                                      0.3, 0.8, 1e-3, 1e-1, (4,), D, D, u_max)
     return Workload("precision_form", dom, bodies, tau, u_max, precision, steps,
-                    meta={"seed": seed})
+                    meta={"seed": seed, "radius_redraws": redraws})
 
 
 def batch_instances(seed=0, n_instances=64):
@@ -144,10 +154,10 @@ def batch_instances(seed=0, n_instances=64):
         nu = (tau - 0.5) / 3.0
         u_max = 10.0 * nu / D
         dom = bifurcation(nx, ny, nz, D, 0.8, th, fil, x_junction=4 * D, u_max=u_max)
-        bodies = _place_capsules(rng, dom.meta["sdf"], (nx, ny, nz), D, ncap, 0.3, 0.9,
-                                 1e-3, 1e-1, (3, 4), D, 0.5 * D, u_max)
+        bodies, redraws = _place_capsules(rng, dom.meta["sdf"], (nx, ny, nz), D, ncap, 0.3, 0.9,
+                                          1e-3, 1e-1, (3, 4), D, 0.5 * D, u_max)
         out.append(Workload(f"batch_{k}", dom, bodies, tau, u_max, "f32", 1000,
-                            meta={"D": D, "theta": th, "fillet": fil}))
+                            meta={"D": D, "theta": th, "fillet": fil, "radius_redraws": redraws}))
     return out
 
 
