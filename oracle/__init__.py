@@ -105,6 +105,7 @@ def lib():
     L.orc_membrane.restype = d
     L.orc_membrane.argtypes = [vp, C.c_int, _P(d), C.c_int, _P(d)]
     L.orc_body_hydro.argtypes = [vp, C.c_int, _P(d)]
+    L.orc_body_fext.argtypes = [vp, C.c_int, _P(d)]
     _lib = L
     return L
 
@@ -282,6 +283,13 @@ class OracleSim:
         _, nf = self.bodies[bid]
         out = np.zeros((nf, 3))
         lib().orc_body_hydro(self._h, bid, _ptr(out, C.c_double))
+        return out
+
+    def body_fext(self, bid):
+        """Per-face external force (hydrodynamic + repulsion) of the last step."""
+        _, nf = self.bodies[bid]
+        out = np.zeros((nf, 3))
+        lib().orc_body_fext(self._h, bid, _ptr(out, C.c_double))
         return out
 
 

@@ -957,34 +957,51 @@ void orc_body_hydro(const orc_sim *s, int id, double *Fface) {
   hydro_faces(s, &s->bodies[id], Fface);
 }
 
+void orc_body_fext(const orc_sim *s, int id, double *Fface) {
+  const body_t *B = &s->bodies[id];
+  memcpy(Fface, B->Fext, sizeof(double) * 3 * B->nf);
+}
+
 /* S6 repulsion (Eq. collision): centroid pairs of different bodies closer
  * than dx push the receiving face along its inward normal with magnitude
  * u_max dt / (8 sqrt 2) sqrt(dx / d^5).  Pairs of bodies whose bounding
  * boxes are more than dx apart are skipped (they have no such pair). */
 static void repulsion(orc_sim *s) {
+  if (s->nbody < 2) return;
   const double pref = s->umax / (8.0 * sqrt(2.0));
+  /* centroid, outward normal and bounding box of every body */
+  double **cen = (double **)calloc(s->nbody, sizeof(double *));
+  double **nrm = (double **)calloc(s->nbody, sizeof(double *));
+  double *box = (double *)malloc(sizeof(double) * 6 * s->nbody);
   for (int b = 0; b < s->nbody; b++) {
     body_t *B = &s->bodies[b];
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    cen[b] = (double *)malloc(sizeof(double) * 3 * B->nf);
+    nrm[b] = (double *)malloc(sizeof(double) * 3 * B->nf);
+    for (int f = 0; f < B->nf; f++) {
+      double A;
+      face_geom(B->x, B->faces + 3 * f, cen[b] + 3 * f, nrm[b] + 3 * f, &A);
+    }
+    double *lo = box + 6 * b, *hi = box + 6 * b + 3;
+    for (int a = 0; a < 3; a++) { lo[a] = 1e300; hi[a] = -1e300; }
     for (int v = 0; v < B->nv; v++)
       for (int a = 0; a < 3; a++) { lo[a] = fmin(lo[a], B->x[3 * v + a]); hi[a] = fmax(hi[a], B->x[3 * v + a]); }
+  }
+  for (int b = 0; b < s->nbody; b++) {
+    body_t *B = &s->bodies[b];
     for (int o = 0; o < s->nbody; o++) {
       if (o == b) continue;
-      body_t *O = &s->bodies[o];
-      double lo2[3] = {1e300, 1e300, 1e300}, hi2[3] = {-1e300, -1e300, -1e300};
-      for (int v = 0; v < O->nv; v++)
-        for (int a = 0; a < 3; a++) { lo2[a] = fmin(lo2[a], O->x[3 * v + a]); hi2[a] = fmax(hi2[a], O->x[3 * v + a]); }
+      const double *lo = box + 6 * b, *hi = box + 6 * b + 3, *lo2 = box + 6 * o, *hi2 = box + 6 * o + 3;
       int far = 0;
       for (int a = 0; a < 3; a++)
         if (lo[a] > hi2[a] + 1.0 || lo2[a] > hi[a] + 1.0) far = 1;
       if (far) continue;
+      const int nfo = s->bodies[o].nf;
+#pragma omp parallel for schedule(static) num_threads(orc_threads())
       for (int f = 0; f < B->nf; f++) {
-        double ci[3], ni[3], Ai;
-        face_geom(B->x, B->faces + 3 * f, ci, ni, &Ai);
-        for (int g = 0; g < O->nf; g++) {
-          double cj[3], nj[3], Aj, d[3];
-          face_geom(O->x, O->faces + 3 * g, cj, nj, &Aj);
-          sub(ci, cj, d);
+        const double *ci = cen[b] + 3 * f, *ni = nrm[b] + 3 * f;
+        for (int g = 0; g < nfo; g++) {
+          double d[3];
+          sub(ci, cen[o] + 3 * g, d);
           double dist = norm(d);
           if (dist < 1.0 && dist > 0.0) {
             double mag = pref * sqrt(1.0 / pow(dist, 5.0));
@@ -994,6 +1011,8 @@ static void repulsion(orc_sim *s) {
       }
     }
   }
+  for (int b = 0; b < s->nbody; b++) { free(cen[b]); free(nrm[b]); }
+  free(cen); free(nrm); free(box);
 }
 
 /* Internal membrane forces for positions x (Eqs. strainFor, bendFor, volFor)

@@ -84,6 +84,9 @@ double orc_zouhe(double *f19, int face, int kind, const double *u_w, double rho_
 double orc_membrane(const orc_sim *s, int id, const double *x, int which, double *F);
 /* Hydrodynamic force per face (nf*3) of body id from the current rho, u. */
 void orc_body_hydro(const orc_sim *s, int id, double *Fface);
+/* External force per face (nf*3) of body id used by the last completed step:
+ * the hydrodynamic force plus the inter-body repulsion. */
+void orc_body_fext(const orc_sim *s, int id, double *Fface);
 
 #ifdef __cplusplus
 }

@@ -188,6 +188,36 @@ def tiny_pipe(precision="f64", steps=20, with_body=True, rigid=True, nx=24, ny=1
     return Workload("tiny_pipe", dom, bodies, tau, u_max, precision, steps)
 
 
+def facing_pair(d=0.5, subdiv=0, radius=3.0, rigid=True, fixed=True, precision="f64", steps=1,
+                u_max=0.04, centre=(11.3, 7.9, 8.2), box=(24, 16, 16)):
+    """Two icospheres in a periodic box of fluid at rest, mirror images of
+    each other through the plane x = centre[0], with face 0 of each parallel
+    to that plane and the two face-0 centroids a distance d apart on the
+    x axis (the closest centroid pair of the two bodies).  No random draws.
+    meta["face"] is the index of the facing face in both bodies."""
+    X, F = icosphere(subdiv, 1.0)
+    a, b, c = X[F[0, 0]], X[F[0, 1]], X[F[0, 2]]
+    n = np.cross(b - a, c - a)
+    n /= np.linalg.norm(n)
+    # rotation taking the outward normal of face 0 onto +x (Rodrigues)
+    ex = np.array([1.0, 0.0, 0.0])
+    k = np.cross(n, ex)
+    sn, cs = np.linalg.norm(k), float(n @ ex)
+    k /= sn
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    R = np.eye(3) + sn * K + (1 - cs) * K @ K
+    XA = (X @ R.T) * radius
+    XA += np.asarray(centre) - XA[F[0]].mean(0) - np.array([d / 2, 0.0, 0.0])
+    XB = XA.copy()
+    XB[:, 0] = 2 * centre[0] - XB[:, 0]
+    FB = F[:, [0, 2, 1]].copy()   # a mirror image reverses the orientation
+    kw = dict(rigid=rigid, fixed=fixed and rigid, ca=0.05, eb=0.001, rho_ratio=1.1, r_ref=radius,
+              u_ref=u_max)
+    dom = periodic_box(*box)
+    return Workload("facing_pair", dom, [Body(XA, F, **kw), Body(XB, FB, **kw)], 0.8, u_max,
+                    precision, steps, meta={"face": 0, "d": d})
+
+
 def tiny_bifurcation(seed=0, precision="f64", steps=20, n_bodies=1, subdiv=2):
     """Small Y-bifurcation (D = 12 on 64x40x16, 60 degrees, fillet 2) with
     one or two deformable capsules; draw order as in bifurcation_capsule."""
@@ -219,6 +249,7 @@ _REGISTRY = {
     "pipe_r1": pipe_r1,
     "tiny_pipe": tiny_pipe,
     "tiny_bifurcation": tiny_bifurcation,
+    "facing_pair": facing_pair,
 }
 
 

@@ -123,6 +123,19 @@ def test_bifurcation_two_soft_capsules(lib, precision):
     _compare(lat, orc, w, TOL[precision])
 
 
+@pytest.mark.parametrize("rigid", [False, True])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_facing_bodies_repel(lib, precision, rigid):
+    """Two bodies with one centroid pair half a spacing apart in fluid at
+    rest: the repulsion is what sets them moving."""
+    w = synth.facing_pair(0.5, subdiv=2, rigid=rigid, fixed=False, precision=precision)
+    lat, orc, st, so = _run_pair(lib, w, precision, 20)
+    assert st == 0 and so == 0
+    x0 = orc.body(0)[0]
+    assert x0[:, 0].mean() < w.bodies[0].x[:, 0].mean()   # pushed apart along x
+    _compare(lat, orc, w, TOL[precision])
+
+
 def test_force_field_matches(lib):
     w = synth.tiny_pipe(precision="f64", rigid=False)
     lat, orc, _, _ = _run_pair(lib, w, "f64", 5)

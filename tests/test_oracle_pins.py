@@ -477,3 +477,33 @@ def test_pipe_poiseuille_profile():
     walls: L2 error below 1% at R = 8 and decreasing with R."""
     e8, e12 = _poiseuille_error(8.0), _poiseuille_error(12.0)
     assert e8 < 0.01 and e12 < e8
+
+
+# ------------------------------------------------- repulsion (Eq. collision)
+
+@pytest.mark.parametrize("d", [0.3, 0.55, 0.9])
+def test_repulsion_closed_form_for_one_facing_pair(d):
+    """Fluid at rest around two fixed bodies: the hydrodynamic force
+    vanishes, and the external force is the repulsion alone.  Only the
+    facing pair is within one spacing, so each facing face is pushed along
+    its inward normal (away from the other body) with magnitude
+    u_max/(8 sqrt 2) d^(-5/2); every other face feels nothing."""
+    w = synth.facing_pair(d)
+    u_max, f0 = w.u_max, w.meta["face"]
+    s = oracle.OracleSim(w.domain, tau=w.tau, u_max=u_max, bodies=w.bodies, threads=1)
+    assert s.step(1) == 0
+    mag = u_max / (8.0 * np.sqrt(2.0)) * d ** -2.5
+    for bid, sign in ((0, -1.0), (1, 1.0)):
+        Fe = s.body_fext(bid)
+        np.testing.assert_allclose(Fe[f0], [sign * mag, 0.0, 0.0], rtol=1e-12, atol=1e-13)
+        rest = np.delete(Fe, f0, axis=0)
+        assert np.abs(rest).max() < 1e-13
+    # Newton's third law for the pair
+    np.testing.assert_allclose(s.body_fext(0).sum(0), -s.body_fext(1).sum(0), atol=1e-13)
+
+
+def test_repulsion_vanishes_beyond_one_spacing():
+    w = synth.facing_pair(1.05)
+    s = oracle.OracleSim(w.domain, tau=w.tau, u_max=w.u_max, bodies=w.bodies, threads=1)
+    assert s.step(1) == 0
+    assert np.abs(s.body_fext(0)).max() < 1e-13 and np.abs(s.body_fext(1)).max() < 1e-13
