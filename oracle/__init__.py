@@ -20,12 +20,14 @@ _lib = None
 # Measurement builds of the same source, used only to gauge how far a
 # trajectory moves under other rounding: "fma" lets the compiler fuse
 # multiply-adds, "reassoc" lets it reorder sums (vectorised reductions),
-# "store_f32" rounds the stored populations to FP32.
+# "store_f32" and "store_f16" round the stored populations to FP32 or to
+# binary16.
 VARIANT_FLAGS = {
     "plain": [],
     "fma": ["-mfma", "-ffp-contract=fast"],
     "reassoc": ["-O3", "-mavx2", "-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math"],
     "store_f32": ["-DORC_STORE_F32"],
+    "store_f16": ["-DORC_STORE_F16"],
 }
 
 

@@ -842,6 +842,16 @@ static int collide_node(orc_sim *s, long n) {
      * gauge how far FP32 storage alone moves a trajectory */
     v = (double)(float)v;
 #endif
+#ifdef ORC_STORE_F16
+    /* measurement build only: the state rounded to binary16 (11 significant
+     * bits, subnormal spacing 2^-24, ties to even) at every store */
+    if (v != 0.0) {
+      int ex;
+      frexp(v, &ex);
+      const double ulp = ldexp(1.0, (ex - 11 < -24) ? -24 : ex - 11);
+      v = nearbyint(v / ulp) * ulp;
+    }
+#endif
     s->fs[19 * n + i] = v;
   }
   for (int a = 0; a < 3; a++) s->u[3 * n + a] = u[a];
