@@ -201,6 +201,65 @@ lbm_status lbm_time_fluid_kernel(lbm_ctx *ctx, int32_t n_steps, double *avg_ms);
 /* Replay steps from captured HIP graphs (default 1) or launch kernels one by one (0). */
 lbm_status lbm_set_graph(lbm_ctx *ctx, int32_t enable);
 
+/* Launch shape of the stream-collide kernel: bulk_v consecutive nodes per
+ * thread (FP64: 1, 2; FP32: 1, 2, 4; FP16S: 2, 4, 8) and block threads per
+ * block (64, 128, 256).  The arithmetic per node does not depend on it, so
+ * results are bitwise unchanged.  Synchronises the context's stream;
+ * LBM_E_INVAL for an unsupported shape. */
+lbm_status lbm_set_launch_shape(lbm_ctx *ctx, int32_t bulk_v, int32_t block);
+
+/* ------------------------------------------------------------------------
+ * Batching form: many independent instances (contexts of any size, e.g. the
+ * bifurcations of a parameter sweep) advanced together.  Every phase of a
+ * coupled step (forcing, stream-collide, probes and vertex velocities,
+ * membrane and motion, close) is ONE launch over the work units of all
+ * instances -- block g takes unit (instance, block of that instance's own
+ * launch) from a device map -- and 16 steps are one HIP graph launch.  Each
+ * instance computes exactly what its own lbm_step computes (bitwise).
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* Fluid-phase launch shape of a batch: bulk_v and block as for
+ * lbm_set_launch_shape; mode 0 runs boundary records and bulk tiles in one
+ * launch, mode 1 runs all records, then all bulk tiles; per_xcd > 0 (mode 1
+ * only) runs the bulk tiles in a persistent grid of per_xcd blocks on each
+ * of the 8 XCDs.  fluid_ms: measured duration of the phase (tuner output). */
+typedef struct {
+  int32_t bulk_v, block, mode, per_xcd;
+  double fluid_ms;
+} lbm_batch_shape;
+
+/* Groups n contexts (n >= 1, all distinct, same precision, same stream,
+ * none periodic along x) into a batch.  The contexts stay owned by the
+ * caller, must outlive the batch, and keep working on their own (lbm_sync,
+ * lbm_get_*, lbm_step); adding a body or stepping one context alone is
+ * picked up by the next batch call.  *out is set even on failure (read
+ * lbm_batch_last_error, then lbm_batch_destroy).  LBM_E_UNSUPPORTED for a
+ * periodic-x context. */
+lbm_status lbm_batch_create(lbm_ctx *const *ctxs, int32_t n, lbm_batch **out);
+lbm_status lbm_batch_destroy(lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+
+/* n_steps coupled steps of every instance, enqueued on the shared stream.
+ * Status bits (unstable, damaged) are per instance: read them with lbm_sync
+ * on each context.  An instance that stopped is skipped by every phase. */
+lbm_status lbm_batch_step(lbm_batch *b, int32_t n_steps);
+
+/* The autotuner: times the batched stream-collide phase (reps launches after
+ * two untimed ones, HIP events on the shared stream) for every shape the
+ * precision supports, keeps the fastest, and writes up to max_out of the
+ * tried shapes with their times to out (may be NULL) and their count to
+ * *n_out.  Timing the phase leaves the run unchanged (it rewrites only what
+ * the next step rewrites from the same inputs). */
+lbm_status lbm_batch_tune(lbm_batch *b, int32_t reps, lbm_batch_shape *out, int32_t max_out,
+                          int32_t *n_out);
+lbm_status lbm_batch_set_shape(lbm_batch *b, const lbm_batch_shape *shape);
+lbm_status lbm_batch_get_shape(lbm_batch *b, lbm_batch_shape *shape);
+/* Average duration (ms) of the batched stream-collide phase over reps launches. */
+lbm_status lbm_batch_time_fluid(lbm_batch *b, int32_t reps, double *avg_ms);
+/* Graph replay (default 1) or one launch at a time (0). */
+lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t enable);
+
 #ifdef __cplusplus
 }
 #endif

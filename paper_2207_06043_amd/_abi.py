@@ -24,7 +24,10 @@ PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 EXPORTS = ["lbm_create", "lbm_destroy", "lbm_last_error", "lbm_info", "lbm_add_body", "lbm_step",
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_get_force", "lbm_get_body",
            "ib_interpolate", "ib_spread", "lbm_adjoint_step", "lbm_save", "lbm_load",
-           "lbm_time_fluid_kernel", "lbm_set_graph"]
+           "lbm_time_fluid_kernel", "lbm_set_graph", "lbm_set_launch_shape", "lbm_batch_create",
+           "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_step", "lbm_batch_tune",
+           "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_time_fluid",
+           "lbm_batch_set_graph"]
 
 
 class LbmError(RuntimeError):
@@ -58,6 +61,14 @@ class LbmInfo(C.Structure):
                 ("n_vertices", C.c_int64), ("n_faces", C.c_int64), ("steps_done", C.c_int64),
                 ("bytes_per_step_alg", C.c_int64), ("precision", C.c_int32),
                 ("mls_singular", C.c_int32), ("fluid_launch", C.c_int32), ("pad", C.c_int32)]
+
+
+class LbmBatchShape(C.Structure):
+    _fields_ = [("bulk_v", C.c_int32), ("block", C.c_int32), ("mode", C.c_int32),
+                ("per_xcd", C.c_int32), ("fluid_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -111,6 +122,26 @@ def load_library():
     L.lbm_time_fluid_kernel.argtypes = [vp, i32, dp]
     L.lbm_set_graph.restype = st
     L.lbm_set_graph.argtypes = [vp, i32]
+    L.lbm_set_launch_shape.restype = st
+    L.lbm_set_launch_shape.argtypes = [vp, i32, i32]
+    L.lbm_batch_create.restype = st
+    L.lbm_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
+    L.lbm_batch_destroy.restype = st
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_last_error.restype = C.c_char_p
+    L.lbm_batch_last_error.argtypes = [vp]
+    L.lbm_batch_step.restype = st
+    L.lbm_batch_step.argtypes = [vp, i32]
+    L.lbm_batch_tune.restype = st
+    L.lbm_batch_tune.argtypes = [vp, i32, C.POINTER(LbmBatchShape), i32, C.POINTER(i32)]
+    L.lbm_batch_set_shape.restype = st
+    L.lbm_batch_set_shape.argtypes = [vp, C.POINTER(LbmBatchShape)]
+    L.lbm_batch_get_shape.restype = st
+    L.lbm_batch_get_shape.argtypes = [vp, C.POINTER(LbmBatchShape)]
+    L.lbm_batch_time_fluid.restype = st
+    L.lbm_batch_time_fluid.argtypes = [vp, i32, dp]
+    L.lbm_batch_set_graph.restype = st
+    L.lbm_batch_set_graph.argtypes = [vp, i32]
     _lib = L
     return L
 
@@ -228,6 +259,9 @@ class Lattice:
         self._check(load_library().lbm_info(self._h, C.byref(o)))
         return {k: getattr(o, k) for k, _ in LbmInfo._fields_}
 
+    def set_launch_shape(self, bulk_v, block):
+        self._check(load_library().lbm_set_launch_shape(self._h, int(bulk_v), int(block)))
+
     def time_fluid_kernel(self, n):
         ms = C.c_double()
         self._check(load_library().lbm_time_fluid_kernel(self._h, int(n), C.byref(ms)))
@@ -289,6 +323,69 @@ class Lattice:
 
     def load(self, path):
         self._check(load_library().lbm_load(self._h, str(path).encode()))
+
+
+class Batch:
+    """Independent lattices advanced together (see ``include/lbm.h``, batching
+    form).  The lattices must share precision and stream and outlive the
+    batch; they keep working on their own."""
+
+    def __init__(self, lattices):
+        L = load_library()
+        self.lattices = list(lattices)
+        arr = (C.c_void_p * len(self.lattices))(*[lat._h.value for lat in self.lattices])
+        h = C.c_void_p()
+        s = L.lbm_batch_create(arr, len(self.lattices), C.byref(h))
+        self._h = h
+        if s != LBM_OK:
+            msg = L.lbm_batch_last_error(h).decode() if h.value else ""
+            if h.value:
+                L.lbm_batch_destroy(h)
+            self._h = None
+            raise LbmError(s, msg)
+
+    def _check(self, s):
+        if s != LBM_OK:
+            raise LbmError(s, load_library().lbm_batch_last_error(self._h).decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                load_library().lbm_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    def step(self, n=1):
+        self._check(load_library().lbm_batch_step(self._h, int(n)))
+
+    def tune(self, reps=10):
+        """Runs the autotuner; returns the tried shapes (dicts with fluid_ms)."""
+        out = (LbmBatchShape * 64)()
+        n = C.c_int32()
+        self._check(load_library().lbm_batch_tune(self._h, int(reps), out, 64, C.byref(n)))
+        return [out[k].as_dict() for k in range(min(n.value, 64))]
+
+    def shape(self):
+        sh = LbmBatchShape()
+        self._check(load_library().lbm_batch_get_shape(self._h, C.byref(sh)))
+        return sh.as_dict()
+
+    def set_shape(self, bulk_v, block, mode=0, per_xcd=0):
+        sh = LbmBatchShape(int(bulk_v), int(block), int(mode), int(per_xcd), 0.0)
+        self._check(load_library().lbm_batch_set_shape(self._h, C.byref(sh)))
+
+    def time_fluid(self, reps=10):
+        ms = C.c_double()
+        self._check(load_library().lbm_batch_time_fluid(self._h, int(reps), C.byref(ms)))
+        return ms.value
+
+    def set_graph(self, enable):
+        self._check(load_library().lbm_batch_set_graph(self._h, int(bool(enable))))
 
 
 def from_workload(w, precision=None, with_bodies=True):

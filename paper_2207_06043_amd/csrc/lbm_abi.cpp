@@ -95,6 +95,8 @@ struct lbm_ctx {
   bool graph_valid = false;
   hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   int64_t enq = 0;
+  std::vector<uint8_t> ncls_h;  // node classes (host copy: bulk tiles of other launch shapes)
+  uint64_t version = 0;         // bumped when bodies or the launch shape change
 };
 
 #define CHK(expr)                                                                    \
@@ -144,6 +146,26 @@ static void free_bodies(lbm_ctx* ctx) {
   ctx->bod_alloc.clear();
 }
 
+// Bulk tiles: blocks of `block` threads x V nodes holding at least one bulk
+// node.
+static std::vector<int32_t> bulk_tiles(const Grid& G, const std::vector<uint8_t>& ncls, int block, int V) {
+  const long long tnodes = (long long)block * V;
+  std::vector<int32_t> tiles;
+  for (long long t = 0; t * tnodes < G.Np; t++) {
+    bool any = false;
+    for (long long k = t * tnodes; k < std::min(G.Np, (t + 1) * tnodes) && !any; k++)
+      any = ncls[k] == CLS_BULK;
+    if (any) tiles.push_back((int32_t)t);
+  }
+  return tiles;
+}
+
+static bool shape_ok(int prec, int V, int block) {
+  const bool vok = (prec == 0 && (V == 1 || V == 2)) || (prec == 1 && (V == 1 || V == 2 || V == 4)) ||
+                   (prec == 2 && (V == 2 || V == 4 || V == 8));
+  return vok && (block == 64 || block == 128 || block == 256);
+}
+
 // ------------------------------------------------------------------ create
 extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** out) {
   if (!out) return LBM_E_INVAL;
@@ -174,15 +196,9 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   if (const char* ev = getenv("LBM_BULK_BLOCK")) ctx->bulk_block = atoi(ev);
   if (const char* ev = getenv("LBM_FLUID_SPLIT")) ctx->fluid_merged = atoi(ev) == 0;
   if (ctx->fluid_merged) ctx->rec_block = ctx->bulk_block;
-  {
-    const int pv = d->precision;
-    const bool vok = (pv == 0 && (ctx->bulk_v == 1 || ctx->bulk_v == 2)) ||
-                     (pv == 1 && (ctx->bulk_v == 1 || ctx->bulk_v == 2 || ctx->bulk_v == 4)) ||
-                     (pv == 2 && (ctx->bulk_v == 2 || ctx->bulk_v == 4 || ctx->bulk_v == 8));
-    if (!vok || (ctx->bulk_block != 64 && ctx->bulk_block != 128 && ctx->bulk_block != 256) ||
-        (ctx->rec_block != 64 && ctx->rec_block != 128 && ctx->rec_block != 256))
-      return bad("unsupported launch shape");
-  }
+  if (!shape_ok(d->precision, ctx->bulk_v, ctx->bulk_block) ||
+      (ctx->rec_block != 64 && ctx->rec_block != 128 && ctx->rec_block != 256))
+    return bad("unsupported launch shape");
   ctx->ssize = d->precision == 0 ? 8 : (d->precision == 1 ? 4 : 2);
   ctx->tau = d->tau;
   ctx->umax = d->u_max;
@@ -345,15 +361,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   std::vector<double> bcT(4 * (size_t)ctx->nrec);
   for (int r = 0; r < ctx->nrec; r++)
     for (int a = 0; a < 4; a++) bcT[(size_t)a * ctx->nrec + r] = r_bc[4 * (size_t)r + a];
-  // bulk tiles: blocks of 256 threads x V nodes holding at least one bulk node
-  const long long tnodes = (long long)ctx->bulk_block * ctx->bulk_v;
-  std::vector<int32_t> tiles;
-  for (long long t = 0; t * tnodes < G.Np; t++) {
-    bool any = false;
-    for (long long k = t * tnodes; k < std::min(G.Np, (t + 1) * tnodes) && !any; k++)
-      any = ncls[k] == CLS_BULK;
-    if (any) tiles.push_back((int32_t)t);
-  }
+  std::vector<int32_t> tiles = bulk_tiles(G, ncls, ctx->bulk_block, ctx->bulk_v);
   ctx->nbulk_blocks = (int)tiles.size();
   ctx->ntiles = (G.Np >> TILE_SHIFT) + 1;
   // device allocations
@@ -368,6 +376,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
     ctx->f[p] = (char*)ctx->f_alloc[p] + (size_t)G.guard * ctx->ssize;
   }
   CHK(upload(&ctx->ncls, ncls));
+  ctx->ncls_h = ncls;
   CHK(upload(&ctx->rec_of, rec_of));
   CHK(upload(&ctx->rec_node, r_node));
   CHK(upload(&ctx->rec_mask, r_mask));
@@ -857,6 +866,7 @@ extern "C" lbm_status lbm_add_body(lbm_ctx* ctx, const lbm_body_desc* bd, int32_
   rig.insert(rig.end(), rs, rs + 32);
   ctx->bodies.push_back(std::move(B));
   free_graphs(ctx);
+  ctx->version++;
   st = build_body_arrays(ctx, cur, Xc, Xp, Vl, rig);
   if (st) return st;
   if (body_id) *body_id = (int32_t)ctx->bodies.size() - 1;
@@ -1039,6 +1049,409 @@ extern "C" lbm_status lbm_time_fluid_kernel(lbm_ctx* ctx, int32_t n, double* avg
   }
   *avg_ms = tot / n;
   return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_launch_shape(lbm_ctx* ctx, int32_t bulk_v, int32_t block) {
+  if (!ctx) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (!shape_ok(ctx->prec, bulk_v, block)) return fail(ctx, LBM_E_INVAL, "unsupported launch shape");
+  if (bulk_v == ctx->bulk_v && block == ctx->bulk_block) return LBM_OK;
+  std::vector<int32_t> tiles = bulk_tiles(ctx->g, ctx->ncls_h, block, bulk_v);
+  // the old list may still be read by enqueued work
+  CHK(hipStreamSynchronize(ctx->stream));
+  free_graphs(ctx);
+  int32_t* old = ctx->tile_list;
+  ctx->tile_list = nullptr;
+  CHK(upload(&ctx->tile_list, tiles));
+  if (old) CHK(hipFree(old));
+  ctx->nbulk_blocks = (int)tiles.size();
+  ctx->bulk_v = bulk_v;
+  ctx->bulk_block = block;
+  if (ctx->fluid_merged) ctx->rec_block = block;
+  ctx->version++;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ batches
+struct lbm_batch {
+  std::vector<lbm_ctx*> ctx;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  int prec = 0;
+  std::string err;
+  bool broken = false;
+  // launch shape of the fluid phase
+  int V = 1, block = 64, mode = 0, per_xcd = 0;
+  // device tables for the two step parities, and the phase maps
+  BatchItem* items = nullptr;  // [2][n]
+  int2* maps = nullptr;
+  int n_ib = 0, n_all = 0, n_rec = 0, n_bulk = 0, n_mls = 0, n_body = 0;
+  int2 *m_ib = nullptr, *m_all = nullptr, *m_rec = nullptr, *m_bulk = nullptr, *m_mls = nullptr,
+       *m_body = nullptr;
+  std::vector<uint64_t> ver;  // context versions the tables were built for
+  std::vector<int> par;       // context parity relative to the batch's at that time
+  bool tables_valid = false;
+  bool use_graph = true;
+  bool graph_valid = false;
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  int64_t enq = 0;
+};
+
+#define CHKB(expr)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      b->broken = true;                                                              \
+      b->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " + #expr;  \
+      return LBM_E_HIP;                                                              \
+    }                                                                                \
+  } while (0)
+
+static lbm_status bfail(lbm_batch* b, lbm_status st, const std::string& msg) {
+  b->err = msg;
+  return st;
+}
+
+static void batch_free_graphs(lbm_batch* b) {
+  for (int k = 0; k < 3; k++)
+    if (b->gexec[k]) {
+      (void)hipGraphExecDestroy(b->gexec[k]);
+      b->gexec[k] = nullptr;
+    }
+  b->graph_valid = false;
+}
+
+// Physical block g of a one-unit-per-block launch takes logical unit
+// xcd_order(g, n): consecutive units land on the same XCD (blocks are
+// dispatched round-robin over the 8 XCDs).
+static int xcd_order(int g, int n) {
+  const int full = n & ~7;
+  if (g >= full) return g;
+  return (g & 7) * (full >> 3) + (g >> 3);
+}
+
+static lbm_status batch_build_tables(lbm_batch* b) {
+  const int n = (int)b->ctx.size();
+  std::vector<BatchItem> items(2 * (size_t)n);
+  std::vector<int2> ib, all, rec, bulk, mls, body;
+  b->ver.assign(n, 0);
+  b->par.assign(n, 0);
+  for (int i = 0; i < n; i++) {
+    lbm_ctx* c = b->ctx[i];
+    b->ver[i] = c->version;
+    b->par[i] = (int)((c->enq - b->enq) & 1);
+    const int nrb = c->nrec > 0 ? (c->nrec + b->block - 1) / b->block : 0;
+    for (int q = 0; q < 2; q++) {
+      const int p = (q + b->par[i]) & 1;
+      BatchItem& it = items[(size_t)q * n + i];
+      it.a = fluid_args(c, p);
+      if (c->nf > 0) {
+        it.b = c->bargs[p];
+        it.fxc = c->fx[p];
+        it.tfc = c->tf[p];
+        it.fxp = c->fx[p ^ 1];
+        it.tfp = c->tf[p ^ 1];
+      }
+      it.counter = counter(c, 0);
+      it.nrb = nrb;
+    }
+    for (int j = 0; j < nrb; j++) {
+      all.push_back(make_int2(i, j));
+      rec.push_back(make_int2(i, j));
+    }
+    for (int j = 0; j < c->nbulk_blocks; j++) {
+      all.push_back(make_int2(i, nrb + j));
+      bulk.push_back(make_int2(i, j));
+    }
+    if (c->nf > 0) {
+      const BodyArgs& B = c->bargs[0];
+      const int nib = B.n_marker_blocks + B.n_elem_blocks + B.n_clear_blocks + B.n_diag_blocks;
+      for (int j = 0; j < nib; j++) ib.push_back(make_int2(i, j));
+      const long long waves = (long long)(B.nf + MLS_FACES_PER_WAVE - 1) / MLS_FACES_PER_WAVE +
+                              (B.nsoft_v + MLS_VERTS_PER_WAVE - 1) / MLS_VERTS_PER_WAVE;
+      const int nm = (int)((waves * 64 + 255) / 256);
+      for (int j = 0; j < nm; j++) mls.push_back(make_int2(i, j));
+      const int nbp = B.nbody + (B.nsoft_v + 63) / 64;
+      for (int j = 0; j < nbp; j++) body.push_back(make_int2(i, j));
+    }
+  }
+  auto order = [](std::vector<int2>& v) {
+    std::vector<int2> o(v.size());
+    for (size_t g = 0; g < v.size(); g++) o[g] = v[xcd_order((int)g, (int)v.size())];
+    v.swap(o);
+  };
+  order(all);
+  order(rec);
+  if (b->per_xcd == 0) order(bulk);
+  // upload (previous tables may still be read by enqueued work)
+  CHKB(hipStreamSynchronize(b->stream));
+  batch_free_graphs(b);
+  if (b->items) CHKB(hipFree(b->items));
+  if (b->maps) CHKB(hipFree(b->maps));
+  b->items = nullptr;
+  b->maps = nullptr;
+  CHKB(hipMalloc(&b->items, sizeof(BatchItem) * items.size()));
+  CHKB(hipMemcpy(b->items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
+  std::vector<int2> m;
+  const std::vector<int2>* parts[6] = {&ib, &all, &rec, &bulk, &mls, &body};
+  for (auto* v : parts) m.insert(m.end(), v->begin(), v->end());
+  CHKB(hipMalloc(&b->maps, sizeof(int2) * std::max<size_t>(m.size(), 1)));
+  if (!m.empty()) CHKB(hipMemcpy(b->maps, m.data(), sizeof(int2) * m.size(), hipMemcpyHostToDevice));
+  int2* base = b->maps;
+  b->m_ib = base;   base += ib.size();
+  b->m_all = base;  base += all.size();
+  b->m_rec = base;  base += rec.size();
+  b->m_bulk = base; base += bulk.size();
+  b->m_mls = base;  base += mls.size();
+  b->m_body = base;
+  b->n_ib = (int)ib.size();
+  b->n_all = (int)all.size();
+  b->n_rec = (int)rec.size();
+  b->n_bulk = (int)bulk.size();
+  b->n_mls = (int)mls.size();
+  b->n_body = (int)body.size();
+  b->tables_valid = true;
+  return LBM_OK;
+}
+
+static BatchFluid batch_fluid(const lbm_batch* b) {
+  BatchFluid f{};
+  f.V = b->V;
+  f.block = b->block;
+  f.mode = b->mode;
+  f.per_xcd = b->per_xcd;
+  f.map_all = b->m_all;
+  f.n_all = b->n_all;
+  f.map_rec = b->m_rec;
+  f.n_rec = b->n_rec;
+  f.map_bulk = b->m_bulk;
+  f.n_bulk = b->n_bulk;
+  return f;
+}
+
+// One coupled step of every instance at batch parity q on stream s.
+static hipError_t batch_enqueue(lbm_batch* b, int q, hipStream_t s) {
+  hipError_t e;
+  const BatchItem* it = b->items + (size_t)q * b->ctx.size();
+  if ((e = launch_batch_ib_force(b->prec, it, b->m_ib, b->n_ib, s)) != hipSuccess) return e;
+  if ((e = launch_batch_fluid(b->prec, batch_fluid(b), it, s)) != hipSuccess) return e;
+  if ((e = launch_batch_mls_post(b->prec, it, b->m_mls, b->n_mls, s)) != hipSuccess) return e;
+  if ((e = launch_batch_body_post(it, b->m_body, b->n_body, s)) != hipSuccess) return e;
+  return launch_batch_close(it, (int)b->ctx.size(), s);
+}
+
+static lbm_status batch_ready(lbm_batch* b) {
+  if (b->broken) return LBM_E_STATE;
+  bool stale = !b->tables_valid;
+  for (size_t i = 0; i < b->ctx.size(); i++) {
+    lbm_ctx* c = b->ctx[i];
+    if (c->broken) return bfail(b, LBM_E_STATE, "a context of the batch has failed");
+    // a context given another launch shape on its own gets the batch's back:
+    // its bulk tiles must match the batched kernels' block and V
+    if (c->bulk_v != b->V || c->bulk_block != b->block) {
+      lbm_status st = lbm_set_launch_shape(c, b->V, b->block);
+      if (st) return bfail(b, st, std::string("launch shape: ") + c->err);
+    }
+    if (!stale && (c->version != b->ver[i] || (int)((c->enq - b->enq) & 1) != b->par[i])) stale = true;
+  }
+  if (stale) return batch_build_tables(b);
+  return LBM_OK;
+}
+
+static lbm_status batch_build_graphs(lbm_batch* b) {
+  batch_free_graphs(b);
+  for (int k = 0; k < 3; k++) {
+    hipGraph_t g;
+    CHKB(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    if (k < 2) e = batch_enqueue(b, k, b->cap);
+    else
+      for (int q = 0; q < GRAPH_CHUNK && e == hipSuccess; q++) e = batch_enqueue(b, q & 1, b->cap);
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    CHKB(e);
+    CHKB(e2);
+    CHKB(hipGraphInstantiate(&b->gexec[k], g, nullptr, nullptr, 0));
+    CHKB(hipGraphDestroy(g));
+  }
+  b->graph_valid = true;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, lbm_batch** out) {
+  if (!out) return LBM_E_INVAL;
+  *out = nullptr;
+  if (!ctxs || n < 1) return LBM_E_INVAL;
+  lbm_batch* b = new lbm_batch();
+  *out = b;  // handed back so that the caller can read the message
+  b->ctx.assign(ctxs, ctxs + n);
+  for (int i = 0; i < n; i++)
+    if (!ctxs[i]) return bfail(b, LBM_E_INVAL, "null context");
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < i; j++)
+      if (ctxs[i] == ctxs[j]) return bfail(b, LBM_E_INVAL, "a context appears twice");
+  lbm_ctx* c0 = ctxs[0];
+  b->stream = c0->stream;
+  b->prec = c0->prec;
+  for (int i = 0; i < n; i++) {
+    lbm_ctx* c = ctxs[i];
+    if (c->broken) return bfail(b, LBM_E_STATE, "a context has failed");
+    if (c->prec != b->prec) return bfail(b, LBM_E_INVAL, "contexts of one batch share their precision");
+    if (c->stream != b->stream) return bfail(b, LBM_E_INVAL, "contexts of one batch share their stream");
+    if (c->g.per[0]) return bfail(b, LBM_E_UNSUPPORTED, "periodic-x contexts are not batched");
+  }
+  // start from the first context's launch shape (the autotuner may change it)
+  b->V = c0->bulk_v;
+  b->block = c0->bulk_block;
+  for (int i = 0; i < n; i++) {
+    lbm_status st = lbm_set_launch_shape(ctxs[i], b->V, b->block);
+    if (st) return bfail(b, st, std::string("launch shape: ") + ctxs[i]->err);
+  }
+  CHKB(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  return batch_build_tables(b);
+}
+
+extern "C" lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  if (b->stream || b->cap) (void)hipDeviceSynchronize();
+  batch_free_graphs(b);
+  if (b->items) (void)hipFree(b->items);
+  if (b->maps) (void)hipFree(b->maps);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return LBM_OK;
+}
+
+extern "C" const char* lbm_batch_last_error(const lbm_batch* b) {
+  return b ? b->err.c_str() : "null batch";
+}
+
+extern "C" lbm_status lbm_batch_set_shape(lbm_batch* b, const lbm_batch_shape* sh) {
+  if (!b || !sh) return LBM_E_INVAL;
+  if (b->broken) return LBM_E_STATE;
+  if (!shape_ok(b->prec, sh->bulk_v, sh->block) || sh->mode < 0 || sh->mode > 1 || sh->per_xcd < 0 ||
+      sh->per_xcd > 1024 || (sh->mode == 0 && sh->per_xcd != 0))
+    return bfail(b, LBM_E_INVAL, "unsupported batch launch shape");
+  for (lbm_ctx* c : b->ctx) {
+    lbm_status st = lbm_set_launch_shape(c, sh->bulk_v, sh->block);
+    if (st) return bfail(b, st, std::string("launch shape: ") + c->err);
+  }
+  b->V = sh->bulk_v;
+  b->block = sh->block;
+  b->mode = sh->mode;
+  b->per_xcd = sh->per_xcd;
+  b->tables_valid = false;
+  return batch_ready(b);
+}
+
+extern "C" lbm_status lbm_batch_get_shape(lbm_batch* b, lbm_batch_shape* sh) {
+  if (!b || !sh) return LBM_E_INVAL;
+  sh->bulk_v = b->V;
+  sh->block = b->block;
+  sh->mode = b->mode;
+  sh->per_xcd = b->per_xcd;
+  sh->fluid_ms = 0.0;
+  return LBM_OK;
+}
+
+// Average duration of the batched fluid phase at the current step parity
+// over reps launches (after two untimed ones).  The phase only rewrites the
+// next populations and the macroscopic field, which the next step rewrites
+// again from the same inputs, so timing it leaves the run unchanged; status
+// bits it may raise are cleared afterwards.
+static lbm_status batch_time_fluid(lbm_batch* b, int reps, double* ms) {
+  lbm_status st = batch_ready(b);
+  if (st) return st;
+  const int q = (int)(b->enq & 1);
+  const BatchItem* it = b->items + (size_t)q * b->ctx.size();
+  const BatchFluid f = batch_fluid(b);
+  hipEvent_t e0, e1;
+  CHKB(hipEventCreate(&e0));
+  CHKB(hipEventCreate(&e1));
+  for (int k = 0; k < 2; k++) CHKB(launch_batch_fluid(b->prec, f, it, b->stream));
+  CHKB(hipEventRecord(e0, b->stream));
+  for (int k = 0; k < reps; k++) CHKB(launch_batch_fluid(b->prec, f, it, b->stream));
+  CHKB(hipEventRecord(e1, b->stream));
+  CHKB(hipEventSynchronize(e1));
+  float t = 0.f;
+  CHKB(hipEventElapsedTime(&t, e0, e1));
+  CHKB(hipEventDestroy(e0));
+  CHKB(hipEventDestroy(e1));
+  for (lbm_ctx* c : b->ctx)
+    CHKB(hipMemsetAsync((char*)c->flags + offsetof(DevFlags, pending), 0, sizeof(uint32_t), b->stream));
+  CHKB(hipStreamSynchronize(b->stream));
+  *ms = (double)t / reps;
+  return LBM_OK;
+}
+
+// The autotuner: times the batched fluid phase for every launch shape this
+// precision supports (V nodes per bulk thread, block size, merged or split
+// records, one block per tile or persistent bulk blocks) and keeps the
+// fastest.  Results go to out[0..min(max, count)) in the order tried.
+extern "C" lbm_status lbm_batch_tune(lbm_batch* b, int32_t reps, lbm_batch_shape* out,
+                                     int32_t max_out, int32_t* n_out) {
+  if (!b || reps < 1) return LBM_E_INVAL;
+  if (b->broken) return LBM_E_STATE;
+  std::vector<int> Vs = b->prec == 0 ? std::vector<int>{1, 2}
+                                     : (b->prec == 1 ? std::vector<int>{1, 2, 4} : std::vector<int>{2, 4, 8});
+  std::vector<lbm_batch_shape> cand;
+  for (int V : Vs)
+    for (int block : {64, 128, 256}) {
+      cand.push_back({V, block, 0, 0, 0.0});
+      cand.push_back({V, block, 1, 0, 0.0});
+      for (int px : {64, 128}) cand.push_back({V, block, 1, px, 0.0});
+    }
+  int best = -1;
+  for (size_t k = 0; k < cand.size(); k++) {
+    lbm_status st = lbm_batch_set_shape(b, &cand[k]);
+    if (st) return st;
+    st = batch_time_fluid(b, reps, &cand[k].fluid_ms);
+    if (st) return st;
+    if (best < 0 || cand[k].fluid_ms < cand[best].fluid_ms) best = (int)k;
+  }
+  lbm_status st = lbm_batch_set_shape(b, &cand[best]);
+  if (st) return st;
+  if (out)
+    for (int k = 0; k < std::min<int>(max_out, (int)cand.size()); k++) out[k] = cand[k];
+  if (n_out) *n_out = (int32_t)cand.size();
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_step(lbm_batch* b, int32_t n) {
+  if (!b || n < 0) return LBM_E_INVAL;
+  lbm_status st = batch_ready(b);
+  if (st) return st;
+  if (b->use_graph && !b->graph_valid) {
+    st = batch_build_graphs(b);
+    if (st) return st;
+  }
+  int32_t k = 0;
+  while (k < n) {
+    const int q = (int)(b->enq & 1);
+    int steps = 1;
+    if (b->use_graph && q == 0 && n - k >= GRAPH_CHUNK) {
+      CHKB(hipGraphLaunch(b->gexec[2], b->stream));
+      steps = GRAPH_CHUNK;
+    } else if (b->use_graph) {
+      CHKB(hipGraphLaunch(b->gexec[q], b->stream));
+    } else {
+      CHKB(batch_enqueue(b, q, b->stream));
+    }
+    b->enq += steps;
+    for (lbm_ctx* c : b->ctx) c->enq += steps;
+    k += steps;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t enable) {
+  if (!b) return LBM_E_INVAL;
+  b->use_graph = enable != 0;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_time_fluid(lbm_batch* b, int32_t reps, double* avg_ms) {
+  if (!b || reps < 1 || !avg_ms) return LBM_E_INVAL;
+  return batch_time_fluid(b, reps, avg_ms);
 }
 
 // ----------------------------------------------------------------- outputs

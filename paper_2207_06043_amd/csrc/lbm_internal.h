@@ -27,6 +27,10 @@ constexpr int TILE_SHIFT = 10;  // force-flag granularity: 1024 nodes
 constexpr int MARKERS_PER_BLOCK = 64;
 constexpr int BOX_CELLS = 729;
 
+// Work per wave of the probe / vertex-velocity launch: 8 faces (4 lanes per
+// MLS point, outer and inner probe) or 16 vertices.
+constexpr int MLS_FACES_PER_WAVE = 8, MLS_VERTS_PER_WAVE = 16;
+
 // Vertex incidence table widths (largest vertex valence accepted: 10).
 constexpr int VT_E = 10, VT_H = 20, VT_F = 10, VT_SLOTS = VT_E + VT_H + VT_F;
 
@@ -125,6 +129,20 @@ struct BodyArgs {
   double nu, umax;
 };
 
+// One instance of a batch: the arguments its own launches take, for one
+// step parity (lbm_abi.cpp keeps two tables).
+struct BatchItem {
+  FluidArgs a;
+  BodyArgs b;
+  long long* fxc;         // force field written this step
+  uint8_t* tfc;           // its tile flags
+  long long* fxp;         // previous step's force field (cleared this step)
+  uint8_t* tfp;
+  unsigned int* counter;  // diagnostics block counter
+  int nrb;                // record blocks ahead of the bulk tiles in the fluid phase
+  int pad;
+};
+
 // Launchers (lbm_kernels.hip)
 hipError_t launch_init(int prec, const Grid& g, void* f, const uint8_t* ncls, const double* rho,
                        const double* u, hipStream_t s);
@@ -153,5 +171,25 @@ hipError_t launch_spread_api(const Grid& g, const uint8_t* ncls, long long n, co
                              const double* F, const double* c, long long* fx, DevFlags* flags,
                              hipStream_t s);
 hipError_t launch_flush_fx(const Grid& g, long long* fx, double* fib, hipStream_t s);
+
+// Launch shape of the batched fluid phase: blocks of `block` threads, V
+// nodes per bulk thread; mode 0 merged (map_all), 1 split (map_rec, then
+// map_bulk); per_xcd > 0 runs the bulk tiles persistently with per_xcd
+// blocks per XCD.
+struct BatchFluid {
+  int V, block, mode, per_xcd;
+  const int2* map_all; int n_all;
+  const int2* map_rec; int n_rec;
+  const int2* map_bulk; int n_bulk;
+};
+
+// Batched phases: n blocks (units) each, map[g] = (instance, unit).
+hipError_t launch_batch_ib_force(int prec, const BatchItem* items, const int2* map, int n,
+                                 hipStream_t s);
+hipError_t launch_batch_fluid(int prec, const BatchFluid& f, const BatchItem* items, hipStream_t s);
+hipError_t launch_batch_mls_post(int prec, const BatchItem* items, const int2* map, int n,
+                                 hipStream_t s);
+hipError_t launch_batch_body_post(const BatchItem* items, const int2* map, int n, hipStream_t s);
+hipError_t launch_batch_close(const BatchItem* items, int n, hipStream_t s);
 
 }  // namespace lbm

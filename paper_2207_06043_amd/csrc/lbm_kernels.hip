@@ -599,15 +599,20 @@ __global__ __launch_bounds__(256) void k_fluid_rec(FluidArgs a) {
 // no fork and join between two streams.  Both parts use blocks of the same
 // size.
 template <class S, int V, bool PERX>
+__device__ __forceinline__ void fluid_unit(const FluidArgs& a, int nrb, int u) {
+  if (u < nrb) {
+    const int r = u * blockDim.x + threadIdx.x;
+    if (r < a.nrec) fluid_record_thread<S>(a, r);
+  } else {
+    fluid_bulk<S, V, PERX>(a, u - nrb);
+  }
+}
+
+template <class S, int V, bool PERX>
 __global__ __launch_bounds__(256) void k_fluid_all(FluidArgs a, int nrb) {
   if (a.flags->stop) return;
   const int b = blockIdx.x;
-  if (b < nrb) {
-    const int r = xcd_remap(b, nrb) * blockDim.x + threadIdx.x;
-    if (r < a.nrec) fluid_record_thread<S>(a, r);
-  } else {
-    fluid_bulk<S, V, PERX>(a, xcd_remap(b - nrb, a.nbulk_blocks));
-  }
+  fluid_unit<S, V, PERX>(a, nrb, b < nrb ? xcd_remap(b, nrb) : nrb + xcd_remap(b - nrb, a.nbulk_blocks));
 }
 
 // Closes a fluid-only step (one thread).
@@ -1388,11 +1393,9 @@ __device__ void membrane_element(const BodyArgs& b, int idx) {
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long long* fxc,
-                                                  uint8_t* tfc, long long* fxp, uint8_t* tfp,
-                                                  unsigned int* counter) {
-  if (a.flags->stop) return;
-  const int blk = blockIdx.x;
+__device__ __forceinline__ void ib_force_block(const FluidArgs& a, const BodyArgs& b, long long* fxc,
+                                               uint8_t* tfc, long long* fxp, uint8_t* tfp,
+                                               unsigned int* counter, int blk) {
   const int nmk = b.n_marker_blocks, nel = b.n_elem_blocks, ncl = b.n_clear_blocks;
   if (blk < nmk) {
     marker_block<S>(a, b, blk, fxc, tfc);
@@ -1410,6 +1413,14 @@ __global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long 
       if (threadIdx.x == 0) *counter = 0u;
     }
   }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long long* fxc,
+                                                  uint8_t* tfc, long long* fxp, uint8_t* tfp,
+                                                  unsigned int* counter) {
+  if (a.flags->stop) return;
+  ib_force_block<S>(a, b, fxc, tfc, fxp, tfp, counter, blockIdx.x);
 }
 
 // Diagnostics of the current positions only (set-up and synchronisation
@@ -1522,12 +1533,10 @@ __device__ __forceinline__ void fit_point(const FluidArgs& a, int sub, double px
 // Face waves take 8 faces: the quad of lanes 4f..4f+3 (f < 8) fits the probe
 // outside face f, lanes 32 + 4f.. the probe inside; vertex waves take 16
 // soft vertices, one quad each.
-constexpr int MLS_FACES_PER_WAVE = 8, MLS_VERTS_PER_WAVE = 16;
 
 template <class S>
-__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
-  if (a.flags->stop) return;
-  const int gw = (blockIdx.x * 256 + threadIdx.x) >> 6;
+__device__ __forceinline__ void mls_post_block(const FluidArgs& a, const BodyArgs& b, int blk) {
+  const int gw = (blk * 256 + threadIdx.x) >> 6;
   const int l = threadIdx.x & 63, sub = l & 3;
   const int nfw = (b.nf + MLS_FACES_PER_WAVE - 1) / MLS_FACES_PER_WAVE;
   if (gw < nfw) {
@@ -1626,6 +1635,12 @@ __global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
     b.u0v[3 * v + 1] = U[1];
     b.u0v[3 * v + 2] = U[2];
   }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
+  if (a.flags->stop) return;
+  mls_post_block<S>(a, b, blockIdx.x);
 }
 
 // ----------------------------------------------------------- k_body_post
@@ -1781,15 +1796,110 @@ __device__ void soft_vertex(const BodyArgs& b, int idx) {
 
 // Last IB launch of a coupled step: rigid blocks, then soft-vertex blocks
 // (one vertex per thread, 64-thread blocks); k_close follows.
-__global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags) {
-  if (flags->stop) return;
-  const int blk = blockIdx.x;
+__device__ __forceinline__ void body_post_block(const BodyArgs& b, int blk) {
   if (blk < b.nbody) {
     if (b.b_rigid[blk]) rigid_block(b, blk);
   } else {
     const int idx = (blk - b.nbody) * (int)blockDim.x + threadIdx.x;
     if (idx < b.nsoft_v) soft_vertex(b, idx);
   }
+}
+
+__global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags) {
+  if (flags->stop) return;
+  body_post_block(b, blockIdx.x);
+}
+
+// ------------------------------------------------------------ batches
+// A batch advances independent contexts together: each phase of a coupled
+// step is one launch over the work units of all of them.  Block g of a
+// phase takes unit map[g] = (instance, block of that instance's own launch);
+// the instance's arguments are read from a device table (per step parity).
+template <class S>
+__global__ __launch_bounds__(256) void kb_ib_force(const BatchItem* items, const int2* map) {
+  const int2 m = map[blockIdx.x];
+  const BatchItem& it = items[m.x];
+  const FluidArgs a = it.a;
+  if (a.flags->stop) return;
+  const BodyArgs b = it.b;
+  ib_force_block<S>(a, b, it.fxc, it.tfc, it.fxp, it.tfp, it.counter, m.y);
+}
+
+// Fluid phase.  Merged form: records and bulk tiles of every instance in
+// one launch (unit = record block or bulk tile).  Split form: the record
+// blocks of all instances, then the bulk tiles of all instances, each
+// kernel with its own register budget (the bulk kernel keeps the occupancy
+// that the bandwidth-bound part needs).  The host orders every map so that
+// each XCD takes a contiguous run of units (whole instances where possible).
+template <class S, int V, bool PERX>
+__global__ __launch_bounds__(256) void kb_fluid_all(const BatchItem* items, const int2* map) {
+  const int2 m = map[blockIdx.x];
+  const FluidArgs a = items[m.x].a;
+  if (a.flags->stop) return;
+  fluid_unit<S, V, PERX>(a, items[m.x].nrb, m.y);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void kb_fluid_rec(const BatchItem* items, const int2* map) {
+  const int2 m = map[blockIdx.x];
+  const FluidArgs a = items[m.x].a;
+  if (a.flags->stop) return;
+  const int r = m.y * blockDim.x + threadIdx.x;
+  if (r < a.nrec) fluid_record_thread<S>(a, r);
+}
+
+// Bulk tiles; per_xcd > 0 is the persistent form: per_xcd blocks on each of
+// the 8 XCDs walk the XCD's contiguous share of the units in strides of
+// per_xcd.
+template <class S, int V, bool PERX>
+__global__ __launch_bounds__(256) void kb_fluid_bulk(const BatchItem* items, const int2* map,
+                                                     int nunits, int per_xcd) {
+  if (per_xcd == 0) {
+    const int2 m = map[blockIdx.x];
+    const FluidArgs a = items[m.x].a;
+    if (a.flags->stop) return;
+    fluid_bulk<S, V, PERX>(a, m.y);
+    return;
+  }
+  const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int u0 = (int)(((long long)nunits * x) >> 3), u1 = (int)(((long long)nunits * (x + 1)) >> 3);
+  for (int u = u0 + j; u < u1; u += per_xcd) {
+    const int2 m = map[u];
+    const FluidArgs a = items[m.x].a;
+    if (a.flags->stop) continue;
+    fluid_bulk<S, V, PERX>(a, m.y);
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void kb_mls_post(const BatchItem* items, const int2* map) {
+  const int2 m = map[blockIdx.x];
+  const BatchItem& it = items[m.x];
+  const FluidArgs a = it.a;
+  if (a.flags->stop) return;
+  const BodyArgs b = it.b;
+  mls_post_block<S>(a, b, m.y);
+}
+
+__global__ __launch_bounds__(256) void kb_body_post(const BatchItem* items, const int2* map) {
+  const int2 m = map[blockIdx.x];
+  const BatchItem& it = items[m.x];
+  if (it.a.flags->stop) return;
+  const BodyArgs b = it.b;
+  body_post_block(b, m.y);
+}
+
+// Closes a step of every instance (one thread each).
+__global__ void kb_close(const BatchItem* items, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  DevFlags* flags = items[i].a.flags;
+  if (flags->stop) return;
+  const unsigned int pend =
+      __hip_atomic_load(&flags->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  flags->steps_done += 1;
+  flags->stop |= pend;
+  flags->pending = 0u;
 }
 
 // ------------------------------------------------------------ API kernels
@@ -2019,6 +2129,68 @@ hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s) {
   // small blocks: the vertex gathers are spread over many CUs' load pipelines
   const unsigned grid = (unsigned)b.nbody + cdiv(b.nsoft_v, 64);
   k_body_post<<<grid, 64, 0, s>>>(b, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_ib_force(int prec, const BatchItem* items, const int2* map, int n,
+                                 hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  switch (prec) {
+    case 0: kb_ib_force<double><<<n, 256, 0, s>>>(items, map); break;
+    case 1: kb_ib_force<float><<<n, 256, 0, s>>>(items, map); break;
+    default: kb_ib_force<_Float16><<<n, 256, 0, s>>>(items, map); break;
+  }
+  return hipGetLastError();
+}
+
+template <class S, int V>
+static void batch_fluid_launch(const BatchFluid& f, const BatchItem* items, hipStream_t s) {
+  if (f.mode == 0) {
+    if (f.n_all) kb_fluid_all<S, V, false><<<f.n_all, f.block, 0, s>>>(items, f.map_all);
+    return;
+  }
+  if (f.n_rec) kb_fluid_rec<S><<<f.n_rec, f.block, 0, s>>>(items, f.map_rec);
+  if (f.n_bulk) {
+    const unsigned grid = f.per_xcd > 0 ? 8u * f.per_xcd : (unsigned)f.n_bulk;
+    kb_fluid_bulk<S, V, false><<<grid, f.block, 0, s>>>(items, f.map_bulk, f.n_bulk, f.per_xcd);
+  }
+}
+
+hipError_t launch_batch_fluid(int prec, const BatchFluid& f, const BatchItem* items, hipStream_t s) {
+  switch (prec * 16 + f.V) {
+    case 0 * 16 + 1: batch_fluid_launch<double, 1>(f, items, s); break;
+    case 0 * 16 + 2: batch_fluid_launch<double, 2>(f, items, s); break;
+    case 1 * 16 + 1: batch_fluid_launch<float, 1>(f, items, s); break;
+    case 1 * 16 + 2: batch_fluid_launch<float, 2>(f, items, s); break;
+    case 1 * 16 + 4: batch_fluid_launch<float, 4>(f, items, s); break;
+    case 2 * 16 + 2: batch_fluid_launch<_Float16, 2>(f, items, s); break;
+    case 2 * 16 + 4: batch_fluid_launch<_Float16, 4>(f, items, s); break;
+    case 2 * 16 + 8: batch_fluid_launch<_Float16, 8>(f, items, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_mls_post(int prec, const BatchItem* items, const int2* map, int n,
+                                 hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  switch (prec) {
+    case 0: kb_mls_post<double><<<n, 256, 0, s>>>(items, map); break;
+    case 1: kb_mls_post<float><<<n, 256, 0, s>>>(items, map); break;
+    default: kb_mls_post<_Float16><<<n, 256, 0, s>>>(items, map); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_body_post(const BatchItem* items, const int2* map, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  kb_body_post<<<n, 64, 0, s>>>(items, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_close(const BatchItem* items, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  kb_close<<<cdiv(n, 64), 64, 0, s>>>(items, n);
   return hipGetLastError();
 }
 

@@ -73,25 +73,57 @@ def bifurcation_capsule(seed=0, precision="f32", steps=5000, nx=256, ny=128, nz=
                     meta={"offset": dy, "seed": seed})
 
 
+# Stability guard of the capsule stiffness.  The explicit vertex update
+# (Verlet predictor, BDF2 velocity, corrector) diverges once the largest
+# eigenvalue of the membrane stiffness over the vertex mass passes about
+# 0.8 (the 2562-vertex capsule of the Y-bifurcation is stable at 0.75 and
+# fails at 0.85).  The largest stretching eigenvalue of the icosphere spring
+# network at rest is 5.2 k_s0 for every subdivision used here, so a capsule
+# is only given a capillary number for which 5.2 k_s0 / m_v <= 0.6.
+STRETCH_EIG = 5.2
+STIFFNESS_LIMIT = 0.6
+
+
+def _mesh_volume(X, F):
+    a, b, c = X[F[:, 0]], X[F[:, 1]], X[F[:, 2]]
+    return float(np.einsum("ij,ij->i", a, np.cross(b, c)).sum() / 6.0)
+
+
+def ca_floor(X, F, nu, u_ref, rho_ratio):
+    """Smallest capillary number Ca = nu u_ref / k_s0 (fluid density 1) that
+    keeps 5.2 k_s0 / m_v <= 0.6, with m_v = rho_ratio V / n_v the vertex
+    mass of the mesh (X, F)."""
+    m_v = rho_ratio * _mesh_volume(X, F) / len(X)
+    return nu * u_ref / (STIFFNESS_LIMIT * m_v / STRETCH_EIG)
+
+
 def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_choices,
-                    x_inlet_clear, face_clear, u_max, max_tries=100000, tries_per_capsule=2000):
+                    x_inlet_clear, face_clear, u_max, nu, eb=1e-4, max_tries=100000,
+                    tries_per_capsule=2000):
     """Rejection sampling of non-overlapping capsules inside the fluid.
-    Draw order per capsule: occlusion ratio, log10 Ca, mesh choice, then
+    Draw order per capsule: occlusion ratio, mesh choice, log10 Ca uniform
+    on [log10 max(ca_lo, ca_floor), log10 ca_hi] (ca_floor: the stability
+    guard above; a capsule whose floor exceeds ca_hi is drawn again), then
     centre candidates (x, y, z) until one fits: wall clearance >= r_p + 1.5
     (signed distance), centre distance >= r_i + r_j + 2 to the capsules
     already placed, at least x_inlet_clear from the inlet and face_clear from
     the other faces.  A capsule that finds no centre within
-    tries_per_capsule candidates has its radius (and Ca, mesh) drawn again
-    from the same stream; the redraws are counted.  Returns (bodies,
-    redraws); stops early once max_tries candidates have been spent."""
+    tries_per_capsule candidates is drawn again (occlusion, mesh, Ca) from
+    the same stream; the redraws are counted.  Returns (bodies, redraws);
+    stops early once max_tries candidates have been spent."""
     nx, ny, nz = box
     bodies, centres, radii = [], [], []
     tries = redraws = 0
     while len(bodies) < n and tries < max_tries:
         occ = rng.uniform(occl_lo, occl_hi)
-        ca = 10.0 ** rng.uniform(np.log10(ca_lo), np.log10(ca_hi))
         sub = subdiv_choices[rng.integers(len(subdiv_choices))]
         rp = occ * D / 2.0
+        Xu, Fu = icosphere(sub, rp, (0.0, 0.0, 0.0), tilt=True)
+        lo = max(ca_lo, ca_floor(Xu, Fu, nu, u_max, 1.1))
+        if lo > ca_hi:
+            redraws += 1
+            continue
+        ca = 10.0 ** rng.uniform(np.log10(lo), np.log10(ca_hi))
         placed = None
         for _ in range(tries_per_capsule):
             if tries >= max_tries:
@@ -109,11 +141,11 @@ def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_
         if placed is None:
             redraws += 1
             continue
-        X, F = icosphere(sub, rp, placed, tilt=True)
+        X, F = Xu + placed, Fu
         if not off_switch_planes(X, F):
             redraws += 1
             continue
-        bodies.append(Body(X, F, rigid=False, ca=ca, eb=0.001, rho_ratio=1.1, r_ref=rp, u_ref=u_max))
+        bodies.append(Body(X, F, rigid=False, ca=ca, eb=eb, rho_ratio=1.1, r_ref=rp, u_ref=u_max))
         centres.append(placed)
         radii.append(rp)
     return bodies, redraws
@@ -122,8 +154,10 @@ def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_
 def precision_form(seed=0, precision="f16s", steps=2000, n_capsules=16):
     """Bifurcation with a 90 degree semi-aperture on 512x256x64, D = 48,
     fillet 4, Re = 10 with tau = 0.7, 16 deformable capsules (2562 vertices)
-    with occlusion ratio ~ U[0.3, 0.8] and Ca log-uniform in [1e-3, 1e-1],
-    placed without overlap at least 1 D from the inlet and the outlet faces."""
+    with occlusion ratio ~ U[0.3, 0.8] and Ca log-uniform in [1e-3, 1e-1]
+    above the stability floor ``ca_floor`` (which only binds for the smaller
+    capsules), Eb = 1e-4 as for the single capsule, placed without overlap at
+    least 1 D from the inlet and the outlet faces."""
     rng = np.random.default_rng(seed)
     tau = 0.7
     nu = (tau - 0.5) / 3.0
@@ -131,34 +165,54 @@ def precision_form(seed=0, precision="f16s", steps=2000, n_capsules=16):
     u_max = 10.0 * nu / D
     dom = bifurcation(512, 256, 64, D, 0.8, 90.0, 4.0, u_max=u_max)
     bodies, redraws = _place_capsules(rng, dom.meta["sdf"], (512, 256, 64), D, n_capsules,
-                                      0.3, 0.8, 1e-3, 1e-1, (4,), D, D, u_max)
+                                      0.3, 0.8, 1e-3, 1e-1, (4,), D, D, u_max, nu)
     return Workload("precision_form", dom, bodies, tau, u_max, precision, steps,
                     meta={"seed": seed, "radius_redraws": redraws})
 
 
-def batch_instances(seed=0, n_instances=64):
-    """Independent bifurcation instances of uneven size: per instance, in
-    draw order, D from {16, 24, 32, 48}, semi-aperture U[30, 120] degrees,
-    fillet U[0, 0.25 D], then 1-4 capsules (occlusion U[0.3, 0.9], Ca
-    log-uniform [1e-3, 1e-1], 642 or 2562 vertices) on an 8D x 4D x 1.25D
-    grid, Re = 10, tau = 0.7."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for k in range(n_instances):
-        D = float(rng.choice([16, 24, 32, 48]))
-        th = rng.uniform(30.0, 120.0)
-        fil = rng.uniform(0.0, 0.25 * D)
-        ncap = int(rng.integers(1, 5))
-        nx, ny, nz = int(8 * D), int(4 * D), int(1.25 * D)
-        tau = 0.7
-        nu = (tau - 0.5) / 3.0
-        u_max = 10.0 * nu / D
-        dom = bifurcation(nx, ny, nz, D, 0.8, th, fil, x_junction=4 * D, u_max=u_max)
-        bodies, redraws = _place_capsules(rng, dom.meta["sdf"], (nx, ny, nz), D, ncap, 0.3, 0.9,
-                                          1e-3, 1e-1, (3, 4), D, 0.5 * D, u_max)
-        out.append(Workload(f"batch_{k}", dom, bodies, tau, u_max, "f32", 1000,
-                            meta={"D": D, "theta": th, "fillet": fil, "radius_redraws": redraws}))
-    return out
+def batch_instance(seed, k):
+    """Instance k of the batching form: the draws come from its own stream
+    numpy.random.default_rng([seed, k]), in the order D from {16, 24, 32,
+    48}, semi-aperture U[30, 120] degrees, fillet U[0, 0.25 D], the number of
+    capsules (1-4), then the capsules (occlusion U[0.3, 0.9], 642 or 2562
+    vertices, Ca log-uniform in [1e-3, 1e-1] above the stability floor
+    ``ca_floor``, Eb = 1e-4) on an 8D x 4D x 1.25D grid, Re = 10, tau = 0.7.
+    The nodes on the box edges are solid (a daughter tube at a small angle
+    leaves through the edge x = nx - 1, y = 0 or ny - 1)."""
+    rng = np.random.default_rng([seed, k])
+    D = float(rng.choice([16, 24, 32, 48]))
+    th = rng.uniform(30.0, 120.0)
+    fil = rng.uniform(0.0, 0.25 * D)
+    ncap = int(rng.integers(1, 5))
+    nx, ny, nz = int(8 * D), int(4 * D), int(1.25 * D)
+    tau = 0.7
+    nu = (tau - 0.5) / 3.0
+    u_max = 10.0 * nu / D
+    dom = bifurcation(nx, ny, nz, D, 0.8, th, fil, x_junction=4 * D, u_max=u_max,
+                      edge_band=0.5)
+    bodies, redraws = _place_capsules(rng, dom.meta["sdf"], (nx, ny, nz), D, ncap, 0.3, 0.9,
+                                      1e-3, 1e-1, (3, 4), D, 0.5 * D, u_max, nu)
+    return Workload(f"batch_{k}", dom, bodies, tau, u_max, "f32", 1000,
+                    meta={"D": D, "theta": th, "fillet": fil, "seed": seed, "index": k,
+                          "radius_redraws": redraws})
+
+
+def _batch_instance_no_sdf(seed, k):
+    w = batch_instance(seed, k)
+    w.domain.meta["sdf"] = None  # a closure: not sent between processes
+    return w
+
+
+def batch_instances(seed=0, n_instances=64, workers=1):
+    """The batching form: instances 0 .. n_instances-1 of ``batch_instance``
+    (each from its own random stream, so any prefix is the same and the
+    instances can be generated in parallel by ``workers`` processes; those
+    come back without the signed-distance function in domain.meta)."""
+    if workers <= 1:
+        return [batch_instance(seed, k) for k in range(n_instances)]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_batch_instance_no_sdf, [seed] * n_instances, range(n_instances)))
 
 
 def periodic_r0(n=256, precision="f32", steps=100):

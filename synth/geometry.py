@@ -240,8 +240,22 @@ def bifurcation_sdf(params):
     return sdf
 
 
+def _edge_band_sdf(nx, ny, nz, band):
+    """band - (distance to the nearest box edge), the distance to an edge
+    being the larger of the distances to its two faces: positive (solid)
+    within ``band`` of any of the twelve edges of the box."""
+    def sdf(p):
+        p = np.atleast_2d(p)
+        dx = np.minimum(p[:, 0], nx - 1 - p[:, 0])
+        dy = np.minimum(p[:, 1], ny - 1 - p[:, 1])
+        dz = np.minimum(p[:, 2], nz - 1 - p[:, 2])
+        d = np.minimum(np.minimum(np.maximum(dx, dy), np.maximum(dx, dz)), np.maximum(dy, dz))
+        return band - d
+    return sdf
+
+
 def bifurcation(nx, ny, nz, D, daughter_ratio=0.8, theta_deg=60.0, fillet=4.0,
-                x_junction=None, u_max=0.0, init="rest"):
+                x_junction=None, u_max=0.0, init="rest", edge_band=0.0):
     """Symmetric Y-bifurcation: main tube of diameter D along x centred at
     (y, z) = ((ny-1)/2, (nz-1)/2), junction at x = x_junction (default nx/2),
     daughters of diameter daughter_ratio*D at the semi-aperture angle
@@ -249,13 +263,21 @@ def bifurcation(nx, ny, nz, D, daughter_ratio=0.8, theta_deg=60.0, fillet=4.0,
 
     x = 0 is a velocity inlet with the parabolic profile of peak u_max; every
     other fluid node on the box boundary is a density outlet (rho = 1).
-    ``init='rest'`` starts from rho = 1, u = 0.
+    ``init='rest'`` starts from rho = 1, u = 0.  ``edge_band > 0`` makes the
+    nodes within that distance of a box edge solid (a daughter tube leaving
+    through a box edge would otherwise put open-boundary nodes on two faces);
+    the wall there is a plane of the band, with its own link fractions.
     """
     yc, zc = (ny - 1) / 2.0, (nz - 1) / 2.0
     xj = nx / 2.0 if x_junction is None else x_junction
     params = {"R": D / 2.0, "Rd": daughter_ratio * D / 2.0, "J": (xj, yc, zc),
               "theta": np.deg2rad(theta_deg), "fillet": fillet}
     sdf = bifurcation_sdf(params)
+    if edge_band > 0.0:
+        tube, band = sdf, _edge_band_sdf(nx, ny, nz, edge_band)
+
+        def sdf(p):
+            return np.maximum(tube(p), band(p))
     x, y, z = _coords(nx, ny, nz)
     pts = np.stack([x, y, z], axis=1)
     solid = sdf(pts) >= 0.0

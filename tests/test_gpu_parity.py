@@ -4,8 +4,12 @@ the same seeded inputs.
 Error measures (relative to the oracle):
   e_u = max |u_gpu - u_orc| / max |u_orc|       (all non-solid nodes)
   e_x = max |x_gpu - x_orc| / max |x_orc^N - x_orc^0|   (vertex positions)
-Bounds: 1e-12 for the FP64 path, 2e-5 for the FP32 path.
+Bounds: 1e-12 for the FP64 path, 2e-5 for the FP32 path; where a case
+amplifies rounding beyond that (stated at the test), the FP64 bound is a
+multiple of how far the oracle's own measurement builds move the result.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -17,6 +21,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 2e-5}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _say(msg):
@@ -44,7 +49,7 @@ def _run_pair(P, w, precision, steps, bodies=True):
     return lat, orc, st, so
 
 
-def _compare(lat, orc, w, tol, bodies=True):
+def _compare(lat, orc, w, tol, bodies=True, tol_x=None):
     rho_g, u_g = (t.cpu().numpy() for t in lat.fields())
     rho_o, u_o = orc.fields()
     fl = w.domain.node_type != 1
@@ -63,7 +68,7 @@ def _compare(lat, orc, w, tol, bodies=True):
     assert e_u <= tol, out
     assert e_r <= tol * 10, out
     if bodies and w.bodies:
-        assert out["e_x"] <= tol, out
+        assert out["e_x"] <= (tol if tol_x is None else tol_x), out
     return out
 
 
@@ -127,13 +132,22 @@ def test_bifurcation_two_soft_capsules(lib, precision):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_facing_bodies_repel(lib, precision, rigid):
     """Two bodies with one centroid pair half a spacing apart in fluid at
-    rest: the repulsion is what sets them moving."""
+    rest: the repulsion is what sets them moving.  The soft pair stirs the
+    fluid only weakly while its membrane amplifies rounding; the FP64 bound
+    is the stated one or ten times what the oracle's own measurement builds
+    (fused multiply-adds, reordered sums) move the result, if larger."""
     w = synth.facing_pair(0.5, subdiv=2, rigid=rigid, fixed=False, precision=precision)
+    with open(os.path.join(GOLDEN, "facing_pair_spread.json")) as f:
+        spread = json.load(f)["spread"]
+    kind = "rigid" if rigid else "soft"
+    env = max(spread[f"{kind}_fma"][0], spread[f"{kind}_reassoc"][0])
+    tol = max(TOL[precision], 10.0 * env) if precision == "f64" else TOL[precision]
     lat, orc, st, so = _run_pair(lib, w, precision, 20)
     assert st == 0 and so == 0
     x0 = orc.body(0)[0]
     assert x0[:, 0].mean() < w.bodies[0].x[:, 0].mean()   # pushed apart along x
-    _compare(lat, orc, w, TOL[precision])
+    out = _compare(lat, orc, w, tol, tol_x=TOL[precision])
+    _say(f"    bound e_u {tol:.2e}")
 
 
 def test_force_field_matches(lib):
