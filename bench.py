@@ -9,6 +9,12 @@ captured HIP graph.  Prints one JSON line.
 
 Metric: lattice updates per second of the full coupled step, counted on the
 fluid (non-solid) nodes; the box-node rate is reported alongside.
+
+Other workloads: ``--workload precision_form`` (512x256x64 bifurcation with
+16 capsules, FP16 storage by default), ``--workload batch_instances`` (the
+batching form: 64 bifurcations of uneven size advanced together, tuned, and
+compared with the same instances stepped one by one), and the bandwidth
+workloads ``periodic_r0`` and ``pipe_r1``.
 """
 from __future__ import annotations
 
@@ -118,7 +124,13 @@ def build_workload(name, precision):
         return synth.periodic_r0(precision=precision)
     if name == "pipe_r1":
         return synth.pipe_r1(precision=precision)
+    if name == "precision_form":
+        return synth.precision_form(precision=precision)
     raise SystemExit(f"unknown workload {name}")
+
+
+def default_precision(workload):
+    return {"pipe_sphere": "f64", "precision_form": "f16s"}.get(workload, "f32")
 
 
 def cpu_baseline(w, target_s=15.0):
@@ -142,6 +154,127 @@ def cpu_baseline(w, target_s=15.0):
                       f"FP64, {dt:.1f} s (+{setup:.1f} s setup), lattice updates counted on fluid nodes"}
 
 
+def cpu_baseline_batch(ws, target_s=15.0):
+    """The FP64 oracle on a seeded subset (the first 8 instances), each for
+    an equal share of the time budget."""
+    import oracle
+    sub = ws[:8]
+    tot_updates, tot_time, steps = 0, 0.0, []
+    for w in sub:
+        sim = oracle.from_workload(w)
+        t = time.time()
+        sim.step(1)
+        per = time.time() - t
+        n = max(1, int(target_s / len(sub) / max(per, 1e-6)))
+        t = time.time()
+        sim.step(n)
+        tot_time += time.time() - t
+        tot_updates += w.domain.n_fluid * n
+        steps.append(n)
+        del sim
+    return {"value": round(tot_updates / tot_time / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.lib().orc_threads(), "kind": "oracle",
+            "sample": f"instances 0-{len(sub) - 1} of the batching form, {steps} coupled steps each "
+                      f"(after 1 untimed), FP64, {tot_time:.1f} s, lattice updates counted on fluid nodes"}
+
+
+def run_batch(args):
+    """The batching form: the instances advance together (one launch per
+    phase, graph replay) after the autotuner has picked the fluid launch
+    shape; then the same instances are stepped one by one with their own
+    step for the comparison."""
+    import torch
+    import paper_2207_06043_amd as P
+    import synth
+    precision = args.precision or "f32"
+    ws = synth.batch_instances(n_instances=args.instances, workers=min(16, os.cpu_count() or 1))
+    for w in ws:
+        w.precision = precision
+    torch.cuda.set_device(0)
+    lats = [P.from_workload(w, precision=precision) for w in ws]
+    infos = [lat.info() for lat in lats]
+    batch = P.Batch(lats)
+    tried = batch.tune(reps=args.tune_reps)
+    shape = batch.shape()
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bad = [k for k, lat in enumerate(lats) if lat.sync(raise_on_stop=False) != P.LBM_OK]
+    if bad:
+        print(json.dumps({"metric": METRIC, "error": f"instances {bad} stopped inside the timed "
+                          "region: throughput invalid"}))
+        sys.exit(1)
+    elapsed = t1 - t0
+    n_fluid = sum(i["n_fluid"] for i in infos)
+    n_box = sum(i["n_nodes"] for i in infos)
+    value = n_fluid * args.steps / elapsed / 1e6
+    avg_ms = batch.time_fluid(args.kernel_reps)
+    bytes_alg = sum(i["bytes_per_step_alg"] for i in infos)
+    achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
+    # the same instances, one by one, with their own step
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for lat in lats:
+        lat.step(args.plain_steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    plain = n_fluid * args.plain_steps / (t3 - t2) / 1e6
+    bad = [k for k, lat in enumerate(lats) if lat.sync(raise_on_stop=False) != P.LBM_OK]
+    fluid_kernel = ("kb_fluid_all (records and bulk tiles of all instances in one launch)"
+                    if shape["mode"] == 0 else
+                    "kb_fluid_rec then kb_fluid_bulk (records, then bulk tiles, of all instances)"
+                    + (f", persistent bulk grid of {shape['per_xcd']} blocks per XCD"
+                       if shape["per_xcd"] else ""))
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": precision,
+        "data": "synthetic",
+        "config": {
+            "workload": "batch_instances",
+            "instances": len(ws),
+            "fluid_nodes": n_fluid,
+            "box_nodes": n_box,
+            "bodies": sum(len(w.bodies) for w in ws),
+            "vertices": sum(i["n_vertices"] for i in infos),
+            "lups_counted_on": "fluid nodes",
+            "mlups_box": round(n_box * args.steps / elapsed / 1e6, 2),
+            "tuned_shape": shape,
+            "shapes_tried": len(tried),
+            "plain_one_by_one_mlups": round(plain, 2),
+            "plain_steps_each": args.plain_steps,
+            "batched_vs_plain": round(value / plain, 3),
+            "plain_status_ok": not bad,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": fluid_kernel,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("batch_instances", precision),
+            "bytes_per_launch_alg": bytes_alg,
+            "avg_launch_us": round(avg_ms * 1e3, 3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(ws, args.cpu_seconds)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +286,12 @@ def main():
                     help="particle-free steps before the capsule is released (untimed)")
     ap.add_argument("--kernel-steps", type=int, default=500,
                     help="steps whose fused stream-collide launches are timed with HIP events")
+    ap.add_argument("--instances", type=int, default=64, help="batch_instances: how many")
+    ap.add_argument("--tune-reps", type=int, default=5, help="batch_instances: timed launches per shape")
+    ap.add_argument("--kernel-reps", type=int, default=50,
+                    help="batch_instances: timed launches of the tuned fluid phase")
+    ap.add_argument("--plain-steps", type=int, default=32,
+                    help="batch_instances: steps of each instance alone for the comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
@@ -164,7 +303,7 @@ def main():
                     help="bytes read and written by one calibration copy")
     args = ap.parse_args()
     if args.summarize_counters:
-        args.precision = args.precision or ("f64" if args.workload == "pipe_sphere" else "f32")
+        args.precision = args.precision or default_precision(args.workload)
         summarize_counters(args)
         return
     if args.copy_calibration_mb > 0:
@@ -185,7 +324,10 @@ def main():
     import torch
     import paper_2207_06043_amd as P
 
-    precision = args.precision or ("f64" if args.workload == "pipe_sphere" else "f32")
+    if args.workload == "batch_instances":
+        run_batch(args)
+        return
+    precision = args.precision or default_precision(args.workload)
     w = build_workload(args.workload, precision)
     torch.cuda.set_device(0)
     lat = P.Lattice(w.domain, w.tau, w.u_max, precision)
