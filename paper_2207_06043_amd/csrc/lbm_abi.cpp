@@ -183,9 +183,15 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   ctx->stream = (hipStream_t)hip_stream;
   ctx->prec = d->precision;
   // launch shape (defaults; overridable for tuning)
-  // small (cache-resident, latency-bound) grids: one node per thread and
-  // 64-thread blocks; large (HBM-bound) grids: 16-byte accesses per thread
-  const bool large = (long long)d->nx * d->ny * d->nz >= (4LL << 20);
+  // few non-solid nodes (cache-resident, latency-bound; or a sparse box,
+  // where big tiles would mostly cover solid nodes): one node per thread and
+  // 64-thread blocks; many (HBM-bound): 16-byte accesses per thread
+  long long n_open = 0;
+  {
+    const long long Nb = (long long)d->nx * d->ny * d->nz;
+    for (long long n = 0; n < Nb; n++) n_open += d->node_type[n] != LBM_NODE_SOLID;
+  }
+  const bool large = n_open >= (4LL << 20);
   ctx->bulk_v = large ? (d->precision == 0 ? 2 : (d->precision == 1 ? 4 : 8)) : (d->precision == 2 ? 2 : 1);
   ctx->bulk_block = large ? 256 : 64;
   // small grids: one fluid launch (no fork/join between streams) with the
@@ -648,6 +654,13 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
     dblk0.push_back(dblk0.back() + nblk);
   }
   std::vector<double> diag(16 * (size_t)nb, 0.0), dpart(12 * dblk_body.size(), 0.0);
+  // first reference centre of each body's bounding sphere: its vertex mean
+  for (int b = 0; b < nb; b++)
+    for (int k = 0; k < 3; k++) {
+      double m = 0.0;
+      for (int v = bv0[b]; v < bv0[b] + bnv[b]; v++) m += Xc[3 * (size_t)v + k];
+      diag[16 * (size_t)b + 13 + k] = m / std::max(bnv[b], 1);
+    }
   CHK(up(&ctx->b_diag, diag));
   double* d_dpart;
   int32_t *d_dblk0, *d_dblkb;

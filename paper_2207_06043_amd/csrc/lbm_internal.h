@@ -19,13 +19,17 @@ enum : uint32_t { ST_UNSTABLE = 1u, ST_DAMAGED = 2u };
 constexpr double FX_SCALE = 144115188075855872.0;
 constexpr double FX_INV = 1.0 / 144115188075855872.0;
 
-constexpr int TILE_SHIFT = 10;  // force-flag granularity: 1024 nodes
+// Force-flag granularity: 64 consecutive nodes (an eighth of a 512-node
+// row), so that the tiles touched by a capsule's spread cover little more
+// than its support region.
+constexpr int TILE_SHIFT = 6;
 
-// Forcing markers per block of the first IB launch (one per lane of its
-// first wave), and the most support nodes a block's bounding box may hold
-// in LDS (larger boxes take the direct path).
+// Forcing markers per block of the first IB launch (a quad of lanes each),
+// and the most support nodes a block's bounding box may hold in LDS (larger
+// boxes take the direct path).  64 neighbouring faces of a capsule of
+// radius 19 (2562 vertices) need up to ~1430 box nodes.
 constexpr int MARKERS_PER_BLOCK = 64;
-constexpr int BOX_CELLS = 729;
+constexpr int BOX_CELLS = 1536;  // 86 KB of LDS; the kernel runs one block per CU anyway (VGPRs)
 
 // Work per wave of the probe / vertex-velocity launch: 8 faces (4 lanes per
 // MLS point, outer and inner probe) or 16 vertices.

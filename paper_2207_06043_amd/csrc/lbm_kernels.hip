@@ -879,10 +879,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // l/l0 of the positions X, written to diag_part[dblk].
 __device__ void diag_block(const BodyArgs& b, const double* X, int dblk) {
   __shared__ double sh[8];
-  __shared__ double shm[4][8];
+  __shared__ double shm[4][9];
   const int body = b.dblk_body[dblk];
   const int i = (dblk - b.b_dblk0[body]) * 256 + threadIdx.x;
-  double V = 0.0, S = 0.0, strain = 0.0, nan = 0.0;
+  // reference centre of the bounding sphere (the previous box centre)
+  const double* cref = b.b_diag + 16 * body + 13;
+  double V = 0.0, S = 0.0, strain = 0.0, nan = 0.0, r2 = 0.0;
   double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
   if (i < b.b_nf[body]) {
     const int f = b.b_face0[body] + i;
@@ -901,6 +903,7 @@ __device__ void diag_block(const BodyArgs& b, const double* X, int dblk) {
       if (!(c == c)) nan = 1.0;
       lo[k] = c;
       hi[k] = c;
+      r2 += (c - cref[k]) * (c - cref[k]);
     }
   }
   if (i < b.b_ne[body]) {
@@ -919,6 +922,7 @@ __device__ void diag_block(const BodyArgs& b, const double* X, int dblk) {
   for (int m = 32; m >= 1; m >>= 1) {
     strain = fmax(strain, __shfl_xor(strain, m, 64));
     nan = fmax(nan, __shfl_xor(nan, m, 64));
+    r2 = fmax(r2, __shfl_xor(r2, m, 64));
   }
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
@@ -928,13 +932,14 @@ __device__ void diag_block(const BodyArgs& b, const double* X, int dblk) {
     }
     shm[w][6] = strain;
     shm[w][7] = nan;
+    shm[w][8] = r2;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double* P = b.diag_part + 12 * (long long)dblk;
     store_coherent(P, V);
     store_coherent(P + 1, S);
-    for (int k = 0; k < 8; k++) {
+    for (int k = 0; k < 9; k++) {
       double m = shm[0][k];
       for (int q = 1; q < (int)(blockDim.x >> 6); q++) m = (k < 3) ? fmin(m, shm[q][k]) : fmax(m, shm[q][k]);
       store_coherent(P + 2 + k, m);
@@ -950,16 +955,16 @@ __device__ unsigned int diag_finalize(const BodyArgs& b) {
   // flight at once), then a fixed-order xor reduction
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int body = wv; body < b.nbody; body += nw) {
-    double V = 0.0, S = 0.0, lo[3], hi[3], strain = 0.0, nan = 0.0;
+    double V = 0.0, S = 0.0, lo[3], hi[3], strain = 0.0, nan = 0.0, r2 = 0.0;
     for (int k = 0; k < 3; k++) {
       lo[k] = DBL_MAX;
       hi[k] = -DBL_MAX;
     }
     for (int q = b.b_dblk0[body] + ln; q < b.b_dblk0[body + 1]; q += 64) {
       const double* P = b.diag_part + 12 * (long long)q;
-      double p[10];
+      double p[11];
 #pragma unroll
-      for (int k = 0; k < 10; k++) p[k] = load_coherent(P + k);
+      for (int k = 0; k < 11; k++) p[k] = load_coherent(P + k);
       V += p[0];
       S += p[1];
       for (int k = 0; k < 3; k++) {
@@ -968,6 +973,7 @@ __device__ unsigned int diag_finalize(const BodyArgs& b) {
       }
       strain = fmax(strain, p[8]);
       nan = fmax(nan, p[9]);
+      r2 = fmax(r2, p[10]);
     }
     V = red64(V);
     S = red64(S);
@@ -978,6 +984,7 @@ __device__ unsigned int diag_finalize(const BodyArgs& b) {
       }
       strain = fmax(strain, __shfl_xor(strain, m, 64));
       nan = fmax(nan, __shfl_xor(nan, m, 64));
+      r2 = fmax(r2, __shfl_xor(r2, m, 64));
     }
     if (ln != 0) continue;
     double* d = b.b_diag + 16 * body;
@@ -988,6 +995,14 @@ __device__ unsigned int diag_finalize(const BodyArgs& b) {
       d[5 + k] = hi[k];
     }
     d[8] = strain;
+    // bounding sphere of the vertices (and so of the face centroids): the
+    // reference centre the blocks measured from, and the largest distance;
+    // the next reference is this box's centre
+    for (int k = 0; k < 3; k++) {
+      d[9 + k] = d[13 + k];
+      d[13 + k] = 0.5 * (lo[k] + hi[k]);
+    }
+    d[12] = sqrt(r2);
     // a link whose length doubles its rest length is damaged (computation stops)
     if (!b.b_rigid[body] && strain >= 2.0) raised |= ST_DAMAGED;
     if (nan > 0.0) raised |= ST_UNSTABLE;
@@ -1346,10 +1361,10 @@ __device__ void clear_tiles(const Grid& G, long long* fxp, uint8_t* tfp, int cb,
     if (tl < ntiles && tfp[tl]) s_list[atomicAdd(&s_n, 1)] = (int)tl;
     __syncthreads();
     const int n = s_n;
-    for (int i = 0; i < n; i++) {
-      const long long n0 = (long long)s_list[i] << TILE_SHIFT;
-      const long long n1 = n0 + (1LL << TILE_SHIFT) < G.Np ? n0 + (1LL << TILE_SHIFT) : G.Np;
-      for (long long q = n0 + threadIdx.x; q < n1; q += blockDim.x) {
+    // the listed tiles' nodes, all threads at once
+    for (int k = threadIdx.x; k < (n << TILE_SHIFT); k += blockDim.x) {
+      const long long q = ((long long)s_list[k >> TILE_SHIFT] << TILE_SHIFT) + (k & ((1 << TILE_SHIFT) - 1));
+      if (q < G.Np) {
         fxp[q] = 0;
         fxp[G.Np + q] = 0;
         fxp[2 * G.Np + q] = 0;
@@ -1559,31 +1574,74 @@ __device__ __forceinline__ void mls_post_block(const FluidArgs& a, const BodyArg
     const int body = b.face_body[fv];
     double acc = 0.0;
     if (b.nbody > 1) {
-      // repulsion: for each face of the wave in turn, all lanes scan the
-      // centroids of the other bodies whose bounding boxes come within dx
-      for (int q = 0; q < MLS_FACES_PER_WAVE; q++) {
-        const double qx = __shfl(cen[0], 4 * q, 64), qy = __shfl(cen[1], 4 * q, 64), qz = __shfl(cen[2], 4 * q, 64);
-        const int qb = __shfl(body, 4 * q, 64);
-        const double* bb = b.b_diag + 16 * qb + 2;
-        double part = 0.0;
-        for (int o = 0; o < b.nbody; o++) {
-          if (o == qb) continue;
-          const double* ob = b.b_diag + 16 * o + 2;
-          bool far = false;
+      // repulsion.  First the lanes test the (face q of the wave, other body
+      // o) pairs in parallel: o's box must come within dx of q's body's box
+      // and of the face itself, and its bounding sphere within dx of the
+      // face.  Then, for each surviving pair in (q, o) order, all lanes scan
+      // o's centroids.
+      const int npair = MLS_FACES_PER_WAVE * b.nbody;
+      int cur_q = -1;
+      double part = 0.0;
+      for (int base = 0; base < npair; base += 64) {
+        const int pi = base + l < npair ? base + l : npair - 1;
+        const int pq = pi / b.nbody, po = pi - pq * b.nbody;
+        const double px = __shfl(cen[0], 4 * pq, 64), py = __shfl(cen[1], 4 * pq, 64),
+                     pz = __shfl(cen[2], 4 * pq, 64);
+        const int pb = __shfl(body, 4 * pq, 64);
+        bool cand = base + l < npair && po != pb;
+        {
+          const double* bb = b.b_diag + 16 * pb + 2;
+          const double* ob = b.b_diag + 16 * po + 2;
+          const double* os = b.b_diag + 16 * po + 9;
 #pragma unroll
           for (int k = 0; k < 3; k++)
-            if (bb[k] > ob[3 + k] + 1.0 || ob[k] > bb[3 + k] + 1.0) far = true;
-          if (far) continue;
+            if (bb[k] > ob[3 + k] + 1.0 || ob[k] > bb[3 + k] + 1.0) cand = false;
+          if (px < ob[0] - 1.0 || px > ob[3] + 1.0 || py < ob[1] - 1.0 || py > ob[4] + 1.0 ||
+              pz < ob[2] - 1.0 || pz > ob[5] + 1.0)
+            cand = false;
+          const double sx = px - os[0], sy = py - os[1], sz = pz - os[2];
+          if (sx * sx + sy * sy + sz * sz > (os[3] + 1.0) * (os[3] + 1.0)) cand = false;
+        }
+        unsigned long long m = __ballot(cand);
+        while (m) {
+          const int bit = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          const int q = (base + bit) / b.nbody, o = base + bit - q * b.nbody;
+          if (q != cur_q) {
+            if (cur_q >= 0) {
+              const double tot = red64(part);
+              if ((l >> 2) == cur_q) acc = tot;
+            }
+            cur_q = q;
+            part = 0.0;
+          }
+          const double qx = __shfl(cen[0], 4 * q, 64), qy = __shfl(cen[1], 4 * q, 64),
+                       qz = __shfl(cen[2], 4 * q, 64);
           const int f0 = b.b_face0[o], nfo = b.b_nf[o];
-          for (int g2 = l; g2 < nfo; g2 += 64) {
-            const double* cj = b.centroid + 3 * (f0 + g2);
-            const double ddx = qx - cj[0], ddy = qy - cj[1], ddz = qz - cj[2];
-            const double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            if (d < 1.0 && d > 0.0) part += 1.0 / sqrt(d * d * d * d * d);
+          // four centroids per lane and pass, loads first (the summation
+          // order is that of one at a time: l, l + 64, l + 128, ...)
+          for (int g0 = l; g0 < nfo; g0 += 256) {
+            double cx[4], cy[4], cz[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+              const int g = g0 + 64 * k < nfo ? g0 + 64 * k : g0;
+              const double* cj = b.centroid + 3 * (f0 + g);
+              cx[k] = cj[0];
+              cy[k] = cj[1];
+              cz[k] = cj[2];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+              const double ddx = qx - cx[k], ddy = qy - cy[k], ddz = qz - cz[k];
+              const double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+              if (g0 + 64 * k < nfo && d < 1.0 && d > 0.0) part += 1.0 / sqrt(d * d * d * d * d);
+            }
           }
         }
-        part = red64(part);
-        if ((l >> 2) == q) acc = part;
+      }
+      if (cur_q >= 0) {
+        const double tot = red64(part);
+        if ((l >> 2) == cur_q) acc = tot;
       }
     }
     if (l < 32 && sub == 0 && valid) {

@@ -97,17 +97,35 @@ def ca_floor(X, F, nu, u_ref, rho_ratio):
     return nu * u_ref / (STIFFNESS_LIMIT * m_v / STRETCH_EIG)
 
 
+# Unit directions at which the wall clearance of a capsule candidate is
+# checked (icosphere vertices, 642 directions, about 8 degrees apart).
+_CLEAR_DIRS = None
+
+
+def _clear_of_walls(sdf, c, radius):
+    """True when the sphere of the given radius around c lies in the fluid:
+    the signed distance is negative at its centre and at 642 points of its
+    surface.  (The smooth union of the tubes keeps the sign of the signed
+    distance exact but overstates the depth where two tubes overlap, so the
+    depth at the centre alone is not a clearance test.)"""
+    global _CLEAR_DIRS
+    if _CLEAR_DIRS is None:
+        _CLEAR_DIRS = icosphere(3, 1.0)[0]
+    pts = np.vstack([c[None, :], c[None, :] + radius * _CLEAR_DIRS])
+    return bool(np.all(sdf(pts) < 0.0))
+
+
 def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_choices,
                     x_inlet_clear, face_clear, u_max, nu, eb=1e-4, max_tries=100000,
-                    tries_per_capsule=2000):
+                    tries_per_capsule=2000, x_max=None):
     """Rejection sampling of non-overlapping capsules inside the fluid.
     Draw order per capsule: occlusion ratio, mesh choice, log10 Ca uniform
     on [log10 max(ca_lo, ca_floor), log10 ca_hi] (ca_floor: the stability
     guard above; a capsule whose floor exceeds ca_hi is drawn again), then
-    centre candidates (x, y, z) until one fits: wall clearance >= r_p + 1.5
-    (signed distance), centre distance >= r_i + r_j + 2 to the capsules
-    already placed, at least x_inlet_clear from the inlet and face_clear from
-    the other faces.  A capsule that finds no centre within
+    centre candidates (x, y, z) until one fits: the sphere of radius r_p + 1.5
+    in the fluid (``_clear_of_walls``), centre distance >= r_i + r_j + 2 to
+    the capsules already placed, at least x_inlet_clear from the inlet and
+    face_clear from the other faces, and x <= x_max if given.  A capsule that finds no centre within
     tries_per_capsule candidates is drawn again (occlusion, mesh, Ca) from
     the same stream; the redraws are counted.  Returns (bodies, redraws);
     stops early once max_tries candidates have been spent."""
@@ -129,10 +147,11 @@ def _place_capsules(rng, sdf, box, D, n, occl_lo, occl_hi, ca_lo, ca_hi, subdiv_
             if tries >= max_tries:
                 break
             tries += 1
-            c = np.array([rng.uniform(x_inlet_clear, nx - 1 - face_clear),
+            x_hi = nx - 1 - face_clear if x_max is None else min(nx - 1 - face_clear, x_max)
+            c = np.array([rng.uniform(x_inlet_clear, x_hi),
                           rng.uniform(face_clear, ny - 1 - face_clear),
                           rng.uniform(0, nz - 1)])
-            if sdf(c[None, :])[0] > -(rp + 1.5):
+            if sdf(c[None, :])[0] > -(rp + 1.5) or not _clear_of_walls(sdf, c, rp + 1.5):
                 continue
             if any(np.linalg.norm(c - cc) < rp + rr + 2.0 for cc, rr in zip(centres, radii)):
                 continue
@@ -177,8 +196,13 @@ def batch_instance(seed, k):
     capsules (1-4), then the capsules (occlusion U[0.3, 0.9], 642 or 2562
     vertices, Ca log-uniform in [1e-3, 1e-1] above the stability floor
     ``ca_floor``, Eb = 1e-4) on an 8D x 4D x 1.25D grid, Re = 10, tau = 0.7.
-    The nodes on the box edges are solid (a daughter tube at a small angle
-    leaves through the edge x = nx - 1, y = 0 or ny - 1)."""
+    Capsule centres lie between 1 D after the inlet and 1.5 D before the
+    junction (x <= 2.5 D): at D = 16 the capsules travel about 1.3 D in the
+    1000 steps, so none reaches the junction apex, where capsules are
+    stretched until the damage stop, or an outlet (the method has no
+    treatment of a capsule crossing an open face).  The nodes on the box
+    edges are solid (a daughter tube at a small angle leaves through the
+    edge x = nx - 1, y = 0 or ny - 1)."""
     rng = np.random.default_rng([seed, k])
     D = float(rng.choice([16, 24, 32, 48]))
     th = rng.uniform(30.0, 120.0)
@@ -191,7 +215,7 @@ def batch_instance(seed, k):
     dom = bifurcation(nx, ny, nz, D, 0.8, th, fil, x_junction=4 * D, u_max=u_max,
                       edge_band=0.5)
     bodies, redraws = _place_capsules(rng, dom.meta["sdf"], (nx, ny, nz), D, ncap, 0.3, 0.9,
-                                      1e-3, 1e-1, (3, 4), D, 0.5 * D, u_max, nu)
+                                      1e-3, 1e-1, (3, 4), D, D, u_max, nu, x_max=2.5 * D)
     return Workload(f"batch_{k}", dom, bodies, tau, u_max, "f32", 1000,
                     meta={"D": D, "theta": th, "fillet": fil, "seed": seed, "index": k,
                           "radius_redraws": redraws})
