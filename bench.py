@@ -288,12 +288,14 @@ def run_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's run length less the warm-up)")
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="bifurcation_capsule")
     ap.add_argument("--precision", default=None)
-    ap.add_argument("--precursor", type=int, default=2000,
-                    help="particle-free steps before the capsule is released (untimed)")
+    ap.add_argument("--precursor", type=int, default=None,
+                    help="particle-free steps before the capsules are released (untimed; "
+                         "default 2000, 1000 for precision_form)")
     ap.add_argument("--kernel-steps", type=int, default=500,
                     help="steps whose fused stream-collide launches are timed with HIP events")
     ap.add_argument("--instances", type=int, default=64, help="batch_instances: how many")
@@ -334,6 +336,14 @@ def main():
     import torch
     import paper_2207_06043_amd as P
 
+    # run lengths of the workloads: the bifurcation capsule 5000 steps after a
+    # 2000-step precursor, the precision form 2000 steps after a 1000-step
+    # precursor, the batching form 1000 steps
+    lengths = {"precision_form": (1000, 100, 1900), "batch_instances": (0, 50, 950)}
+    pre, warm, steps = lengths.get(args.workload, (2000, 200, 5000))
+    args.precursor = pre if args.precursor is None else args.precursor
+    args.warmup = warm if args.warmup is None else args.warmup
+    args.steps = steps if args.steps is None else args.steps
     if args.workload == "batch_instances":
         run_batch(args)
         return

@@ -202,8 +202,10 @@ lbm_status lbm_time_fluid_kernel(lbm_ctx *ctx, int32_t n_steps, double *avg_ms);
 lbm_status lbm_set_graph(lbm_ctx *ctx, int32_t enable);
 
 /* Launch shape of the stream-collide kernel: bulk_v consecutive nodes per
- * thread (FP64: 1, 2; FP32: 1, 2, 4; FP16S: 2, 4, 8) and block threads per
- * block (64, 128, 256).  The arithmetic per node does not depend on it, so
+ * thread of a tile (FP64: 1, 2; FP32: 1, 2, 4; FP16S: 2, 4, 8), or 0 for
+ * the list form (one bulk node per thread, from the ordered list of bulk
+ * nodes: no idle lanes on sparse geometries), and block threads per block
+ * (64, 128, 256).  The arithmetic per node does not depend on it, so
  * results are bitwise unchanged.  Synchronises the context's stream;
  * LBM_E_INVAL for an unsupported shape. */
 lbm_status lbm_set_launch_shape(lbm_ctx *ctx, int32_t bulk_v, int32_t block);

@@ -69,6 +69,7 @@ struct lbm_ctx {
   uint32_t* rec_mb = nullptr;  // [nrec] bit j: link j has q >= 1/2
   int nlinks_rec = 0;
   int32_t* tile_list = nullptr;
+  int32_t* bulk_list = nullptr;  // list form: the bulk nodes in order (built on first use)
   int nbulk_blocks = 0;
   long long ntiles = 0;
   long long* fx[2] = {nullptr, nullptr};
@@ -161,9 +162,25 @@ static std::vector<int32_t> bulk_tiles(const Grid& G, const std::vector<uint8_t>
 }
 
 static bool shape_ok(int prec, int V, int block) {
-  const bool vok = (prec == 0 && (V == 1 || V == 2)) || (prec == 1 && (V == 1 || V == 2 || V == 4)) ||
-                   (prec == 2 && (V == 2 || V == 4 || V == 8));
+  const bool vok = V == 0 || (prec == 0 && (V == 1 || V == 2)) ||
+                   (prec == 1 && (V == 1 || V == 2 || V == 4)) || (prec == 2 && (V == 2 || V == 4 || V == 8));
   return vok && (block == 64 || block == 128 || block == 256);
+}
+
+// List form of the bulk part (launch shape V = 0): the bulk node indices in
+// order, one per thread.
+static hipError_t ensure_bulk_list(lbm_ctx* ctx) {
+  if (ctx->bulk_list) return hipSuccess;
+  std::vector<int32_t> lst;
+  lst.reserve((size_t)ctx->n_bulk);
+  for (long long n = 0; n < (long long)ctx->ncls_h.size(); n++)
+    if (ctx->ncls_h[n] == CLS_BULK) lst.push_back((int32_t)n);
+  if (lst.empty()) lst.push_back(0);  // never read (no bulk blocks), keeps the allocation non-empty
+  return upload(&ctx->bulk_list, lst);
+}
+
+static int bulk_blocks(const lbm_ctx* ctx, int V, int block, size_t ntiles) {
+  return V == 0 ? (int)((ctx->n_bulk + block - 1) / block) : (int)ntiles;
 }
 
 // ------------------------------------------------------------------ create
@@ -367,8 +384,9 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   std::vector<double> bcT(4 * (size_t)ctx->nrec);
   for (int r = 0; r < ctx->nrec; r++)
     for (int a = 0; a < 4; a++) bcT[(size_t)a * ctx->nrec + r] = r_bc[4 * (size_t)r + a];
-  std::vector<int32_t> tiles = bulk_tiles(G, ncls, ctx->bulk_block, ctx->bulk_v);
-  ctx->nbulk_blocks = (int)tiles.size();
+  std::vector<int32_t> tiles =
+      ctx->bulk_v > 0 ? bulk_tiles(G, ncls, ctx->bulk_block, ctx->bulk_v) : std::vector<int32_t>(1, 0);
+  ctx->nbulk_blocks = bulk_blocks(ctx, ctx->bulk_v, ctx->bulk_block, tiles.size());
   ctx->ntiles = (G.Np >> TILE_SHIFT) + 1;
   // device allocations
   CHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
@@ -383,6 +401,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   }
   CHK(upload(&ctx->ncls, ncls));
   ctx->ncls_h = ncls;
+  if (ctx->bulk_v == 0) CHK(ensure_bulk_list(ctx));
   CHK(upload(&ctx->rec_of, rec_of));
   CHK(upload(&ctx->rec_node, r_node));
   CHK(upload(&ctx->rec_mask, r_mask));
@@ -445,7 +464,7 @@ extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
   free_bodies(ctx);
   void* ptrs[] = {ctx->f_alloc[0], ctx->f_alloc[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
                   ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_c, ctx->rec_mb,
-                  ctx->tile_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
+                  ctx->tile_list, ctx->bulk_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
                   ctx->api_flags, ctx->mac, ctx->flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -905,6 +924,8 @@ static FluidArgs fluid_args(lbm_ctx* ctx, int p) {
   a.nlinks = ctx->nlinks_rec;
   a.tile_list = ctx->tile_list;
   a.nbulk_blocks = ctx->nbulk_blocks;
+  a.bulk_list = ctx->bulk_v == 0 ? ctx->bulk_list : nullptr;
+  a.nbulk_nodes = (int)ctx->n_bulk;
   a.omega = 1.0 / ctx->tau;
   a.gx = ctx->gfx;
   a.gy = ctx->gfy;
@@ -1069,15 +1090,20 @@ extern "C" lbm_status lbm_set_launch_shape(lbm_ctx* ctx, int32_t bulk_v, int32_t
   if (ctx->broken) return LBM_E_STATE;
   if (!shape_ok(ctx->prec, bulk_v, block)) return fail(ctx, LBM_E_INVAL, "unsupported launch shape");
   if (bulk_v == ctx->bulk_v && block == ctx->bulk_block) return LBM_OK;
-  std::vector<int32_t> tiles = bulk_tiles(ctx->g, ctx->ncls_h, block, bulk_v);
-  // the old list may still be read by enqueued work
+  // the old tile list may still be read by enqueued work
   CHK(hipStreamSynchronize(ctx->stream));
   free_graphs(ctx);
-  int32_t* old = ctx->tile_list;
-  ctx->tile_list = nullptr;
-  CHK(upload(&ctx->tile_list, tiles));
-  if (old) CHK(hipFree(old));
-  ctx->nbulk_blocks = (int)tiles.size();
+  if (bulk_v == 0) {
+    CHK(ensure_bulk_list(ctx));
+    ctx->nbulk_blocks = bulk_blocks(ctx, 0, block, 0);
+  } else {
+    std::vector<int32_t> tiles = bulk_tiles(ctx->g, ctx->ncls_h, block, bulk_v);
+    int32_t* old = ctx->tile_list;
+    ctx->tile_list = nullptr;
+    CHK(upload(&ctx->tile_list, tiles));
+    if (old) CHK(hipFree(old));
+    ctx->nbulk_blocks = (int)tiles.size();
+  }
   ctx->bulk_v = bulk_v;
   ctx->bulk_block = block;
   if (ctx->fluid_merged) ctx->rec_block = block;
@@ -1397,15 +1423,15 @@ static lbm_status batch_time_fluid(lbm_batch* b, int reps, double* ms) {
 }
 
 // The autotuner: times the batched fluid phase for every launch shape this
-// precision supports (V nodes per bulk thread, block size, merged or split
-// records, one block per tile or persistent bulk blocks) and keeps the
-// fastest.  Results go to out[0..min(max, count)) in the order tried.
+// precision supports (V nodes per bulk thread or the list form, block size,
+// merged or split records, one block per tile or persistent bulk blocks)
+// and keeps the fastest.  Results go to out[0..min(max, count)) in the order tried.
 extern "C" lbm_status lbm_batch_tune(lbm_batch* b, int32_t reps, lbm_batch_shape* out,
                                      int32_t max_out, int32_t* n_out) {
   if (!b || reps < 1) return LBM_E_INVAL;
   if (b->broken) return LBM_E_STATE;
-  std::vector<int> Vs = b->prec == 0 ? std::vector<int>{1, 2}
-                                     : (b->prec == 1 ? std::vector<int>{1, 2, 4} : std::vector<int>{2, 4, 8});
+  std::vector<int> Vs = b->prec == 0 ? std::vector<int>{0, 1, 2}
+                                     : (b->prec == 1 ? std::vector<int>{0, 1, 2, 4} : std::vector<int>{0, 2, 4, 8});
   std::vector<lbm_batch_shape> cand;
   for (int V : Vs)
     for (int block : {64, 128, 256}) {

@@ -73,8 +73,10 @@ struct FluidArgs {
   const void* lk_c;          // [3][nlinks] interpolated bounce-back coefficients (compute type)
   const uint32_t* rec_mb;    // [nrec] bit j: the link of direction j has q >= 1/2
   int nlinks;
-  const int32_t* tile_list;  // blocks of the bulk part
+  const int32_t* tile_list;  // blocks of the bulk part (tile form)
   int nbulk_blocks;
+  const int32_t* bulk_list;  // list form (bulk_v 0): the bulk nodes in order, else null
+  int nbulk_nodes;
   double omega;              // 1/tau
   double gx, gy, gz;         // uniform body force
   const long long* fx;       // fixed-point IB force [3][Np] of this step (may be null)
@@ -84,7 +86,7 @@ struct FluidArgs {
   unsigned int* counter;     // block counter used when this launch closes the step
   int close_step;            // 1: no bodies, this launch is the whole step
   int rec_block;             // threads per block of the record kernel
-  int bulk_v;                // nodes per thread of the bulk kernel
+  int bulk_v;                // nodes per thread of the bulk kernel (0: list form, one)
   int bulk_block;            // threads per block of the bulk kernel
 };
 

@@ -468,8 +468,17 @@ __device__ void fluid_bulk(const FluidArgs& a, int blk) {
   typedef typename Vec<S, V>::a vec;
   typedef typename Vec<S, V>::u vecu;
   const Grid& G = a.g;
-  const long long tile = a.tile_list[blk];
-  const long long base = tile * ((long long)blockDim.x * V) + (long long)threadIdx.x * V;
+  long long base;
+  if (V == 1 && a.bulk_list) {
+    // list form: one bulk node per thread from the sorted list of bulk
+    // nodes (no idle lanes on sparse geometries; runs along x stay coalesced)
+    const long long i = (long long)blk * blockDim.x + threadIdx.x;
+    if (i >= a.nbulk_nodes) return;
+    base = a.bulk_list[i];
+  } else {
+    const long long tile = a.tile_list[blk];
+    base = tile * ((long long)blockDim.x * V) + (long long)threadIdx.x * V;
+  }
   if (base >= G.Np) return;
   const typename ClsWord<V>::T cw = *(const typename ClsWord<V>::T*)(a.ncls + base);
   bool isb[V];
@@ -2106,12 +2115,13 @@ static void bulk_launch(const FluidArgs& a, unsigned grid, hipStream_t s) {
 hipError_t launch_fluid_bulk(int prec, const FluidArgs& a, hipStream_t s) {
   if (a.nbulk_blocks == 0) return hipSuccess;
   const unsigned grid = (unsigned)a.nbulk_blocks;
-  switch (prec * 16 + a.bulk_v) {
+  switch (prec * 16 + (a.bulk_v == 0 ? 1 : a.bulk_v)) {  // 0: list form, one node per thread
     case 0 * 16 + 1: bulk_launch<double, 1>(a, grid, s); break;
     case 0 * 16 + 2: bulk_launch<double, 2>(a, grid, s); break;
     case 1 * 16 + 1: bulk_launch<float, 1>(a, grid, s); break;
     case 1 * 16 + 2: bulk_launch<float, 2>(a, grid, s); break;
     case 1 * 16 + 4: bulk_launch<float, 4>(a, grid, s); break;
+    case 2 * 16 + 1: bulk_launch<_Float16, 1>(a, grid, s); break;
     case 2 * 16 + 2: bulk_launch<_Float16, 2>(a, grid, s); break;
     case 2 * 16 + 4: bulk_launch<_Float16, 4>(a, grid, s); break;
     case 2 * 16 + 8: bulk_launch<_Float16, 8>(a, grid, s); break;
@@ -2142,10 +2152,16 @@ hipError_t launch_fluid_all(int prec, const FluidArgs& a, hipStream_t s) {
   const int nrb = a.nrec > 0 ? (int)cdiv(a.nrec, a.bulk_block) : 0;
   const unsigned grid = (unsigned)(nrb + a.nbulk_blocks);
   if (grid == 0) return hipSuccess;
-  switch (prec * 16 + a.bulk_v) {
+  switch (prec * 16 + (a.bulk_v == 0 ? 1 : a.bulk_v)) {  // 0: list form
     case 0 * 16 + 1: all_launch<double, 1>(a, nrb, grid, s); break;
+    case 0 * 16 + 2: all_launch<double, 2>(a, nrb, grid, s); break;
     case 1 * 16 + 1: all_launch<float, 1>(a, nrb, grid, s); break;
+    case 1 * 16 + 2: all_launch<float, 2>(a, nrb, grid, s); break;
+    case 1 * 16 + 4: all_launch<float, 4>(a, nrb, grid, s); break;
+    case 2 * 16 + 1: all_launch<_Float16, 1>(a, nrb, grid, s); break;
     case 2 * 16 + 2: all_launch<_Float16, 2>(a, nrb, grid, s); break;
+    case 2 * 16 + 4: all_launch<_Float16, 4>(a, nrb, grid, s); break;
+    case 2 * 16 + 8: all_launch<_Float16, 8>(a, nrb, grid, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2215,12 +2231,13 @@ static void batch_fluid_launch(const BatchFluid& f, const BatchItem* items, hipS
 }
 
 hipError_t launch_batch_fluid(int prec, const BatchFluid& f, const BatchItem* items, hipStream_t s) {
-  switch (prec * 16 + f.V) {
+  switch (prec * 16 + (f.V == 0 ? 1 : f.V)) {  // 0: list form
     case 0 * 16 + 1: batch_fluid_launch<double, 1>(f, items, s); break;
     case 0 * 16 + 2: batch_fluid_launch<double, 2>(f, items, s); break;
     case 1 * 16 + 1: batch_fluid_launch<float, 1>(f, items, s); break;
     case 1 * 16 + 2: batch_fluid_launch<float, 2>(f, items, s); break;
     case 1 * 16 + 4: batch_fluid_launch<float, 4>(f, items, s); break;
+    case 2 * 16 + 1: batch_fluid_launch<_Float16, 1>(f, items, s); break;
     case 2 * 16 + 2: batch_fluid_launch<_Float16, 2>(f, items, s); break;
     case 2 * 16 + 4: batch_fluid_launch<_Float16, 4>(f, items, s); break;
     case 2 * 16 + 8: batch_fluid_launch<_Float16, 8>(f, items, s); break;

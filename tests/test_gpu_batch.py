@@ -54,7 +54,8 @@ def _assert_same(lat_a, lat_b, what):
         assert torch.equal(p, q), what
 
 
-@pytest.mark.parametrize("shape", [None, (2, 128, 1, 0), (1, 64, 1, 64), (4, 256, 0, 0)])
+@pytest.mark.parametrize("shape", [None, (2, 128, 1, 0), (1, 64, 1, 64), (4, 256, 0, 0),
+                                   (0, 64, 0, 0), (0, 128, 1, 64)])
 def test_batch_equals_own_steps_bitwise(lib, shape):
     ws = _small_instances("f32")
     A = [lib.from_workload(w) for w in ws]
@@ -108,16 +109,35 @@ def test_batch_autotuner_keeps_results(lib):
     batch.step(3)
     tried = batch.tune(reps=3)
     _say(f"[batch] tuner tried {len(tried)} shapes, chose {batch.shape()}")
-    assert len(tried) == 36
+    assert len(tried) == 48   # FP32: V in {list, 1, 2, 4} x 3 block sizes x 4 fluid forms
     best = min(tried, key=lambda t: t["fluid_ms"])
     chosen = batch.shape()
     assert (chosen["bulk_v"], chosen["block"], chosen["mode"], chosen["per_xcd"]) == \
         (best["bulk_v"], best["block"], best["mode"], best["per_xcd"])
     batch.step(20)
+    for lat in A:           # the tuned shape also serves each context's own step
+        lat.step(5)
     for lat in B:
-        lat.step(23)
+        lat.step(28)
     for k, (a, b) in enumerate(zip(A, B)):
         _assert_same(a, b, f"instance {k}")
+
+
+@pytest.mark.parametrize("precision,shapes", [("f64", [(1, 64), (2, 128), (0, 64)]),
+                                              ("f32", [(1, 64), (2, 256), (4, 128), (0, 128)]),
+                                              ("f16s", [(2, 64), (4, 128), (8, 256), (0, 256)])])
+def test_own_step_bitwise_for_every_launch_shape(lib, precision, shapes):
+    """A context's own step gives the same bits for every supported launch
+    shape of the stream-collide kernel."""
+    w = synth.tiny_bifurcation(precision=precision, n_bodies=2)
+    ref = lib.from_workload(w)
+    ref.step(21)
+    for v, blk in shapes:
+        lat = lib.from_workload(w)
+        lat.set_launch_shape(v, blk)
+        lat.step(21)
+        assert lat.sync(raise_on_stop=False) == 0
+        _assert_same(lat, ref, f"shape {v}x{blk}")
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
