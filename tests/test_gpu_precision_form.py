@@ -1,0 +1,99 @@
+"""GPU parity at full size for the precision form: the bifurcation with a 90
+degree semi-aperture (512x256x64, D = 48) carrying 16 deformable capsules of
+2562 vertices, run the way the benchmark runs it (a 1000-step particle-free
+precursor, then the capsules are released; graph launches), in FP16S (the
+form's storage: deviations f - w_i in binary16, FP32 arithmetic), FP32 and
+FP64, against the FP64 oracle's state in tests/golden/precision_form_oracle.npz
+(written by make_precision_form.py beside it, which calls only the oracle).
+
+Measures at each stored step count after the release (0 = end of precursor):
+  e_u = max |u_gpu - u_orc| / max |u_orc|   over the sampled fluid nodes
+  e_x = the largest over the capsules of max |x_gpu - x_orc| over the sampled
+        vertices, relative to that capsule's largest displacement since release
+
+Bounds at step k, from how far the oracle's own trajectory moves when only
+its rounding changes (stored beside the states):
+  FP64: the bar 1e-12, or 100 x the larger spread of the FMA and
+        reordered-sum builds when that is larger;
+  FP32: the bar 2e-5, or 100 x the spread of the build that stores its
+        populations in FP32 when larger; positions held to the bar;
+  FP16S: 10 x the spread of the build that stores its populations (their
+        deviations) in binary16 -- what binary16 storage alone does to this
+        trajectory -- and at least the FP32 bar.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "precision_form_oracle.npz")
+BAR = {"f64": 1e-12, "f32": 2e-5, "f16s": 2e-5}
+ENV = {"f64": ("env_fma", "env_reassoc"), "f32": ("env_f32",), "f16s": ("env_f16",)}
+FACTOR = {"f64": 100.0, "f32": 100.0, "f16s": 10.0}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2207_06043_amd as P
+    P.load_library()
+    return P
+
+
+@pytest.fixture(scope="module")
+def workload():
+    return synth.precision_form()
+
+
+@pytest.mark.parametrize("precision", ["f16s", "f32", "f64"])
+def test_precision_form_full_size(lib, workload, precision):
+    g = np.load(GOLDEN)
+    w = workload
+    vs = int(g["vstride"])
+    x_rel = [b.x[::vs] for b in w.bodies]
+    print(f"[parity] precision_form {precision} precursor={int(g['precursor'])}", flush=True)
+    lat = lib.Lattice(w.domain, w.tau, w.u_max, precision)
+    lat.step(int(g["precursor"]))
+    assert lat.sync(raise_on_stop=False) == lib.LBM_OK
+    for b in w.bodies:
+        lat.add_body(b)
+    sample = g["sample"]
+    done = 0
+    failures = []
+    for k in g["checkpoints"]:
+        k = int(k)
+        if k > done:
+            lat.step(k - done)
+        done = k
+        st = lat.sync(raise_on_stop=False)
+        assert st == int(g[f"status_{k}"]) == lib.LBM_OK
+        _, u = lat.fields()
+        u = u.cpu().numpy()[:, sample]
+        uo = g[f"u_{k}"]
+        e_u = np.abs(u - uo).max() / np.abs(uo).max()
+        e_x = 0.0
+        for i in range(len(w.bodies)):
+            x = lat.body(i)[0].cpu().numpy()[::vs]
+            xo = g[f"x_{k}_{i}"]
+            disp = np.abs(xo - x_rel[i]).max()
+            if disp > 0:
+                e_x = max(e_x, np.abs(x - xo).max() / disp)
+        envs = [g[f"{e}_{k}"] for e in ENV[precision]]
+        env_u = max(e[0] for e in envs)
+        env_x = max(e[1] for e in envs)
+        tol_u = max(BAR[precision], FACTOR[precision] * env_u)
+        tol_x = BAR[precision] if precision == "f32" else max(BAR[precision], FACTOR[precision] * env_x)
+        print(f"  step {k}: e_u {e_u:.3e} (bound {tol_u:.1e}, oracle spread {env_u:.1e}) "
+              f"e_x {e_x:.3e} (bound {tol_x:.1e}, spread {env_x:.1e})", flush=True)
+        sys.stdout.flush()
+        if e_u > tol_u or e_x > tol_x:
+            failures.append((k, e_u, tol_u, e_x, tol_x))
+    assert not failures, failures
