@@ -27,9 +27,10 @@ constexpr int TILE_SHIFT = 6;
 // Forcing markers per block of the first IB launch (a quad of lanes each),
 // and the most support nodes a block's bounding box may hold in LDS (larger
 // boxes take the direct path).  64 neighbouring faces of a capsule of
-// radius 19 (2562 vertices) need up to ~1430 box nodes.
+// radius 19 (2562 vertices) need up to ~1430 box nodes; one block in a
+// thousand of the 16-capsule workload takes the direct path.
 constexpr int MARKERS_PER_BLOCK = 64;
-constexpr int BOX_CELLS = 1536;  // 86 KB of LDS; the kernel runs one block per CU anyway (VGPRs)
+constexpr int BOX_CELLS = 1400;  // 73 KB of LDS: two blocks fit a CU
 
 // Work per wave of the probe / vertex-velocity launch: 8 faces (4 lanes per
 // MLS point, outer and inner probe) or 16 vertices.

@@ -1184,7 +1184,7 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
                              uint8_t* tfc) {
   __shared__ double s_u[3][BOX_CELLS];
   __shared__ long long s_acc[3][BOX_CELLS];
-  __shared__ long long s_node[BOX_CELLS];
+  __shared__ int s_node[BOX_CELLS];  // padded node index (< 2^31) or -1
   __shared__ int s_box[6];
   const Grid& G = a.g;
   const int t = threadIdx.x, sub = t & 3;
@@ -1244,7 +1244,7 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
       s_u[k][c] = u3[k];
       s_acc[k][c] = 0;
     }
-    s_node[c] = node;
+    s_node[c] = (int)node;
   }
   __syncthreads();
   // a quad always holds one marker (or none), so the quad sums below see
@@ -1439,8 +1439,11 @@ __device__ __forceinline__ void ib_force_block(const FluidArgs& a, const BodyArg
   }
 }
 
+// Two blocks per CU (two waves per SIMD) in FP32 and FP16S: the marker
+// blocks are latency-bound chains, and a second resident block hides them.
+// (FP64 would spill to scratch at that register budget.)
 template <class S>
-__global__ __launch_bounds__(256) void k_ib_force(FluidArgs a, BodyArgs b, long long* fxc,
+__global__ __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) void k_ib_force(FluidArgs a, BodyArgs b, long long* fxc,
                                                   uint8_t* tfc, long long* fxp, uint8_t* tfp,
                                                   unsigned int* counter) {
   if (a.flags->stop) return;
@@ -1883,13 +1886,14 @@ __global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags) 
 // phase takes unit map[g] = (instance, block of that instance's own launch);
 // the instance's arguments are read from a device table (per step parity).
 template <class S>
-__global__ __launch_bounds__(256) void kb_ib_force(const BatchItem* items, const int2* map) {
+__global__ __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) void kb_ib_force(const BatchItem* items,
+                                                                          const int2* map) {
   const int2 m = map[blockIdx.x];
+  // the tables are read in place (uniform addresses: scalar loads), not
+  // copied into registers
   const BatchItem& it = items[m.x];
-  const FluidArgs a = it.a;
-  if (a.flags->stop) return;
-  const BodyArgs b = it.b;
-  ib_force_block<S>(a, b, it.fxc, it.tfc, it.fxp, it.tfp, it.counter, m.y);
+  if (it.a.flags->stop) return;
+  ib_force_block<S>(it.a, it.b, it.fxc, it.tfc, it.fxp, it.tfp, it.counter, m.y);
 }
 
 // Fluid phase.  Merged form: records and bulk tiles of every instance in
