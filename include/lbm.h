@@ -223,9 +223,10 @@ typedef struct lbm_batch lbm_batch;
 
 /* Fluid-phase launch shape of a batch: bulk_v and block as for
  * lbm_set_launch_shape; mode 0 runs boundary records and bulk tiles in one
- * launch, mode 1 runs all records, then all bulk tiles; per_xcd > 0 (mode 1
- * only) runs the bulk tiles in a persistent grid of per_xcd blocks on each
- * of the 8 XCDs.  fluid_ms: measured duration of the phase (tuner output). */
+ * launch, mode 1 runs all records, then all bulk tiles; per_xcd > 0 runs the
+ * merged units (mode 0) or the bulk tiles (mode 1) in a persistent grid of
+ * per_xcd blocks on each of the 8 XCDs, which load an instance's arguments
+ * once per run of its units.  fluid_ms: measured duration of the phase (tuner output). */
 typedef struct {
   int32_t bulk_v, block, mode, per_xcd;
   double fluid_ms;

@@ -365,10 +365,10 @@ class Batch:
 
     def tune(self, reps=10):
         """Runs the autotuner; returns the tried shapes (dicts with fluid_ms)."""
-        out = (LbmBatchShape * 64)()
+        out = (LbmBatchShape * 128)()
         n = C.c_int32()
-        self._check(load_library().lbm_batch_tune(self._h, int(reps), out, 64, C.byref(n)))
-        return [out[k].as_dict() for k in range(min(n.value, 64))]
+        self._check(load_library().lbm_batch_tune(self._h, int(reps), out, 128, C.byref(n)))
+        return [out[k].as_dict() for k in range(min(n.value, 128))]
 
     def shape(self):
         sh = LbmBatchShape()

@@ -1219,9 +1219,11 @@ static lbm_status batch_build_tables(lbm_batch* b) {
     for (size_t g = 0; g < v.size(); g++) o[g] = v[xcd_order((int)g, (int)v.size())];
     v.swap(o);
   };
-  order(all);
   order(rec);
-  if (b->per_xcd == 0) order(bulk);
+  if (b->per_xcd == 0) {  // the persistent forms walk the units in logical order
+    order(all);
+    order(bulk);
+  }
   // upload (previous tables may still be read by enqueued work)
   CHKB(hipStreamSynchronize(b->stream));
   batch_free_graphs(b);
@@ -1368,7 +1370,7 @@ extern "C" lbm_status lbm_batch_set_shape(lbm_batch* b, const lbm_batch_shape* s
   if (!b || !sh) return LBM_E_INVAL;
   if (b->broken) return LBM_E_STATE;
   if (!shape_ok(b->prec, sh->bulk_v, sh->block) || sh->mode < 0 || sh->mode > 1 || sh->per_xcd < 0 ||
-      sh->per_xcd > 1024 || (sh->mode == 0 && sh->per_xcd != 0))
+      sh->per_xcd > 1024)
     return bfail(b, LBM_E_INVAL, "unsupported batch launch shape");
   for (lbm_ctx* c : b->ctx) {
     lbm_status st = lbm_set_launch_shape(c, sh->bulk_v, sh->block);
@@ -1435,9 +1437,10 @@ extern "C" lbm_status lbm_batch_tune(lbm_batch* b, int32_t reps, lbm_batch_shape
   std::vector<lbm_batch_shape> cand;
   for (int V : Vs)
     for (int block : {64, 128, 256}) {
-      cand.push_back({V, block, 0, 0, 0.0});
-      cand.push_back({V, block, 1, 0, 0.0});
-      for (int px : {64, 128}) cand.push_back({V, block, 1, px, 0.0});
+      for (int mode : {0, 1}) {
+        cand.push_back({V, block, mode, 0, 0.0});
+        for (int px : {64, 128}) cand.push_back({V, block, mode, px, 0.0});
+      }
     }
   int best = -1;
   for (size_t k = 0; k < cand.size(); k++) {

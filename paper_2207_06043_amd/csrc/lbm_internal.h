@@ -180,9 +180,9 @@ hipError_t launch_spread_api(const Grid& g, const uint8_t* ncls, long long n, co
 hipError_t launch_flush_fx(const Grid& g, long long* fx, double* fib, hipStream_t s);
 
 // Launch shape of the batched fluid phase: blocks of `block` threads, V
-// nodes per bulk thread; mode 0 merged (map_all), 1 split (map_rec, then
-// map_bulk); per_xcd > 0 runs the bulk tiles persistently with per_xcd
-// blocks per XCD.
+// nodes per bulk thread (0: list form); mode 0 merged (map_all), 1 split
+// (map_rec, then map_bulk); per_xcd > 0 runs the merged units, or the bulk
+// tiles, persistently with per_xcd blocks per XCD.
 struct BatchFluid {
   int V, block, mode, per_xcd;
   const int2* map_all; int n_all;

@@ -1903,11 +1903,33 @@ __global__ __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) void kb_ib_force(const
 // that the bandwidth-bound part needs).  The host orders every map so that
 // each XCD takes a contiguous run of units (whole instances where possible).
 template <class S, int V, bool PERX>
-__global__ __launch_bounds__(256) void kb_fluid_all(const BatchItem* items, const int2* map) {
-  const int2 m = map[blockIdx.x];
-  const FluidArgs a = items[m.x].a;
-  if (a.flags->stop) return;
-  fluid_unit<S, V, PERX>(a, items[m.x].nrb, m.y);
+__global__ __launch_bounds__(256) void kb_fluid_all(const BatchItem* items, const int2* map,
+                                                    int nunits, int per_xcd) {
+  if (per_xcd == 0) {
+    const int2 m = map[blockIdx.x];
+    const FluidArgs a = items[m.x].a;
+    if (a.flags->stop) return;
+    fluid_unit<S, V, PERX>(a, items[m.x].nrb, m.y);
+    return;
+  }
+  // persistent: per_xcd blocks on each of the 8 XCDs walk the XCD's
+  // contiguous share of the units; an instance's arguments are loaded once
+  // per run of its units
+  const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int u0 = (int)(((long long)nunits * x) >> 3), u1 = (int)(((long long)nunits * (x + 1)) >> 3);
+  int cur = -1, nrb = 0;
+  bool stop = true;
+  FluidArgs a;
+  for (int u = u0 + j; u < u1; u += per_xcd) {
+    const int2 m = map[u];
+    if (m.x != cur) {
+      cur = m.x;
+      a = items[m.x].a;
+      nrb = items[m.x].nrb;
+      stop = a.flags->stop != 0u;
+    }
+    if (!stop) fluid_unit<S, V, PERX>(a, nrb, m.y);
+  }
 }
 
 template <class S>
@@ -1934,11 +1956,17 @@ __global__ __launch_bounds__(256) void kb_fluid_bulk(const BatchItem* items, con
   }
   const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
   const int u0 = (int)(((long long)nunits * x) >> 3), u1 = (int)(((long long)nunits * (x + 1)) >> 3);
+  int cur = -1;
+  bool stop = true;
+  FluidArgs a;
   for (int u = u0 + j; u < u1; u += per_xcd) {
     const int2 m = map[u];
-    const FluidArgs a = items[m.x].a;
-    if (a.flags->stop) continue;
-    fluid_bulk<S, V, PERX>(a, m.y);
+    if (m.x != cur) {  // an instance's arguments once per run of its units
+      cur = m.x;
+      a = items[m.x].a;
+      stop = a.flags->stop != 0u;
+    }
+    if (!stop) fluid_bulk<S, V, PERX>(a, m.y);
   }
 }
 
@@ -2224,7 +2252,10 @@ hipError_t launch_batch_ib_force(int prec, const BatchItem* items, const int2* m
 template <class S, int V>
 static void batch_fluid_launch(const BatchFluid& f, const BatchItem* items, hipStream_t s) {
   if (f.mode == 0) {
-    if (f.n_all) kb_fluid_all<S, V, false><<<f.n_all, f.block, 0, s>>>(items, f.map_all);
+    if (f.n_all) {
+      const unsigned grid = f.per_xcd > 0 ? 8u * f.per_xcd : (unsigned)f.n_all;
+      kb_fluid_all<S, V, false><<<grid, f.block, 0, s>>>(items, f.map_all, f.n_all, f.per_xcd);
+    }
     return;
   }
   if (f.n_rec) kb_fluid_rec<S><<<f.n_rec, f.block, 0, s>>>(items, f.map_rec);

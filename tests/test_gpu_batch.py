@@ -55,7 +55,8 @@ def _assert_same(lat_a, lat_b, what):
 
 
 @pytest.mark.parametrize("shape", [None, (2, 128, 1, 0), (1, 64, 1, 64), (4, 256, 0, 0),
-                                   (0, 64, 0, 0), (0, 128, 1, 64)])
+                                   (0, 64, 0, 0), (0, 128, 1, 64), (0, 256, 0, 128),
+                                   (2, 64, 0, 64)])
 def test_batch_equals_own_steps_bitwise(lib, shape):
     ws = _small_instances("f32")
     A = [lib.from_workload(w) for w in ws]
@@ -109,7 +110,7 @@ def test_batch_autotuner_keeps_results(lib):
     batch.step(3)
     tried = batch.tune(reps=3)
     _say(f"[batch] tuner tried {len(tried)} shapes, chose {batch.shape()}")
-    assert len(tried) == 48   # FP32: V in {list, 1, 2, 4} x 3 block sizes x 4 fluid forms
+    assert len(tried) == 72   # FP32: V in {list, 1, 2, 4} x 3 block sizes x 6 fluid forms
     best = min(tried, key=lambda t: t["fluid_ms"])
     chosen = batch.shape()
     assert (chosen["bulk_v"], chosen["block"], chosen["mode"], chosen["per_xcd"]) == \
