@@ -35,7 +35,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fluid_kernel_traffic.json")
 # sources that decide what the fluid kernels read and write (code and launch shapes)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_06043_amd", "csrc", n)
                for n in ("lbm_kernels.hip", "lbm_abi.cpp", "lbm_internal.h")]
-FLUID_KERNELS = ("k_fluid_all", "k_fluid_bulk", "k_fluid_rec")
+FLUID_KERNELS = ("k_fluid_all", "k_fluid_bulk", "k_fluid_rec", "kb_fluid_all", "kb_fluid_bulk",
+                 "kb_fluid_rec")
 
 
 def kernel_hash():
@@ -45,15 +46,23 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per launch of the fused stream-collide kernel from the
+def traffic_key(workload, precision, shape=None):
+    key = f"{workload}:{precision}"
+    if shape:
+        key += ":" + ",".join(str(shape[k]) for k in ("bulk_v", "block", "mode", "per_xcd"))
+    return key
+
+
+def measured_traffic(workload, precision, shape=None):
+    """HBM bytes per launch of the fused stream-collide kernel (the batched
+    fluid phase for the batching form, keyed by its launch shape) from the
     committed rocprofv3 counter summary, if it was taken on the current
     kernel source; else None."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    e = d.get(f"{workload}:{precision}")
+    e = d.get(traffic_key(workload, precision, shape))
     if not e or e.get("kernel_sha") != kernel_hash():
         return None
     return e.get("bytes_per_launch")
@@ -97,7 +106,11 @@ def summarize_counters(args):
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         d = {}
-    d[f"{args.workload}:{args.precision}"] = {
+    shape = None
+    if args.batch_shape:
+        shape = dict(zip(("bulk_v", "block", "mode", "per_xcd"), map(int, args.batch_shape.split(","))))
+    key = traffic_key(args.workload, args.precision, shape)
+    d[key] = {
         "kernel_sha": kernel_hash(),
         "bytes_per_launch": round(rd + wr),
         "read_bytes": round(rd),
@@ -111,7 +124,7 @@ def summarize_counters(args):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(d, fh, indent=1, sort_keys=True)
         fh.write("\n")
-    print(json.dumps(d[f"{args.workload}:{args.precision}"]))
+    print(json.dumps(d[key]))
 
 
 def build_workload(name, precision):
@@ -150,7 +163,7 @@ def cpu_baseline(w, target_s=15.0):
     nf = w.domain.n_fluid
     return {"value": round(nf * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.lib().orc_threads(),
             "kind": "oracle",
-            "sample": f"{w.name}: {n} coupled steps (after 2 untimed) of the same grid and capsule, "
+            "sample": f"{w.name}: {n} coupled steps (after 2 untimed) of the same grid and bodies, "
                       f"FP64, {dt:.1f} s (+{setup:.1f} s setup), lattice updates counted on fluid nodes"}
 
 
@@ -194,7 +207,11 @@ def run_batch(args):
     lats = [P.from_workload(w, precision=precision) for w in ws]
     infos = [lat.info() for lat in lats]
     batch = P.Batch(lats)
-    tried = batch.tune(reps=args.tune_reps)
+    if args.batch_shape:
+        batch.set_shape(*map(int, args.batch_shape.split(",")))
+        tried = []
+    else:
+        tried = batch.tune(reps=args.tune_reps)
     shape = batch.shape()
     batch.step(args.warmup)
     for lat in lats:
@@ -218,19 +235,21 @@ def run_batch(args):
     bytes_alg = sum(i["bytes_per_step_alg"] for i in infos)
     achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
     # the same instances, one by one, with their own step
-    for lat in lats:
-        lat.sync(raise_on_stop=False)
-    done1 = [lat.info()["steps_done"] for lat in lats]
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for lat in lats:
-        lat.step(args.plain_steps)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    bad = [k for k, lat in enumerate(lats) if lat.sync(raise_on_stop=False) != P.LBM_OK]
-    upd_plain = sum(i["n_fluid"] * (lat.info()["steps_done"] - d1)
-                    for i, lat, d1 in zip(infos, lats, done1))
-    plain = upd_plain / (t3 - t2) / 1e6
+    plain, bad = float("nan"), []
+    if args.plain_steps > 0:
+        for lat in lats:
+            lat.sync(raise_on_stop=False)
+        done1 = [lat.info()["steps_done"] for lat in lats]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for lat in lats:
+            lat.step(args.plain_steps)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        bad = [k for k, lat in enumerate(lats) if lat.sync(raise_on_stop=False) != P.LBM_OK]
+        upd_plain = sum(i["n_fluid"] * (lat.info()["steps_done"] - d1)
+                        for i, lat, d1 in zip(infos, lats, done1))
+        plain = upd_plain / (t3 - t2) / 1e6
     fluid_kernel = ("kb_fluid_all (records and bulk tiles of all instances in one launch)"
                     if shape["mode"] == 0 else
                     "kb_fluid_rec then kb_fluid_bulk (records, then bulk tiles, of all instances)"
@@ -260,9 +279,9 @@ def run_batch(args):
             "mlups_box": round(n_box * args.steps / elapsed / 1e6, 2),
             "tuned_shape": shape,
             "shapes_tried": len(tried),
-            "plain_one_by_one_mlups": round(plain, 2),
+            "plain_one_by_one_mlups": round(plain, 2) if plain == plain else None,
             "plain_steps_each": args.plain_steps,
-            "batched_vs_plain": round(value / plain, 3),
+            "batched_vs_plain": round(value / plain, 3) if plain == plain else None,
             "plain_stopped": bad,
             "instances_stopped": {str(k): done[k] for k in stopped},
             "updates_counted": "fluid nodes x steps each instance actually completed",
@@ -275,7 +294,7 @@ def run_batch(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("batch_instances", precision),
+            "traffic": measured_traffic("batch_instances", precision, shape),
             "bytes_per_launch_alg": bytes_alg,
             "avg_launch_us": round(avg_ms * 1e3, 3),
         },
@@ -302,6 +321,8 @@ def main():
     ap.add_argument("--tune-reps", type=int, default=5, help="batch_instances: timed launches per shape")
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="batch_instances: timed launches of the tuned fluid phase")
+    ap.add_argument("--batch-shape", default=None,
+                    help="batch_instances: fluid launch shape 'V,block,mode,per_xcd' instead of tuning")
     ap.add_argument("--plain-steps", type=int, default=32,
                     help="batch_instances: steps of each instance alone for the comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -192,10 +192,12 @@ lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t n_steps, const double *d_dJ_ds
 lbm_status lbm_save(lbm_ctx *ctx, const char *path);
 lbm_status lbm_load(lbm_ctx *ctx, const char *path);
 
-/* Timing support: average duration in milliseconds of the fused
- * stream-collide kernel over n_steps full steps, measured with HIP events
- * around each launch on the context's stream (the steps are launched one
- * kernel at a time instead of from the graph). */
+/* Timing support: average duration in milliseconds of one launch of the
+ * fused stream-collide phase, over n_steps full steps launched one kernel
+ * at a time (not from the graph).  In each of them the phase is launched 8
+ * times back to back between two HIP events on the context's stream (it
+ * rewrites the next populations and the macro field from the same inputs,
+ * so the step's result is unchanged) and the span is divided by 8. */
 lbm_status lbm_time_fluid_kernel(lbm_ctx *ctx, int32_t n_steps, double *avg_ms);
 
 /* Replay steps from captured HIP graphs (default 1) or launch kernels one by one (0). */
