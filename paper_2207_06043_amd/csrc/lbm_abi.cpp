@@ -696,8 +696,9 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.n_clear_blocks = (int)std::min<long long>(64, ((ctx->g.Np >> TILE_SHIFT) + 1 + 255) / 256);
   std::vector<double> zf(3 * (size_t)f0, 0.0), zv(3 * (size_t)v0, 0.0);
   double *d_cen, *d_fext, *d_u0v, *d_fslot;
-  int32_t *d_sle, *d_slh, *d_slf;
+  int32_t *d_sle, *d_slh, *d_slf, *d_cbox;
   CHK(up(&d_cen, zf));
+  CHK(up(&d_cbox, std::vector<int32_t>(6 * (size_t)B.n_marker_blocks, 0)));
   CHK(up(&d_fext, zf));
   CHK(up(&d_u0v, zv));
   // slots nobody writes stay zero
@@ -734,6 +735,7 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.b_diag = ctx->b_diag;
   B.centroid = d_cen;
   B.fext = d_fext;
+  B.chunk_box = d_cbox;
   B.u0v = d_u0v;
   B.nu = (ctx->tau - 0.5) / 3.0;
   B.umax = ctx->umax;

@@ -131,6 +131,7 @@ struct BodyArgs {
   // per face / vertex work arrays
   double* centroid;            // [nf][3]
   double* fext;                // [nf][3] hydrodynamic + repulsion force
+  int* chunk_box;              // [n_marker_blocks][6] box of stencil bases of each 64-face chunk
   double* u0v;                 // [nv][3] interpolated velocity at vertices
   int n_clear_blocks;          // blocks clearing the previous step's force tiles
   double nu, umax;

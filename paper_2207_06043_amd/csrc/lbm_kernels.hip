@@ -1224,6 +1224,9 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
     }
   }
   __syncthreads();
+  // this block's faces form one chunk of 64: its box of stencil bases lets
+  // the repulsion skip the chunk when a face is farther than dx from it
+  if (t < 6) b.chunk_box[6 * blk + t] = s_box[t];
   const int x0 = s_box[0] - 1, y0 = s_box[1] - 1, z0 = s_box[2] - 1;
   const int ex = s_box[3] - s_box[0] + 3, ey = s_box[4] - s_box[1] + 3, ez = s_box[5] - s_box[2] + 3;
   const bool fits = s_box[3] >= s_box[0] && (long long)ex * ey * ez <= BOX_CELLS;
@@ -1630,23 +1633,29 @@ __device__ __forceinline__ void mls_post_block(const FluidArgs& a, const BodyArg
           const double qx = __shfl(cen[0], 4 * q, 64), qy = __shfl(cen[1], 4 * q, 64),
                        qz = __shfl(cen[2], 4 * q, 64);
           const int f0 = b.b_face0[o], nfo = b.b_nf[o];
-          // four centroids per lane and pass, loads first (the summation
-          // order is that of one at a time: l, l + 64, l + 128, ...)
-          for (int g0 = l; g0 < nfo; g0 += 256) {
-            double cx[4], cy[4], cz[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-              const int g = g0 + 64 * k < nfo ? g0 + 64 * k : g0;
-              const double* cj = b.centroid + 3 * (f0 + g);
-              cx[k] = cj[0];
-              cy[k] = cj[1];
-              cz[k] = cj[2];
+          // the lanes test o's 64-face chunks in parallel (a centroid c of a
+          // chunk has floor(c + 1/2) inside the chunk's box of bases, so a
+          // face farther than 1.5 from that box has no partner there); the
+          // surviving chunks are scanned one centroid per lane
+          const int c0 = f0 / MARKERS_PER_BLOCK, c1 = (f0 + nfo - 1) / MARKERS_PER_BLOCK;
+          for (int cb0 = c0; cb0 <= c1; cb0 += 64) {
+            bool near = false;
+            if (cb0 + l <= c1) {
+              const int* cb = b.chunk_box + 6 * (cb0 + l);
+              near = !(qx < cb[0] - 1.5 || qx > cb[3] + 1.5 || qy < cb[1] - 1.5 || qy > cb[4] + 1.5 ||
+                       qz < cb[2] - 1.5 || qz > cb[5] + 1.5);
             }
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-              const double ddx = qx - cx[k], ddy = qy - cy[k], ddz = qz - cz[k];
-              const double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-              if (g0 + 64 * k < nfo && d < 1.0 && d > 0.0) part += 1.0 / sqrt(d * d * d * d * d);
+            unsigned long long mc = __ballot(near);
+            while (mc) {
+              const int cbit = __ffsll((unsigned long long)mc) - 1;
+              mc &= mc - 1;
+              const int g = (cb0 + cbit) * MARKERS_PER_BLOCK + l;
+              if (g >= f0 && g < f0 + nfo) {
+                const double* cj = b.centroid + 3 * g;
+                const double ddx = qx - cj[0], ddy = qy - cj[1], ddz = qz - cj[2];
+                const double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+                if (d < 1.0 && d > 0.0) part += 1.0 / sqrt(d * d * d * d * d);
+              }
             }
           }
         }
