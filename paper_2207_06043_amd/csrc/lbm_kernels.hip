@@ -798,16 +798,9 @@ __device__ __forceinline__ void macro_at(const Grid& G, const S* f, const long l
   uz = ((double)mz - 0.5 * Fz) / rho;
 }
 
-__device__ __forceinline__ void face_geom(const double* X, const int32_t* faces, int f,
-                                          double (&c)[3], double (&n)[3], double& area) {
-  const int a = faces[3 * f], b = faces[3 * f + 1], d = faces[3 * f + 2];
-  double pa[3], pb[3], pd[3];
-#pragma unroll
-  for (int k = 0; k < 3; k++) {
-    pa[k] = X[3 * a + k];
-    pb[k] = X[3 * b + k];
-    pd[k] = X[3 * d + k];
-  }
+__device__ __forceinline__ void face_geom_pts(const double (&pa)[3], const double (&pb)[3],
+                                              const double (&pd)[3], double (&c)[3], double (&n)[3],
+                                              double& area) {
   double u[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
   double v[3] = {pd[0] - pa[0], pd[1] - pa[1], pd[2] - pa[2]};
   double N[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
@@ -818,6 +811,19 @@ __device__ __forceinline__ void face_geom(const double* X, const int32_t* faces,
     n[k] = N[k] / l;
   }
   area = 0.5 * l;
+}
+
+__device__ __forceinline__ void face_geom(const double* X, const int32_t* faces, int f,
+                                          double (&c)[3], double (&n)[3], double& area) {
+  const int a = faces[3 * f], b = faces[3 * f + 1], d = faces[3 * f + 2];
+  double pa[3], pb[3], pd[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    pa[k] = X[3 * a + k];
+    pb[k] = X[3 * b + k];
+    pd[k] = X[3 * d + k];
+  }
+  face_geom_pts(pa, pb, pd, c, n, area);
 }
 
 __device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
@@ -1195,20 +1201,35 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
   double cen[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0}, area = 0.0;
   int bs[3] = {0, 0, 0};
   if (mk) {
-    double nrm[3];
-    face_geom(b.Xcur, b.faces, m, cen, nrm, area);
+    // two rounds of loads: the face's vertices and body, then everything
+    // that depends on them at once (positions, vertex velocities, rigid
+    // state; the unused of the last two are discarded)
+    const int v0 = b.faces[3 * m], v1 = b.faces[3 * m + 1], v2 = b.faces[3 * m + 2];
     const int body = b.face_body[m];
-    if (b.b_rigid[body]) {
-      const double* rs = b.b_rig + 32 * body;
+    double pa[3], pb[3], pd[3], va[3], vb[3], vd[3], rs[12];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      pa[k] = b.Xcur[3 * v0 + k];
+      pb[k] = b.Xcur[3 * v1 + k];
+      pd[k] = b.Xcur[3 * v2 + k];
+      va[k] = b.Vel[3 * v0 + k];
+      vb[k] = b.Vel[3 * v1 + k];
+      vd[k] = b.Vel[3 * v2 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; k++) rs[k] = b.b_rig[32 * body + k];
+    const int rigid = b.b_rigid[body];
+    double nrm[3];
+    face_geom_pts(pa, pb, pd, cen, nrm, area);
+    if (rigid) {
       const double r[3] = {cen[0] - rs[0], cen[1] - rs[1], cen[2] - rs[2]};
       const double* w = rs + 9;
       Ub[0] = rs[3] + (w[1] * r[2] - w[2] * r[1]);
       Ub[1] = rs[4] + (w[2] * r[0] - w[0] * r[2]);
       Ub[2] = rs[5] + (w[0] * r[1] - w[1] * r[0]);
     } else {
-      const int v0 = b.faces[3 * m], v1 = b.faces[3 * m + 1], v2 = b.faces[3 * m + 2];
 #pragma unroll
-      for (int k = 0; k < 3; k++) Ub[k] = (b.Vel[3 * v0 + k] + b.Vel[3 * v1 + k] + b.Vel[3 * v2 + k]) / 3.0;
+      for (int k = 0; k < 3; k++) Ub[k] = (va[k] + vb[k] + vd[k]) / 3.0;
     }
 #pragma unroll
     for (int k = 0; k < 3; k++) bs[k] = (int)floor(cen[k] + 0.5);

@@ -479,6 +479,44 @@ def test_pipe_poiseuille_profile():
     assert e8 < 0.01 and e12 < e8
 
 
+def test_bfl_second_order_on_a_curved_wall():
+    """The interpolated bounce-back on the curved wall of a circular pipe
+    (radii off the lattice, so the link fractions vary around the wall):
+    the L2 error of Hagen-Poiseuille flow falls as R^-2 (fitted slope over
+    R = 4.3, 8.3, 16.3 above 1.6; measured 2.0)."""
+    R = np.array([4.3, 8.3, 16.3])
+    errs = np.array([_poiseuille_error(r) for r in R])
+    slope = -np.polyfit(np.log(R), np.log(errs), 1)[0]
+    assert slope > 1.6, (errs, slope)
+
+
+def test_stokes_drag_on_a_fixed_sphere():
+    """A fixed rigid sphere (radius 3, 162 vertices) in a periodic 24^3 box
+    of fluid driven by a uniform body force g at low Reynolds number.  At the
+    steady state the immersed-boundary force spread on the fluid balances
+    the body force exactly (sum f_ib = -g N), and the drag F = g N against
+    the mean velocity U follows Stokes' law for a periodic array of spheres
+    (Hasimoto's correction K(phi) to 6 pi mu R U).  The diffuse interface
+    makes the sphere act slightly larger than R: F / (6 pi mu R U K) is 1.07
+    here; it is held to [0.95, 1.15]."""
+    L, R, tau, g = 24, 3.0, 1.0, 1e-6
+    d = synth.periodic_box(L, L, L, body_force=(g, 0.0, 0.0))
+    X, F = synth.icosphere(2, R, (11.7, 11.6, 11.55), tilt=True)
+    b = synth.Body(X, F, rigid=True, fixed=True, rho_ratio=1.1, r_ref=R)
+    s = oracle.OracleSim(d, tau=tau, u_max=0.0, bodies=[b], threads=4)
+    assert s.step(9000) == 0
+    _, u = s.fields()
+    fib = s.force()
+    N = L ** 3
+    np.testing.assert_allclose(fib.sum(1), [-g * N, 0.0, 0.0], rtol=2e-4, atol=2e-4 * g * N)
+    nu = (tau - 0.5) / 3.0
+    U = u[0].mean()
+    phi = 4.0 / 3.0 * np.pi * R ** 3 / N
+    K = 1.0 / (1.0 - 1.7601 * phi ** (1 / 3) + phi - 1.5593 * phi ** 2)
+    ratio = g * N / (6.0 * np.pi * nu * R * U * K)
+    assert 0.95 < ratio < 1.15, ratio
+
+
 # ------------------------------------------------- repulsion (Eq. collision)
 
 @pytest.mark.parametrize("d", [0.3, 0.55, 0.9])
