@@ -190,3 +190,20 @@ def test_batching_form_instances_bitwise(lib):
         assert a.sync(raise_on_stop=False) == 0
         _assert_same(a, b, f"instance {k}")
         del b
+
+
+def test_batch_of_one_and_of_fluid_only_instances(lib):
+    """A batch of a single instance, and a batch whose instances carry no
+    bodies (the IB phases have no work), equal their own steps bitwise."""
+    for ws in ([synth.tiny_bifurcation(seed=4, precision="f32", n_bodies=1)],
+               [synth.tiny_pipe(precision="f32", with_body=False),
+                synth.tiny_bifurcation(seed=5, precision="f32", n_bodies=0)]):
+        A = [lib.from_workload(w) for w in ws]
+        B = [lib.from_workload(w) for w in ws]
+        batch = lib.Batch(A)
+        batch.step(19)
+        for lat in B:
+            lat.step(19)
+        for k, (a, b) in enumerate(zip(A, B)):
+            assert a.sync(raise_on_stop=False) == 0
+            _assert_same(a, b, f"instance {k}")

@@ -342,3 +342,21 @@ def test_f16s_within_storage_rounding(lib, name):
     _say(f"    f16s e_u {e_u:.3e} (storage alone {env['e_u']:.3e}, bound {tol_u:.2e}); "
          f"e_x {e_x:.3e} (storage alone {env['e_x']:.3e}, bound {tol_x:.2e})")
     assert e_u <= tol_u and e_x <= tol_x
+
+
+# ------------------------------------------------------------ edge cases
+def test_zero_sized_calls_are_no_ops(lib):
+    """No points to interpolate or spread, and zero steps, change nothing."""
+    import torch
+    w = synth.tiny_pipe(precision="f64", rigid=True)
+    lat = lib.from_workload(w)
+    lat.step(3)
+    f0 = lat.populations()
+    lat.step(0)
+    assert torch.equal(lat.populations(), f0)
+    empty = torch.zeros(0, 3, dtype=torch.float64, device="cuda")
+    assert lat.ib_interpolate(empty).shape == (0, 3)
+    fib = lat.ib_spread(empty, empty, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert float(fib.abs().max()) == 0.0
+    assert torch.equal(lat.populations(), f0)
+    assert lat.sync(raise_on_stop=False) == 0
