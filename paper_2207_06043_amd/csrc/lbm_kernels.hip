@@ -1933,18 +1933,20 @@ __global__ __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) void kb_ib_force(const
 // that the bandwidth-bound part needs).  The host orders every map so that
 // each XCD takes a contiguous run of units (whole instances where possible).
 template <class S, int V, bool PERX>
-__global__ __launch_bounds__(256) void kb_fluid_all(const BatchItem* items, const int2* map,
-                                                    int nunits, int per_xcd) {
-  if (per_xcd == 0) {
-    const int2 m = map[blockIdx.x];
-    const FluidArgs a = items[m.x].a;
-    if (a.flags->stop) return;
-    fluid_unit<S, V, PERX>(a, items[m.x].nrb, m.y);
-    return;
-  }
-  // persistent: per_xcd blocks on each of the 8 XCDs walk the XCD's
-  // contiguous share of the units; an instance's arguments are loaded once
-  // per run of its units
+__global__ __launch_bounds__(256) void kb_fluid_all(const BatchItem* items, const int2* map) {
+  const int2 m = map[blockIdx.x];
+  const FluidArgs a = items[m.x].a;
+  if (a.flags->stop) return;
+  fluid_unit<S, V, PERX>(a, items[m.x].nrb, m.y);
+}
+
+// Persistent form (its own kernel: holding an instance's arguments across
+// units takes registers the one-unit form does not need): per_xcd blocks on
+// each of the 8 XCDs walk the XCD's contiguous share of the units; an
+// instance's arguments are loaded once per run of its units.
+template <class S, int V, bool PERX>
+__global__ __launch_bounds__(256) void kb_fluid_all_persist(const BatchItem* items, const int2* map,
+                                                            int nunits, int per_xcd) {
   const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
   const int u0 = (int)(((long long)nunits * x) >> 3), u1 = (int)(((long long)nunits * (x + 1)) >> 3);
   int cur = -1, nrb = 0;
@@ -1975,15 +1977,16 @@ __global__ __launch_bounds__(256) void kb_fluid_rec(const BatchItem* items, cons
 // the 8 XCDs walk the XCD's contiguous share of the units in strides of
 // per_xcd.
 template <class S, int V, bool PERX>
-__global__ __launch_bounds__(256) void kb_fluid_bulk(const BatchItem* items, const int2* map,
-                                                     int nunits, int per_xcd) {
-  if (per_xcd == 0) {
-    const int2 m = map[blockIdx.x];
-    const FluidArgs a = items[m.x].a;
-    if (a.flags->stop) return;
-    fluid_bulk<S, V, PERX>(a, m.y);
-    return;
-  }
+__global__ __launch_bounds__(256) void kb_fluid_bulk(const BatchItem* items, const int2* map) {
+  const int2 m = map[blockIdx.x];
+  const FluidArgs a = items[m.x].a;
+  if (a.flags->stop) return;
+  fluid_bulk<S, V, PERX>(a, m.y);
+}
+
+template <class S, int V, bool PERX>
+__global__ __launch_bounds__(256) void kb_fluid_bulk_persist(const BatchItem* items, const int2* map,
+                                                             int nunits, int per_xcd) {
   const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
   const int u0 = (int)(((long long)nunits * x) >> 3), u1 = (int)(((long long)nunits * (x + 1)) >> 3);
   int cur = -1;
@@ -2282,17 +2285,17 @@ hipError_t launch_batch_ib_force(int prec, const BatchItem* items, const int2* m
 template <class S, int V>
 static void batch_fluid_launch(const BatchFluid& f, const BatchItem* items, hipStream_t s) {
   if (f.mode == 0) {
-    if (f.n_all) {
-      const unsigned grid = f.per_xcd > 0 ? 8u * f.per_xcd : (unsigned)f.n_all;
-      kb_fluid_all<S, V, false><<<grid, f.block, 0, s>>>(items, f.map_all, f.n_all, f.per_xcd);
-    }
+    if (f.n_all && f.per_xcd > 0)
+      kb_fluid_all_persist<S, V, false><<<8u * f.per_xcd, f.block, 0, s>>>(items, f.map_all, f.n_all, f.per_xcd);
+    else if (f.n_all)
+      kb_fluid_all<S, V, false><<<f.n_all, f.block, 0, s>>>(items, f.map_all);
     return;
   }
   if (f.n_rec) kb_fluid_rec<S><<<f.n_rec, f.block, 0, s>>>(items, f.map_rec);
-  if (f.n_bulk) {
-    const unsigned grid = f.per_xcd > 0 ? 8u * f.per_xcd : (unsigned)f.n_bulk;
-    kb_fluid_bulk<S, V, false><<<grid, f.block, 0, s>>>(items, f.map_bulk, f.n_bulk, f.per_xcd);
-  }
+  if (f.n_bulk && f.per_xcd > 0)
+    kb_fluid_bulk_persist<S, V, false><<<8u * f.per_xcd, f.block, 0, s>>>(items, f.map_bulk, f.n_bulk, f.per_xcd);
+  else if (f.n_bulk)
+    kb_fluid_bulk<S, V, false><<<f.n_bulk, f.block, 0, s>>>(items, f.map_bulk);
 }
 
 hipError_t launch_batch_fluid(int prec, const BatchFluid& f, const BatchItem* items, hipStream_t s) {
