@@ -200,6 +200,16 @@ lbm_status lbm_load(lbm_ctx *ctx, const char *path);
  * so the step's result is unchanged) and the span is divided by 8. */
 lbm_status lbm_time_fluid_kernel(lbm_ctx *ctx, int32_t n_steps, double *avg_ms);
 
+/* FP64 diagnostics of the last completed step (the checks the paper runs on
+ * its simulations: conservation, capsule volume and surface, damage):
+ * out[0] total mass (sum over non-solid nodes of sum_i f_i), out[1..3] total
+ * momentum (sum of f_i e_i) of the post-collision populations, reduced in a
+ * fixed order (bitwise reproducible); then per body b, out[4 + 3b ..]: its
+ * enclosed volume V, surface S and largest link stretch l/l0 at the current
+ * positions.  out is host memory of 4 + 3 * n_bodies doubles.  Synchronises
+ * the context's stream. */
+lbm_status lbm_diagnostics(lbm_ctx *ctx, double *out);
+
 /* Replay steps from captured HIP graphs (default 1) or launch kernels one by one (0). */
 lbm_status lbm_set_graph(lbm_ctx *ctx, int32_t enable);
 

@@ -24,7 +24,8 @@ PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 EXPORTS = ["lbm_create", "lbm_destroy", "lbm_last_error", "lbm_info", "lbm_add_body", "lbm_step",
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_get_force", "lbm_get_body",
            "ib_interpolate", "ib_spread", "lbm_adjoint_step", "lbm_save", "lbm_load",
-           "lbm_time_fluid_kernel", "lbm_set_graph", "lbm_set_launch_shape", "lbm_batch_create",
+           "lbm_time_fluid_kernel", "lbm_set_graph", "lbm_set_launch_shape", "lbm_diagnostics",
+           "lbm_batch_create",
            "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_step", "lbm_batch_tune",
            "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_time_fluid",
            "lbm_batch_set_graph"]
@@ -122,6 +123,8 @@ def load_library():
     L.lbm_time_fluid_kernel.argtypes = [vp, i32, dp]
     L.lbm_set_graph.restype = st
     L.lbm_set_graph.argtypes = [vp, i32]
+    L.lbm_diagnostics.restype = st
+    L.lbm_diagnostics.argtypes = [vp, dp]
     L.lbm_set_launch_shape.restype = st
     L.lbm_set_launch_shape.argtypes = [vp, i32, i32]
     L.lbm_batch_create.restype = st
@@ -258,6 +261,15 @@ class Lattice:
         o = LbmInfo()
         self._check(load_library().lbm_info(self._h, C.byref(o)))
         return {k: getattr(o, k) for k, _ in LbmInfo._fields_}
+
+    def diagnostics(self):
+        """FP64 total mass and momentum of the last completed step, and per body
+        (volume, surface, largest stretch) at the current positions."""
+        out = (C.c_double * (4 + 3 * len(self.bodies)))()
+        self._check(load_library().lbm_diagnostics(self._h, out))
+        vals = list(out)
+        return {"mass": vals[0], "momentum": vals[1:4],
+                "bodies": [tuple(vals[4 + 3 * b: 7 + 3 * b]) for b in range(len(self.bodies))]}
 
     def set_launch_shape(self, bulk_v, block):
         self._check(load_library().lbm_set_launch_shape(self._h, int(bulk_v), int(block)))

@@ -76,6 +76,7 @@ struct lbm_ctx {
   uint8_t* tf[2] = {nullptr, nullptr};
   void* mac = nullptr;  // [Np][4] rho - 1, u of the step in the compute type (bodies only)
   long long* fx_api = nullptr;
+  double* gdiag = nullptr;  // global mass/momentum reduction: 5 x 1024 partials + 5 results
   DevFlags* api_flags = nullptr;  // range flags of ib_spread (kept apart from the run's)
   DevFlags* flags = nullptr;  // followed by the block counter
   // bodies
@@ -465,7 +466,7 @@ extern "C" lbm_status lbm_destroy(lbm_ctx* ctx) {
   void* ptrs[] = {ctx->f_alloc[0], ctx->f_alloc[1], ctx->ncls, ctx->rec_of, ctx->rec_node, ctx->rec_mask,
                   ctx->rec_link0, ctx->rec_face, ctx->rec_bc, ctx->lk_c, ctx->rec_mb,
                   ctx->tile_list, ctx->bulk_list, ctx->fx[0], ctx->fx[1], ctx->tf[0], ctx->tf[1], ctx->fx_api,
-                  ctx->api_flags, ctx->mac, ctx->flags};
+                  ctx->api_flags, ctx->mac, ctx->flags, ctx->gdiag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -1505,6 +1506,33 @@ extern "C" lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t enable) {
 extern "C" lbm_status lbm_batch_time_fluid(lbm_batch* b, int32_t reps, double* avg_ms) {
   if (!b || reps < 1 || !avg_ms) return LBM_E_INVAL;
   return batch_time_fluid(b, reps, avg_ms);
+}
+
+extern "C" lbm_status lbm_diagnostics(lbm_ctx* ctx, double* out) {
+  if (!ctx || !out) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (!ctx->gdiag) CHK(hipMalloc(&ctx->gdiag, sizeof(double) * (5 * 1024 + 8)));
+  // the bodies' volume, area and stretch of the current positions
+  if (ctx->nf > 0)
+    CHK(launch_check(ctx->bargs[0], ctx->X[0], ctx->X[1], ctx->flags, counter(ctx, 3), ctx->stream));
+  CHK(launch_diag_sums(ctx->prec, ctx->g, ctx->f[0], ctx->f[1], ctx->ncls, ctx->flags, ctx->gdiag,
+                       ctx->gdiag + 5 * 1024, ctx->stream));
+  double sums[5];
+  const size_t nb = ctx->bodies.size();
+  std::vector<double> bd(16 * nb);
+  CHK(hipMemcpyAsync(sums, ctx->gdiag + 5 * 1024, sizeof sums, hipMemcpyDeviceToHost, ctx->stream));
+  if (nb) CHK(hipMemcpyAsync(bd.data(), ctx->b_diag, sizeof(double) * bd.size(), hipMemcpyDeviceToHost, ctx->stream));
+  CHK(hipStreamSynchronize(ctx->stream));
+  out[0] = sums[0] + sums[1];  // each non-solid node holds 1 + the sum of its deviations
+  out[1] = sums[2];
+  out[2] = sums[3];
+  out[3] = sums[4];
+  for (size_t b = 0; b < nb; b++) {
+    out[4 + 3 * b] = bd[16 * b];          // enclosed volume
+    out[4 + 3 * b + 1] = bd[16 * b + 1];  // surface
+    out[4 + 3 * b + 2] = bd[16 * b + 8];  // largest stretch l / l0
+  }
+  return LBM_OK;
 }
 
 // ----------------------------------------------------------------- outputs

@@ -163,6 +163,10 @@ hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long
                            unsigned int* counter, hipStream_t s);
 hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s);
 hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s);
+// Mass and momentum sums of the last completed step into out[5] (non-solid
+// node count, sum of deviations, momentum); part holds 5 x 1024 doubles.
+hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void* f1, const uint8_t* ncls,
+                            const DevFlags* flags, double* part, double* out, hipStream_t s);
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,

@@ -2337,6 +2337,57 @@ hipError_t launch_batch_close(const BatchItem* items, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Global FP64 mass and momentum of the populations of the last completed
+// step: per block, each thread sums its nodes in index order, then a fixed
+// tree; k_diag_final sums the blocks in a fixed order (bitwise reproducible).
+constexpr int DIAG_SUM_BLOCKS = 1024;
+
+template <class S>
+__global__ __launch_bounds__(256) void k_diag_sum(Grid G, const S* f0, const S* f1, const uint8_t* ncls,
+                                                  const DevFlags* flags, double* part) {
+  __shared__ double sh[8];
+  const S* f = (flags->steps_done & 1) ? f1 : f0;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // non-solid nodes, sum of deviations, momentum
+  for (long long p = blockIdx.x * 256LL + threadIdx.x; p < G.Np; p += (long long)gridDim.x * 256) {
+    if (ncls[p] == CLS_SOLID) continue;
+    v[0] += 1.0;
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+      const double g = (double)to_c(f[(long long)i * G.plane + p]);
+      v[1] += g;
+      v[2] += EX[i] * g;
+      v[3] += EY[i] * g;
+      v[4] += EZ[i] * g;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    const double t = block_sum(v[k], sh);
+    if (threadIdx.x == 0) part[5 * blockIdx.x + k] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double* part, int nblk, double* out) {
+  __shared__ double sh[8];
+  for (int k = 0; k < 5; k++) {
+    double v = 0.0;
+    for (int j = threadIdx.x; j < nblk; j += blockDim.x) v += part[5 * j + k];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) out[k] = v;
+  }
+}
+
+hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void* f1, const uint8_t* ncls,
+                            const DevFlags* flags, double* part, double* out, hipStream_t s) {
+  switch (prec) {
+    case 0: k_diag_sum<double><<<DIAG_SUM_BLOCKS, 256, 0, s>>>(g, (const double*)f0, (const double*)f1, ncls, flags, part); break;
+    case 1: k_diag_sum<float><<<DIAG_SUM_BLOCKS, 256, 0, s>>>(g, (const float*)f0, (const float*)f1, ncls, flags, part); break;
+    default: k_diag_sum<_Float16><<<DIAG_SUM_BLOCKS, 256, 0, s>>>(g, (const _Float16*)f0, (const _Float16*)f1, ncls, flags, part); break;
+  }
+  k_diag_final<<<1, 256, 0, s>>>(part, DIAG_SUM_BLOCKS, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s) {
   if (b.nbody == 0) return hipSuccess;

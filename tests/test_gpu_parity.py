@@ -360,3 +360,48 @@ def test_zero_sized_calls_are_no_ops(lib):
     assert float(fib.abs().max()) == 0.0
     assert torch.equal(lat.populations(), f0)
     assert lat.sync(raise_on_stop=False) == 0
+
+
+# ------------------------------------------------------------ diagnostics
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_global_mass_momentum_budget_on_device(lib, precision):
+    """The device's FP64 mass and momentum reductions: with a uniform force g
+    on every node of a periodic box each step adds exactly g per node to the
+    momentum and leaves the mass unchanged; the sums equal the oracle's."""
+    g = np.array([1e-5, -2e-6, 3e-6])
+    d = synth.periodic_box(20, 13, 11, body_force=tuple(g))
+    rng = np.random.default_rng(3)
+    d.init_rho = 1 + 0.01 * rng.standard_normal(d.n_nodes)
+    d.init_u = 0.01 * rng.standard_normal(3 * d.n_nodes)
+    lat = lib.Lattice(d, 0.9, 0.0, precision)
+    d0 = lat.diagnostics()
+    lat.step(5)
+    d5 = lat.diagnostics()
+    N = d.n_nodes
+    # FP32 storage rounds each stored deviation (~3e-9 relative to w_i)
+    tol_m, tol_p = (1e-12 * N, 1e-13 * N) if precision == "f64" else (1e-6 * N, 1e-8 * N)
+    _say(f"    mass change {d5['mass'] - d0['mass']:.3e}, momentum budget error "
+         f"{np.abs(np.array(d5['momentum']) - np.array(d0['momentum']) - 5 * N * g).max():.3e}")
+    assert abs(d5["mass"] - d0["mass"]) < tol_m
+    np.testing.assert_allclose(d5["momentum"], np.array(d0["momentum"]) + 5 * N * g, rtol=0, atol=tol_p)
+    s = oracle.OracleSim(d, tau=0.9, threads=1)
+    s.step(5)
+    e, _ = oracle.lattice()
+    f = s.populations()
+    assert abs(d5["mass"] - f.sum()) < tol_m
+    np.testing.assert_allclose(d5["momentum"], (e.T @ f).sum(axis=1), rtol=0, atol=tol_p)
+    assert lat.diagnostics() == d5  # bitwise reproducible
+
+
+def test_body_diagnostics_match_oracle(lib):
+    w = synth.tiny_pipe(precision="f64", rigid=False)
+    lat = lib.from_workload(w)
+    lat.step(10)
+    dg = lat.diagnostics()
+    o = oracle.from_workload(w)
+    o.step(10)
+    od = o.body_diag(0)
+    V, S, strain = dg["bodies"][0]
+    _say(f"    V {V:.6f} S {S:.6f} stretch {strain:.6f}; oracle {od}")
+    assert abs(V - od["V"]) < 1e-12 * abs(od["V"]) and abs(S - od["S"]) < 1e-12 * od["S"]
+    assert abs(strain - od["max_strain"]) < 1e-12
