@@ -139,7 +139,11 @@ lbm_status lbm_info(lbm_ctx *ctx, lbm_info_t *out);
 
 /* Add a capsule (host data copied).  Rest lengths, areas, angles and volume
  * are taken from the given positions.  LBM_E_INVAL for an open or
- * inconsistently oriented mesh. */
+ * inconsistently oriented mesh, or a vertex in more than 10 faces.  The
+ * forcing markers are processed in blocks of 64 consecutive faces: a
+ * spatially coherent face order (icosphere subdivision order is one) keeps
+ * each block's support nodes in on-chip memory; a scattered order is still
+ * correct, only slower. */
 lbm_status lbm_add_body(lbm_ctx *ctx, const lbm_body_desc *body, int32_t *body_id);
 
 /* Advance n_steps coupled steps (asynchronous on the context's stream):

@@ -545,3 +545,43 @@ def test_repulsion_vanishes_beyond_one_spacing():
     s = oracle.OracleSim(w.domain, tau=w.tau, u_max=w.u_max, bodies=w.bodies, threads=1)
     assert s.step(1) == 0
     assert np.abs(s.body_fext(0)).max() < 1e-13 and np.abs(s.body_fext(1)).max() < 1e-13
+
+
+# ------------------------------------------------ property tests (hypothesis)
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+_finite = dict(allow_nan=False, allow_infinity=False)
+
+
+@settings(max_examples=40, deadline=None)
+@given(r=st.floats(0.0, 4.4, **_finite), t=st.floats(0.0, 6.283, **_finite),
+       xp=st.floats(0.0, 11.0, **_finite), a=st.floats(-2.0, 2.0, **_finite),
+       g=st.tuples(*[st.floats(-1.0, 1.0, **_finite)] * 3))
+def test_mls_reproduces_linear_fields_anywhere(r, t, xp, a, g):
+    """Any point of the pipe, any linear field: the MLS weights reproduce its
+    value and gradient (also where the support is cut by the wall)."""
+    d, s = _pipe_sim()
+    p = np.array([xp, 5.5 + r * np.cos(t), 5.5 + r * np.sin(t)])
+    ok, node, psi = s.mls_point(p)
+    assert ok
+    G = np.array(g)
+    x = np.stack([node % 12, (node // 12) % 12, node // 144], 1).astype(float)
+    x[:, 0] += 12 * np.round((p[0] - x[:, 0]) / 12)
+    m = node >= 0
+    val = a + (x[m] - p) @ G
+    assert abs(psi[m, 0] @ val - a) < 1e-11
+    assert np.abs(psi[m, 1:].T @ val - G).max() < 1e-11
+
+
+@settings(max_examples=25, deadline=None)
+@given(seed=st.integers(0, 2 ** 31 - 1), amp=st.floats(0.01, 0.3, **_finite),
+       which=st.sampled_from([1, 2, 4, 7]))
+def test_membrane_balance_on_random_shapes(seed, amp, which):
+    """Randomly deformed capsules: stretching, bending and volume forces
+    (and their sum) exert no net force or torque."""
+    b, s = _capsule_sim()
+    x = b.x + np.random.default_rng(seed).normal(scale=amp, size=b.x.shape)
+    _, F = s.membrane(0, x, which)
+    scale = max(np.abs(F).max(), 1e-300)
+    assert np.abs(F.sum(0)).max() < 1e-12 * scale * len(x)
+    assert np.abs(np.cross(x, F).sum(0)).max() < 1e-11 * scale * len(x)
