@@ -185,10 +185,28 @@ lbm_status ib_interpolate(lbm_ctx *ctx, int64_t n, const double *d_pts, const do
 lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double *d_F,
                      const double *d_c, double *d_fib);
 
-/* Discrete adjoint of the step: not available in this build
- * (LBM_E_UNSUPPORTED). */
-lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t n_steps, const double *d_dJ_dstate,
-                            double *d_grad_params);
+/* Discrete adjoint of the fluid step (Eqs. evoleq, forcing, bbouzidi,
+ * extbound taken as one map g^k -> g^{k+1} of the post-collision deviations
+ * g = f - w_i).  For the n_steps-step trajectory that starts from the
+ * context's current state g^0 and the objective
+ *   J = <lambda, g^n> + sum_{t=1..n} <w, g^t>
+ * (lambda, w: [19][N] FP64 device arrays, N = nx ny nz, x fastest; w may be
+ * NULL), it returns in d_lambda (overwritten) dJ/dg^0 and in d_grad (4
+ * doubles, device) dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz: s scales the wall velocity
+ * of every velocity-face (inlet) node, F is the uniform body force, both
+ * held fixed over the n steps, derivatives at the context's own values
+ * (s = 1).  The gradient is the exact derivative of the FP64 step
+ * (node-local Jacobians by forward-mode differentiation of the collision and
+ * Zou-He; exact transposes of the streaming and bounce-back).  Entries of w
+ * and lambda at solid nodes are ignored; dJ/dg^0 is zero there.
+ * Checkpoints: the state is kept every checkpoint_every steps and each
+ * segment is recomputed once in the reverse sweep (device memory
+ * (ceil(n/K) + max(K, 2) + 4) x 19 x plane doubles, allocated and freed by
+ * the call; LBM_E_NOMEM if it does not fit).  The context's state and step
+ * count are not changed.  FP64 contexts without bodies only (else
+ * LBM_E_UNSUPPORTED).  Synchronises the context's stream. */
+lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t n_steps, int32_t checkpoint_every,
+                            const double *d_w, double *d_lambda, double *d_grad);
 
 /* Checkpoint / restart of the full state (populations, force field, body
  * state) to a binary file; lbm_load requires a context created with the

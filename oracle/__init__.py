@@ -90,6 +90,7 @@ def lib():
     for name in ("orc_get_fields",):
         getattr(L, name).argtypes = [vp, _P(d), _P(d)]
     L.orc_get_populations.argtypes = [vp, _P(d)]
+    L.orc_get_populations_at.argtypes = [vp, i64, _P(i64), _P(d)]
     L.orc_get_force.argtypes = [vp, _P(d)]
     L.orc_get_body.argtypes = [vp, C.c_int, _P(d), _P(d)]
     L.orc_body_diag.argtypes = [vp, C.c_int, _P(d)]
@@ -229,6 +230,13 @@ class OracleSim:
         f = np.zeros(19 * self.N)
         lib().orc_get_populations(self._h, _ptr(f, C.c_double))
         return f.reshape(19, self.N)
+
+    def populations_at(self, nodes):
+        """f_i at the listed node indices only, [19][len(nodes)]."""
+        idx = np.ascontiguousarray(nodes, np.int64)
+        f = np.zeros(19 * len(idx))
+        lib().orc_get_populations_at(self._h, len(idx), _ptr(idx, C.c_int64), _ptr(f, C.c_double))
+        return f.reshape(19, len(idx))
 
     def force(self):
         f = np.zeros(3 * self.N)

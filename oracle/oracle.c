@@ -1303,6 +1303,14 @@ void orc_get_populations(const orc_sim *s, double *f) {
       f[(long)i * s->N + n] = s->type[n] == T_SOLID ? 0.0 : Wt[i] + s->fs[19 * n + i];
 }
 
+/* The populations f_i of the listed nodes only: f[i * n + k] for node
+ * nodes[k] (the same values as orc_get_populations). */
+void orc_get_populations_at(const orc_sim *s, long n, const long *nodes, double *f) {
+  for (long k = 0; k < n; k++)
+    for (int i = 0; i < 19; i++)
+      f[(long)i * n + k] = s->type[nodes[k]] == T_SOLID ? 0.0 : Wt[i] + s->fs[19 * nodes[k] + i];
+}
+
 void orc_get_force(const orc_sim *s, double *fib) {
   for (long n = 0; n < s->N; n++)
     for (int a = 0; a < 3; a++) fib[(long)a * s->N + n] = s->fib[3 * n + a];

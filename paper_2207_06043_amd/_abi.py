@@ -114,7 +114,7 @@ def load_library():
     L.ib_spread.restype = st
     L.ib_spread.argtypes = [vp, i64, vp, vp, vp, vp]
     L.lbm_adjoint_step.restype = st
-    L.lbm_adjoint_step.argtypes = [vp, i32, vp, vp]
+    L.lbm_adjoint_step.argtypes = [vp, i32, i32, vp, vp, vp]
     L.lbm_save.restype = st
     L.lbm_save.argtypes = [vp, C.c_char_p]
     L.lbm_load.restype = st
@@ -327,8 +327,20 @@ class Lattice:
         self.stream.synchronize()
         return fib
 
-    def adjoint_step(self, n=1):
-        self._check(load_library().lbm_adjoint_step(self._h, int(n), None, None))
+    def adjoint(self, n_steps, lam, w=None, checkpoint_every=100):
+        """Gradient of J = <lam, g^n> + sum_{t=1..n} <w, g^t> over the
+        n_steps-step trajectory from the current state (g: the populations'
+        deviations f - w_i, [19][N]); returns (dJ/dg^0 [19][N],
+        [dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz]) with s the inlet-velocity scale and
+        F the body force.  The lattice's state is not changed."""
+        t = self._torch
+        lam = lam.to(self.device, t.float64).reshape(19, self.N).clone()
+        wd = None if w is None else w.to(self.device, t.float64).reshape(19, self.N).contiguous()
+        grad = self._empty(4)
+        self._check(load_library().lbm_adjoint_step(self._h, int(n_steps), int(checkpoint_every),
+                                                    _ptr(wd), _ptr(lam), _ptr(grad)))
+        self.stream.synchronize()
+        return lam, grad
 
     def save(self, path):
         self._check(load_library().lbm_save(self._h, str(path).encode()))

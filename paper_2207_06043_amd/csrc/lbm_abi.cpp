@@ -1607,9 +1607,114 @@ extern "C" lbm_status ib_spread(lbm_ctx* ctx, int64_t n, const double* d_pts, co
   return LBM_OK;
 }
 
-extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t, const double*, double*) {
+// ----------------------------------------------------------------- adjoint
+// Reverse sweep over n steps from the current state with checkpoints every
+// K steps: a forward pass keeps g at the start of every segment; then, from
+// the last segment back, the segment's states are recomputed into a tape
+// and the adjoint steps run over them in reverse.  The context's own state
+// and counters are left as they are.
+namespace {
+struct AdjBuffers {
+  std::vector<double*> ck, tape;
+  double *lam = nullptr, *lam2 = nullptr, *mu = nullptr, *w = nullptr, *part = nullptr;
+  int32_t* olist = nullptr;
+  ~AdjBuffers() {
+    for (double* p : ck) hipFree(p);
+    for (double* p : tape) hipFree(p);
+    for (double* p : {lam, lam2, mu, w, part})
+      if (p) hipFree(p);
+    if (olist) hipFree(olist);
+  }
+};
+}  // namespace
+
+extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t every, const double* d_w,
+                                       double* d_lambda, double* d_grad) {
   if (!ctx) return LBM_E_INVAL;
-  return fail(ctx, LBM_E_UNSUPPORTED, "the discrete adjoint is not available in this build");
+  if (ctx->broken) return LBM_E_STATE;
+  if (n_steps < 0 || every < 1 || !d_lambda || !d_grad)
+    return fail(ctx, LBM_E_INVAL, "adjoint: n_steps >= 0, checkpoint interval >= 1, lambda and grad required");
+  if (ctx->prec != LBM_F64) return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: FP64 contexts only");
+  if (!ctx->bodies.empty()) return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: contexts without bodies only");
+  DevFlags h;
+  lbm_status st = read_flags(ctx, &h);
+  if (st) return st;
+  CHK(ensure_bulk_list(ctx));
+  const Grid& G = ctx->g;
+  const size_t sbytes = 19 * (size_t)G.plane * sizeof(double);
+  const int nseg = n_steps == 0 ? 0 : (n_steps + every - 1) / every;
+  const int tlen = n_steps == 0 ? 0 : std::min(every, n_steps);
+  // the records on an open face (Zou-He)
+  std::vector<uint8_t> rf(ctx->nrec);
+  if (ctx->nrec) CHK(hipMemcpy(rf.data(), ctx->rec_face, ctx->nrec, hipMemcpyDeviceToHost));
+  std::vector<int32_t> ol;
+  for (int r = 0; r < ctx->nrec; r++)
+    if (rf[r] != 0xff) ol.push_back(r);
+  AdjBuffers m;
+  auto grab = [&](void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return false;
+    }
+    return true;
+  };
+  m.ck.assign(nseg, nullptr);
+  m.tape.assign(std::max(tlen, 2), nullptr);
+  bool ok = grab((void**)&m.lam, sbytes) && grab((void**)&m.lam2, sbytes) && grab((void**)&m.mu, sbytes) &&
+            grab((void**)&m.part, 4 * ADJ_BLOCKS * sizeof(double)) && (!d_w || grab((void**)&m.w, sbytes)) &&
+            (ol.empty() || grab((void**)&m.olist, ol.size() * sizeof(int32_t)));
+  for (auto& p : m.ck) ok = ok && grab((void**)&p, sbytes);
+  for (auto& p : m.tape) ok = ok && grab((void**)&p, sbytes);
+  if (!ok) return fail(ctx, LBM_E_NOMEM, "adjoint: not enough device memory for the checkpoints and the tape");
+  hipStream_t s = ctx->stream;
+  // solid entries stay zero in every buffer (never written by the sweep)
+  for (double* p : {m.lam, m.lam2, m.mu, m.w})
+    if (p) CHK(hipMemsetAsync(p, 0, sbytes, s));
+  for (double* p : m.ck) CHK(hipMemsetAsync(p, 0, sbytes, s));
+  for (double* p : m.tape) CHK(hipMemsetAsync(p, 0, sbytes, s));
+  CHK(hipMemsetAsync(m.part, 0, 4 * ADJ_BLOCKS * sizeof(double), s));
+  if (!ol.empty()) CHK(hipMemcpyAsync(m.olist, ol.data(), ol.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  CHK(launch_adjoint_layout(G, ctx->ncls, d_lambda, m.lam, 1, s));
+  if (d_w) CHK(launch_adjoint_layout(G, ctx->ncls, d_w, m.w, 1, s));
+  FluidArgs a = fluid_args(ctx, 0);
+  a.fx = nullptr;
+  a.tflag = nullptr;
+  a.mac = nullptr;
+  a.bulk_list = ctx->bulk_list;
+  a.nbulk_nodes = (int)ctx->n_bulk;
+  // forward pass: the state at the start of every segment
+  if (nseg > 0) {
+    CHK(hipMemcpyAsync(m.ck[0], ctx->f[h.steps_done & 1], sbytes, hipMemcpyDeviceToDevice, s));
+    for (int c = 1; c < nseg; c++) {
+      const double* src = m.ck[c - 1];
+      for (int k = 0; k < every; k++) {
+        a.A = src;
+        a.B = k == every - 1 ? m.ck[c] : m.tape[k & 1];
+        CHK(launch_adjoint_forward(a, s));
+        src = (const double*)a.B;
+      }
+    }
+  }
+  // reverse pass, segment by segment: recompute its states, then step back
+  for (int c = nseg - 1; c >= 0; c--) {
+    const int len = std::min(every, n_steps - c * every);
+    CHK(hipMemcpyAsync(m.tape[0], m.ck[c], sbytes, hipMemcpyDeviceToDevice, s));
+    for (int k = 1; k < len; k++) {
+      a.A = m.tape[k - 1];
+      a.B = m.tape[k];
+      CHK(launch_adjoint_forward(a, s));
+    }
+    for (int k = len - 1; k >= 0; k--) {
+      a.A = m.tape[k];
+      CHK(launch_adjoint_step(a, m.olist, (int)ol.size(), m.lam, m.w, m.mu, m.lam2, m.part, s));
+      std::swap(m.lam, m.lam2);
+    }
+  }
+  CHK(launch_adjoint_layout(G, ctx->ncls, m.lam, d_lambda, 0, s));
+  CHK(launch_adjoint_grad(m.part, d_grad, s));
+  CHK(hipStreamSynchronize(s));
+  return LBM_OK;
 }
 
 // ------------------------------------------------------- checkpoint / restart

@@ -167,6 +167,21 @@ hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s);
 // node count, sum of deviations, momentum); part holds 5 x 1024 doubles.
 hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void* f1, const uint8_t* ncls,
                             const DevFlags* flags, double* part, double* out, hipStream_t s);
+// Adjoint of the fluid step (FP64, no bodies; FluidArgs with A = the state
+// g^k in [19][plane], bulk_list/nbulk_nodes set).  Solid entries of every
+// buffer of the sweep hold zero and are never written.
+// launch_adjoint_forward: g^{k+1} = step(A) into B.
+// launch_adjoint_step: lam_out = dJ/dg^k from lam_in + w = dJ/dg^{k+1}
+// (w may be null; mu is scratch of the same layout; olist: the nopen
+// records on an open face); part[ADJ_BLOCKS][4] += the step's derivatives
+// of the inlet-velocity scale and the body force.
+constexpr int ADJ_BLOCKS = 1024;
+hipError_t launch_adjoint_forward(const FluidArgs& a, hipStream_t s);
+hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const double* lam_in,
+                               const double* w, double* mu, double* lam_out, double* part, hipStream_t s);
+hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,
+                                 hipStream_t s);
+hipError_t launch_adjoint_grad(const double* part, double* grad, hipStream_t s);
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,

@@ -279,7 +279,7 @@ __device__ __forceinline__ typename Store<S>::C bfl_value(const Bfl<S>& b) {
 // from outside the box reads the node's own rest value (no traffic) and is
 // not used.
 template <class S>
-__device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19]) {
+__device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19], bool zh = true) {
   typedef typename Store<S>::C C;
   const Grid& G = a.g;
   const long long node = a.rec_node[r];
@@ -311,7 +311,7 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
     const bool unknown = fc != 0xff && s * (ax == 0 ? e[0] : (ax == 1 ? e[1] : e[2])) == 1;
     g[j] = linked ? bfl_value<S>(bb[j]) : (unknown ? C(0) : pl[j]);
   }
-  if (fc != 0xff) {
+  if (fc != 0xff && zh) {
     zouhe<C>(g, face, kind, (C)a.rec_bc[r], (C)a.rec_bc[a.nrec + r], (C)a.rec_bc[2 * a.nrec + r],
              (C)a.rec_bc[3 * a.nrec + r]);
   }
@@ -2385,6 +2385,318 @@ hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void*
     default: k_diag_sum<_Float16><<<DIAG_SUM_BLOCKS, 256, 0, s>>>(g, (const _Float16*)f0, (const _Float16*)f1, ncls, flags, part); break;
   }
   k_diag_final<<<1, 256, 0, s>>>(part, DIAG_SUM_BLOCKS, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- adjoint
+// Discrete adjoint of the fluid step (FP64, no bodies).  One step maps the
+// post-collision deviations g^k to g^{k+1} = C(P(g^k)): P is the streaming
+// (plain pulls, interpolated bounce-back, Zou-He -- affine in g^k) and C
+// the forced BGK collision of each node.  Given lam = dJ/dg^{k+1}, the step
+// back is mu = (dC/dh)^T lam node by node, then lam' = P^T mu.  The
+// node-local Jacobian products are forward-mode derivatives of the very
+// collide and Zou-He templates the step runs, one seed per input.
+struct Dual {
+  double v, d;
+  __device__ Dual() : v(0.0), d(0.0) {}
+  __device__ Dual(double x) : v(x), d(0.0) {}
+  __device__ Dual(double x, double dx) : v(x), d(dx) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+__device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+__device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+__device__ __forceinline__ bool operator==(Dual a, Dual b) { return a.v == b.v; }
+
+__device__ __forceinline__ bool zh_unknown(int fc, int j) {
+  const int face = fc & 7, ax = face >> 1, sg = (face & 1) ? -1 : 1;
+  return fc != 0xff && sg * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j])) == 1;
+}
+
+// One forward step of the FP64 fluid (the same pull and collision as the
+// stream-collide kernels) from a.A into a.B: the bulk nodes (a.bulk_list)
+// here, the boundary records in k_adj_fwd_rec.  Solid nodes are not
+// written (they hold zero in every buffer of the sweep).
+__global__ __launch_bounds__(256) void k_adj_fwd_bulk(FluidArgs a) {
+  const Grid& G = a.g;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.nbulk_nodes) return;
+  const long long n = a.bulk_list[t];
+  const double* A = (const double*)a.A;
+  double* B = (double*)a.B;
+  int x, y, z;
+  coords(G, n, x, y, z);
+  double g[19], dr, ux, uy, uz;
+#pragma unroll
+  for (int j = 0; j < 19; j++) g[j] = A[(long long)j * G.plane + nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j])];
+  collide<double>(g, a.gx, a.gy, a.gz, a.omega, dr, ux, uy, uz);
+#pragma unroll
+  for (int j = 0; j < 19; j++) B[(long long)j * G.plane + n] = g[j];
+}
+
+__global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= a.nrec) return;
+  double g[19], dr, ux, uy, uz;
+  pull_general<double>(a, r, g);
+  collide<double>(g, a.gx, a.gy, a.gz, a.omega, dr, ux, uy, uz);
+  const long long n = a.rec_node[r];
+  double* B = (double*)a.B;
+#pragma unroll
+  for (int j = 0; j < 19; j++) B[(long long)j * a.g.plane + n] = g[j];
+}
+
+// The transpose of the collision's Jacobian, written out: with
+// Phi = sum_i l_i (omega g^eq_i + G_i) as a function of (rho - 1, u, F),
+//   P   = dPhi/d(rho - 1) at fixed u,  U_a = dPhi/du_a,  Q_a = dPhi/dF_a at fixed u,
+// and du_a/dh_j = (e_ja - u_a)/rho, d(rho - 1)/dh_j = 1, du_a/dF_a = 1/(2 rho):
+//   mu_j = (1 - omega) l_j + P + sum_a U_a (e_ja - u_a)/rho,
+//   dJ/dF_a += Q_a + U_a/(2 rho).
+// With the sums over i of w_i l_i times 1, (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u),
+// (3 + 9 e.u) e_a and (e.F) e_a (SL, P', V_a, Z_a):
+//   P = omega P',  U_a = omega rho V_a + 9 kf Z_a - 3 (omega rho u_a + kf F_a) SL,
+//   Q_a = kf (V_a - 3 u_a SL),  kf = 1 - omega/2.
+__device__ __forceinline__ void collide_vjp(const double (&h)[19], const double (&l)[19], double Fx, double Fy,
+                                            double Fz, double omega, double (&mu)[19], double (&dF)[3]) {
+  const double drho = dev_sum(h);
+  const double mx = (h[1] - h[2]) + (h[7] + h[8]) + (h[9] + h[10]) - (h[11] + h[12]) - (h[13] + h[14]);
+  const double my = (h[3] - h[4]) + (h[7] - h[8]) + (h[11] - h[12]) + (h[15] + h[16]) - (h[17] + h[18]);
+  const double mz = (h[5] - h[6]) + (h[9] - h[10]) + (h[13] - h[14]) + (h[15] - h[16]) + (h[17] - h[18]);
+  const double rho = 1.0 + drho, ir = 1.0 / rho;
+  const double ux = (mx + 0.5 * Fx) * ir, uy = (my + 0.5 * Fy) * ir, uz = (mz + 0.5 * Fz) * ir;
+  const double usq = ux * ux + uy * uy + uz * uz;
+  const double kf = 1.0 - 0.5 * omega;
+  double SL = 0.0, Pp = 0.0, V0 = 0.0, V1 = 0.0, V2 = 0.0, Z0 = 0.0, Z1 = 0.0, Z2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 19; i++) {
+    const double eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+    const double eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
+    const double wl = WD[i] * l[i];
+    SL += wl;
+    Pp += wl * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+    const double v = wl * (3.0 + 9.0 * eu), zz = wl * eF;
+    if (EX[i]) { V0 += EX[i] * v; Z0 += EX[i] * zz; }
+    if (EY[i]) { V1 += EY[i] * v; Z1 += EY[i] * zz; }
+    if (EZ[i]) { V2 += EZ[i] * v; Z2 += EZ[i] * zz; }
+  }
+  const double orho = omega * rho;
+  const double U0 = orho * V0 + 9.0 * kf * Z0 - 3.0 * (orho * ux + kf * Fx) * SL;
+  const double U1 = orho * V1 + 9.0 * kf * Z1 - 3.0 * (orho * uy + kf * Fy) * SL;
+  const double U2 = orho * V2 + 9.0 * kf * Z2 - 3.0 * (orho * uz + kf * Fz) * SL;
+  const double A0 = omega * Pp - (U0 * ux + U1 * uy + U2 * uz) * ir;
+  const double a0 = U0 * ir, a1 = U1 * ir, a2 = U2 * ir;
+#pragma unroll
+  for (int j = 0; j < 19; j++) mu[j] = (1.0 - omega) * l[j] + A0 + (EX[j] * a0 + EY[j] * a1 + EZ[j] * a2);
+  dF[0] += kf * (V0 - 3.0 * ux * SL) + 0.5 * a0;
+  dF[1] += kf * (V1 - 3.0 * uy * SL) + 0.5 * a1;
+  dF[2] += kf * (V2 - 3.0 * uz * SL) + 0.5 * a2;
+}
+
+// mu = (dC/dh)^T (lam + w) at the bulk nodes (REC false, a.bulk_list) or at the boundary
+// records (REC true; h: the populations that entered the collision, Zou-He
+// applied); part[block][1..3] += the step's derivatives of the body force
+// (fixed order: bitwise reproducible).  Two kernels, so that the bulk one
+// keeps the small register budget of the plain pull.
+template <bool REC>
+__global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, const double* lam, const double* w,
+                                                     double* mu, double* part) {
+  __shared__ double sh[8];
+  const Grid& G = a.g;
+  double dF[3] = {0.0, 0.0, 0.0};
+  const int count = REC ? a.nrec : a.nbulk_nodes;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256) {
+    double h[19], l[19], m[19];
+    long long n;
+    if (REC) {
+      n = a.rec_node[t];
+      pull_general<double>(a, t, h);
+    } else {
+      n = a.bulk_list[t];
+      int x, y, z;
+      coords(G, n, x, y, z);
+#pragma unroll
+      for (int j = 0; j < 19; j++)
+        h[j] = ((const double*)a.A)[(long long)j * G.plane + nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j])];
+    }
+#pragma unroll
+    for (int j = 0; j < 19; j++) l[j] = lam[(long long)j * G.plane + n] + (w ? w[(long long)j * G.plane + n] : 0.0);
+    collide_vjp(h, l, a.gx, a.gy, a.gz, a.omega, m, dF);
+#pragma unroll
+    for (int j = 0; j < 19; j++) mu[(long long)j * G.plane + n] = m[j];
+  }
+  const double t1 = block_sum(dF[0], sh);
+  const double t2 = block_sum(dF[1], sh);
+  const double t3 = block_sum(dF[2], sh);
+  if (threadIdx.x == 0) {
+    double* p = part + 4 * blockIdx.x;
+    p[1] += t1;
+    p[2] += t2;
+    p[3] += t3;
+  }
+}
+
+// Zou-He's transpose at the open-face records (olist): mu (taken at the
+// populations after Zou-He) -> mu at the populations before it, by
+// forward-mode derivatives of the same rule.  32 lanes per record, lane k
+// < 19 seeds input k (the unknown inputs are overwritten by the rule: no
+// derivative), lane 19 seeds the scale of the wall velocity of a velocity
+// face: part[block][0] += its derivative.
+__global__ __launch_bounds__(256) void k_adj_zouhe(FluidArgs a, const int32_t* olist, int nopen, double* mu,
+                                                   double* part) {
+  __shared__ double sh[8];
+  const Grid& G = a.g;
+  const int k = threadIdx.x & 31;
+  double gs = 0.0;
+  const int groups = (nopen + 7) / 8;
+  for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {  // the same trip count for the whole block
+    const int o = grp * 8 + (threadIdx.x >> 5);
+    const bool act = o < nopen && k < 20;
+    double res = 0.0;
+    long long n = 0;
+    if (act) {
+      const int r = olist[o];
+      const int fc = a.rec_face[r];
+      n = a.rec_node[r];
+      if (!(k < 19 && zh_unknown(fc, k))) {
+        double h[19];
+        pull_general<double>(a, r, h, false);
+        const int face = fc & 7, kind = (fc >> 4) & 1;
+        double bc[4];
+        for (int q = 0; q < 4; q++) bc[q] = a.rec_bc[(long long)q * a.nrec + r];
+        Dual x[19];
+#pragma unroll
+        for (int j = 0; j < 19; j++) x[j] = Dual(h[j], j == k ? 1.0 : 0.0);
+        const double sd = (k == 19 && kind == 0) ? 1.0 : 0.0;
+        zouhe<Dual>(x, face, kind, Dual(bc[0], sd * bc[0]), Dual(bc[1], sd * bc[1]), Dual(bc[2], sd * bc[2]),
+                    Dual(bc[3]));
+#pragma unroll
+        for (int j = 0; j < 19; j++) res += mu[(long long)j * G.plane + n] * x[j].d;
+      }
+    }
+    __syncthreads();  // every lane of the record has read mu before it is replaced
+    if (act) {
+      if (k < 19) mu[(long long)k * G.plane + n] = res;
+      else gs += res;
+    }
+    __syncthreads();
+  }
+  const double t0 = block_sum(gs, sh);
+  if (threadIdx.x == 0) part[4 * blockIdx.x] += t0;
+}
+
+// The transpose of the plain pulls, at every non-solid node y (bulk list,
+// then the records): lam'[j][y] = mu[j][y + e_j] where node y + e_j pulls
+// direction j plainly from y, else 0.
+__global__ __launch_bounds__(256) void k_adj_gather(FluidArgs a, const double* mu, double* lam) {
+  const Grid& G = a.g;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.nbulk_nodes + a.nrec) return;
+  const long long y = t < a.nbulk_nodes ? (long long)a.bulk_list[t] : (long long)a.rec_node[t - a.nbulk_nodes];
+  int px, py, pz;
+  coords(G, y, px, py, pz);
+  for (int j = 0; j < 19; j++) {
+    const long long x = j == 0 ? y : nbr(G, px, py, pz, EX[j], EY[j], EZ[j]);
+    const uint8_t c = a.ncls[x];
+    bool plain = c == CLS_BULK;
+    if (c == CLS_GENERAL) {
+      const int r = a.rec_of[x];
+      plain = j == 0 || (!((a.rec_mask[r] >> j) & 1u) && !zh_unknown(a.rec_face[r], j));
+    }
+    lam[(long long)j * G.plane + y] = plain ? mu[(long long)j * G.plane + x] : 0.0;
+  }
+}
+
+// The transpose of the interpolated bounce-back: the mu of each linked
+// direction goes back to the three populations its rule read.
+__global__ __launch_bounds__(256) void k_adj_links(FluidArgs a, const double* mu, double* lam) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= a.nrec) return;
+  const uint32_t mask = a.rec_mask[r];
+  if (!mask) return;
+  const Grid& G = a.g;
+  const long long node = a.rec_node[r];
+  const uint32_t hqm = a.rec_mb[r];
+  const int lk0 = a.rec_link0[r];
+  const double* lc = (const double*)a.lk_c;
+  const long long nl = a.nlinks;
+  int x, y, z;
+  coords(G, node, x, y, z);
+  for (int j = 1; j < 19; j++) {
+    if (!((mask >> j) & 1u)) continue;
+    const int l = lk0 + __popc(mask & ((1u << j) - 1u));
+    const int i = OPP[j];
+    const bool hq = (hqm >> j) & 1u;
+    const double m = mu[(long long)j * G.plane + node];
+    const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
+    const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
+    const double k0 = lc[l], k1 = lc[nl + l], k2 = lc[2 * nl + l];
+    if (k0 != 0.0) atomicAdd(lam + (long long)i * G.plane + node, k0 * m);
+    if (k1 != 0.0) atomicAdd(lam + (long long)(hq ? j : i) * G.plane + (hq ? node : n1), k1 * m);
+    if (k2 != 0.0) atomicAdd(lam + (long long)(hq ? j : i) * G.plane + (hq ? n1 : n2), k2 * m);
+  }
+}
+
+// [19][N] with x fastest (N = nx ny nz) <-> the padded [19][plane] layout;
+// towards the padded side only the non-solid nodes are written.
+__global__ void k_adj_layout(Grid G, const uint8_t* ncls, const double* in, double* out, int to_padded) {
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= G.Np) return;
+  const long long N = (long long)G.nx * G.ny * G.nz;
+  const unsigned int t = (unsigned int)(p / G.px);
+  const int x = (int)(p - (long long)t * G.px);
+  const long long n = x + (long long)G.nx * t;
+  const bool solid = ncls[p] == CLS_SOLID;  // padding included
+  for (int j = 0; j < 19; j++) {
+    if (to_padded) {
+      if (!solid) out[(long long)j * G.plane + p] = in[(long long)j * N + n];
+    } else if (x < G.nx) {
+      out[(long long)j * N + n] = in[(long long)j * G.plane + p];
+    }
+  }
+}
+
+__global__ void k_adj_grad_final(const double* part, int nblk, double* grad) {
+  const int q = threadIdx.x;
+  if (q >= 4) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; b++) t += part[4 * b + q];
+  grad[q] = t;
+}
+
+hipError_t launch_adjoint_forward(const FluidArgs& a, hipStream_t s) {
+  if (a.nbulk_nodes > 0) k_adj_fwd_bulk<<<cdiv(a.nbulk_nodes, 256), 256, 0, s>>>(a);
+  if (a.nrec > 0) k_adj_fwd_rec<<<cdiv(a.nrec, 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const double* lam_in,
+                               const double* w, double* mu, double* lam_out, double* part, hipStream_t s) {
+  if (a.nbulk_nodes > 0) {
+    k_adj_collide<false><<<std::min<unsigned>(cdiv(a.nbulk_nodes, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu,
+                                                                                                  part);
+  }
+  if (a.nrec > 0) {
+    k_adj_collide<true><<<std::min<unsigned>(cdiv(a.nrec, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu, part);
+  }
+  if (nopen > 0) k_adj_zouhe<<<std::min<unsigned>(cdiv(nopen, 8), ADJ_BLOCKS), 256, 0, s>>>(a, olist, nopen, mu, part);
+  if (a.nbulk_nodes + a.nrec > 0) k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
+  if (a.nrec > 0) k_adj_links<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,
+                                 hipStream_t s) {
+  k_adj_layout<<<cdiv(g.Np, 256), 256, 0, s>>>(g, ncls, in, out, to_padded);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_grad(const double* part, double* grad, hipStream_t s) {
+  k_adj_grad_final<<<1, 64, 0, s>>>(part, ADJ_BLOCKS, grad);
   return hipGetLastError();
 }
 

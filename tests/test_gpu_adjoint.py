@@ -1,0 +1,241 @@
+"""The discrete adjoint of the fluid step (lbm_adjoint_step) against central
+finite differences taken on the FP64 oracle, which shares no code with it.
+
+Small cases (a straight pipe with Zou-He inlet/outlet and curved-wall
+bounce-back; a bifurcation from rest), objective
+    J = <c, f^n> + sum_{t=1..n} <w, f^t>
+with c a seeded random field on the fluid nodes and w the outward flux
+weights of the outlet nodes.  Checked: dJ/ds (inlet-velocity scale),
+dJ/dF (body force) and the state gradient dJ/dg^0, the last through the
+derivative along seeded perturbations of the initial density and
+velocity fields (the initial state is their equilibrium, Eq. eqfunc).
+
+Full size: the differentiation-form workload (256x128x40 bifurcation, 2000
+steps, checkpoints every 100) against the oracle's differences stored in
+tests/golden/adjoint_fd.npz: the time-integrated upper-daughter flux and
+the flux split.
+
+Bounds: the differences are taken at two step sizes; their gap estimates
+the finite-difference error.  The adjoint must lie within 1e-8 relative
+(the FP64 rounding of the n-step sums, with margin) plus 4x that gap.
+"""
+import copy
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_adjoint_fd as fdcase  # noqa: E402
+
+REL = 1e-8
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2207_06043_amd as P
+    P.load_library()
+    return P
+
+
+def _case(name):
+    if name == "pipe":
+        w = synth.tiny_pipe(precision="f64", with_body=False)
+    else:
+        w = synth.tiny_bifurcation(precision="f64", n_bodies=0)
+        d = w.domain
+        d.init_rho = np.ones(d.n_nodes)
+        d.init_u = np.zeros(3 * d.n_nodes)
+    d = w.domain
+    fl = d.node_type != synth.SOLID
+    rng = np.random.default_rng(11)
+    c = rng.standard_normal((19, d.n_nodes)) * fl
+    e = oracle.lattice()[0].astype(np.float64)
+    out = np.flatnonzero(d.node_type == synth.OUTLET)
+    wv = np.zeros((19, d.n_nodes))
+    # outward normal of each outlet node: the face it sits on
+    x, y, z = out % d.nx, (out // d.nx) % d.ny, out // (d.nx * d.ny)
+    nrm = np.zeros((len(out), 3))
+    nrm[x == d.nx - 1, 0] = 1
+    nrm[x == 0, 0] = -1
+    nrm[y == d.ny - 1, 1] = 1
+    nrm[y == 0, 1] = -1
+    nrm[z == d.nz - 1, 2] = 1
+    nrm[z == 0, 2] = -1
+    wv[:, out] = e @ nrm.T
+    du = 1e-3 * rng.standard_normal((3, d.n_nodes)) * fl
+    dr = 1e-3 * rng.standard_normal(d.n_nodes) * fl
+    return w, c, wv, du, dr
+
+
+def _J(d, w, n, c, wv):
+    sim = oracle.OracleSim(d, w.tau, w.u_max, threads=4)
+    J = 0.0
+    for _ in range(n):
+        assert sim.step(1) == 0
+        J += float(np.sum(wv * sim.populations()))
+    return J + float(np.sum(c * sim.populations()))
+
+
+def _perturb(d, what, h, du=None, dr=None):
+    q = copy.copy(d)
+    if what == "s":
+        q.inlet_u = d.inlet_u * (1.0 + h)
+    elif what in ("Fx", "Fy", "Fz"):
+        f = list(d.body_force)
+        f["xyz".index(what[1])] += h
+        q.body_force = tuple(f)
+    elif what == "u0":
+        q.init_u = d.init_u + h * du.ravel()
+    elif what == "rho0":
+        q.init_rho = d.init_rho + h * dr
+    return q
+
+
+def _fd(d, w, n, c, wv, what, hs, **kw):
+    return [(_J(_perturb(d, what, h, **kw), w, n, c, wv) - _J(_perturb(d, what, -h, **kw), w, n, c, wv)) / (2 * h)
+            for h in hs]
+
+
+def _check(name, adj, fds, scale):
+    gap = abs(fds[0] - fds[-1])
+    tol = REL * scale + 4 * gap
+    _say(f"  {name}: adjoint {adj:+.12e}  oracle FD {fds[-1]:+.12e}  |diff| {abs(adj - fds[-1]):.2e} "
+         f"(bound {tol:.2e})")
+    return abs(adj - fds[-1]) <= tol
+
+
+def _dfeq_du(rho, u, du):
+    """Derivative of the equilibrium deviations w_i (drho + rho (3 e.u +
+    9/2 (e.u)^2 - 3/2 u.u)) along a velocity change du; [19][N]."""
+    e, wts = (a.astype(np.float64) for a in oracle.lattice())
+    eu, edu = e @ u, e @ du
+    return wts[:, None] * rho * (3 * edu + 9 * eu * edu - 3 * np.sum(u * du, axis=0))
+
+
+def _dfeq_drho(rho, u, dr):
+    e, wts = (a.astype(np.float64) for a in oracle.lattice())
+    eu = e @ u
+    return wts[:, None] * dr * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * np.sum(u * u, axis=0))
+
+
+@pytest.mark.parametrize("name", ["pipe", "bifurcation"])
+def test_adjoint_matches_oracle_differences(lib, name):
+    import torch
+    w, c, wv, du, dr = _case(name)
+    d = w.domain
+    n, K = 30, 7                      # segments of 7, 7, 7, 7 and 2 steps
+    _say(f"[adjoint] {name} {d.nx}x{d.ny}x{d.nz}, {n} steps, checkpoints every {K}")
+    lat = lib.from_workload(w)
+    lam, grad = lat.adjoint(n, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=K)
+    lam, grad = lam.cpu().numpy(), grad.cpu().numpy()
+    fl = d.node_type != synth.SOLID
+    assert np.all(lam[:, ~fl] == 0)
+    ok = True
+    ok &= _check("dJ/ds", grad[0], _fd(d, w, n, c, wv, "s", (1e-4, 5e-5)), abs(grad[0]))
+    fscale = np.abs(grad[1:]).max()
+    for k, comp in enumerate(("Fx", "Fy", "Fz")):
+        ok &= _check(f"dJ/d{comp}", grad[1 + k], _fd(d, w, n, c, wv, comp, (1e-6, 5e-7)), fscale)
+    # the state gradient, along perturbations of the initial fields
+    rho0 = d.init_rho
+    u0 = d.init_u.reshape(3, -1)
+    adj_u = float(np.sum(lam * _dfeq_du(rho0, u0, du)))
+    adj_r = float(np.sum(lam * _dfeq_drho(rho0, u0, dr)))
+    ok &= _check("dJ/dg0 . dg0/du0 du", adj_u, _fd(d, w, n, c, wv, "u0", (1e-3, 5e-4), du=du), abs(adj_u))
+    ok &= _check("dJ/dg0 . dg0/drho0 drho", adj_r, _fd(d, w, n, c, wv, "rho0", (1e-3, 5e-4), dr=dr),
+                 abs(adj_r))
+    assert ok
+
+
+def test_adjoint_checkpoint_interval_and_state(lib):
+    """The result does not depend on the checkpoint interval (to rounding:
+    the bounce-back transpose adds with atomics), and the lattice's own
+    state is left as it was."""
+    import torch
+    w, c, wv, _, _ = _case("pipe")
+    lat = lib.from_workload(w)
+    lat.step(5)
+    lat.sync()
+    before = lat.populations().clone()
+    ref_lam, ref_g = lat.adjoint(23, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=23)
+    for K in (1, 4, 100):
+        lam, g = lat.adjoint(23, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=K)
+        e_l = float((lam - ref_lam).abs().max() / ref_lam.abs().max())
+        e_g = float(((g - ref_g).abs() / ref_g.abs().clamp_min(1e-300)).max())
+        _say(f"[adjoint] interval {K}: lambda {e_l:.1e}, grad {e_g:.1e}")
+        assert e_l <= 1e-13 and e_g <= 1e-12
+    assert torch.equal(lat.populations(), before)
+    assert lat.info()["steps_done"] == 5
+    lam, g = lat.adjoint(0, torch.from_numpy(c))
+    assert torch.equal(lam.cpu(), torch.from_numpy(c)) and torch.all(g == 0)
+
+
+def test_adjoint_rejects_unsupported_contexts(lib):
+    import torch
+    lam = torch.zeros(19, 8 * 8 * 8, dtype=torch.float64)
+    lat = lib.Lattice(synth.periodic_box(8, 8, 8), 0.8, precision="f32")
+    with pytest.raises(lib.LbmError) as e:
+        lat.adjoint(1, lam)
+    assert e.value.status == 7
+    wb = synth.tiny_pipe(precision="f64", rigid=True)
+    lb = lib.from_workload(wb)
+    with pytest.raises(lib.LbmError) as e:
+        lb.adjoint(1, torch.zeros(19, wb.domain.n_nodes, dtype=torch.float64))
+    assert e.value.status == 7
+    lat = lib.Lattice(synth.periodic_box(8, 8, 8), 0.8, precision="f64")
+    with pytest.raises(lib.LbmError) as e:
+        lat.adjoint(1, lam, checkpoint_every=0)
+    assert e.value.status == 1
+
+
+def test_differentiation_form_full_size(lib):
+    """2000 steps of the 256x128x40 bifurcation from rest, checkpoints every
+    100: gradients of the time-integrated upper-daughter flux and of the
+    flux split against the oracle's central differences."""
+    import torch
+    g = np.load(os.path.join(HERE, "golden", "adjoint_fd.npz"))
+    w = fdcase.workload()
+    w.bodies = []
+    d = w.domain
+    steps = int(g["steps"])
+    w_up, w_lo = fdcase.weights(d)
+    j_up, j_lo = g["base"]
+    lat = lib.from_workload(w)
+    zero = torch.zeros(19, d.n_nodes, dtype=torch.float64)
+    _say(f"[adjoint] full size {d.nx}x{d.ny}x{d.nz}, {steps} steps")
+    _, g_up = lat.adjoint(steps, zero, torch.from_numpy(w_up), checkpoint_every=100)
+    w_split = (j_lo * w_up - j_up * w_lo) / (j_up + j_lo) ** 2
+    _, g_split = lat.adjoint(steps, zero, torch.from_numpy(w_split), checkpoint_every=100)
+    g_up, g_split = g_up.cpu().numpy(), g_split.cpu().numpy()
+
+    def fd(p, which):
+        out = []
+        for h, (pu, pl), (mu, ml) in zip(g[f"h_{p}"], g[f"plus_{p}"], g[f"minus_{p}"]):
+            if which == "up":
+                out.append((pu - mu) / (2 * h))
+            else:
+                out.append((pu / (pu + pl) - mu / (mu + ml)) / (2 * h))
+        return out
+
+    ok = True
+    ok &= _check("dJ_up/ds", g_up[0], fd("s", "up"), abs(g_up[0]))
+    ok &= _check("dJ_up/dFx", g_up[1], fd("Fx", "up"), np.abs(g_up[1:]).max())
+    ok &= _check("dJ_up/dFy", g_up[2], fd("Fy", "up"), np.abs(g_up[1:]).max())
+    ok &= _check("dS/dFy", g_split[2], fd("Fy", "split"), abs(g_split[2]))
+    # the geometry is symmetric in y: the split does not move with s
+    ok &= _check("dS/ds", g_split[0], fd("s", "split"), abs(g_split[2]) * 1e-3)
+    assert ok

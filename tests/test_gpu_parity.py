@@ -277,13 +277,6 @@ def test_invalid_geometry_is_rejected(lib):
     assert e.value.status == 1
 
 
-def test_adjoint_reports_unsupported(lib):
-    lat = lib.Lattice(synth.periodic_box(8, 8, 8), 0.8)
-    with pytest.raises(lib.LbmError) as e:
-        lat.adjoint_step(1)
-    assert e.value.status == 7
-
-
 def test_checkpoint_roundtrip(lib, tmp_path):
     w = synth.tiny_pipe(precision="f32", rigid=False)
     a = lib.from_workload(w)
