@@ -1614,16 +1614,10 @@ extern "C" lbm_status ib_spread(lbm_ctx* ctx, int64_t n, const double* d_pts, co
 // and the adjoint steps run over them in reverse.  The context's own state
 // and counters are left as they are.
 namespace {
-struct AdjBuffers {
-  std::vector<double*> ck, tape;
-  double *lam = nullptr, *lam2 = nullptr, *mu = nullptr, *w = nullptr, *part = nullptr;
-  int32_t* olist = nullptr;
-  ~AdjBuffers() {
-    for (double* p : ck) hipFree(p);
-    for (double* p : tape) hipFree(p);
-    for (double* p : {lam, lam2, mu, w, part})
-      if (p) hipFree(p);
-    if (olist) hipFree(olist);
+struct DevArena {  // one allocation, carved in 256-byte aligned pieces
+  char* base = nullptr;
+  ~DevArena() {
+    if (base) hipFree(base);
   }
 };
 }  // namespace
@@ -1650,30 +1644,41 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   std::vector<int32_t> ol;
   for (int r = 0; r < ctx->nrec; r++)
     if (rf[r] != 0xff) ol.push_back(r);
-  AdjBuffers m;
-  auto grab = [&](void** p, size_t bytes) {
-    if (hipMalloc(p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      *p = nullptr;
-      return false;
-    }
-    return true;
+  // one arena: lam, lam2, mu, w, the checkpoints, the tape, then the small pieces
+  const size_t nbig = 4 + nseg + std::max(tlen, 2);
+  const size_t small = 4 * ADJ_BLOCKS * sizeof(double) + ol.size() * sizeof(int32_t) +
+                       ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + 3 * 256;
+  DevArena ar;
+  if (hipMalloc(&ar.base, nbig * sbytes + small) != hipSuccess) {
+    (void)hipGetLastError();
+    ar.base = nullptr;
+    return fail(ctx, LBM_E_NOMEM, "adjoint: not enough device memory for the checkpoints and the tape");
+  }
+  auto big = [&](size_t i) { return (double*)(ar.base + i * sbytes); };  // sbytes: a multiple of 8 * plane
+  struct {
+    double *lam, *lam2, *mu, *w, *part;
+    int32_t* olist;
+    uint32_t* pmask;
+    std::vector<double*> ck, tape;
+  } m;
+  m.lam = big(0);
+  m.lam2 = big(1);
+  m.mu = big(2);
+  m.w = d_w ? big(3) : nullptr;
+  for (int c = 0; c < nseg; c++) m.ck.push_back(big(4 + c));
+  for (int k = 0; k < std::max(tlen, 2); k++) m.tape.push_back(big(4 + nseg + k));
+  char* sp = ar.base + nbig * sbytes;
+  auto carve = [&](size_t bytes) {
+    char* p = (char*)(((uintptr_t)sp + 255) & ~(uintptr_t)255);
+    sp = p + bytes;
+    return (void*)p;
   };
-  m.ck.assign(nseg, nullptr);
-  m.tape.assign(std::max(tlen, 2), nullptr);
-  bool ok = grab((void**)&m.lam, sbytes) && grab((void**)&m.lam2, sbytes) && grab((void**)&m.mu, sbytes) &&
-            grab((void**)&m.part, 4 * ADJ_BLOCKS * sizeof(double)) && (!d_w || grab((void**)&m.w, sbytes)) &&
-            (ol.empty() || grab((void**)&m.olist, ol.size() * sizeof(int32_t)));
-  for (auto& p : m.ck) ok = ok && grab((void**)&p, sbytes);
-  for (auto& p : m.tape) ok = ok && grab((void**)&p, sbytes);
-  if (!ok) return fail(ctx, LBM_E_NOMEM, "adjoint: not enough device memory for the checkpoints and the tape");
+  m.part = (double*)carve(4 * ADJ_BLOCKS * sizeof(double));
+  m.olist = (int32_t*)carve(ol.size() * sizeof(int32_t));
+  m.pmask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
   hipStream_t s = ctx->stream;
   // solid entries stay zero in every buffer (never written by the sweep)
-  for (double* p : {m.lam, m.lam2, m.mu, m.w})
-    if (p) CHK(hipMemsetAsync(p, 0, sbytes, s));
-  for (double* p : m.ck) CHK(hipMemsetAsync(p, 0, sbytes, s));
-  for (double* p : m.tape) CHK(hipMemsetAsync(p, 0, sbytes, s));
-  CHK(hipMemsetAsync(m.part, 0, 4 * ADJ_BLOCKS * sizeof(double), s));
+  CHK(hipMemsetAsync(ar.base, 0, nbig * sbytes + 4 * ADJ_BLOCKS * sizeof(double) + 256, s));
   if (!ol.empty()) CHK(hipMemcpyAsync(m.olist, ol.data(), ol.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, d_lambda, m.lam, 1, s));
   if (d_w) CHK(launch_adjoint_layout(G, ctx->ncls, d_w, m.w, 1, s));
@@ -1683,6 +1688,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   a.mac = nullptr;
   a.bulk_list = ctx->bulk_list;
   a.nbulk_nodes = (int)ctx->n_bulk;
+  CHK(launch_adjoint_mask(a, m.pmask, s));
   // forward pass: the state at the start of every segment
   if (nseg > 0) {
     CHK(hipMemcpyAsync(m.ck[0], ctx->f[h.steps_done & 1], sbytes, hipMemcpyDeviceToDevice, s));
@@ -1707,7 +1713,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     }
     for (int k = len - 1; k >= 0; k--) {
       a.A = m.tape[k];
-      CHK(launch_adjoint_step(a, m.olist, (int)ol.size(), m.lam, m.w, m.mu, m.lam2, m.part, s));
+      CHK(launch_adjoint_step(a, m.olist, (int)ol.size(), m.pmask, m.lam, m.w, m.mu, m.lam2, m.part, s));
       std::swap(m.lam, m.lam2);
     }
   }

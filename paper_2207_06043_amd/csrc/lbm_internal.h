@@ -173,12 +173,15 @@ hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void*
 // launch_adjoint_forward: g^{k+1} = step(A) into B.
 // launch_adjoint_step: lam_out = dJ/dg^k from lam_in + w = dJ/dg^{k+1}
 // (w may be null; mu is scratch of the same layout; olist: the nopen
-// records on an open face); part[ADJ_BLOCKS][4] += the step's derivatives
+// records on an open face; pmask: from launch_adjoint_mask, one word per
+// bulk node then per record); part[ADJ_BLOCKS][4] += the step's derivatives
 // of the inlet-velocity scale and the body force.
 constexpr int ADJ_BLOCKS = 1024;
 hipError_t launch_adjoint_forward(const FluidArgs& a, hipStream_t s);
-hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const double* lam_in,
-                               const double* w, double* mu, double* lam_out, double* part, hipStream_t s);
+hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t s);
+hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const uint32_t* pmask,
+                               const double* lam_in, const double* w, double* mu, double* lam_out, double* part,
+                               hipStream_t s);
 hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,
                                  hipStream_t s);
 hipError_t launch_adjoint_grad(const double* part, double* grad, hipStream_t s);

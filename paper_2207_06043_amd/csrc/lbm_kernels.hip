@@ -2589,16 +2589,16 @@ __global__ __launch_bounds__(256) void k_adj_zouhe(FluidArgs a, const int32_t* o
   if (threadIdx.x == 0) part[4 * blockIdx.x] += t0;
 }
 
-// The transpose of the plain pulls, at every non-solid node y (bulk list,
-// then the records): lam'[j][y] = mu[j][y + e_j] where node y + e_j pulls
-// direction j plainly from y, else 0.
-__global__ __launch_bounds__(256) void k_adj_gather(FluidArgs a, const double* mu, double* lam) {
+// For every non-solid node y (bulk list, then the records): bit j set when
+// node y + e_j pulls direction j plainly from y (computed once per sweep).
+__global__ __launch_bounds__(256) void k_adj_mask(FluidArgs a, uint32_t* pmask) {
   const Grid& G = a.g;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= a.nbulk_nodes + a.nrec) return;
   const long long y = t < a.nbulk_nodes ? (long long)a.bulk_list[t] : (long long)a.rec_node[t - a.nbulk_nodes];
   int px, py, pz;
   coords(G, y, px, py, pz);
+  uint32_t m = 0;
   for (int j = 0; j < 19; j++) {
     const long long x = j == 0 ? y : nbr(G, px, py, pz, EX[j], EY[j], EZ[j]);
     const uint8_t c = a.ncls[x];
@@ -2607,7 +2607,27 @@ __global__ __launch_bounds__(256) void k_adj_gather(FluidArgs a, const double* m
       const int r = a.rec_of[x];
       plain = j == 0 || (!((a.rec_mask[r] >> j) & 1u) && !zh_unknown(a.rec_face[r], j));
     }
-    lam[(long long)j * G.plane + y] = plain ? mu[(long long)j * G.plane + x] : 0.0;
+    m |= plain ? (1u << j) : 0u;
+  }
+  pmask[t] = m;
+}
+
+// The transpose of the plain pulls, at every non-solid node y (bulk list,
+// then the records): lam'[j][y] = mu[j][y + e_j] where node y + e_j pulls
+// direction j plainly from y, else 0.
+__global__ __launch_bounds__(256) void k_adj_gather(FluidArgs a, const uint32_t* pmask, const double* mu,
+                                                    double* lam) {
+  const Grid& G = a.g;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.nbulk_nodes + a.nrec) return;
+  const long long y = t < a.nbulk_nodes ? (long long)a.bulk_list[t] : (long long)a.rec_node[t - a.nbulk_nodes];
+  const uint32_t m = pmask[t];
+  int px, py, pz;
+  coords(G, y, px, py, pz);
+#pragma unroll
+  for (int j = 0; j < 19; j++) {
+    const long long x = j == 0 ? y : nbr(G, px, py, pz, EX[j], EY[j], EZ[j]);
+    lam[(long long)j * G.plane + y] = ((m >> j) & 1u) ? mu[(long long)j * G.plane + x] : 0.0;
   }
 }
 
@@ -2674,8 +2694,14 @@ hipError_t launch_adjoint_forward(const FluidArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const double* lam_in,
-                               const double* w, double* mu, double* lam_out, double* part, hipStream_t s) {
+hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t s) {
+  if (a.nbulk_nodes + a.nrec > 0) k_adj_mask<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const uint32_t* pmask,
+                               const double* lam_in, const double* w, double* mu, double* lam_out, double* part,
+                               hipStream_t s) {
   if (a.nbulk_nodes > 0) {
     k_adj_collide<false><<<std::min<unsigned>(cdiv(a.nbulk_nodes, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu,
                                                                                                   part);
@@ -2684,7 +2710,7 @@ hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nop
     k_adj_collide<true><<<std::min<unsigned>(cdiv(a.nrec, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu, part);
   }
   if (nopen > 0) k_adj_zouhe<<<std::min<unsigned>(cdiv(nopen, 8), ADJ_BLOCKS), 256, 0, s>>>(a, olist, nopen, mu, part);
-  if (a.nbulk_nodes + a.nrec > 0) k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
+  if (a.nbulk_nodes + a.nrec > 0) k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, mu, lam_out);
   if (a.nrec > 0) k_adj_links<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
   return hipGetLastError();
 }
