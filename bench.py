@@ -81,6 +81,18 @@ def _counter_medians(run_dir, counter):
     return {k: statistics.median(v) for k, v in vals.items()}
 
 
+def _counter_totals(run_dir, counter):
+    """Sum over all dispatches (KiB) of a rocprofv3 --pmc counter for each
+    kernel name in run_dir/run_counter_collection.csv."""
+    import csv
+    tot = {}
+    with open(os.path.join(run_dir, "run_counter_collection.csv")) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                tot[r["Kernel_Name"]] = tot.get(r["Kernel_Name"], 0.0) + float(r["Counter_Value"])
+    return tot
+
+
 def summarize_counters(args):
     """Writes the HBM traffic of one launch of the fluid kernels (bulk +
     boundary records, the span the roofline times) into TRAFFIC_FILE, from
@@ -98,10 +110,18 @@ def summarize_counters(args):
 
     kf = copy_bytes / (only(_counter_medians(cp_f, "FETCH_SIZE"), "copyBuffer") * 1024.0)
     kw = copy_bytes / (only(_counter_medians(cp_w, "WRITE_SIZE"), "copyBuffer") * 1024.0)
-    fetch = _counter_medians(wl_f, "FETCH_SIZE")
-    write = _counter_medians(wl_w, "WRITE_SIZE")
-    rd = sum(1024.0 * kf * v for k, v in fetch.items() if any(n in k for n in FLUID_KERNELS))
-    wr = sum(1024.0 * kw * v for k, v in write.items() if any(n in k for n in FLUID_KERNELS))
+    if args.workload == "differentiation_form":
+        # every dispatch of the sweep's kernels, per adjoint step of the run
+        # (the warmup call and the timed call)
+        names, per = ADJ_KERNELS, 1.0 / (args.warmup + args.steps)
+        fetch = _counter_totals(wl_f, "FETCH_SIZE")
+        write = _counter_totals(wl_w, "WRITE_SIZE")
+    else:
+        names, per = FLUID_KERNELS, 1.0
+        fetch = _counter_medians(wl_f, "FETCH_SIZE")
+        write = _counter_medians(wl_w, "WRITE_SIZE")
+    rd = per * sum(1024.0 * kf * v for k, v in fetch.items() if any(n in k for n in names))
+    wr = per * sum(1024.0 * kw * v for k, v in write.items() if any(n in k for n in names))
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -118,7 +138,7 @@ def summarize_counters(args):
         "fetch_scale": round(kf, 5),
         "write_scale": round(kw, 5),
         "kernels": {k: {"FETCH_SIZE_KiB": fetch.get(k), "WRITE_SIZE_KiB": write.get(k)}
-                    for k in sorted(set(fetch) | set(write)) if any(n in k for n in FLUID_KERNELS)},
+                    for k in sorted(set(fetch) | set(write)) if any(n in k for n in names)},
     }
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:
@@ -163,7 +183,7 @@ def cpu_baseline(w, target_s=15.0):
     nf = w.domain.n_fluid
     return {"value": round(nf * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.lib().orc_threads(),
             "kind": "oracle",
-            "sample": f"{w.name}: {n} coupled steps (after 2 untimed) of the same grid and bodies, "
+            "sample": f"{w.name}: {n} steps (after 2 untimed) of the same grid and bodies, "
                       f"FP64, {dt:.1f} s (+{setup:.1f} s setup), lattice updates counted on fluid nodes"}
 
 
@@ -304,6 +324,116 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+# per fluid node and adjoint step, FP64: the forward pass and the segment
+# recompute (each a pull and a write of 19 populations, 2 x 304 B), the
+# collision transpose (reads the pulled populations, lambda and w, writes
+# mu: 608 B) and the transposed streaming (reads mu and a mask word, writes
+# lambda: 308 B)
+ADJ_BYTES_PER_NODE = 2 * 304 + 608 + 308
+ADJ_KERNELS = ("k_adj_",)
+
+
+def run_adjoint(args):
+    """The differentiation form: gradients of the time-integrated upper
+    daughter flux of the fluid-only bifurcation (256x128x40, D = 32, from
+    rest) with respect to the inlet-velocity scale and the body force, over
+    args.steps steps with checkpoints every args.checkpoint_every steps, in
+    one call of the adjoint; then the same number of plain FP64 steps for
+    the comparison."""
+    import torch
+    import numpy as np
+    import paper_2207_06043_amd as P
+    import synth
+    w = synth.bifurcation_capsule(precision="f64")
+    w.bodies = []
+    w.name = "differentiation_form (the bifurcation without its capsule)"
+    d = w.domain
+    torch.cuda.set_device(0)
+    lat = P.Lattice(d, w.tau, w.u_max, "f64")
+    info = lat.info()
+    n_fluid, n_box = info["n_fluid"], info["n_nodes"]
+    out_nodes = np.flatnonzero(d.node_type == synth.OUTLET)
+    up = out_nodes[(out_nodes // d.nx) % d.ny == d.ny - 1]
+    e_y = torch.tensor([0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1], dtype=torch.float64)
+    wv = torch.zeros(19, d.n_nodes, dtype=torch.float64)
+    wv[:, torch.from_numpy(up)] = e_y[:, None]
+    wv = wv.cuda()
+    lam0 = torch.zeros(19, d.n_nodes, dtype=torch.float64, device="cuda")
+    K = args.checkpoint_every
+    if args.warmup > 0:
+        lat.adjoint(args.warmup, lam0, wv, checkpoint_every=K)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(lat.stream)
+    lam, grad = lat.adjoint(args.steps, lam0, wv, checkpoint_every=K)
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    gpu_s = ev0.elapsed_time(ev1) * 1e-3
+    value = n_fluid * args.steps / elapsed / 1e6
+    # the same number of plain FP64 steps of the same lattice
+    lat.step(args.warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lat.step(args.steps)
+    lat.sync()
+    torch.cuda.synchronize()
+    plain = n_fluid * args.steps / (time.perf_counter() - t2) / 1e6
+    bytes_step = ADJ_BYTES_PER_NODE * n_fluid
+    achieved = bytes_step / (gpu_s / args.steps) / 1e9
+    g = grad.cpu().numpy()
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "differentiation_form",
+            "grid": [d.nx, d.ny, d.nz],
+            "fluid_nodes": n_fluid,
+            "box_nodes": n_box,
+            "bodies": 0,
+            "checkpoint_every": K,
+            "objective": "time-integrated upper-daughter flux; gradient w.r.t. inlet-velocity scale and body force",
+            "lups_counted_on": "fluid nodes x adjoint steps (forward pass, recompute and reverse step included)",
+            "plain_fp64_mlups": round(plain, 2),
+            "adjoint_vs_plain": round(value / plain, 4),
+            "grad": [float(x) for x in g],
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": ("one adjoint step: k_adj_collide (bulk, records), k_adj_zouhe, k_adj_gather, "
+                       "k_adj_links, plus the forward and recompute launches k_adj_fwd_bulk/k_adj_fwd_rec "
+                       "(no single kernel dominates)"),
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("differentiation_form", "f64"),
+            "bytes_per_step_alg": bytes_step,
+            "avg_step_us": round(gpu_s / args.steps * 1e6, 3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w, args.cpu_seconds)
+        cb["sample"] += ("; forward steps only: the oracle has no adjoint, a central-difference "
+                         "derivative costs two such runs per parameter")
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +455,8 @@ def main():
                     help="batch_instances: fluid launch shape 'V,block,mode,per_xcd' instead of tuning")
     ap.add_argument("--plain-steps", type=int, default=32,
                     help="batch_instances: steps of each instance alone for the comparison")
+    ap.add_argument("--checkpoint-every", type=int, default=100,
+                    help="differentiation_form: checkpoint interval of the adjoint sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
@@ -360,13 +492,17 @@ def main():
     # run lengths of the workloads: the bifurcation capsule 5000 steps after a
     # 2000-step precursor, the precision form 2000 steps after a 1000-step
     # precursor, the batching form 1000 steps
-    lengths = {"precision_form": (1000, 100, 1900), "batch_instances": (0, 50, 950)}
+    lengths = {"precision_form": (1000, 100, 1900), "batch_instances": (0, 50, 950),
+               "differentiation_form": (0, 200, 2000)}
     pre, warm, steps = lengths.get(args.workload, (2000, 200, 5000))
     args.precursor = pre if args.precursor is None else args.precursor
     args.warmup = warm if args.warmup is None else args.warmup
     args.steps = steps if args.steps is None else args.steps
     if args.workload == "batch_instances":
         run_batch(args)
+        return
+    if args.workload == "differentiation_form":
+        run_adjoint(args)
         return
     precision = args.precision or default_precision(args.workload)
     w = build_workload(args.workload, precision)

@@ -1646,7 +1646,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     if (rf[r] != 0xff) ol.push_back(r);
   // one arena: lam, lam2, mu, w, the checkpoints, the tape, then the small pieces
   const size_t nbig = 4 + nseg + std::max(tlen, 2);
-  const size_t small = 4 * ADJ_BLOCKS * sizeof(double) + ol.size() * sizeof(int32_t) +
+  const size_t small = 8 * ADJ_BLOCKS * sizeof(double) + ol.size() * sizeof(int32_t) +
                        ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + 3 * 256;
   DevArena ar;
   if (hipMalloc(&ar.base, nbig * sbytes + small) != hipSuccess) {
@@ -1673,12 +1673,12 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     sp = p + bytes;
     return (void*)p;
   };
-  m.part = (double*)carve(4 * ADJ_BLOCKS * sizeof(double));
+  m.part = (double*)carve(8 * ADJ_BLOCKS * sizeof(double));
   m.olist = (int32_t*)carve(ol.size() * sizeof(int32_t));
   m.pmask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
   hipStream_t s = ctx->stream;
   // solid entries stay zero in every buffer (never written by the sweep)
-  CHK(hipMemsetAsync(ar.base, 0, nbig * sbytes + 4 * ADJ_BLOCKS * sizeof(double) + 256, s));
+  CHK(hipMemsetAsync(ar.base, 0, nbig * sbytes + 8 * ADJ_BLOCKS * sizeof(double) + 256, s));
   if (!ol.empty()) CHK(hipMemcpyAsync(m.olist, ol.data(), ol.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, d_lambda, m.lam, 1, s));
   if (d_w) CHK(launch_adjoint_layout(G, ctx->ncls, d_w, m.w, 1, s));

@@ -174,8 +174,9 @@ hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void*
 // launch_adjoint_step: lam_out = dJ/dg^k from lam_in + w = dJ/dg^{k+1}
 // (w may be null; mu is scratch of the same layout; olist: the nopen
 // records on an open face; pmask: from launch_adjoint_mask, one word per
-// bulk node then per record); part[ADJ_BLOCKS][4] += the step's derivatives
-// of the inlet-velocity scale and the body force.
+// bulk node then per record); part[2][ADJ_BLOCKS][4] += the step's
+// derivatives of the inlet-velocity scale and the body force (first half:
+// bulk kernel, second: record kernels).
 constexpr int ADJ_BLOCKS = 1024;
 hipError_t launch_adjoint_forward(const FluidArgs& a, hipStream_t s);
 hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t s);

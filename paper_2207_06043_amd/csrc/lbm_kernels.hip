@@ -2702,14 +2702,17 @@ hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t 
 hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const uint32_t* pmask,
                                const double* lam_in, const double* w, double* mu, double* lam_out, double* part,
                                hipStream_t s) {
+  double* part_rec = part + 4 * ADJ_BLOCKS;
   if (a.nbulk_nodes > 0) {
     k_adj_collide<false><<<std::min<unsigned>(cdiv(a.nbulk_nodes, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu,
                                                                                                   part);
   }
   if (a.nrec > 0) {
-    k_adj_collide<true><<<std::min<unsigned>(cdiv(a.nrec, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu, part);
+    k_adj_collide<true><<<std::min<unsigned>(cdiv(a.nrec, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu, part_rec);
   }
-  if (nopen > 0) k_adj_zouhe<<<std::min<unsigned>(cdiv(nopen, 8), ADJ_BLOCKS), 256, 0, s>>>(a, olist, nopen, mu, part);
+  if (nopen > 0) {
+    k_adj_zouhe<<<std::min<unsigned>(cdiv(nopen, 8), ADJ_BLOCKS), 256, 0, s>>>(a, olist, nopen, mu, part_rec);
+  }
   if (a.nbulk_nodes + a.nrec > 0) k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, mu, lam_out);
   if (a.nrec > 0) k_adj_links<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
   return hipGetLastError();
@@ -2722,7 +2725,7 @@ hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const doubl
 }
 
 hipError_t launch_adjoint_grad(const double* part, double* grad, hipStream_t s) {
-  k_adj_grad_final<<<1, 64, 0, s>>>(part, ADJ_BLOCKS, grad);
+  k_adj_grad_final<<<1, 64, 0, s>>>(part, 2 * ADJ_BLOCKS, grad);
   return hipGetLastError();
 }
 
