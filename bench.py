@@ -163,7 +163,7 @@ def build_workload(name, precision):
 
 
 def default_precision(workload):
-    return {"pipe_sphere": "f64", "precision_form": "f16s"}.get(workload, "f32")
+    return {"pipe_sphere": "f64", "precision_form": "f16s", "differentiation_form": "f64"}.get(workload, "f32")
 
 
 def cpu_baseline(w, target_s=15.0):
