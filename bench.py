@@ -414,7 +414,7 @@ def run_adjoint(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("one adjoint step: k_adj_collide (bulk, records), k_adj_zouhe, k_adj_gather, "
+            "kernel": ("one adjoint step: k_adj_collide (bulk; records with the Zou-He transpose), k_adj_gather, "
                        "k_adj_links, plus the forward and recompute launches k_adj_fwd_bulk/k_adj_fwd_rec "
                        "(no single kernel dominates)"),
             "achieved": round(achieved, 1),

@@ -1638,16 +1638,11 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   const size_t sbytes = 19 * (size_t)G.plane * sizeof(double);
   const int nseg = n_steps == 0 ? 0 : (n_steps + every - 1) / every;
   const int tlen = n_steps == 0 ? 0 : std::min(every, n_steps);
-  // the records on an open face (Zou-He)
-  std::vector<uint8_t> rf(ctx->nrec);
-  if (ctx->nrec) CHK(hipMemcpy(rf.data(), ctx->rec_face, ctx->nrec, hipMemcpyDeviceToHost));
-  std::vector<int32_t> ol;
-  for (int r = 0; r < ctx->nrec; r++)
-    if (rf[r] != 0xff) ol.push_back(r);
   // one arena: lam, lam2, mu, w, the checkpoints, the tape, then the small pieces
   const size_t nbig = 4 + nseg + std::max(tlen, 2);
-  const size_t small = 8 * ADJ_BLOCKS * sizeof(double) + ol.size() * sizeof(int32_t) +
-                       ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + 3 * 256;
+  const size_t hbytes = 19 * (size_t)ctx->nrec * sizeof(double);  // one step's record populations
+  const size_t small = 8 * ADJ_BLOCKS * sizeof(double) + ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) +
+                       tlen * (hbytes + 256) + 2 * 256;
   DevArena ar;
   if (hipMalloc(&ar.base, nbig * sbytes + small) != hipSuccess) {
     (void)hipGetLastError();
@@ -1657,9 +1652,8 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   auto big = [&](size_t i) { return (double*)(ar.base + i * sbytes); };  // sbytes: a multiple of 8 * plane
   struct {
     double *lam, *lam2, *mu, *w, *part;
-    int32_t* olist;
     uint32_t* pmask;
-    std::vector<double*> ck, tape;
+    std::vector<double*> ck, tape, hrec;
   } m;
   m.lam = big(0);
   m.lam2 = big(1);
@@ -1674,12 +1668,11 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     return (void*)p;
   };
   m.part = (double*)carve(8 * ADJ_BLOCKS * sizeof(double));
-  m.olist = (int32_t*)carve(ol.size() * sizeof(int32_t));
   m.pmask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
+  for (int k = 0; k < tlen; k++) m.hrec.push_back((double*)carve(hbytes));
   hipStream_t s = ctx->stream;
   // solid entries stay zero in every buffer (never written by the sweep)
   CHK(hipMemsetAsync(ar.base, 0, nbig * sbytes + 8 * ADJ_BLOCKS * sizeof(double) + 256, s));
-  if (!ol.empty()) CHK(hipMemcpyAsync(m.olist, ol.data(), ol.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, d_lambda, m.lam, 1, s));
   if (d_w) CHK(launch_adjoint_layout(G, ctx->ncls, d_w, m.w, 1, s));
   FluidArgs a = fluid_args(ctx, 0);
@@ -1697,23 +1690,25 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
       for (int k = 0; k < every; k++) {
         a.A = src;
         a.B = k == every - 1 ? m.ck[c] : m.tape[k & 1];
-        CHK(launch_adjoint_forward(a, s));
+        CHK(launch_adjoint_forward(a, nullptr, s));
         src = (const double*)a.B;
       }
     }
   }
-  // reverse pass, segment by segment: recompute its states, then step back
+  // reverse pass, segment by segment: recompute its states (and the records'
+  // populations entering each collision; the last step's output goes to mu,
+  // which the step back overwrites at every non-solid node), then step back
   for (int c = nseg - 1; c >= 0; c--) {
     const int len = std::min(every, n_steps - c * every);
     CHK(hipMemcpyAsync(m.tape[0], m.ck[c], sbytes, hipMemcpyDeviceToDevice, s));
-    for (int k = 1; k < len; k++) {
-      a.A = m.tape[k - 1];
-      a.B = m.tape[k];
-      CHK(launch_adjoint_forward(a, s));
+    for (int k = 0; k < len; k++) {
+      a.A = m.tape[k];
+      a.B = k + 1 < len ? m.tape[k + 1] : m.mu;
+      CHK(launch_adjoint_forward(a, m.hrec[k], s));
     }
     for (int k = len - 1; k >= 0; k--) {
       a.A = m.tape[k];
-      CHK(launch_adjoint_step(a, m.olist, (int)ol.size(), m.pmask, m.lam, m.w, m.mu, m.lam2, m.part, s));
+      CHK(launch_adjoint_step(a, m.pmask, m.hrec[k], m.lam, m.w, m.mu, m.lam2, m.part, s));
       std::swap(m.lam, m.lam2);
     }
   }

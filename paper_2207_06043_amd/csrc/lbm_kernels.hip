@@ -2393,26 +2393,7 @@ hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void*
 // post-collision deviations g^k to g^{k+1} = C(P(g^k)): P is the streaming
 // (plain pulls, interpolated bounce-back, Zou-He -- affine in g^k) and C
 // the forced BGK collision of each node.  Given lam = dJ/dg^{k+1}, the step
-// back is mu = (dC/dh)^T lam node by node, then lam' = P^T mu.  The
-// node-local Jacobian products are forward-mode derivatives of the very
-// collide and Zou-He templates the step runs, one seed per input.
-struct Dual {
-  double v, d;
-  __device__ Dual() : v(0.0), d(0.0) {}
-  __device__ Dual(double x) : v(x), d(0.0) {}
-  __device__ Dual(double x, double dx) : v(x), d(dx) {}
-};
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
-__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
-__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
-__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
-  return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
-}
-__device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
-__device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
-__device__ __forceinline__ bool operator==(Dual a, Dual b) { return a.v == b.v; }
-
+// back is mu = (dC/dh)^T lam node by node, then lam' = P^T mu.
 __device__ __forceinline__ bool zh_unknown(int fc, int j) {
   const int face = fc & 7, ax = face >> 1, sg = (face & 1) ? -1 : 1;
   return fc != 0xff && sg * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j])) == 1;
@@ -2439,11 +2420,17 @@ __global__ __launch_bounds__(256) void k_adj_fwd_bulk(FluidArgs a) {
   for (int j = 0; j < 19; j++) B[(long long)j * G.plane + n] = g[j];
 }
 
-__global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a) {
+// hrec (may be null): [19][nrec], the records' populations entering the
+// collision (after Zou-He), kept for the step back.
+__global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a, double* hrec) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= a.nrec) return;
   double g[19], dr, ux, uy, uz;
   pull_general<double>(a, r, g);
+  if (hrec) {
+#pragma unroll
+    for (int j = 0; j < 19; j++) hrec[(long long)j * a.nrec + r] = g[j];
+  }
   collide<double>(g, a.gx, a.gy, a.gz, a.omega, dr, ux, uy, uz);
   const long long n = a.rec_node[r];
   double* B = (double*)a.B;
@@ -2497,24 +2484,96 @@ __device__ __forceinline__ void collide_vjp(const double (&h)[19], const double 
   dF[2] += kf * (V2 - 3.0 * uz * SL) + 0.5 * a2;
 }
 
+// Zou-He's transpose (the rule of zouhe(), affine in the known populations
+// for a fixed wall velocity or density): m = dJ/d(populations after the
+// rule) -> dJ/d(populations before it), in place; gs += dJ/ds with s the
+// scale of the wall velocity of a velocity face.  hz: the populations after
+// the rule (its known entries are the ones before).  With c_i = 1, 2, 0 for
+// e_i.n = 0, -1, +1, rho_w depends on g_i through c_i / (1 - u_n) (velocity
+// face) and u_n through -c_i / rho_w (density face); the tangential sums T
+// through e_i (e_i.n = 0); each unknown j adds m_j to its opposite input.
+__device__ __forceinline__ void zouhe_vjp(const double (&hz)[19], double (&m)[19], int face, int kind,
+                                          const double* bc, double& gs) {
+  const int ax = face >> 1;
+  const int sg = (face & 1) ? -1 : 1;
+  double G0 = 0.0, Gout = 0.0;
+#pragma unroll
+  for (int j = 0; j < 19; j++) {
+    const int en = sg * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]));
+    G0 += en == 0 ? hz[j] : 0.0;
+    Gout += en == -1 ? hz[j] : 0.0;
+  }
+  double u[3] = {bc[0], bc[1], bc[2]};
+  double rho, un;
+  if (kind == 0) {
+    un = sg * u[ax];
+    rho = (1.0 + G0 + 2.0 * Gout) / (1.0 - un);
+  } else {
+    rho = bc[3];
+    un = (rho - 1.0 - G0 - 2.0 * Gout) / rho;
+    u[0] = ax == 0 ? sg * un : 0.0;
+    u[1] = ax == 1 ? sg * un : 0.0;
+    u[2] = ax == 2 ? sg * un : 0.0;
+  }
+  // R = sum over unknowns of m_j d(fill_j)/d(rho_w) (velocity face) or
+  // d(fill_j)/d(u_n) (density face); W = sum over diagonal unknowns of m_j t_j
+  double R = 0.0, W[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 19; j++) {
+    const int en = sg * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j]));
+    if (en != 1) continue;
+    const double t[3] = {ax == 0 ? 0.0 : (double)EX[j], ax == 1 ? 0.0 : (double)EY[j], ax == 2 ? 0.0 : (double)EZ[j]};
+    const bool axis = t[0] == 0.0 && t[1] == 0.0 && t[2] == 0.0;
+    const double ut = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
+    const double coef = kind == 0 ? (axis ? un / 3.0 : (un + ut) / 6.0 + ut / 3.0) : (axis ? rho / 3.0 : rho / 6.0);
+    R += m[j] * coef;
+    if (!axis) {
+      W[0] += m[j] * t[0];
+      W[1] += m[j] * t[1];
+      W[2] += m[j] * t[2];
+    }
+  }
+  double out[19];
+#pragma unroll
+  for (int i = 0; i < 19; i++) {
+    const int en = sg * (ax == 0 ? EX[i] : (ax == 1 ? EY[i] : EZ[i]));
+    const double c = en == 0 ? 1.0 : (en == -1 ? 2.0 : 0.0);
+    double v = en != 1 ? m[i] : 0.0;
+    if (en == -1) v += m[OPP[i]];  // the unknown opposite copies this input
+    v += R * (kind == 0 ? c / (1.0 - un) : -c / rho);
+    if (en == 0) v -= 0.5 * (W[0] * EX[i] + W[1] * EY[i] + W[2] * EZ[i]);
+    out[i] = v;
+  }
+#pragma unroll
+  for (int i = 0; i < 19; i++) m[i] = out[i];
+  if (kind == 0) gs += (rho * un / (1.0 - un) + rho) * R;
+}
+
 // mu = (dC/dh)^T (lam + w) at the bulk nodes (REC false, a.bulk_list) or at the boundary
 // records (REC true; h: the populations that entered the collision, Zou-He
-// applied); part[block][1..3] += the step's derivatives of the body force
-// (fixed order: bitwise reproducible).  Two kernels, so that the bulk one
+// applied, from hrec when the recompute kept them, else pulled again; at
+// open-face records mu is then taken back through Zou-He);
+// part[block][0..3] += the step's derivatives of the inlet-velocity scale
+// and the body force (fixed order: bitwise reproducible).  Two kernels, so that the bulk one
 // keeps the small register budget of the plain pull.
 template <bool REC>
-__global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, const double* lam, const double* w,
-                                                     double* mu, double* part) {
+__global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, const double* hrec, const double* lam,
+                                                                  const double* w, double* mu, double* part) {
   __shared__ double sh[8];
   const Grid& G = a.g;
-  double dF[3] = {0.0, 0.0, 0.0};
+  double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
   const int count = REC ? a.nrec : a.nbulk_nodes;
   for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256) {
     double h[19], l[19], m[19];
     long long n;
     if (REC) {
       n = a.rec_node[t];
-      pull_general<double>(a, t, h);
+      if (hrec) {
+#pragma unroll
+        for (int j = 0; j < 19; j++) h[j] = hrec[(long long)j * a.nrec + t];
+      } else {
+        pull_general<double>(a, t, h);
+      }
     } else {
       n = a.bulk_list[t];
       int x, y, z;
@@ -2526,67 +2585,28 @@ __global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, c
 #pragma unroll
     for (int j = 0; j < 19; j++) l[j] = lam[(long long)j * G.plane + n] + (w ? w[(long long)j * G.plane + n] : 0.0);
     collide_vjp(h, l, a.gx, a.gy, a.gz, a.omega, m, dF);
+    if (REC) {
+      const int fc = a.rec_face[t];
+      if (fc != 0xff) {
+        double bc[4];
+        for (int q = 0; q < 4; q++) bc[q] = a.rec_bc[(long long)q * a.nrec + t];
+        zouhe_vjp(h, m, fc & 7, (fc >> 4) & 1, bc, gs);
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 19; j++) mu[(long long)j * G.plane + n] = m[j];
   }
+  const double t0 = block_sum(gs, sh);
   const double t1 = block_sum(dF[0], sh);
   const double t2 = block_sum(dF[1], sh);
   const double t3 = block_sum(dF[2], sh);
   if (threadIdx.x == 0) {
     double* p = part + 4 * blockIdx.x;
+    p[0] += t0;
     p[1] += t1;
     p[2] += t2;
     p[3] += t3;
   }
-}
-
-// Zou-He's transpose at the open-face records (olist): mu (taken at the
-// populations after Zou-He) -> mu at the populations before it, by
-// forward-mode derivatives of the same rule.  32 lanes per record, lane k
-// < 19 seeds input k (the unknown inputs are overwritten by the rule: no
-// derivative), lane 19 seeds the scale of the wall velocity of a velocity
-// face: part[block][0] += its derivative.
-__global__ __launch_bounds__(256) void k_adj_zouhe(FluidArgs a, const int32_t* olist, int nopen, double* mu,
-                                                   double* part) {
-  __shared__ double sh[8];
-  const Grid& G = a.g;
-  const int k = threadIdx.x & 31;
-  double gs = 0.0;
-  const int groups = (nopen + 7) / 8;
-  for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {  // the same trip count for the whole block
-    const int o = grp * 8 + (threadIdx.x >> 5);
-    const bool act = o < nopen && k < 20;
-    double res = 0.0;
-    long long n = 0;
-    if (act) {
-      const int r = olist[o];
-      const int fc = a.rec_face[r];
-      n = a.rec_node[r];
-      if (!(k < 19 && zh_unknown(fc, k))) {
-        double h[19];
-        pull_general<double>(a, r, h, false);
-        const int face = fc & 7, kind = (fc >> 4) & 1;
-        double bc[4];
-        for (int q = 0; q < 4; q++) bc[q] = a.rec_bc[(long long)q * a.nrec + r];
-        Dual x[19];
-#pragma unroll
-        for (int j = 0; j < 19; j++) x[j] = Dual(h[j], j == k ? 1.0 : 0.0);
-        const double sd = (k == 19 && kind == 0) ? 1.0 : 0.0;
-        zouhe<Dual>(x, face, kind, Dual(bc[0], sd * bc[0]), Dual(bc[1], sd * bc[1]), Dual(bc[2], sd * bc[2]),
-                    Dual(bc[3]));
-#pragma unroll
-        for (int j = 0; j < 19; j++) res += mu[(long long)j * G.plane + n] * x[j].d;
-      }
-    }
-    __syncthreads();  // every lane of the record has read mu before it is replaced
-    if (act) {
-      if (k < 19) mu[(long long)k * G.plane + n] = res;
-      else gs += res;
-    }
-    __syncthreads();
-  }
-  const double t0 = block_sum(gs, sh);
-  if (threadIdx.x == 0) part[4 * blockIdx.x] += t0;
 }
 
 // For every non-solid node y (bulk list, then the records): bit j set when
@@ -2688,9 +2708,9 @@ __global__ void k_adj_grad_final(const double* part, int nblk, double* grad) {
   grad[q] = t;
 }
 
-hipError_t launch_adjoint_forward(const FluidArgs& a, hipStream_t s) {
+hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, hipStream_t s) {
   if (a.nbulk_nodes > 0) k_adj_fwd_bulk<<<cdiv(a.nbulk_nodes, 256), 256, 0, s>>>(a);
-  if (a.nrec > 0) k_adj_fwd_rec<<<cdiv(a.nrec, 256), 256, 0, s>>>(a);
+  if (a.nrec > 0) k_adj_fwd_rec<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, hrec);
   return hipGetLastError();
 }
 
@@ -2699,19 +2719,16 @@ hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const FluidArgs& a, const int32_t* olist, int nopen, const uint32_t* pmask,
-                               const double* lam_in, const double* w, double* mu, double* lam_out, double* part,
-                               hipStream_t s) {
+hipError_t launch_adjoint_step(const FluidArgs& a, const uint32_t* pmask, const double* hrec, const double* lam_in,
+                               const double* w, double* mu, double* lam_out, double* part, hipStream_t s) {
   double* part_rec = part + 4 * ADJ_BLOCKS;
   if (a.nbulk_nodes > 0) {
-    k_adj_collide<false><<<std::min<unsigned>(cdiv(a.nbulk_nodes, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu,
-                                                                                                  part);
+    k_adj_collide<false><<<std::min<unsigned>(cdiv(a.nbulk_nodes, 256), ADJ_BLOCKS), 256, 0, s>>>(a, nullptr, lam_in, w,
+                                                                                                  mu, part);
   }
   if (a.nrec > 0) {
-    k_adj_collide<true><<<std::min<unsigned>(cdiv(a.nrec, 256), ADJ_BLOCKS), 256, 0, s>>>(a, lam_in, w, mu, part_rec);
-  }
-  if (nopen > 0) {
-    k_adj_zouhe<<<std::min<unsigned>(cdiv(nopen, 8), ADJ_BLOCKS), 256, 0, s>>>(a, olist, nopen, mu, part_rec);
+    k_adj_collide<true><<<std::min<unsigned>(cdiv(a.nrec, 256), ADJ_BLOCKS), 256, 0, s>>>(a, hrec, lam_in, w, mu,
+                                                                                         part_rec);
   }
   if (a.nbulk_nodes + a.nrec > 0) k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, mu, lam_out);
   if (a.nrec > 0) k_adj_links<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
