@@ -1641,8 +1641,13 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   // one arena: lam, lam2, mu, w, the checkpoints, the tape, then the small pieces
   const size_t nbig = 4 + nseg + std::max(tlen, 2);
   const size_t hbytes = 19 * (size_t)ctx->nrec * sizeof(double);  // one step's record populations
-  const size_t small = 8 * ADJ_BLOCKS * sizeof(double) + ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) +
-                       tlen * (hbytes + 256) + 2 * 256;
+  const int npart = adj_part_blocks(ctx->nrec, ctx->n_bulk);
+  const size_t pbytes = 4 * (size_t)npart * sizeof(double);
+  const size_t small = pbytes + ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + tlen * (hbytes + 256) + 2 * 256;
+  // one launch for records and bulk nodes below 4M non-solid nodes (the
+  // records' blocks are latency-bound; LBM_ADJ_SPLIT=1 forces two)
+  const char* sp_env = getenv("LBM_ADJ_SPLIT");
+  const int merged = (ctx->n_bulk + ctx->nrec < (4LL << 20)) && !(sp_env && atoi(sp_env) != 0);
   DevArena ar;
   if (hipMalloc(&ar.base, nbig * sbytes + small) != hipSuccess) {
     (void)hipGetLastError();
@@ -1667,12 +1672,12 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     sp = p + bytes;
     return (void*)p;
   };
-  m.part = (double*)carve(8 * ADJ_BLOCKS * sizeof(double));
+  m.part = (double*)carve(pbytes);
   m.pmask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
   for (int k = 0; k < tlen; k++) m.hrec.push_back((double*)carve(hbytes));
   hipStream_t s = ctx->stream;
   // solid entries stay zero in every buffer (never written by the sweep)
-  CHK(hipMemsetAsync(ar.base, 0, nbig * sbytes + 8 * ADJ_BLOCKS * sizeof(double) + 256, s));
+  CHK(hipMemsetAsync(ar.base, 0, nbig * sbytes + pbytes + 256, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, d_lambda, m.lam, 1, s));
   if (d_w) CHK(launch_adjoint_layout(G, ctx->ncls, d_w, m.w, 1, s));
   FluidArgs a = fluid_args(ctx, 0);
@@ -1690,7 +1695,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
       for (int k = 0; k < every; k++) {
         a.A = src;
         a.B = k == every - 1 ? m.ck[c] : m.tape[k & 1];
-        CHK(launch_adjoint_forward(a, nullptr, s));
+        CHK(launch_adjoint_forward(a, nullptr, merged, s));
         src = (const double*)a.B;
       }
     }
@@ -1704,16 +1709,16 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     for (int k = 0; k < len; k++) {
       a.A = m.tape[k];
       a.B = k + 1 < len ? m.tape[k + 1] : m.mu;
-      CHK(launch_adjoint_forward(a, m.hrec[k], s));
+      CHK(launch_adjoint_forward(a, m.hrec[k], merged, s));
     }
     for (int k = len - 1; k >= 0; k--) {
       a.A = m.tape[k];
-      CHK(launch_adjoint_step(a, m.pmask, m.hrec[k], m.lam, m.w, m.mu, m.lam2, m.part, s));
+      CHK(launch_adjoint_step(a, m.pmask, m.hrec[k], m.lam, m.w, m.mu, m.lam2, m.part, merged, s));
       std::swap(m.lam, m.lam2);
     }
   }
   CHK(launch_adjoint_layout(G, ctx->ncls, m.lam, d_lambda, 0, s));
-  CHK(launch_adjoint_grad(m.part, d_grad, s));
+  CHK(launch_adjoint_grad(m.part, npart, d_grad, s));
   CHK(hipStreamSynchronize(s));
   return LBM_OK;
 }

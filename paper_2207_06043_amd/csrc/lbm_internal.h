@@ -169,23 +169,29 @@ hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void*
                             const DevFlags* flags, double* part, double* out, hipStream_t s);
 // Adjoint of the fluid step (FP64, no bodies; FluidArgs with A = the state
 // g^k in [19][plane], bulk_list/nbulk_nodes set).  Solid entries of every
-// buffer of the sweep hold zero and are never written.
+// buffer of the sweep hold zero and are never written.  merged: records and
+// bulk nodes in one launch (small grids), else two.
 // launch_adjoint_forward: g^{k+1} = step(A) into B; hrec (may be null):
 // [19][nrec], the records' populations entering the collision.
 // launch_adjoint_step: lam_out = dJ/dg^k from lam_in + w = dJ/dg^{k+1}
 // (w may be null; mu is scratch of the same layout; pmask: from
 // launch_adjoint_mask, one word per bulk node then per record; hrec: the
-// forward's record populations for A, or null to pull them again); part[2][ADJ_BLOCKS][4] += the step's
-// derivatives of the inlet-velocity scale and the body force (first half:
-// bulk kernel, second: record kernels).
+// forward's record populations for A, or null to pull them again);
+// part[adj_part_blocks][4] += the step's derivatives of the inlet-velocity
+// scale and the body force, per block in a fixed order.
 constexpr int ADJ_BLOCKS = 1024;
-hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, hipStream_t s);
+inline int adj_part_blocks(long long nrec, long long nbulk) {
+  const long long merged = (nrec + 255) / 256 + (nbulk + 255) / 256;
+  return (int)(merged > 2 * ADJ_BLOCKS ? merged : 2 * ADJ_BLOCKS);
+}
+hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, int merged, hipStream_t s);
 hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t s);
 hipError_t launch_adjoint_step(const FluidArgs& a, const uint32_t* pmask, const double* hrec, const double* lam_in,
-                               const double* w, double* mu, double* lam_out, double* part, hipStream_t s);
+                               const double* w, double* mu, double* lam_out, double* part, int merged,
+                               hipStream_t s);
 hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,
                                  hipStream_t s);
-hipError_t launch_adjoint_grad(const double* part, double* grad, hipStream_t s);
+hipError_t launch_adjoint_grad(const double* part, int nblk, double* grad, hipStream_t s);
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,

@@ -2400,13 +2400,12 @@ __device__ __forceinline__ bool zh_unknown(int fc, int j) {
 }
 
 // One forward step of the FP64 fluid (the same pull and collision as the
-// stream-collide kernels) from a.A into a.B: the bulk nodes (a.bulk_list)
-// here, the boundary records in k_adj_fwd_rec.  Solid nodes are not
-// written (they hold zero in every buffer of the sweep).
-__global__ __launch_bounds__(256) void k_adj_fwd_bulk(FluidArgs a) {
+// stream-collide kernels) from a.A into a.B: bulk node t of a.bulk_list, or
+// boundary record r.  Solid nodes are not written (they hold zero in every
+// buffer of the sweep).  hrec (may be null): [19][nrec], the records'
+// populations entering the collision (after Zou-He), kept for the step back.
+__device__ __forceinline__ void adj_fwd_bulk_one(const FluidArgs& a, int t) {
   const Grid& G = a.g;
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= a.nbulk_nodes) return;
   const long long n = a.bulk_list[t];
   const double* A = (const double*)a.A;
   double* B = (double*)a.B;
@@ -2420,11 +2419,7 @@ __global__ __launch_bounds__(256) void k_adj_fwd_bulk(FluidArgs a) {
   for (int j = 0; j < 19; j++) B[(long long)j * G.plane + n] = g[j];
 }
 
-// hrec (may be null): [19][nrec], the records' populations entering the
-// collision (after Zou-He), kept for the step back.
-__global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a, double* hrec) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= a.nrec) return;
+__device__ __forceinline__ void adj_fwd_rec_one(const FluidArgs& a, double* hrec, int r) {
   double g[19], dr, ux, uy, uz;
   pull_general<double>(a, r, g);
   if (hrec) {
@@ -2436,6 +2431,30 @@ __global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a, double* hrec) 
   double* B = (double*)a.B;
 #pragma unroll
   for (int j = 0; j < 19; j++) B[(long long)j * a.g.plane + n] = g[j];
+}
+
+// Split form: the bulk kernel keeps the small register budget of the plain
+// pull; merged form (small grids): the records' latency-bound blocks run
+// alongside the bulk blocks in one launch (blocks below rec_blocks take
+// records).
+__global__ __launch_bounds__(256) void k_adj_fwd_bulk(FluidArgs a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < a.nbulk_nodes) adj_fwd_bulk_one(a, t);
+}
+
+__global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a, double* hrec) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r < a.nrec) adj_fwd_rec_one(a, hrec, r);
+}
+
+__global__ __launch_bounds__(256) void k_adj_fwd_all(FluidArgs a, double* hrec, int rec_blocks) {
+  if ((int)blockIdx.x < rec_blocks) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < a.nrec) adj_fwd_rec_one(a, hrec, r);
+  } else {
+    const int t = (blockIdx.x - rec_blocks) * 256 + threadIdx.x;
+    if (t < a.nbulk_nodes) adj_fwd_bulk_one(a, t);
+  }
 }
 
 // The transpose of the collision's Jacobian, written out: with
@@ -2549,53 +2568,52 @@ __device__ __forceinline__ void zouhe_vjp(const double (&hz)[19], double (&m)[19
   if (kind == 0) gs += (rho * un / (1.0 - un) + rho) * R;
 }
 
-// mu = (dC/dh)^T (lam + w) at the bulk nodes (REC false, a.bulk_list) or at the boundary
-// records (REC true; h: the populations that entered the collision, Zou-He
-// applied, from hrec when the recompute kept them, else pulled again; at
-// open-face records mu is then taken back through Zou-He);
-// part[block][0..3] += the step's derivatives of the inlet-velocity scale
-// and the body force (fixed order: bitwise reproducible).  Two kernels, so that the bulk one
-// keeps the small register budget of the plain pull.
+// mu = (dC/dh)^T (lam + w) at bulk node t of a.bulk_list (REC false) or at
+// boundary record t (REC true; h: the populations that entered the
+// collision, Zou-He applied, from hrec when the recompute kept them, else
+// pulled again; at open-face records mu is then taken back through
+// Zou-He).  dF, gs += the node's derivatives of the body force and of the
+// inlet-velocity scale.
 template <bool REC>
-__global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, const double* hrec, const double* lam,
-                                                                  const double* w, double* mu, double* part) {
-  __shared__ double sh[8];
+__device__ __forceinline__ void adj_collide_one(const FluidArgs& a, const double* hrec, const double* lam,
+                                                const double* w, double* mu, int t, double (&dF)[3], double& gs) {
   const Grid& G = a.g;
-  double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
-  const int count = REC ? a.nrec : a.nbulk_nodes;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256) {
-    double h[19], l[19], m[19];
-    long long n;
-    if (REC) {
-      n = a.rec_node[t];
-      if (hrec) {
+  double h[19], l[19], m[19];
+  long long n;
+  if (REC) {
+    n = a.rec_node[t];
+    if (hrec) {
 #pragma unroll
-        for (int j = 0; j < 19; j++) h[j] = hrec[(long long)j * a.nrec + t];
-      } else {
-        pull_general<double>(a, t, h);
-      }
+      for (int j = 0; j < 19; j++) h[j] = hrec[(long long)j * a.nrec + t];
     } else {
-      n = a.bulk_list[t];
-      int x, y, z;
-      coords(G, n, x, y, z);
-#pragma unroll
-      for (int j = 0; j < 19; j++)
-        h[j] = ((const double*)a.A)[(long long)j * G.plane + nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j])];
+      pull_general<double>(a, t, h);
     }
+  } else {
+    n = a.bulk_list[t];
+    int x, y, z;
+    coords(G, n, x, y, z);
 #pragma unroll
-    for (int j = 0; j < 19; j++) l[j] = lam[(long long)j * G.plane + n] + (w ? w[(long long)j * G.plane + n] : 0.0);
-    collide_vjp(h, l, a.gx, a.gy, a.gz, a.omega, m, dF);
-    if (REC) {
-      const int fc = a.rec_face[t];
-      if (fc != 0xff) {
-        double bc[4];
-        for (int q = 0; q < 4; q++) bc[q] = a.rec_bc[(long long)q * a.nrec + t];
-        zouhe_vjp(h, m, fc & 7, (fc >> 4) & 1, bc, gs);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 19; j++) mu[(long long)j * G.plane + n] = m[j];
+    for (int j = 0; j < 19; j++)
+      h[j] = ((const double*)a.A)[(long long)j * G.plane + nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j])];
   }
+#pragma unroll
+  for (int j = 0; j < 19; j++) l[j] = lam[(long long)j * G.plane + n] + (w ? w[(long long)j * G.plane + n] : 0.0);
+  collide_vjp(h, l, a.gx, a.gy, a.gz, a.omega, m, dF);
+  if (REC) {
+    const int fc = a.rec_face[t];
+    if (fc != 0xff) {
+      double bc[4];
+      for (int q = 0; q < 4; q++) bc[q] = a.rec_bc[(long long)q * a.nrec + t];
+      zouhe_vjp(h, m, fc & 7, (fc >> 4) & 1, bc, gs);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 19; j++) mu[(long long)j * G.plane + n] = m[j];
+}
+
+// part[block][0..3] += the block's sums (fixed order: bitwise reproducible).
+__device__ __forceinline__ void adj_part_add(double* part, double gs, const double (&dF)[3]) {
+  __shared__ double sh[8];
   const double t0 = block_sum(gs, sh);
   const double t1 = block_sum(dF[0], sh);
   const double t2 = block_sum(dF[1], sh);
@@ -2607,6 +2625,32 @@ __global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, c
     p[2] += t2;
     p[3] += t3;
   }
+}
+
+// Split form: bulk (REC false) and records (REC true) in two launches,
+// grid-stride over at most ADJ_BLOCKS blocks each.
+template <bool REC>
+__global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, const double* hrec, const double* lam,
+                                                                  const double* w, double* mu, double* part) {
+  double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
+  const int count = REC ? a.nrec : a.nbulk_nodes;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256)
+    adj_collide_one<REC>(a, hrec, lam, w, mu, t, dF, gs);
+  adj_part_add(part, gs, dF);
+}
+
+// Merged form: blocks below rec_blocks take records, the rest bulk nodes.
+__global__ __launch_bounds__(256) void k_adj_collide_all(FluidArgs a, const double* hrec, const double* lam,
+                                                         const double* w, double* mu, double* part, int rec_blocks) {
+  double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
+  if ((int)blockIdx.x < rec_blocks) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < a.nrec) adj_collide_one<true>(a, hrec, lam, w, mu, t, dF, gs);
+  } else {
+    const int t = (blockIdx.x - rec_blocks) * 256 + threadIdx.x;
+    if (t < a.nbulk_nodes) adj_collide_one<false>(a, hrec, lam, w, mu, t, dF, gs);
+  }
+  adj_part_add(part, gs, dF);
 }
 
 // For every non-solid node y (bulk list, then the records): bit j set when
@@ -2708,9 +2752,14 @@ __global__ void k_adj_grad_final(const double* part, int nblk, double* grad) {
   grad[q] = t;
 }
 
-hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, hipStream_t s) {
-  if (a.nbulk_nodes > 0) k_adj_fwd_bulk<<<cdiv(a.nbulk_nodes, 256), 256, 0, s>>>(a);
-  if (a.nrec > 0) k_adj_fwd_rec<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, hrec);
+hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, int merged, hipStream_t s) {
+  const int rb = (int)cdiv(a.nrec, 256), bb = (int)cdiv(a.nbulk_nodes, 256);
+  if (merged) {
+    if (rb + bb > 0) k_adj_fwd_all<<<rb + bb, 256, 0, s>>>(a, hrec, rb);
+  } else {
+    if (bb > 0) k_adj_fwd_bulk<<<bb, 256, 0, s>>>(a);
+    if (rb > 0) k_adj_fwd_rec<<<rb, 256, 0, s>>>(a, hrec);
+  }
   return hipGetLastError();
 }
 
@@ -2720,15 +2769,16 @@ hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t 
 }
 
 hipError_t launch_adjoint_step(const FluidArgs& a, const uint32_t* pmask, const double* hrec, const double* lam_in,
-                               const double* w, double* mu, double* lam_out, double* part, hipStream_t s) {
-  double* part_rec = part + 4 * ADJ_BLOCKS;
-  if (a.nbulk_nodes > 0) {
-    k_adj_collide<false><<<std::min<unsigned>(cdiv(a.nbulk_nodes, 256), ADJ_BLOCKS), 256, 0, s>>>(a, nullptr, lam_in, w,
-                                                                                                  mu, part);
-  }
-  if (a.nrec > 0) {
-    k_adj_collide<true><<<std::min<unsigned>(cdiv(a.nrec, 256), ADJ_BLOCKS), 256, 0, s>>>(a, hrec, lam_in, w, mu,
-                                                                                         part_rec);
+                               const double* w, double* mu, double* lam_out, double* part, int merged,
+                               hipStream_t s) {
+  const int rb = (int)cdiv(a.nrec, 256), bb = (int)cdiv(a.nbulk_nodes, 256);
+  if (merged) {
+    if (rb + bb > 0) k_adj_collide_all<<<rb + bb, 256, 0, s>>>(a, hrec, lam_in, w, mu, part, rb);
+  } else {
+    if (bb > 0) k_adj_collide<false><<<std::min(bb, ADJ_BLOCKS), 256, 0, s>>>(a, nullptr, lam_in, w, mu, part);
+    if (rb > 0) {
+      k_adj_collide<true><<<std::min(rb, ADJ_BLOCKS), 256, 0, s>>>(a, hrec, lam_in, w, mu, part + 4 * ADJ_BLOCKS);
+    }
   }
   if (a.nbulk_nodes + a.nrec > 0) k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, mu, lam_out);
   if (a.nrec > 0) k_adj_links<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
@@ -2741,8 +2791,8 @@ hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_grad(const double* part, double* grad, hipStream_t s) {
-  k_adj_grad_final<<<1, 64, 0, s>>>(part, 2 * ADJ_BLOCKS, grad);
+hipError_t launch_adjoint_grad(const double* part, int nblk, double* grad, hipStream_t s) {
+  k_adj_grad_final<<<1, 64, 0, s>>>(part, nblk, grad);
   return hipGetLastError();
 }
 

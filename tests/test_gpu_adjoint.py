@@ -2,7 +2,8 @@
 finite differences taken on the FP64 oracle, which shares no code with it.
 
 Small cases (a straight pipe with Zou-He inlet/outlet and curved-wall
-bounce-back; a bifurcation from rest), objective
+bounce-back; a bifurcation from rest; a forced periodic box, all bulk),
+objective
     J = <c, f^n> + sum_{t=1..n} <w, f^t>
 with c a seeded random field on the fluid nodes and w the outward flux
 weights of the outlet nodes.  Checked: dJ/ds (inlet-velocity scale),
@@ -55,6 +56,13 @@ def lib():
 def _case(name):
     if name == "pipe":
         w = synth.tiny_pipe(precision="f64", with_body=False)
+    elif name == "periodic":
+        # no boundary records at all: every node is bulk
+        d = synth.periodic_box(12, 9, 7, body_force=(1e-5, -2e-6, 3e-6))
+        rng = np.random.default_rng(3)
+        d.init_rho = 1 + 0.01 * rng.standard_normal(d.n_nodes)
+        d.init_u = 0.02 * rng.standard_normal(3 * d.n_nodes)
+        w = synth.Workload("periodic_box", d, [], 0.9, 0.0, "f64", 20)
     else:
         w = synth.tiny_bifurcation(precision="f64", n_bodies=0)
         d = w.domain
@@ -66,6 +74,8 @@ def _case(name):
     c = rng.standard_normal((19, d.n_nodes)) * fl
     e = oracle.lattice()[0].astype(np.float64)
     out = np.flatnonzero(d.node_type == synth.OUTLET)
+    if len(out) == 0:  # periodic: the x-momentum of one plane
+        out = np.flatnonzero(np.arange(d.n_nodes) % d.nx == d.nx - 1)
     wv = np.zeros((19, d.n_nodes))
     # outward normal of each outlet node: the face it sits on
     x, y, z = out % d.nx, (out // d.nx) % d.ny, out // (d.nx * d.ny)
@@ -133,7 +143,7 @@ def _dfeq_drho(rho, u, dr):
     return wts[:, None] * dr * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * np.sum(u * u, axis=0))
 
 
-@pytest.mark.parametrize("name", ["pipe", "bifurcation"])
+@pytest.mark.parametrize("name", ["pipe", "bifurcation", "periodic"])
 def test_adjoint_matches_oracle_differences(lib, name):
     import torch
     w, c, wv, du, dr = _case(name)
@@ -146,7 +156,10 @@ def test_adjoint_matches_oracle_differences(lib, name):
     fl = d.node_type != synth.SOLID
     assert np.all(lam[:, ~fl] == 0)
     ok = True
-    ok &= _check("dJ/ds", grad[0], _fd(d, w, n, c, wv, "s", (1e-4, 5e-5)), abs(grad[0]))
+    if len(d.inlet_u):
+        ok &= _check("dJ/ds", grad[0], _fd(d, w, n, c, wv, "s", (1e-4, 5e-5)), abs(grad[0]))
+    else:
+        assert grad[0] == 0.0  # no velocity face
     fscale = np.abs(grad[1:]).max()
     for k, comp in enumerate(("Fx", "Fy", "Fz")):
         ok &= _check(f"dJ/d{comp}", grad[1 + k], _fd(d, w, n, c, wv, comp, (1e-6, 5e-7)), fscale)
@@ -182,6 +195,22 @@ def test_adjoint_checkpoint_interval_and_state(lib):
     assert lat.info()["steps_done"] == 5
     lam, g = lat.adjoint(0, torch.from_numpy(c))
     assert torch.equal(lam.cpu(), torch.from_numpy(c)) and torch.all(g == 0)
+
+
+def test_adjoint_split_and_merged_launches_agree(lib, monkeypatch):
+    """Records and bulk nodes in one launch (the small-grid default) or two
+    (LBM_ADJ_SPLIT=1, the large-grid form): the same gradient to rounding
+    (the per-block gradient sums are grouped differently)."""
+    import torch
+    w, c, wv, _, _ = _case("bifurcation")
+    lat = lib.from_workload(w)
+    lam_m, g_m = lat.adjoint(25, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=10)
+    monkeypatch.setenv("LBM_ADJ_SPLIT", "1")
+    lam_s, g_s = lat.adjoint(25, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=10)
+    e_l = float((lam_s - lam_m).abs().max() / lam_m.abs().max())
+    e_g = float(((g_s - g_m).abs() / g_m.abs().clamp_min(1e-300)).max())
+    _say(f"[adjoint] split vs merged: lambda {e_l:.1e}, grad {e_g:.1e}")
+    assert e_l <= 1e-13 and e_g <= 1e-12
 
 
 def test_adjoint_rejects_unsupported_contexts(lib):
