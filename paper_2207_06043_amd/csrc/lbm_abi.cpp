@@ -1638,12 +1638,14 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   const size_t sbytes = 19 * (size_t)G.plane * sizeof(double);
   const int nseg = n_steps == 0 ? 0 : (n_steps + every - 1) / every;
   const int tlen = n_steps == 0 ? 0 : std::min(every, n_steps);
-  // one arena: lam, lam2, mu, w, the checkpoints, the tape, then the small pieces
-  const size_t nbig = 4 + nseg + std::max(tlen, 2);
+  // one arena: lam, the two mu, w, the two bounce-back accumulators, the
+  // checkpoints, the tape, then the small pieces
+  const size_t nbig = 6 + nseg + std::max(tlen, 2);
   const size_t hbytes = 19 * (size_t)ctx->nrec * sizeof(double);  // one step's record populations
   const int npart = adj_part_blocks(ctx->nrec, ctx->n_bulk);
   const size_t pbytes = 4 * (size_t)npart * sizeof(double);
-  const size_t small = pbytes + ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + tlen * (hbytes + 256) + 2 * 256;
+  const size_t small = pbytes + 2 * ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + tlen * (hbytes + 256) +
+                       3 * 256;
   // one launch for records and bulk nodes below 4M non-solid nodes (the
   // records' blocks are latency-bound; LBM_ADJ_SPLIT=1 forces two)
   const char* sp_env = getenv("LBM_ADJ_SPLIT");
@@ -1656,16 +1658,18 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   }
   auto big = [&](size_t i) { return (double*)(ar.base + i * sbytes); };  // sbytes: a multiple of 8 * plane
   struct {
-    double *lam, *lam2, *mu, *w, *part;
-    uint32_t* pmask;
+    double *lam, *mu[2], *acc[2], *w, *part;
+    uint32_t *pmask, *amask;
     std::vector<double*> ck, tape, hrec;
   } m;
   m.lam = big(0);
-  m.lam2 = big(1);
-  m.mu = big(2);
+  m.mu[0] = big(1);
+  m.mu[1] = big(2);
   m.w = d_w ? big(3) : nullptr;
-  for (int c = 0; c < nseg; c++) m.ck.push_back(big(4 + c));
-  for (int k = 0; k < std::max(tlen, 2); k++) m.tape.push_back(big(4 + nseg + k));
+  m.acc[0] = big(4);
+  m.acc[1] = big(5);
+  for (int c = 0; c < nseg; c++) m.ck.push_back(big(6 + c));
+  for (int k = 0; k < std::max(tlen, 2); k++) m.tape.push_back(big(6 + nseg + k));
   char* sp = ar.base + nbig * sbytes;
   auto carve = [&](size_t bytes) {
     char* p = (char*)(((uintptr_t)sp + 255) & ~(uintptr_t)255);
@@ -1674,6 +1678,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   };
   m.part = (double*)carve(pbytes);
   m.pmask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
+  m.amask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
   for (int k = 0; k < tlen; k++) m.hrec.push_back((double*)carve(hbytes));
   hipStream_t s = ctx->stream;
   // solid entries stay zero in every buffer (never written by the sweep)
@@ -1686,7 +1691,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   a.mac = nullptr;
   a.bulk_list = ctx->bulk_list;
   a.nbulk_nodes = (int)ctx->n_bulk;
-  CHK(launch_adjoint_mask(a, m.pmask, s));
+  CHK(launch_adjoint_mask(a, m.pmask, m.amask, s));
   // forward pass: the state at the start of every segment
   if (nseg > 0) {
     CHK(hipMemcpyAsync(m.ck[0], ctx->f[h.steps_done & 1], sbytes, hipMemcpyDeviceToDevice, s));
@@ -1701,22 +1706,40 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     }
   }
   // reverse pass, segment by segment: recompute its states (and the records'
-  // populations entering each collision; the last step's output goes to mu,
-  // which the step back overwrites at every non-solid node), then step back
+  // populations entering each collision; the last step's output goes to the
+  // mu buffer that the next step back rewrites at every non-solid node), then
+  // step back.  mu and the bounce-back accumulator alternate between two
+  // buffers: each step reads those of the step after it.
+  int cur = 0;
+  bool first = true;
   for (int c = nseg - 1; c >= 0; c--) {
     const int len = std::min(every, n_steps - c * every);
     CHK(hipMemcpyAsync(m.tape[0], m.ck[c], sbytes, hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < len; k++) {
       a.A = m.tape[k];
-      a.B = k + 1 < len ? m.tape[k + 1] : m.mu;
+      a.B = k + 1 < len ? m.tape[k + 1] : m.mu[cur];
       CHK(launch_adjoint_forward(a, m.hrec[k], merged, s));
     }
     for (int k = len - 1; k >= 0; k--) {
       a.A = m.tape[k];
-      CHK(launch_adjoint_step(a, m.pmask, m.hrec[k], m.lam, m.w, m.mu, m.lam2, m.part, merged, s));
-      std::swap(m.lam, m.lam2);
+      AdjStep st;
+      st.hrec = m.hrec[k];
+      st.lam = first ? m.lam : nullptr;
+      st.mu_next = m.mu[cur ^ 1];
+      st.acc_in = m.acc[cur ^ 1];
+      st.acc_out = m.acc[cur];
+      st.w = m.w;
+      st.mu = m.mu[cur];
+      st.pmask = m.pmask;
+      st.amask = m.amask;
+      st.part = m.part;
+      CHK(launch_adjoint_reverse(a, st, merged, s));
+      first = false;
+      cur ^= 1;
     }
   }
+  // dJ/dg^0 = P^T mu of the last step back (plain pulls and bounce-back)
+  if (n_steps > 0) CHK(launch_adjoint_gather(a, m.pmask, m.amask, m.mu[cur ^ 1], m.acc[cur ^ 1], m.lam, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, m.lam, d_lambda, 0, s));
   CHK(launch_adjoint_grad(m.part, npart, d_grad, s));
   CHK(hipStreamSynchronize(s));

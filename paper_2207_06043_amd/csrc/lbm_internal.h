@@ -171,24 +171,38 @@ hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void*
 // g^k in [19][plane], bulk_list/nbulk_nodes set).  Solid entries of every
 // buffer of the sweep hold zero and are never written.  merged: records and
 // bulk nodes in one launch (small grids), else two.
+// Buffers of one reverse step (from state k+1 back to state k).
+struct AdjStep {
+  const double* hrec;      // records' populations entering the collision of step k (null: pull again)
+  const double* lam;       // dJ/dg^{k+1} given directly (first step of the sweep), else null
+  const double* mu_next;   // mu of step k+1 (when lam is null)
+  double* acc_in;          // bounce-back transposes of mu_next, consumed (and cleared) here
+  double* acc_out;         // bounce-back transposes of this step's mu, added here
+  const double* w;         // per-step observable (may be null)
+  double* mu;              // this step's mu
+  const uint32_t* pmask;   // per node (bulk list, then records): plainly pulled directions
+  const uint32_t* amask;   // per node: directions that can receive a bounce-back transpose
+  double* part;            // [blocks][4] gradient partials
+};
 // launch_adjoint_forward: g^{k+1} = step(A) into B; hrec (may be null):
 // [19][nrec], the records' populations entering the collision.
-// launch_adjoint_step: lam_out = dJ/dg^k from lam_in + w = dJ/dg^{k+1}
-// (w may be null; mu is scratch of the same layout; pmask: from
-// launch_adjoint_mask, one word per bulk node then per record; hrec: the
-// forward's record populations for A, or null to pull them again);
-// part[adj_part_blocks][4] += the step's derivatives of the inlet-velocity
-// scale and the body force, per block in a fixed order.
+// launch_adjoint_mask: pmask / amask (one word per bulk node, then per
+// record), once per sweep.
+// launch_adjoint_reverse: one step back, mu of step k from dJ/dg^{k+1}
+// (st.lam, or P^T st.mu_next with st.acc_in) + st.w; the links' transposes
+// of mu into st.acc_out; part[adj_part_blocks][4] += the step's derivatives
+// of the inlet-velocity scale and the body force, per block in a fixed order.
+// launch_adjoint_gather: lam = P^T mu (with acc) after the last step back.
 constexpr int ADJ_BLOCKS = 1024;
 inline int adj_part_blocks(long long nrec, long long nbulk) {
   const long long merged = (nrec + 255) / 256 + (nbulk + 255) / 256;
   return (int)(merged > 2 * ADJ_BLOCKS ? merged : 2 * ADJ_BLOCKS);
 }
 hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, int merged, hipStream_t s);
-hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t s);
-hipError_t launch_adjoint_step(const FluidArgs& a, const uint32_t* pmask, const double* hrec, const double* lam_in,
-                               const double* w, double* mu, double* lam_out, double* part, int merged,
-                               hipStream_t s);
+hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, uint32_t* amask, hipStream_t s);
+hipError_t launch_adjoint_reverse(const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s);
+hipError_t launch_adjoint_gather(const FluidArgs& a, const uint32_t* pmask, const uint32_t* amask, const double* mu,
+                                 const double* acc, double* lam, hipStream_t s);
 hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,
                                  hipStream_t s);
 hipError_t launch_adjoint_grad(const double* part, int nblk, double* grad, hipStream_t s);

@@ -2568,36 +2568,91 @@ __device__ __forceinline__ void zouhe_vjp(const double (&hz)[19], double (&m)[19
   if (kind == 0) gs += (rho * un / (1.0 - un) + rho) * R;
 }
 
-// mu = (dC/dh)^T (lam + w) at bulk node t of a.bulk_list (REC false) or at
-// boundary record t (REC true; h: the populations that entered the
-// collision, Zou-He applied, from hrec when the recompute kept them, else
-// pulled again; at open-face records mu is then taken back through
-// Zou-He).  dF, gs += the node's derivatives of the body force and of the
-// inlet-velocity scale.
+
+// The bounce-back transpose of record r's links: the mu m of each linked
+// direction goes back, with the rule's coefficients, to the three
+// populations the rule read (FP64 atomics: several links may feed one).
+__device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long long node, const double (&m)[19],
+                                              double* acc) {
+  const uint32_t mask = a.rec_mask[r];
+  if (!mask) return;
+  const Grid& G = a.g;
+  const uint32_t hqm = a.rec_mb[r];
+  const int lk0 = a.rec_link0[r];
+  const double* lc = (const double*)a.lk_c;
+  const long long nl = a.nlinks;
+  int x, y, z;
+  coords(G, node, x, y, z);
+#pragma unroll
+  for (int j = 1; j < 19; j++) {
+    if (!((mask >> j) & 1u)) continue;
+    const int l = lk0 + __popc(mask & ((1u << j) - 1u));
+    const int i = OPP[j];
+    const bool hq = (hqm >> j) & 1u;
+    const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
+    const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
+    const double k0 = lc[l], k1 = lc[nl + l], k2 = lc[2 * nl + l];
+    if (k0 != 0.0) atomicAdd(acc + (long long)i * G.plane + node, k0 * m[j]);
+    if (k1 != 0.0) atomicAdd(acc + (long long)(hq ? j : i) * G.plane + (hq ? node : n1), k1 * m[j]);
+    if (k2 != 0.0) atomicAdd(acc + (long long)(hq ? j : i) * G.plane + (hq ? n1 : n2), k2 * m[j]);
+  }
+}
+
+// One node of the reverse step: lam = P^T mu_next at the node (plain pulls
+// transposed: mu_next of direction j at the node that pulled j from here;
+// plus the bounce-back transposes gathered in acc_in), then mu = (dC/dh)^T
+// (lam + w) for bulk node t of a.bulk_list (REC false) or boundary record t
+// (REC true; h: the populations that entered the collision, Zou-He applied,
+// from hrec when the recompute kept them, else pulled again; at open-face
+// records mu is then taken back through Zou-He and the links' transposes
+// go to acc_out).  dF, gs += the node's derivatives of the body force and
+// of the inlet-velocity scale.
 template <bool REC>
-__device__ __forceinline__ void adj_collide_one(const FluidArgs& a, const double* hrec, const double* lam,
-                                                const double* w, double* mu, int t, double (&dF)[3], double& gs) {
+__device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjStep& st, int t, double (&dF)[3],
+                                                double& gs) {
   const Grid& G = a.g;
   double h[19], l[19], m[19];
   long long n;
   if (REC) {
     n = a.rec_node[t];
-    if (hrec) {
+    if (st.hrec) {
 #pragma unroll
-      for (int j = 0; j < 19; j++) h[j] = hrec[(long long)j * a.nrec + t];
+      for (int j = 0; j < 19; j++) h[j] = st.hrec[(long long)j * a.nrec + t];
     } else {
       pull_general<double>(a, t, h);
     }
   } else {
     n = a.bulk_list[t];
-    int x, y, z;
-    coords(G, n, x, y, z);
+  }
+  int x, y, z;
+  coords(G, n, x, y, z);
+  if (!REC) {
 #pragma unroll
     for (int j = 0; j < 19; j++)
       h[j] = ((const double*)a.A)[(long long)j * G.plane + nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j])];
   }
+  if (st.lam) {
 #pragma unroll
-  for (int j = 0; j < 19; j++) l[j] = lam[(long long)j * G.plane + n] + (w ? w[(long long)j * G.plane + n] : 0.0);
+    for (int j = 0; j < 19; j++) l[j] = st.lam[(long long)j * G.plane + n];
+  } else {
+    const int q = REC ? a.nbulk_nodes + t : t;
+    const uint32_t pm = st.pmask[q], am = st.amask[q];
+#pragma unroll
+    for (int j = 0; j < 19; j++) {
+      const long long src = j == 0 ? n : nbr(G, x, y, z, EX[j], EY[j], EZ[j]);
+      double v = ((pm >> j) & 1u) ? st.mu_next[(long long)j * G.plane + src] : 0.0;
+      if ((am >> j) & 1u) {
+        double* pa = st.acc_in + (long long)j * G.plane + n;
+        v += *pa;
+        *pa = 0.0;
+      }
+      l[j] = v;
+    }
+  }
+  if (st.w) {
+#pragma unroll
+    for (int j = 0; j < 19; j++) l[j] += st.w[(long long)j * G.plane + n];
+  }
   collide_vjp(h, l, a.gx, a.gy, a.gz, a.omega, m, dF);
   if (REC) {
     const int fc = a.rec_face[t];
@@ -2608,7 +2663,8 @@ __device__ __forceinline__ void adj_collide_one(const FluidArgs& a, const double
     }
   }
 #pragma unroll
-  for (int j = 0; j < 19; j++) mu[(long long)j * G.plane + n] = m[j];
+  for (int j = 0; j < 19; j++) st.mu[(long long)j * G.plane + n] = m[j];
+  if (REC) adj_links_one(a, t, n, m, st.acc_out);
 }
 
 // part[block][0..3] += the block's sums (fixed order: bitwise reproducible).
@@ -2628,41 +2684,48 @@ __device__ __forceinline__ void adj_part_add(double* part, double gs, const doub
 }
 
 // Split form: bulk (REC false) and records (REC true) in two launches,
-// grid-stride over at most ADJ_BLOCKS blocks each.
+// grid-stride over at most ADJ_BLOCKS blocks each (partials of the record
+// launch in the second half of part).
 template <bool REC>
-__global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_collide(FluidArgs a, const double* hrec, const double* lam,
-                                                                  const double* w, double* mu, double* part) {
+__global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_reverse(FluidArgs a, AdjStep st) {
   double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
   const int count = REC ? a.nrec : a.nbulk_nodes;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256)
-    adj_collide_one<REC>(a, hrec, lam, w, mu, t, dF, gs);
-  adj_part_add(part, gs, dF);
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256) adj_reverse_one<REC>(a, st, t, dF, gs);
+  adj_part_add(st.part + (REC ? 4 * ADJ_BLOCKS : 0), gs, dF);
 }
 
 // Merged form: blocks below rec_blocks take records, the rest bulk nodes.
-__global__ __launch_bounds__(256) void k_adj_collide_all(FluidArgs a, const double* hrec, const double* lam,
-                                                         const double* w, double* mu, double* part, int rec_blocks) {
+__global__ __launch_bounds__(256) void k_adj_reverse_all(FluidArgs a, AdjStep st, int rec_blocks) {
   double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
   if ((int)blockIdx.x < rec_blocks) {
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < a.nrec) adj_collide_one<true>(a, hrec, lam, w, mu, t, dF, gs);
+    if (t < a.nrec) adj_reverse_one<true>(a, st, t, dF, gs);
   } else {
     const int t = (blockIdx.x - rec_blocks) * 256 + threadIdx.x;
-    if (t < a.nbulk_nodes) adj_collide_one<false>(a, hrec, lam, w, mu, t, dF, gs);
+    if (t < a.nbulk_nodes) adj_reverse_one<false>(a, st, t, dF, gs);
   }
-  adj_part_add(part, gs, dF);
+  adj_part_add(st.part, gs, dF);
 }
 
-// For every non-solid node y (bulk list, then the records): bit j set when
-// node y + e_j pulls direction j plainly from y (computed once per sweep).
-__global__ __launch_bounds__(256) void k_adj_mask(FluidArgs a, uint32_t* pmask) {
+// Per non-solid node y (bulk list, then the records), once per sweep:
+// pmask bit j: node y + e_j pulls direction j plainly from y; amask bit d:
+// population d of y can receive a bounce-back transpose, i.e. some link
+// reads it: the link of direction opp(d) or d at y, of opp(d) at y + e_d
+// or y + 2 e_d, or of d at y - e_d (a superset: the coefficient and the
+// branch of each link are not looked at).
+__device__ __forceinline__ bool adj_linked(const FluidArgs& a, long long x, int j) {
+  if (a.ncls[x] != CLS_GENERAL) return false;
+  return (a.rec_mask[a.rec_of[x]] >> j) & 1u;
+}
+
+__global__ __launch_bounds__(256) void k_adj_mask(FluidArgs a, uint32_t* pmask, uint32_t* amask) {
   const Grid& G = a.g;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= a.nbulk_nodes + a.nrec) return;
   const long long y = t < a.nbulk_nodes ? (long long)a.bulk_list[t] : (long long)a.rec_node[t - a.nbulk_nodes];
   int px, py, pz;
   coords(G, y, px, py, pz);
-  uint32_t m = 0;
+  uint32_t m = 0, am = 0;
   for (int j = 0; j < 19; j++) {
     const long long x = j == 0 ? y : nbr(G, px, py, pz, EX[j], EY[j], EZ[j]);
     const uint8_t c = a.ncls[x];
@@ -2672,56 +2735,37 @@ __global__ __launch_bounds__(256) void k_adj_mask(FluidArgs a, uint32_t* pmask) 
       plain = j == 0 || (!((a.rec_mask[r] >> j) & 1u) && !zh_unknown(a.rec_face[r], j));
     }
     m |= plain ? (1u << j) : 0u;
+    if (j > 0) {
+      const int o = OPP[j];
+      const bool recv = adj_linked(a, y, o) || adj_linked(a, y, j) ||
+                        adj_linked(a, nbr(G, px, py, pz, EX[j], EY[j], EZ[j]), o) ||
+                        adj_linked(a, nbr(G, px, py, pz, 2 * EX[j], 2 * EY[j], 2 * EZ[j]), o) ||
+                        adj_linked(a, nbr(G, px, py, pz, -EX[j], -EY[j], -EZ[j]), j);
+      am |= recv ? (1u << j) : 0u;
+    }
   }
   pmask[t] = m;
+  amask[t] = am;
 }
 
-// The transpose of the plain pulls, at every non-solid node y (bulk list,
-// then the records): lam'[j][y] = mu[j][y + e_j] where node y + e_j pulls
-// direction j plainly from y, else 0.
-__global__ __launch_bounds__(256) void k_adj_gather(FluidArgs a, const uint32_t* pmask, const double* mu,
-                                                    double* lam) {
+// The last step of the sweep's transpose, lam = P^T mu: the plain pulls
+// transposed plus the bounce-back transposes gathered in acc, at every
+// non-solid node (bulk list, then the records).
+__global__ __launch_bounds__(256) void k_adj_gather(FluidArgs a, const uint32_t* pmask, const uint32_t* amask,
+                                                    const double* mu, const double* acc, double* lam) {
   const Grid& G = a.g;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= a.nbulk_nodes + a.nrec) return;
   const long long y = t < a.nbulk_nodes ? (long long)a.bulk_list[t] : (long long)a.rec_node[t - a.nbulk_nodes];
-  const uint32_t m = pmask[t];
+  const uint32_t m = pmask[t], am = amask[t];
   int px, py, pz;
   coords(G, y, px, py, pz);
 #pragma unroll
   for (int j = 0; j < 19; j++) {
     const long long x = j == 0 ? y : nbr(G, px, py, pz, EX[j], EY[j], EZ[j]);
-    lam[(long long)j * G.plane + y] = ((m >> j) & 1u) ? mu[(long long)j * G.plane + x] : 0.0;
-  }
-}
-
-// The transpose of the interpolated bounce-back: the mu of each linked
-// direction goes back to the three populations its rule read.
-__global__ __launch_bounds__(256) void k_adj_links(FluidArgs a, const double* mu, double* lam) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= a.nrec) return;
-  const uint32_t mask = a.rec_mask[r];
-  if (!mask) return;
-  const Grid& G = a.g;
-  const long long node = a.rec_node[r];
-  const uint32_t hqm = a.rec_mb[r];
-  const int lk0 = a.rec_link0[r];
-  const double* lc = (const double*)a.lk_c;
-  const long long nl = a.nlinks;
-  int x, y, z;
-  coords(G, node, x, y, z);
-  for (int j = 1; j < 19; j++) {
-    if (!((mask >> j) & 1u)) continue;
-    const int l = lk0 + __popc(mask & ((1u << j) - 1u));
-    const int i = OPP[j];
-    const bool hq = (hqm >> j) & 1u;
-    const double m = mu[(long long)j * G.plane + node];
-    const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
-    const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
-    const double k0 = lc[l], k1 = lc[nl + l], k2 = lc[2 * nl + l];
-    if (k0 != 0.0) atomicAdd(lam + (long long)i * G.plane + node, k0 * m);
-    if (k1 != 0.0) atomicAdd(lam + (long long)(hq ? j : i) * G.plane + (hq ? node : n1), k1 * m);
-    if (k2 != 0.0) atomicAdd(lam + (long long)(hq ? j : i) * G.plane + (hq ? n1 : n2), k2 * m);
+    double v = ((m >> j) & 1u) ? mu[(long long)j * G.plane + x] : 0.0;
+    if ((am >> j) & 1u) v += acc[(long long)j * G.plane + y];
+    lam[(long long)j * G.plane + y] = v;
   }
 }
 
@@ -2763,25 +2807,27 @@ hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, int merged, 
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, hipStream_t s) {
-  if (a.nbulk_nodes + a.nrec > 0) k_adj_mask<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask);
+hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, uint32_t* amask, hipStream_t s) {
+  if (a.nbulk_nodes + a.nrec > 0) k_adj_mask<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, amask);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const FluidArgs& a, const uint32_t* pmask, const double* hrec, const double* lam_in,
-                               const double* w, double* mu, double* lam_out, double* part, int merged,
-                               hipStream_t s) {
+hipError_t launch_adjoint_reverse(const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s) {
   const int rb = (int)cdiv(a.nrec, 256), bb = (int)cdiv(a.nbulk_nodes, 256);
   if (merged) {
-    if (rb + bb > 0) k_adj_collide_all<<<rb + bb, 256, 0, s>>>(a, hrec, lam_in, w, mu, part, rb);
+    if (rb + bb > 0) k_adj_reverse_all<<<rb + bb, 256, 0, s>>>(a, st, rb);
   } else {
-    if (bb > 0) k_adj_collide<false><<<std::min(bb, ADJ_BLOCKS), 256, 0, s>>>(a, nullptr, lam_in, w, mu, part);
-    if (rb > 0) {
-      k_adj_collide<true><<<std::min(rb, ADJ_BLOCKS), 256, 0, s>>>(a, hrec, lam_in, w, mu, part + 4 * ADJ_BLOCKS);
-    }
+    if (bb > 0) k_adj_reverse<false><<<std::min(bb, ADJ_BLOCKS), 256, 0, s>>>(a, st);
+    if (rb > 0) k_adj_reverse<true><<<std::min(rb, ADJ_BLOCKS), 256, 0, s>>>(a, st);
   }
-  if (a.nbulk_nodes + a.nrec > 0) k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, mu, lam_out);
-  if (a.nrec > 0) k_adj_links<<<cdiv(a.nrec, 256), 256, 0, s>>>(a, mu, lam_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gather(const FluidArgs& a, const uint32_t* pmask, const uint32_t* amask, const double* mu,
+                                 const double* acc, double* lam, hipStream_t s) {
+  if (a.nbulk_nodes + a.nrec > 0) {
+    k_adj_gather<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, amask, mu, acc, lam);
+  }
   return hipGetLastError();
 }
 
