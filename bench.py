@@ -325,11 +325,10 @@ def run_batch(args):
 
 
 # per fluid node and adjoint step, FP64: the forward pass and the segment
-# recompute (each a pull and a write of 19 populations, 2 x 304 B), the
-# collision transpose (reads the pulled populations, lambda and w, writes
-# mu: 608 B) and the transposed streaming (reads mu and a mask word, writes
-# lambda: 308 B)
-ADJ_BYTES_PER_NODE = 2 * 304 + 608 + 308
+# recompute (each a pull and a write of 19 populations, 2 x 304 B), and the
+# step back (reads the pulled populations, the next step's mu at the
+# neighbours and w, writes mu: 4 x 152 B; two mask words)
+ADJ_BYTES_PER_NODE = 2 * 304 + 4 * 152 + 8
 ADJ_KERNELS = ("k_adj_",)
 
 
@@ -414,9 +413,9 @@ def run_adjoint(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("one adjoint step: k_adj_collide (bulk; records with the Zou-He transpose), k_adj_gather, "
-                       "k_adj_links, plus the forward and recompute launches k_adj_fwd_bulk/k_adj_fwd_rec "
-                       "(no single kernel dominates)"),
+            "kernel": ("one adjoint step: k_adj_reverse_all (transposed streaming and bounce-back, collision "
+                       "and Zou-He transposes; records and bulk nodes in one launch) plus the forward-pass and "
+                       "recompute launches of k_adj_fwd_all"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
