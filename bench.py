@@ -163,7 +163,7 @@ def build_workload(name, precision):
 
 
 def default_precision(workload):
-    return {"pipe_sphere": "f64", "precision_form": "f16s", "differentiation_form": "f64"}.get(workload, "f32")
+    return {"pipe_sphere": "f64", "precision_form": "f16s"}.get(workload, "f32")
 
 
 def cpu_baseline(w, target_s=15.0):
@@ -324,12 +324,18 @@ def run_batch(args):
     print(json.dumps(out))
 
 
-# per fluid node and adjoint step, FP64: the forward pass and the segment
-# recompute (each a pull and a write of 19 populations, 2 x 304 B), and the
-# step back (reads the pulled populations, the next step's mu at the
-# neighbours and w, writes mu: 4 x 152 B; two mask words)
-ADJ_BYTES_PER_NODE = 2 * 304 + 4 * 152 + 8
 ADJ_KERNELS = ("k_adj_",)
+
+
+def adj_bytes_per_step(n_fluid, n_records, s):
+    """Algorithmic bytes of one adjoint step with states stored in s bytes
+    per population: per fluid node, the forward pass and the segment
+    recompute (each a pull and a write of 19 populations, 2 x 2 x 19 s), the
+    step back (reads the pulled populations, 19 s, and the next step's mu at
+    the neighbours and w, writes mu: 3 x 152 B; two mask words, 8 B); per
+    boundary record, its populations entering the collision kept by the
+    recompute and read back (2 x 152 B)."""
+    return n_fluid * (4 * 19 * s + 19 * s + 3 * 152 + 8) + n_records * 2 * 152
 
 
 def run_adjoint(args):
@@ -337,8 +343,9 @@ def run_adjoint(args):
     daughter flux of the fluid-only bifurcation (256x128x40, D = 32, from
     rest) with respect to the inlet-velocity scale and the body force, over
     args.steps steps with checkpoints every args.checkpoint_every steps, in
-    one call of the adjoint; then the same number of plain FP64 steps for
-    the comparison."""
+    one call of the adjoint (states in the lattice's precision, FP32 unless
+    --precision f64; the adjoint in FP64); then the same number of plain
+    steps of the same lattice for the comparison."""
     import torch
     import numpy as np
     import paper_2207_06043_amd as P
@@ -348,7 +355,8 @@ def run_adjoint(args):
     w.name = "differentiation_form (the bifurcation without its capsule)"
     d = w.domain
     torch.cuda.set_device(0)
-    lat = P.Lattice(d, w.tau, w.u_max, "f64")
+    precision = args.precision or "f32"
+    lat = P.Lattice(d, w.tau, w.u_max, precision)
     info = lat.info()
     n_fluid, n_box = info["n_fluid"], info["n_nodes"]
     out_nodes = np.flatnonzero(d.node_type == synth.OUTLET)
@@ -372,7 +380,7 @@ def run_adjoint(args):
     elapsed = t1 - t0
     gpu_s = ev0.elapsed_time(ev1) * 1e-3
     value = n_fluid * args.steps / elapsed / 1e6
-    # the same number of plain FP64 steps of the same lattice
+    # the same number of plain steps of the same lattice
     lat.step(args.warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -381,7 +389,7 @@ def run_adjoint(args):
     lat.sync()
     torch.cuda.synchronize()
     plain = n_fluid * args.steps / (time.perf_counter() - t2) / 1e6
-    bytes_step = ADJ_BYTES_PER_NODE * n_fluid
+    bytes_step = adj_bytes_per_step(n_fluid, info["n_general"], 8 if precision == "f64" else 4)
     achieved = bytes_step / (gpu_s / args.steps) / 1e9
     g = grad.cpu().numpy()
     out = {
@@ -395,7 +403,7 @@ def run_adjoint(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": precision + " forward, f64 adjoint",
         "data": "synthetic",
         "config": {
             "workload": "differentiation_form",
@@ -406,7 +414,7 @@ def run_adjoint(args):
             "checkpoint_every": K,
             "objective": "time-integrated upper-daughter flux; gradient w.r.t. inlet-velocity scale and body force",
             "lups_counted_on": "fluid nodes x adjoint steps (forward pass, recompute and reverse step included)",
-            "plain_fp64_mlups": round(plain, 2),
+            "plain_mlups": round(plain, 2),
             "adjoint_vs_plain": round(value / plain, 4),
             "grad": [float(x) for x in g],
             "parallelism": "single GPU",
@@ -420,7 +428,7 @@ def run_adjoint(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("differentiation_form", "f64"),
+            "traffic": measured_traffic("differentiation_form", precision),
             "bytes_per_step_alg": bytes_step,
             "avg_step_us": round(gpu_s / args.steps * 1e6, 3),
         },

@@ -1628,19 +1628,24 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   if (ctx->broken) return LBM_E_STATE;
   if (n_steps < 0 || every < 1 || !d_lambda || !d_grad)
     return fail(ctx, LBM_E_INVAL, "adjoint: n_steps >= 0, checkpoint interval >= 1, lambda and grad required");
-  if (ctx->prec != LBM_F64) return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: FP64 contexts only");
+  if (ctx->prec != LBM_F64 && ctx->prec != LBM_F32)
+    return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: FP64 and FP32 contexts only");
   if (!ctx->bodies.empty()) return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: contexts without bodies only");
   DevFlags h;
   lbm_status st = read_flags(ctx, &h);
   if (st) return st;
   CHK(ensure_bulk_list(ctx));
   const Grid& G = ctx->g;
-  const size_t sbytes = 19 * (size_t)G.plane * sizeof(double);
+  auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t dbytes = up256(19 * (size_t)G.plane * sizeof(double));  // an adjoint field (FP64)
+  const size_t xraw = 19 * (size_t)G.plane * ctx->ssize;                // a state (context's storage)
+  const size_t xbytes = up256(xraw);
   const int nseg = n_steps == 0 ? 0 : (n_steps + every - 1) / every;
   const int tlen = n_steps == 0 ? 0 : std::min(every, n_steps);
-  // one arena: lam, the two mu, w, the two bounce-back accumulators, the
-  // checkpoints, the tape, then the small pieces
-  const size_t nbig = 6 + nseg + std::max(tlen, 2);
+  const int ntape = std::max(tlen, 2);
+  // one arena: lam, the two mu, w, the two bounce-back accumulators (FP64),
+  // the checkpoints and the tape (storage type), then the small pieces
+  const size_t big_bytes = 6 * dbytes + (size_t)(nseg + ntape) * xbytes;
   const size_t hbytes = 19 * (size_t)ctx->nrec * sizeof(double);  // one step's record populations
   const int npart = adj_part_blocks(ctx->nrec, ctx->n_bulk);
   const size_t pbytes = 4 * (size_t)npart * sizeof(double);
@@ -1651,16 +1656,18 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   const char* sp_env = getenv("LBM_ADJ_SPLIT");
   const int merged = (ctx->n_bulk + ctx->nrec < (4LL << 20)) && !(sp_env && atoi(sp_env) != 0);
   DevArena ar;
-  if (hipMalloc(&ar.base, nbig * sbytes + small) != hipSuccess) {
+  if (hipMalloc(&ar.base, big_bytes + small) != hipSuccess) {
     (void)hipGetLastError();
     ar.base = nullptr;
     return fail(ctx, LBM_E_NOMEM, "adjoint: not enough device memory for the checkpoints and the tape");
   }
-  auto big = [&](size_t i) { return (double*)(ar.base + i * sbytes); };  // sbytes: a multiple of 8 * plane
+  auto big = [&](size_t i) { return (double*)(ar.base + i * dbytes); };
+  auto state = [&](size_t i) { return (void*)(ar.base + 6 * dbytes + i * xbytes); };
   struct {
     double *lam, *mu[2], *acc[2], *w, *part;
     uint32_t *pmask, *amask;
-    std::vector<double*> ck, tape, hrec;
+    std::vector<void*> ck, tape;
+    std::vector<double*> hrec;
   } m;
   m.lam = big(0);
   m.mu[0] = big(1);
@@ -1668,9 +1675,9 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   m.w = d_w ? big(3) : nullptr;
   m.acc[0] = big(4);
   m.acc[1] = big(5);
-  for (int c = 0; c < nseg; c++) m.ck.push_back(big(6 + c));
-  for (int k = 0; k < std::max(tlen, 2); k++) m.tape.push_back(big(6 + nseg + k));
-  char* sp = ar.base + nbig * sbytes;
+  for (int c = 0; c < nseg; c++) m.ck.push_back(state(c));
+  for (int k = 0; k < ntape; k++) m.tape.push_back(state(nseg + k));
+  char* sp = ar.base + big_bytes;
   auto carve = [&](size_t bytes) {
     char* p = (char*)(((uintptr_t)sp + 255) & ~(uintptr_t)255);
     sp = p + bytes;
@@ -1682,7 +1689,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   for (int k = 0; k < tlen; k++) m.hrec.push_back((double*)carve(hbytes));
   hipStream_t s = ctx->stream;
   // solid entries stay zero in every buffer (never written by the sweep)
-  CHK(hipMemsetAsync(ar.base, 0, nbig * sbytes + pbytes + 256, s));
+  CHK(hipMemsetAsync(ar.base, 0, big_bytes + pbytes + 256, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, d_lambda, m.lam, 1, s));
   if (d_w) CHK(launch_adjoint_layout(G, ctx->ncls, d_w, m.w, 1, s));
   FluidArgs a = fluid_args(ctx, 0);
@@ -1694,14 +1701,14 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   CHK(launch_adjoint_mask(a, m.pmask, m.amask, s));
   // forward pass: the state at the start of every segment
   if (nseg > 0) {
-    CHK(hipMemcpyAsync(m.ck[0], ctx->f[h.steps_done & 1], sbytes, hipMemcpyDeviceToDevice, s));
+    CHK(hipMemcpyAsync(m.ck[0], ctx->f[h.steps_done & 1], xraw, hipMemcpyDeviceToDevice, s));
     for (int c = 1; c < nseg; c++) {
-      const double* src = m.ck[c - 1];
+      const void* src = m.ck[c - 1];
       for (int k = 0; k < every; k++) {
         a.A = src;
         a.B = k == every - 1 ? m.ck[c] : m.tape[k & 1];
-        CHK(launch_adjoint_forward(a, nullptr, merged, s));
-        src = (const double*)a.B;
+        CHK(launch_adjoint_forward(ctx->prec, a, nullptr, merged, s));
+        src = a.B;
       }
     }
   }
@@ -1714,11 +1721,11 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   bool first = true;
   for (int c = nseg - 1; c >= 0; c--) {
     const int len = std::min(every, n_steps - c * every);
-    CHK(hipMemcpyAsync(m.tape[0], m.ck[c], sbytes, hipMemcpyDeviceToDevice, s));
+    CHK(hipMemcpyAsync(m.tape[0], m.ck[c], xraw, hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < len; k++) {
       a.A = m.tape[k];
-      a.B = k + 1 < len ? m.tape[k + 1] : m.mu[cur];
-      CHK(launch_adjoint_forward(a, m.hrec[k], merged, s));
+      a.B = k + 1 < len ? m.tape[k + 1] : (void*)m.mu[cur];  // mu[cur]: large enough for any storage
+      CHK(launch_adjoint_forward(ctx->prec, a, m.hrec[k], merged, s));
     }
     for (int k = len - 1; k >= 0; k--) {
       a.A = m.tape[k];
@@ -1733,7 +1740,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
       st.pmask = m.pmask;
       st.amask = m.amask;
       st.part = m.part;
-      CHK(launch_adjoint_reverse(a, st, merged, s));
+      CHK(launch_adjoint_reverse(ctx->prec, a, st, merged, s));
       first = false;
       cur ^= 1;
     }

@@ -167,10 +167,11 @@ hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, hipStream_t s);
 // node count, sum of deviations, momentum); part holds 5 x 1024 doubles.
 hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void* f1, const uint8_t* ncls,
                             const DevFlags* flags, double* part, double* out, hipStream_t s);
-// Adjoint of the fluid step (FP64, no bodies; FluidArgs with A = the state
-// g^k in [19][plane], bulk_list/nbulk_nodes set).  Solid entries of every
-// buffer of the sweep hold zero and are never written.  merged: records and
-// bulk nodes in one launch (small grids), else two.
+// Adjoint of the fluid step (no bodies; FluidArgs with A = the state g^k in
+// [19][plane] in the context's storage, prec 0 FP64 or 1 FP32, bulk_list /
+// nbulk_nodes set); the adjoint quantities are FP64 in both.  Solid entries
+// of every buffer of the sweep hold zero and are never written.  merged:
+// records and bulk nodes in one launch (small grids), else two.
 // Buffers of one reverse step (from state k+1 back to state k).
 struct AdjStep {
   const double* hrec;      // records' populations entering the collision of step k (null: pull again)
@@ -198,9 +199,9 @@ inline int adj_part_blocks(long long nrec, long long nbulk) {
   const long long merged = (nrec + 255) / 256 + (nbulk + 255) / 256;
   return (int)(merged > 2 * ADJ_BLOCKS ? merged : 2 * ADJ_BLOCKS);
 }
-hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, int merged, hipStream_t s);
+hipError_t launch_adjoint_forward(int prec, const FluidArgs& a, double* hrec, int merged, hipStream_t s);
 hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, uint32_t* amask, hipStream_t s);
-hipError_t launch_adjoint_reverse(const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s);
+hipError_t launch_adjoint_reverse(int prec, const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s);
 hipError_t launch_adjoint_gather(const FluidArgs& a, const uint32_t* pmask, const uint32_t* amask, const double* mu,
                                  const double* acc, double* lam, hipStream_t s);
 hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,

@@ -2399,61 +2399,68 @@ __device__ __forceinline__ bool zh_unknown(int fc, int j) {
   return fc != 0xff && sg * (ax == 0 ? EX[j] : (ax == 1 ? EY[j] : EZ[j])) == 1;
 }
 
-// One forward step of the FP64 fluid (the same pull and collision as the
-// stream-collide kernels) from a.A into a.B: bulk node t of a.bulk_list, or
+// One forward step of the fluid in the context's precision (storage S, the
+// same pull and collision as the stream-collide kernels) from a.A into a.B:
+// bulk node t of a.bulk_list, or
 // boundary record r.  Solid nodes are not written (they hold zero in every
 // buffer of the sweep).  hrec (may be null): [19][nrec], the records'
 // populations entering the collision (after Zou-He), kept for the step back.
+template <class S>
 __device__ __forceinline__ void adj_fwd_bulk_one(const FluidArgs& a, int t) {
+  typedef typename Store<S>::C C;
   const Grid& G = a.g;
   const long long n = a.bulk_list[t];
-  const double* A = (const double*)a.A;
-  double* B = (double*)a.B;
+  S* B = (S*)a.B;
   int x, y, z;
   coords(G, n, x, y, z);
-  double g[19], dr, ux, uy, uz;
+  C g[19], dr, ux, uy, uz;
 #pragma unroll
-  for (int j = 0; j < 19; j++) g[j] = A[(long long)j * G.plane + nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j])];
-  collide<double>(g, a.gx, a.gy, a.gz, a.omega, dr, ux, uy, uz);
+  for (int j = 0; j < 19; j++) g[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
+  collide<C>(g, (C)a.gx, (C)a.gy, (C)a.gz, (C)a.omega, dr, ux, uy, uz);
 #pragma unroll
-  for (int j = 0; j < 19; j++) B[(long long)j * G.plane + n] = g[j];
+  for (int j = 0; j < 19; j++) B[(long long)j * G.plane + n] = (S)g[j];
 }
 
+template <class S>
 __device__ __forceinline__ void adj_fwd_rec_one(const FluidArgs& a, double* hrec, int r) {
-  double g[19], dr, ux, uy, uz;
-  pull_general<double>(a, r, g);
+  typedef typename Store<S>::C C;
+  C g[19], dr, ux, uy, uz;
+  pull_general<S>(a, r, g);
   if (hrec) {
 #pragma unroll
-    for (int j = 0; j < 19; j++) hrec[(long long)j * a.nrec + r] = g[j];
+    for (int j = 0; j < 19; j++) hrec[(long long)j * a.nrec + r] = (double)g[j];
   }
-  collide<double>(g, a.gx, a.gy, a.gz, a.omega, dr, ux, uy, uz);
+  collide<C>(g, (C)a.gx, (C)a.gy, (C)a.gz, (C)a.omega, dr, ux, uy, uz);
   const long long n = a.rec_node[r];
-  double* B = (double*)a.B;
+  S* B = (S*)a.B;
 #pragma unroll
-  for (int j = 0; j < 19; j++) B[(long long)j * a.g.plane + n] = g[j];
+  for (int j = 0; j < 19; j++) B[(long long)j * a.g.plane + n] = (S)g[j];
 }
 
 // Split form: the bulk kernel keeps the small register budget of the plain
 // pull; merged form (small grids): the records' latency-bound blocks run
 // alongside the bulk blocks in one launch (blocks below rec_blocks take
 // records).
+template <class S>
 __global__ __launch_bounds__(256) void k_adj_fwd_bulk(FluidArgs a) {
   const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t < a.nbulk_nodes) adj_fwd_bulk_one(a, t);
+  if (t < a.nbulk_nodes) adj_fwd_bulk_one<S>(a, t);
 }
 
+template <class S>
 __global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a, double* hrec) {
   const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r < a.nrec) adj_fwd_rec_one(a, hrec, r);
+  if (r < a.nrec) adj_fwd_rec_one<S>(a, hrec, r);
 }
 
+template <class S>
 __global__ __launch_bounds__(256) void k_adj_fwd_all(FluidArgs a, double* hrec, int rec_blocks) {
   if ((int)blockIdx.x < rec_blocks) {
     const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r < a.nrec) adj_fwd_rec_one(a, hrec, r);
+    if (r < a.nrec) adj_fwd_rec_one<S>(a, hrec, r);
   } else {
     const int t = (blockIdx.x - rec_blocks) * 256 + threadIdx.x;
-    if (t < a.nbulk_nodes) adj_fwd_bulk_one(a, t);
+    if (t < a.nbulk_nodes) adj_fwd_bulk_one<S>(a, t);
   }
 }
 
@@ -2572,6 +2579,7 @@ __device__ __forceinline__ void zouhe_vjp(const double (&hz)[19], double (&m)[19
 // The bounce-back transpose of record r's links: the mu m of each linked
 // direction goes back, with the rule's coefficients, to the three
 // populations the rule read (FP64 atomics: several links may feed one).
+template <class S>
 __device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long long node, const double (&m)[19],
                                               double* acc) {
   const uint32_t mask = a.rec_mask[r];
@@ -2579,7 +2587,7 @@ __device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long lo
   const Grid& G = a.g;
   const uint32_t hqm = a.rec_mb[r];
   const int lk0 = a.rec_link0[r];
-  const double* lc = (const double*)a.lk_c;
+  const typename Store<S>::C* lc = (const typename Store<S>::C*)a.lk_c;
   const long long nl = a.nlinks;
   int x, y, z;
   coords(G, node, x, y, z);
@@ -2591,7 +2599,7 @@ __device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long lo
     const bool hq = (hqm >> j) & 1u;
     const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
     const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
-    const double k0 = lc[l], k1 = lc[nl + l], k2 = lc[2 * nl + l];
+    const double k0 = (double)lc[l], k1 = (double)lc[nl + l], k2 = (double)lc[2 * nl + l];
     if (k0 != 0.0) atomicAdd(acc + (long long)i * G.plane + node, k0 * m[j]);
     if (k1 != 0.0) atomicAdd(acc + (long long)(hq ? j : i) * G.plane + (hq ? node : n1), k1 * m[j]);
     if (k2 != 0.0) atomicAdd(acc + (long long)(hq ? j : i) * G.plane + (hq ? n1 : n2), k2 * m[j]);
@@ -2607,7 +2615,7 @@ __device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long lo
 // records mu is then taken back through Zou-He and the links' transposes
 // go to acc_out).  dF, gs += the node's derivatives of the body force and
 // of the inlet-velocity scale.
-template <bool REC>
+template <bool REC, class S>
 __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjStep& st, int t, double (&dF)[3],
                                                 double& gs) {
   const Grid& G = a.g;
@@ -2619,7 +2627,10 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
 #pragma unroll
       for (int j = 0; j < 19; j++) h[j] = st.hrec[(long long)j * a.nrec + t];
     } else {
-      pull_general<double>(a, t, h);
+      typename Store<S>::C hc[19];
+      pull_general<S>(a, t, hc);
+#pragma unroll
+      for (int j = 0; j < 19; j++) h[j] = (double)hc[j];
     }
   } else {
     n = a.bulk_list[t];
@@ -2628,8 +2639,7 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
   coords(G, n, x, y, z);
   if (!REC) {
 #pragma unroll
-    for (int j = 0; j < 19; j++)
-      h[j] = ((const double*)a.A)[(long long)j * G.plane + nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j])];
+    for (int j = 0; j < 19; j++) h[j] = (double)ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
   }
   if (st.lam) {
 #pragma unroll
@@ -2664,7 +2674,7 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
   }
 #pragma unroll
   for (int j = 0; j < 19; j++) st.mu[(long long)j * G.plane + n] = m[j];
-  if (REC) adj_links_one(a, t, n, m, st.acc_out);
+  if (REC) adj_links_one<S>(a, t, n, m, st.acc_out);
 }
 
 // part[block][0..3] += the block's sums (fixed order: bitwise reproducible).
@@ -2686,23 +2696,25 @@ __device__ __forceinline__ void adj_part_add(double* part, double gs, const doub
 // Split form: bulk (REC false) and records (REC true) in two launches,
 // grid-stride over at most ADJ_BLOCKS blocks each (partials of the record
 // launch in the second half of part).
-template <bool REC>
+template <bool REC, class S>
 __global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_reverse(FluidArgs a, AdjStep st) {
   double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
   const int count = REC ? a.nrec : a.nbulk_nodes;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256) adj_reverse_one<REC>(a, st, t, dF, gs);
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256)
+    adj_reverse_one<REC, S>(a, st, t, dF, gs);
   adj_part_add(st.part + (REC ? 4 * ADJ_BLOCKS : 0), gs, dF);
 }
 
 // Merged form: blocks below rec_blocks take records, the rest bulk nodes.
+template <class S>
 __global__ __launch_bounds__(256) void k_adj_reverse_all(FluidArgs a, AdjStep st, int rec_blocks) {
   double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
   if ((int)blockIdx.x < rec_blocks) {
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < a.nrec) adj_reverse_one<true>(a, st, t, dF, gs);
+    if (t < a.nrec) adj_reverse_one<true, S>(a, st, t, dF, gs);
   } else {
     const int t = (blockIdx.x - rec_blocks) * 256 + threadIdx.x;
-    if (t < a.nbulk_nodes) adj_reverse_one<false>(a, st, t, dF, gs);
+    if (t < a.nbulk_nodes) adj_reverse_one<false, S>(a, st, t, dF, gs);
   }
   adj_part_add(st.part, gs, dF);
 }
@@ -2796,14 +2808,20 @@ __global__ void k_adj_grad_final(const double* part, int nblk, double* grad) {
   grad[q] = t;
 }
 
-hipError_t launch_adjoint_forward(const FluidArgs& a, double* hrec, int merged, hipStream_t s) {
+template <class S>
+static void adj_forward(const FluidArgs& a, double* hrec, int merged, hipStream_t s) {
   const int rb = (int)cdiv(a.nrec, 256), bb = (int)cdiv(a.nbulk_nodes, 256);
   if (merged) {
-    if (rb + bb > 0) k_adj_fwd_all<<<rb + bb, 256, 0, s>>>(a, hrec, rb);
+    if (rb + bb > 0) k_adj_fwd_all<S><<<rb + bb, 256, 0, s>>>(a, hrec, rb);
   } else {
-    if (bb > 0) k_adj_fwd_bulk<<<bb, 256, 0, s>>>(a);
-    if (rb > 0) k_adj_fwd_rec<<<rb, 256, 0, s>>>(a, hrec);
+    if (bb > 0) k_adj_fwd_bulk<S><<<bb, 256, 0, s>>>(a);
+    if (rb > 0) k_adj_fwd_rec<S><<<rb, 256, 0, s>>>(a, hrec);
   }
+}
+
+hipError_t launch_adjoint_forward(int prec, const FluidArgs& a, double* hrec, int merged, hipStream_t s) {
+  if (prec == 0) adj_forward<double>(a, hrec, merged, s);
+  else adj_forward<float>(a, hrec, merged, s);
   return hipGetLastError();
 }
 
@@ -2812,14 +2830,20 @@ hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, uint32_t* am
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_reverse(const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s) {
+template <class S>
+static void adj_reverse(const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s) {
   const int rb = (int)cdiv(a.nrec, 256), bb = (int)cdiv(a.nbulk_nodes, 256);
   if (merged) {
-    if (rb + bb > 0) k_adj_reverse_all<<<rb + bb, 256, 0, s>>>(a, st, rb);
+    if (rb + bb > 0) k_adj_reverse_all<S><<<rb + bb, 256, 0, s>>>(a, st, rb);
   } else {
-    if (bb > 0) k_adj_reverse<false><<<std::min(bb, ADJ_BLOCKS), 256, 0, s>>>(a, st);
-    if (rb > 0) k_adj_reverse<true><<<std::min(rb, ADJ_BLOCKS), 256, 0, s>>>(a, st);
+    if (bb > 0) k_adj_reverse<false, S><<<std::min(bb, ADJ_BLOCKS), 256, 0, s>>>(a, st);
+    if (rb > 0) k_adj_reverse<true, S><<<std::min(rb, ADJ_BLOCKS), 256, 0, s>>>(a, st);
   }
+}
+
+hipError_t launch_adjoint_reverse(int prec, const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s) {
+  if (prec == 0) adj_reverse<double>(a, st, merged, s);
+  else adj_reverse<float>(a, st, merged, s);
   return hipGetLastError();
 }
 

@@ -121,9 +121,9 @@ def _fd(d, w, n, c, wv, what, hs, **kw):
             for h in hs]
 
 
-def _check(name, adj, fds, scale):
+def _check(name, adj, fds, scale, rel=REL):
     gap = abs(fds[0] - fds[-1])
-    tol = REL * scale + 4 * gap
+    tol = rel * scale + 4 * gap
     _say(f"  {name}: adjoint {adj:+.12e}  oracle FD {fds[-1]:+.12e}  |diff| {abs(adj - fds[-1]):.2e} "
          f"(bound {tol:.2e})")
     return abs(adj - fds[-1]) <= tol
@@ -197,6 +197,33 @@ def test_adjoint_checkpoint_interval_and_state(lib):
     assert torch.equal(lam.cpu(), torch.from_numpy(c)) and torch.all(g == 0)
 
 
+@pytest.mark.parametrize("name", ["pipe", "bifurcation"])
+def test_adjoint_fp32_forward_matches_oracle_differences(lib, name):
+    """FP32 forward (states and tape in FP32, the step of an FP32 lattice),
+    FP64 adjoint: the gradient moves from the FP64 one by what FP32 does to
+    the trajectory; held to the FP32 bar 2e-5 (relative) against the oracle's
+    differences and against the FP64 adjoint."""
+    import torch
+    w, c, wv, du, dr = _case(name)
+    d = w.domain
+    n, K = 30, 7
+    lam64, g64 = lib.from_workload(w).adjoint(n, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=K)
+    lat = lib.from_workload(w, precision="f32")
+    lam, grad = lat.adjoint(n, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=K)
+    lam, grad, lam64, g64 = (t.cpu().numpy() for t in (lam, grad, lam64, g64))
+    e_l = np.abs(lam - lam64).max() / np.abs(lam64).max()
+    _say(f"[adjoint] {name} FP32 forward: lambda vs FP64 adjoint {e_l:.1e}")
+    assert e_l <= 2e-5
+    fscale = np.abs(grad[1:]).max()
+    fd_s = _fd(d, w, n, c, wv, "s", (1e-4, 5e-5))
+    assert abs(grad[0] - fd_s[-1]) <= 2e-5 * abs(fd_s[-1]) + 4 * abs(fd_s[0] - fd_s[-1]), (grad[0], fd_s)
+    _say(f"  dJ/ds: FP32 forward {grad[0]:+.10e}  oracle FD {fd_s[-1]:+.10e}  FP64 adjoint {g64[0]:+.10e}")
+    for k, comp in enumerate(("Fx", "Fy", "Fz")):
+        fd = _fd(d, w, n, c, wv, comp, (1e-6, 5e-7))
+        _say(f"  dJ/d{comp}: FP32 forward {grad[1 + k]:+.10e}  oracle FD {fd[-1]:+.10e}")
+        assert abs(grad[1 + k] - fd[-1]) <= 2e-5 * fscale + 4 * abs(fd[0] - fd[-1])
+
+
 def test_adjoint_split_and_merged_launches_agree(lib, monkeypatch):
     """Records and bulk nodes in one launch (the small-grid default) or two
     (LBM_ADJ_SPLIT=1, the large-grid form): the same gradient to rounding
@@ -216,7 +243,7 @@ def test_adjoint_split_and_merged_launches_agree(lib, monkeypatch):
 def test_adjoint_rejects_unsupported_contexts(lib):
     import torch
     lam = torch.zeros(19, 8 * 8 * 8, dtype=torch.float64)
-    lat = lib.Lattice(synth.periodic_box(8, 8, 8), 0.8, precision="f32")
+    lat = lib.Lattice(synth.periodic_box(8, 8, 8), 0.8, precision="f16s")
     with pytest.raises(lib.LbmError) as e:
         lat.adjoint(1, lam)
     assert e.value.status == 7
@@ -231,11 +258,14 @@ def test_adjoint_rejects_unsupported_contexts(lib):
     assert e.value.status == 1
 
 
-def test_differentiation_form_full_size(lib):
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_differentiation_form_full_size(lib, precision):
     """2000 steps of the 256x128x40 bifurcation from rest, checkpoints every
     100: gradients of the time-integrated upper-daughter flux and of the
-    flux split against the oracle's central differences."""
+    flux split against the oracle's central differences; FP64 forward to
+    1e-8, FP32 forward (FP64 adjoint) to the FP32 bar 2e-5."""
     import torch
+    rel = {"f64": REL, "f32": 2e-5}[precision]
     g = np.load(os.path.join(HERE, "golden", "adjoint_fd.npz"))
     w = fdcase.workload()
     w.bodies = []
@@ -243,9 +273,9 @@ def test_differentiation_form_full_size(lib):
     steps = int(g["steps"])
     w_up, w_lo = fdcase.weights(d)
     j_up, j_lo = g["base"]
-    lat = lib.from_workload(w)
+    lat = lib.from_workload(w, precision=precision)
     zero = torch.zeros(19, d.n_nodes, dtype=torch.float64)
-    _say(f"[adjoint] full size {d.nx}x{d.ny}x{d.nz}, {steps} steps")
+    _say(f"[adjoint] full size {d.nx}x{d.ny}x{d.nz}, {steps} steps, {precision} forward")
     _, g_up = lat.adjoint(steps, zero, torch.from_numpy(w_up), checkpoint_every=100)
     w_split = (j_lo * w_up - j_up * w_lo) / (j_up + j_lo) ** 2
     _, g_split = lat.adjoint(steps, zero, torch.from_numpy(w_split), checkpoint_every=100)
@@ -261,10 +291,10 @@ def test_differentiation_form_full_size(lib):
         return out
 
     ok = True
-    ok &= _check("dJ_up/ds", g_up[0], fd("s", "up"), abs(g_up[0]))
-    ok &= _check("dJ_up/dFx", g_up[1], fd("Fx", "up"), np.abs(g_up[1:]).max())
-    ok &= _check("dJ_up/dFy", g_up[2], fd("Fy", "up"), np.abs(g_up[1:]).max())
-    ok &= _check("dS/dFy", g_split[2], fd("Fy", "split"), abs(g_split[2]))
+    ok &= _check("dJ_up/ds", g_up[0], fd("s", "up"), abs(g_up[0]), rel)
+    ok &= _check("dJ_up/dFx", g_up[1], fd("Fx", "up"), np.abs(g_up[1:]).max(), rel)
+    ok &= _check("dJ_up/dFy", g_up[2], fd("Fy", "up"), np.abs(g_up[1:]).max(), rel)
+    ok &= _check("dS/dFy", g_split[2], fd("Fy", "split"), abs(g_split[2]), rel)
     # the geometry is symmetric in y: the split does not move with s
-    ok &= _check("dS/ds", g_split[0], fd("s", "split"), abs(g_split[2]) * 1e-3)
+    ok &= _check("dS/ds", g_split[0], fd("s", "split"), abs(g_split[2]) * 1e-3, rel)
     assert ok
