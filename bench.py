@@ -327,15 +327,16 @@ def run_batch(args):
 ADJ_KERNELS = ("k_adj_",)
 
 
-def adj_bytes_per_step(n_fluid, n_records, s):
+def adj_bytes_per_step(n_fluid, n_records, n_w, s):
     """Algorithmic bytes of one adjoint step with states stored in s bytes
     per population: per fluid node, the forward pass and the segment
     recompute (each a pull and a write of 19 populations, 2 x 2 x 19 s), the
     step back (reads the pulled populations, 19 s, and the next step's mu at
-    the neighbours and w, writes mu: 3 x 152 B; two mask words, 8 B); per
-    boundary record, its populations entering the collision kept by the
-    recompute and read back (2 x 152 B)."""
-    return n_fluid * (4 * 19 * s + 19 * s + 3 * 152 + 8) + n_records * 2 * 152
+    the neighbours, writes mu: 2 x 152 B; two mask words, 8 B); per node
+    where the observable w is non-zero, its 152 B; per boundary record, its
+    populations entering the collision kept by the recompute and read back
+    (2 x 152 B)."""
+    return n_fluid * (4 * 19 * s + 19 * s + 2 * 152 + 8) + n_w * 152 + n_records * 2 * 152
 
 
 def run_adjoint(args):
@@ -389,7 +390,7 @@ def run_adjoint(args):
     lat.sync()
     torch.cuda.synchronize()
     plain = n_fluid * args.steps / (time.perf_counter() - t2) / 1e6
-    bytes_step = adj_bytes_per_step(n_fluid, info["n_general"], 8 if precision == "f64" else 4)
+    bytes_step = adj_bytes_per_step(n_fluid, info["n_general"], len(up), 8 if precision == "f64" else 4)
     achieved = bytes_step / (gpu_s / args.steps) / 1e9
     g = grad.cpu().numpy()
     out = {

@@ -1698,7 +1698,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   a.mac = nullptr;
   a.bulk_list = ctx->bulk_list;
   a.nbulk_nodes = (int)ctx->n_bulk;
-  CHK(launch_adjoint_mask(a, m.pmask, m.amask, s));
+  CHK(launch_adjoint_mask(a, m.w, m.pmask, m.amask, s));
   // forward pass: the state at the start of every segment
   if (nseg > 0) {
     CHK(hipMemcpyAsync(m.ck[0], ctx->f[h.steps_done & 1], xraw, hipMemcpyDeviceToDevice, s));

@@ -174,7 +174,7 @@ hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void*
 // records and bulk nodes in one launch (small grids), else two.
 // Buffers of one reverse step (from state k+1 back to state k).
 struct AdjStep {
-  const double* hrec;      // records' populations entering the collision of step k (null: pull again)
+  const double* hrec;      // records' populations entering the collision of step k
   const double* lam;       // dJ/dg^{k+1} given directly (first step of the sweep), else null
   const double* mu_next;   // mu of step k+1 (when lam is null)
   double* acc_in;          // bounce-back transposes of mu_next, consumed (and cleared) here
@@ -188,7 +188,8 @@ struct AdjStep {
 // launch_adjoint_forward: g^{k+1} = step(A) into B; hrec (may be null):
 // [19][nrec], the records' populations entering the collision.
 // launch_adjoint_mask: pmask / amask (one word per bulk node, then per
-// record), once per sweep.
+// record; amask bit 31: w non-zero at the node), once per sweep, after w
+// is in place.
 // launch_adjoint_reverse: one step back, mu of step k from dJ/dg^{k+1}
 // (st.lam, or P^T st.mu_next with st.acc_in) + st.w; the links' transposes
 // of mu into st.acc_out; part[adj_part_blocks][4] += the step's derivatives
@@ -200,7 +201,8 @@ inline int adj_part_blocks(long long nrec, long long nbulk) {
   return (int)(merged > 2 * ADJ_BLOCKS ? merged : 2 * ADJ_BLOCKS);
 }
 hipError_t launch_adjoint_forward(int prec, const FluidArgs& a, double* hrec, int merged, hipStream_t s);
-hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, uint32_t* amask, hipStream_t s);
+hipError_t launch_adjoint_mask(const FluidArgs& a, const double* w, uint32_t* pmask, uint32_t* amask,
+                               hipStream_t s);
 hipError_t launch_adjoint_reverse(int prec, const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s);
 hipError_t launch_adjoint_gather(const FluidArgs& a, const uint32_t* pmask, const uint32_t* amask, const double* mu,
                                  const double* acc, double* lam, hipStream_t s);

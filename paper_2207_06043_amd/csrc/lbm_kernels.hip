@@ -2611,9 +2611,8 @@ __device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long lo
 // plus the bounce-back transposes gathered in acc_in), then mu = (dC/dh)^T
 // (lam + w) for bulk node t of a.bulk_list (REC false) or boundary record t
 // (REC true; h: the populations that entered the collision, Zou-He applied,
-// from hrec when the recompute kept them, else pulled again; at open-face
-// records mu is then taken back through Zou-He and the links' transposes
-// go to acc_out).  dF, gs += the node's derivatives of the body force and
+// as the recompute kept them in hrec; at open-face records mu is then taken
+// back through Zou-He and the links' transposes go to acc_out).  dF, gs += the node's derivatives of the body force and
 // of the inlet-velocity scale.
 template <bool REC, class S>
 __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjStep& st, int t, double (&dF)[3],
@@ -2623,15 +2622,8 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
   long long n;
   if (REC) {
     n = a.rec_node[t];
-    if (st.hrec) {
 #pragma unroll
-      for (int j = 0; j < 19; j++) h[j] = st.hrec[(long long)j * a.nrec + t];
-    } else {
-      typename Store<S>::C hc[19];
-      pull_general<S>(a, t, hc);
-#pragma unroll
-      for (int j = 0; j < 19; j++) h[j] = (double)hc[j];
-    }
+    for (int j = 0; j < 19; j++) h[j] = st.hrec[(long long)j * a.nrec + t];
   } else {
     n = a.bulk_list[t];
   }
@@ -2641,12 +2633,13 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
 #pragma unroll
     for (int j = 0; j < 19; j++) h[j] = (double)ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
   }
+  const int q = REC ? a.nbulk_nodes + t : t;
+  const uint32_t am = st.amask[q];
   if (st.lam) {
 #pragma unroll
     for (int j = 0; j < 19; j++) l[j] = st.lam[(long long)j * G.plane + n];
   } else {
-    const int q = REC ? a.nbulk_nodes + t : t;
-    const uint32_t pm = st.pmask[q], am = st.amask[q];
+    const uint32_t pm = st.pmask[q];
 #pragma unroll
     for (int j = 0; j < 19; j++) {
       const long long src = j == 0 ? n : nbr(G, x, y, z, EX[j], EY[j], EZ[j]);
@@ -2659,7 +2652,7 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
       l[j] = v;
     }
   }
-  if (st.w) {
+  if (st.w && (am >> 31)) {  // w is non-zero at this node
 #pragma unroll
     for (int j = 0; j < 19; j++) l[j] += st.w[(long long)j * G.plane + n];
   }
@@ -2720,7 +2713,8 @@ __global__ __launch_bounds__(256) void k_adj_reverse_all(FluidArgs a, AdjStep st
 }
 
 // Per non-solid node y (bulk list, then the records), once per sweep:
-// pmask bit j: node y + e_j pulls direction j plainly from y; amask bit d:
+// pmask bit j: node y + e_j pulls direction j plainly from y; amask bit 31:
+// the observable w is non-zero at y; amask bit d < 19:
 // population d of y can receive a bounce-back transpose, i.e. some link
 // reads it: the link of direction opp(d) or d at y, of opp(d) at y + e_d
 // or y + 2 e_d, or of d at y - e_d (a superset: the coefficient and the
@@ -2730,7 +2724,7 @@ __device__ __forceinline__ bool adj_linked(const FluidArgs& a, long long x, int 
   return (a.rec_mask[a.rec_of[x]] >> j) & 1u;
 }
 
-__global__ __launch_bounds__(256) void k_adj_mask(FluidArgs a, uint32_t* pmask, uint32_t* amask) {
+__global__ __launch_bounds__(256) void k_adj_mask(FluidArgs a, const double* w, uint32_t* pmask, uint32_t* amask) {
   const Grid& G = a.g;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= a.nbulk_nodes + a.nrec) return;
@@ -2755,6 +2749,11 @@ __global__ __launch_bounds__(256) void k_adj_mask(FluidArgs a, uint32_t* pmask, 
                         adj_linked(a, nbr(G, px, py, pz, -EX[j], -EY[j], -EZ[j]), j);
       am |= recv ? (1u << j) : 0u;
     }
+  }
+  if (w) {
+    bool nz = false;
+    for (int j = 0; j < 19; j++) nz |= w[(long long)j * G.plane + y] != 0.0;
+    am |= nz ? (1u << 31) : 0u;
   }
   pmask[t] = m;
   amask[t] = am;
@@ -2825,8 +2824,9 @@ hipError_t launch_adjoint_forward(int prec, const FluidArgs& a, double* hrec, in
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_mask(const FluidArgs& a, uint32_t* pmask, uint32_t* amask, hipStream_t s) {
-  if (a.nbulk_nodes + a.nrec > 0) k_adj_mask<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, pmask, amask);
+hipError_t launch_adjoint_mask(const FluidArgs& a, const double* w, uint32_t* pmask, uint32_t* amask,
+                               hipStream_t s) {
+  if (a.nbulk_nodes + a.nrec > 0) k_adj_mask<<<cdiv(a.nbulk_nodes + a.nrec, 256), 256, 0, s>>>(a, w, pmask, amask);
   return hipGetLastError();
 }
 
