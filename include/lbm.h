@@ -161,6 +161,13 @@ lbm_status lbm_sync(lbm_ctx *ctx);
 lbm_status lbm_get_fields(lbm_ctx *ctx, double *d_rho, double *d_u);
 /* Post-collision populations [19][N] (solid nodes 0). */
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *d_f);
+/* The inverse: the current state's post-collision populations become d_f
+ * ([19][N] FP64 device array, x fastest; entries at solid nodes ignored),
+ * stored as f - w_i rounded to the context's storage (the state the next
+ * lbm_step starts from, as Eq. evoleq's f* of the last step).  The step
+ * count, the force field and the bodies are not changed.  Asynchronous on
+ * the context's stream (d_f must stay valid until it completes). */
+lbm_status lbm_set_populations(lbm_ctx *ctx, const double *d_f);
 /* Immersed-boundary force density [3][N] of the last completed step. */
 lbm_status lbm_get_force(lbm_ctx *ctx, double *d_fib);
 /* Vertex positions and velocities [nv][3] of a body. */

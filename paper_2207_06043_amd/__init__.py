@@ -4,7 +4,7 @@ immersed-boundary step of Coclite, de Tullio, Pascazio and Politi (arXiv
 ABI in ``include/lbm.h``; this package only marshals arguments to it.
 """
 from ._abi import (EXPORTS, LIB_PATH, LBM_E_DAMAGED, LBM_E_UNSTABLE, LBM_OK, Batch, Lattice,
-                   LbmError, from_workload, load_library)
+                   LbmError, from_workload, load_library, trajectory)
 
 __all__ = ["EXPORTS", "LIB_PATH", "LBM_E_DAMAGED", "LBM_E_UNSTABLE", "LBM_OK", "Batch", "Lattice",
-           "LbmError", "from_workload", "load_library"]
+           "LbmError", "from_workload", "load_library", "trajectory"]

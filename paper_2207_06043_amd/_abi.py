@@ -22,7 +22,8 @@ PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTS = ["lbm_create", "lbm_destroy", "lbm_last_error", "lbm_info", "lbm_add_body", "lbm_step",
-           "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_get_force", "lbm_get_body",
+           "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_force",
+           "lbm_get_body",
            "ib_interpolate", "ib_spread", "lbm_adjoint_step", "lbm_save", "lbm_load",
            "lbm_time_fluid_kernel", "lbm_set_graph", "lbm_set_launch_shape", "lbm_diagnostics",
            "lbm_batch_create",
@@ -105,6 +106,8 @@ def load_library():
         getattr(L, name).argtypes = [vp, vp, vp]
     L.lbm_get_populations.restype = st
     L.lbm_get_populations.argtypes = [vp, vp]
+    L.lbm_set_populations.restype = st
+    L.lbm_set_populations.argtypes = [vp, vp]
     L.lbm_get_force.restype = st
     L.lbm_get_force.argtypes = [vp, vp]
     L.lbm_get_body.restype = st
@@ -295,6 +298,13 @@ class Lattice:
         self.stream.synchronize()
         return f
 
+    def set_populations(self, f):
+        """The current state's populations become f ([19][N]; see
+        lbm_set_populations)."""
+        f = f.to(self.device, self._torch.float64).reshape(19, self.N).contiguous()
+        self._check(load_library().lbm_set_populations(self._h, _ptr(f)))
+        self.stream.synchronize()
+
     def force(self):
         f = self._empty(3, self.N)
         self._check(load_library().lbm_get_force(self._h, _ptr(f)))
@@ -418,3 +428,57 @@ def from_workload(w, precision=None, with_bodies=True):
         for b in w.bodies:
             lat.add_body(b)
     return lat
+
+
+_TRAJECTORY = None
+
+
+def _trajectory_class():
+    global _TRAJECTORY
+    if _TRAJECTORY is None:
+        import torch
+
+        class Trajectory(torch.autograd.Function):
+            """J(f0) = <lam, f^n> + sum_{t=1..n} <w, f^t> over n steps of a
+            lattice started from the populations f0; the backward pass is the
+            lattice's discrete adjoint (lbm_adjoint_step) from f0."""
+
+            @staticmethod
+            def forward(ctx, f0, lat, n_steps, w, lam, checkpoint_every):
+                lat.set_populations(f0)
+                J = torch.zeros((), dtype=torch.float64, device=lat.device)
+                for _ in range(n_steps):
+                    lat.step(1)
+                    if w is not None:
+                        J += (w * lat.populations()).sum()
+                if lam is not None:
+                    J += (lam * lat.populations()).sum()
+                ctx.save_for_backward(f0)
+                ctx.lat, ctx.n, ctx.w, ctx.lam, ctx.k = lat, n_steps, w, lam, checkpoint_every
+                return J
+
+            @staticmethod
+            def backward(ctx, gJ):
+                (f0,) = ctx.saved_tensors
+                lat = ctx.lat
+                end = lat.populations()
+                lat.set_populations(f0)
+                lam = torch.zeros(19, lat.N, dtype=torch.float64, device=lat.device)
+                if ctx.lam is not None:
+                    lam = gJ * ctx.lam
+                w = None if ctx.w is None else gJ * ctx.w
+                g0, _ = lat.adjoint(ctx.n, lam, w, checkpoint_every=ctx.k)
+                lat.set_populations(end)  # the lattice is left at the trajectory's end
+                return g0.reshape(f0.shape), None, None, None, None, None
+
+        _TRAJECTORY = Trajectory
+    return _TRAJECTORY
+
+
+def trajectory(lat, f0, n_steps, w=None, lam=None, checkpoint_every=100):
+    """Differentiable J(f0) = <lam, f^n> + sum_{t=1..n} <w, f^t> ([19][N]
+    weights, FP64, on the lattice's device) over n_steps steps of lat from
+    the populations f0; J.backward() gives dJ/df0 through the discrete
+    adjoint.  Fluid-only FP64 or FP32 lattices (lbm_adjoint_step's scope).
+    The lattice is left at the trajectory's end."""
+    return _trajectory_class().apply(f0, lat, int(n_steps), w, lam, int(checkpoint_every))

@@ -1552,6 +1552,13 @@ extern "C" lbm_status lbm_get_populations(lbm_ctx* ctx, double* d_f) {
   if (!d_f) return LBM_E_INVAL;
   return fields_common(ctx, nullptr, nullptr, d_f, nullptr);
 }
+extern "C" lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f) {
+  if (!ctx) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (!d_f) return fail(ctx, LBM_E_INVAL, "set_populations: null input");
+  CHK(launch_set_populations(ctx->prec, ctx->g, ctx->f[0], ctx->f[1], ctx->ncls, ctx->flags, d_f, ctx->stream));
+  return LBM_OK;
+}
 extern "C" lbm_status lbm_get_force(lbm_ctx* ctx, double* d_fib) {
   if (!d_fib) return LBM_E_INVAL;
   return fields_common(ctx, nullptr, nullptr, nullptr, d_fib);

@@ -211,6 +211,8 @@ hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const doubl
 hipError_t launch_adjoint_grad(const double* part, int nblk, double* grad, hipStream_t s);
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
+hipError_t launch_set_populations(int prec, const Grid& g, void* f0, void* f1, const uint8_t* ncls,
+                                  const DevFlags* flags, const double* pops, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,
                              const uint8_t* ncls, const long long* fx0, const long long* fx1,
                              const uint8_t* tf0, const uint8_t* tf1, double gx, double gy,

@@ -2873,6 +2873,35 @@ hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, D
   return hipGetLastError();
 }
 
+// The inverse of the populations output: the current state (the buffer of
+// the completed step count's parity) takes f - w_i at every non-solid node,
+// rounded to the storage type; solid nodes keep zero.
+template <class S>
+__global__ void k_set_pops(Grid G, S* f0, S* f1, const uint8_t* ncls, const DevFlags* flags, const double* pops) {
+  const long long N = (long long)G.nx * G.ny * G.nz;
+  const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  S* f = (flags->steps_done & 1) ? f1 : f0;
+  const int x = (int)(n % G.nx);
+  const long long t = n / G.nx;
+  const long long p = x + (long long)G.px * t;
+  if (ncls[p] == CLS_SOLID) return;
+  for (int i = 0; i < 19; i++) f[(long long)i * G.plane + p] = (S)(pops[(long long)i * N + n] - WD[i]);
+}
+
+hipError_t launch_set_populations(int prec, const Grid& g, void* f0, void* f1, const uint8_t* ncls,
+                                  const DevFlags* flags, const double* pops, hipStream_t s) {
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  switch (prec) {
+    case 0: k_set_pops<double><<<cdiv(N, 256), 256, 0, s>>>(g, (double*)f0, (double*)f1, ncls, flags, pops); break;
+    case 1: k_set_pops<float><<<cdiv(N, 256), 256, 0, s>>>(g, (float*)f0, (float*)f1, ncls, flags, pops); break;
+    default:
+      k_set_pops<_Float16><<<cdiv(N, 256), 256, 0, s>>>(g, (_Float16*)f0, (_Float16*)f1, ncls, flags, pops);
+      break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,
                              const uint8_t* ncls, const long long* fx0, const long long* fx1,
                              const uint8_t* tf0, const uint8_t* tf1, double gx, double gy,

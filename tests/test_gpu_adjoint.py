@@ -298,3 +298,51 @@ def test_differentiation_form_full_size(lib, precision):
     # the geometry is symmetric in y: the split does not move with s
     ok &= _check("dS/ds", g_split[0], fd("s", "split"), abs(g_split[2]) * 1e-3, rel)
     assert ok
+
+
+def test_set_populations_round_trip(lib):
+    """A lattice started elsewhere and given another's populations steps on
+    as that one does (FP64: to the rounding of f = g + w_i and back)."""
+    w = synth.tiny_bifurcation(precision="f64", n_bodies=0)
+    a = lib.from_workload(w)
+    a.step(9)
+    a.sync()
+    d0 = synth.tiny_bifurcation(precision="f64", n_bodies=0).domain  # from rest
+    b = lib.Lattice(d0, w.tau, w.u_max, "f64")
+    b.set_populations(a.populations())
+    assert float((b.populations() - a.populations()).abs().max()) <= 1e-16
+    a.step(15)
+    b.step(15)
+    fa, fb = a.populations(), b.populations()
+    e = float((fb - fa).abs().max() / (fa - fa.mean()).abs().max())
+    _say(f"[set_populations] 15 steps after the hand-over: {e:.1e}")
+    assert e <= 1e-13
+
+
+def test_trajectory_autograd(lib):
+    """J(f0) through torch.autograd: backward equals the adjoint's dJ/dg^0,
+    and a central difference of J along a seeded direction (J evaluated by
+    the same function's forward) matches <dJ/df0, d>."""
+    import torch
+    w, c, wv, _, _ = _case("pipe")
+    lat = lib.from_workload(w)
+    lat.step(3)
+    base = lat.populations()
+    fl = torch.from_numpy(w.domain.node_type != synth.SOLID).to(base.device)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    dirn = (1e-4 * torch.randn(19, lat.N, generator=gen, dtype=torch.float64)).to(base.device) * fl
+    cc, ww = torch.from_numpy(c).to(base.device), torch.from_numpy(wv).to(base.device)
+    f0 = base.clone().requires_grad_(True)
+    J = lib.trajectory(lat, f0, 20, ww, cc, checkpoint_every=6)
+    J.backward()
+    lat.set_populations(base)
+    lam0, _ = lat.adjoint(20, cc, ww, checkpoint_every=6)
+    assert torch.allclose(f0.grad, lam0, rtol=0, atol=1e-13 * float(lam0.abs().max()))
+    with torch.no_grad():
+        eps = 1e-2
+        Jp = lib.trajectory(lat, base + eps * dirn, 20, ww, cc)
+        Jm = lib.trajectory(lat, base - eps * dirn, 20, ww, cc)
+    fd = float((Jp - Jm) / (2 * eps))
+    ad = float((f0.grad * dirn).sum())
+    _say(f"[trajectory] directional derivative: autograd {ad:+.12e}  central difference {fd:+.12e}")
+    assert abs(ad - fd) <= 1e-7 * abs(fd)
