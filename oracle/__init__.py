@@ -91,6 +91,7 @@ def lib():
         getattr(L, name).argtypes = [vp, _P(d), _P(d)]
     L.orc_get_populations.argtypes = [vp, _P(d)]
     L.orc_get_populations_at.argtypes = [vp, i64, _P(i64), _P(d)]
+    L.orc_set_populations.argtypes = [vp, _P(d)]
     L.orc_get_force.argtypes = [vp, _P(d)]
     L.orc_get_body.argtypes = [vp, C.c_int, _P(d), _P(d)]
     L.orc_body_diag.argtypes = [vp, C.c_int, _P(d)]
@@ -230,6 +231,11 @@ class OracleSim:
         f = np.zeros(19 * self.N)
         lib().orc_get_populations(self._h, _ptr(f, C.c_double))
         return f.reshape(19, self.N)
+
+    def set_populations(self, f):
+        """The stored populations become f ([19][N]; solid entries ignored)."""
+        f = _f64(np.asarray(f, np.float64).reshape(19 * self.N))
+        lib().orc_set_populations(self._h, _ptr(f, C.c_double))
 
     def populations_at(self, nodes):
         """f_i at the listed node indices only, [19][len(nodes)]."""

@@ -1303,6 +1303,14 @@ void orc_get_populations(const orc_sim *s, double *f) {
       f[(long)i * s->N + n] = s->type[n] == T_SOLID ? 0.0 : Wt[i] + s->fs[19 * n + i];
 }
 
+/* The inverse of orc_get_populations: the stored post-collision
+ * populations become f ([19][N]); entries at solid nodes are ignored. */
+void orc_set_populations(orc_sim *s, const double *f) {
+  for (long n = 0; n < s->N; n++)
+    if (s->type[n] != T_SOLID)
+      for (int i = 0; i < 19; i++) s->fs[19 * n + i] = f[(long)i * s->N + n] - Wt[i];
+}
+
 /* The populations f_i of the listed nodes only: f[i * n + k] for node
  * nodes[k] (the same values as orc_get_populations). */
 void orc_get_populations_at(const orc_sim *s, long n, const long *nodes, double *f) {

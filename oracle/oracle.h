@@ -56,6 +56,7 @@ int orc_mls_singular_count(const orc_sim *s);
  * [19][N] post-collision; force field [3][N] of the last step. */
 void orc_get_fields(const orc_sim *s, double *rho, double *u);
 void orc_get_populations(const orc_sim *s, double *f);
+void orc_set_populations(orc_sim *s, const double *f);
 void orc_get_populations_at(const orc_sim *s, long n, const long *nodes, double *f);
 void orc_get_force(const orc_sim *s, double *fib);
 void orc_get_body(const orc_sim *s, int id, double *x, double *v);

@@ -346,3 +346,54 @@ def test_trajectory_autograd(lib):
     ad = float((f0.grad * dirn).sum())
     _say(f"[trajectory] directional derivative: autograd {ad:+.12e}  central difference {fd:+.12e}")
     assert abs(ad - fd) <= 1e-7 * abs(fd)
+
+
+@pytest.mark.parametrize("name", ["pipe", "bifurcation"])
+def test_adjoint_state_gradient_elementwise(lib, name):
+    """dJ/dg^0 entry by entry at sampled populations -- of wall-link nodes
+    (read by the bounce-back rule), of their neighbours, of inlet and outlet
+    nodes (Zou-He), of bulk nodes -- against central differences of the
+    oracle with that one population of the initial state perturbed."""
+    import torch
+    w, c, wv, _, _ = _case(name)
+    d = w.domain
+    n = 10
+    lat = lib.from_workload(w)
+    lam, _ = lat.adjoint(n, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=4)
+    lam = lam.cpu().numpy()
+    f0 = oracle.from_workload(w).populations()
+    rng = np.random.default_rng(5)
+    fl = np.flatnonzero(d.node_type != synth.SOLID)
+    links = np.unique(d.link_node)
+    nbrs = np.unique(np.clip(links + rng.choice([-1, 1, -d.nx, d.nx], len(links)), 0, d.n_nodes - 1))
+    nbrs = nbrs[d.node_type[nbrs] != synth.SOLID]
+    groups = {"link": links, "link neighbour": nbrs, "inlet": np.flatnonzero(d.node_type == synth.INLET),
+              "outlet": np.flatnonzero(d.node_type == synth.OUTLET), "fluid": fl}
+    samples = []
+    for g, nodes in groups.items():
+        for node in rng.choice(nodes, 5, replace=False):
+            samples.append((g, int(rng.integers(19)), int(node)))
+
+    def J(f):
+        sim = oracle.OracleSim(d, w.tau, w.u_max, threads=2)
+        sim.set_populations(f)
+        tot = 0.0
+        for _ in range(n):
+            assert sim.step(1) == 0
+            tot += float(np.sum(wv * sim.populations()))
+        return tot + float(np.sum(c * sim.populations()))
+
+    scale = np.abs(lam).max()
+    bad = []
+    for g, j, node in samples:
+        fds = []
+        for h in (1e-6, 5e-7):
+            fp, fm = f0.copy(), f0.copy()
+            fp[j, node] += h
+            fm[j, node] -= h
+            fds.append((J(fp) - J(fm)) / (2 * h))
+        tol = 1e-8 * scale + 4 * abs(fds[0] - fds[1])
+        _say(f"  {g:15s} node {node:6d} dir {j:2d}: adjoint {lam[j, node]:+.10e}  oracle FD {fds[1]:+.10e}")
+        if abs(lam[j, node] - fds[1]) > tol:
+            bad.append((g, j, node, lam[j, node], fds[1], tol))
+    assert not bad, bad

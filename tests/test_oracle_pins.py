@@ -585,3 +585,17 @@ def test_membrane_balance_on_random_shapes(seed, amp, which):
     scale = max(np.abs(F).max(), 1e-300)
     assert np.abs(F.sum(0)).max() < 1e-12 * scale * len(x)
     assert np.abs(np.cross(x, F).sum(0)).max() < 1e-11 * scale * len(x)
+
+
+def test_set_populations_is_the_inverse_of_get():
+    """Handing one simulation's populations to another makes it step on as
+    the first does (the state is the post-collision populations alone)."""
+    w = synth.tiny_pipe(with_body=False)
+    a = oracle.from_workload(w, threads=1)
+    a.step(4)
+    b = oracle.OracleSim(synth.pipe(24, 12, 12, 4.5, u_max=0.05, tau=0.8, init="rest"), 0.8, 0.05, threads=1)
+    b.set_populations(a.populations())
+    assert np.abs(b.populations() - a.populations()).max() <= 1e-16
+    a.step(5)
+    b.step(5)
+    assert np.abs(b.populations() - a.populations()).max() <= 1e-15
