@@ -988,8 +988,7 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
   if (ib) {
     const BodyArgs& b = ctx->bargs[p];
     if ((e = launch_mls_post(ctx->prec, a, b, s)) != hipSuccess) return e;
-    if ((e = launch_body_post(b, ctx->flags, s)) != hipSuccess) return e;
-    if ((e = launch_close(ctx->flags, s)) != hipSuccess) return e;
+    if ((e = launch_body_post(b, ctx->flags, counter(ctx, 1), s)) != hipSuccess) return e;  // closes the step
   } else {
     if ((e = launch_close(ctx->flags, s)) != hipSuccess) return e;
   }
