@@ -988,7 +988,10 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
   if (ib) {
     const BodyArgs& b = ctx->bargs[p];
     if ((e = launch_mls_post(ctx->prec, a, b, s)) != hipSuccess) return e;
-    if ((e = launch_body_post(b, ctx->flags, counter(ctx, 1), s)) != hipSuccess) return e;  // closes the step
+    // a few tens of blocks close the step in their last one; more: k_close
+    const bool fold = body_post_blocks(b) <= 128;
+    if ((e = launch_body_post(b, ctx->flags, fold ? counter(ctx, 1) : nullptr, s)) != hipSuccess) return e;
+    if (!fold && (e = launch_close(ctx->flags, s)) != hipSuccess) return e;
   } else {
     if ((e = launch_close(ctx->flags, s)) != hipSuccess) return e;
   }

@@ -162,9 +162,11 @@ hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long
                            uint8_t* tf_cur, long long* fx_prev, uint8_t* tf_prev,
                            unsigned int* counter, hipStream_t s);
 hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s);
-// closes the step (steps_done, stop from pending) in its last block; counter
-// is a zeroed block counter that it leaves zeroed
+// with a counter (zeroed; left zeroed) it closes the step (steps_done, stop
+// from pending) in its last block; with null, launch_close must follow
 hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter, hipStream_t s);
+// blocks of launch_body_post (the host's choice of closing in it)
+inline unsigned body_post_blocks(const BodyArgs& b) { return (unsigned)b.nbody + (unsigned)((b.nsoft_v + 63) / 64); }
 // Mass and momentum sums of the last completed step into out[5] (non-solid
 // node count, sum of deviations, momentum); part holds 5 x 1024 doubles.
 hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void* f1, const uint8_t* ncls,

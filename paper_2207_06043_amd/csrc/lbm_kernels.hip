@@ -1895,9 +1895,12 @@ __device__ void soft_vertex(const BodyArgs& b, int idx) {
 }
 
 // Last IB launch of a coupled step: rigid blocks, then soft-vertex blocks
-// (one vertex per thread, 64-thread blocks).  The last block to finish
-// closes the step (what k_close does for a fluid-only step), so that a
-// coupled step is four launches.
+// (one vertex per thread, 64-thread blocks).  With a counter, the last block
+// to finish closes the step (what k_close does), so that a coupled step is
+// four launches: worth it for a few tens of blocks (one capsule: 42 blocks,
+// 4 us saved per step); with hundreds, each block's wait for its stores
+// before it is counted costs more than the k_close launch (16 capsules:
+// +5.8 us against 4.6 us), and k_close follows instead.
 __device__ __forceinline__ void body_post_block(const BodyArgs& b, int blk) {
   if (blk < b.nbody) {
     if (b.b_rigid[blk]) rigid_block(b, blk);
@@ -1910,7 +1913,7 @@ __device__ __forceinline__ void body_post_block(const BodyArgs& b, int blk) {
 __global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags, unsigned int* counter) {
   if (flags->stop) return;  // read before any block closes: every block returns here, or none
   body_post_block(b, blockIdx.x);
-  if (last_block(counter, gridDim.x) && threadIdx.x == 0) {
+  if (counter && last_block(counter, gridDim.x) && threadIdx.x == 0) {
     const unsigned int pend =
         __hip_atomic_load(&flags->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     flags->steps_done += 1;
@@ -2276,8 +2279,7 @@ hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipS
 
 hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter, hipStream_t s) {
   // small blocks: the vertex gathers are spread over many CUs' load pipelines
-  const unsigned grid = (unsigned)b.nbody + cdiv(b.nsoft_v, 64);
-  k_body_post<<<grid, 64, 0, s>>>(b, flags, counter);
+  k_body_post<<<body_post_blocks(b), 64, 0, s>>>(b, flags, counter);
   return hipGetLastError();
 }
 
