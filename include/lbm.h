@@ -202,11 +202,11 @@ lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double 
  * doubles, device) dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz: s scales the wall velocity
  * of every velocity-face (inlet) node, F is the uniform body force, both
  * held fixed over the n steps, derivatives at the context's own values
- * (s = 1).  The trajectory is recomputed in the context's precision (FP64
- * or FP32 storage and arithmetic, as lbm_step runs it); the adjoint is FP64:
+ * (s = 1).  The trajectory is recomputed in the context's precision (its
+ * storage and arithmetic, as lbm_step runs it); the adjoint is FP64:
  * the transposes of the collision and of Zou-He written out at each node's
  * state, exact transposes of the streaming and bounce-back (for an FP32
- * context, the derivative of the step in exact arithmetic at the FP32
+ * or FP16S context, the derivative of the step in exact arithmetic at its
  * states).  Entries of w and lambda at solid nodes are ignored; dJ/dg^0 is
  * zero there.
  * Checkpoints: the state is kept every checkpoint_every steps and each
@@ -214,7 +214,7 @@ lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double 
  * fields and ceil(n/K) + max(K, 2) states of 19 x plane values, plus K x 19
  * doubles per boundary record, allocated and freed by the call; LBM_E_NOMEM
  * if it does not fit).  The context's state and step count are not changed.
- * FP64 and FP32 contexts without bodies only (else LBM_E_UNSUPPORTED).
+ * Contexts without bodies only (else LBM_E_UNSUPPORTED).
  * Synchronises the context's stream. */
 lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t n_steps, int32_t checkpoint_every,
                             const double *d_w, double *d_lambda, double *d_grad);

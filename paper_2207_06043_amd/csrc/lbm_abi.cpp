@@ -1637,8 +1637,6 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   if (ctx->broken) return LBM_E_STATE;
   if (n_steps < 0 || every < 1 || !d_lambda || !d_grad)
     return fail(ctx, LBM_E_INVAL, "adjoint: n_steps >= 0, checkpoint interval >= 1, lambda and grad required");
-  if (ctx->prec != LBM_F64 && ctx->prec != LBM_F32)
-    return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: FP64 and FP32 contexts only");
   if (!ctx->bodies.empty()) return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: contexts without bodies only");
   DevFlags h;
   lbm_status st = read_flags(ctx, &h);

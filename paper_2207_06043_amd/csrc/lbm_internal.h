@@ -172,8 +172,8 @@ inline unsigned body_post_blocks(const BodyArgs& b) { return (unsigned)b.nbody +
 hipError_t launch_diag_sums(int prec, const Grid& g, const void* f0, const void* f1, const uint8_t* ncls,
                             const DevFlags* flags, double* part, double* out, hipStream_t s);
 // Adjoint of the fluid step (no bodies; FluidArgs with A = the state g^k in
-// [19][plane] in the context's storage, prec 0 FP64 or 1 FP32, bulk_list /
-// nbulk_nodes set); the adjoint quantities are FP64 in both.  Solid entries
+// [19][plane] in the context's storage, prec 0 FP64, 1 FP32 or 2 FP16S,
+// bulk_list / nbulk_nodes set); the adjoint quantities are FP64 in all.  Solid entries
 // of every buffer of the sweep hold zero and are never written.  merged:
 // records and bulk nodes in one launch (small grids), else two.
 // Buffers of one reverse step (from state k+1 back to state k).

@@ -2832,7 +2832,8 @@ static void adj_forward(const FluidArgs& a, double* hrec, int merged, hipStream_
 
 hipError_t launch_adjoint_forward(int prec, const FluidArgs& a, double* hrec, int merged, hipStream_t s) {
   if (prec == 0) adj_forward<double>(a, hrec, merged, s);
-  else adj_forward<float>(a, hrec, merged, s);
+  else if (prec == 1) adj_forward<float>(a, hrec, merged, s);
+  else adj_forward<_Float16>(a, hrec, merged, s);
   return hipGetLastError();
 }
 
@@ -2855,7 +2856,8 @@ static void adj_reverse(const FluidArgs& a, const AdjStep& st, int merged, hipSt
 
 hipError_t launch_adjoint_reverse(int prec, const FluidArgs& a, const AdjStep& st, int merged, hipStream_t s) {
   if (prec == 0) adj_reverse<double>(a, st, merged, s);
-  else adj_reverse<float>(a, st, merged, s);
+  else if (prec == 1) adj_reverse<float>(a, st, merged, s);
+  else adj_reverse<_Float16>(a, st, merged, s);
   return hipGetLastError();
 }
 

@@ -197,31 +197,35 @@ def test_adjoint_checkpoint_interval_and_state(lib):
     assert torch.equal(lam.cpu(), torch.from_numpy(c)) and torch.all(g == 0)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f16s"])
 @pytest.mark.parametrize("name", ["pipe", "bifurcation"])
-def test_adjoint_fp32_forward_matches_oracle_differences(lib, name):
-    """FP32 forward (states and tape in FP32, the step of an FP32 lattice),
-    FP64 adjoint: the gradient moves from the FP64 one by what FP32 does to
-    the trajectory; held to the FP32 bar 2e-5 (relative) against the oracle's
-    differences and against the FP64 adjoint."""
+def test_adjoint_reduced_precision_forward_matches_oracle_differences(lib, name, precision):
+    """FP32 or FP16S forward (states and tape in the lattice's storage, its
+    step), FP64 adjoint: the gradient moves from the FP64 one by what the
+    storage does to the trajectory; held to the FP32 bar 2e-5 (FP32) and to
+    2e-3 (FP16S: ten times what binary16 storage moves these small cases,
+    2.4-3.5e-4) relative, against the oracle's differences and against the
+    FP64 adjoint."""
     import torch
+    bar = {"f32": 2e-5, "f16s": 2e-3}[precision]
     w, c, wv, du, dr = _case(name)
     d = w.domain
     n, K = 30, 7
     lam64, g64 = lib.from_workload(w).adjoint(n, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=K)
-    lat = lib.from_workload(w, precision="f32")
+    lat = lib.from_workload(w, precision=precision)
     lam, grad = lat.adjoint(n, torch.from_numpy(c), torch.from_numpy(wv), checkpoint_every=K)
     lam, grad, lam64, g64 = (t.cpu().numpy() for t in (lam, grad, lam64, g64))
     e_l = np.abs(lam - lam64).max() / np.abs(lam64).max()
-    _say(f"[adjoint] {name} FP32 forward: lambda vs FP64 adjoint {e_l:.1e}")
-    assert e_l <= 2e-5
+    _say(f"[adjoint] {name} {precision} forward: lambda vs FP64 adjoint {e_l:.1e}")
+    assert e_l <= bar
     fscale = np.abs(grad[1:]).max()
     fd_s = _fd(d, w, n, c, wv, "s", (1e-4, 5e-5))
-    assert abs(grad[0] - fd_s[-1]) <= 2e-5 * abs(fd_s[-1]) + 4 * abs(fd_s[0] - fd_s[-1]), (grad[0], fd_s)
-    _say(f"  dJ/ds: FP32 forward {grad[0]:+.10e}  oracle FD {fd_s[-1]:+.10e}  FP64 adjoint {g64[0]:+.10e}")
+    _say(f"  dJ/ds: {precision} forward {grad[0]:+.10e}  oracle FD {fd_s[-1]:+.10e}  FP64 adjoint {g64[0]:+.10e}")
+    assert abs(grad[0] - fd_s[-1]) <= bar * abs(fd_s[-1]) + 4 * abs(fd_s[0] - fd_s[-1]), (grad[0], fd_s)
     for k, comp in enumerate(("Fx", "Fy", "Fz")):
         fd = _fd(d, w, n, c, wv, comp, (1e-6, 5e-7))
-        _say(f"  dJ/d{comp}: FP32 forward {grad[1 + k]:+.10e}  oracle FD {fd[-1]:+.10e}")
-        assert abs(grad[1 + k] - fd[-1]) <= 2e-5 * fscale + 4 * abs(fd[0] - fd[-1])
+        _say(f"  dJ/d{comp}: {precision} forward {grad[1 + k]:+.10e}  oracle FD {fd[-1]:+.10e}")
+        assert abs(grad[1 + k] - fd[-1]) <= bar * fscale + 4 * abs(fd[0] - fd[-1])
 
 
 def test_adjoint_split_and_merged_launches_agree(lib, monkeypatch):
@@ -243,10 +247,6 @@ def test_adjoint_split_and_merged_launches_agree(lib, monkeypatch):
 def test_adjoint_rejects_unsupported_contexts(lib):
     import torch
     lam = torch.zeros(19, 8 * 8 * 8, dtype=torch.float64)
-    lat = lib.Lattice(synth.periodic_box(8, 8, 8), 0.8, precision="f16s")
-    with pytest.raises(lib.LbmError) as e:
-        lat.adjoint(1, lam)
-    assert e.value.status == 7
     wb = synth.tiny_pipe(precision="f64", rigid=True)
     lb = lib.from_workload(wb)
     with pytest.raises(lib.LbmError) as e:
@@ -258,14 +258,15 @@ def test_adjoint_rejects_unsupported_contexts(lib):
     assert e.value.status == 1
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
 def test_differentiation_form_full_size(lib, precision):
     """2000 steps of the 256x128x40 bifurcation from rest, checkpoints every
     100: gradients of the time-integrated upper-daughter flux and of the
     flux split against the oracle's central differences; FP64 forward to
-    1e-8, FP32 forward (FP64 adjoint) to the FP32 bar 2e-5."""
+    1e-8, FP32 forward (FP64 adjoint) to the FP32 bar 2e-5, FP16S forward to
+    2e-3."""
     import torch
-    rel = {"f64": REL, "f32": 2e-5}[precision]
+    rel = {"f64": REL, "f32": 2e-5, "f16s": 2e-3}[precision]
     g = np.load(os.path.join(HERE, "golden", "adjoint_fd.npz"))
     w = fdcase.workload()
     w.bodies = []
