@@ -413,7 +413,8 @@ def run_adjoint(args):
             "box_nodes": n_box,
             "bodies": 0,
             "checkpoint_every": K,
-            "objective": "time-integrated upper-daughter flux; gradient w.r.t. inlet-velocity scale and body force",
+            "objective": ("time-integrated upper-daughter flux; gradient w.r.t. inlet-velocity scale, "
+                          "body force and relaxation time"),
             "lups_counted_on": "fluid nodes x adjoint steps (forward pass, recompute and reverse step included)",
             "plain_mlups": round(plain, 2),
             "adjoint_vs_plain": round(value / plain, 4),

@@ -198,11 +198,11 @@ lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double 
  * context's current state g^0 and the objective
  *   J = <lambda, g^n> + sum_{t=1..n} <w, g^t>
  * (lambda, w: [19][N] FP64 device arrays, N = nx ny nz, x fastest; w may be
- * NULL), it returns in d_lambda (overwritten) dJ/dg^0 and in d_grad (4
- * doubles, device) dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz: s scales the wall velocity
- * of every velocity-face (inlet) node, F is the uniform body force, both
- * held fixed over the n steps, derivatives at the context's own values
- * (s = 1).  The trajectory is recomputed in the context's precision (its
+ * NULL), it returns in d_lambda (overwritten) dJ/dg^0 and in d_grad (5
+ * doubles, device) dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz, dJ/dtau: s scales the wall
+ * velocity of every velocity-face (inlet) node, F is the uniform body force,
+ * tau the relaxation time (Eq. evoleq; the viscosity), all held fixed over
+ * the n steps, derivatives at the context's own values (s = 1).  The trajectory is recomputed in the context's precision (its
  * storage and arithmetic, as lbm_step runs it); the adjoint is FP64:
  * the transposes of the collision and of Zou-He written out at each node's
  * state, exact transposes of the streaming and bounce-back (for an FP32

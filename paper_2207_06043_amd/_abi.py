@@ -341,12 +341,13 @@ class Lattice:
         """Gradient of J = <lam, g^n> + sum_{t=1..n} <w, g^t> over the
         n_steps-step trajectory from the current state (g: the populations'
         deviations f - w_i, [19][N]); returns (dJ/dg^0 [19][N],
-        [dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz]) with s the inlet-velocity scale and
-        F the body force.  The lattice's state is not changed."""
+        [dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz, dJ/dtau]) with s the inlet-velocity
+        scale, F the body force and tau the relaxation time.  The lattice's
+        state is not changed."""
         t = self._torch
         lam = lam.to(self.device, t.float64).reshape(19, self.N).clone()
         wd = None if w is None else w.to(self.device, t.float64).reshape(19, self.N).contiguous()
-        grad = self._empty(4)
+        grad = self._empty(5)
         self._check(load_library().lbm_adjoint_step(self._h, int(n_steps), int(checkpoint_every),
                                                     _ptr(wd), _ptr(lam), _ptr(grad)))
         self.stream.synchronize()

@@ -1655,7 +1655,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   const size_t big_bytes = 6 * dbytes + (size_t)(nseg + ntape) * xbytes;
   const size_t hbytes = 19 * (size_t)ctx->nrec * sizeof(double);  // one step's record populations
   const int npart = adj_part_blocks(ctx->nrec, ctx->n_bulk);
-  const size_t pbytes = 4 * (size_t)npart * sizeof(double);
+  const size_t pbytes = ADJ_PART * (size_t)npart * sizeof(double);
   const size_t small = pbytes + 2 * ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + tlen * (hbytes + 256) +
                        3 * 256;
   // one launch for records and bulk nodes below 4M non-solid nodes (the
@@ -1755,7 +1755,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   // dJ/dg^0 = P^T mu of the last step back (plain pulls and bounce-back)
   if (n_steps > 0) CHK(launch_adjoint_gather(a, m.pmask, m.amask, m.mu[cur ^ 1], m.acc[cur ^ 1], m.lam, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, m.lam, d_lambda, 0, s));
-  CHK(launch_adjoint_grad(m.part, npart, d_grad, s));
+  CHK(launch_adjoint_grad(m.part, npart, 1.0 / ctx->tau, d_grad, s));
   CHK(hipStreamSynchronize(s));
   return LBM_OK;
 }

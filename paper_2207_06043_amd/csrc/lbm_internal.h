@@ -196,10 +196,12 @@ struct AdjStep {
 // is in place.
 // launch_adjoint_reverse: one step back, mu of step k from dJ/dg^{k+1}
 // (st.lam, or P^T st.mu_next with st.acc_in) + st.w; the links' transposes
-// of mu into st.acc_out; part[adj_part_blocks][4] += the step's derivatives
-// of the inlet-velocity scale and the body force, per block in a fixed order.
+// of mu into st.acc_out; part[adj_part_blocks][ADJ_PART] += the step's
+// derivatives of the inlet-velocity scale, the body force and omega, per
+// block in a fixed order.
 // launch_adjoint_gather: lam = P^T mu (with acc) after the last step back.
 constexpr int ADJ_BLOCKS = 1024;
+constexpr int ADJ_PART = 8;  // doubles per block of gradient partials (5 used)
 inline int adj_part_blocks(long long nrec, long long nbulk) {
   const long long merged = (nrec + 255) / 256 + (nbulk + 255) / 256;
   return (int)(merged > 2 * ADJ_BLOCKS ? merged : 2 * ADJ_BLOCKS);
@@ -212,7 +214,7 @@ hipError_t launch_adjoint_gather(const FluidArgs& a, const uint32_t* pmask, cons
                                  const double* acc, double* lam, hipStream_t s);
 hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,
                                  hipStream_t s);
-hipError_t launch_adjoint_grad(const double* part, int nblk, double* grad, hipStream_t s);
+hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, double* grad, hipStream_t s);
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
 hipError_t launch_set_populations(int prec, const Grid& g, void* f0, void* f1, const uint8_t* ncls,

@@ -2486,8 +2486,9 @@ __global__ __launch_bounds__(256) void k_adj_fwd_all(FluidArgs a, double* hrec, 
 // (3 + 9 e.u) e_a and (e.F) e_a (SL, P', V_a, Z_a):
 //   P = omega P',  U_a = omega rho V_a + 9 kf Z_a - 3 (omega rho u_a + kf F_a) SL,
 //   Q_a = kf (V_a - 3 u_a SL),  kf = 1 - omega/2.
+// dF[3] += dJ/d(omega) at fixed h: sum_i l_i (g^eq_i - h_i - G_i / (2 kf)).
 __device__ __forceinline__ void collide_vjp(const double (&h)[19], const double (&l)[19], double Fx, double Fy,
-                                            double Fz, double omega, double (&mu)[19], double (&dF)[3]) {
+                                            double Fz, double omega, double (&mu)[19], double (&dF)[4]) {
   const double drho = dev_sum(h);
   const double mx = (h[1] - h[2]) + (h[7] + h[8]) + (h[9] + h[10]) - (h[11] + h[12]) - (h[13] + h[14]);
   const double my = (h[3] - h[4]) + (h[7] - h[8]) + (h[11] - h[12]) + (h[15] + h[16]) - (h[17] + h[18]);
@@ -2496,7 +2497,8 @@ __device__ __forceinline__ void collide_vjp(const double (&h)[19], const double 
   const double ux = (mx + 0.5 * Fx) * ir, uy = (my + 0.5 * Fy) * ir, uz = (mz + 0.5 * Fz) * ir;
   const double usq = ux * ux + uy * uy + uz * uz;
   const double kf = 1.0 - 0.5 * omega;
-  double SL = 0.0, Pp = 0.0, V0 = 0.0, V1 = 0.0, V2 = 0.0, Z0 = 0.0, Z1 = 0.0, Z2 = 0.0;
+  const double uF = ux * Fx + uy * Fy + uz * Fz;
+  double SL = 0.0, Pp = 0.0, V0 = 0.0, V1 = 0.0, V2 = 0.0, Z0 = 0.0, Z1 = 0.0, Z2 = 0.0, Dw = 0.0;
 #pragma unroll
   for (int i = 0; i < 19; i++) {
     const double eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
@@ -2504,6 +2506,9 @@ __device__ __forceinline__ void collide_vjp(const double (&h)[19], const double 
     const double wl = WD[i] * l[i];
     SL += wl;
     Pp += wl * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+    // d(out_i)/d(omega) = -(h_i - g^eq_i) - 1/2 w_i (3 (e.F - u.F) + 9 (e.u)(e.F))
+    Dw += wl * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq) - 0.5 * (3.0 * (eF - uF) + 9.0 * eu * eF)) -
+          l[i] * h[i];
     const double v = wl * (3.0 + 9.0 * eu), zz = wl * eF;
     if (EX[i]) { V0 += EX[i] * v; Z0 += EX[i] * zz; }
     if (EY[i]) { V1 += EY[i] * v; Z1 += EY[i] * zz; }
@@ -2520,6 +2525,7 @@ __device__ __forceinline__ void collide_vjp(const double (&h)[19], const double 
   dF[0] += kf * (V0 - 3.0 * ux * SL) + 0.5 * a0;
   dF[1] += kf * (V1 - 3.0 * uy * SL) + 0.5 * a1;
   dF[2] += kf * (V2 - 3.0 * uz * SL) + 0.5 * a2;
+  dF[3] += Dw;
 }
 
 // Zou-He's transpose (the rule of zouhe(), affine in the known populations
@@ -2627,7 +2633,7 @@ __device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long lo
 // back through Zou-He and the links' transposes go to acc_out).  dF, gs += the node's derivatives of the body force and
 // of the inlet-velocity scale.
 template <bool REC, class S>
-__device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjStep& st, int t, double (&dF)[3],
+__device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjStep& st, int t, double (&dF)[4],
                                                 double& gs) {
   const Grid& G = a.g;
   double h[19], l[19], m[19];
@@ -2682,19 +2688,22 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
   if (REC) adj_links_one<S>(a, t, n, m, st.acc_out);
 }
 
-// part[block][0..3] += the block's sums (fixed order: bitwise reproducible).
-__device__ __forceinline__ void adj_part_add(double* part, double gs, const double (&dF)[3]) {
+// part[block][0..4] += the block's sums of dJ/ds, dJ/dF, dJ/d(omega)
+// (fixed order: bitwise reproducible).
+__device__ __forceinline__ void adj_part_add(double* part, double gs, const double (&dF)[4]) {
   __shared__ double sh[8];
   const double t0 = block_sum(gs, sh);
   const double t1 = block_sum(dF[0], sh);
   const double t2 = block_sum(dF[1], sh);
   const double t3 = block_sum(dF[2], sh);
+  const double t4 = block_sum(dF[3], sh);
   if (threadIdx.x == 0) {
-    double* p = part + 4 * blockIdx.x;
+    double* p = part + ADJ_PART * blockIdx.x;
     p[0] += t0;
     p[1] += t1;
     p[2] += t2;
     p[3] += t3;
+    p[4] += t4;
   }
 }
 
@@ -2703,17 +2712,17 @@ __device__ __forceinline__ void adj_part_add(double* part, double gs, const doub
 // launch in the second half of part).
 template <bool REC, class S>
 __global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_reverse(FluidArgs a, AdjStep st) {
-  double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
+  double dF[4] = {0.0, 0.0, 0.0, 0.0}, gs = 0.0;
   const int count = REC ? a.nrec : a.nbulk_nodes;
   for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256)
     adj_reverse_one<REC, S>(a, st, t, dF, gs);
-  adj_part_add(st.part + (REC ? 4 * ADJ_BLOCKS : 0), gs, dF);
+  adj_part_add(st.part + (REC ? ADJ_PART * ADJ_BLOCKS : 0), gs, dF);
 }
 
 // Merged form: blocks below rec_blocks take records, the rest bulk nodes.
 template <class S>
 __global__ __launch_bounds__(256) void k_adj_reverse_all(FluidArgs a, AdjStep st, int rec_blocks) {
-  double dF[3] = {0.0, 0.0, 0.0}, gs = 0.0;
+  double dF[4] = {0.0, 0.0, 0.0, 0.0}, gs = 0.0;
   if ((int)blockIdx.x < rec_blocks) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t < a.nrec) adj_reverse_one<true, S>(a, st, t, dF, gs);
@@ -2811,12 +2820,14 @@ __global__ void k_adj_layout(Grid G, const uint8_t* ncls, const double* in, doub
   }
 }
 
-__global__ void k_adj_grad_final(const double* part, int nblk, double* grad) {
+// grad[0..4] = dJ/ds, dJ/dF, dJ/dtau = -omega^2 dJ/d(omega), summed over the
+// blocks in a fixed order.
+__global__ void k_adj_grad_final(const double* part, int nblk, double omega, double* grad) {
   const int q = threadIdx.x;
-  if (q >= 4) return;
+  if (q >= 5) return;
   double t = 0.0;
-  for (int b = 0; b < nblk; b++) t += part[4 * b + q];
-  grad[q] = t;
+  for (int b = 0; b < nblk; b++) t += part[ADJ_PART * b + q];
+  grad[q] = q == 4 ? -omega * omega * t : t;
 }
 
 template <class S>
@@ -2875,8 +2886,8 @@ hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_grad(const double* part, int nblk, double* grad, hipStream_t s) {
-  k_adj_grad_final<<<1, 64, 0, s>>>(part, nblk, grad);
+hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, double* grad, hipStream_t s) {
+  k_adj_grad_final<<<1, 64, 0, s>>>(part, nblk, omega, grad);
   return hipGetLastError();
 }
 

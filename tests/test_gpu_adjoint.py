@@ -7,7 +7,7 @@ objective
     J = <c, f^n> + sum_{t=1..n} <w, f^t>
 with c a seeded random field on the fluid nodes and w the outward flux
 weights of the outlet nodes.  Checked: dJ/ds (inlet-velocity scale),
-dJ/dF (body force) and the state gradient dJ/dg^0, the last through the
+dJ/dF (body force), dJ/dtau (relaxation time) and the state gradient dJ/dg^0, the last through the
 derivative along seeded perturbations of the initial density and
 velocity fields (the initial state is their equilibrium, Eq. eqfunc).
 
@@ -92,8 +92,8 @@ def _case(name):
     return w, c, wv, du, dr
 
 
-def _J(d, w, n, c, wv):
-    sim = oracle.OracleSim(d, w.tau, w.u_max, threads=4)
+def _J(d, w, n, c, wv, tau=None):
+    sim = oracle.OracleSim(d, w.tau if tau is None else tau, w.u_max, threads=4)
     J = 0.0
     for _ in range(n):
         assert sim.step(1) == 0
@@ -117,6 +117,8 @@ def _perturb(d, what, h, du=None, dr=None):
 
 
 def _fd(d, w, n, c, wv, what, hs, **kw):
+    if what == "tau":
+        return [(_J(d, w, n, c, wv, w.tau + h) - _J(d, w, n, c, wv, w.tau - h)) / (2 * h) for h in hs]
     return [(_J(_perturb(d, what, h, **kw), w, n, c, wv) - _J(_perturb(d, what, -h, **kw), w, n, c, wv)) / (2 * h)
             for h in hs]
 
@@ -160,9 +162,10 @@ def test_adjoint_matches_oracle_differences(lib, name):
         ok &= _check("dJ/ds", grad[0], _fd(d, w, n, c, wv, "s", (1e-4, 5e-5)), abs(grad[0]))
     else:
         assert grad[0] == 0.0  # no velocity face
-    fscale = np.abs(grad[1:]).max()
+    fscale = np.abs(grad[1:4]).max()
     for k, comp in enumerate(("Fx", "Fy", "Fz")):
         ok &= _check(f"dJ/d{comp}", grad[1 + k], _fd(d, w, n, c, wv, comp, (1e-6, 5e-7)), fscale)
+    ok &= _check("dJ/dtau", grad[4], _fd(d, w, n, c, wv, "tau", (1e-5, 5e-6)), abs(grad[4]))
     # the state gradient, along perturbations of the initial fields
     rho0 = d.init_rho
     u0 = d.init_u.reshape(3, -1)
@@ -218,7 +221,7 @@ def test_adjoint_reduced_precision_forward_matches_oracle_differences(lib, name,
     e_l = np.abs(lam - lam64).max() / np.abs(lam64).max()
     _say(f"[adjoint] {name} {precision} forward: lambda vs FP64 adjoint {e_l:.1e}")
     assert e_l <= bar
-    fscale = np.abs(grad[1:]).max()
+    fscale = np.abs(grad[1:4]).max()
     fd_s = _fd(d, w, n, c, wv, "s", (1e-4, 5e-5))
     _say(f"  dJ/ds: {precision} forward {grad[0]:+.10e}  oracle FD {fd_s[-1]:+.10e}  FP64 adjoint {g64[0]:+.10e}")
     assert abs(grad[0] - fd_s[-1]) <= bar * abs(fd_s[-1]) + 4 * abs(fd_s[0] - fd_s[-1]), (grad[0], fd_s)
@@ -226,6 +229,13 @@ def test_adjoint_reduced_precision_forward_matches_oracle_differences(lib, name,
         fd = _fd(d, w, n, c, wv, comp, (1e-6, 5e-7))
         _say(f"  dJ/d{comp}: {precision} forward {grad[1 + k]:+.10e}  oracle FD {fd[-1]:+.10e}")
         assert abs(grad[1 + k] - fd[-1]) <= bar * fscale + 4 * abs(fd[0] - fd[-1])
+    # dJ/dtau weights the non-equilibrium part h - g^eq of every population,
+    # small against the stored deviations: binary16 storage resolves it to
+    # about 1e-2 of itself (FP32 well within its bar)
+    bar_t = {"f32": 2e-5, "f16s": 1e-2}[precision]
+    fd_t = _fd(d, w, n, c, wv, "tau", (1e-5, 5e-6))
+    _say(f"  dJ/dtau: {precision} forward {grad[4]:+.10e}  oracle FD {fd_t[-1]:+.10e}")
+    assert abs(grad[4] - fd_t[-1]) <= bar_t * abs(fd_t[-1]) + 4 * abs(fd_t[0] - fd_t[-1])
 
 
 def test_adjoint_split_and_merged_launches_agree(lib, monkeypatch):
@@ -293,8 +303,8 @@ def test_differentiation_form_full_size(lib, precision):
 
     ok = True
     ok &= _check("dJ_up/ds", g_up[0], fd("s", "up"), abs(g_up[0]), rel)
-    ok &= _check("dJ_up/dFx", g_up[1], fd("Fx", "up"), np.abs(g_up[1:]).max(), rel)
-    ok &= _check("dJ_up/dFy", g_up[2], fd("Fy", "up"), np.abs(g_up[1:]).max(), rel)
+    ok &= _check("dJ_up/dFx", g_up[1], fd("Fx", "up"), np.abs(g_up[1:4]).max(), rel)
+    ok &= _check("dJ_up/dFy", g_up[2], fd("Fy", "up"), np.abs(g_up[1:4]).max(), rel)
     ok &= _check("dS/dFy", g_split[2], fd("Fy", "split"), abs(g_split[2]), rel)
     # the geometry is symmetric in y: the split does not move with s
     ok &= _check("dS/ds", g_split[0], fd("s", "split"), abs(g_split[2]) * 1e-3, rel)
