@@ -202,13 +202,15 @@ lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double 
  * doubles, device) dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz, dJ/dtau: s scales the wall
  * velocity of every velocity-face (inlet) node, F is the uniform body force,
  * tau the relaxation time (Eq. evoleq; the viscosity), all held fixed over
- * the n steps, derivatives at the context's own values (s = 1).  The trajectory is recomputed in the context's precision (its
- * storage and arithmetic, as lbm_step runs it); the adjoint is FP64:
- * the transposes of the collision and of Zou-He written out at each node's
- * state, exact transposes of the streaming and bounce-back (for an FP32
- * or FP16S context, the derivative of the step in exact arithmetic at its
- * states).  Entries of w and lambda at solid nodes are ignored; dJ/dg^0 is
- * zero there.
+ * the n steps, derivatives at the context's own values (s = 1).  The
+ * trajectory is recomputed in the context's precision (its storage and
+ * arithmetic, as lbm_step runs it); the adjoint is FP64: the transposes of
+ * the collision and of Zou-He written out at each node's state, exact
+ * transposes of the streaming and bounce-back (for an FP32 or FP16S
+ * context, the derivative of the step in exact arithmetic at its states).
+ * Entries of w and lambda at solid nodes are ignored; dJ/dg^0 is zero
+ * there.  checkpoint_every (K) >= 1; d_w may be NULL; every other pointer
+ * is required (else LBM_E_INVAL).
  * Checkpoints: the state is kept every checkpoint_every steps and each
  * segment is recomputed once in the reverse sweep (device memory: 6 FP64
  * fields and ceil(n/K) + max(K, 2) states of 19 x plane values, plus K x 19
