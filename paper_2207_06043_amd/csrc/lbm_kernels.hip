@@ -2465,13 +2465,21 @@ __global__ __launch_bounds__(256) void k_adj_fwd_rec(FluidArgs a, double* hrec) 
   if (r < a.nrec) adj_fwd_rec_one<S>(a, hrec, r);
 }
 
+// Block b of a merged launch -> record block or bulk block, each part's
+// blocks remapped so that every XCD takes a contiguous run (neighbouring
+// rows share its L2).
+__device__ __forceinline__ int adj_unit(int b, int rec_blocks, int nblocks) {
+  return b < rec_blocks ? xcd_remap(b, rec_blocks) : rec_blocks + xcd_remap(b - rec_blocks, nblocks - rec_blocks);
+}
+
 template <class S>
 __global__ __launch_bounds__(256) void k_adj_fwd_all(FluidArgs a, double* hrec, int rec_blocks) {
-  if ((int)blockIdx.x < rec_blocks) {
-    const int r = blockIdx.x * 256 + threadIdx.x;
+  const int u = adj_unit(blockIdx.x, rec_blocks, gridDim.x);
+  if (u < rec_blocks) {
+    const int r = u * 256 + threadIdx.x;
     if (r < a.nrec) adj_fwd_rec_one<S>(a, hrec, r);
   } else {
-    const int t = (blockIdx.x - rec_blocks) * 256 + threadIdx.x;
+    const int t = (u - rec_blocks) * 256 + threadIdx.x;
     if (t < a.nbulk_nodes) adj_fwd_bulk_one<S>(a, t);
   }
 }
@@ -2723,11 +2731,12 @@ __global__ __launch_bounds__(256, REC ? 1 : 2) void k_adj_reverse(FluidArgs a, A
 template <class S>
 __global__ __launch_bounds__(256) void k_adj_reverse_all(FluidArgs a, AdjStep st, int rec_blocks) {
   double dF[4] = {0.0, 0.0, 0.0, 0.0}, gs = 0.0;
-  if ((int)blockIdx.x < rec_blocks) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
+  const int u = adj_unit(blockIdx.x, rec_blocks, gridDim.x);
+  if (u < rec_blocks) {
+    const int t = u * 256 + threadIdx.x;
     if (t < a.nrec) adj_reverse_one<true, S>(a, st, t, dF, gs);
   } else {
-    const int t = (blockIdx.x - rec_blocks) * 256 + threadIdx.x;
+    const int t = (u - rec_blocks) * 256 + threadIdx.x;
     if (t < a.nbulk_nodes) adj_reverse_one<false, S>(a, st, t, dF, gs);
   }
   adj_part_add(st.part, gs, dF);
