@@ -192,6 +192,21 @@ lbm_status ib_interpolate(lbm_ctx *ctx, int64_t n, const double *d_pts, const do
 lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double *d_F,
                      const double *d_c, double *d_fib);
 
+/* ib_spread without allocating: for callers that cannot allocate device
+ * memory (code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and errors as
+ * ib_spread, bitwise the same d_fib; it allocates nothing (no hipMalloc,
+ * hipFree or allocating library call).  Its fixed-point sums live in a
+ * fixed device scratch array of 48 MiB plus 256 bytes that every GPU the
+ * library runs on holds until the process ends; the call clears the part it
+ * uses first.  Lattices of more than 2^21 padded nodes (rows padded to a
+ * multiple of 8: px ny nz > 2097152) are refused with LBM_E_INVAL.  All calls
+ * on one GPU share that array: calls that overlap on one GPU (other streams,
+ * other host threads, other contexts) race and must be serialised by the
+ * caller.  Synchronises the context's stream. */
+lbm_status ib_spread_noalloc(lbm_ctx *ctx, int64_t n, const double *d_pts, const double *d_F,
+                             const double *d_c, double *d_fib);
+
 /* Discrete adjoint of the fluid step (Eqs. evoleq, forcing, bbouzidi,
  * extbound taken as one map g^k -> g^{k+1} of the post-collision deviations
  * g = f - w_i).  For the n_steps-step trajectory that starts from the

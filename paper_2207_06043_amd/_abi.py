@@ -24,7 +24,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 EXPORTS = ["lbm_create", "lbm_destroy", "lbm_last_error", "lbm_info", "lbm_add_body", "lbm_step",
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_force",
            "lbm_get_body",
-           "ib_interpolate", "ib_spread", "lbm_adjoint_step", "lbm_save", "lbm_load",
+           "ib_interpolate", "ib_spread", "ib_spread_noalloc", "lbm_adjoint_step", "lbm_save", "lbm_load",
            "lbm_time_fluid_kernel", "lbm_set_graph", "lbm_set_launch_shape", "lbm_diagnostics",
            "lbm_batch_create",
            "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_step", "lbm_batch_tune",
@@ -116,6 +116,8 @@ def load_library():
     L.ib_interpolate.argtypes = [vp, i64, vp, vp, vp]
     L.ib_spread.restype = st
     L.ib_spread.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.ib_spread_noalloc.restype = st
+    L.ib_spread_noalloc.argtypes = [vp, i64, vp, vp, vp, vp]
     L.lbm_adjoint_step.restype = st
     L.lbm_adjoint_step.argtypes = [vp, i32, i32, vp, vp, vp]
     L.lbm_save.restype = st
@@ -335,6 +337,13 @@ class Lattice:
             fib = t.zeros(3, self.N, dtype=t.float64, device=self.device)
         self._check(load_library().ib_spread(self._h, pts.shape[0], _ptr(pts), _ptr(F), _ptr(c), _ptr(fib)))
         self.stream.synchronize()
+        return fib
+
+    def ib_spread_noalloc(self, pts, F, c, fib):
+        """The allocation-free spread: fib ([3][N] FP64 on the device) += the
+        spread of c*F at pts; the caller supplies every buffer."""
+        self._check(load_library().ib_spread_noalloc(self._h, pts.shape[0], _ptr(pts), _ptr(F), _ptr(c),
+                                                     _ptr(fib)))
         return fib
 
     def adjoint(self, n_steps, lam, w=None, checkpoint_every=100):

@@ -43,6 +43,7 @@ struct HostBody {
 }  // namespace
 
 struct lbm_ctx {
+  int device = 0;                  // HIP device the context was created on
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   hipStream_t side = nullptr;      // boundary-record kernel (forked from the step stream)
@@ -200,6 +201,13 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   if ((long long)d->nx * d->ny * d->nz > (1LL << 31) - (1LL << 20)) return bad("grid too large");
   ctx->stream = (hipStream_t)hip_stream;
   ctx->prec = d->precision;
+  {
+    // the context lives on the current device; look up that device's
+    // scratch of the allocation-free spread once, here, with it current
+    if (hipGetDevice(&ctx->device) != hipSuccess) return bad("no HIP device");
+    long long* scr = nullptr;
+    if (noalloc_scratch(ctx->device, &scr) != hipSuccess) return bad("device scratch not addressable");
+  }
   // launch shape (defaults; overridable for tuning)
   // few non-solid nodes (cache-resident, latency-bound; or a sparse box,
   // where big tiles would mostly cover solid nodes): one node per thread and
@@ -1613,6 +1621,24 @@ extern "C" lbm_status ib_spread(lbm_ctx* ctx, int64_t n, const double* d_pts, co
     CHK(hipMemset(ctx->api_flags, 0, sizeof(DevFlags)));
     return fail(ctx, LBM_E_INVAL, "ib_spread: a contribution c*phi*F exceeded +-1 (dropped)");
   }
+  return LBM_OK;
+}
+
+extern "C" lbm_status ib_spread_noalloc(lbm_ctx* ctx, int64_t n, const double* d_pts, const double* d_F,
+                                        const double* d_c, double* d_fib) {
+  if (!ctx || n < 0 || !d_fib || (n > 0 && (!d_pts || !d_F || !d_c))) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (ctx->g.Np > NOALLOC_MAX_NODES)
+    return fail(ctx, LBM_E_INVAL,
+                "ib_spread_noalloc: the lattice has " + std::to_string(ctx->g.Np) +
+                    " padded nodes; the scratch holds at most " + std::to_string(NOALLOC_MAX_NODES));
+  long long* scr = nullptr;
+  CHK(noalloc_scratch(ctx->device, &scr));
+  CHK(launch_spread_noalloc(ctx->g, ctx->ncls, n, d_pts, d_F, d_c, d_fib, scr, ctx->stream));
+  DevFlags h;
+  CHK(hipStreamSynchronize(ctx->stream));
+  CHK(hipMemcpy(&h, scr + 3 * NOALLOC_MAX_NODES, sizeof(DevFlags), hipMemcpyDeviceToHost));
+  if (h.overflow) return fail(ctx, LBM_E_INVAL, "ib_spread_noalloc: a contribution c*phi*F exceeded +-1 (dropped)");
   return LBM_OK;
 }
 

@@ -234,6 +234,24 @@ hipError_t launch_spread_api(const Grid& g, const uint8_t* ncls, long long n, co
                              hipStream_t s);
 hipError_t launch_flush_fx(const Grid& g, long long* fx, double* fib, hipStream_t s);
 
+// Allocation-free spread: a fixed scratch array in device memory (one copy
+// per GPU, held until the process ends) holds the fixed-point sums of up to
+// NOALLOC_MAX_NODES padded nodes ([3][NOALLOC_MAX_NODES] 64-bit words, 48 MiB)
+// followed by NOALLOC_FLAG_WORDS words for the range flags.
+constexpr long long NOALLOC_MAX_NODES = 1LL << 21;
+constexpr long long NOALLOC_FLAG_WORDS = 32;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static_assert(sizeof(DevFlags) <= NOALLOC_FLAG_WORDS * 8, "flags fit the scratch tail");
+// Device address of the scratch on `device` (looked up once per device with
+// that device current, then kept).
+hipError_t noalloc_scratch(int device, long long** out);
+// Clear the scratch for the lattice, spread, add the sums into fib (as
+// ib_spread does with its own buffer); overflow is reported in the flags at
+// scr + 3 NOALLOC_MAX_NODES.  Requires g.Np <= NOALLOC_MAX_NODES.
+hipError_t launch_spread_noalloc(const Grid& g, const uint8_t* ncls, long long n, const double* pts,
+                                 const double* F, const double* c, double* fib, long long* scr,
+                                 hipStream_t s);
+
 // Launch shape of the batched fluid phase: blocks of `block` threads, V
 // nodes per bulk thread (0: list form); mode 0 merged (map_all), 1 split
 // (map_rec, then map_bulk); per_xcd > 0 runs the merged units, or the bulk

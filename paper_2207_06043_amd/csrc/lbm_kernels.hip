@@ -21,6 +21,8 @@
 #include <limits.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -2998,6 +3000,60 @@ hipError_t launch_flush_fx(const Grid& g, long long* fx, double* fib, hipStream_
   const long long N = (long long)g.nx * g.ny * g.nz;
   k_flush_fx<<<cdiv(N, 256), 256, 0, s>>>(g, fx, fib);
   return hipGetLastError();
+}
+
+// ------------------------------------------------- allocation-free spread
+// Fixed-point force sums of the allocation-free spread, then its flags.  In
+// host code the name stands for nothing on the device: the kernels get the
+// address that hipGetSymbolAddress returned for the device in use.
+static __device__ __align__(256) long long scratch[3 * NOALLOC_MAX_NODES + NOALLOC_FLAG_WORDS];
+
+namespace {
+std::mutex scratch_mu;
+long long* scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+__global__ void k_zero_words(long long* p, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+}  // namespace
+
+hipError_t noalloc_scratch(int device, long long** out) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[device] = (long long*)p;
+  }
+  *out = scratch_dev[device];
+  return hipSuccess;
+}
+
+hipError_t launch_spread_noalloc(const Grid& g, const uint8_t* ncls, long long n, const double* pts,
+                                 const double* F, const double* c, double* fib, long long* scr,
+                                 hipStream_t s) {
+  if (g.Np > NOALLOC_MAX_NODES) return hipErrorInvalidValue;
+  long long* flag_words = scr + 3 * NOALLOC_MAX_NODES;
+  // the last call's sums are normally flushed to zero already; clear anyway
+  // (a fill kernel, not a memset, so that the sequence can be captured)
+  k_zero_words<<<cdiv(3 * g.Np, 256), 256, 0, s>>>(scr, 3 * g.Np);
+  k_zero_words<<<1, 64, 0, s>>>(flag_words, NOALLOC_FLAG_WORDS);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_spread_api(g, ncls, n, pts, F, c, scr, (DevFlags*)flag_words, s);
+  if (e != hipSuccess) return e;
+  return launch_flush_fx(g, scr, fib, s);
 }
 
 }  // namespace lbm
