@@ -238,7 +238,11 @@ lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t n_steps, int32_t checkpoint_ev
 
 /* Checkpoint / restart of the full state (populations, force field, body
  * state) to a binary file; lbm_load requires a context created with the
- * same geometry and bodies. */
+ * same geometry and bodies.  lbm_save returns LBM_E_INVAL if the file
+ * cannot be opened or fully written.  lbm_load reads and checks the whole
+ * file before it changes anything: a file that does not match the context,
+ * is truncated or is longer than its state gives LBM_E_INVAL and leaves the
+ * context as it was. */
 lbm_status lbm_save(lbm_ctx *ctx, const char *path);
 lbm_status lbm_load(lbm_ctx *ctx, const char *path);
 

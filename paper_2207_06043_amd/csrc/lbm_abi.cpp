@@ -995,7 +995,7 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
   if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return e;
   if (ib) {
     const BodyArgs& b = ctx->bargs[p];
-    if ((e = launch_mls_post(ctx->prec, a, b, s)) != hipSuccess) return e;
+    if ((e = launch_mls_post(ctx->prec, a, b, ctx->fx[p ^ 1], ctx->tf[p ^ 1], s)) != hipSuccess) return e;
     // a few tens of blocks close the step in their last one; more: k_close
     const bool fold = body_post_blocks(b) <= 128;
     if ((e = launch_body_post(b, ctx->flags, fold ? counter(ctx, 1) : nullptr, s)) != hipSuccess) return e;
@@ -1226,11 +1226,12 @@ static lbm_status batch_build_tables(lbm_batch* b) {
     }
     if (c->nf > 0) {
       const BodyArgs& B = c->bargs[0];
-      const int nib = B.n_marker_blocks + B.n_elem_blocks + B.n_clear_blocks + B.n_diag_blocks;
+      const int nib = B.n_marker_blocks + B.n_elem_blocks + B.n_diag_blocks;
       for (int j = 0; j < nib; j++) ib.push_back(make_int2(i, j));
+      // probe / vertex-velocity blocks, then the previous step's tile clears
       const long long waves = (long long)(B.nf + MLS_FACES_PER_WAVE - 1) / MLS_FACES_PER_WAVE +
                               (B.nsoft_v + MLS_VERTS_PER_WAVE - 1) / MLS_VERTS_PER_WAVE;
-      const int nm = (int)((waves * 64 + 255) / 256);
+      const int nm = (int)((waves * 64 + 255) / 256) + B.n_clear_blocks;
       for (int j = 0; j < nm; j++) mls.push_back(make_int2(i, j));
       const int nbp = B.nbody + (B.nsoft_v + 63) / 64;
       for (int j = 0; j < nbp; j++) body.push_back(make_int2(i, j));
@@ -1795,12 +1796,29 @@ struct CkptHeader {
 };
 }  // namespace
 
-extern "C" lbm_status lbm_save(lbm_ctx* ctx, const char* path) {
-  if (!ctx || !path) return LBM_E_INVAL;
-  if (ctx->broken) return LBM_E_STATE;
-  DevFlags h;
-  lbm_status st = read_flags(ctx, &h);
-  if (st) return st;
+// The sections of a checkpoint after the header and flags, in file order:
+// both population buffers; with bodies, per parity the force field, its tile
+// flags and the vertex positions, then the velocities and the rigid-body and
+// diagnostics tables.
+static std::vector<std::pair<void*, size_t>> ckpt_sections(lbm_ctx* ctx) {
+  std::vector<std::pair<void*, size_t>> v;
+  const size_t fbytes = (size_t)19 * ctx->g.plane * ctx->ssize;
+  for (int p = 0; p < 2; p++) v.emplace_back(ctx->f[p], fbytes);
+  if (ctx->nf > 0) {
+    const size_t fxb = 3 * (size_t)ctx->g.Np * sizeof(long long);
+    for (int p = 0; p < 2; p++) {
+      v.emplace_back(ctx->fx[p], fxb);
+      v.emplace_back(ctx->tf[p], (size_t)ctx->ntiles);
+      v.emplace_back(ctx->X[p], 3 * sizeof(double) * ctx->nv);
+    }
+    v.emplace_back(ctx->Vel, 3 * sizeof(double) * ctx->nv);
+    v.emplace_back(ctx->b_rig, 32 * sizeof(double) * ctx->bodies.size());
+    v.emplace_back(ctx->b_diag, 16 * sizeof(double) * ctx->bodies.size());
+  }
+  return v;
+}
+
+static CkptHeader ckpt_header(lbm_ctx* ctx, int64_t steps_done) {
   CkptHeader hd{};
   memcpy(hd.magic, "LBMIB01", 8);
   hd.nx = ctx->g.nx;
@@ -1810,40 +1828,38 @@ extern "C" lbm_status lbm_save(lbm_ctx* ctx, const char* path) {
   hd.nbody = (int)ctx->bodies.size();
   hd.nv = ctx->nv;
   hd.nf = ctx->nf;
-  hd.steps_done = h.steps_done;
+  hd.steps_done = steps_done;
+  return hd;
+}
+
+extern "C" lbm_status lbm_save(lbm_ctx* ctx, const char* path) {
+  if (!ctx || !path) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  DevFlags h;
+  lbm_status st = read_flags(ctx, &h);
+  if (st) return st;
+  const CkptHeader hd = ckpt_header(ctx, h.steps_done);
+  // everything is copied to the host first, so a device error leaves no file behind
+  const auto secs = ckpt_sections(ctx);
+  std::vector<std::vector<char>> bufs(secs.size());
+  for (size_t k = 0; k < secs.size(); k++) {
+    bufs[k].resize(secs[k].second);
+    CHK(hipMemcpy(bufs[k].data(), secs[k].first, secs[k].second, hipMemcpyDeviceToHost));
+  }
   FILE* fp = fopen(path, "wb");
   if (!fp) return fail(ctx, LBM_E_INVAL, std::string("cannot open ") + path);
-  fwrite(&hd, sizeof hd, 1, fp);
-  fwrite(&h, sizeof h, 1, fp);
-  auto dump = [&](const void* d, size_t bytes) -> hipError_t {
-    std::vector<char> buf(bytes);
-    hipError_t e = hipMemcpy(buf.data(), d, bytes, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) fwrite(buf.data(), 1, bytes, fp);
-    return e;
-  };
-  const size_t fbytes = (size_t)19 * ctx->g.plane * ctx->ssize;
-  hipError_t e = hipSuccess;
-  for (int p = 0; p < 2 && e == hipSuccess; p++) e = dump(ctx->f[p], fbytes);
-  if (e == hipSuccess && ctx->nf > 0) {
-    const size_t fxb = 3 * (size_t)ctx->g.Np * sizeof(long long);
-    for (int p = 0; p < 2 && e == hipSuccess; p++) {
-      e = dump(ctx->fx[p], fxb);
-      if (e == hipSuccess) e = dump(ctx->tf[p], ctx->ntiles);
-      if (e == hipSuccess) e = dump(ctx->X[p], 3 * sizeof(double) * ctx->nv);
-    }
-    if (e == hipSuccess) e = dump(ctx->Vel, 3 * sizeof(double) * ctx->nv);
-    if (e == hipSuccess) e = dump(ctx->b_rig, 32 * sizeof(double) * ctx->bodies.size());
-    if (e == hipSuccess) e = dump(ctx->b_diag, 16 * sizeof(double) * ctx->bodies.size());
-  }
-  fclose(fp);
-  CHK(e);
+  bool ok = fwrite(&hd, sizeof hd, 1, fp) == 1 && fwrite(&h, sizeof h, 1, fp) == 1;
+  for (size_t k = 0; ok && k < bufs.size(); k++)
+    ok = fwrite(bufs[k].data(), 1, bufs[k].size(), fp) == bufs[k].size();
+  ok = (fflush(fp) == 0) && ok;
+  ok = (fclose(fp) == 0) && ok;
+  if (!ok) return fail(ctx, LBM_E_INVAL, std::string("short write to ") + path);
   return LBM_OK;
 }
 
 extern "C" lbm_status lbm_load(lbm_ctx* ctx, const char* path) {
   if (!ctx || !path) return LBM_E_INVAL;
   if (ctx->broken) return LBM_E_STATE;
-  CHK(hipStreamSynchronize(ctx->stream));
   FILE* fp = fopen(path, "rb");
   if (!fp) return fail(ctx, LBM_E_INVAL, std::string("cannot open ") + path);
   CkptHeader hd{};
@@ -1851,33 +1867,26 @@ extern "C" lbm_status lbm_load(lbm_ctx* ctx, const char* path) {
   bool ok = fread(&hd, sizeof hd, 1, fp) == 1 && fread(&h, sizeof h, 1, fp) == 1;
   ok = ok && memcmp(hd.magic, "LBMIB01", 8) == 0 && hd.nx == ctx->g.nx && hd.ny == ctx->g.ny &&
        hd.nz == ctx->g.nz && hd.prec == ctx->prec && hd.nbody == (int)ctx->bodies.size() &&
-       hd.nv == ctx->nv && hd.nf == ctx->nf;
+       hd.nv == ctx->nv && hd.nf == ctx->nf && hd.steps_done == h.steps_done;
   if (!ok) {
     fclose(fp);
     return fail(ctx, LBM_E_INVAL, "checkpoint does not match this context");
   }
-  auto load = [&](void* d, size_t bytes) -> hipError_t {
-    std::vector<char> buf(bytes);
-    if (fread(buf.data(), 1, bytes, fp) != bytes) return hipErrorInvalidValue;
-    return hipMemcpy(d, buf.data(), bytes, hipMemcpyHostToDevice);
-  };
-  const size_t fbytes = (size_t)19 * ctx->g.plane * ctx->ssize;
-  hipError_t e = hipSuccess;
-  for (int p = 0; p < 2 && e == hipSuccess; p++) e = load(ctx->f[p], fbytes);
-  if (e == hipSuccess && ctx->nf > 0) {
-    const size_t fxb = 3 * (size_t)ctx->g.Np * sizeof(long long);
-    for (int p = 0; p < 2 && e == hipSuccess; p++) {
-      e = load(ctx->fx[p], fxb);
-      if (e == hipSuccess) e = load(ctx->tf[p], ctx->ntiles);
-      if (e == hipSuccess) e = load(ctx->X[p], 3 * sizeof(double) * ctx->nv);
-    }
-    if (e == hipSuccess) e = load(ctx->Vel, 3 * sizeof(double) * ctx->nv);
-    if (e == hipSuccess) e = load(ctx->b_rig, 32 * sizeof(double) * ctx->bodies.size());
-    if (e == hipSuccess) e = load(ctx->b_diag, 16 * sizeof(double) * ctx->bodies.size());
+  // read and size-check the whole file before the first device copy: a
+  // truncated or oversized file leaves the context as it was
+  const auto secs = ckpt_sections(ctx);
+  std::vector<std::vector<char>> bufs(secs.size());
+  for (size_t k = 0; ok && k < secs.size(); k++) {
+    bufs[k].resize(secs[k].second);
+    ok = fread(bufs[k].data(), 1, secs[k].second, fp) == secs[k].second;
   }
+  const bool at_end = ok && fgetc(fp) == EOF;
   fclose(fp);
-  if (e == hipErrorInvalidValue) return fail(ctx, LBM_E_INVAL, "truncated checkpoint");
-  CHK(e);
+  if (!ok) return fail(ctx, LBM_E_INVAL, "truncated checkpoint (context unchanged)");
+  if (!at_end) return fail(ctx, LBM_E_INVAL, "checkpoint longer than this context's state (context unchanged)");
+  CHK(hipStreamSynchronize(ctx->stream));
+  for (size_t k = 0; k < secs.size(); k++)
+    CHK(hipMemcpy(secs[k].first, bufs[k].data(), secs[k].second, hipMemcpyHostToDevice));
   CHK(hipMemcpy(ctx->flags, &h, sizeof h, hipMemcpyHostToDevice));
   ctx->enq = h.steps_done;
   return LBM_OK;

@@ -161,7 +161,8 @@ hipError_t launch_close(DevFlags* flags, hipStream_t s);
 hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fx_cur,
                            uint8_t* tf_cur, long long* fx_prev, uint8_t* tf_prev,
                            unsigned int* counter, hipStream_t s);
-hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s);
+hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, long long* fxp, uint8_t* tfp,
+                           hipStream_t s);
 // with a counter (zeroed; left zeroed) it closes the step (steps_done, stop
 // from pending) in its last block; with null, launch_close must follow
 hipError_t launch_body_post(const BodyArgs& b, DevFlags* flags, unsigned int* counter, hipStream_t s);

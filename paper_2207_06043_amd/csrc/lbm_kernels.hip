@@ -1446,15 +1446,15 @@ template <class S>
 __device__ __forceinline__ void ib_force_block(const FluidArgs& a, const BodyArgs& b, long long* fxc,
                                                uint8_t* tfc, long long* fxp, uint8_t* tfp,
                                                unsigned int* counter, int blk) {
-  const int nmk = b.n_marker_blocks, nel = b.n_elem_blocks, ncl = b.n_clear_blocks;
+  const int nmk = b.n_marker_blocks, nel = b.n_elem_blocks;
+  (void)fxp;
+  (void)tfp;
   if (blk < nmk) {
     marker_block<S>(a, b, blk, fxc, tfc);
   } else if (blk < nmk + nel) {
     membrane_element(b, (blk - nmk) * 256 + threadIdx.x);
-  } else if (blk < nmk + nel + ncl) {
-    clear_tiles(a.g, fxp, tfp, blk - nmk - nel, ncl);
   } else {
-    diag_block(b, b.Xcur, blk - nmk - nel - ncl);
+    diag_block(b, b.Xcur, blk - nmk - nel);
     // the diagnostics blocks count themselves; the last one combines them
     if (last_block(counter, b.n_diag_blocks)) {
       const unsigned int raised = diag_finalize(b);
@@ -1739,10 +1739,29 @@ __device__ __forceinline__ void mls_post_block(const FluidArgs& a, const BodyArg
   }
 }
 
+// Blocks of the probe / vertex-velocity part of the launch.
+__host__ __device__ __forceinline__ int mls_post_blocks(const BodyArgs& b) {
+  const long long waves = (long long)(b.nf + MLS_FACES_PER_WAVE - 1) / MLS_FACES_PER_WAVE +
+                          (b.nsoft_v + MLS_VERTS_PER_WAVE - 1) / MLS_VERTS_PER_WAVE;
+  return (int)((waves * 64 + 255) / 256);
+}
+
+// The launch also clears the force tiles of the previous step (the buffer
+// the next step spreads into).  It runs after the forcing launch has checked
+// the positions: a damage stop raised there skips this launch, so the force
+// of the last completed step survives the stop.
 template <class S>
-__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b) {
+__device__ __forceinline__ void mls_post_unit(const FluidArgs& a, const BodyArgs& b, long long* fxp,
+                                              uint8_t* tfp, int blk) {
+  const int nm = mls_post_blocks(b);
+  if (blk < nm) mls_post_block<S>(a, b, blk);
+  else clear_tiles(a.g, fxp, tfp, blk - nm, b.n_clear_blocks);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_mls_post(FluidArgs a, BodyArgs b, long long* fxp, uint8_t* tfp) {
   if (a.flags->stop) return;
-  mls_post_block<S>(a, b, blockIdx.x);
+  mls_post_unit<S>(a, b, fxp, tfp, blockIdx.x);
 }
 
 // ----------------------------------------------------------- k_body_post
@@ -2025,7 +2044,7 @@ __global__ __launch_bounds__(256) void kb_mls_post(const BatchItem* items, const
   const FluidArgs a = it.a;
   if (a.flags->stop) return;
   const BodyArgs b = it.b;
-  mls_post_block<S>(a, b, m.y);
+  mls_post_unit<S>(a, b, it.fxp, it.tfp, m.y);
 }
 
 __global__ __launch_bounds__(256) void kb_body_post(const BatchItem* items, const int2* map) {
@@ -2255,8 +2274,7 @@ hipError_t launch_close(DevFlags* flags, hipStream_t s) {
 hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long long* fxc,
                            uint8_t* tfc, long long* fxp, uint8_t* tfp, unsigned int* counter,
                            hipStream_t s) {
-  const unsigned grid =
-      (unsigned)(b.n_marker_blocks + b.n_elem_blocks + b.n_clear_blocks + b.n_diag_blocks);
+  const unsigned grid = (unsigned)(b.n_marker_blocks + b.n_elem_blocks + b.n_diag_blocks);
   if (grid == 0) return hipSuccess;
   switch (prec) {
     case 0: k_ib_force<double><<<grid, 256, 0, s>>>(a, b, fxc, tfc, fxp, tfp, counter); break;
@@ -2266,15 +2284,14 @@ hipError_t launch_ib_force(int prec, const FluidArgs& a, const BodyArgs& b, long
   return hipGetLastError();
 }
 
-hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, hipStream_t s) {
+hipError_t launch_mls_post(int prec, const FluidArgs& a, const BodyArgs& b, long long* fxp, uint8_t* tfp,
+                           hipStream_t s) {
   if (b.nf == 0) return hipSuccess;
-  const long long waves = (long long)(b.nf + MLS_FACES_PER_WAVE - 1) / MLS_FACES_PER_WAVE +
-                          (b.nsoft_v + MLS_VERTS_PER_WAVE - 1) / MLS_VERTS_PER_WAVE;
-  const unsigned grid = cdiv(waves * 64, 256);
+  const unsigned grid = (unsigned)(mls_post_blocks(b) + b.n_clear_blocks);
   switch (prec) {
-    case 0: k_mls_post<double><<<grid, 256, 0, s>>>(a, b); break;
-    case 1: k_mls_post<float><<<grid, 256, 0, s>>>(a, b); break;
-    default: k_mls_post<_Float16><<<grid, 256, 0, s>>>(a, b); break;
+    case 0: k_mls_post<double><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
+    case 1: k_mls_post<float><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
+    default: k_mls_post<_Float16><<<grid, 256, 0, s>>>(a, b, fxp, tfp); break;
   }
   return hipGetLastError();
 }

@@ -257,6 +257,38 @@ def test_damage_stops_on_device(lib):
     assert np.array_equal(lat.body(0)[0].cpu().numpy(), x1)
 
 
+def test_damage_stop_keeps_the_last_completed_step(lib):
+    """A small capsule in open fluid, given an expanding history, is damaged
+    by its first update.  The stop is raised at the start of the next step:
+    the force field, the fields and the positions read afterwards are those
+    of the last completed step (the force is non-zero there), as the
+    oracle's state after the step that produced the damaged shape."""
+    d = synth.pipe(24, 24, 24, 8.0, periodic_x=True, init="rest")
+    c = np.array([12.2, 11.3, 11.6])
+    X, Fc = synth.icosphere(1, 0.5, tuple(c), tilt=True)
+    b = synth.Body(X, Fc, rigid=False, ca=0.05, r_ref=0.5, u_ref=0.02, v0=-2.4 * (X - c))
+    w = synth.Workload("damage_force", d, [b], 0.8, 0.02, "f64", 3)
+    _say("[failure] damage keeps the last step")
+    lat = lib.from_workload(w)
+    lat.step(3)
+    assert lat.sync(raise_on_stop=False) == lib.LBM_E_DAMAGED
+    assert lat.info()["steps_done"] == 1
+    orc = oracle.from_workload(w)
+    assert orc.step(3) == 5 and orc.steps_done == 1
+    fo = orc.force()
+    assert np.abs(fo).max() > 1e-2
+    fg = lat.force().cpu().numpy()
+    assert np.abs(fg - fo).max() < 1e-12 * np.abs(fo).max()
+    rho_g, u_g = (t.cpu().numpy() for t in lat.fields())
+    rho_o, u_o = orc.fields()
+    assert np.abs(u_g - u_o).max() < 1e-12 * np.abs(u_o).max()
+    assert np.abs(rho_g - rho_o).max() < 1e-13
+    # positions of the damaged shape (about 1.2 lu from the step before),
+    # to rounding of coordinates near 12
+    xg, xo = lat.body(0)[0].cpu().numpy(), orc.body(0)[0]
+    assert np.abs(xg - xo).max() < 1e-12 * np.abs(xo).max()
+
+
 def test_unstable_flow_stops_on_device(lib):
     d = synth.periodic_box(8, 8, 8)
     d.init_u = np.full(3 * d.n_nodes, 0.4)
@@ -291,6 +323,40 @@ def test_checkpoint_roundtrip(lib, tmp_path):
     b.step(5)
     b.sync()
     assert np.array_equal(b.populations().cpu().numpy(), ref)
+
+
+def test_checkpoint_truncated_or_oversized_leaves_the_context(lib, tmp_path):
+    """A checkpoint cut short (or with bytes appended) is refused before
+    anything is copied: the context keeps its own state and steps on as if
+    the load had not been tried."""
+    w = synth.tiny_pipe(precision="f32", rigid=False)
+    a = lib.from_workload(w)
+    a.step(4)
+    a.sync()
+    a.save(tmp_path / "ck.bin")
+    raw = (tmp_path / "ck.bin").read_bytes()
+    (tmp_path / "cut.bin").write_bytes(raw[: len(raw) - 1000])
+    (tmp_path / "long.bin").write_bytes(raw + b"\0" * 8)
+    b = lib.from_workload(w)
+    b.step(7)
+    b.sync()
+    f7 = b.populations().cpu().numpy()
+    x7 = b.body(0)[0].cpu().numpy()
+    for name in ("cut.bin", "long.bin"):
+        with pytest.raises(lib.LbmError) as e:
+            b.load(tmp_path / name)
+        assert e.value.status == 1
+        assert b.info()["steps_done"] == 7
+        assert np.array_equal(b.populations().cpu().numpy(), f7)
+        assert np.array_equal(b.body(0)[0].cpu().numpy(), x7)
+    c = lib.from_workload(w)
+    c.step(8)
+    c.sync()
+    b.step(1)
+    b.sync()
+    assert np.array_equal(b.populations().cpu().numpy(), c.populations().cpu().numpy())
+    with pytest.raises(lib.LbmError):
+        a.save(tmp_path / "no_such_dir" / "ck.bin")
 
 
 # ------------------------------------------------------------ FP16 storage
