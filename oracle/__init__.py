@@ -21,13 +21,18 @@ _lib = None
 # trajectory moves under other rounding: "fma" lets the compiler fuse
 # multiply-adds, "reassoc" lets it reorder sums (vectorised reductions),
 # "store_f32" and "store_f16" round the stored populations to FP32 or to
-# binary16.
+# binary16; "ldouble" runs the fluid state and arithmetic in long double (a
+# near-exact reference trajectory); "fullpop" stores full populations f
+# instead of the deviations f - w ("fullpop_ldouble": both).
 VARIANT_FLAGS = {
     "plain": [],
     "fma": ["-mfma", "-ffp-contract=fast"],
     "reassoc": ["-O3", "-mavx2", "-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math"],
     "store_f32": ["-DORC_STORE_F32"],
     "store_f16": ["-DORC_STORE_F16"],
+    "ldouble": ["-DORC_LDOUBLE"],
+    "fullpop": ["-DORC_FULL_POP"],
+    "fullpop_ldouble": ["-DORC_FULL_POP", "-DORC_LDOUBLE"],
 }
 
 
@@ -110,6 +115,10 @@ def lib():
     L.orc_membrane.argtypes = [vp, C.c_int, _P(d), C.c_int, _P(d)]
     L.orc_body_hydro.argtypes = [vp, C.c_int, _P(d)]
     L.orc_body_fext.argtypes = [vp, C.c_int, _P(d)]
+    L.orc_body_inertia.argtypes = [vp, C.c_int, _P(d)]
+    L.orc_rodrigues.argtypes = [_P(d), _P(d)]
+    L.orc_move_rigid.restype = C.c_int
+    L.orc_move_rigid.argtypes = [vp, C.c_int, _P(d)]
     _lib = L
     return L
 
@@ -307,6 +316,23 @@ class OracleSim:
         out = np.zeros((nf, 3))
         lib().orc_body_fext(self._h, bid, _ptr(out, C.c_double))
         return out
+
+    def body_inertia(self, bid):
+        """Body-frame inertia tensor of a body about its centre of mass."""
+        out = np.zeros(9)
+        lib().orc_body_inertia(self._h, bid, _ptr(out, C.c_double))
+        return out.reshape(3, 3)
+
+    def move_rigid(self, bid, Fv):
+        """One rigid-body update of body bid with vertex forces Fv [nv, 3]."""
+        return lib().orc_move_rigid(self._h, bid, _ptr(_f64(Fv), C.c_double))
+
+
+def rodrigues(phi):
+    """Rotation matrix of the rotation vector phi (the oracle's own)."""
+    R = np.zeros(9)
+    lib().orc_rodrigues(_ptr(_f64(phi), C.c_double), _ptr(R, C.c_double))
+    return R.reshape(3, 3)
 
 
 def from_workload(w, threads=None, with_bodies=True):

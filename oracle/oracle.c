@@ -53,6 +53,18 @@
 
 enum { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3 };
 
+/* Type of the fluid state and arithmetic (populations, moments, collision).
+ * double in the oracle; the measurement build ORC_LDOUBLE makes it long
+ * double (64-bit significand) to give a near-exact trajectory against which
+ * the rounding of the double builds is measured. */
+#ifdef ORC_LDOUBLE
+typedef long double preal;
+#define PR(x) x##L
+#else
+typedef double preal;
+#define PR(x) x
+#endif
+
 /* D3Q19 velocity set in the column order printed in the "Fluid evolution"
  * section (Eq. e_i); weights 1/3, 1/18 (axis), 1/36 (diagonal) from the text
  * following Eq. eqfunc. */
@@ -60,11 +72,12 @@ static const int E[19][3] = {
     {0, 0, 0},   {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
     {1, 1, 0},   {1, -1, 0}, {1, 0, 1},  {1, 0, -1}, {-1, 1, 0}, {-1, -1, 0}, {-1, 0, 1},
     {-1, 0, -1}, {0, 1, 1},  {0, 1, -1}, {0, -1, 1}, {0, -1, -1}};
-static const double Wt[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
-                              1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
-                              1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
-                              1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const preal Wt[19] = {PR(1.0) / 3,  PR(1.0) / 18, PR(1.0) / 18, PR(1.0) / 18, PR(1.0) / 18,
+                             PR(1.0) / 18, PR(1.0) / 18, PR(1.0) / 36, PR(1.0) / 36, PR(1.0) / 36,
+                             PR(1.0) / 36, PR(1.0) / 36, PR(1.0) / 36, PR(1.0) / 36, PR(1.0) / 36,
+                             PR(1.0) / 36, PR(1.0) / 36, PR(1.0) / 36, PR(1.0) / 36};
 static const double CS2 = 1.0 / 3.0; /* c_s^2, c_s = 1/sqrt(3) */
+static const preal CS2P = PR(1.0) / PR(3.0);
 
 /* Opposite direction: the one whose vector is -e_i (found by search). */
 static int opposite_search(int i) {
@@ -107,10 +120,11 @@ struct orc_sim {
   double *lk_q;
   double *uin;             /* [N*3], inlet nodes only */
   double rho_out;
-  double *fs;              /* post-collision populations, as f - w [N*19] (the state) */
-  double *f;               /* streamed populations, as f - w [N*19] (work) */
-  double *rho, *u;         /* outputs of the last step [N], [N*3] */
-  double *mom;             /* pre-collision momentum sum_i f_i e_i [N*3] */
+  preal *fs;               /* post-collision populations, as f - w [N*19] (the state) */
+  preal *f;                /* streamed populations, as f - w [N*19] (work) */
+  preal *rho;              /* density of the last step [N] */
+  double *u;               /* velocity of the last step [N*3] */
+  preal *mom;              /* pre-collision momentum sum_i f_i e_i [N*3] */
   double *ustar;           /* pre-force velocity m/rho [N*3] */
   double *fib;             /* immersed-boundary force density [N*3] */
   int nbody;
@@ -170,39 +184,51 @@ static double find_q(const orc_sim *s, long n, int dir) {
 }
 
 /* Eq. eqfunc: second-order expansion of the Maxwell-Boltzmann distribution. */
-static double feq_i(int i, double rho, const double *u) {
-  double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
-  double uu = dot(u, u);
-  return Wt[i] * rho * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+static preal feq_i(int i, preal rho, const preal *u) {
+  preal eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+  preal uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return Wt[i] * rho * (PR(1.0) + eu / CS2P + eu * eu / (PR(2.0) * CS2P * CS2P) - uu / (PR(2.0) * CS2P));
 }
 
 /* f^eq_i - w_i, the same expansion written as a deviation from the rest
  * weights (the form the populations are stored in, below). */
-static double feq_dev_i(int i, double rho, const double *u) {
-  double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
-  double uu = dot(u, u);
-  return Wt[i] * ((rho - 1.0) + rho * (eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2)));
+__attribute__((unused)) static preal feq_dev_i(int i, preal rho, const preal *u) {
+  preal eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+  preal uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return Wt[i] * ((rho - PR(1.0)) + rho * (eu / CS2P + eu * eu / (PR(2.0) * CS2P * CS2P) - uu / (PR(2.0) * CS2P)));
+}
+
+/* The stored form of the equilibrium: deviations f^eq - w (full
+ * populations in the measurement build ORC_FULL_POP). */
+static preal feq_store_i(int i, preal rho, const preal *u) {
+#ifdef ORC_FULL_POP
+  return feq_i(i, rho, u);
+#else
+  return feq_dev_i(i, rho, u);
+#endif
 }
 
 /* Eq. forcing: the discrete forcing term projected on direction i. */
-static double guo_i(int i, double tau, const double *u, const double *F) {
-  double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
-  double acc = 0.0;
-  for (int a = 0; a < 3; a++) acc += ((E[i][a] - u[a]) / CS2 + eu * E[i][a] / (CS2 * CS2)) * F[a];
-  return (1.0 - 1.0 / (2.0 * tau)) * Wt[i] * acc;
+static preal guo_i(int i, preal tau, const preal *u, const preal *F) {
+  preal eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+  preal acc = PR(0.0);
+  for (int a = 0; a < 3; a++) acc += ((E[i][a] - u[a]) / CS2P + eu * E[i][a] / (CS2P * CS2P)) * F[a];
+  return (PR(1.0) - PR(1.0) / (PR(2.0) * tau)) * Wt[i] * acc;
 }
 
 void orc_lattice(int32_t *e57, double *w19) {
   for (int i = 0; i < 19; i++) {
     for (int a = 0; a < 3; a++) e57[3 * i + a] = E[i][a];
-    w19[i] = Wt[i];
+    w19[i] = (double)Wt[i];
   }
 }
 void orc_feq(double rho, const double *u, double *out19) {
-  for (int i = 0; i < 19; i++) out19[i] = feq_i(i, rho, u);
+  preal up[3] = {u[0], u[1], u[2]};
+  for (int i = 0; i < 19; i++) out19[i] = (double)feq_i(i, rho, up);
 }
 void orc_guo(double tau, const double *u, const double *F, double *out19) {
-  for (int i = 0; i < 19; i++) out19[i] = guo_i(i, tau, u, F);
+  preal up[3] = {u[0], u[1], u[2]}, Fp[3] = {F[0], F[1], F[2]};
+  for (int i = 0; i < 19; i++) out19[i] = (double)guo_i(i, tau, up, Fp);
 }
 
 /* Eq. bbouzidi: interpolated bounce-back for the population j = opposite(i)
@@ -218,18 +244,24 @@ void orc_guo(double tau, const double *u, const double *F, double *out19) {
  * the plain bounce-back f*_i(x) when none remains (q < 1/2).
  * Every branch's coefficients add up to 1, so the rule applies unchanged to
  * deviations f - w (w_i = w_j for a link and its opposite). */
-double orc_bfl(double q, double fi_x, double fi_xm1, double fi_xm2, double fj_x,
-               double fj_xm1, int avail1, int avail2) {
-  if (q < 0.5) {
+static preal bfl(preal q, preal fi_x, preal fi_xm1, preal fi_xm2, preal fj_x, preal fj_xm1,
+                 int avail1, int avail2) {
+  if (q < PR(0.5)) {
     if (avail1 && avail2)
-      return q * (1.0 + 2.0 * q) * fi_x + (1.0 - 4.0 * q * q) * fi_xm1 - q * (1.0 - 2.0 * q) * fi_xm2;
-    if (avail1) return 2.0 * q * fi_x + (1.0 - 2.0 * q) * fi_xm1;
+      return q * (PR(1.0) + PR(2.0) * q) * fi_x + (PR(1.0) - PR(4.0) * q * q) * fi_xm1 -
+             q * (PR(1.0) - PR(2.0) * q) * fi_xm2;
+    if (avail1) return PR(2.0) * q * fi_x + (PR(1.0) - PR(2.0) * q) * fi_xm1;
     return fi_x;
   }
   if (avail1)
-    return fi_x / (q * (2.0 * q + 1.0)) + (2.0 * q - 1.0) / q * fj_x +
-           (1.0 - 2.0 * q) / (1.0 + 2.0 * q) * fj_xm1;
-  return fi_x / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * fj_x;
+    return fi_x / (q * (PR(2.0) * q + PR(1.0))) + (PR(2.0) * q - PR(1.0)) / q * fj_x +
+           (PR(1.0) - PR(2.0) * q) / (PR(1.0) + PR(2.0) * q) * fj_xm1;
+  return fi_x / (PR(2.0) * q) + (PR(2.0) * q - PR(1.0)) / (PR(2.0) * q) * fj_x;
+}
+
+double orc_bfl(double q, double fi_x, double fi_xm1, double fi_xm2, double fj_x,
+               double fj_xm1, int avail1, int avail2) {
+  return (double)bfl(q, fi_x, fi_xm1, fi_xm2, fj_x, fj_xm1, avail1, avail2);
 }
 
 /* Inward unit normal of box face: 0 x=0, 1 x=nx-1, 2 y=0, 3 y=ny-1, 4 z=0, 5 z=nz-1. */
@@ -245,55 +277,69 @@ static void face_normal(int face, int *n) {
  * than Eq. e_i, so it is applied through direction vectors; its 1/6 terms
  * carry the wall density rho_w, which the momentum balance requires.
  * Fills the unknowns of f19 in place and returns rho_w. */
-static double zouhe_dev(double *d, int face, int kind, const double *u_w_in, double rho_w) {
+static preal zouhe_dev(preal *d, int face, int kind, const double *u_w_in, preal rho_w) {
   int n[3];
   face_normal(face, n);
   /* with d = f - w: sum_{e.n=0} f + 2 sum_{e.n=-1} f = 1 + D0 + 2 Dout, since
-   * the rest weights of those sets add up to 2/3 and 1/6 */
-  double D0 = 0.0, Dout = 0.0;
+   * the rest weights of those sets add up to 2/3 and 1/6 (in the
+   * measurement build ORC_FULL_POP, d holds f itself and the 1 is dropped) */
+#ifdef ORC_FULL_POP
+  const preal one = PR(0.0);
+#else
+  const preal one = PR(1.0);
+#endif
+  preal D0 = PR(0.0), Dout = PR(0.0);
   for (int j = 0; j < 19; j++) {
     int en = E[j][0] * n[0] + E[j][1] * n[1] + E[j][2] * n[2];
     if (en == 0) D0 += d[j];
     else if (en == -1) Dout += d[j];
   }
-  double uw[3];
+  preal uw[3];
   if (kind == 0) {
     for (int a = 0; a < 3; a++) uw[a] = u_w_in[a];
-    double un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
-    rho_w = (1.0 + D0 + 2.0 * Dout) / (1.0 - un);
+    preal un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
+    rho_w = (one + D0 + PR(2.0) * Dout) / (PR(1.0) - un);
   } else {
-    double un = (rho_w - 1.0 - D0 - 2.0 * Dout) / rho_w;
+    preal un = (rho_w - one - D0 - PR(2.0) * Dout) / rho_w;
     for (int a = 0; a < 3; a++) uw[a] = un * n[a];
   }
-  double un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
+  preal un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
   for (int j = 0; j < 19; j++) {
     int en = E[j][0] * n[0] + E[j][1] * n[1] + E[j][2] * n[2];
     if (en != 1) continue;
     int jb = opposite(j);
     int t[3] = {E[j][0] - n[0], E[j][1] - n[1], E[j][2] - n[2]};
     if (t[0] == 0 && t[1] == 0 && t[2] == 0) {
-      d[j] = d[jb] + rho_w / 3.0 * un;
+      d[j] = d[jb] + rho_w / PR(3.0) * un;
     } else {
-      double ut = uw[0] * t[0] + uw[1] * t[1] + uw[2] * t[2];
+      preal ut = uw[0] * t[0] + uw[1] * t[1] + uw[2] * t[2];
       /* the rest weights cancel in this sum (symmetric pairs) */
-      double Nt = 0.0;
+      preal Nt = PR(0.0);
       for (int k = 0; k < 19; k++) {
         int ek = E[k][0] * n[0] + E[k][1] * n[1] + E[k][2] * n[2];
         if (ek == 0) Nt += d[k] * (E[k][0] * t[0] + E[k][1] * t[1] + E[k][2] * t[2]);
       }
-      Nt = 0.5 * Nt - rho_w / 3.0 * ut;
-      d[j] = d[jb] + rho_w / 6.0 * (un + ut) - Nt;
+      Nt = PR(0.5) * Nt - rho_w / PR(3.0) * ut;
+      d[j] = d[jb] + rho_w / PR(6.0) * (un + ut) - Nt;
     }
   }
   return rho_w;
 }
 
-/* The same condition on full populations f (public entry). */
+/* The same condition on full populations f (public entry, plain build). */
 double orc_zouhe(double *f, int face, int kind, const double *u_w_in, double rho_w) {
-  double d[19];
+  preal d[19];
+#ifdef ORC_FULL_POP
+  for (int j = 0; j < 19; j++) d[j] = f[j];
+#else
   for (int j = 0; j < 19; j++) d[j] = f[j] - Wt[j];
-  double r = zouhe_dev(d, face, kind, u_w_in, rho_w);
-  for (int j = 0; j < 19; j++) f[j] = Wt[j] + d[j];
+#endif
+  double r = (double)zouhe_dev(d, face, kind, u_w_in, rho_w);
+#ifdef ORC_FULL_POP
+  for (int j = 0; j < 19; j++) f[j] = (double)d[j];
+#else
+  for (int j = 0; j < 19; j++) f[j] = (double)(Wt[j] + d[j]);
+#endif
   return r;
 }
 
@@ -346,11 +392,11 @@ orc_sim *orc_create(int nx, int ny, int nz, const int32_t *periodic, double tau,
   s->lk_dir = (unsigned char *)malloc(n_links > 0 ? n_links : 1);
   s->lk_q = (double *)malloc(sizeof(double) * (n_links > 0 ? n_links : 1));
   s->uin = (double *)calloc(N * 3, sizeof(double));
-  s->fs = (double *)malloc(sizeof(double) * N * 19);
-  s->f = (double *)malloc(sizeof(double) * N * 19);
-  s->rho = (double *)calloc(N, sizeof(double));
+  s->fs = (preal *)malloc(sizeof(preal) * N * 19);
+  s->f = (preal *)malloc(sizeof(preal) * N * 19);
+  s->rho = (preal *)calloc(N, sizeof(preal));
   s->u = (double *)calloc(N * 3, sizeof(double));
-  s->mom = (double *)calloc(N * 3, sizeof(double));
+  s->mom = (preal *)calloc(N * 3, sizeof(preal));
   s->ustar = (double *)calloc(N * 3, sizeof(double));
   s->fib = (double *)calloc(N * 3, sizeof(double));
   if (!s->fs || !s->f || !s->rho || !s->u || !s->ustar || !s->fib || !s->mom) {
@@ -425,17 +471,17 @@ orc_sim *orc_create(int nx, int ny, int nz, const int32_t *periodic, double tau,
   }
   /* initial state: f = f^eq(rho0, u0) on non-solid nodes (stored as f - w) */
   for (long n = 0; n < N; n++) {
-    double r = init_rho ? init_rho[n] : 1.0;
-    double uu[3] = {0, 0, 0};
+    preal r = init_rho ? init_rho[n] : 1.0;
+    preal uu[3] = {0, 0, 0};
     if (init_u)
       for (int a = 0; a < 3; a++) uu[a] = init_u[(long)a * N + n];
     if (s->type[n] == T_SOLID) {
       for (int i = 0; i < 19; i++) s->fs[19 * n + i] = 0.0;
       continue;
     }
-    for (int i = 0; i < 19; i++) s->fs[19 * n + i] = feq_dev_i(i, r, uu);
+    for (int i = 0; i < 19; i++) s->fs[19 * n + i] = feq_store_i(i, r, uu);
     s->rho[n] = r;
-    for (int a = 0; a < 3; a++) s->u[3 * n + a] = uu[a];
+    for (int a = 0; a < 3; a++) s->u[3 * n + a] = (double)uu[a];
   }
   return s;
 }
@@ -784,8 +830,8 @@ void orc_ib_spread(const orc_sim *s, int64_t n, const double *pts, const double 
 /* ------------------------------------------------------------ the step */
 /* S1 + S2 + S3 for one node: streamed populations into s->f, moments. */
 static void stream_node(orc_sim *s, long n) {
-  double *f = s->f + 19 * n;
-  const double *fs = s->fs;
+  preal *f = s->f + 19 * n;
+  const preal *fs = s->fs;
   int x, y, z;
   coords(s, n, &x, &y, &z);
   f[0] = fs[19 * n + 0];
@@ -795,52 +841,56 @@ static void stream_node(orc_sim *s, long n) {
       f[j] = 0.0; /* unknown: filled by the open-face condition below */
     } else if (s->type[src] == T_SOLID) {
       int i = opposite(j); /* x + e_i = src is solid */
-      double q = find_q(s, n, i);
+      preal q = find_q(s, n, i);
       long a1 = neighbour(s, x, y, z, -E[i][0], -E[i][1], -E[i][2]);
       long a2 = neighbour(s, x, y, z, -2 * E[i][0], -2 * E[i][1], -2 * E[i][2]);
       int av1 = a1 >= 0 && s->type[a1] != T_SOLID;
       int av2 = a2 >= 0 && s->type[a2] != T_SOLID;
-      f[j] = orc_bfl(q, fs[19 * n + i], av1 ? fs[19 * a1 + i] : 0.0, av2 ? fs[19 * a2 + i] : 0.0,
-                     fs[19 * n + j], av1 ? fs[19 * a1 + j] : 0.0, av1, av2);
+      f[j] = bfl(q, fs[19 * n + i], av1 ? fs[19 * a1 + i] : PR(0.0), av2 ? fs[19 * a2 + i] : PR(0.0),
+                 fs[19 * n + j], av1 ? fs[19 * a1 + j] : PR(0.0), av1, av2);
     } else {
       f[j] = fs[19 * src + j];
     }
   }
   if (s->type[n] == T_INLET || s->type[n] == T_OUTLET) {
     int face = open_face(s, n);
-    if (s->type[n] == T_INLET) zouhe_dev(f, face, 0, s->uin + 3 * n, 0.0);
+    if (s->type[n] == T_INLET) zouhe_dev(f, face, 0, s->uin + 3 * n, PR(0.0));
     else zouhe_dev(f, face, 1, NULL, s->rho_out);
   }
   /* moments of f = w + d: the weights add up to 1 and carry no momentum */
-  double dsum = 0.0, m[3] = {0, 0, 0};
+  preal dsum = PR(0.0), m[3] = {0, 0, 0};
   for (int i = 0; i < 19; i++) {
     dsum += f[i];
     for (int a = 0; a < 3; a++) m[a] += f[i] * E[i][a];
   }
-  double rho = 1.0 + dsum;
+#ifdef ORC_FULL_POP
+  preal rho = dsum;
+#else
+  preal rho = PR(1.0) + dsum;
+#endif
   s->rho[n] = rho;
   for (int a = 0; a < 3; a++) {
     s->mom[3 * n + a] = m[a];
-    s->ustar[3 * n + a] = m[a] / rho;
+    s->ustar[3 * n + a] = (double)(m[a] / rho);
   }
 }
 
 /* S5 for one node: BGK collision with the forcing term. */
 static int collide_node(orc_sim *s, long n) {
-  double *f = s->f + 19 * n;
-  double rho = s->rho[n];
-  double F[3], u[3];
+  preal *f = s->f + 19 * n;
+  preal rho = s->rho[n];
+  preal F[3], u[3];
   for (int a = 0; a < 3; a++) {
-    F[a] = s->g[a] + s->fib[3 * n + a];
+    F[a] = (preal)s->g[a] + s->fib[3 * n + a];
     /* rho u = sum f e + (dt/2) f_ib */
-    u[a] = (s->mom[3 * n + a] + 0.5 * F[a]) / rho;
+    u[a] = (s->mom[3 * n + a] + PR(0.5) * F[a]) / rho;
   }
   for (int i = 0; i < 19; i++) {
-    double v = f[i] - (f[i] - feq_dev_i(i, rho, u)) / s->tau + guo_i(i, s->tau, u, F);
+    preal v = f[i] - (f[i] - feq_store_i(i, rho, u)) / s->tau + guo_i(i, s->tau, u, F);
 #ifdef ORC_STORE_F32
     /* measurement build only: the state rounded to FP32 at every store, to
      * gauge how far FP32 storage alone moves a trajectory */
-    v = (double)(float)v;
+    v = (preal)(float)v;
 #endif
 #ifdef ORC_STORE_F16
     /* measurement build only: the state rounded to binary16 (11 significant
@@ -854,8 +904,9 @@ static int collide_node(orc_sim *s, long n) {
 #endif
     s->fs[19 * n + i] = v;
   }
-  for (int a = 0; a < 3; a++) s->u[3 * n + a] = u[a];
-  double uu = dot(u, u);
+  double ud[3];
+  for (int a = 0; a < 3; a++) s->u[3 * n + a] = ud[a] = (double)u[a];
+  double uu = dot(ud, ud);
   return !(uu <= 0.09) || !(rho == rho);
 }
 
@@ -1222,6 +1273,21 @@ static void move_rigid(body_t *B, const double *Fv) {
   }
 }
 
+/* Test hooks of the rigid-body update (they change nothing in the step). */
+void orc_body_inertia(const orc_sim *s, int id, double *I9) {
+  memcpy(I9, s->bodies[id].Ibody, sizeof(double) * 9);
+}
+
+void orc_rodrigues(const double *phi, double *R9) { rodrigues(phi, R9); }
+
+/* One S8 update of rigid body id driven by the given vertex forces [nv][3]
+ * (in place of the hydrodynamic and repulsion forces of a step). */
+int orc_move_rigid(orc_sim *s, int id, const double *Fv) {
+  if (!s || id < 0 || id >= s->nbody || !s->bodies[id].rigid) return ORC_E_INVAL;
+  move_rigid(&s->bodies[id], Fv);
+  return ORC_OK;
+}
+
 static int one_step(orc_sim *s) {
   long N = s->N;
   int nthr = orc_threads();
@@ -1291,16 +1357,25 @@ int orc_mls_singular_count(const orc_sim *s) { return s->mls_singular; }
 void orc_get_fields(const orc_sim *s, double *rho, double *u) {
   for (long n = 0; n < s->N; n++) {
     int solid = s->type[n] == T_SOLID;
-    if (rho) rho[n] = solid ? 0.0 : s->rho[n];
+    if (rho) rho[n] = solid ? 0.0 : (double)s->rho[n];
     if (u)
       for (int a = 0; a < 3; a++) u[(long)a * s->N + n] = solid ? 0.0 : s->u[3 * n + a];
   }
 }
 
+/* The stored value of population i at node n as a full population f_i. */
+static preal full_pop(const orc_sim *s, long n, int i) {
+#ifdef ORC_FULL_POP
+  return s->fs[19 * n + i];
+#else
+  return Wt[i] + s->fs[19 * n + i];
+#endif
+}
+
 void orc_get_populations(const orc_sim *s, double *f) {
   for (long n = 0; n < s->N; n++)
     for (int i = 0; i < 19; i++)
-      f[(long)i * s->N + n] = s->type[n] == T_SOLID ? 0.0 : Wt[i] + s->fs[19 * n + i];
+      f[(long)i * s->N + n] = s->type[n] == T_SOLID ? 0.0 : (double)full_pop(s, n, i);
 }
 
 /* The inverse of orc_get_populations: the stored post-collision
@@ -1308,7 +1383,13 @@ void orc_get_populations(const orc_sim *s, double *f) {
 void orc_set_populations(orc_sim *s, const double *f) {
   for (long n = 0; n < s->N; n++)
     if (s->type[n] != T_SOLID)
-      for (int i = 0; i < 19; i++) s->fs[19 * n + i] = f[(long)i * s->N + n] - Wt[i];
+      for (int i = 0; i < 19; i++) {
+#ifdef ORC_FULL_POP
+        s->fs[19 * n + i] = f[(long)i * s->N + n];
+#else
+        s->fs[19 * n + i] = f[(long)i * s->N + n] - Wt[i];
+#endif
+      }
 }
 
 /* The populations f_i of the listed nodes only: f[i * n + k] for node
@@ -1316,7 +1397,7 @@ void orc_set_populations(orc_sim *s, const double *f) {
 void orc_get_populations_at(const orc_sim *s, long n, const long *nodes, double *f) {
   for (long k = 0; k < n; k++)
     for (int i = 0; i < 19; i++)
-      f[(long)i * n + k] = s->type[nodes[k]] == T_SOLID ? 0.0 : Wt[i] + s->fs[19 * nodes[k] + i];
+      f[(long)i * n + k] = s->type[nodes[k]] == T_SOLID ? 0.0 : (double)full_pop(s, nodes[k], i);
 }
 
 void orc_get_force(const orc_sim *s, double *fib) {

@@ -90,6 +90,15 @@ void orc_body_hydro(const orc_sim *s, int id, double *Fface);
  * the hydrodynamic force plus the inter-body repulsion. */
 void orc_body_fext(const orc_sim *s, int id, double *Fface);
 
+/* Pins of the rigid-body update: the body-frame inertia tensor (about the
+ * centre of mass, orientation at creation) of body id; the rotation matrix
+ * of a rotation vector (Rodrigues); one rigid-body update of body id with
+ * given vertex forces [nv*3] in place of the step's external forces
+ * (ORC_E_INVAL for a soft body). */
+void orc_body_inertia(const orc_sim *s, int id, double *I9);
+void orc_rodrigues(const double *phi, double *R9);
+int orc_move_rigid(orc_sim *s, int id, const double *Fv);
+
 #ifdef __cplusplus
 }
 #endif

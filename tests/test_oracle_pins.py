@@ -599,3 +599,204 @@ def test_set_populations_is_the_inverse_of_get():
     a.step(5)
     b.step(5)
     assert np.abs(b.populations() - a.populations()).max() <= 1e-15
+
+
+# ------------------------------------------------ rigid-body rotation (S8)
+def _box_mesh(a, b, c, center, Q=np.eye(3)):
+    """Closed triangle mesh of an a x b x c box (8 corners, 12 faces, outward
+    counter-clockwise), its edges along the columns of the rotation Q."""
+    corners = np.array([[(i - 0.5) * a, (j - 0.5) * b, (k - 0.5) * c]
+                        for k in (0, 1) for j in (0, 1) for i in (0, 1)])
+    quads = [(0, 2, 6, 4), (1, 3, 7, 5), (0, 1, 5, 4), (2, 3, 7, 6), (0, 1, 3, 2), (4, 5, 7, 6)]
+    tris = []
+    for q in quads:
+        for t in ((q[0], q[1], q[2]), (q[0], q[2], q[3])):
+            p = corners[list(t)]
+            if np.dot(np.cross(p[1] - p[0], p[2] - p[0]), p.mean(0)) < 0:
+                t = (t[0], t[2], t[1])
+            tris.append(t)
+    return corners @ Q.T + np.asarray(center), np.array(tris, dtype=np.int32)
+
+
+def _rot(axis, angle):
+    from scipy.spatial.transform import Rotation
+    axis = np.asarray(axis, float)
+    return Rotation.from_rotvec(angle * axis / np.linalg.norm(axis)).as_matrix()
+
+
+def _rigid_sim(X, F, rho_ratio=1.3):
+    d = synth.periodic_box(24, 24, 24)
+    body = synth.Body(X, F, rigid=True, ca=0.05, eb=0.0, rho_ratio=rho_ratio, r_ref=2.0, u_ref=0.02)
+    return oracle.OracleSim(d, tau=0.8, u_max=0.02, bodies=[body], threads=1)
+
+
+@pytest.mark.parametrize("rotated", [False, True])
+def test_rigid_inertia_exact_on_box_meshes(rotated):
+    """The inertia of the uniform solid inside a closed box mesh is the
+    textbook m (b^2 + c^2) / 12 etc. along its edges, whatever its position
+    and orientation.  The box sits away from the origin and is anisotropic:
+    a missing shift to the centre of mass, the second-moment matrix C used
+    in place of tr(C) 1 - C, a wrong 1/20 tetrahedron factor or a sign error
+    in the products of inertia (the rotated case) each fail."""
+    a, b, c, rr = 3.0, 2.0, 1.2, 1.3
+    Q = _rot((0.3, -0.5, 0.8), 0.9) if rotated else np.eye(3)
+    X, F = _box_mesh(a, b, c, (10.3, 11.7, 12.2), Q)
+    s = _rigid_sim(X, F, rr)
+    m = rr * a * b * c
+    assert abs(s.body_diag(0)["mass"] - m) < 1e-12 * m
+    I_ref = Q @ np.diag([m * (b * b + c * c) / 12, m * (a * a + c * c) / 12, m * (a * a + b * b) / 12]) @ Q.T
+    assert np.abs(s.body_inertia(0) - I_ref).max() < 1e-12 * np.abs(I_ref).max()
+    assert np.abs(s.body_diag(0)["xc"] - [10.3, 11.7, 12.2]).max() < 1e-12
+
+
+def test_rigid_inertia_of_refined_icospheres_tends_to_the_solid_sphere():
+    """For icospheres of radius r the mesh inertia is isotropic and I / (m r^2)
+    approaches the solid sphere's 2/5 as the mesh is refined, with the error
+    shrinking about four times per subdivision (second order in the edge)."""
+    r = 5.0
+    errs = []
+    for sub in range(1, 5):
+        X, F = synth.icosphere(sub, r, (11.1, 12.3, 11.6), tilt=True)
+        s = _rigid_sim(X, F)
+        I = s.body_inertia(0)
+        m = s.body_diag(0)["mass"]
+        assert np.abs(I - np.diag(np.diag(I))).max() < 1e-12 * I[0, 0]
+        assert np.ptp(np.diag(I)) < 1e-3 * I[0, 0] / 4 ** sub
+        errs.append(abs(I[0, 0] / (m * r * r) - 0.4))
+    assert errs[-1] < 2e-3
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.0 < e0 / e1 < 5.0
+
+
+def test_rodrigues_matches_scipy():
+    """The oracle's rotation matrix of a rotation vector equals scipy's
+    (a transposed matrix, a sign error in the cross-product term or a wrong
+    1 - cos term would each fail), including tiny and large angles."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(7)
+    vecs = [rng.normal(size=3) * s for s in (1e-9, 1e-4, 0.05, 0.7, 2.0, 3.1)]
+    vecs += [np.array([np.pi, 0, 0]), np.array([0.0, 0.0, 0.0])]
+    for phi in vecs:
+        R = oracle.rodrigues(phi)
+        assert np.abs(R - Rotation.from_rotvec(phi).as_matrix()).max() < 2e-15
+        assert np.abs(R @ R.T - np.eye(3)).max() < 2e-15 and np.linalg.det(R) > 0
+
+
+@pytest.mark.parametrize("rotated", [False, True])
+def test_rigid_second_order_backward_recurrence(rotated):
+    """Constant force f on every corner and a torque about a principal axis e
+    (corner forces s e x (x_v - x_c), the same moment at every step) drive a
+    box from rest.  The second-order backward update
+    u^{n+1} = 2/3 (2 u^n - u^{n-1}/2 + F/m) from u^0 = u^{-1} = 0 has the
+    closed form u^n = (F/m)(n - 1/2 + 3^{-n}/2), and likewise omega^n with
+    M/I_e; the centre moves by the sum of the u^k and the body turns about e
+    by the sum of the |omega^k| (rotations about one axis commute).  A sign
+    slip in the angular update, a transposed rotation (turning the wrong
+    way), a wrong inertia or wrong history weights each fail."""
+    a, b, c, rr = 3.0, 2.0, 1.2, 1.3
+    Q = _rot((0.3, -0.5, 0.8), 0.9) if rotated else np.eye(3)
+    c0 = np.array([10.3, 11.7, 12.2])
+    X, F = _box_mesh(a, b, c, c0, Q)
+    s = _rigid_sim(X, F, rr)
+    m = rr * a * b * c
+    e = Q[:, 2]                               # principal axis of I_e = m (a^2 + b^2) / 12
+    I_e = m * (a * a + b * b) / 12
+    f = np.array([2e-4, -1e-4, 3e-4])
+    sm = 3e-4
+    M = sm * 2 * (a * a + b * b)              # sum over corners of r x (e x r) along e
+    xc_ref = c0.copy()
+    theta = 0.0
+    for n in range(1, 13):
+        x, _ = s.body(0)
+        xc = s.body_diag(0)["xc"]
+        Fv = f + sm * np.cross(e, x - xc)
+        assert s.move_rigid(0, Fv) == 0
+        k = n - 0.5 + 0.5 * 3.0 ** (-n)
+        u_ref = 8 * f / m * k
+        w_ref = M / I_e * k * e
+        dg = s.body_diag(0)
+        assert np.abs(dg["u"] - u_ref).max() < 1e-12 * np.abs(u_ref).max()
+        assert np.abs(dg["omega"] - w_ref).max() < 1e-12 * np.abs(w_ref).max()
+        xc_ref += u_ref
+        theta += np.linalg.norm(w_ref)
+        assert np.abs(dg["xc"] - xc_ref).max() < 1e-12
+        x, v = s.body(0)
+        x_ref = xc_ref + (X - c0) @ _rot(e, theta).T
+        assert np.abs(x - x_ref).max() < 1e-12
+        # vertex velocities are the rigid motion's
+        assert np.abs(v - (u_ref + np.cross(w_ref, x - xc_ref))).max() < 1e-13
+    assert theta > 0.05                       # the box really turned
+
+
+def test_rigid_rotations_compose_in_the_world_frame():
+    """A cube (isotropic inertia m a^2 / 6 in any orientation) driven by
+    moments about changing axes: each step's rotation Rodrigues(omega^{n+1})
+    acts in the world frame after the previous ones, R <- R(omega) R.  The
+    reference composes scipy rotations in that order; composing in the body
+    frame (R R(omega)) or transposing either factor fails, since rotations
+    about different axes do not commute."""
+    from scipy.spatial.transform import Rotation
+    a, rr = 2.5, 1.2
+    c0 = np.array([11.2, 12.4, 11.8])
+    X, F = _box_mesh(a, a, a, c0, _rot((1.0, 2.0, -0.5), 0.4))
+    s = _rigid_sim(X, F, rr)
+    m = rr * a ** 3
+    I = m * a * a / 6
+    axes = [np.array(v, float) / np.linalg.norm(v) for v in
+            ((1, 0, 0), (1, 0, 0), (0, 1, 0), (0, 1, 0), (0, 0.6, 0.8), (1, 1, 0), (0, 0, 1), (1, -1, 1))]
+    sm = 5e-3
+    w, wprev = np.zeros(3), np.zeros(3)
+    R = Rotation.identity()
+    for d in axes:
+        x, _ = s.body(0)
+        xc = s.body_diag(0)["xc"]
+        assert s.move_rigid(0, sm * np.cross(d, x - xc)) == 0
+        M = 4 * sm * a * a * d                # sum over corners of r x (d x r)
+        w, wprev = 2.0 / 3.0 * (2 * w - 0.5 * wprev + M / I), w
+        R = Rotation.from_rotvec(w) * R       # world-frame increment after the previous ones
+        dg = s.body_diag(0)
+        assert np.abs(dg["omega"] - w).max() < 1e-12 * np.abs(w).max()
+        x, _ = s.body(0)
+        assert np.abs(x - (c0 + (X - c0) @ R.as_matrix().T)).max() < 1e-12
+    assert R.magnitude() > 0.1
+
+
+# ------------------------------------------ storage form of the populations
+_STORAGE_RUN = '''
+import sys
+import numpy as np
+sys.path.insert(0, {root!r})
+import oracle, synth
+if sys.argv[1]:
+    oracle.use_library(sys.argv[1])
+w = synth.tiny_bifurcation(precision="f64", n_bodies=0)
+s = oracle.from_workload(w, with_bodies=False, threads=2)
+assert s.step(600) == 0
+np.save(sys.argv[2], s.fields()[1])
+'''
+
+
+def test_deviation_storage_is_nearer_the_exact_trajectory(tmp_path):
+    """The oracle stores populations as deviations f - w; storing full
+    populations instead is the same map in exact arithmetic.  Against a
+    long-double run of the same source (rounding ~2^-64) on a small
+    bifurcation after 600 steps, the double oracle stays within 3e-14 of the
+    velocity scale, while full-population storage drifts more than ten times
+    further: its rounding of values near w_i has the same sign step after
+    step.  (The full-size workload: tests/golden/storage_form.json, written by
+    make_storage_form.py: 1.3e-14 against 1.1e-12 after 2000 steps.)"""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "run.py"
+    script.write_text(_STORAGE_RUN.format(root=root))
+    res = {}
+    for b in ("ldouble", "fullpop", "plain"):
+        lib = "" if b == "plain" else oracle.build(variant=b, path=str(tmp_path / f"{b}.so"))
+        subprocess.run([sys.executable, str(script), lib, str(tmp_path / f"{b}.npy")], check=True)
+        res[b] = np.load(tmp_path / f"{b}.npy")
+    fl = synth.tiny_bifurcation(precision="f64", n_bodies=0).domain.node_type != synth.SOLID
+    ref = res["ldouble"][:, fl]
+    e = {b: np.abs(res[b][:, fl] - ref).max() / np.abs(ref).max() for b in ("plain", "fullpop")}
+    assert e["plain"] < 3e-14, e
+    assert e["fullpop"] > 10 * e["plain"], e
