@@ -207,34 +207,74 @@ lbm_status ib_spread(lbm_ctx *ctx, int64_t n, const double *d_pts, const double 
 lbm_status ib_spread_noalloc(lbm_ctx *ctx, int64_t n, const double *d_pts, const double *d_F,
                              const double *d_c, double *d_fib);
 
-/* Discrete adjoint of the fluid step (Eqs. evoleq, forcing, bbouzidi,
- * extbound taken as one map g^k -> g^{k+1} of the post-collision deviations
- * g = f - w_i).  For the n_steps-step trajectory that starts from the
- * context's current state g^0 and the objective
+/* Discrete adjoint of the coupled step (Eqs. evoleq, forcing, bbouzidi,
+ * extbound for the fluid; with a soft body, the direct forcing, spreading
+ * and MLS interpolation (Eqs. uLag, l2norm, intKernel, bodyforce), the
+ * membrane forces (Eqs. strainFor, bendFor, volFor), the probe tractions
+ * (Eqs. hydroForP, hydroForNu) and the Verlet update (Eqs. verletPos,
+ * verletVel, verletPosC) taken with the step as one map of the state (g, P,
+ * Q, V): post-collision deviations g = f - w_i, vertex positions x^n and
+ * x^{n-1}, vertex velocities).  For the n_steps-step trajectory that starts
+ * from the context's current state and the objective
  *   J = <lambda, g^n> + sum_{t=1..n} <w, g^t>
  * (lambda, w: [19][N] FP64 device arrays, N = nx ny nz, x fastest; w may be
  * NULL), it returns in d_lambda (overwritten) dJ/dg^0 and in d_grad (5
  * doubles, device) dJ/ds, dJ/dFx, dJ/dFy, dJ/dFz, dJ/dtau: s scales the wall
  * velocity of every velocity-face (inlet) node, F is the uniform body force,
- * tau the relaxation time (Eq. evoleq; the viscosity), all held fixed over
- * the n steps, derivatives at the context's own values (s = 1).  The
- * trajectory is recomputed in the context's precision (its storage and
- * arithmetic, as lbm_step runs it); the adjoint is FP64: the transposes of
- * the collision and of Zou-He written out at each node's state, exact
- * transposes of the streaming and bounce-back (for an FP32 or FP16S
- * context, the derivative of the step in exact arithmetic at its states).
- * Entries of w and lambda at solid nodes are ignored; dJ/dg^0 is zero
- * there.  checkpoint_every (K) >= 1; d_w may be NULL; every other pointer
- * is required (else LBM_E_INVAL).
+ * tau the relaxation time (Eq. evoleq; the viscosity, also in the probes'
+ * stress; the membrane modulus k_s0 held fixed), all held fixed over the n
+ * steps, derivatives at the context's current values.  The trajectory is
+ * recomputed in the context's precision (its storage and arithmetic, as
+ * lbm_step runs it); the adjoint is FP64: the transposes of the collision
+ * and of Zou-He written out at each node's state, exact transposes of the
+ * streaming and bounce-back, and, with a body, the transposes of the IB
+ * operations including the derivatives of the MLS weights, face areas and
+ * normals with respect to the moving points (for an FP32 or FP16S context,
+ * the derivative of the step in exact arithmetic at its states).  Entries of
+ * w and lambda at solid nodes are ignored; dJ/dg^0 is zero there.
+ * checkpoint_every (K) >= 1; d_w may be NULL; every other pointer is
+ * required (else LBM_E_INVAL).
  * Checkpoints: the state is kept every checkpoint_every steps and each
  * segment is recomputed once in the reverse sweep (device memory: 6 FP64
  * fields and ceil(n/K) + max(K, 2) states of 19 x plane values, plus K x 19
- * doubles per boundary record, allocated and freed by the call; LBM_E_NOMEM
- * if it does not fit).  The context's state and step count are not changed.
- * Contexts without bodies only (else LBM_E_UNSUPPORTED).
- * Synchronises the context's stream. */
+ * doubles per boundary record; with a body, eleven FP64 [Np] fields, a
+ * state and 9 nv doubles per checkpoint and per step of a segment;
+ * allocated and freed by the call; LBM_E_NOMEM if it does not fit).  The
+ * context's state and step count are not changed.  Contexts with rigid or
+ * fixed bodies, or with more than one body (the repulsion), give
+ * LBM_E_UNSUPPORTED; a trajectory on which a capsule is damaged or the flow
+ * becomes unstable gives LBM_E_DAMAGED / LBM_E_UNSTABLE.  Synchronises the
+ * context's stream. */
 lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t n_steps, int32_t checkpoint_every,
                             const double *d_w, double *d_lambda, double *d_grad);
+
+/* The same sweep with the capsule objective of the differentiation form and
+ * the membrane-stiffness gradient: J adds taylor_weight times the sum over
+ * the n steps of the Taylor deformation D = (sqrt(l1) - sqrt(l3)) /
+ * (sqrt(l1) + sqrt(l3)) of body taylor_body after each step (l1, l3 the
+ * largest and smallest eigenvalues of the second-moment tensor of its vertex
+ * positions about their mean).  d_grad takes 6 doubles: the 5 of
+ * lbm_adjoint_step, then dJ/dkappa, kappa scaling the membrane modulus k_s0
+ * of every body (stretching, bending and the default volume constant follow
+ * it; Eqs. strainFor, bendFor, volFor), at the context's current scale
+ * (lbm_set_scales; dJ/dk_s0 = dJ/dkappa / k_s0).  d_body_grad (device,
+ * [3][nv][3] over all vertices, or NULL): dJ/dx^0, dJ/dx^{-1} and dJ/du_v^0
+ * of the initial body state.  J (host, 2 doubles, or NULL): the value of
+ * <lambda, g^n> + sum_t <w, g^t>, and the unweighted sum over the steps of
+ * the Taylor deformation (0 without bodies), from the recomputed trajectory.
+ * taylor_body is ignored when taylor_weight is 0. */
+lbm_status lbm_adjoint_run(lbm_ctx *ctx, int32_t n_steps, int32_t checkpoint_every, const double *d_w,
+                           double taylor_weight, int32_t taylor_body, double *d_lambda, double *d_grad,
+                           double *d_body_grad, double *J);
+
+/* Parameter scales of the problem, relative to the context as created: every
+ * inlet (velocity-face) wall velocity times inlet_scale (Eq. extbound), and
+ * the membrane modulus k_s0 of every body times stiffness_scale (> 0; the
+ * stretching and bending constants and the default volume constant follow;
+ * the capillary number becomes Ca / stiffness_scale).  Applies to the steps
+ * enqueued after the call; the adjoint's parameter derivatives are taken at
+ * these values.  Synchronises the context's stream. */
+lbm_status lbm_set_scales(lbm_ctx *ctx, double inlet_scale, double stiffness_scale);
 
 /* Checkpoint / restart of the full state (populations, force field, body
  * state) to a binary file; lbm_load requires a context created with the

@@ -24,7 +24,8 @@ PRECISIONS = {"f64": 0, "f32": 1, "f16s": 2}
 EXPORTS = ["lbm_create", "lbm_destroy", "lbm_last_error", "lbm_info", "lbm_add_body", "lbm_step",
            "lbm_sync", "lbm_get_fields", "lbm_get_populations", "lbm_set_populations", "lbm_get_force",
            "lbm_get_body",
-           "ib_interpolate", "ib_spread", "ib_spread_noalloc", "lbm_adjoint_step", "lbm_save", "lbm_load",
+           "ib_interpolate", "ib_spread", "ib_spread_noalloc", "lbm_adjoint_step", "lbm_adjoint_run",
+           "lbm_set_scales", "lbm_save", "lbm_load",
            "lbm_time_fluid_kernel", "lbm_set_graph", "lbm_set_launch_shape", "lbm_diagnostics",
            "lbm_batch_create",
            "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_step", "lbm_batch_tune",
@@ -120,6 +121,10 @@ def load_library():
     L.ib_spread_noalloc.argtypes = [vp, i64, vp, vp, vp, vp]
     L.lbm_adjoint_step.restype = st
     L.lbm_adjoint_step.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.lbm_adjoint_run.restype = st
+    L.lbm_adjoint_run.argtypes = [vp, i32, i32, vp, C.c_double, i32, vp, vp, vp, dp]
+    L.lbm_set_scales.restype = st
+    L.lbm_set_scales.argtypes = [vp, C.c_double, C.c_double]
     L.lbm_save.restype = st
     L.lbm_save.argtypes = [vp, C.c_char_p]
     L.lbm_load.restype = st
@@ -361,6 +366,33 @@ class Lattice:
                                                     _ptr(wd), _ptr(lam), _ptr(grad)))
         self.stream.synchronize()
         return lam, grad
+
+    def adjoint_run(self, n_steps, lam=None, w=None, taylor_weight=0.0, taylor_body=0,
+                    checkpoint_every=100, body_grad=False):
+        """lbm_adjoint_run: the gradient of J = <lam, g^n> + sum_t <w, g^t> +
+        taylor_weight * sum_t D_T(body) over the n_steps-step trajectory from
+        the current state.  Returns (dJ/dg^0 [19][N], [dJ/ds, dJ/dF (3),
+        dJ/dtau, dJ/dkappa], dJ/d(x^0, x^{-1}, u_v^0) [3][nv][3] or None,
+        (J's population part, the sum of D_T)).  The state is not changed."""
+        t = self._torch
+        if lam is None:
+            lam = t.zeros(19, self.N, dtype=t.float64, device=self.device)
+        lam = lam.to(self.device, t.float64).reshape(19, self.N).clone()
+        wd = None if w is None else w.to(self.device, t.float64).reshape(19, self.N).contiguous()
+        grad = self._empty(6)
+        nv = sum(b[0] for b in self.bodies)
+        bg = self._empty(3, nv, 3) if body_grad else None
+        J = (C.c_double * 2)()
+        self._check(load_library().lbm_adjoint_run(self._h, int(n_steps), int(checkpoint_every), _ptr(wd),
+                                                   float(taylor_weight), int(taylor_body), _ptr(lam),
+                                                   _ptr(grad), _ptr(bg), J))
+        self.stream.synchronize()
+        return lam, grad, bg, (J[0], J[1])
+
+    def set_scales(self, inlet=1.0, stiffness=1.0):
+        """lbm_set_scales: inlet wall velocities times `inlet`, membrane
+        moduli times `stiffness` (relative to the lattice as created)."""
+        self._check(load_library().lbm_set_scales(self._h, float(inlet), float(stiffness)))
 
     def save(self, path):
         self._check(load_library().lbm_save(self._h, str(path).encode()))

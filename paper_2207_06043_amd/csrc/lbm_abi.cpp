@@ -36,6 +36,7 @@ struct HostBody {
   std::vector<int> hinges;  // local [nh][4]
   std::vector<double> theta0, kb;
   double V0, S0, ks0, kv, m_v, mass;
+  bool kv_default;  // kv = 10 k_s0 / r_ref (follows the stiffness scale)
   double cm[3], Ibody[9];
   std::vector<double> Xbody;
 };
@@ -100,6 +101,9 @@ struct lbm_ctx {
   int64_t enq = 0;
   std::vector<uint8_t> ncls_h;  // node classes (host copy: bulk tiles of other launch shapes)
   uint64_t version = 0;         // bumped when bodies or the launch shape change
+  // parameter scales (lbm_set_scales): inlet wall velocities and membrane moduli
+  double inlet_scale = 1.0, stiff_scale = 1.0;
+  std::vector<double> rec_bc_h;  // [4][nrec] as created (scale 1)
 };
 
 #define CHK(expr)                                                                    \
@@ -417,6 +421,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   CHK(upload(&ctx->rec_link0, r_link0));
   CHK(upload(&ctx->rec_face, r_face));
   CHK(upload(&ctx->rec_bc, bcT));
+  ctx->rec_bc_h = bcT;
   // Each branch of the rule has three terms: q < 1/2 uses c0 f_i(x),
   // c1 f_i(x-e_i), c2 f_i(x-2e_i); q >= 1/2 uses c0 f_i(x), c3 f_j(x),
   // c4 f_j(x-e_i).  Stored per link as k0, k1, k2 (in that order, [3][nl],
@@ -586,17 +591,18 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
     for (size_t k = 0; k < B.edges.size(); k++) edges.push_back(B.edges[k] + v0);
     for (size_t k = 0; k < B.hinges.size(); k++) hinges.push_back(B.hinges[k] + v0);
     l0.insert(l0.end(), B.l0.begin(), B.l0.end());
-    kl.insert(kl.end(), B.kl.begin(), B.kl.end());
+    for (double k : B.kl) kl.push_back(k * ctx->stiff_scale);
     th0.insert(th0.end(), B.theta0.begin(), B.theta0.end());
-    kb.insert(kb.end(), B.kb.begin(), B.kb.end());
+    for (double k : B.kb) kb.push_back(k * ctx->stiff_scale);
     Xbody.insert(Xbody.end(), B.Xbody.begin(), B.Xbody.end());
     double* pp = param.data() + 8 * b;
     pp[0] = B.V0;
     pp[1] = B.S0;
-    pp[2] = B.kv;
+    pp[2] = B.kv * (B.kv_default ? ctx->stiff_scale : 1.0);
     pp[3] = B.m_v;
     pp[4] = B.mass;
-    pp[5] = B.ks0;
+    pp[5] = B.ks0 * ctx->stiff_scale;
+    pp[6] = B.kv_default ? 1.0 : 0.0;
     for (int k = 0; k < 9; k++) param[8 * (size_t)nb + 9 * b + k] = B.Ibody[k];
     v0 += B.nv;
     f0 += B.nf;
@@ -808,6 +814,7 @@ extern "C" lbm_status lbm_add_body(lbm_ctx* ctx, const lbm_body_desc* bd, int32_
   const double nu = (ctx->tau - 0.5) / 3.0;
   B.ks0 = bd->ca > 0.0 ? nu * bd->u_ref / bd->ca : 0.0;
   B.kv = bd->kv > 0.0 ? bd->kv : 10.0 * B.ks0 / bd->r_ref;
+  B.kv_default = !(bd->kv > 0.0);
   B.V0 = V0;
   B.S0 = S0;
   B.mass = bd->rho_ratio * V0;
@@ -1658,17 +1665,70 @@ struct DevArena {  // one allocation, carved in 256-byte aligned pieces
 };
 }  // namespace
 
-extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t every, const double* d_w,
-                                       double* d_lambda, double* d_grad) {
+extern "C" lbm_status lbm_set_scales(lbm_ctx* ctx, double inlet_scale, double stiffness_scale) {
+  if (!ctx) return LBM_E_INVAL;
+  if (ctx->broken) return LBM_E_STATE;
+  if (!std::isfinite(inlet_scale) || !(stiffness_scale > 0.0) || !std::isfinite(stiffness_scale))
+    return fail(ctx, LBM_E_INVAL, "scales: a finite inlet scale and a positive stiffness scale");
+  CHK(hipStreamSynchronize(ctx->stream));
+  ctx->inlet_scale = inlet_scale;
+  ctx->stiff_scale = stiffness_scale;
+  // velocity-face records: their wall velocity times the scale
+  std::vector<double> bc = ctx->rec_bc_h;
+  std::vector<uint8_t> face(ctx->nrec);
+  if (ctx->nrec > 0) CHK(hipMemcpy(face.data(), ctx->rec_face, ctx->nrec, hipMemcpyDeviceToHost));
+  for (int r = 0; r < ctx->nrec; r++)
+    if (face[r] != 0xff && !((face[r] >> 4) & 1))
+      for (int c = 0; c < 3; c++) bc[(size_t)c * ctx->nrec + r] *= inlet_scale;
+  if (!bc.empty()) CHK(hipMemcpy(ctx->rec_bc, bc.data(), sizeof(double) * bc.size(), hipMemcpyHostToDevice));
+  // membrane moduli of every body
+  if (!ctx->bodies.empty()) {
+    std::vector<double> kl, kb;
+    for (const HostBody& B : ctx->bodies) {
+      for (double k : B.kl) kl.push_back(k * stiffness_scale);
+      for (double k : B.kb) kb.push_back(k * stiffness_scale);
+    }
+    CHK(hipMemcpy((void*)ctx->bargs[0].kl, kl.data(), sizeof(double) * kl.size(), hipMemcpyHostToDevice));
+    CHK(hipMemcpy((void*)ctx->bargs[0].kb, kb.data(), sizeof(double) * kb.size(), hipMemcpyHostToDevice));
+    for (size_t b = 0; b < ctx->bodies.size(); b++) {
+      const HostBody& B = ctx->bodies[b];
+      const double kv = B.kv * (B.kv_default ? stiffness_scale : 1.0), ks0 = B.ks0 * stiffness_scale;
+      CHK(hipMemcpy((void*)(ctx->bargs[0].b_param + 8 * b + 2), &kv, sizeof(double), hipMemcpyHostToDevice));
+      CHK(hipMemcpy((void*)(ctx->bargs[0].b_param + 8 * b + 5), &ks0, sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
+  return LBM_OK;
+}
+
+// The sweep of lbm_adjoint_step and lbm_adjoint_run.  With bodies, each
+// step of the recompute is the coupled step (forcing, stream-collide with the
+// per-node force, probes and vertex velocities, vertex update) on buffers of
+// the sweep, keeping the body state (P, Q, V) of every step of the segment;
+// each step back first re-runs the step's forcing and stream-collide (for
+// the force field and the step's rho, u), then transposes the vertex update,
+// the elements, probes and vertex velocities, the volume term, the force
+// adjoint at the forced nodes (mode 1), the forcing markers, and finally the
+// fluid step with all node sources (mode 0).
+static lbm_status adjoint_sweep(lbm_ctx* ctx, int32_t n_steps, int32_t every, const double* d_w, double theta,
+                                int32_t tbody, double* d_lambda, double* d_grad, int nout, double* d_body,
+                                double* h_J) {
   if (!ctx) return LBM_E_INVAL;
   if (ctx->broken) return LBM_E_STATE;
   if (n_steps < 0 || every < 1 || !d_lambda || !d_grad)
     return fail(ctx, LBM_E_INVAL, "adjoint: n_steps >= 0, checkpoint interval >= 1, lambda and grad required");
-  if (!ctx->bodies.empty()) return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: contexts without bodies only");
+  const int nb = (int)ctx->bodies.size();
+  for (const HostBody& B : ctx->bodies)
+    if (B.rigid || B.fixed)
+      return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: soft bodies only (the rigid-body transpose is not built)");
+  if (nb > 1)
+    return fail(ctx, LBM_E_UNSUPPORTED, "adjoint: at most one body (the repulsion transpose is not built)");
+  if (theta != 0.0 && (tbody < 0 || tbody >= nb)) return fail(ctx, LBM_E_INVAL, "adjoint: no such body");
+  if (d_body && nb == 0) return fail(ctx, LBM_E_INVAL, "adjoint: no bodies for the body gradient");
   DevFlags h;
   lbm_status st = read_flags(ctx, &h);
   if (st) return st;
   CHK(ensure_bulk_list(ctx));
+  const bool ib = nb > 0;
   const Grid& G = ctx->g;
   auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t dbytes = up256(19 * (size_t)G.plane * sizeof(double));  // an adjoint field (FP64)
@@ -1683,14 +1743,25 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   const size_t hbytes = 19 * (size_t)ctx->nrec * sizeof(double);  // one step's record populations
   const int npart = adj_part_blocks(ctx->nrec, ctx->n_bulk);
   const size_t pbytes = ADJ_PART * (size_t)npart * sizeof(double);
+  // with bodies: two force fields and their tile flags, the node sources and
+  // flags, dJ/dF at nodes, a scratch state, body checkpoints and tape (P, Q,
+  // V per step), eight body adjoint arrays
+  const long long ntiles = (G.Np >> TILE_SHIFT) + 1;
+  const size_t bstate = 9 * sizeof(double) * (size_t)ctx->nv;  // P, Q, V
+  const size_t ib_bytes = ib ? 2 * up256(3 * (size_t)G.Np * 8) + 2 * up256(ntiles) + up256(7 * (size_t)G.Np * 8) +
+                                   up256(ntiles) + up256(3 * (size_t)G.Np * 8) + xbytes +
+                                   (size_t)(nseg + tlen + 1) * up256(bstate) + 8 * up256(bstate / 3) +
+                                   up256(sizeof(double) * (2 + nb)) + up256(sizeof(DevFlags) + 64)
+                             : 0;
+  const size_t jbytes = up256(sizeof(double) * (ADJ_BLOCKS + 8));
   const size_t small = pbytes + 2 * ((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t) + tlen * (hbytes + 256) +
-                       3 * 256;
+                       4 * 256 + jbytes;
   // one launch for records and bulk nodes below 4M non-solid nodes (the
   // records' blocks are latency-bound; LBM_ADJ_SPLIT=1 forces two)
   const char* sp_env = getenv("LBM_ADJ_SPLIT");
   const int merged = (ctx->n_bulk + ctx->nrec < (4LL << 20)) && !(sp_env && atoi(sp_env) != 0);
   DevArena ar;
-  if (hipMalloc(&ar.base, big_bytes + small) != hipSuccess) {
+  if (hipMalloc(&ar.base, big_bytes + small + ib_bytes + 16 * 256) != hipSuccess) {
     (void)hipGetLastError();
     ar.base = nullptr;
     return fail(ctx, LBM_E_NOMEM, "adjoint: not enough device memory for the checkpoints and the tape");
@@ -1698,7 +1769,7 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   auto big = [&](size_t i) { return (double*)(ar.base + i * dbytes); };
   auto state = [&](size_t i) { return (void*)(ar.base + 6 * dbytes + i * xbytes); };
   struct {
-    double *lam, *mu[2], *acc[2], *w, *part;
+    double *lam, *mu[2], *acc[2], *w, *part, *jpart;
     uint32_t *pmask, *amask;
     std::vector<void*> ck, tape;
     std::vector<double*> hrec;
@@ -1718,12 +1789,48 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
     return (void*)p;
   };
   m.part = (double*)carve(pbytes);
+  m.jpart = (double*)carve(sizeof(double) * (ADJ_BLOCKS + 8));
   m.pmask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
   m.amask = (uint32_t*)carve(((size_t)ctx->n_bulk + ctx->nrec) * sizeof(uint32_t));
   for (int k = 0; k < tlen; k++) m.hrec.push_back((double*)carve(hbytes));
   hipStream_t s = ctx->stream;
   // solid entries stay zero in every buffer (never written by the sweep)
-  CHK(hipMemsetAsync(ar.base, 0, big_bytes + pbytes + 256, s));
+  CHK(hipMemsetAsync(ar.base, 0, big_bytes + pbytes + sizeof(double) * (ADJ_BLOCKS + 8) + 512, s));
+  // the body part of the arena
+  struct {
+    long long* fx[2];
+    uint8_t* tf[2];
+    double *ext, *fbar, *gsum;
+    uint8_t* etf;
+    void* gB;
+    std::vector<double*> bck, bt;
+    double *arr[8];
+    DevFlags* flags;
+    unsigned int* cnt;
+  } q{};
+  double* bdiag_save = nullptr;
+  std::vector<double> bdiag_h;
+  if (ib) {
+    char* ib0 = (char*)carve(ib_bytes);
+    sp = ib0;
+    for (int k = 0; k < 2; k++) q.fx[k] = (long long*)carve(3 * (size_t)G.Np * 8);
+    for (int k = 0; k < 2; k++) q.tf[k] = (uint8_t*)carve(ntiles);
+    q.ext = (double*)carve(7 * (size_t)G.Np * 8);
+    q.etf = (uint8_t*)carve(ntiles);
+    q.fbar = (double*)carve(3 * (size_t)G.Np * 8);
+    q.gB = carve(xraw);
+    for (int c = 0; c < nseg; c++) q.bck.push_back((double*)carve(bstate));
+    for (int k = 0; k <= tlen; k++) q.bt.push_back((double*)carve(bstate));
+    for (int k = 0; k < 8; k++) q.arr[k] = (double*)carve(bstate / 3);
+    q.gsum = (double*)carve(sizeof(double) * (2 + nb));
+    q.flags = (DevFlags*)carve(sizeof(DevFlags) + 64);
+    q.cnt = (unsigned int*)(q.flags + 1);
+    CHK(hipMemsetAsync(ib0, 0, (size_t)(sp - ib0), s));
+    bdiag_h.resize(16 * (size_t)nb);
+    CHK(hipMemcpyAsync(bdiag_h.data(), ctx->b_diag, sizeof(double) * bdiag_h.size(), hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    bdiag_save = ctx->b_diag;
+  }
   CHK(launch_adjoint_layout(G, ctx->ncls, d_lambda, m.lam, 1, s));
   if (d_w) CHK(launch_adjoint_layout(G, ctx->ncls, d_w, m.w, 1, s));
   FluidArgs a = fluid_args(ctx, 0);
@@ -1733,19 +1840,74 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   a.bulk_list = ctx->bulk_list;
   a.nbulk_nodes = (int)ctx->n_bulk;
   CHK(launch_adjoint_mask(a, m.w, m.pmask, m.amask, s));
+  const int nv3 = 3 * ctx->nv;
+  const size_t vb = sizeof(double) * nv3;
+  BodyArgs bb = ib ? ctx->bargs[0] : BodyArgs{};
+  // one coupled step from (gin, body slot `from`) into (gout, slot `to`)
+  auto coupled = [&](const void* gin, void* gout, double* from, double* to, double* hrec) -> hipError_t {
+    hipError_t e;
+    // slot to: P' (written), Q' = P, V' (written): the step reads x^{n-1}
+    // from Xnext and V from Vel before overwriting them
+    if ((e = hipMemcpyAsync(to, from + nv3, vb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(to + nv3, from, vb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(to + 2 * nv3, from + 2 * nv3, vb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    FluidArgs fa = a;
+    fa.A = gin;
+    fa.B = gout;
+    fa.fx = q.fx[0];
+    fa.tflag = q.tf[0];
+    fa.mac = ctx->mac;
+    fa.flags = q.flags;
+    BodyArgs b2 = bb;
+    b2.Xcur = from;
+    b2.Xnext = to;
+    b2.Vel = to + 2 * nv3;
+    if ((e = launch_ib_force(ctx->prec, fa, b2, q.fx[0], q.tf[0], q.fx[1], q.tf[1], q.cnt, s)) != hipSuccess) return e;
+    if ((e = launch_adjoint_forward(ctx->prec, fa, hrec, merged, s)) != hipSuccess) return e;
+    if ((e = launch_mls_post(ctx->prec, fa, b2, q.fx[1], q.tf[1], s)) != hipSuccess) return e;
+    if ((e = launch_body_post(b2, q.flags, nullptr, s)) != hipSuccess) return e;
+    if ((e = launch_close(q.flags, s)) != hipSuccess) return e;
+    // this step's force field is not needed again: clear it (the forcing of
+    // the next step spreads into the same buffer)
+    return launch_adjb_clear(G, q.ext, q.etf, q.fx[0], q.tf[0], s);
+  };
   // forward pass: the state at the start of every segment
+  const int cur0 = (int)(h.steps_done & 1);
   if (nseg > 0) {
-    CHK(hipMemcpyAsync(m.ck[0], ctx->f[h.steps_done & 1], xraw, hipMemcpyDeviceToDevice, s));
+    CHK(hipMemcpyAsync(m.ck[0], ctx->f[cur0], xraw, hipMemcpyDeviceToDevice, s));
+    if (ib) {
+      double* b0 = q.bck[0];
+      CHK(hipMemcpyAsync(b0, ctx->X[cur0], vb, hipMemcpyDeviceToDevice, s));
+      CHK(hipMemcpyAsync(b0 + nv3, ctx->X[cur0 ^ 1], vb, hipMemcpyDeviceToDevice, s));
+      CHK(hipMemcpyAsync(b0 + 2 * nv3, ctx->Vel, vb, hipMemcpyDeviceToDevice, s));
+    }
     for (int c = 1; c < nseg; c++) {
       const void* src = m.ck[c - 1];
+      double* bsrc = ib ? q.bck[c - 1] : nullptr;
       for (int k = 0; k < every; k++) {
-        a.A = src;
-        a.B = k == every - 1 ? m.ck[c] : m.tape[k & 1];
-        CHK(launch_adjoint_forward(ctx->prec, a, nullptr, merged, s));
-        src = a.B;
+        void* dst = k == every - 1 ? m.ck[c] : m.tape[k & 1];
+        if (ib) {
+          double* bdst = k == every - 1 ? q.bck[c] : q.bt[k & 1];
+          CHK(coupled(src, dst, bsrc, bdst, nullptr));
+          bsrc = bdst;
+        } else {
+          a.A = src;
+          a.B = dst;
+          CHK(launch_adjoint_forward(ctx->prec, a, nullptr, merged, s));
+        }
+        src = dst;
       }
     }
   }
+  // the recompute's extras: J's terms along the trajectory
+  double* jsum = m.jpart + ADJ_BLOCKS;  // [0] sum of D_T
+  auto observe = [&](const void* g, const double* P) -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (!h_J) return e;
+    if (m.w && (e = launch_adj_wdot(ctx->prec, a, g, m.w, m.amask, 1, m.jpart, s)) != hipSuccess) return e;
+    if (ib && (e = launch_taylor(bb, P, std::max(tbody, 0), 0.0, nullptr, jsum, s)) != hipSuccess) return e;
+    return e;
+  };
   // reverse pass, segment by segment: recompute its states (and the records'
   // populations entering each collision; the last step's output goes to the
   // mu buffer that the next step back rewrites at every non-solid node), then
@@ -1753,17 +1915,34 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   // buffers: each step reads those of the step after it.
   int cur = 0;
   bool first = true;
+  double* A3[3] = {nullptr, nullptr, nullptr};  // aP, aQ, aV
+  double* B3[3] = {nullptr, nullptr, nullptr};  // LP, Qn, Vn
+  if (ib) {
+    for (int k = 0; k < 3; k++) {
+      A3[k] = q.arr[k];
+      B3[k] = q.arr[3 + k];
+    }
+  }
   for (int c = nseg - 1; c >= 0; c--) {
     const int len = std::min(every, n_steps - c * every);
     CHK(hipMemcpyAsync(m.tape[0], m.ck[c], xraw, hipMemcpyDeviceToDevice, s));
+    if (ib) CHK(hipMemcpyAsync(q.bt[0], q.bck[c], bstate, hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < len; k++) {
-      a.A = m.tape[k];
-      a.B = k + 1 < len ? m.tape[k + 1] : (void*)m.mu[cur];  // mu[cur]: large enough for any storage
-      CHK(launch_adjoint_forward(ctx->prec, a, m.hrec[k], merged, s));
+      void* out = k + 1 < len ? m.tape[k + 1] : (void*)m.mu[cur];  // mu[cur]: large enough for any storage
+      if (ib) {
+        CHK(coupled(m.tape[k], out, q.bt[k], q.bt[k + 1], m.hrec[k]));
+      } else {
+        a.A = m.tape[k];
+        a.B = out;
+        CHK(launch_adjoint_forward(ctx->prec, a, m.hrec[k], merged, s));
+      }
+      CHK(observe(out, ib ? q.bt[k + 1] : nullptr));
+      if (h_J && first && c == nseg - 1 && k == len - 1)  // <lambda, g^n>
+        CHK(launch_adj_wdot(ctx->prec, a, out, m.lam, m.amask, 0, m.jpart, s));
     }
     for (int k = len - 1; k >= 0; k--) {
       a.A = m.tape[k];
-      AdjStep st;
+      AdjStep st{};
       st.hrec = m.hrec[k];
       st.lam = first ? m.lam : nullptr;
       st.mu_next = m.mu[cur ^ 1];
@@ -1774,7 +1953,56 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
       st.pmask = m.pmask;
       st.amask = m.amask;
       st.part = m.part;
+      if (ib) {
+        double* Pk = q.bt[k];  // the state the step started from
+        if (theta != 0.0) CHK(launch_taylor(bb, q.bt[k + 1], tbody, theta, A3[0], nullptr, s));
+        // the step's force field and fields again (into scratch)
+        FluidArgs fa = a;
+        fa.B = q.gB;
+        fa.fx = q.fx[0];
+        fa.tflag = q.tf[0];
+        fa.mac = ctx->mac;
+        fa.flags = q.flags;
+        BodyArgs b2 = bb;
+        b2.Xcur = Pk;
+        b2.Xnext = q.bt[k + 1];  // not written by the forcing launch
+        b2.Vel = Pk + 2 * nv3;
+        CHK(launch_ib_force(ctx->prec, fa, b2, q.fx[0], q.tf[0], q.fx[1], q.tf[1], q.cnt, s));
+        CHK(launch_adjoint_forward(ctx->prec, fa, nullptr, merged, s));
+        AdjIB ibp{};
+        ibp.aP = A3[0];
+        ibp.aQ = A3[1];
+        ibp.aV = A3[2];
+        ibp.LP = B3[0];
+        ibp.Qn = B3[1];
+        ibp.Vn = B3[2];
+        ibp.Fb = q.arr[6];
+        ibp.ub0 = q.arr[7];
+        ibp.ext = q.ext;
+        ibp.etf = q.etf;
+        ibp.fbar = q.fbar;
+        ibp.gsum = q.gsum;
+        ibp.kappa = ctx->stiff_scale;
+        CHK(hipMemsetAsync(q.gsum + 2, 0, sizeof(double) * nb, s));
+        CHK(launch_adjb_vertex(b2, ibp, s));
+        CHK(launch_adjb_body(ctx->prec, fa, b2, ibp, s));
+        CHK(launch_adjb_volume(b2, ibp, s));
+        CHK(launch_adjb_support(G, ctx->ncls, b2, q.etf, s));
+        st.fx = q.fx[0];
+        st.ftf = q.tf[0];
+        st.ext = q.ext;
+        st.etf = q.etf;
+        st.fbar = q.fbar;
+        st.mode = 1;
+        CHK(launch_adjoint_reverse(ctx->prec, a, st, merged, s));
+        CHK(launch_adjb_markers(ctx->prec, fa, b2, ibp, s));
+        st.mode = 0;
+      }
       CHK(launch_adjoint_reverse(ctx->prec, a, st, merged, s));
+      if (ib) {
+        CHK(launch_adjb_clear(G, q.ext, q.etf, q.fx[0], q.tf[0], s));
+        for (int t = 0; t < 3; t++) std::swap(A3[t], B3[t]);
+      }
       first = false;
       cur ^= 1;
     }
@@ -1782,9 +2010,44 @@ extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t ev
   // dJ/dg^0 = P^T mu of the last step back (plain pulls and bounce-back)
   if (n_steps > 0) CHK(launch_adjoint_gather(a, m.pmask, m.amask, m.mu[cur ^ 1], m.acc[cur ^ 1], m.lam, s));
   CHK(launch_adjoint_layout(G, ctx->ncls, m.lam, d_lambda, 0, s));
-  CHK(launch_adjoint_grad(m.part, npart, 1.0 / ctx->tau, d_grad, s));
+  CHK(launch_adjoint_grad(m.part, npart, 1.0 / ctx->tau, ib ? q.gsum : nullptr, nout, d_grad, s));
+  if (d_body) {
+    for (int t = 0; t < 3; t++)
+      CHK(hipMemcpyAsync(d_body + (size_t)t * nv3, A3[t], vb, hipMemcpyDeviceToDevice, s));
+  }
+  double jv[2] = {0.0, 0.0};
+  if (h_J) {
+    CHK(launch_adj_sum(m.jpart, ADJ_BLOCKS, m.jpart + ADJ_BLOCKS + 1, s));
+    double hj[2];
+    CHK(hipMemcpyAsync(hj, m.jpart + ADJ_BLOCKS, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    jv[0] = hj[1];
+    jv[1] = hj[0];
+  }
+  DevFlags hf{};
+  if (ib) {
+    CHK(hipMemcpyAsync(&hf, q.flags, sizeof hf, hipMemcpyDeviceToHost, s));
+    CHK(hipMemcpyAsync(bdiag_save, bdiag_h.data(), sizeof(double) * bdiag_h.size(), hipMemcpyHostToDevice, s));
+  }
   CHK(hipStreamSynchronize(s));
+  if (h_J) {
+    h_J[0] = jv[0];
+    h_J[1] = jv[1];
+  }
+  if (hf.stop & ST_DAMAGED) return fail(ctx, LBM_E_DAMAGED, "adjoint: a capsule was damaged along the trajectory");
+  if (hf.stop & ST_UNSTABLE) return fail(ctx, LBM_E_UNSTABLE, "adjoint: the trajectory became unstable");
   return LBM_OK;
+}
+
+extern "C" lbm_status lbm_adjoint_step(lbm_ctx* ctx, int32_t n_steps, int32_t every, const double* d_w,
+                                       double* d_lambda, double* d_grad) {
+  return adjoint_sweep(ctx, n_steps, every, d_w, 0.0, -1, d_lambda, d_grad, 5, nullptr, nullptr);
+}
+
+extern "C" lbm_status lbm_adjoint_run(lbm_ctx* ctx, int32_t n_steps, int32_t every, const double* d_w,
+                                      double taylor_weight, int32_t taylor_body, double* d_lambda,
+                                      double* d_grad, double* d_body_grad, double* J) {
+  return adjoint_sweep(ctx, n_steps, every, d_w, taylor_weight, taylor_body, d_lambda, d_grad, 6, d_body_grad, J);
 }
 
 // ------------------------------------------------------- checkpoint / restart

@@ -189,6 +189,34 @@ struct AdjStep {
   const uint32_t* pmask;   // per node (bulk list, then records): plainly pulled directions
   const uint32_t* amask;   // per node: directions that can receive a bounce-back transpose
   double* part;            // [blocks][4] gradient partials
+  // steps with bodies (null / 0 otherwise)
+  const long long* fx;     // fixed-point IB force of the step [3][Np] ...
+  const uint8_t* ftf;      // ... and its tile flags
+  const double* ext;       // [7][Np] adjoint sources at nodes: dJ/drho, dJ/du of the step's
+                           // fields (probes, vertex velocities), dJ/du* (forcing markers)
+  const uint8_t* etf;      // tile flags of ext
+  double* fbar;            // [3][Np] dJ/dF at the nodes of flagged force tiles (mode 1)
+  int mode;                // 0: the step back; 1: only fbar, nothing else written
+};
+// Adjoint of the immersed-boundary part of a step (soft bodies).  The state
+// a step maps is (g, P, Q, V): populations, positions x^n, previous
+// positions x^{n-1} and vertex velocities; aP, aQ, aV are dJ/d of the state
+// after the step, LP, Qn, Vn of the state before it.
+struct AdjIB {
+  const double* aP;
+  const double* aQ;
+  const double* aV;
+  double* LP;        // [nv][3] dJ/dx^n (accumulated by several launches)
+  double* Qn;        // [nv][3] dJ/dx^{n-1}
+  double* Vn;        // [nv][3] dJ/du_v^n (accumulated)
+  double* Fb;        // [nv][3] dJ/d(vertex force) of the step
+  double* ub0;       // [nv][3] dJ/d(MLS vertex velocity) of the step
+  double* ext;       // [7][Np] node sources (see AdjStep)
+  uint8_t* etf;      // their tile flags
+  const double* fbar;  // [3][Np] dJ/dF at the nodes of flagged force tiles
+  double* gsum;      // [0] dJ/dtau through the probes' viscosity, [1] dJ/dkappa,
+                     // [2 + b] sum over body b's faces of dJ/dF_face . A n (volume)
+  double kappa;      // stiffness scale of the membrane moduli
 };
 // launch_adjoint_forward: g^{k+1} = step(A) into B; hrec (may be null):
 // [19][nrec], the records' populations entering the collision.
@@ -215,7 +243,30 @@ hipError_t launch_adjoint_gather(const FluidArgs& a, const uint32_t* pmask, cons
                                  const double* acc, double* lam, hipStream_t s);
 hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const double* in, double* out, int to_padded,
                                  hipStream_t s);
-hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, double* grad, hipStream_t s);
+// grad[0..4] from the partials (dJ/ds, dJ/dF, dJ/dtau), plus ibsum[0] in
+// dJ/dtau and grad[5] = ibsum[1] (dJ/dkappa) when nout is 6 (ibsum may be null).
+hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, const double* ibsum, int nout,
+                               double* grad, hipStream_t s);
+// Coupled adjoint (soft bodies): vertex update transposed (Fb, ub0, Qn, LP,
+// Vn = 0); elements, probes and vertex velocities transposed (LP, ext, gsum);
+// the global volume term (LP); the forcing markers transposed (needs fbar:
+// ext's dJ/du*, Vn, LP); the Taylor deformation of body `body` at X (its value
+// added to *jsum, or theta times its gradient added to aP when aP is set);
+// clearing of the flagged tiles of ext / fx after a step back.
+hipError_t launch_adjb_vertex(const BodyArgs& b, const AdjIB& ib, hipStream_t s);
+hipError_t launch_adjb_body(int prec, const FluidArgs& a, const BodyArgs& b, const AdjIB& ib, hipStream_t s);
+hipError_t launch_adjb_volume(const BodyArgs& b, const AdjIB& ib, hipStream_t s);
+hipError_t launch_adjb_support(const Grid& g, const uint8_t* ncls, const BodyArgs& b, uint8_t* etf, hipStream_t s);
+hipError_t launch_adjb_markers(int prec, const FluidArgs& a, const BodyArgs& b, const AdjIB& ib, hipStream_t s);
+hipError_t launch_taylor(const BodyArgs& b, const double* X, int body, double theta, double* aP, double* jsum,
+                         hipStream_t s);
+hipError_t launch_adjb_clear(const Grid& g, double* ext, uint8_t* etf, long long* fx, uint8_t* ftf, hipStream_t s);
+// <w, g> over the non-solid nodes (where amask bit 31 is set when use_mask),
+// added per block into part[ADJ_BLOCKS] (fixed order); the sum in *out.
+hipError_t launch_adj_wdot(int prec, const FluidArgs& a, const void* g, const double* w, const uint32_t* amask,
+                           int use_mask, double* part, hipStream_t s);
+hipError_t launch_adj_sum(const double* part, int n, double* out, hipStream_t s);
+
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
 hipError_t launch_set_populations(int prec, const Grid& g, void* f0, void* f1, const uint8_t* ncls,

@@ -2444,10 +2444,12 @@ __device__ __forceinline__ void adj_fwd_bulk_one(const FluidArgs& a, int t) {
   S* B = (S*)a.B;
   int x, y, z;
   coords(G, n, x, y, z);
-  C g[19], dr, ux, uy, uz;
+  C g[19], dr, ux, uy, uz, Fx, Fy, Fz;
 #pragma unroll
   for (int j = 0; j < 19; j++) g[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
-  collide<C>(g, (C)a.gx, (C)a.gy, (C)a.gz, (C)a.omega, dr, ux, uy, uz);
+  node_force<C>(a, n, a.tflag && a.tflag[n >> TILE_SHIFT], Fx, Fy, Fz);
+  collide<C>(g, Fx, Fy, Fz, (C)a.omega, dr, ux, uy, uz);
+  if (a.mac) store_mac<C>(a, n, dr, ux, uy, uz);
 #pragma unroll
   for (int j = 0; j < 19; j++) B[(long long)j * G.plane + n] = (S)g[j];
 }
@@ -2455,14 +2457,16 @@ __device__ __forceinline__ void adj_fwd_bulk_one(const FluidArgs& a, int t) {
 template <class S>
 __device__ __forceinline__ void adj_fwd_rec_one(const FluidArgs& a, double* hrec, int r) {
   typedef typename Store<S>::C C;
-  C g[19], dr, ux, uy, uz;
+  C g[19], dr, ux, uy, uz, Fx, Fy, Fz;
   pull_general<S>(a, r, g);
   if (hrec) {
 #pragma unroll
     for (int j = 0; j < 19; j++) hrec[(long long)j * a.nrec + r] = (double)g[j];
   }
-  collide<C>(g, (C)a.gx, (C)a.gy, (C)a.gz, (C)a.omega, dr, ux, uy, uz);
   const long long n = a.rec_node[r];
+  node_force<C>(a, n, a.tflag && a.tflag[n >> TILE_SHIFT], Fx, Fy, Fz);
+  collide<C>(g, Fx, Fy, Fz, (C)a.omega, dr, ux, uy, uz);
+  if (a.mac) store_mac<C>(a, n, dr, ux, uy, uz);
   S* B = (S*)a.B;
 #pragma unroll
   for (int j = 0; j < 19; j++) B[(long long)j * a.g.plane + n] = (S)g[j];
@@ -2514,8 +2518,14 @@ __global__ __launch_bounds__(256) void k_adj_fwd_all(FluidArgs a, double* hrec, 
 //   P = omega P',  U_a = omega rho V_a + 9 kf Z_a - 3 (omega rho u_a + kf F_a) SL,
 //   Q_a = kf (V_a - 3 u_a SL),  kf = 1 - omega/2.
 // dF[3] += dJ/d(omega) at fixed h: sum_i l_i (g^eq_i - h_i - G_i / (2 kf)).
+// With bodies, x7 adds adjoint sources at the node: x7[0] = dJ/drho and
+// x7[1..3] = dJ/du of the step's fields (read by the probes and the vertex
+// velocities; u depends on F, so they enter dJ/dF too), x7[4..6] = dJ/du*
+// of the pre-force velocity u* = m / rho that the forcing markers read
+// (mu_j += dJ/du* . (e_j - u*) / rho).  dFn: this node's dJ/dF, dw: dJ/d(omega).
 __device__ __forceinline__ void collide_vjp(const double (&h)[19], const double (&l)[19], double Fx, double Fy,
-                                            double Fz, double omega, double (&mu)[19], double (&dF)[4]) {
+                                            double Fz, double omega, const double (&x7)[7], double (&mu)[19],
+                                            double (&dFn)[3], double& dw) {
   const double drho = dev_sum(h);
   const double mx = (h[1] - h[2]) + (h[7] + h[8]) + (h[9] + h[10]) - (h[11] + h[12]) - (h[13] + h[14]);
   const double my = (h[3] - h[4]) + (h[7] - h[8]) + (h[11] - h[12]) + (h[15] + h[16]) - (h[17] + h[18]);
@@ -2542,17 +2552,22 @@ __device__ __forceinline__ void collide_vjp(const double (&h)[19], const double 
     if (EZ[i]) { V2 += EZ[i] * v; Z2 += EZ[i] * zz; }
   }
   const double orho = omega * rho;
-  const double U0 = orho * V0 + 9.0 * kf * Z0 - 3.0 * (orho * ux + kf * Fx) * SL;
-  const double U1 = orho * V1 + 9.0 * kf * Z1 - 3.0 * (orho * uy + kf * Fy) * SL;
-  const double U2 = orho * V2 + 9.0 * kf * Z2 - 3.0 * (orho * uz + kf * Fz) * SL;
-  const double A0 = omega * Pp - (U0 * ux + U1 * uy + U2 * uz) * ir;
-  const double a0 = U0 * ir, a1 = U1 * ir, a2 = U2 * ir;
+  const double U0 = orho * V0 + 9.0 * kf * Z0 - 3.0 * (orho * ux + kf * Fx) * SL + x7[1];
+  const double U1 = orho * V1 + 9.0 * kf * Z1 - 3.0 * (orho * uy + kf * Fy) * SL + x7[2];
+  const double U2 = orho * V2 + 9.0 * kf * Z2 - 3.0 * (orho * uz + kf * Fz) * SL + x7[3];
+  double A0 = omega * Pp + x7[0] - (U0 * ux + U1 * uy + U2 * uz) * ir;
+  double a0 = U0 * ir, a1 = U1 * ir, a2 = U2 * ir;
+  dFn[0] = kf * (V0 - 3.0 * ux * SL) + 0.5 * a0;
+  dFn[1] = kf * (V1 - 3.0 * uy * SL) + 0.5 * a1;
+  dFn[2] = kf * (V2 - 3.0 * uz * SL) + 0.5 * a2;
+  dw = Dw;
+  // u* = m / rho (no force): mu_j += x7[4..6] . (e_j - u*) / rho
+  A0 -= (x7[4] * mx + x7[5] * my + x7[6] * mz) * ir * ir;
+  a0 += x7[4] * ir;
+  a1 += x7[5] * ir;
+  a2 += x7[6] * ir;
 #pragma unroll
   for (int j = 0; j < 19; j++) mu[j] = (1.0 - omega) * l[j] + A0 + (EX[j] * a0 + EY[j] * a1 + EZ[j] * a2);
-  dF[0] += kf * (V0 - 3.0 * ux * SL) + 0.5 * a0;
-  dF[1] += kf * (V1 - 3.0 * uy * SL) + 0.5 * a1;
-  dF[2] += kf * (V2 - 3.0 * uz * SL) + 0.5 * a2;
-  dF[3] += Dw;
 }
 
 // Zou-He's transpose (the rule of zouhe(), affine in the known populations
@@ -2672,6 +2687,12 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
   } else {
     n = a.bulk_list[t];
   }
+  // with bodies: the IB force at the node, and whether the force-adjoint
+  // pass (mode 1) has anything to do here
+  // (mode 1 also visits the tiles of every marker's supports, flagged in etf
+  // beforehand: dJ/dF is needed there even where the step's force is zero)
+  const bool fflag = st.ftf && st.ftf[n >> TILE_SHIFT];
+  if (st.mode == 1 && !fflag && !(st.etf && st.etf[n >> TILE_SHIFT])) return;
   int x, y, z;
   coords(G, n, x, y, z);
   if (!REC) {
@@ -2692,7 +2713,7 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
       if ((am >> j) & 1u) {
         double* pa = st.acc_in + (long long)j * G.plane + n;
         v += *pa;
-        *pa = 0.0;
+        if (st.mode == 0) *pa = 0.0;
       }
       l[j] = v;
     }
@@ -2701,7 +2722,28 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
 #pragma unroll
     for (int j = 0; j < 19; j++) l[j] += st.w[(long long)j * G.plane + n];
   }
-  collide_vjp(h, l, a.gx, a.gy, a.gz, a.omega, m, dF);
+  double Fx = a.gx, Fy = a.gy, Fz = a.gz;
+  if (fflag) {
+    Fx += (double)st.fx[n] * FX_INV;
+    Fy += (double)st.fx[G.Np + n] * FX_INV;
+    Fz += (double)st.fx[2 * G.Np + n] * FX_INV;
+  }
+  double x7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (st.etf && st.etf[n >> TILE_SHIFT]) {
+#pragma unroll
+    for (int k = 0; k < 7; k++) x7[k] = st.ext[(long long)k * G.Np + n];
+  }
+  double dFn[3], dw;
+  collide_vjp(h, l, Fx, Fy, Fz, a.omega, x7, m, dFn, dw);
+  if (st.mode == 1) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) st.fbar[(long long)k * G.Np + n] = dFn[k];
+    return;
+  }
+  dF[0] += dFn[0];
+  dF[1] += dFn[1];
+  dF[2] += dFn[2];
+  dF[3] += dw;
   if (REC) {
     const int fc = a.rec_face[t];
     if (fc != 0xff) {
@@ -2850,12 +2892,17 @@ __global__ void k_adj_layout(Grid G, const uint8_t* ncls, const double* in, doub
 
 // grad[0..4] = dJ/ds, dJ/dF, dJ/dtau = -omega^2 dJ/d(omega), summed over the
 // blocks in a fixed order.
-__global__ void k_adj_grad_final(const double* part, int nblk, double omega, double* grad) {
+__global__ void k_adj_grad_final(const double* part, int nblk, double omega, const double* ibsum, int nout,
+                                 double* grad) {
   const int q = threadIdx.x;
-  if (q >= 5) return;
+  if (q >= nout) return;
+  if (q == 5) {
+    grad[5] = ibsum ? ibsum[1] : 0.0;
+    return;
+  }
   double t = 0.0;
   for (int b = 0; b < nblk; b++) t += part[ADJ_PART * b + q];
-  grad[q] = q == 4 ? -omega * omega * t : t;
+  grad[q] = q == 4 ? -omega * omega * t + (ibsum ? ibsum[0] : 0.0) : t;
 }
 
 template <class S>
@@ -2914,8 +2961,9 @@ hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, double* grad, hipStream_t s) {
-  k_adj_grad_final<<<1, 64, 0, s>>>(part, nblk, omega, grad);
+hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, const double* ibsum, int nout,
+                               double* grad, hipStream_t s) {
+  k_adj_grad_final<<<1, 64, 0, s>>>(part, nblk, omega, ibsum, nout, grad);
   return hipGetLastError();
 }
 
@@ -3071,6 +3119,764 @@ hipError_t launch_spread_noalloc(const Grid& g, const uint8_t* ncls, long long n
   e = launch_spread_api(g, ncls, n, pts, F, c, scr, (DevFlags*)flag_words, s);
   if (e != hipSuccess) return e;
   return launch_flush_fx(g, scr, fib, s);
+}
+
+// ====================================================== coupled adjoint (IB)
+// The immersed-boundary part of the discrete adjoint of a coupled step, for
+// soft bodies.  The step maps (g, P, Q, V) -> (g', P', Q', V'), with P the
+// vertex positions x^n, Q = x^{n-1} and V the vertex velocities; going
+// back, the transposes of the Verlet update (Eqs. verletPos, verletVel,
+// verletPosC), the membrane forces (Eqs. strainFor, bendFor, volFor), the
+// probe tractions (Eqs. hydroForP, hydroForNu), the MLS vertex velocities
+// and the direct forcing with its spreading (Eqs. uLag, l2norm, intKernel,
+// bodyforce) are applied, each with the derivative of its weights with
+// respect to the moving points.  All in FP64.
+
+// Forward-mode dual numbers (value and N partial derivatives), for the
+// derivatives of the small per-point and per-element functions of the
+// vertex positions.
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+};
+
+template <class T>
+struct Scal;
+template <>
+struct Scal<double> {
+  __device__ static double c(double v) { return v; }
+};
+template <int N>
+struct Scal<Dual<N>> {
+  __device__ static Dual<N> c(double v) {
+    Dual<N> r;
+    r.v = v;
+#pragma unroll
+    for (int i = 0; i < N; i++) r.d[i] = 0.0;
+    return r;
+  }
+};
+
+template <int N>
+__device__ __forceinline__ Dual<N> dseed(double v, int k) {
+  Dual<N> r = Scal<Dual<N>>::c(v);
+  r.d[k] = 1.0;
+  return r;
+}
+__device__ __forceinline__ double dval(double x) { return x; }
+template <int N>
+__device__ __forceinline__ double dval(const Dual<N>& x) {
+  return x.v;
+}
+
+#define DUAL_BIN(OP, VEXPR, DEXPR)                                                           \
+  template <int N>                                                                           \
+  __device__ __forceinline__ Dual<N> operator OP(const Dual<N>& a, const Dual<N>& b) {       \
+    Dual<N> r;                                                                               \
+    r.v = VEXPR;                                                                             \
+    _Pragma("unroll") for (int i = 0; i < N; i++) r.d[i] = DEXPR;                           \
+    return r;                                                                                \
+  }
+DUAL_BIN(+, a.v + b.v, a.d[i] + b.d[i])
+DUAL_BIN(-, a.v - b.v, a.d[i] - b.d[i])
+DUAL_BIN(*, a.v * b.v, a.d[i] * b.v + a.v * b.d[i])
+DUAL_BIN(/, a.v / b.v, (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v))
+#undef DUAL_BIN
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(const Dual<N>& a, double b) {
+  Dual<N> r = a;
+  r.v += b;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator+(double b, const Dual<N>& a) {
+  return a + b;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a, double b) {
+  Dual<N> r = a;
+  r.v -= b;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(const Dual<N>& a) {
+  Dual<N> r;
+  r.v = -a.v;
+#pragma unroll
+  for (int i = 0; i < N; i++) r.d[i] = -a.d[i];
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator-(double b, const Dual<N>& a) {
+  Dual<N> r = -a;
+  r.v += b;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, double b) {
+  Dual<N> r;
+  r.v = a.v * b;
+#pragma unroll
+  for (int i = 0; i < N; i++) r.d[i] = a.d[i] * b;
+  return r;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator*(double b, const Dual<N>& a) {
+  return a * b;
+}
+template <int N>
+__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, double b) {
+  return a * (1.0 / b);
+}
+template <int N>
+__device__ __forceinline__ Dual<N>& operator+=(Dual<N>& a, const Dual<N>& b) {
+  a = a + b;
+  return a;
+}
+template <int N>
+__device__ __forceinline__ Dual<N>& operator-=(Dual<N>& a, const Dual<N>& b) {
+  a = a - b;
+  return a;
+}
+// chain rule of a scalar function: value f, derivative df at a.v
+template <int N>
+__device__ __forceinline__ Dual<N> dchain(const Dual<N>& a, double f, double df) {
+  Dual<N> r;
+  r.v = f;
+#pragma unroll
+  for (int i = 0; i < N; i++) r.d[i] = df * a.d[i];
+  return r;
+}
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double dexp(double a) { return exp(a); }
+__device__ __forceinline__ double dsin(double a) { return sin(a); }
+__device__ __forceinline__ double dcos(double a) { return cos(a); }
+__device__ __forceinline__ double datan2(double y, double x) { return atan2(y, x); }
+template <int N>
+__device__ __forceinline__ Dual<N> dsqrt(const Dual<N>& a) {
+  const double r = sqrt(a.v);
+  return dchain(a, r, 0.5 / r);
+}
+template <int N>
+__device__ __forceinline__ Dual<N> dexp(const Dual<N>& a) {
+  const double e = exp(a.v);
+  return dchain(a, e, e);
+}
+template <int N>
+__device__ __forceinline__ Dual<N> dsin(const Dual<N>& a) {
+  return dchain(a, sin(a.v), cos(a.v));
+}
+template <int N>
+__device__ __forceinline__ Dual<N> dcos(const Dual<N>& a) {
+  return dchain(a, cos(a.v), -sin(a.v));
+}
+template <int N>
+__device__ __forceinline__ Dual<N> datan2(const Dual<N>& y, const Dual<N>& x) {
+  Dual<N> r;
+  r.v = atan2(y.v, x.v);
+  const double q = 1.0 / (x.v * x.v + y.v * y.v);
+#pragma unroll
+  for (int i = 0; i < N; i++) r.d[i] = (x.v * y.d[i] - y.v * x.d[i]) * q;
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ void cross_t(const T (&a)[3], const T (&b)[3], T (&c)[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+template <class T>
+__device__ __forceinline__ T dot_t(const T (&a)[3], const T (&b)[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// MLS at point p in any scalar type: the 27 supports of floor(p + 1/2)
+// (solid and out-of-box nodes left out, as in the step), A = sum W P P^T
+// with W = exp(-|d|^2 / (2.6^2 0.3^2)) and P = (1, d), d = x_k - p, then for
+// each usable support fn(k, node, psi), psi = W A^{-1} P (psi[0] the
+// interpolation weight phi_k, psi[1..3] the gradient weights of the linear
+// fit).  A singular moment matrix (the step's rule) calls nothing and
+// returns false.
+template <class T, class Fn>
+__device__ bool mls_each(const Grid& G, const uint8_t* ncls, const T (&p)[3], Fn&& fn) {
+  const int bs[3] = {(int)floor(dval(p[0]) + 0.5), (int)floor(dval(p[1]) + 0.5), (int)floor(dval(p[2]) + 0.5)};
+  T A[10];
+#pragma unroll
+  for (int k = 0; k < 10; k++) A[k] = Scal<T>::c(0.0);
+  for (int k = 0; k < 27; k++) {
+    long long node;
+    const int c[3] = {bs[0] + k % 3 - 1, bs[1] + (k / 3) % 3 - 1, bs[2] + k / 9 - 1};
+    if (!support_node(G, ncls, c[0], c[1], c[2], node)) continue;
+    const T dx = (double)c[0] - p[0], dy = (double)c[1] - p[1], dz = (double)c[2] - p[2];
+    const T W = dexp((dx * dx + dy * dy + dz * dz) * (-MLS_K));
+    const T wx = W * dx, wy = W * dy, wz = W * dz;
+    A[0] += W;
+    A[1] += wx;
+    A[2] += wy;
+    A[3] += wz;
+    A[4] += wx * dx;
+    A[5] += wx * dy;
+    A[6] += wx * dz;
+    A[7] += wy * dy;
+    A[8] += wy * dz;
+    A[9] += wz * dz;
+  }
+  const int ix[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
+  const double dmax = fmax(fmax(dval(A[0]), dval(A[4])), fmax(dval(A[7]), dval(A[9])));
+  if (!(dmax > 0.0)) return false;
+  T L[4][4];
+  for (int j = 0; j < 4; j++) {
+    T d = A[ix[j][j]];
+    for (int k = 0; k < j; k++) d -= L[j][k] * L[j][k];
+    if (!(dval(d) > 1e-10 * dmax)) return false;
+    L[j][j] = dsqrt(d);
+    for (int i = j + 1; i < 4; i++) {
+      T v = A[ix[i][j]];
+      for (int k = 0; k < j; k++) v -= L[i][k] * L[j][k];
+      L[i][j] = v / L[j][j];
+    }
+  }
+  T Ai[4][4];
+  for (int c = 0; c < 4; c++) {
+    T y[4], z[4];
+    for (int i = 0; i < 4; i++) {
+      T v = Scal<T>::c(i == c ? 1.0 : 0.0);
+      for (int k = 0; k < i; k++) v -= L[i][k] * y[k];
+      y[i] = v / L[i][i];
+    }
+    for (int i = 3; i >= 0; i--) {
+      T v = y[i];
+      for (int k = i + 1; k < 4; k++) v -= L[k][i] * z[k];
+      z[i] = v / L[i][i];
+    }
+    for (int i = 0; i < 4; i++) Ai[i][c] = z[i];
+  }
+  for (int k = 0; k < 27; k++) {
+    long long node;
+    const int c[3] = {bs[0] + k % 3 - 1, bs[1] + (k / 3) % 3 - 1, bs[2] + k / 9 - 1};
+    if (!support_node(G, ncls, c[0], c[1], c[2], node)) continue;
+    const T P[4] = {Scal<T>::c(1.0), (double)c[0] - p[0], (double)c[1] - p[1], (double)c[2] - p[2]};
+    const T W = dexp((P[1] * P[1] + P[2] * P[2] + P[3] * P[3]) * (-MLS_K));
+    T psi[4];
+    for (int i = 0; i < 4; i++) {
+      T v = Ai[i][0] * P[0];
+      for (int j = 1; j < 4; j++) v += Ai[i][j] * P[j];
+      psi[i] = W * v;
+    }
+    fn(k, node, psi);
+  }
+  return true;
+}
+
+// The bending force of a hinge (a, b, c, d) in any scalar type: the signed
+// dihedral angle and F_r = -k_b sin(theta - theta0) dtheta/dx_r, with the
+// closed-form angle gradient of the step.
+template <class T>
+__device__ void hinge_force_t(const T (&X)[4][3], double kb, double th0, T (&F)[4][3]) {
+  T e[3], ca[3], da[3], ab[3], db[3], n1[3], n2[3];
+  for (int k = 0; k < 3; k++) {
+    e[k] = X[1][k] - X[0][k];
+    ca[k] = X[2][k] - X[0][k];
+    da[k] = X[3][k] - X[0][k];
+    ab[k] = X[0][k] - X[1][k];
+    db[k] = X[3][k] - X[1][k];
+  }
+  cross_t(e, ca, n1);
+  cross_t(ab, db, n2);
+  const T q1 = dot_t(n1, n1), q2 = dot_t(n2, n2), le2 = dot_t(e, e);
+  const T le = dsqrt(le2), l1 = dsqrt(q1), l2 = dsqrt(q2);
+  T m1[3], m2[3], t[3];
+  for (int k = 0; k < 3; k++) {
+    m1[k] = n1[k] / l1;
+    m2[k] = n2[k] / l2;
+  }
+  cross_t(m1, m2, t);
+  const T theta = datan2(dot_t(t, e) / le, dot_t(m1, m2));
+  const T al_c = dot_t(ca, e) / le2, al_d = dot_t(da, e) / le2;
+  const T amp = dsin(theta - th0) * (-kb);
+  for (int k = 0; k < 3; k++) {
+    const T gc = -(le * n1[k]) / q1;
+    const T gd = -(le * n2[k]) / q2;
+    F[0][k] = amp * (-((1.0 - al_c) * gc + (1.0 - al_d) * gd));
+    F[1][k] = amp * (-(al_c * gc + al_d * gd));
+    F[2][k] = amp * gc;
+    F[3][k] = amp * gd;
+  }
+}
+
+__device__ __forceinline__ void set_tile(uint8_t* tf, long long node) {
+  if (!tf[node >> TILE_SHIFT]) tf[node >> TILE_SHIFT] = 1;
+}
+
+// The vertex update transposed.  With P' = P/2 + 3/2 u0 + 5/2 acc + Q/2,
+// V' = -P/2 + 3/2 u0 + 3/2 acc + Q/2, Q' = P and acc = F / (2 m_v):
+// dJ/du0 = 3/2 (aP + aV), dJ/dF = (5/2 aP + 3/2 aV) / (2 m_v),
+// dJ/dQ = (aP + aV)/2, dJ/dP = aP/2 - aV/2 + aQ (more added by the later
+// launches), dJ/dV = 0 (the forcing markers add theirs).
+__global__ __launch_bounds__(256) void k_adjb_vertex(BodyArgs b, AdjIB ib) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= b.nsoft_v) return;
+  const int v = b.soft_vlist[idx];
+  const double mv = b.b_param[8 * b.vert_body[v] + 3];
+  for (int q = 0; q < 3; q++) {
+    const int i = 3 * v + q;
+    const double aX = ib.aP[i], aV = ib.aV[i], aQ = ib.aQ[i];
+    ib.ub0[i] = 1.5 * (aX + aV);
+    ib.Fb[i] = (2.5 * aX + 1.5 * aV) * 0.5 / mv;
+    ib.Qn[i] = 0.5 * aX + 0.5 * aV;
+    ib.LP[i] = 0.5 * aX - 0.5 * aV + aQ;
+    ib.Vn[i] = 0.0;
+  }
+}
+
+// Lift a function of a probe point (derivatives along its three
+// coordinates) to the nine vertex coordinates the point depends on.
+__device__ __forceinline__ Dual<9> lift9(const Dual<3>& f, const Dual<9> (&p)[3]) {
+  Dual<9> r;
+  r.v = f.v;
+#pragma unroll
+  for (int i = 0; i < 9; i++) r.d[i] = f.d[0] * p[0].d[i] + f.d[1] * p[1].d[i] + f.d[2] * p[2].d[i];
+  return r;
+}
+
+// Elements, probes and vertex velocities transposed, one thread each:
+// items [0, ne) edges, [ne, ne + nh) hinges, then faces, then soft vertices.
+template <class S>
+__global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjIB ib) {
+  const int it = blockIdx.x * 128 + threadIdx.x;
+  const Grid& G = a.g;
+  const double* X = b.Xcur;
+  const double ikap = 1.0 / ib.kappa;
+  if (it < b.ne) {
+    // stretching (Eq. strainFor): F_a = -k (l - l0) r / l, r = x_a - x_b; its
+    // Jacobian K = -k [(1 - l0/l) 1 + l0 r r^T / l^3] is symmetric, and
+    // dF_b = -dF_a
+    const int e = it, va = b.edges[2 * e], vb = b.edges[2 * e + 1];
+    double r[3], y[3];
+    for (int k = 0; k < 3; k++) {
+      r[k] = X[3 * va + k] - X[3 * vb + k];
+      y[k] = ib.Fb[3 * va + k] - ib.Fb[3 * vb + k];
+    }
+    const double l = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double kl = b.kl[e], l0 = b.l0[e];
+    const double ry = r[0] * y[0] + r[1] * y[1] + r[2] * y[2];
+    double fy = 0.0;
+    for (int k = 0; k < 3; k++) {
+      const double g = -kl * ((1.0 - l0 / l) * y[k] + l0 * ry * r[k] / (l * l * l));
+      atomicAdd(ib.LP + 3 * va + k, g);
+      atomicAdd(ib.LP + 3 * vb + k, -g);
+      fy += -kl * (l - l0) * r[k] / l * y[k];
+    }
+    atomicAdd(ib.gsum + 1, fy * ikap);  // the force is linear in the modulus
+    return;
+  }
+  if (it < b.ne + b.nh) {
+    // bending: the force is minus the gradient of the hinge energy, so its
+    // Jacobian is symmetric and the transposed product is the derivative
+    // along the adjoint itself (one dual direction)
+    const int h = it - b.ne;
+    const int32_t* H = b.hinges + 4 * h;
+    Dual<1> P[4][3], F[4][3];
+    for (int r = 0; r < 4; r++)
+      for (int k = 0; k < 3; k++) {
+        P[r][k].v = X[3 * H[r] + k];
+        P[r][k].d[0] = ib.Fb[3 * H[r] + k];
+      }
+    hinge_force_t(P, b.kb[h], b.theta0[h], F);
+    double fy = 0.0;
+    for (int r = 0; r < 4; r++)
+      for (int k = 0; k < 3; k++) {
+        atomicAdd(ib.LP + 3 * H[r] + k, F[r][k].d[0]);
+        fy += F[r][k].v * ib.Fb[3 * H[r] + k];
+      }
+    atomicAdd(ib.gsum + 1, fy * ikap);
+    return;
+  }
+  if (it < b.ne + b.nh + b.nf) {
+    // face force Ft = A [-(r+ - r-)/3 n + nu (r+ (G+ + G+^T) - r- (G- + G-^T)) n]
+    // + k_v (1 - V/V0) A n (probes at c +- 1.2 n: fitted density r and
+    // velocity gradient G), a third at each vertex: dJ/dFt = the mean of
+    // the vertices' dJ/dF
+    const int f = it - b.ne - b.nh;
+    const int body = b.face_body[f];
+    const int vv[3] = {b.faces[3 * f], b.faces[3 * f + 1], b.faces[3 * f + 2]};
+    double ab[3];
+    for (int k = 0; k < 3; k++) ab[k] = (ib.Fb[3 * vv[0] + k] + ib.Fb[3 * vv[1] + k] + ib.Fb[3 * vv[2] + k]) / 3.0;
+    Dual<9> P[3][3];
+    for (int r = 0; r < 3; r++)
+      for (int k = 0; k < 3; k++) P[r][k] = dseed<9>(X[3 * vv[r] + k], 3 * r + k);
+    Dual<9> u[3], w[3], N[3];
+    for (int k = 0; k < 3; k++) {
+      u[k] = P[1][k] - P[0][k];
+      w[k] = P[2][k] - P[0][k];
+    }
+    cross_t(u, w, N);
+    const Dual<9> ln = dsqrt(dot_t(N, N));
+    Dual<9> n[3], cen[3];
+    for (int k = 0; k < 3; k++) {
+      n[k] = N[k] / ln;
+      cen[k] = (P[0][k] + P[1][k] + P[2][k]) / 3.0;
+    }
+    const Dual<9> A = ln * 0.5;
+    const double nu = b.nu;
+    const double V0 = b.b_param[8 * body], kv = b.b_param[8 * body + 2];
+    const double cv = kv * (1.0 - b.b_diag[16 * body] / V0);
+    const Dual<9> an = ab[0] * n[0] + ab[1] * n[1] + ab[2] * n[2];
+    Dual<9> s = A * an * cv;  // the volume force
+    double visc = 0.0;        // d s / d nu
+    for (int side = 0; side < 2; side++) {
+      const double sg = side == 0 ? 1.2 : -1.2, sgn = side == 0 ? 1.0 : -1.0;
+      Dual<9> pp[3];
+      for (int k = 0; k < 3; k++) pp[k] = cen[k] + n[k] * sg;
+      const Dual<3> q[3] = {dseed<3>(pp[0].v, 0), dseed<3>(pp[1].v, 1), dseed<3>(pp[2].v, 2)};
+      Dual<3> r3 = Scal<Dual<3>>::c(1.0), G3[3][3];
+      for (int i = 0; i < 3; i++)
+        for (int c = 0; c < 3; c++) G3[i][c] = Scal<Dual<3>>::c(0.0);
+      mls_each(G, a.ncls, q, [&](int, long long node, const Dual<3>(&psi)[4]) {
+        double dr, uu[3];
+        load_mac<S>(a, node, dr, uu[0], uu[1], uu[2]);
+        r3 += psi[0] * dr;
+        for (int i = 0; i < 3; i++)
+          for (int c = 0; c < 3; c++) G3[i][c] += psi[1 + c] * uu[i];
+      });
+      const Dual<9> r9 = lift9(r3, pp);
+      Dual<9> sv = Scal<Dual<9>>::c(0.0);  // ab . ((G + G^T) n)
+      double svv = 0.0;
+      double Gv[3][3];
+      for (int i = 0; i < 3; i++)
+        for (int c = 0; c < 3; c++) {
+          Gv[i][c] = G3[i][c].v;
+          const Dual<9> g9 = lift9(G3[i][c], pp);
+          const Dual<9> t = g9 * (ab[i] * 1.0);
+          sv += t * n[c];  // ab_i G_ic n_c
+          Dual<9> t2 = g9 * n[i];
+          sv += t2 * ab[c];  // ab_c G_ic n_i (the transpose)
+        }
+      for (int i = 0; i < 3; i++)
+        for (int c = 0; c < 3; c++) svv += ab[i] * (Gv[i][c] + Gv[c][i]) * n[c].v;
+      s += A * sgn * (r9 * an * (-1.0 / 3.0) + r9 * sv * nu);
+      visc += A.v * sgn * r9.v * svv;
+      // field adjoints at this probe's supports
+      const double rbar = A.v * sgn * (-an.v / 3.0 + nu * svv);
+      double Gbar[3][3];
+      for (int i = 0; i < 3; i++)
+        for (int c = 0; c < 3; c++) Gbar[i][c] = A.v * sgn * nu * r9.v * (ab[i] * n[c].v + ab[c] * n[i].v);
+      const double qv[3] = {pp[0].v, pp[1].v, pp[2].v};
+      mls_each(G, a.ncls, qv, [&](int, long long node, const double(&psi)[4]) {
+        atomicAdd(ib.ext + node, rbar * psi[0]);
+        for (int i = 0; i < 3; i++)
+          atomicAdd(ib.ext + (long long)(1 + i) * G.Np + node,
+                    Gbar[i][0] * psi[1] + Gbar[i][1] * psi[2] + Gbar[i][2] * psi[3]);
+        set_tile(ib.etf, node);
+      });
+    }
+    for (int r = 0; r < 3; r++)
+      for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * vv[r] + k, s.d[3 * r + k]);
+    atomicAdd(ib.gsum, visc / 3.0);  // nu = (tau - 1/2) / 3
+    if (b.b_param[8 * body + 6] != 0.0) atomicAdd(ib.gsum + 1, cv * A.v * an.v * ikap);
+    atomicAdd(ib.gsum + 2 + body, A.v * an.v);
+    return;
+  }
+  const int idx = it - b.ne - b.nh - b.nf;
+  if (idx >= b.nsoft_v) return;
+  // MLS velocity at the vertex: u0 = sum phi_k u_k
+  const int v = b.soft_vlist[idx];
+  const double ub[3] = {ib.ub0[3 * v], ib.ub0[3 * v + 1], ib.ub0[3 * v + 2]};
+  const Dual<3> p[3] = {dseed<3>(X[3 * v], 0), dseed<3>(X[3 * v + 1], 1), dseed<3>(X[3 * v + 2], 2)};
+  Dual<3> s = Scal<Dual<3>>::c(0.0);
+  mls_each(G, a.ncls, p, [&](int, long long node, const Dual<3>(&psi)[4]) {
+    double dr, uu[3];
+    load_mac<S>(a, node, dr, uu[0], uu[1], uu[2]);
+    s += psi[0] * (uu[0] * ub[0] + uu[1] * ub[1] + uu[2] * ub[2]);
+    for (int i = 0; i < 3; i++) atomicAdd(ib.ext + (long long)(1 + i) * G.Np + node, psi[0].v * ub[i]);
+    set_tile(ib.etf, node);
+  });
+  for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * v + k, s.d[k]);
+}
+
+// Flags the tiles of every forcing marker's support nodes (the force adjoint
+// is needed there whatever the step's force was).
+__global__ __launch_bounds__(256) void k_adjb_support(Grid G, const uint8_t* ncls, BodyArgs b, uint8_t* etf) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= b.nf) return;
+  double cen[3], n[3], area;
+  face_geom(b.Xcur, b.faces, m, cen, n, area);
+  const int bs[3] = {(int)floor(cen[0] + 0.5), (int)floor(cen[1] + 0.5), (int)floor(cen[2] + 0.5)};
+  for (int k = 0; k < 27; k++) {
+    long long node;
+    if (support_node(G, ncls, bs[0] + k % 3 - 1, bs[1] + (k / 3) % 3 - 1, bs[2] + k / 9 - 1, node))
+      set_tile(etf, node);
+  }
+}
+
+// The volume force through V: Ft_f contains k_v (1 - V/V0) A_f n_f, and
+// dV/dx_v is a third of the sum of A n over the faces at v.
+__global__ __launch_bounds__(256) void k_adjb_volume(BodyArgs b, AdjIB ib) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= b.nf) return;
+  const int body = b.face_body[f];
+  const double V0 = b.b_param[8 * body], kv = b.b_param[8 * body + 2];
+  const double c = -kv / V0 * ib.gsum[2 + body] / 3.0;
+  double cen[3], n[3], area;
+  face_geom(b.Xcur, b.faces, f, cen, n, area);
+  for (int r = 0; r < 3; r++)
+    for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * b.faces[3 * f + r] + k, c * area * n[k]);
+}
+
+// The forcing markers transposed (one thread per face): U = sum phi u*,
+// F_l = U_b - U, f_ib += A phi F_l.  dJ/dF_l = A sum phi dJ/dF_k; dJ/dU_b =
+// dJ/dF_l (a third to each vertex velocity); dJ/du*_k -= phi_k dJ/dF_l; and
+// the positions through the centroid (phi) and the area.
+template <class S>
+__global__ __launch_bounds__(128) void k_adjb_markers(FluidArgs a, BodyArgs b, AdjIB ib) {
+  const int m = blockIdx.x * 128 + threadIdx.x;
+  if (m >= b.nf) return;
+  const Grid& G = a.g;
+  const int vv[3] = {b.faces[3 * m], b.faces[3 * m + 1], b.faces[3 * m + 2]};
+  double cen[3], n[3], area, Ub[3];
+  face_geom(b.Xcur, b.faces, m, cen, n, area);
+  for (int k = 0; k < 3; k++) Ub[k] = (b.Vel[3 * vv[0] + k] + b.Vel[3 * vv[1] + k] + b.Vel[3 * vv[2] + k]) / 3.0;
+  double U[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
+  mls_each(G, a.ncls, cen, [&](int, long long node, const double(&psi)[4]) {
+    const Moments mo = streamed_moments<S>(a, node);
+    const double rho = 1.0 + mo.drho;
+    for (int k = 0; k < 3; k++) {
+      U[k] += psi[0] * (mo.m[k] / rho);
+      Fs[k] += psi[0] * ib.fbar[(long long)k * G.Np + node];
+    }
+  });
+  double Fl[3], Fbl[3];
+  for (int k = 0; k < 3; k++) {
+    Fl[k] = Ub[k] - U[k];
+    Fbl[k] = area * Fs[k];
+  }
+  for (int r = 0; r < 3; r++)
+    for (int k = 0; k < 3; k++) atomicAdd(ib.Vn + 3 * vv[r] + k, Fbl[k] / 3.0);
+  const Dual<3> q[3] = {dseed<3>(cen[0], 0), dseed<3>(cen[1], 1), dseed<3>(cen[2], 2)};
+  Dual<3> s = Scal<Dual<3>>::c(0.0);
+  double Abar = 0.0;
+  mls_each(G, a.ncls, q, [&](int, long long node, const Dual<3>(&psi)[4]) {
+    const Moments mo = streamed_moments<S>(a, node);
+    const double rho = 1.0 + mo.drho;
+    double fF = 0.0, uF = 0.0;
+    for (int k = 0; k < 3; k++) {
+      fF += Fl[k] * ib.fbar[(long long)k * G.Np + node];
+      uF += (mo.m[k] / rho) * Fbl[k];
+    }
+    s += psi[0] * (area * fF - uF);
+    Abar += psi[0].v * fF;
+    for (int k = 0; k < 3; k++) atomicAdd(ib.ext + (long long)(4 + k) * G.Np + node, -psi[0].v * Fbl[k]);
+    set_tile(ib.etf, node);
+  });
+  // d area / d vertex: (1/2) n x (opposite edge), counter-clockwise
+  for (int r = 0; r < 3; r++) {
+    const double* xb = b.Xcur + 3 * vv[(r + 1) % 3];
+    const double* xc = b.Xcur + 3 * vv[(r + 2) % 3];
+    const double e[3] = {xc[0] - xb[0], xc[1] - xb[1], xc[2] - xb[2]};
+    const double dA[3] = {0.5 * (n[1] * e[2] - n[2] * e[1]), 0.5 * (n[2] * e[0] - n[0] * e[2]),
+                          0.5 * (n[0] * e[1] - n[1] * e[0])};
+    for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * vv[r] + k, s.d[k] / 3.0 + Abar * dA[k]);
+  }
+}
+
+// Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations:
+// eigenvalues in d, eigenvectors in the columns of V.
+__device__ void jacobi3(double (&M)[3][3], double (&d)[3], double (&V)[3][3]) {
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) V[i][j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 50; sweep++) {
+    const double off = M[0][1] * M[0][1] + M[0][2] * M[0][2] + M[1][2] * M[1][2];
+    const double dg = M[0][0] * M[0][0] + M[1][1] * M[1][1] + M[2][2] * M[2][2];
+    if (off <= 1e-36 * dg) break;
+    for (int p = 0; p < 2; p++)
+      for (int q = p + 1; q < 3; q++) {
+        if (M[p][q] == 0.0) continue;
+        const double th = (M[q][q] - M[p][p]) / (2.0 * M[p][q]);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; k++) {  // M <- M J
+          const double mkp = M[k][p], mkq = M[k][q];
+          M[k][p] = c * mkp - sn * mkq;
+          M[k][q] = sn * mkp + c * mkq;
+        }
+        for (int k = 0; k < 3; k++) {  // M <- J^T M
+          const double mpk = M[p][k], mqk = M[q][k];
+          M[p][k] = c * mpk - sn * mqk;
+          M[q][k] = sn * mpk + c * mqk;
+        }
+        for (int k = 0; k < 3; k++) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < 3; i++) d[i] = M[i][i];
+}
+
+// Taylor deformation of a body, D = (sqrt(l1) - sqrt(l3)) / (sqrt(l1) +
+// sqrt(l3)) from the largest and smallest eigenvalues of the vertex
+// second-moment tensor M = sum (x - xbar)(x - xbar)^T / n; one block.  Adds
+// D to *jsum, or theta dD/dx = theta (2/n) G (x - xbar) to aP, with G =
+// dD/dl1 v1 v1^T + dD/dl3 v3 v3^T.
+__global__ __launch_bounds__(256) void k_taylor(BodyArgs b, const double* X, int body, double theta, double* aP,
+                                                double* jsum) {
+  __shared__ double sh[8];
+  __shared__ double s_G[9], s_m[3];
+  const int v0 = b.b_vert0[body], nvb = b.b_nv[body];
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int v = v0 + threadIdx.x; v < v0 + nvb; v += 256)
+    for (int k = 0; k < 3; k++) m[k] += X[3 * v + k];
+  for (int k = 0; k < 3; k++) m[k] = block_sum(m[k], sh) / nvb;
+  double M6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int v = v0 + threadIdx.x; v < v0 + nvb; v += 256) {
+    const double d[3] = {X[3 * v] - m[0], X[3 * v + 1] - m[1], X[3 * v + 2] - m[2]};
+    M6[0] += d[0] * d[0];
+    M6[1] += d[0] * d[1];
+    M6[2] += d[0] * d[2];
+    M6[3] += d[1] * d[1];
+    M6[4] += d[1] * d[2];
+    M6[5] += d[2] * d[2];
+  }
+  for (int k = 0; k < 6; k++) M6[k] = block_sum(M6[k], sh) / nvb;
+  if (threadIdx.x == 0) {
+    double M[3][3] = {{M6[0], M6[1], M6[2]}, {M6[1], M6[3], M6[4]}, {M6[2], M6[4], M6[5]}};
+    double d[3], V[3][3];
+    jacobi3(M, d, V);
+    int i1 = 0, i3 = 0;
+    for (int i = 1; i < 3; i++) {
+      if (d[i] > d[i1]) i1 = i;
+      if (d[i] < d[i3]) i3 = i;
+    }
+    const double a = sqrt(d[i1]), c = sqrt(d[i3]), s2 = (a + c) * (a + c);
+    if (jsum) *jsum += (a - c) / (a + c);
+    const double g1 = c / (a * s2), g3 = -a / (c * s2);  // dD/dl1, dD/dl3
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) s_G[3 * i + j] = g1 * V[i][i1] * V[j][i1] + g3 * V[i][i3] * V[j][i3];
+    for (int k = 0; k < 3; k++) s_m[k] = m[k];
+  }
+  __syncthreads();
+  if (!aP) return;
+  for (int v = v0 + threadIdx.x; v < v0 + nvb; v += 256) {
+    const double d[3] = {X[3 * v] - s_m[0], X[3 * v + 1] - s_m[1], X[3 * v + 2] - s_m[2]};
+    for (int i = 0; i < 3; i++)
+      aP[3 * v + i] += theta * 2.0 / nvb * (s_G[3 * i] * d[0] + s_G[3 * i + 1] * d[1] + s_G[3 * i + 2] * d[2]);
+  }
+}
+
+// Zero the extra adjoint sources and the fixed-point force in flagged
+// tiles (data first, then, in a second launch, the flags).
+__global__ __launch_bounds__(256) void k_adjb_clear_data(Grid G, double* ext, const uint8_t* etf, long long* fx,
+                                                         const uint8_t* ftf) {
+  const long long n = blockIdx.x * 256LL + threadIdx.x;
+  if (n >= G.Np) return;
+  if (etf[n >> TILE_SHIFT])
+    for (int k = 0; k < 7; k++) ext[(long long)k * G.Np + n] = 0.0;
+  if (ftf[n >> TILE_SHIFT])
+    for (int k = 0; k < 3; k++) fx[(long long)k * G.Np + n] = 0;
+}
+__global__ __launch_bounds__(256) void k_adjb_clear_flags(long long ntiles, uint8_t* etf, uint8_t* ftf) {
+  const long long t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= ntiles) return;
+  etf[t] = 0;
+  ftf[t] = 0;
+}
+
+// <w, g> at the non-solid nodes (those with amask bit 31 when use_mask),
+// each block adding its sum to part[block] (grid-stride, fixed order).
+template <class S>
+__global__ __launch_bounds__(256) void k_adj_wdot(FluidArgs a, const S* g, const double* w, const uint32_t* amask,
+                                                  int use_mask, double* part) {
+  __shared__ double sh[8];
+  const Grid& G = a.g;
+  double acc = 0.0;
+  const int count = a.nbulk_nodes + a.nrec;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < count; t += gridDim.x * 256) {
+    if (use_mask && !(amask[t] >> 31)) continue;
+    const long long n = t < a.nbulk_nodes ? (long long)a.bulk_list[t] : (long long)a.rec_node[t - a.nbulk_nodes];
+    for (int j = 0; j < 19; j++)
+      acc += w[(long long)j * G.plane + n] * (double)to_c(g[(long long)j * G.plane + n]);
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] += acc;
+}
+
+__global__ void k_adj_sum(const double* part, int n, double* out) {
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (int k = 0; k < n; k++) t += part[k];
+  *out = t;
+}
+
+hipError_t launch_adjb_vertex(const BodyArgs& b, const AdjIB& ib, hipStream_t s) {
+  if (b.nsoft_v > 0) k_adjb_vertex<<<cdiv(b.nsoft_v, 256), 256, 0, s>>>(b, ib);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjb_body(int prec, const FluidArgs& a, const BodyArgs& b, const AdjIB& ib, hipStream_t s) {
+  const long long items = (long long)b.ne + b.nh + b.nf + b.nsoft_v;
+  if (items == 0) return hipSuccess;
+  const unsigned grid = cdiv(items, 128);
+  switch (prec) {
+    case 0: k_adjb_body<double><<<grid, 128, 0, s>>>(a, b, ib); break;
+    case 1: k_adjb_body<float><<<grid, 128, 0, s>>>(a, b, ib); break;
+    default: k_adjb_body<_Float16><<<grid, 128, 0, s>>>(a, b, ib); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjb_volume(const BodyArgs& b, const AdjIB& ib, hipStream_t s) {
+  if (b.nf > 0) k_adjb_volume<<<cdiv(b.nf, 256), 256, 0, s>>>(b, ib);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjb_support(const Grid& g, const uint8_t* ncls, const BodyArgs& b, uint8_t* etf, hipStream_t s) {
+  if (b.nf > 0) k_adjb_support<<<cdiv(b.nf, 256), 256, 0, s>>>(g, ncls, b, etf);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjb_markers(int prec, const FluidArgs& a, const BodyArgs& b, const AdjIB& ib, hipStream_t s) {
+  if (b.nf == 0) return hipSuccess;
+  const unsigned grid = cdiv(b.nf, 128);
+  switch (prec) {
+    case 0: k_adjb_markers<double><<<grid, 128, 0, s>>>(a, b, ib); break;
+    case 1: k_adjb_markers<float><<<grid, 128, 0, s>>>(a, b, ib); break;
+    default: k_adjb_markers<_Float16><<<grid, 128, 0, s>>>(a, b, ib); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_taylor(const BodyArgs& b, const double* X, int body, double theta, double* aP, double* jsum,
+                         hipStream_t s) {
+  k_taylor<<<1, 256, 0, s>>>(b, X, body, theta, aP, jsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjb_clear(const Grid& g, double* ext, uint8_t* etf, long long* fx, uint8_t* ftf, hipStream_t s) {
+  const long long ntiles = (g.Np >> TILE_SHIFT) + 1;
+  k_adjb_clear_data<<<cdiv(g.Np, 256), 256, 0, s>>>(g, ext, etf, fx, ftf);
+  k_adjb_clear_flags<<<cdiv(ntiles, 256), 256, 0, s>>>(ntiles, etf, ftf);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_wdot(int prec, const FluidArgs& a, const void* g, const double* w, const uint32_t* amask,
+                           int use_mask, double* part, hipStream_t s) {
+  const int count = a.nbulk_nodes + a.nrec;
+  if (count == 0) return hipSuccess;
+  const unsigned grid = std::min<unsigned>(cdiv(count, 256), ADJ_BLOCKS);
+  switch (prec) {
+    case 0: k_adj_wdot<double><<<grid, 256, 0, s>>>(a, (const double*)g, w, amask, use_mask, part); break;
+    case 1: k_adj_wdot<float><<<grid, 256, 0, s>>>(a, (const float*)g, w, amask, use_mask, part); break;
+    default: k_adj_wdot<_Float16><<<grid, 256, 0, s>>>(a, (const _Float16*)g, w, amask, use_mask, part); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_sum(const double* part, int n, double* out, hipStream_t s) {
+  k_adj_sum<<<1, 64, 0, s>>>(part, n, out);
+  return hipGetLastError();
 }
 
 }  // namespace lbm
