@@ -166,9 +166,22 @@ def default_precision(workload):
     return {"pipe_sphere": "f64", "precision_form": "f16s"}.get(workload, "f32")
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, target_s=15.0):
     """The FP64 oracle as it stands, on the host cores, on a bounded sample of
-    the same workload (the first steps after release)."""
+    the same workload (the first steps after release); then the same with
+    one thread, on a shorter sample."""
     import oracle
     t0 = time.time()
     sim = oracle.from_workload(w)
@@ -181,10 +194,43 @@ def cpu_baseline(w, target_s=15.0):
     sim.step(n)
     dt = time.time() - t
     nf = w.domain.n_fluid
-    return {"value": round(nf * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.lib().orc_threads(),
-            "kind": "oracle",
-            "sample": f"{w.name}: {n} steps (after 2 untimed) of the same grid and bodies, "
-                      f"FP64, {dt:.1f} s (+{setup:.1f} s setup), lattice updates counted on fluid nodes"}
+    threads = oracle.lib().orc_threads()
+    oracle.lib().orc_set_threads(1)
+    t = time.time()
+    sim.step(1)
+    per1 = time.time() - t
+    n1 = max(1, min(500, int(target_s / 3 / max(per1, 1e-6))))
+    t = time.time()
+    sim.step(n1)
+    dt1 = time.time() - t
+    oracle.lib().orc_set_threads(0)
+    return {"value": round(nf * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "value_1_thread": round(nf * n1 / dt1 / 1e6, 3), "cpu_model": cpu_model(),
+            "sample": f"{w.name}: {n} steps (after 2 untimed) of the same grid and bodies on {threads} "
+                      f"threads, FP64, {dt:.1f} s (+{setup:.1f} s setup); then {n1} steps on 1 thread, "
+                      f"{dt1:.1f} s; lattice updates counted on fluid nodes"}
+
+
+def measured_copy_gbs(nbytes=1.024e9, reps=10):
+    """Bandwidth of a plain device-to-device copy of nbytes (read + write
+    bytes over the time of reps copies, HIP events): the achievable figure
+    beside the datasheet peak."""
+    import torch
+    n = int(nbytes / 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
 
 
 def cpu_baseline_batch(ws, target_s=15.0):
@@ -340,24 +386,29 @@ def adj_bytes_per_step(n_fluid, n_records, n_w, s):
 
 
 def run_adjoint(args):
-    """The differentiation form: gradients of the time-integrated upper
-    daughter flux of the fluid-only bifurcation (256x128x40, D = 32, from
-    rest) with respect to the inlet-velocity scale and the body force, over
-    args.steps steps with checkpoints every args.checkpoint_every steps, in
-    one call of the adjoint (states in the lattice's precision, FP32 unless
-    --precision f64; the adjoint in FP64); then the same number of plain
-    steps of the same lattice for the comparison."""
+    """The differentiation form: the bifurcation of the single-capsule case
+    (256x128x40, D = 32) after its particle-free precursor, with the
+    2562-vertex capsule released; one call of the coupled adjoint over
+    args.steps steps with checkpoints every args.checkpoint_every steps
+    (states in the lattice's precision, FP32 unless --precision f64; the
+    adjoint in FP64) gives the gradients of the time-integrated Taylor
+    deformation of the capsule plus the upper daughter's flux with respect to
+    the inlet-velocity scale, the body force, the relaxation time and the
+    membrane stiffness; then the same number of plain coupled steps of the
+    same lattice for the comparison."""
     import torch
     import numpy as np
     import paper_2207_06043_amd as P
     import synth
     w = synth.bifurcation_capsule(precision="f64")
-    w.bodies = []
-    w.name = "differentiation_form (the bifurcation without its capsule)"
     d = w.domain
     torch.cuda.set_device(0)
     precision = args.precision or "f32"
     lat = P.Lattice(d, w.tau, w.u_max, precision)
+    if args.precursor > 0:
+        lat.step(args.precursor)
+        lat.sync()
+    lat.add_body(w.bodies[0])
     info = lat.info()
     n_fluid, n_box = info["n_fluid"], info["n_nodes"]
     out_nodes = np.flatnonzero(d.node_type == synth.OUTLET)
@@ -366,22 +417,21 @@ def run_adjoint(args):
     wv = torch.zeros(19, d.n_nodes, dtype=torch.float64)
     wv[:, torch.from_numpy(up)] = e_y[:, None]
     wv = wv.cuda()
-    lam0 = torch.zeros(19, d.n_nodes, dtype=torch.float64, device="cuda")
     K = args.checkpoint_every
     if args.warmup > 0:
-        lat.adjoint(args.warmup, lam0, wv, checkpoint_every=K)
+        lat.adjoint_run(args.warmup, None, wv, taylor_weight=1.0, checkpoint_every=K)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(lat.stream)
-    lam, grad = lat.adjoint(args.steps, lam0, wv, checkpoint_every=K)
+    lam, grad, _, J = lat.adjoint_run(args.steps, None, wv, taylor_weight=1.0, checkpoint_every=K)
     ev1.record(lat.stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     gpu_s = ev0.elapsed_time(ev1) * 1e-3
     value = n_fluid * args.steps / elapsed / 1e6
-    # the same number of plain steps of the same lattice
+    # the same number of plain coupled steps of the same lattice
     lat.step(args.warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -411,10 +461,14 @@ def run_adjoint(args):
             "grid": [d.nx, d.ny, d.nz],
             "fluid_nodes": n_fluid,
             "box_nodes": n_box,
-            "bodies": 0,
+            "bodies": 1,
+            "vertices": info["n_vertices"],
+            "precursor_steps": args.precursor,
             "checkpoint_every": K,
-            "objective": ("time-integrated upper-daughter flux; gradient w.r.t. inlet-velocity scale, "
-                          "body force and relaxation time"),
+            "objective": ("sum over the steps of the capsule's Taylor deformation plus the upper daughter's "
+                          "outward flux; gradient w.r.t. inlet-velocity scale, body force, relaxation time "
+                          "and membrane-stiffness scale"),
+            "J": [float(J[0]), float(J[1])],
             "lups_counted_on": "fluid nodes x adjoint steps (forward pass, recompute and reverse step included)",
             "plain_mlups": round(plain, 2),
             "adjoint_vs_plain": round(value / plain, 4),
@@ -423,9 +477,9 @@ def run_adjoint(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("one adjoint step: k_adj_reverse_all (transposed streaming and bounce-back, collision "
-                       "and Zou-He transposes; records and bulk nodes in one launch) plus the forward-pass and "
-                       "recompute launches of k_adj_fwd_all"),
+            "kernel": ("one coupled adjoint step: the fluid step back (k_adj_reverse_all, twice: force "
+                       "adjoint at the forced nodes, then the whole step) with the forward-pass, recompute "
+                       "and re-run launches of k_adj_fwd_all, and the IB transposes (k_adjb_*)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -433,12 +487,13 @@ def run_adjoint(args):
             "traffic": measured_traffic("differentiation_form", precision),
             "bytes_per_step_alg": bytes_step,
             "avg_step_us": round(gpu_s / args.steps * 1e6, 3),
+            "peak_copy_measured": measured_copy_gbs(),
         },
     }
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, args.cpu_seconds)
-        cb["sample"] += ("; forward steps only: the oracle has no adjoint, a central-difference "
-                         "derivative costs two such runs per parameter")
+        cb["sample"] += ("; forward coupled steps only (from rest): a central-difference derivative "
+                         "costs two such runs per parameter")
         out["cpu_baseline"] = cb
     print(json.dumps(out))
 
@@ -502,7 +557,7 @@ def main():
     # 2000-step precursor, the precision form 2000 steps after a 1000-step
     # precursor, the batching form 1000 steps
     lengths = {"precision_form": (1000, 100, 1900), "batch_instances": (0, 50, 950),
-               "differentiation_form": (0, 200, 2000)}
+               "differentiation_form": (2000, 200, 2000)}
     pre, warm, steps = lengths.get(args.workload, (2000, 200, 5000))
     args.precursor = pre if args.precursor is None else args.precursor
     args.warmup = warm if args.warmup is None else args.warmup
@@ -569,7 +624,10 @@ def main():
             "vertices": info["n_vertices"],
             "lups_counted_on": "fluid nodes",
             "mlups_box": round(n_box * args.steps / elapsed / 1e6, 2),
-            "markers_per_s": round(info["n_faces"] * 3 * args.steps / elapsed, 1) if w.bodies else 0,
+            # MLS points per step: forcing marker and two probes per face, one
+            # velocity interpolation per vertex of a soft body
+            "markers_per_s": round((info["n_faces"] * 3 + info["n_vertices"]) * args.steps / elapsed, 1)
+            if w.bodies else 0,
             "precursor_steps": args.precursor if w.bodies else 0,
             "parallelism": "single GPU",
             "cache_note": "working set %.1f MB fits the 256 MB Infinity Cache" % (bytes_alg / 1e6)
@@ -588,6 +646,8 @@ def main():
             "traffic": traffic,
             "bytes_per_launch_alg": bytes_alg,
             "avg_launch_us": round(avg_ms * 1e3, 3),
+            "peak_copy_measured": measured_copy_gbs(),
+            "working_set_in_infinity_cache": bool(bytes_alg < 200e6),
         },
     }
     if not args.no_cpu_baseline:

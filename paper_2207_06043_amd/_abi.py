@@ -481,46 +481,45 @@ def _trajectory_class():
         import torch
 
         class Trajectory(torch.autograd.Function):
-            """J(f0) = <lam, f^n> + sum_{t=1..n} <w, f^t> over n steps of a
-            lattice started from the populations f0; the backward pass is the
-            lattice's discrete adjoint (lbm_adjoint_step) from f0."""
+            """J(f0, p) = <lam, g^n> + sum_{t=1..n} <w, g^t> + taylor_weight
+            sum_t D_T over n steps of a lattice started from the populations
+            f0 (its bodies from their current state), with p = (inlet scale,
+            membrane-stiffness scale).  The forward pass runs the lattice's
+            discrete adjoint sweep once (lbm_adjoint_run: J from the
+            recomputed trajectory, and every derivative); the backward pass
+            scales the derivatives by the incoming gradient."""
 
             @staticmethod
-            def forward(ctx, f0, lat, n_steps, w, lam, checkpoint_every):
+            def forward(ctx, f0, params, lat, n_steps, w, lam, checkpoint_every, taylor_weight, taylor_body):
+                if params is not None:
+                    lat.set_scales(float(params[0]), float(params[1]))
                 lat.set_populations(f0)
-                J = torch.zeros((), dtype=torch.float64, device=lat.device)
-                for _ in range(n_steps):
-                    lat.step(1)
-                    if w is not None:
-                        J += (w * lat.populations()).sum()
-                if lam is not None:
-                    J += (lam * lat.populations()).sum()
-                ctx.save_for_backward(f0)
-                ctx.lat, ctx.n, ctx.w, ctx.lam, ctx.k = lat, n_steps, w, lam, checkpoint_every
-                return J
+                g0, grad, _, J = lat.adjoint_run(n_steps, lam, w, taylor_weight, taylor_body, checkpoint_every)
+                ctx.g0, ctx.grad, ctx.has_p = g0, grad, params is not None
+                ctx.inlet, ctx.stiff = (float(params[0]), float(params[1])) if params is not None else (1.0, 1.0)
+                return torch.tensor(J[0] + taylor_weight * J[1], dtype=torch.float64, device=lat.device)
 
             @staticmethod
             def backward(ctx, gJ):
-                (f0,) = ctx.saved_tensors
-                lat = ctx.lat
-                end = lat.populations()
-                lat.set_populations(f0)
-                lam = torch.zeros(19, lat.N, dtype=torch.float64, device=lat.device)
-                if ctx.lam is not None:
-                    lam = gJ * ctx.lam
-                w = None if ctx.w is None else gJ * ctx.w
-                g0, _ = lat.adjoint(ctx.n, lam, w, checkpoint_every=ctx.k)
-                lat.set_populations(end)  # the lattice is left at the trajectory's end
-                return g0.reshape(f0.shape), None, None, None, None, None
+                dp = None
+                if ctx.has_p:
+                    # dJ/ds for the inlet scale; dJ/dkappa for the stiffness scale
+                    dp = gJ * torch.stack([ctx.grad[0], ctx.grad[5]])
+                return gJ * ctx.g0, dp, None, None, None, None, None, None, None
 
         _TRAJECTORY = Trajectory
     return _TRAJECTORY
 
 
-def trajectory(lat, f0, n_steps, w=None, lam=None, checkpoint_every=100):
-    """Differentiable J(f0) = <lam, f^n> + sum_{t=1..n} <w, f^t> ([19][N]
-    weights, FP64, on the lattice's device) over n_steps steps of lat from
-    the populations f0; J.backward() gives dJ/df0 through the discrete
-    adjoint.  Fluid-only FP64 or FP32 lattices (lbm_adjoint_step's scope).
-    The lattice is left at the trajectory's end."""
-    return _trajectory_class().apply(f0, lat, int(n_steps), w, lam, int(checkpoint_every))
+def trajectory(lat, f0, n_steps, w=None, lam=None, checkpoint_every=100, params=None, taylor_weight=0.0,
+               taylor_body=0):
+    """Differentiable J(f0, params) = <lam, g^n> + sum_{t=1..n} <w, g^t> +
+    taylor_weight * sum_t D_T(body taylor_body) over n_steps steps of lat from
+    the populations f0 ([19][N] FP64 on the lattice's device; g = f - w_i);
+    params (optional, FP64 tensor of 2): the inlet-velocity scale and the
+    membrane-stiffness scale (lbm_set_scales), else the lattice's current
+    scales.  J.backward() gives dJ/df0 and dJ/dparams through the discrete
+    adjoint (lbm_adjoint_run; soft bodies, at most one).  The lattice is left
+    holding f0 (the sweep does not step it), at the scales params."""
+    return _trajectory_class().apply(f0, params, lat, int(n_steps), w, lam, int(checkpoint_every),
+                                     float(taylor_weight), int(taylor_body))

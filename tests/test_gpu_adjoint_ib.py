@@ -207,3 +207,27 @@ def test_scales_step_like_the_oracle_with_scaled_parameters(lib):
     assert np.abs(ug[:, fl] - uo[:, fl]).max() <= 1e-12 * np.abs(uo[:, fl]).max()
     xo = o.body(0)[0]
     assert np.abs(lat.body(0)[0].cpu().numpy() - xo).max() <= 1e-12 * np.abs(xo - w.bodies[0].x).max()
+
+
+def test_trajectory_autograd_with_parameters(lib):
+    """torch.autograd through the coupled adjoint: J(f0, (s, kappa)) with the
+    capsule's Taylor term; backward gives dJ/df0 and dJ/d(s, kappa), equal
+    to the oracle's reverse-mode derivatives."""
+    name, n = "pipe", 10
+    w = _case(name)
+    ref = _reference(name, n, THETA[name])
+    lat = lib.from_workload(w)
+    f0 = lat.populations().clone().requires_grad_(True)
+    p = torch.tensor([1.0, 1.0], dtype=torch.float64, device=f0.device, requires_grad=True)
+    dev = f0.device
+    _say("[adjoint-ib] autograd with parameters")
+    J = lib.trajectory(lat, f0, n, torch.from_numpy(ref["w"]).to(dev), torch.from_numpy(ref["lam"]).to(dev),
+                       checkpoint_every=4, params=p, taylor_weight=THETA[name])
+    J.backward()
+    Jref = ref["J"][0] + THETA[name] * ref["J"][1]
+    assert abs(float(J) - Jref) <= 1e-12 * abs(Jref)
+    gp = p.grad.cpu().numpy()
+    want = np.array([ref["grad"][0], ref["grad"][5]])
+    assert (np.abs(gp - want) <= 1e-9 * np.abs(want)).all(), (gp, want)
+    g0 = f0.grad.cpu().numpy()
+    assert np.abs(g0 - ref["g0"]).max() <= 1e-10 * np.abs(ref["g0"]).max()
