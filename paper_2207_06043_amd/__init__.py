@@ -6,5 +6,7 @@ ABI in ``include/lbm.h``; this package only marshals arguments to it.
 from ._abi import (EXPORTS, LIB_PATH, LBM_E_DAMAGED, LBM_E_UNSTABLE, LBM_E_UNSUPPORTED, LBM_OK, Batch,
                    Lattice, LbmError, from_workload, load_library, trajectory)
 
-__all__ = ["EXPORTS", "LIB_PATH", "LBM_E_DAMAGED", "LBM_E_UNSTABLE", "LBM_E_UNSUPPORTED", "LBM_OK", "Batch",
+from . import campaign  # noqa: E402
+
+__all__ = ["campaign", "EXPORTS", "LIB_PATH", "LBM_E_DAMAGED", "LBM_E_UNSTABLE", "LBM_E_UNSUPPORTED", "LBM_OK", "Batch",
            "Lattice", "LbmError", "from_workload", "load_library", "trajectory"]

@@ -15,11 +15,13 @@ from .geometry import (FLUID, SOLID, INLET, OUTLET, D3Q19_DIRS, Domain,
 from .mesh import icosphere, Body
 from .configs import (Workload, pipe_sphere, bifurcation_capsule,
                       precision_form, periodic_r0, pipe_r1, tiny_pipe,
-                      tiny_bifurcation, facing_pair, batch_instance, batch_instances, get)
+                      tiny_bifurcation, facing_pair, batch_instance, batch_instances, get,
+                      capsule_train, tiny_train, TRAIN_KINDS)
 
 __all__ = [
     "FLUID", "SOLID", "INLET", "OUTLET", "D3Q19_DIRS", "Domain",
     "periodic_box", "pipe", "bifurcation", "icosphere", "Body", "Workload", "facing_pair", "batch_instance",
     "pipe_sphere", "bifurcation_capsule", "precision_form", "periodic_r0",
-    "pipe_r1", "tiny_pipe", "tiny_bifurcation", "batch_instances", "get",
+    "pipe_r1", "tiny_pipe", "tiny_bifurcation", "batch_instances", "get", "capsule_train", "tiny_train",
+    "TRAIN_KINDS",
 ]

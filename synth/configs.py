@@ -319,6 +319,69 @@ def tiny_bifurcation(seed=0, precision="f64", steps=20, n_bodies=1, subdiv=2):
                     meta={"seed": seed})
 
 
+TRAIN_KINDS = {"soft": ("soft", "soft", "soft"), "rigid_top": ("rigid", "soft", "soft"),
+               "rigid_middle": ("soft", "rigid", "soft"), "rigid_bottom": ("soft", "soft", "rigid"),
+               "all_rigid": ("rigid", "rigid", "rigid")}
+
+
+def _train_bodies(kinds, x0, spacing, yc, zc, rp, ca, eb, u_ref, subdiv, rigid_subdiv):
+    """A train along the axis: body k at x0 + k spacing (k = 0 the one
+    nearest the inlet); "soft" a deformable capsule of radius rp, "rigid" a
+    rigid sphere of half its diameter and the same density."""
+    bodies = []
+    for k, kind in enumerate(kinds):
+        c = (x0 + k * spacing, yc, zc)
+        if kind == "soft":
+            X, F = icosphere(subdiv, rp, c, tilt=True)
+            b = Body(X, F, rigid=False, ca=ca, eb=eb, rho_ratio=1.1, r_ref=rp, u_ref=u_ref)
+        else:
+            X, F = icosphere(rigid_subdiv, rp / 2.0, c, tilt=True)
+            b = Body(X, F, rigid=True, ca=ca, eb=eb, rho_ratio=1.1, r_ref=rp / 2.0, u_ref=u_ref)
+        assert off_switch_planes(X, F)
+        bodies.append(b)
+    return bodies
+
+
+def capsule_train(train="soft", seed=0, precision="f32", steps=5000, theta_deg=60.0, junction="smooth",
+                  ca=0.01, eb=1e-4):
+    """A train of three capsules in the Y-bifurcation of the single-capsule
+    workload (256x128x40, D = 32, daughters 0.8 D, fillet 4, Re = 10, tau =
+    0.7) with the given junction ('smooth': the trapezoidal chamber with a
+    flat wall; 'sharp').  Occlusion ratio 2/3 (r_p = D/3, 2562 vertices),
+    the first capsule at 1.16 D from the inlet, the others downstream at a
+    mutual centre distance of 0.85 D, all on the line y = (ny-1)/2 + dy with
+    dy drawn first from U[-0.1 D, 0.1 D] (seed).  ``train`` picks the kinds
+    (TRAIN_KINDS): all soft, one rigid sphere of half the capsule diameter
+    in the top (nearest the inlet), middle or bottom place, or three rigid
+    spheres.  Ca = 0.01 and Eb = 1e-4 (the bending number of the
+    single-capsule workload)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz, D = 256, 128, 40, 32.0
+    tau = 0.7
+    nu = (tau - 0.5) / 3.0
+    u_max = 10.0 * nu / D
+    dom = bifurcation(nx, ny, nz, D, 0.8, theta_deg, 4.0, u_max=u_max, junction=junction)
+    dy = rng.uniform(-0.1 * D, 0.1 * D)
+    bodies = _train_bodies(TRAIN_KINDS[train], 1.16 * D, 0.85 * D, (ny - 1) / 2.0 + dy, (nz - 1) / 2.0,
+                           D / 3.0, ca, eb, u_max, 4, 3)
+    return Workload(f"capsule_train_{train}", dom, bodies, tau, u_max, precision, steps,
+                    meta={"offset": dy, "seed": seed, "junction": junction, "train": train, "D": D})
+
+
+def tiny_train(train="soft", seed=0, precision="f64", steps=30, junction="smooth"):
+    """Small variant of capsule_train for parity checks: the 64x40x16
+    bifurcation of tiny_bifurcation (D = 12) with the chosen junction and a
+    train of three capsules of radius 2.6 (162 vertices) spaced 0.85 D from
+    x = 6 (rigid: radius 1.3, 42 vertices)."""
+    rng = np.random.default_rng(seed)
+    tau, D, u_max = 0.7, 12.0, 0.02
+    dom = bifurcation(64, 40, 16, D, 0.8, 60.0, 2.0, x_junction=32.0, u_max=u_max, junction=junction)
+    dy = rng.uniform(-0.1 * D, 0.1 * D)
+    bodies = _train_bodies(TRAIN_KINDS[train], 6.0, 0.85 * D, 19.5 + dy, 7.5, 2.6, 0.05, 0.001, u_max, 2, 1)
+    return Workload(f"tiny_train_{train}", dom, bodies, tau, u_max, precision, steps,
+                    meta={"seed": seed, "junction": junction, "train": train})
+
+
 _REGISTRY = {
     "pipe_sphere": pipe_sphere,
     "bifurcation_capsule": bifurcation_capsule,
@@ -328,6 +391,8 @@ _REGISTRY = {
     "tiny_pipe": tiny_pipe,
     "tiny_bifurcation": tiny_bifurcation,
     "facing_pair": facing_pair,
+    "capsule_train": capsule_train,
+    "tiny_train": tiny_train,
 }
 
 

@@ -254,8 +254,37 @@ def _edge_band_sdf(nx, ny, nz, band):
     return sdf
 
 
+def _junction_chamber_sdf(params):
+    """The smooth junction: a prism whose section in the plane of the
+    bifurcation is a trapezoid, from the end of the main tube (x = x_j) to a
+    flat wall at x_j + H, H = Rd / sin(theta) + Rd (one daughter radius past
+    the apex of the sharp junction, where the daughters' inner walls meet),
+    its sides along the daughters' outer walls, its thickness the daughters'
+    diameter.  The value is the largest signed distance to its bounding
+    planes (exact in sign, a lower bound in size)."""
+    Rd = params["Rd"]
+    J = np.asarray(params["J"], np.float64)
+    th = params["theta"]
+    H = Rd / np.sin(th) + Rd
+    sl = np.tan(th) if th < np.pi / 2 - 1e-9 else None
+    cth = np.cos(th)
+
+    def sdf(p):
+        p = np.atleast_2d(p)
+        rel = p - J
+        xp, yp, zp = rel[:, 0], np.abs(rel[:, 1]), np.abs(rel[:, 2])
+        d = np.maximum(-xp, xp - H)
+        d = np.maximum(d, zp - Rd)
+        if sl is not None:
+            # side plane y = x tan(theta) + Rd / cos(theta), unit normal
+            # (-sin(theta), cos(theta))
+            d = np.maximum(d, (yp - xp * sl - Rd / cth) * cth)
+        return d
+    return sdf
+
+
 def bifurcation(nx, ny, nz, D, daughter_ratio=0.8, theta_deg=60.0, fillet=4.0,
-                x_junction=None, u_max=0.0, init="rest", edge_band=0.0):
+                x_junction=None, u_max=0.0, init="rest", edge_band=0.0, junction="sharp"):
     """Symmetric Y-bifurcation: main tube of diameter D along x centred at
     (y, z) = ((ny-1)/2, (nz-1)/2), junction at x = x_junction (default nx/2),
     daughters of diameter daughter_ratio*D at the semi-aperture angle
@@ -267,12 +296,21 @@ def bifurcation(nx, ny, nz, D, daughter_ratio=0.8, theta_deg=60.0, fillet=4.0,
     nodes within that distance of a box edge solid (a daughter tube leaving
     through a box edge would otherwise put open-boundary nodes on two faces);
     the wall there is a plane of the band, with its own link fractions.
+    ``junction='smooth'`` replaces the sharp apex between the daughters by
+    the flat wall of a trapezoidal chamber (the paper's two junctions).
     """
     yc, zc = (ny - 1) / 2.0, (nz - 1) / 2.0
     xj = nx / 2.0 if x_junction is None else x_junction
     params = {"R": D / 2.0, "Rd": daughter_ratio * D / 2.0, "J": (xj, yc, zc),
-              "theta": np.deg2rad(theta_deg), "fillet": fillet}
+              "theta": np.deg2rad(theta_deg), "fillet": fillet, "junction": junction}
     sdf = bifurcation_sdf(params)
+    if junction == "smooth":
+        tubes, chamber = sdf, _junction_chamber_sdf(params)
+
+        def sdf(p):
+            return np.minimum(tubes(p), chamber(p))
+    elif junction != "sharp":
+        raise ValueError("junction: 'sharp' or 'smooth'")
     if edge_band > 0.0:
         tube, band = sdf, _edge_band_sdf(nx, ny, nz, edge_band)
 
