@@ -13,8 +13,14 @@ fluid (non-solid) nodes; the box-node rate is reported alongside.
 Other workloads: ``--workload precision_form`` (512x256x64 bifurcation with
 16 capsules, FP16 storage by default), ``--workload batch_instances`` (the
 batching form: 64 bifurcations of uneven size advanced together, tuned, and
-compared with the same instances stepped one by one), and the bandwidth
-workloads ``periodic_r0`` and ``pipe_r1``.
+compared with the same instances stepped one by one), ``--workload
+differentiation_form`` (the coupled adjoint sweep with the capsule against the
+plain steps), ``--workload capsule_train`` (trains of three capsules, soft or
+with rigid spheres, ``--train``/``--junction``), ``pipe_sphere`` and the
+bandwidth workloads ``periodic_r0`` and ``pipe_r1``.  With ``--log-out`` the
+released steps run as a logged run (surface strain, centre, Taylor
+deformation and stretch of every body every ``--log-every`` steps, up to the
+damage stop) and the log is written to that file.
 """
 from __future__ import annotations
 
@@ -147,8 +153,10 @@ def summarize_counters(args):
     print(json.dumps(d[key]))
 
 
-def build_workload(name, precision):
+def build_workload(name, precision, train="soft", junction="smooth"):
     import synth
+    if name == "capsule_train":
+        return synth.capsule_train(train, precision=precision, junction=junction)
     if name == "bifurcation_capsule":
         return synth.bifurcation_capsule(precision=precision)
     if name == "pipe_sphere":
@@ -498,6 +506,38 @@ def run_adjoint(args):
     print(json.dumps(out))
 
 
+def run_logged(args, lat, w, info, precision):
+    """The released steps as a logged run (campaign.log_run): the surface
+    strain dS(t) = S/S0 - 1, centre, Taylor deformation and largest stretch
+    of every body every --log-every steps against t u_max / D, up to the
+    damage stop; the log goes to --log-out, the line reports the throughput
+    of the logged run (recording included)."""
+    import torch
+    import paper_2207_06043_amd as P
+    D = 2.0 * w.domain.meta["params"]["R"] if "params" in w.domain.meta else 1.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    log = P.campaign.log_run(lat, args.steps, args.log_every, w.u_max, D)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log.update({"workload": w.name, "precision": precision, "grid": [w.domain.nx, w.domain.ny, w.domain.nz],
+                "D": D, "u_max": w.u_max, "precursor_steps": args.precursor, "every": args.log_every,
+                "bodies": log["bodies"],
+                "kinds": ["rigid" if b.rigid else "soft" for b in w.bodies]})
+    with open(args.log_out, "w") as f:
+        json.dump(log, f)
+    n_fluid = info["n_fluid"]
+    done = max(log["steps_done"], 1)
+    out = {"metric": METRIC, "value": round(n_fluid * done / elapsed / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
+           "steps": done, "warmup": 0, "ms_per_step": round(elapsed / done * 1e3, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": precision, "data": "synthetic",
+           "config": {"workload": w.name, "logged_run": True, "log": args.log_out, "status": log["status"],
+                      "peak_dS": [b["peak_dS"] for b in log["bodies"]],
+                      "t_peak": [b["t_peak"] for b in log["bodies"]],
+                      "fluid_nodes": n_fluid, "bodies": len(w.bodies), "parallelism": "single GPU"}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -521,6 +561,14 @@ def main():
                     help="batch_instances: steps of each instance alone for the comparison")
     ap.add_argument("--checkpoint-every", type=int, default=100,
                     help="differentiation_form: checkpoint interval of the adjoint sweep")
+    ap.add_argument("--train", default="soft", help="capsule_train: soft, rigid_top, rigid_middle, "
+                    "rigid_bottom or all_rigid")
+    ap.add_argument("--junction", default="smooth", help="capsule_train: smooth or sharp")
+    ap.add_argument("--log-every", type=int, default=100,
+                    help="with --log-out: steps between records of the surface strain dS(t)")
+    ap.add_argument("--log-out", default=None,
+                    help="bodies: run the released steps as a logged run (dS, centre, Taylor deformation, "
+                         "stretch every --log-every steps, up to the damage stop) and write the log here")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
@@ -569,7 +617,7 @@ def main():
         run_adjoint(args)
         return
     precision = args.precision or default_precision(args.workload)
-    w = build_workload(args.workload, precision)
+    w = build_workload(args.workload, precision, args.train, args.junction)
     torch.cuda.set_device(0)
     lat = P.Lattice(w.domain, w.tau, w.u_max, precision)
     if args.precursor > 0 and w.bodies:
@@ -578,6 +626,9 @@ def main():
     for b in w.bodies:
         lat.add_body(b)
     info = lat.info()
+    if args.log_out and w.bodies:
+        run_logged(args, lat, w, info, precision)
+        return
     lat.step(args.warmup)
     lat.sync()
 

@@ -23,7 +23,8 @@ _lib = None
 # "store_f32" and "store_f16" round the stored populations to FP32 or to
 # binary16; "ldouble" runs the fluid state and arithmetic in long double (a
 # near-exact reference trajectory); "fullpop" stores full populations f
-# instead of the deviations f - w ("fullpop_ldouble": both).
+# instead of the deviations f - w ("fullpop_ldouble": both); "float" runs the
+# fluid state and arithmetic in binary32; "fma_reassoc" both fma and reassoc.
 VARIANT_FLAGS = {
     "plain": [],
     "fma": ["-mfma", "-ffp-contract=fast"],
@@ -33,6 +34,9 @@ VARIANT_FLAGS = {
     "ldouble": ["-DORC_LDOUBLE"],
     "fullpop": ["-DORC_FULL_POP"],
     "fullpop_ldouble": ["-DORC_FULL_POP", "-DORC_LDOUBLE"],
+    "float": ["-DORC_FLOAT"],
+    "fma_reassoc": ["-mfma", "-ffp-contract=fast", "-O3", "-mavx2", "-fassociative-math",
+                    "-fno-signed-zeros", "-fno-trapping-math"],
 }
 
 
@@ -192,6 +196,7 @@ class OracleSim:
                                _ptr(ir, C.c_double), _ptr(iv, C.c_double), err, 256)
         if not self._h:
             raise ValueError("oracle create failed: " + err.value.decode())
+        self._destroy = lib().orc_destroy  # still reachable at interpreter exit
         self.tau = tau
         self.bodies = []
         for b in bodies:
@@ -200,7 +205,7 @@ class OracleSim:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def add_body(self, b):

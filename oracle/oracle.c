@@ -57,9 +57,14 @@ enum { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3 };
  * double in the oracle; the measurement build ORC_LDOUBLE makes it long
  * double (64-bit significand) to give a near-exact trajectory against which
  * the rounding of the double builds is measured. */
-#ifdef ORC_LDOUBLE
+#if defined(ORC_LDOUBLE)
 typedef long double preal;
 #define PR(x) x##L
+#elif defined(ORC_FLOAT)
+/* measurement build only: the fluid state and arithmetic in binary32, to
+ * gauge how far FP32 arithmetic (not only FP32 storage) moves a trajectory */
+typedef float preal;
+#define PR(x) x##f
 #else
 typedef double preal;
 #define PR(x) x

@@ -16,12 +16,12 @@ from .mesh import icosphere, Body
 from .configs import (Workload, pipe_sphere, bifurcation_capsule,
                       precision_form, periodic_r0, pipe_r1, tiny_pipe,
                       tiny_bifurcation, facing_pair, batch_instance, batch_instances, get,
-                      capsule_train, tiny_train, TRAIN_KINDS)
+                      capsule_train, tiny_train, TRAIN_KINDS, outlet_flux_weights, terminal_weights)
 
 __all__ = [
     "FLUID", "SOLID", "INLET", "OUTLET", "D3Q19_DIRS", "Domain",
     "periodic_box", "pipe", "bifurcation", "icosphere", "Body", "Workload", "facing_pair", "batch_instance",
     "pipe_sphere", "bifurcation_capsule", "precision_form", "periodic_r0",
     "pipe_r1", "tiny_pipe", "tiny_bifurcation", "batch_instances", "get", "capsule_train", "tiny_train",
-    "TRAIN_KINDS",
+    "TRAIN_KINDS", "outlet_flux_weights", "terminal_weights",
 ]

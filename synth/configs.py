@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .geometry import Domain, bifurcation, periodic_box, pipe
+from .geometry import D3Q19_DIRS, OUTLET, SOLID, Domain, bifurcation, periodic_box, pipe
 from .mesh import Body, icosphere, off_switch_planes
 
 
@@ -394,6 +394,28 @@ _REGISTRY = {
     "capsule_train": capsule_train,
     "tiny_train": tiny_train,
 }
+
+
+def outlet_flux_weights(domain):
+    """Weights [19, N] of the outward fluxes of a bifurcation's two daughters:
+    (w_up, w_lo), e_iy at the outlet nodes of the upper face (y = ny - 1) and
+    -e_iy at those of the lower face (y = 0), zero elsewhere, so that
+    <w, f> = <w, f - w_i> is the daughter's outward y-momentum flux."""
+    ey = np.asarray(D3Q19_DIRS, dtype=np.float64)[:, 1]
+    out = np.flatnonzero(domain.node_type == OUTLET)
+    y = (out // domain.nx) % domain.ny
+    w_up = np.zeros((19, domain.n_nodes))
+    w_lo = np.zeros((19, domain.n_nodes))
+    w_up[:, out[y == domain.ny - 1]] = ey[:, None]
+    w_lo[:, out[y == 0]] = -ey[:, None]
+    return w_up, w_lo
+
+
+def terminal_weights(domain, seed):
+    """Seeded weights [19, N]: one draw rng.normal(size=(19, N)) of
+    default_rng(seed), zeroed at the solid nodes."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(19, domain.n_nodes)) * (domain.node_type != SOLID)
 
 
 def get(name, **kw):
