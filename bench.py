@@ -603,9 +603,11 @@ def main():
 
     # run lengths of the workloads: the bifurcation capsule 5000 steps after a
     # 2000-step precursor, the precision form 2000 steps after a 1000-step
-    # precursor, the batching form 1000 steps
+    # precursor, the batching form 1000 steps, the pipe with the rigid sphere
+    # its 200 steps from the developed Poiseuille flow (the sphere would leave
+    # the 48-node pipe in a longer run)
     lengths = {"precision_form": (1000, 100, 1900), "batch_instances": (0, 50, 950),
-               "differentiation_form": (2000, 200, 2000)}
+               "differentiation_form": (2000, 200, 2000), "pipe_sphere": (0, 20, 180)}
     pre, warm, steps = lengths.get(args.workload, (2000, 200, 5000))
     args.precursor = pre if args.precursor is None else args.precursor
     args.warmup = warm if args.warmup is None else args.warmup

@@ -140,10 +140,14 @@ lbm_status lbm_info(lbm_ctx *ctx, lbm_info_t *out);
 /* Add a capsule (host data copied).  Rest lengths, areas, angles and volume
  * are taken from the given positions.  LBM_E_INVAL for an open or
  * inconsistently oriented mesh, or a vertex in more than 10 faces.  The
- * forcing markers are processed in blocks of 64 consecutive faces: a
- * spatially coherent face order (icosphere subdivision order is one) keeps
- * each block's support nodes in on-chip memory; a scattered order is still
- * correct, only slower. */
+ * faces may be given in any order and each in any rotation of its
+ * (counter-clockwise) vertices: the library keeps them in a canonical order
+ * (turned to start at the smallest vertex id, sorted by vertex triple), and
+ * its results do not depend on the order given.  The forcing markers
+ * (Eq. bodyforce) are processed in blocks of 64 faces taken along the
+ * Hilbert curve of their stencil bases, sorted on the device when the body
+ * is added, after lbm_load and every 512 steps, so that a block's support
+ * nodes form one compact box in on-chip memory. */
 lbm_status lbm_add_body(lbm_ctx *ctx, const lbm_body_desc *body, int32_t *body_id);
 
 /* Advance n_steps coupled steps (asynchronous on the context's stream):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -99,6 +100,7 @@ struct lbm_ctx {
   bool graph_valid = false;
   hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   int64_t enq = 0;
+  int64_t bin_enq = 0;  // enq at the last sort of the marker order
   std::vector<uint8_t> ncls_h;  // node classes (host copy: bulk tiles of other launch shapes)
   uint64_t version = 0;         // bumped when bodies or the launch shape change
   // parameter scales (lbm_set_scales): inlet wall velocities and membrane moduli
@@ -705,7 +707,18 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.b_dblk0 = d_dblk0;
   B.dblk_body = d_dblkb;
   B.n_diag_blocks = (int)dblk_body.size();
-  B.n_marker_blocks = (f0 + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
+  // marker chunks: CHUNK_CAP per 64 faces of each body, plain runs of 64 in
+  // face order until k_bin_faces cuts them
+  std::vector<int32_t> bch0(1, 0), ch_s0, ch_n;
+  for (int b = 0; b < nb; b++) {
+    const int nrun = (bnf[b] + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
+    for (int c = 0; c < CHUNK_CAP * nrun; c++) {
+      ch_s0.push_back(bf0[b] + std::min(c, nrun) * MARKERS_PER_BLOCK);
+      ch_n.push_back(c < nrun ? std::min(MARKERS_PER_BLOCK, bnf[b] - c * MARKERS_PER_BLOCK) : 0);
+    }
+    bch0.push_back(bch0.back() + CHUNK_CAP * nrun);
+  }
+  B.n_marker_blocks = bch0.back();
   B.n_elem_blocks = (2 * e0 + 255) / 256;
   // one flag per thread: blocks of 256 threads cover 256 tiles each
   B.n_clear_blocks = (int)std::min<long long>(64, ((ctx->g.Np >> TILE_SHIFT) + 1 + 255) / 256);
@@ -748,6 +761,35 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.b_rig = ctx->b_rig;
   B.Xbody = d_Xbody;
   B.b_diag = ctx->b_diag;
+  // marker order: identity until k_bin_faces runs (below, and every
+  // BIN_EVERY steps); sort space in global memory for bodies above the LDS
+  // capacity of the binning kernel
+  std::vector<int32_t> ident(f0);
+  for (int f = 0; f < f0; f++) ident[f] = f;
+  std::vector<long long> key0(nb, 0);
+  long long nkeys = 0;
+  for (int b = 0; b < nb; b++) {
+    long long n2 = 1;
+    while (n2 < bnf[b]) n2 <<= 1;
+    key0[b] = nkeys;
+    if (n2 > BIN_LDS_KEYS) nkeys += n2;
+  }
+  int32_t* d_perm;
+  long long* d_key0;
+  unsigned long long* d_bkeys;
+  CHK(up(&d_perm, ident));
+  CHK(up(&d_key0, key0));
+  CHK(up(&d_bkeys, std::vector<unsigned long long>(std::max<long long>(nkeys, 1), 0ull)));
+  int32_t *d_chs0, *d_chn, *d_bch0;
+  CHK(up(&d_chs0, ch_s0));
+  CHK(up(&d_chn, ch_n));
+  CHK(up(&d_bch0, bch0));
+  B.chunk_s0 = d_chs0;
+  B.chunk_n = d_chn;
+  B.b_chunk0 = d_bch0;
+  B.perm = d_perm;
+  B.b_key0 = d_key0;
+  B.bin_keys = d_bkeys;
   B.centroid = d_cen;
   B.fext = d_fext;
   B.chunk_box = d_cbox;
@@ -772,7 +814,9 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
     CHK(hipMalloc(&ctx->mac, macb));
     CHK(hipMemset(ctx->mac, 0, macb));
   }
-  // diagnostics of the current positions
+  // marker order of the current positions, and their diagnostics
+  CHK(launch_bin_faces(ctx->bargs[cur], ctx->stream));
+  ctx->bin_enq = ctx->enq;
   CHK(launch_check(ctx->bargs[cur], ctx->X[0], ctx->X[1], ctx->flags, counter(ctx, 3), ctx->stream));
   CHK(hipStreamSynchronize(ctx->stream));
   return LBM_OK;
@@ -791,6 +835,21 @@ extern "C" lbm_status lbm_add_body(lbm_ctx* ctx, const lbm_body_desc* bd, int32_
   B.faces.assign(bd->faces, bd->faces + 3 * (size_t)bd->nf);
   for (int k = 0; k < 3 * bd->nf; k++)
     if (B.faces[k] < 0 || B.faces[k] >= bd->nv) return fail(ctx, LBM_E_INVAL, "face index out of range");
+  // canonical face order: each face turned to start at its smallest vertex
+  // (orientation kept), the faces sorted by their vertex triples, so that no
+  // sum or table below depends on the order or rotation the caller chose
+  {
+    std::vector<std::array<int, 3>> fl((size_t)bd->nf);
+    for (int f = 0; f < bd->nf; f++) {
+      int a = B.faces[3 * f], b = B.faces[3 * f + 1], c = B.faces[3 * f + 2];
+      if (b < a && b < c) fl[f] = {b, c, a};
+      else if (c < a && c < b) fl[f] = {c, a, b};
+      else fl[f] = {a, b, c};
+    }
+    std::sort(fl.begin(), fl.end());
+    for (int f = 0; f < bd->nf; f++)
+      for (int k = 0; k < 3; k++) B.faces[3 * f + k] = fl[f][k];
+  }
   // closed, consistently oriented: each directed edge once, with its reverse
   std::map<std::pair<int, int>, int> dir_edge;  // (a, b) -> face
   for (int f = 0; f < bd->nf; f++)
@@ -1017,6 +1076,10 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
 // starting at parity 0) so that the launch gap between graphs is paid once
 // per chunk.
 static const int GRAPH_CHUNK = 16;
+// Steps between re-sorts of the marker order (between graph launches; the
+// faces of a membrane patch stay neighbours as it deforms, so the order
+// only needs refreshing now and then)
+static const long long BIN_EVERY = 512;
 
 static lbm_status build_graphs(lbm_ctx* ctx) {
   free_graphs(ctx);
@@ -1047,6 +1110,10 @@ extern "C" lbm_status lbm_step(lbm_ctx* ctx, int32_t n) {
   int32_t k = 0;
   while (k < n) {
     const int p = (int)(ctx->enq & 1);
+    if (!ctx->bodies.empty() && ctx->enq - ctx->bin_enq >= BIN_EVERY) {
+      CHK(launch_bin_faces(ctx->bargs[p], ctx->stream));
+      ctx->bin_enq = ctx->enq;
+    }
     if (ctx->use_graph && p == 0 && n - k >= GRAPH_CHUNK) {
       CHK(hipGraphLaunch(ctx->gexec[2], ctx->stream));
       ctx->enq += GRAPH_CHUNK;
@@ -2152,5 +2219,11 @@ extern "C" lbm_status lbm_load(lbm_ctx* ctx, const char* path) {
     CHK(hipMemcpy(secs[k].first, bufs[k].data(), secs[k].second, hipMemcpyHostToDevice));
   CHK(hipMemcpy(ctx->flags, &h, sizeof h, hipMemcpyHostToDevice));
   ctx->enq = h.steps_done;
+  if (!ctx->bodies.empty()) {
+    // the marker order of the restored positions
+    CHK(launch_bin_faces(ctx->bargs[ctx->enq & 1], ctx->stream));
+    CHK(hipStreamSynchronize(ctx->stream));
+  }
+  ctx->bin_enq = ctx->enq;
   return LBM_OK;
 }

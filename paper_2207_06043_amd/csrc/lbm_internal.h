@@ -31,6 +31,9 @@ constexpr int TILE_SHIFT = 6;
 // thousand of the 16-capsule workload takes the direct path.
 constexpr int MARKERS_PER_BLOCK = 64;
 constexpr int BOX_CELLS = 1400;  // 73 KB of LDS: two blocks fit a CU
+constexpr int BIN_LDS_KEYS = 8192;  // bodies up to this many faces are binned in LDS (64 KB)
+constexpr int BIN_THREADS = 1024;   // threads of the binning block
+constexpr int CHUNK_CAP = 3;        // marker chunks per 64 faces of a body
 
 // Work per wave of the probe / vertex-velocity launch: 8 faces (4 lanes per
 // MLS point, outer and inner probe) or 16 vertices.
@@ -128,10 +131,25 @@ struct BodyArgs {
   const int32_t* dblk_body;    // [n_diag_blocks] body of each diagnostics block
   const int32_t* b_dblk0;      // [nbody + 1] first diagnostics block of each body
   int n_marker_blocks, n_elem_blocks, n_diag_blocks;
+  // Marker order: the marker blocks take the faces in slot order, slot s
+  // holding face perm[s].  perm keeps each body's faces in its own slot
+  // range (that of its face indices), sorted by the Morton code of their
+  // stencil bases (k_bin_faces), so that a block's 64 faces are neighbours
+  // whatever order the caller gave.  Results do not depend on it.
+  // The marker blocks take chunks of at most 64 consecutive slots: block c
+  // the slots chunk_s0[c] .. + chunk_n[c] (0 for an unused chunk); body b
+  // owns chunks b_chunk0[b] .. b_chunk0[b + 1] - 1 (CHUNK_CAP chunks per
+  // 64 faces), cut by k_bin_faces where the sorted faces jump apart.
+  int* perm;                   // [nf]
+  int* chunk_s0;               // [n_marker_blocks]
+  int* chunk_n;                // [n_marker_blocks]
+  const int32_t* b_chunk0;     // [nbody + 1]
+  unsigned long long* bin_keys;  // [sum of pow2 >= nf_b] sort buffer of bodies above BIN_LDS_KEYS
+  const long long* b_key0;     // [nbody] offset of each body's part of bin_keys
   // per face / vertex work arrays
-  double* centroid;            // [nf][3]
+  double* centroid;            // [nf][3] by slot
   double* fext;                // [nf][3] hydrodynamic + repulsion force
-  int* chunk_box;              // [n_marker_blocks][6] box of stencil bases of each 64-face chunk
+  int* chunk_box;              // [n_marker_blocks][6] box of stencil bases of each chunk
   double* u0v;                 // [nv][3] interpolated velocity at vertices
   int n_clear_blocks;          // blocks clearing the previous step's force tiles
   double nu, umax;
@@ -269,6 +287,9 @@ hipError_t launch_adj_sum(const double* part, int n, double* out, hipStream_t s)
 
 hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, DevFlags* flags,
                         unsigned int* counter, hipStream_t s);
+// Sorts each body's faces into marker slots by the Morton code of their
+// stencil bases at b.Xcur (b.perm); one block of 1024 threads per body.
+hipError_t launch_bin_faces(const BodyArgs& b, hipStream_t s);
 hipError_t launch_set_populations(int prec, const Grid& g, void* f0, void* f1, const uint8_t* ncls,
                                   const DevFlags* flags, const double* pops, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,

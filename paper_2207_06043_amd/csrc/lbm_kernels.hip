@@ -1196,18 +1196,19 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
   __shared__ int s_box[6];
   const Grid& G = a.g;
   const int t = threadIdx.x, sub = t & 3;
-  const int m = blk * MARKERS_PER_BLOCK + (t >> 2);
-  const bool mk = (t >> 2) < MARKERS_PER_BLOCK && m < b.nf;
+  const int m = b.chunk_s0[blk] + (t >> 2);  // slot
+  const bool mk = (t >> 2) < b.chunk_n[blk];
   if (t < 6) s_box[t] = t < 3 ? INT_MAX : INT_MIN;
   __syncthreads();
   double cen[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0}, area = 0.0;
   int bs[3] = {0, 0, 0};
   if (mk) {
-    // two rounds of loads: the face's vertices and body, then everything
-    // that depends on them at once (positions, vertex velocities, rigid
-    // state; the unused of the last two are discarded)
-    const int v0 = b.faces[3 * m], v1 = b.faces[3 * m + 1], v2 = b.faces[3 * m + 2];
-    const int body = b.face_body[m];
+    // three rounds of loads: the slot's face, its vertices and body, then
+    // everything that depends on them at once (positions, vertex
+    // velocities, rigid state; the unused of the last two are discarded)
+    const int fm = b.perm[m];
+    const int v0 = b.faces[3 * fm], v1 = b.faces[3 * fm + 1], v2 = b.faces[3 * fm + 2];
+    const int body = b.face_body[fm];
     double pa[3], pb[3], pd[3], va[3], vb[3], vd[3], rs[12];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -1247,8 +1248,9 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
     }
   }
   __syncthreads();
-  // this block's faces form one chunk of 64: its box of stencil bases lets
-  // the repulsion skip the chunk when a face is farther than dx from it
+  // this block's slots form one chunk: its box of stencil bases lets the
+  // repulsion skip the chunk when a face is farther than dx from it (an
+  // unused chunk keeps the empty box)
   if (t < 6) b.chunk_box[6 * blk + t] = s_box[t];
   const int x0 = s_box[0] - 1, y0 = s_box[1] - 1, z0 = s_box[2] - 1;
   const int ex = s_box[3] - s_box[0] + 3, ey = s_box[4] - s_box[1] + 3, ez = s_box[5] - s_box[2] + 3;
@@ -1377,6 +1379,270 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
       }
     }
     if (any) tfc[node >> TILE_SHIFT] = 1;
+  }
+}
+
+// ------------------------------------------------------------ face binning
+// The marker order.  One block per body: each face's key is the position of
+// its stencil base floor(c + 1/2) (relative to the body's smallest base, 10
+// bits per axis) along the 3-D Hilbert curve, above the face's index within
+// the body; the keys are bitonic-sorted (in LDS up to BIN_LDS_KEYS faces,
+// else in the body's part of bin_keys) and slot f0 + r takes the face of
+// rank r.  The keys are distinct, so the order is a function of the
+// positions alone.  The Hilbert curve (unlike the Morton order) has no
+// jumps, so 64 consecutive faces stay one compact patch of the membrane.
+__device__ __forceinline__ unsigned int spread_bits10(unsigned int x) {
+  x &= 1023u;
+  x = (x | (x << 16)) & 0x030000FFu;
+  x = (x | (x << 8)) & 0x0300F00Fu;
+  x = (x | (x << 4)) & 0x030C30C3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+// Hilbert index of a point of [0, 1024)^3, by Skilling's transpose method
+// (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707, 2004):
+// the coordinates are turned, level by level from the top, into the
+// transposed index, whose bits interleaved give the distance along the
+// curve.
+__device__ __forceinline__ unsigned int hilbert10(int a, int b, int c) {
+  unsigned int X[3] = {(unsigned int)min(max(a, 0), 1023), (unsigned int)min(max(b, 0), 1023),
+                       (unsigned int)min(max(c, 0), 1023)};
+  for (unsigned int Q = 512u; Q > 1u; Q >>= 1) {
+    const unsigned int P = Q - 1u;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      if (X[i] & Q) {
+        X[0] ^= P;  // invert the low bits of the first axis
+      } else {      // exchange the low bits of axes 0 and i
+        const unsigned int t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];  // Gray encode
+  X[2] ^= X[1];
+  unsigned int t = 0u;
+  for (unsigned int Q = 512u; Q > 1u; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1u;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  return (spread_bits10(X[0]) << 2) | (spread_bits10(X[1]) << 1) | spread_bits10(X[2]);
+}
+
+__device__ __forceinline__ void face_base(const double* X, const int32_t* faces, int f, int (&bs)[3]) {
+  const int v0 = faces[3 * f], v1 = faces[3 * f + 1], v2 = faces[3 * f + 2];
+#pragma unroll
+  for (int k = 0; k < 3; k++) bs[k] = (int)floor((X[3 * v0 + k] + X[3 * v1 + k] + X[3 * v2 + k]) / 3.0 + 0.5);
+}
+
+// Keys and sort of one body; K is LDS or global memory (inlined separately
+// for each, so that LDS accesses stay LDS instructions).  On return K[0..nf)
+// holds the body's keys in increasing order.
+__device__ __forceinline__ void hilbert_sort(const BodyArgs& b, int f0, int nf, int n2, const int (&lo)[3],
+                                             unsigned long long* K) {
+  const int t = threadIdx.x;
+  for (int i = t; i < n2; i += blockDim.x) {
+    unsigned long long key = ~0ull;  // padding sorts last
+    if (i < nf) {
+      int bs[3];
+      face_base(b.Xcur, b.faces, f0 + i, bs);
+      key = ((unsigned long long)hilbert10(bs[0] - lo[0], bs[1] - lo[1], bs[2] - lo[2]) << 32) | (unsigned int)i;
+    }
+    K[i] = key;
+  }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < n2; i += blockDim.x) {
+        const int p = i ^ j;
+        if (p > i) {
+          const unsigned long long x = K[i], y = K[p];
+          if ((x > y) == ((i & k) == 0)) {
+            K[i] = y;
+            K[p] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ unsigned int compact_bits10(unsigned int x) {
+  x &= 0x09249249u;
+  x = (x | (x >> 2)) & 0x030C30C3u;
+  x = (x | (x >> 4)) & 0x0300F00Fu;
+  x = (x | (x >> 8)) & 0x030000FFu;
+  x = (x | (x >> 16)) & 0x000003FFu;
+  return x;
+}
+
+// The point of [0, 1024)^3 at Hilbert index h (the inverse of hilbert10:
+// Gray decode, then the exchanges and inversions undone from the bottom
+// level up).
+__device__ __forceinline__ void hilbert10_point(unsigned int h, int (&c)[3]) {
+  unsigned int X[3] = {compact_bits10(h >> 2), compact_bits10(h >> 1), compact_bits10(h)};
+  const unsigned int t = X[2] >> 1;
+  X[2] ^= X[1];
+  X[1] ^= X[0];
+  X[0] ^= t;
+  for (unsigned int Q = 2u; Q != 1024u; Q <<= 1) {
+    const unsigned int P = Q - 1u;
+#pragma unroll
+    for (int i = 2; i >= 0; i--) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const unsigned int u = (X[0] ^ X[i]) & P;
+        X[0] ^= u;
+        X[i] ^= u;
+      }
+    }
+  }
+  c[0] = (int)X[0];
+  c[1] = (int)X[1];
+  c[2] = (int)X[2];
+}
+
+// Exclusive prefix sum over the block's threads in thread order; total gets
+// the sum.  s_tmp holds BIN_THREADS / 64 + 1 values.
+template <class T>
+__device__ __forceinline__ T block_scan(T v, T* s_tmp, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_tmp[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T acc = 0;
+    for (int k = 0; k < nw; k++) {
+      const T c = s_tmp[k];
+      s_tmp[k] = acc;
+      acc += c;
+    }
+    s_tmp[nw] = acc;
+  }
+  __syncthreads();
+  const T ex = s_tmp[w] + x - v;
+  total = s_tmp[nw];
+  __syncthreads();
+  return ex;
+}
+
+// Chunks of at most 64 consecutive slots, in order: nrun runs of 64 (the
+// last one shorter), the rest of the body's chunks unused.
+__device__ __forceinline__ void fixed_chunks(const BodyArgs& b, int f0, int nf, int c0, int cap) {
+  const int nrun = (nf + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
+  for (int c = threadIdx.x; c < cap; c += blockDim.x) {
+    b.chunk_s0[c0 + c] = f0 + min(c, nrun) * MARKERS_PER_BLOCK;
+    b.chunk_n[c0 + c] = c < nrun ? min(MARKERS_PER_BLOCK, nf - c * MARKERS_PER_BLOCK) : 0;
+  }
+}
+
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_faces(BodyArgs b) {
+  __shared__ unsigned long long s_keys[BIN_LDS_KEYS];
+  __shared__ unsigned long long s_tmp[BIN_THREADS / 64 + 1];
+  __shared__ int s_min[3];
+  const int body = blockIdx.x, t = threadIdx.x;
+  const int f0 = b.b_face0[body], nf = b.b_nf[body];
+  const int c0 = b.b_chunk0[body], cap = b.b_chunk0[body + 1] - c0;
+  int n2 = 1;
+  while (n2 < nf) n2 <<= 1;
+  if (t < 3) s_min[t] = INT_MAX;
+  __syncthreads();
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX};
+  for (int i = t; i < nf; i += blockDim.x) {
+    int bs[3];
+    face_base(b.Xcur, b.faces, f0 + i, bs);
+#pragma unroll
+    for (int k = 0; k < 3; k++) lo[k] = min(lo[k], bs[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; k++) atomicMin(&s_min[k], lo[k]);
+  __syncthreads();
+  const int mn[3] = {s_min[0], s_min[1], s_min[2]};
+  if (n2 > BIN_LDS_KEYS) {
+    // large body: sorted in global memory, cut in runs of 64
+    unsigned long long* K = b.bin_keys + b.b_key0[body];
+    hilbert_sort(b, f0, nf, n2, mn, K);
+    for (int i = t; i < nf; i += blockDim.x) b.perm[f0 + i] = f0 + (int)(K[i] & 0xffffffffull);
+    fixed_chunks(b, f0, nf, c0, cap);
+    return;
+  }
+  hilbert_sort(b, f0, nf, n2, mn, s_keys);
+  // Chunks: thread t owns the sorted positions t R .. t R + R - 1.  A
+  // position starts a segment where its base is more than J (Chebyshev)
+  // from the previous one's; each segment of length L is cut into
+  // ceil(L / 64) near-equal chunks.  J is the smallest of 1..4 whose
+  // segments fit the body's chunks (else plain runs of 64).
+  const int R = (nf + BIN_THREADS - 1) / BIN_THREADS;  // <= 8
+  unsigned int jm[4] = {0u, 0u, 0u, 0u};
+  {
+    int prev[3] = {0, 0, 0};
+    const int i0 = t * R;
+    if (i0 >= 1 && i0 - 1 < nf) hilbert10_point((unsigned int)(s_keys[i0 - 1] >> 32), prev);
+    for (int r = 0; r < R; r++) {
+      const int i = i0 + r;
+      if (i >= nf) break;
+      const unsigned long long key = s_keys[i];
+      b.perm[f0 + i] = f0 + (int)(key & 0xffffffffull);
+      int c[3];
+      hilbert10_point((unsigned int)(key >> 32), c);
+      const int d = max(abs(c[0] - prev[0]), max(abs(c[1] - prev[1]), abs(c[2] - prev[2])));
+#pragma unroll
+      for (int J = 0; J < 4; J++)
+        if (i == 0 || d > J + 1) jm[J] |= 1u << r;
+      prev[0] = c[0];
+      prev[1] = c[1];
+      prev[2] = c[2];
+    }
+  }
+  unsigned long long packed = 0ull;
+#pragma unroll
+  for (int J = 0; J < 4; J++) packed |= (unsigned long long)__popc(jm[J]) << (16 * J);
+  unsigned long long tot;
+  const unsigned long long ex = block_scan(packed, s_tmp, tot);  // syncs: the keys are free after
+  const int nrun = (nf + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
+  int J = -1;
+  for (int q = 3; q >= 0; q--)
+    if ((int)((tot >> (16 * q)) & 0xffffull) + nrun <= cap) J = q;
+  if (J < 0) {
+    fixed_chunks(b, f0, nf, c0, cap);
+    return;
+  }
+  const int S = (int)((tot >> (16 * J)) & 0xffffull);
+  int* SS = reinterpret_cast<int*>(s_keys);  // segment starts [S + 1]
+  {
+    int o = (int)((ex >> (16 * J)) & 0xffffull);
+    for (int r = 0; r < R; r++)
+      if (jm[J] & (1u << r)) SS[o++] = t * R + r;
+    if (t == 0) SS[S] = nf;
+  }
+  __syncthreads();
+  // chunks of thread t's segments t Rs .. t Rs + Rs - 1
+  const int Rs = (S + BIN_THREADS - 1) / BIN_THREADS;
+  int nk = 0;
+  for (int s = t * Rs; s < min(S, t * Rs + Rs); s++) nk += (SS[s + 1] - SS[s] + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
+  unsigned long long ntot;
+  int cc = c0 + (int)block_scan((unsigned long long)nk, s_tmp, ntot);
+  for (int s = t * Rs; s < min(S, t * Rs + Rs); s++) {
+    const int a = SS[s], L = SS[s + 1] - a;
+    const int k = (L + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
+    for (int q = 0; q < k; q++, cc++) {
+      const int lo_q = (L * q) / k, hi_q = (L * (q + 1)) / k;
+      b.chunk_s0[cc] = f0 + a + lo_q;
+      b.chunk_n[cc] = hi_q - lo_q;
+    }
+  }
+  for (int c = (int)ntot + t; c < cap; c += blockDim.x) {
+    b.chunk_s0[c0 + c] = f0 + nf;
+    b.chunk_n[c0 + c] = 0;
   }
 }
 
@@ -1655,12 +1921,12 @@ __device__ __forceinline__ void mls_post_block(const FluidArgs& a, const BodyArg
           }
           const double qx = __shfl(cen[0], 4 * q, 64), qy = __shfl(cen[1], 4 * q, 64),
                        qz = __shfl(cen[2], 4 * q, 64);
-          const int f0 = b.b_face0[o], nfo = b.b_nf[o];
-          // the lanes test o's 64-face chunks in parallel (a centroid c of a
-          // chunk has floor(c + 1/2) inside the chunk's box of bases, so a
-          // face farther than 1.5 from that box has no partner there); the
-          // surviving chunks are scanned one centroid per lane
-          const int c0 = f0 / MARKERS_PER_BLOCK, c1 = (f0 + nfo - 1) / MARKERS_PER_BLOCK;
+          // the lanes test o's chunks in parallel (a centroid c of a chunk
+          // has floor(c + 1/2) inside the chunk's box of bases, so a face
+          // farther than 1.5 from that box has no partner there); the
+          // surviving chunks are scanned one centroid per lane (centroids
+          // are stored by slot)
+          const int c0 = b.b_chunk0[o], c1 = b.b_chunk0[o + 1] - 1;
           for (int cb0 = c0; cb0 <= c1; cb0 += 64) {
             bool near = false;
             if (cb0 + l <= c1) {
@@ -1672,8 +1938,9 @@ __device__ __forceinline__ void mls_post_block(const FluidArgs& a, const BodyArg
             while (mc) {
               const int cbit = __ffsll((unsigned long long)mc) - 1;
               mc &= mc - 1;
-              const int g = (cb0 + cbit) * MARKERS_PER_BLOCK + l;
-              if (g >= f0 && g < f0 + nfo) {
+              const int cb = cb0 + cbit;
+              if (l < b.chunk_n[cb]) {
+                const int g = b.chunk_s0[cb] + l;
                 const double* cj = b.centroid + 3 * g;
                 const double ddx = qx - cj[0], ddy = qy - cj[1], ddz = qz - cj[2];
                 const double d = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
@@ -2964,6 +3231,12 @@ hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const doubl
 hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, const double* ibsum, int nout,
                                double* grad, hipStream_t s) {
   k_adj_grad_final<<<1, 64, 0, s>>>(part, nblk, omega, ibsum, nout, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_faces(const BodyArgs& b, hipStream_t s) {
+  if (b.nbody == 0) return hipSuccess;
+  k_bin_faces<<<(unsigned)b.nbody, BIN_THREADS, 0, s>>>(b);
   return hipGetLastError();
 }
 
