@@ -9,17 +9,20 @@ Measures at each stored step count after the release (0 = end of precursor):
   e_u = max |u_gpu - u_orc| / max |u_orc|   over the sampled fluid nodes
   e_x = max |x_gpu - x_orc| / max |x_orc - x_release|   over all vertices
 
-Bound at step k: the fixed bar (1e-12 for FP64, 2e-5 for FP32), or 100 times
+Samples: a fixed seeded set of fluid nodes, and at each step count every
+fluid node within 3 lattice spacings of the capsule's bounding box (where
+its forcing, probes and vertex velocities act).
+
+Bound at step k: the fixed bar (1e-12 for FP64, 2e-5 for FP32), or 10 times
 the oracle's own spread at k when that is larger.  The spread is how far the
-oracle's trajectory moves when only its rounding changes, stored beside the
-states: for FP64 the larger of its FMA and reordered-sum builds, for FP32 the
-build that stores its populations in FP32.  The capsule's motion amplifies
-rounding (by about 1e7 over the 5200 steps), so no evaluation stays closer
-than that spread; one realization of it is only an estimate (realizations
-differ by more than 10x a thousand steps after release), hence the factor.
-Checkpoints where the spread is below a hundredth of the bar are held to the
-bar: FP64 through release + 200, FP32 through release + 1000.  Marker
-positions in FP32 are held to the bar at every checkpoint.
+oracle's trajectory moves when only its rounding changes, the largest over
+several realizations stored beside the states: for FP64 the oracle built
+with fused multiply-adds, with reordered sums and with both; for FP32 the
+oracle storing its populations in FP32 and the oracle running its fluid
+state and arithmetic in FP32.  The capsule's motion amplifies rounding (by
+about 1e7 over the 5200 steps), so no evaluation stays closer than that
+spread.  The test prints, per checkpoint, whether the fixed bar itself is
+met.
 """
 import os
 import sys
@@ -34,8 +37,8 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "bifurcation_capsule_oracle.npz")
 BAR = {"f64": 1e-12, "f32": 2e-5}
-ENV = {"f64": ("env_fma", "env_reassoc"), "f32": ("env_f32",)}
-ENV_FACTOR = 100.0
+ENV = {"f64": ("env_fma", "env_reassoc", "env_fma_reassoc"), "f32": ("env_f32", "env_float32")}
+ENV_FACTOR = 10.0
 
 
 @pytest.fixture(scope="module")
@@ -58,7 +61,6 @@ def test_bifurcation_capsule_full_size(lib, precision):
     lat.step(int(g["precursor"]))
     assert lat.sync(raise_on_stop=False) == lib.LBM_OK
     lat.add_body(w.bodies[0])
-    sample = g["sample"]
     done = 0
     failures = []
     for k in g["checkpoints"]:
@@ -69,6 +71,7 @@ def test_bifurcation_capsule_full_size(lib, precision):
         st = lat.sync(raise_on_stop=False)
         assert st == int(g[f"status_{k}"]) == lib.LBM_OK
         rho, u = lat.fields()
+        sample = g[f"sample_{k}"]
         u = u.cpu().numpy()[:, sample]
         rho = rho.cpu().numpy()[sample]
         x = lat.body(0)[0].cpu().numpy()
@@ -81,9 +84,11 @@ def test_bifurcation_capsule_full_size(lib, precision):
         env_u = max(e[0] for e in envs)
         env_x = max(e[1] for e in envs)
         tol_u = max(BAR[precision], ENV_FACTOR * env_u)
-        tol_x = BAR[precision] if precision == "f32" else max(BAR[precision], ENV_FACTOR * env_x)
+        tol_x = max(BAR[precision], ENV_FACTOR * env_x)
+        bar = "meets the bar" if e_u <= BAR[precision] and e_x <= BAR[precision] else "above the bar"
         print(f"  step {k}: e_u {e_u:.3e} (bound {tol_u:.1e}, oracle spread {env_u:.1e}) "
-              f"e_rho {e_r:.3e} e_x {e_x:.3e} (bound {tol_x:.1e}, spread {env_x:.1e})", flush=True)
+              f"e_rho {e_r:.3e} e_x {e_x:.3e} (bound {tol_x:.1e}, spread {env_x:.1e}) "
+              f"[{len(sample)} nodes; {bar}]", flush=True)
         sys.stdout.flush()
         if e_u > tol_u or e_x > tol_x:
             failures.append((k, e_u, tol_u, e_x, tol_x))
