@@ -97,6 +97,9 @@ struct lbm_ctx {
   int bulk_v = 4;
   int bulk_block = 256;
   bool fluid_merged = false;  // records and bulk tiles in one launch (small grids)
+  // spread in two passes (staged block sums, then an owner pass without
+  // atomics) instead of atomics; LBM_SPREAD_TWO_PASS=1 at creation
+  bool spread_two_pass = false;
   bool graph_valid = false;
   hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   int64_t enq = 0;
@@ -233,6 +236,7 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   if (const char* ev = getenv("LBM_BULK_V")) ctx->bulk_v = atoi(ev);
   if (const char* ev = getenv("LBM_BULK_BLOCK")) ctx->bulk_block = atoi(ev);
   if (const char* ev = getenv("LBM_FLUID_SPLIT")) ctx->fluid_merged = atoi(ev) == 0;
+  if (const char* ev = getenv("LBM_SPREAD_TWO_PASS")) ctx->spread_two_pass = atoi(ev) != 0;
   if (ctx->fluid_merged) ctx->rec_block = ctx->bulk_block;
   if (!shape_ok(d->precision, ctx->bulk_v, ctx->bulk_block) ||
       (ctx->rec_block != 64 && ctx->rec_block != 128 && ctx->rec_block != 256))
@@ -787,6 +791,14 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   B.chunk_s0 = d_chs0;
   B.chunk_n = d_chn;
   B.b_chunk0 = d_bch0;
+  if (ctx->spread_two_pass) {
+    long long* d_stage;
+    int32_t* d_snode;
+    CHK(up(&d_stage, std::vector<long long>((size_t)B.n_marker_blocks * BOX_CELLS * 3, 0)));
+    CHK(up(&d_snode, std::vector<int32_t>((size_t)B.n_marker_blocks * BOX_CELLS, -1)));
+    B.stage = d_stage;
+    B.stage_node = d_snode;
+  }
   B.perm = d_perm;
   B.b_key0 = d_key0;
   B.bin_keys = d_bkeys;
@@ -1039,6 +1051,8 @@ static hipError_t enqueue_step(lbm_ctx* ctx, int p, hipStream_t s, hipEvent_t ev
     if ((e = launch_ib_force(ctx->prec, a, b, ctx->fx[p], ctx->tf[p], ctx->fx[p ^ 1], ctx->tf[p ^ 1],
                              counter(ctx, 0), s)) != hipSuccess)
       return e;
+    if (b.stage && (e = launch_spread_owner(ctx->g, b, ctx->fx[p], ctx->tf[p], ctx->flags, s)) != hipSuccess)
+      return e;
   }
   if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
   // (fluid_reps > 1 only for timing: the phase rewrites B and the macro field
@@ -1282,6 +1296,8 @@ static lbm_status batch_build_tables(lbm_batch* b) {
       it.a = fluid_args(c, p);
       if (c->nf > 0) {
         it.b = c->bargs[p];
+        it.b.stage = nullptr;  // the batched forcing spreads in one pass
+        it.b.stage_node = nullptr;
         it.fxc = c->fx[p];
         it.tfc = c->tf[p];
         it.fxp = c->fx[p ^ 1];
@@ -1910,6 +1926,8 @@ static lbm_status adjoint_sweep(lbm_ctx* ctx, int32_t n_steps, int32_t every, co
   const int nv3 = 3 * ctx->nv;
   const size_t vb = sizeof(double) * nv3;
   BodyArgs bb = ib ? ctx->bargs[0] : BodyArgs{};
+  bb.stage = nullptr;  // the recomputed steps spread in one pass
+  bb.stage_node = nullptr;
   // one coupled step from (gin, body slot `from`) into (gout, slot `to`)
   auto coupled = [&](const void* gin, void* gout, double* from, double* to, double* hrec) -> hipError_t {
     hipError_t e;

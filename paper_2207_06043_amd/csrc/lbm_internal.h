@@ -150,6 +150,11 @@ struct BodyArgs {
   double* centroid;            // [nf][3] by slot
   double* fext;                // [nf][3] hydrodynamic + repulsion force
   int* chunk_box;              // [n_marker_blocks][6] box of stencil bases of each chunk
+  // Two-pass spread (null: one pass with atomics): each marker block's box
+  // sums, [n_marker_blocks][BOX_CELLS][3] fixed point, and the node of each
+  // box cell (-1: none), [n_marker_blocks][BOX_CELLS].
+  long long* stage;
+  int* stage_node;
   double* u0v;                 // [nv][3] interpolated velocity at vertices
   int n_clear_blocks;          // blocks clearing the previous step's force tiles
   double nu, umax;
@@ -290,6 +295,10 @@ hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, D
 // Sorts each body's faces into marker slots by the Morton code of their
 // stencil bases at b.Xcur (b.perm); one block of 1024 threads per body.
 hipError_t launch_bin_faces(const BodyArgs& b, hipStream_t s);
+// Owner pass of the two-pass spread (b.stage set): adds the staged box sums
+// into fxc without atomics and flags the tiles.
+hipError_t launch_spread_owner(const Grid& g, const BodyArgs& b, long long* fxc, uint8_t* tfc,
+                               const DevFlags* flags, hipStream_t s);
 hipError_t launch_set_populations(int prec, const Grid& g, void* f0, void* f1, const uint8_t* ncls,
                                   const DevFlags* flags, const double* pops, hipStream_t s);
 hipError_t launch_get_fields(int prec, const Grid& g, const void* f0, const void* f1,

@@ -1366,6 +1366,18 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
     }
   }
   __syncthreads();
+  if (b.stage) {
+    // two-pass spread: the block's sums go to its staging box; the owner
+    // pass (k_spread_owner) adds them up across blocks without atomics
+    long long* st = b.stage + (long long)blk * BOX_CELLS * 3;
+    int* sn = b.stage_node + (long long)blk * BOX_CELLS;
+    for (int c = t; c < ncell; c += blockDim.x) {
+      sn[c] = s_node[c];
+#pragma unroll
+      for (int q = 0; q < 3; q++) st[3 * c + q] = s_acc[q][c];
+    }
+    return;
+  }
   for (int c = t; c < ncell; c += blockDim.x) {
     const long long node = s_node[c];
     if (node < 0) continue;
@@ -1380,6 +1392,71 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
     }
     if (any) tfc[node >> TILE_SHIFT] = 1;
   }
+}
+
+// Cell of node (x, y, z) in a chunk's box (origin o, extents e), trying the
+// periodic images one period away; -1 if outside.
+__device__ __forceinline__ int box_cell(const Grid& G, const int (&o)[3], const int (&e)[3], int x, int y, int z) {
+  const int p[3] = {x, y, z}, n[3] = {G.nx, G.ny, G.nz};
+  int c[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    int d = p[a] - o[a];
+    if (G.per[a] && (d < 0 || d >= e[a])) d = d < 0 ? d + n[a] : d - n[a];
+    if (d < 0 || d >= e[a]) return -1;
+    c[a] = d;
+  }
+  return c[0] + e[0] * (c[1] + e[1] * c[2]);
+}
+
+// The box of chunk k from its bases (cb: its six ints); false when the chunk
+// did not fit LDS (its block added its sums with atomics) or is empty.
+__device__ __forceinline__ bool chunk_geom(const int* cb, int (&o)[3], int (&e)[3]) {
+  if (cb[3] < cb[0]) return false;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    o[a] = cb[a] - 1;
+    e[a] = cb[3 + a] - cb[a] + 3;
+  }
+  return (long long)e[0] * e[1] * e[2] <= BOX_CELLS;
+}
+
+// Owner pass of the two-pass spread: thread (chunk c, cell i) holds node n;
+// it is the owner when no lower chunk's box holds n, and then adds the
+// staged sums of every chunk that holds n, in chunk order, into the force
+// field (plain stores: one owner per node), and flags the tile.
+__global__ __launch_bounds__(256) void k_spread_owner(Grid G, BodyArgs b, long long* fxc, uint8_t* tfc,
+                                                      const DevFlags* flags) {
+  if (flags->stop) return;
+  const int nch = b.n_marker_blocks, c = blockIdx.y;
+  int o[3], e[3];
+  if (!chunk_geom(b.chunk_box + 6 * c, o, e)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e[0] * e[1] * e[2]) return;
+  const int node = b.stage_node[(long long)c * BOX_CELLS + i];
+  if (node < 0) return;
+  int x, y, z;
+  coords(G, node, x, y, z);
+  for (int k = 0; k < c; k++) {
+    int ok[3], ek[3];
+    if (!chunk_geom(b.chunk_box + 6 * k, ok, ek)) continue;
+    const int j = box_cell(G, ok, ek, x, y, z);
+    if (j >= 0 && b.stage_node[(long long)k * BOX_CELLS + j] == node) return;  // not the owner
+  }
+  long long acc[3] = {0, 0, 0};
+  for (int k = c; k < nch; k++) {
+    int ok[3], ek[3];
+    if (!chunk_geom(b.chunk_box + 6 * k, ok, ek)) continue;
+    const int j = box_cell(G, ok, ek, x, y, z);
+    if (j < 0 || b.stage_node[(long long)k * BOX_CELLS + j] != node) continue;
+    const long long* st = b.stage + ((long long)k * BOX_CELLS + j) * 3;
+#pragma unroll
+    for (int q = 0; q < 3; q++) acc[q] += st[q];
+  }
+  if (acc[0] == 0 && acc[1] == 0 && acc[2] == 0) return;
+#pragma unroll
+  for (int q = 0; q < 3; q++) fxc[q * G.Np + node] += acc[q];
+  tfc[node >> TILE_SHIFT] = 1;
 }
 
 // ------------------------------------------------------------ face binning
@@ -3231,6 +3308,14 @@ hipError_t launch_adjoint_layout(const Grid& g, const uint8_t* ncls, const doubl
 hipError_t launch_adjoint_grad(const double* part, int nblk, double omega, const double* ibsum, int nout,
                                double* grad, hipStream_t s) {
   k_adj_grad_final<<<1, 64, 0, s>>>(part, nblk, omega, ibsum, nout, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_spread_owner(const Grid& g, const BodyArgs& b, long long* fxc, uint8_t* tfc,
+                               const DevFlags* flags, hipStream_t s) {
+  if (b.nbody == 0 || !b.stage) return hipSuccess;
+  const dim3 grid((BOX_CELLS + 255) / 256, (unsigned)b.n_marker_blocks);
+  k_spread_owner<<<grid, 256, 0, s>>>(g, b, fxc, tfc, flags);
   return hipGetLastError();
 }
 
