@@ -295,6 +295,9 @@ hipError_t launch_check(const BodyArgs& b, const double* X0, const double* X1, D
 // Sorts each body's faces into marker slots by the Morton code of their
 // stencil bases at b.Xcur (b.perm); one block of 1024 threads per body.
 hipError_t launch_bin_faces(const BodyArgs& b, hipStream_t s);
+// to[0..nv3) = from[nv3..2 nv3), to[nv3..2 nv3) = from[0..nv3), to[2 nv3..3 nv3)
+// = from[2 nv3..3 nv3): a coupled step's body slot set up from its input's.
+hipError_t launch_body_slots(const double* from, double* to, long long nv3, hipStream_t s);
 // Owner pass of the two-pass spread (b.stage set): adds the staged box sums
 // into fxc without atomics and flags the tiles.
 hipError_t launch_spread_owner(const Grid& g, const BodyArgs& b, long long* fxc, uint8_t* tfc,

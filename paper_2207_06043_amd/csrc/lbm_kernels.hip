@@ -3650,6 +3650,25 @@ __device__ __forceinline__ T dot_t(const T (&a)[3], const T (&b)[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+__device__ __forceinline__ double shfl_xor_t(double a, int m) { return __shfl_xor(a, m, 64); }
+template <int N>
+__device__ __forceinline__ Dual<N> shfl_xor_t(const Dual<N>& a, int m) {
+  Dual<N> r;
+  r.v = __shfl_xor(a.v, m, 64);
+#pragma unroll
+  for (int i = 0; i < N; i++) r.d[i] = __shfl_xor(a.d[i], m, 64);
+  return r;
+}
+
+// Sum over the GS lanes of an aligned group inside one wave (xor tree:
+// every lane ends with the same value, bit for bit).
+template <int GS, class T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int m = GS / 2; m >= 1; m >>= 1) v = v + shfl_xor_t(v, m);
+  return v;
+}
+
 // MLS at point p in any scalar type: the 27 supports of floor(p + 1/2)
 // (solid and out-of-box nodes left out, as in the step), A = sum W P P^T
 // with W = exp(-|d|^2 / (2.6^2 0.3^2)) and P = (1, d), d = x_k - p, then for
@@ -3657,13 +3676,16 @@ __device__ __forceinline__ T dot_t(const T (&a)[3], const T (&b)[3]) {
 // interpolation weight phi_k, psi[1..3] the gradient weights of the linear
 // fit).  A singular moment matrix (the step's rule) calls nothing and
 // returns false.
-template <class T, class Fn>
-__device__ bool mls_each(const Grid& G, const uint8_t* ncls, const T (&p)[3], Fn&& fn) {
+// The work is split over a group of GS lanes (all of them call it, with the
+// same p): lane l takes the supports l, l + GS, ...; the moment matrix is
+// summed over the group, and fn runs for the lane's own supports.
+template <int GS, class T, class Fn>
+__device__ bool mls_each_g(const Grid& G, const uint8_t* ncls, const T (&p)[3], int lane, Fn&& fn) {
   const int bs[3] = {(int)floor(dval(p[0]) + 0.5), (int)floor(dval(p[1]) + 0.5), (int)floor(dval(p[2]) + 0.5)};
   T A[10];
 #pragma unroll
   for (int k = 0; k < 10; k++) A[k] = Scal<T>::c(0.0);
-  for (int k = 0; k < 27; k++) {
+  for (int k = lane; k < 27; k += GS) {
     long long node;
     const int c[3] = {bs[0] + k % 3 - 1, bs[1] + (k / 3) % 3 - 1, bs[2] + k / 9 - 1};
     if (!support_node(G, ncls, c[0], c[1], c[2], node)) continue;
@@ -3680,6 +3702,10 @@ __device__ bool mls_each(const Grid& G, const uint8_t* ncls, const T (&p)[3], Fn
     A[7] += wy * dy;
     A[8] += wy * dz;
     A[9] += wz * dz;
+  }
+  if (GS > 1) {
+#pragma unroll
+    for (int k = 0; k < 10; k++) A[k] = group_sum<GS>(A[k]);
   }
   const int ix[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
   const double dmax = fmax(fmax(dval(A[0]), dval(A[4])), fmax(dval(A[7]), dval(A[9])));
@@ -3711,7 +3737,7 @@ __device__ bool mls_each(const Grid& G, const uint8_t* ncls, const T (&p)[3], Fn
     }
     for (int i = 0; i < 4; i++) Ai[i][c] = z[i];
   }
-  for (int k = 0; k < 27; k++) {
+  for (int k = lane; k < 27; k += GS) {
     long long node;
     const int c[3] = {bs[0] + k % 3 - 1, bs[1] + (k / 3) % 3 - 1, bs[2] + k / 9 - 1};
     if (!support_node(G, ncls, c[0], c[1], c[2], node)) continue;
@@ -3727,6 +3753,14 @@ __device__ bool mls_each(const Grid& G, const uint8_t* ncls, const T (&p)[3], Fn
   }
   return true;
 }
+
+template <class T, class Fn>
+__device__ bool mls_each(const Grid& G, const uint8_t* ncls, const T (&p)[3], Fn&& fn) {
+  return mls_each_g<1>(G, ncls, p, 0, fn);
+}
+
+// Lanes per point in the IB transposes' MLS fits.
+constexpr int ADJ_GS = 8;
 
 // The bending force of a hinge (a, b, c, d) in any scalar type: the signed
 // dihedral angle and F_r = -k_b sin(theta - theta0) dtheta/dx_r, with the
@@ -3775,6 +3809,7 @@ __device__ __forceinline__ void set_tile(uint8_t* tf, long long node) {
 // launches), dJ/dV = 0 (the forcing markers add theirs).
 __global__ __launch_bounds__(256) void k_adjb_vertex(BodyArgs b, AdjIB ib) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx < b.nbody) ib.gsum[2 + idx] = 0.0;  // sum of A n . dJ/dFt per body (k_adjb_body adds it)
   if (idx >= b.nsoft_v) return;
   const int v = b.soft_vlist[idx];
   const double mv = b.b_param[8 * b.vert_body[v] + 3];
@@ -3801,63 +3836,78 @@ __device__ __forceinline__ Dual<9> lift9(const Dual<3>& f, const Dual<9> (&p)[3]
 
 // Elements, probes and vertex velocities transposed, one thread each:
 // items [0, ne) edges, [ne, ne + nh) hinges, then faces, then soft vertices.
+// Threads: one per edge and hinge, then (from the next multiple of 64) a
+// group of ADJ_GS lanes per face and probe side, then per soft vertex; a
+// group's MLS fits split the supports over its lanes.
+__host__ __device__ __forceinline__ long long adjb_body_face0(const BodyArgs& b) {
+  return ((long long)b.ne + b.nh + 63) / 64 * 64;
+}
+
 template <class S>
 __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjIB ib) {
-  const int it = blockIdx.x * 128 + threadIdx.x;
+  const long long gt = blockIdx.x * 128LL + threadIdx.x;
   const Grid& G = a.g;
   const double* X = b.Xcur;
   const double ikap = 1.0 / ib.kappa;
-  if (it < b.ne) {
-    // stretching (Eq. strainFor): F_a = -k (l - l0) r / l, r = x_a - x_b; its
-    // Jacobian K = -k [(1 - l0/l) 1 + l0 r r^T / l^3] is symmetric, and
-    // dF_b = -dF_a
-    const int e = it, va = b.edges[2 * e], vb = b.edges[2 * e + 1];
-    double r[3], y[3];
-    for (int k = 0; k < 3; k++) {
-      r[k] = X[3 * va + k] - X[3 * vb + k];
-      y[k] = ib.Fb[3 * va + k] - ib.Fb[3 * vb + k];
-    }
-    const double l = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    const double kl = b.kl[e], l0 = b.l0[e];
-    const double ry = r[0] * y[0] + r[1] * y[1] + r[2] * y[2];
+  const long long g0 = adjb_body_face0(b);
+  if (gt < g0) {
+    // whole waves of elements (and padding lanes): dJ/dkappa summed over
+    // the wave first, one atomic per wave
+    const int it = gt < b.ne + b.nh ? (int)gt : -1;
     double fy = 0.0;
-    for (int k = 0; k < 3; k++) {
-      const double g = -kl * ((1.0 - l0 / l) * y[k] + l0 * ry * r[k] / (l * l * l));
-      atomicAdd(ib.LP + 3 * va + k, g);
-      atomicAdd(ib.LP + 3 * vb + k, -g);
-      fy += -kl * (l - l0) * r[k] / l * y[k];
+    if (it >= 0 && it < b.ne) {
+      // stretching (Eq. strainFor): F_a = -k (l - l0) r / l, r = x_a - x_b; its
+      // Jacobian K = -k [(1 - l0/l) 1 + l0 r r^T / l^3] is symmetric, and
+      // dF_b = -dF_a
+      const int e = it, va = b.edges[2 * e], vb = b.edges[2 * e + 1];
+      double r[3], y[3];
+      for (int k = 0; k < 3; k++) {
+        r[k] = X[3 * va + k] - X[3 * vb + k];
+        y[k] = ib.Fb[3 * va + k] - ib.Fb[3 * vb + k];
+      }
+      const double l = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      const double kl = b.kl[e], l0 = b.l0[e];
+      const double ry = r[0] * y[0] + r[1] * y[1] + r[2] * y[2];
+      for (int k = 0; k < 3; k++) {
+        const double g = -kl * ((1.0 - l0 / l) * y[k] + l0 * ry * r[k] / (l * l * l));
+        atomicAdd(ib.LP + 3 * va + k, g);
+        atomicAdd(ib.LP + 3 * vb + k, -g);
+        fy += -kl * (l - l0) * r[k] / l * y[k];  // the force is linear in the modulus
+      }
+    } else if (it >= 0) {
+      // bending: the force is minus the gradient of the hinge energy, so its
+      // Jacobian is symmetric and the transposed product is the derivative
+      // along the adjoint itself (one dual direction)
+      const int h = it - b.ne;
+      const int32_t* H = b.hinges + 4 * h;
+      Dual<1> P[4][3], F[4][3];
+      for (int r = 0; r < 4; r++)
+        for (int k = 0; k < 3; k++) {
+          P[r][k].v = X[3 * H[r] + k];
+          P[r][k].d[0] = ib.Fb[3 * H[r] + k];
+        }
+      hinge_force_t(P, b.kb[h], b.theta0[h], F);
+      for (int r = 0; r < 4; r++)
+        for (int k = 0; k < 3; k++) {
+          atomicAdd(ib.LP + 3 * H[r] + k, F[r][k].d[0]);
+          fy += F[r][k].v * ib.Fb[3 * H[r] + k];
+        }
     }
-    atomicAdd(ib.gsum + 1, fy * ikap);  // the force is linear in the modulus
+    fy = group_sum<64>(fy);
+    if ((threadIdx.x & 63) == 0 && fy != 0.0) atomicAdd(ib.gsum + 1, fy * ikap);
     return;
   }
-  if (it < b.ne + b.nh) {
-    // bending: the force is minus the gradient of the hinge energy, so its
-    // Jacobian is symmetric and the transposed product is the derivative
-    // along the adjoint itself (one dual direction)
-    const int h = it - b.ne;
-    const int32_t* H = b.hinges + 4 * h;
-    Dual<1> P[4][3], F[4][3];
-    for (int r = 0; r < 4; r++)
-      for (int k = 0; k < 3; k++) {
-        P[r][k].v = X[3 * H[r] + k];
-        P[r][k].d[0] = ib.Fb[3 * H[r] + k];
-      }
-    hinge_force_t(P, b.kb[h], b.theta0[h], F);
-    double fy = 0.0;
-    for (int r = 0; r < 4; r++)
-      for (int k = 0; k < 3; k++) {
-        atomicAdd(ib.LP + 3 * H[r] + k, F[r][k].d[0]);
-        fy += F[r][k].v * ib.Fb[3 * H[r] + k];
-      }
-    atomicAdd(ib.gsum + 1, fy * ikap);
-    return;
-  }
-  if (it < b.ne + b.nh + b.nf) {
+  const int lane = (int)((gt - g0) % ADJ_GS);
+  const long long grp = (gt - g0) / ADJ_GS;
+  const long long nfg = (2LL * b.nf * ADJ_GS + 63) / 64 * 64 / ADJ_GS;  // face groups, whole waves
+  if (grp < nfg) {
     // face force Ft = A [-(r+ - r-)/3 n + nu (r+ (G+ + G+^T) - r- (G- + G-^T)) n]
     // + k_v (1 - V/V0) A n (probes at c +- 1.2 n: fitted density r and
     // velocity gradient G), a third at each vertex: dJ/dFt = the mean of
-    // the vertices' dJ/dF
-    const int f = it - b.ne - b.nh;
+    // the vertices' dJ/dF.  Two groups per face: the outer probe's terms
+    // with the volume term, and the inner probe's.
+    const bool real = grp < 2LL * b.nf;  // groups past the faces pad the last wave
+    const int f = real ? (int)(grp >> 1) : 0, side = (int)(grp & 1);
     const int body = b.face_body[f];
     const int vv[3] = {b.faces[3 * f], b.faces[3 * f + 1], b.faces[3 * f + 2]};
     double ab[3];
@@ -3882,23 +3932,26 @@ __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjI
     const double V0 = b.b_param[8 * body], kv = b.b_param[8 * body + 2];
     const double cv = kv * (1.0 - b.b_diag[16 * body] / V0);
     const Dual<9> an = ab[0] * n[0] + ab[1] * n[1] + ab[2] * n[2];
-    Dual<9> s = A * an * cv;  // the volume force
-    double visc = 0.0;        // d s / d nu
-    for (int side = 0; side < 2; side++) {
+    Dual<9> s = side == 0 ? A * an * cv : Scal<Dual<9>>::c(0.0);  // the volume force
+    double visc = 0.0;                                              // d s / d nu
+    {
       const double sg = side == 0 ? 1.2 : -1.2, sgn = side == 0 ? 1.0 : -1.0;
       Dual<9> pp[3];
       for (int k = 0; k < 3; k++) pp[k] = cen[k] + n[k] * sg;
       const Dual<3> q[3] = {dseed<3>(pp[0].v, 0), dseed<3>(pp[1].v, 1), dseed<3>(pp[2].v, 2)};
-      Dual<3> r3 = Scal<Dual<3>>::c(1.0), G3[3][3];
+      Dual<3> r3 = Scal<Dual<3>>::c(0.0), G3[3][3];
       for (int i = 0; i < 3; i++)
         for (int c = 0; c < 3; c++) G3[i][c] = Scal<Dual<3>>::c(0.0);
-      mls_each(G, a.ncls, q, [&](int, long long node, const Dual<3>(&psi)[4]) {
+      mls_each_g<ADJ_GS>(G, a.ncls, q, lane, [&](int, long long node, const Dual<3>(&psi)[4]) {
         double dr, uu[3];
         load_mac<S>(a, node, dr, uu[0], uu[1], uu[2]);
         r3 += psi[0] * dr;
         for (int i = 0; i < 3; i++)
           for (int c = 0; c < 3; c++) G3[i][c] += psi[1 + c] * uu[i];
       });
+      r3 = group_sum<ADJ_GS>(r3) + 1.0;  // the weights add up to 1: rho = 1 + the fit of rho - 1
+      for (int i = 0; i < 3; i++)
+        for (int c = 0; c < 3; c++) G3[i][c] = group_sum<ADJ_GS>(G3[i][c]);
       const Dual<9> r9 = lift9(r3, pp);
       Dual<9> sv = Scal<Dual<9>>::c(0.0);  // ab . ((G + G^T) n)
       double svv = 0.0;
@@ -3922,36 +3975,62 @@ __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjI
       for (int i = 0; i < 3; i++)
         for (int c = 0; c < 3; c++) Gbar[i][c] = A.v * sgn * nu * r9.v * (ab[i] * n[c].v + ab[c] * n[i].v);
       const double qv[3] = {pp[0].v, pp[1].v, pp[2].v};
-      mls_each(G, a.ncls, qv, [&](int, long long node, const double(&psi)[4]) {
-        atomicAdd(ib.ext + node, rbar * psi[0]);
-        for (int i = 0; i < 3; i++)
-          atomicAdd(ib.ext + (long long)(1 + i) * G.Np + node,
-                    Gbar[i][0] * psi[1] + Gbar[i][1] * psi[2] + Gbar[i][2] * psi[3]);
-        set_tile(ib.etf, node);
-      });
+      if (real)  // (uniform over the group)
+        mls_each_g<ADJ_GS>(G, a.ncls, qv, lane, [&](int, long long node, const double(&psi)[4]) {
+          atomicAdd(ib.ext + node, rbar * psi[0]);
+          for (int i = 0; i < 3; i++)
+            atomicAdd(ib.ext + (long long)(1 + i) * G.Np + node,
+                      Gbar[i][0] * psi[1] + Gbar[i][1] * psi[2] + Gbar[i][2] * psi[3]);
+          set_tile(ib.etf, node);
+        });
     }
+    // the scalar gradients summed over the wave first (one group's lane 0
+    // per face side contributes), then one atomic per wave
+    const bool lead = real && lane == 0;
+    const double gv = group_sum<64>(lead ? visc / 3.0 : 0.0);  // nu = (tau - 1/2) / 3
+    const double gk = group_sum<64>(lead && side == 0 && b.b_param[8 * body + 6] != 0.0 ? cv * A.v * an.v * ikap : 0.0);
+    if ((threadIdx.x & 63) == 0) {
+      if (gv != 0.0) atomicAdd(ib.gsum, gv);
+      if (gk != 0.0) atomicAdd(ib.gsum + 1, gk);
+    }
+    // sum of A n . dJ/dFt per body: one atomic per wave when its faces
+    // belong to one body
+    {
+      const int bsel = lead && side == 0 ? body : -1;
+      const double gb = bsel >= 0 ? A.v * an.v : 0.0;
+      const unsigned long long bm = __ballot(bsel >= 0);
+      if (bm) {
+        const int first = __shfl(bsel, __ffsll((unsigned long long)bm) - 1, 64);
+        if (__ballot(bsel >= 0 && bsel != first) == 0ull) {
+          const double t = group_sum<64>(gb);
+          if ((threadIdx.x & 63) == 0) atomicAdd(ib.gsum + 2 + first, t);
+        } else if (bsel >= 0) {
+          atomicAdd(ib.gsum + 2 + bsel, gb);
+        }
+      }
+    }
+    if (!lead) return;
     for (int r = 0; r < 3; r++)
       for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * vv[r] + k, s.d[3 * r + k]);
-    atomicAdd(ib.gsum, visc / 3.0);  // nu = (tau - 1/2) / 3
-    if (b.b_param[8 * body + 6] != 0.0) atomicAdd(ib.gsum + 1, cv * A.v * an.v * ikap);
-    atomicAdd(ib.gsum + 2 + body, A.v * an.v);
     return;
   }
-  const int idx = it - b.ne - b.nh - b.nf;
+  const long long idx = grp - nfg;
   if (idx >= b.nsoft_v) return;
   // MLS velocity at the vertex: u0 = sum phi_k u_k
   const int v = b.soft_vlist[idx];
   const double ub[3] = {ib.ub0[3 * v], ib.ub0[3 * v + 1], ib.ub0[3 * v + 2]};
   const Dual<3> p[3] = {dseed<3>(X[3 * v], 0), dseed<3>(X[3 * v + 1], 1), dseed<3>(X[3 * v + 2], 2)};
   Dual<3> s = Scal<Dual<3>>::c(0.0);
-  mls_each(G, a.ncls, p, [&](int, long long node, const Dual<3>(&psi)[4]) {
+  mls_each_g<ADJ_GS>(G, a.ncls, p, lane, [&](int, long long node, const Dual<3>(&psi)[4]) {
     double dr, uu[3];
     load_mac<S>(a, node, dr, uu[0], uu[1], uu[2]);
     s += psi[0] * (uu[0] * ub[0] + uu[1] * ub[1] + uu[2] * ub[2]);
     for (int i = 0; i < 3; i++) atomicAdd(ib.ext + (long long)(1 + i) * G.Np + node, psi[0].v * ub[i]);
     set_tile(ib.etf, node);
   });
-  for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * v + k, s.d[k]);
+  s = group_sum<ADJ_GS>(s);
+  if (lane == 0)
+    for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * v + k, s.d[k]);
 }
 
 // Flags the tiles of every forcing marker's support nodes (the force adjoint
@@ -3989,15 +4068,17 @@ __global__ __launch_bounds__(256) void k_adjb_volume(BodyArgs b, AdjIB ib) {
 // the positions through the centroid (phi) and the area.
 template <class S>
 __global__ __launch_bounds__(128) void k_adjb_markers(FluidArgs a, BodyArgs b, AdjIB ib) {
-  const int m = blockIdx.x * 128 + threadIdx.x;
-  if (m >= b.nf) return;
+  // a group of ADJ_GS lanes per face, the supports split over it
+  const int gt = blockIdx.x * 128 + threadIdx.x;
+  const int m = gt / ADJ_GS, lane = gt % ADJ_GS;
+  if (m >= b.nf) return;  // whole groups
   const Grid& G = a.g;
   const int vv[3] = {b.faces[3 * m], b.faces[3 * m + 1], b.faces[3 * m + 2]};
   double cen[3], n[3], area, Ub[3];
   face_geom(b.Xcur, b.faces, m, cen, n, area);
   for (int k = 0; k < 3; k++) Ub[k] = (b.Vel[3 * vv[0] + k] + b.Vel[3 * vv[1] + k] + b.Vel[3 * vv[2] + k]) / 3.0;
   double U[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
-  mls_each(G, a.ncls, cen, [&](int, long long node, const double(&psi)[4]) {
+  mls_each_g<ADJ_GS>(G, a.ncls, cen, lane, [&](int, long long node, const double(&psi)[4]) {
     const Moments mo = streamed_moments<S>(a, node);
     const double rho = 1.0 + mo.drho;
     for (int k = 0; k < 3; k++) {
@@ -4007,15 +4088,18 @@ __global__ __launch_bounds__(128) void k_adjb_markers(FluidArgs a, BodyArgs b, A
   });
   double Fl[3], Fbl[3];
   for (int k = 0; k < 3; k++) {
+    U[k] = group_sum<ADJ_GS>(U[k]);
+    Fs[k] = group_sum<ADJ_GS>(Fs[k]);
     Fl[k] = Ub[k] - U[k];
     Fbl[k] = area * Fs[k];
   }
-  for (int r = 0; r < 3; r++)
-    for (int k = 0; k < 3; k++) atomicAdd(ib.Vn + 3 * vv[r] + k, Fbl[k] / 3.0);
+  if (lane == 0)
+    for (int r = 0; r < 3; r++)
+      for (int k = 0; k < 3; k++) atomicAdd(ib.Vn + 3 * vv[r] + k, Fbl[k] / 3.0);
   const Dual<3> q[3] = {dseed<3>(cen[0], 0), dseed<3>(cen[1], 1), dseed<3>(cen[2], 2)};
   Dual<3> s = Scal<Dual<3>>::c(0.0);
   double Abar = 0.0;
-  mls_each(G, a.ncls, q, [&](int, long long node, const Dual<3>(&psi)[4]) {
+  mls_each_g<ADJ_GS>(G, a.ncls, q, lane, [&](int, long long node, const Dual<3>(&psi)[4]) {
     const Moments mo = streamed_moments<S>(a, node);
     const double rho = 1.0 + mo.drho;
     double fF = 0.0, uF = 0.0;
@@ -4028,6 +4112,9 @@ __global__ __launch_bounds__(128) void k_adjb_markers(FluidArgs a, BodyArgs b, A
     for (int k = 0; k < 3; k++) atomicAdd(ib.ext + (long long)(4 + k) * G.Np + node, -psi[0].v * Fbl[k]);
     set_tile(ib.etf, node);
   });
+  s = group_sum<ADJ_GS>(s);
+  Abar = group_sum<ADJ_GS>(Abar);
+  if (lane != 0) return;
   // d area / d vertex: (1/2) n x (opposite edge), counter-clockwise
   for (int r = 0; r < 3; r++) {
     const double* xb = b.Xcur + 3 * vv[(r + 1) % 3];
@@ -4169,14 +4256,31 @@ __global__ void k_adj_sum(const double* part, int n, double* out) {
 }
 
 hipError_t launch_adjb_vertex(const BodyArgs& b, const AdjIB& ib, hipStream_t s) {
-  if (b.nsoft_v > 0) k_adjb_vertex<<<cdiv(b.nsoft_v, 256), 256, 0, s>>>(b, ib);
+  const int n = std::max(b.nsoft_v, b.nbody);
+  if (n > 0) k_adjb_vertex<<<cdiv(n, 256), 256, 0, s>>>(b, ib);
+  return hipGetLastError();
+}
+
+// The body state of a coupled step's output slot before the step: x^n
+// where x^{n+1} will be written, x^{n-1} = the input's x^n, and the input's
+// velocities (three arrays of nv3 doubles each).
+__global__ __launch_bounds__(256) void k_body_slots(const double* from, double* to, long long nv3) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= nv3) return;
+  to[i] = from[nv3 + i];
+  to[nv3 + i] = from[i];
+  to[2 * nv3 + i] = from[2 * nv3 + i];
+}
+
+hipError_t launch_body_slots(const double* from, double* to, long long nv3, hipStream_t s) {
+  if (nv3 > 0) k_body_slots<<<cdiv(nv3, 256), 256, 0, s>>>(from, to, nv3);
   return hipGetLastError();
 }
 
 hipError_t launch_adjb_body(int prec, const FluidArgs& a, const BodyArgs& b, const AdjIB& ib, hipStream_t s) {
-  const long long items = (long long)b.ne + b.nh + b.nf + b.nsoft_v;
-  if (items == 0) return hipSuccess;
-  const unsigned grid = cdiv(items, 128);
+  const long long threads = adjb_body_face0(b) + (2LL * b.nf * ADJ_GS + 63) / 64 * 64 + (long long)b.nsoft_v * ADJ_GS;
+  if ((long long)b.ne + b.nh + b.nf + b.nsoft_v == 0) return hipSuccess;
+  const unsigned grid = cdiv(threads, 128);
   switch (prec) {
     case 0: k_adjb_body<double><<<grid, 128, 0, s>>>(a, b, ib); break;
     case 1: k_adjb_body<float><<<grid, 128, 0, s>>>(a, b, ib); break;
@@ -4197,7 +4301,7 @@ hipError_t launch_adjb_support(const Grid& g, const uint8_t* ncls, const BodyArg
 
 hipError_t launch_adjb_markers(int prec, const FluidArgs& a, const BodyArgs& b, const AdjIB& ib, hipStream_t s) {
   if (b.nf == 0) return hipSuccess;
-  const unsigned grid = cdiv(b.nf, 128);
+  const unsigned grid = cdiv((long long)b.nf * ADJ_GS, 128);
   switch (prec) {
     case 0: k_adjb_markers<double><<<grid, 128, 0, s>>>(a, b, ib); break;
     case 1: k_adjb_markers<float><<<grid, 128, 0, s>>>(a, b, ib); break;
