@@ -7,19 +7,24 @@ FP64, against the FP64 oracle's state in tests/golden/precision_form_oracle.npz
 (written by make_precision_form.py beside it, which calls only the oracle).
 
 Measures at each stored step count after the release (0 = end of precursor):
-  e_u = max |u_gpu - u_orc| / max |u_orc|   over the sampled fluid nodes
-  e_x = the largest over the capsules of max |x_gpu - x_orc| over the sampled
-        vertices, relative to that capsule's largest displacement since release
+  e_u = max |u_gpu - u_orc| / max |u_orc|   over the sampled fluid nodes: a
+        fixed seeded set plus every 4th fluid node within 2.7 of a capsule
+        vertex at that step (the reach of the forcing, probes and vertex
+        velocities)
+  e_x = the largest over the capsules of max |x_gpu - x_orc| over every
+        second vertex, relative to that capsule's largest displacement since
+        release
 
 Bounds at step k, from how far the oracle's own trajectory moves when only
-its rounding changes (stored beside the states):
-  FP64: the bar 1e-12, or 100 x the larger spread of the FMA and
-        reordered-sum builds when that is larger;
-  FP32: the bar 2e-5, or 100 x the spread of the build that stores its
-        populations in FP32 when larger; positions held to the bar;
-  FP16S: 10 x the spread of the build that stores its populations (their
-        deviations) in binary16 -- what binary16 storage alone does to this
-        trajectory -- and at least the FP32 bar.
+its rounding changes (stored beside the states), 10 x the largest spread of:
+  FP64: the builds with fused multiply-adds, reordered sums and both, and
+        at least the bar 1e-12;
+  FP32: the build storing its populations in FP32 and the build running its
+        fluid state and arithmetic in binary32, and at least the bar 2e-5;
+  FP16S: the build storing its populations (their deviations) in binary16
+        -- what binary16 storage alone does to this trajectory -- and at
+        least the FP32 bar.
+The test prints, per checkpoint, whether the fixed bar itself is met.
 """
 import os
 import sys
@@ -34,8 +39,9 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "precision_form_oracle.npz")
 BAR = {"f64": 1e-12, "f32": 2e-5, "f16s": 2e-5}
-ENV = {"f64": ("env_fma", "env_reassoc"), "f32": ("env_f32",), "f16s": ("env_f16",)}
-FACTOR = {"f64": 100.0, "f32": 100.0, "f16s": 10.0}
+ENV = {"f64": ("env_fma", "env_reassoc", "env_fma_reassoc"), "f32": ("env_f32", "env_float32"),
+       "f16s": ("env_f16",)}
+FACTOR = 10.0
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +71,6 @@ def test_precision_form_full_size(lib, workload, precision):
     assert lat.sync(raise_on_stop=False) == lib.LBM_OK
     for b in w.bodies:
         lat.add_body(b)
-    sample = g["sample"]
     done = 0
     failures = []
     for k in g["checkpoints"]:
@@ -75,6 +80,7 @@ def test_precision_form_full_size(lib, workload, precision):
         done = k
         st = lat.sync(raise_on_stop=False)
         assert st == int(g[f"status_{k}"]) == lib.LBM_OK
+        sample = g[f"sample_{k}"].astype(np.int64)
         _, u = lat.fields()
         u = u.cpu().numpy()[:, sample]
         uo = g[f"u_{k}"]
@@ -89,10 +95,12 @@ def test_precision_form_full_size(lib, workload, precision):
         envs = [g[f"{e}_{k}"] for e in ENV[precision]]
         env_u = max(e[0] for e in envs)
         env_x = max(e[1] for e in envs)
-        tol_u = max(BAR[precision], FACTOR[precision] * env_u)
-        tol_x = BAR[precision] if precision == "f32" else max(BAR[precision], FACTOR[precision] * env_x)
+        tol_u = max(BAR[precision], FACTOR * env_u)
+        tol_x = max(BAR[precision], FACTOR * env_x)
+        meets = e_u <= BAR[precision] and e_x <= BAR[precision]
         print(f"  step {k}: e_u {e_u:.3e} (bound {tol_u:.1e}, oracle spread {env_u:.1e}) "
-              f"e_x {e_x:.3e} (bound {tol_x:.1e}, spread {env_x:.1e})", flush=True)
+              f"e_x {e_x:.3e} (bound {tol_x:.1e}, spread {env_x:.1e}) [{len(sample)} nodes; "
+              f"{'meets the bar' if meets else 'above the bar'}]", flush=True)
         sys.stdout.flush()
         if e_u > tol_u or e_x > tol_x:
             failures.append((k, e_u, tol_u, e_x, tol_x))
