@@ -109,3 +109,25 @@ def test_torch_adjoint_matches_oracle_differences(name):
             fd.append((jp - jm) / (2 * h * base))
         gap = abs(fd[0] - fd[1])
         assert abs(grad[k] - fd[1]) <= 1e-8 * abs(grad[k]) + 4 * gap, (k, grad[k], fd)
+
+
+def test_taylor_deformation_of_a_stretched_sphere():
+    """The vertex second-moment tensor of an icosphere is isotropic (its
+    icosahedral symmetry admits no other symmetric tensor), so stretching it
+    by (a, b, c) along rotated axes makes the eigenvalues proportional to
+    a^2, b^2, c^2 and D_T = (a - c) / (a + c) exactly (the Taylor deformation
+    of the stretched sphere).  Picking the middle eigenvalue, dropping the
+    square roots or not centring the vertices fails this."""
+    from scipy.spatial.transform import Rotation
+
+    X, _ = synth.icosphere(3, 1.0, (0.0, 0.0, 0.0), tilt=True)
+    d = X - X.mean(0)
+    M = d.T @ d / len(X)
+    assert np.abs(M - np.eye(3) * M.trace() / 3).max() < 1e-14
+    Q = Rotation.from_rotvec([0.4, -1.1, 0.7]).as_matrix()
+    for abc in [(1.3, 1.0, 0.8), (2.0, 0.5, 0.5), (0.7, 1.6, 1.1), (1.0, 1.0, 1.0)]:
+        s = np.array(abc)
+        Y = ((X @ Q) * s) @ Q.T + np.array([10.0, -3.0, 7.5])
+        D = float(taylor_deformation(torch.tensor(Y)))
+        want = (s.max() - s.min()) / (s.max() + s.min())
+        assert abs(D - want) < 1e-12, (abc, D, want)
