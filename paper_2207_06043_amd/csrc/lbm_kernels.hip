@@ -3710,32 +3710,18 @@ __device__ bool mls_each_g(const Grid& G, const uint8_t* ncls, const T (&p)[3], 
   const int ix[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
   const double dmax = fmax(fmax(dval(A[0]), dval(A[4])), fmax(dval(A[7]), dval(A[9])));
   if (!(dmax > 0.0)) return false;
-  T L[4][4];
+  // Cholesky factor, lower triangle packed row by row: L(i, j) = Lp[i (i + 1) / 2 + j]
+  T Lp[10];
   for (int j = 0; j < 4; j++) {
     T d = A[ix[j][j]];
-    for (int k = 0; k < j; k++) d -= L[j][k] * L[j][k];
+    for (int k = 0; k < j; k++) d -= Lp[j * (j + 1) / 2 + k] * Lp[j * (j + 1) / 2 + k];
     if (!(dval(d) > 1e-10 * dmax)) return false;
-    L[j][j] = dsqrt(d);
+    Lp[j * (j + 1) / 2 + j] = dsqrt(d);
     for (int i = j + 1; i < 4; i++) {
       T v = A[ix[i][j]];
-      for (int k = 0; k < j; k++) v -= L[i][k] * L[j][k];
-      L[i][j] = v / L[j][j];
+      for (int k = 0; k < j; k++) v -= Lp[i * (i + 1) / 2 + k] * Lp[j * (j + 1) / 2 + k];
+      Lp[i * (i + 1) / 2 + j] = v / Lp[j * (j + 1) / 2 + j];
     }
-  }
-  T Ai[4][4];
-  for (int c = 0; c < 4; c++) {
-    T y[4], z[4];
-    for (int i = 0; i < 4; i++) {
-      T v = Scal<T>::c(i == c ? 1.0 : 0.0);
-      for (int k = 0; k < i; k++) v -= L[i][k] * y[k];
-      y[i] = v / L[i][i];
-    }
-    for (int i = 3; i >= 0; i--) {
-      T v = y[i];
-      for (int k = i + 1; k < 4; k++) v -= L[k][i] * z[k];
-      z[i] = v / L[i][i];
-    }
-    for (int i = 0; i < 4; i++) Ai[i][c] = z[i];
   }
   for (int k = lane; k < 27; k += GS) {
     long long node;
@@ -3743,12 +3729,19 @@ __device__ bool mls_each_g(const Grid& G, const uint8_t* ncls, const T (&p)[3], 
     if (!support_node(G, ncls, c[0], c[1], c[2], node)) continue;
     const T P[4] = {Scal<T>::c(1.0), (double)c[0] - p[0], (double)c[1] - p[1], (double)c[2] - p[2]};
     const T W = dexp((P[1] * P[1] + P[2] * P[2] + P[3] * P[3]) * (-MLS_K));
-    T psi[4];
+    // psi = W A^{-1} P by the two triangular solves
+    T y[4], psi[4];
     for (int i = 0; i < 4; i++) {
-      T v = Ai[i][0] * P[0];
-      for (int j = 1; j < 4; j++) v += Ai[i][j] * P[j];
-      psi[i] = W * v;
+      T v = P[i];
+      for (int j = 0; j < i; j++) v -= Lp[i * (i + 1) / 2 + j] * y[j];
+      y[i] = v / Lp[i * (i + 1) / 2 + i];
     }
+    for (int i = 3; i >= 0; i--) {
+      T v = y[i];
+      for (int j = i + 1; j < 4; j++) v -= Lp[j * (j + 1) / 2 + i] * psi[j];
+      psi[i] = v / Lp[i * (i + 1) / 2 + i];
+    }
+    for (int i = 0; i < 4; i++) psi[i] = W * psi[i];
     fn(k, node, psi);
   }
   return true;
