@@ -3905,33 +3905,45 @@ __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjI
     const int vv[3] = {b.faces[3 * f], b.faces[3 * f + 1], b.faces[3 * f + 2]};
     double ab[3];
     for (int k = 0; k < 3; k++) ab[k] = (ib.Fb[3 * vv[0] + k] + ib.Fb[3 * vv[1] + k] + ib.Fb[3 * vv[2] + k]) / 3.0;
-    Dual<9> P[3][3];
-    for (int r = 0; r < 3; r++)
-      for (int k = 0; k < 3; k++) P[r][k] = dseed<9>(X[3 * vv[r] + k], 3 * r + k);
-    Dual<9> u[3], w[3], N[3];
-    for (int k = 0; k < 3; k++) {
-      u[k] = P[1][k] - P[0][k];
-      w[k] = P[2][k] - P[0][k];
+    // unit normal n and area A with their derivatives in the nine vertex
+    // coordinates (j = 3 r + k), by dual numbers in this scope only
+    double nv[3], Av, dn[3][9], dA[9], cen[3];
+    {
+      Dual<9> P[3][3];
+      for (int r = 0; r < 3; r++)
+        for (int k = 0; k < 3; k++) P[r][k] = dseed<9>(X[3 * vv[r] + k], 3 * r + k);
+      Dual<9> u[3], w[3], N[3];
+      for (int k = 0; k < 3; k++) {
+        u[k] = P[1][k] - P[0][k];
+        w[k] = P[2][k] - P[0][k];
+      }
+      cross_t(u, w, N);
+      const Dual<9> ln = dsqrt(dot_t(N, N));
+      for (int k = 0; k < 3; k++) {
+        const Dual<9> nk = N[k] / ln;
+        nv[k] = nk.v;
+        for (int j = 0; j < 9; j++) dn[k][j] = nk.d[j];
+        cen[k] = (P[0][k].v + P[1][k].v + P[2][k].v) / 3.0;
+      }
+      Av = 0.5 * ln.v;
+      for (int j = 0; j < 9; j++) dA[j] = 0.5 * ln.d[j];
     }
-    cross_t(u, w, N);
-    const Dual<9> ln = dsqrt(dot_t(N, N));
-    Dual<9> n[3], cen[3];
-    for (int k = 0; k < 3; k++) {
-      n[k] = N[k] / ln;
-      cen[k] = (P[0][k] + P[1][k] + P[2][k]) / 3.0;
-    }
-    const Dual<9> A = ln * 0.5;
     const double nu = b.nu;
     const double V0 = b.b_param[8 * body], kv = b.b_param[8 * body + 2];
     const double cv = kv * (1.0 - b.b_diag[16 * body] / V0);
-    const Dual<9> an = ab[0] * n[0] + ab[1] * n[1] + ab[2] * n[2];
-    Dual<9> s = side == 0 ? A * an * cv : Scal<Dual<9>>::c(0.0);  // the volume force
-    double visc = 0.0;                                              // d s / d nu
+    const double an = ab[0] * nv[0] + ab[1] * nv[1] + ab[2] * nv[2];
+    double dan[9];
+    for (int j = 0; j < 9; j++) dan[j] = ab[0] * dn[0][j] + ab[1] * dn[1][j] + ab[2] * dn[2][j];
+    // ds[j]: derivative of this group's part of ab . Ft in vertex coordinate j
+    double ds[9];
+    for (int j = 0; j < 9; j++) ds[j] = side == 0 ? cv * (dA[j] * an + Av * dan[j]) : 0.0;  // the volume force
+    double visc = 0.0;  // d s / d nu
     {
       const double sg = side == 0 ? 1.2 : -1.2, sgn = side == 0 ? 1.0 : -1.0;
-      Dual<9> pp[3];
-      for (int k = 0; k < 3; k++) pp[k] = cen[k] + n[k] * sg;
-      const Dual<3> q[3] = {dseed<3>(pp[0].v, 0), dseed<3>(pp[1].v, 1), dseed<3>(pp[2].v, 2)};
+      double pp[3];
+      for (int k = 0; k < 3; k++) pp[k] = cen[k] + nv[k] * sg;
+      // the fits at the probe, with their derivatives in its coordinates
+      const Dual<3> q[3] = {dseed<3>(pp[0], 0), dseed<3>(pp[1], 1), dseed<3>(pp[2], 2)};
       Dual<3> r3 = Scal<Dual<3>>::c(0.0), G3[3][3];
       for (int i = 0; i < 3; i++)
         for (int c = 0; c < 3; c++) G3[i][c] = Scal<Dual<3>>::c(0.0);
@@ -3945,31 +3957,35 @@ __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjI
       r3 = group_sum<ADJ_GS>(r3) + 1.0;  // the weights add up to 1: rho = 1 + the fit of rho - 1
       for (int i = 0; i < 3; i++)
         for (int c = 0; c < 3; c++) G3[i][c] = group_sum<ADJ_GS>(G3[i][c]);
-      const Dual<9> r9 = lift9(r3, pp);
-      Dual<9> sv = Scal<Dual<9>>::c(0.0);  // ab . ((G + G^T) n)
-      double svv = 0.0;
-      double Gv[3][3];
+      // s = A sgn r Q with Q = -an/3 + nu sv, sv = sum_ic ab_i (G_ic + G_ci) n_c;
+      // the probe moves with the face: dp_m/dx_j = [m == j % 3]/3 + sg dn_m/dx_j
+      double sv = 0.0, h[3] = {0.0, 0.0, 0.0}, qc[3] = {0.0, 0.0, 0.0};
       for (int i = 0; i < 3; i++)
         for (int c = 0; c < 3; c++) {
-          Gv[i][c] = G3[i][c].v;
-          const Dual<9> g9 = lift9(G3[i][c], pp);
-          const Dual<9> t = g9 * (ab[i] * 1.0);
-          sv += t * n[c];  // ab_i G_ic n_c
-          Dual<9> t2 = g9 * n[i];
-          sv += t2 * ab[c];  // ab_c G_ic n_i (the transpose)
+          const double gs = G3[i][c].v + G3[c][i].v;
+          sv += ab[i] * gs * nv[c];
+          qc[c] += ab[i] * gs;
+          for (int m = 0; m < 3; m++) h[m] += ab[i] * (G3[i][c].d[m] + G3[c][i].d[m]) * nv[c];
         }
-      for (int i = 0; i < 3; i++)
-        for (int c = 0; c < 3; c++) svv += ab[i] * (Gv[i][c] + Gv[c][i]) * n[c].v;
-      s += A * sgn * (r9 * an * (-1.0 / 3.0) + r9 * sv * nu);
-      visc += A.v * sgn * r9.v * svv;
+      const double rv = r3.v, Q = -an / 3.0 + nu * sv;
+      for (int j = 0; j < 9; j++) {
+        double drj = 0.0, dsvj = 0.0;
+        for (int m = 0; m < 3; m++) {
+          const double dp = (m == j % 3 ? 1.0 / 3.0 : 0.0) + sg * dn[m][j];
+          drj += r3.d[m] * dp;
+          dsvj += h[m] * dp + qc[m] * dn[m][j];
+        }
+        const double dQ = -dan[j] / 3.0 + nu * dsvj;
+        ds[j] += sgn * (dA[j] * rv * Q + Av * (drj * Q + rv * dQ));
+      }
+      visc += Av * sgn * rv * sv;
       // field adjoints at this probe's supports
-      const double rbar = A.v * sgn * (-an.v / 3.0 + nu * svv);
+      const double rbar = Av * sgn * Q;
       double Gbar[3][3];
       for (int i = 0; i < 3; i++)
-        for (int c = 0; c < 3; c++) Gbar[i][c] = A.v * sgn * nu * r9.v * (ab[i] * n[c].v + ab[c] * n[i].v);
-      const double qv[3] = {pp[0].v, pp[1].v, pp[2].v};
+        for (int c = 0; c < 3; c++) Gbar[i][c] = Av * sgn * nu * rv * (ab[i] * nv[c] + ab[c] * nv[i]);
       if (real)  // (uniform over the group)
-        mls_each_g<ADJ_GS>(G, a.ncls, qv, lane, [&](int, long long node, const double(&psi)[4]) {
+        mls_each_g<ADJ_GS>(G, a.ncls, pp, lane, [&](int, long long node, const double(&psi)[4]) {
           atomicAdd(ib.ext + node, rbar * psi[0]);
           for (int i = 0; i < 3; i++)
             atomicAdd(ib.ext + (long long)(1 + i) * G.Np + node,
@@ -3977,11 +3993,12 @@ __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjI
           set_tile(ib.etf, node);
         });
     }
+    const double A_v = Av;
     // the scalar gradients summed over the wave first (one group's lane 0
     // per face side contributes), then one atomic per wave
     const bool lead = real && lane == 0;
     const double gv = group_sum<64>(lead ? visc / 3.0 : 0.0);  // nu = (tau - 1/2) / 3
-    const double gk = group_sum<64>(lead && side == 0 && b.b_param[8 * body + 6] != 0.0 ? cv * A.v * an.v * ikap : 0.0);
+    const double gk = group_sum<64>(lead && side == 0 && b.b_param[8 * body + 6] != 0.0 ? cv * A_v * an * ikap : 0.0);
     if ((threadIdx.x & 63) == 0) {
       if (gv != 0.0) atomicAdd(ib.gsum, gv);
       if (gk != 0.0) atomicAdd(ib.gsum + 1, gk);
@@ -3990,7 +4007,7 @@ __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjI
     // belong to one body
     {
       const int bsel = lead && side == 0 ? body : -1;
-      const double gb = bsel >= 0 ? A.v * an.v : 0.0;
+      const double gb = bsel >= 0 ? A_v * an : 0.0;
       const unsigned long long bm = __ballot(bsel >= 0);
       if (bm) {
         const int first = __shfl(bsel, __ffsll((unsigned long long)bm) - 1, 64);
@@ -4004,7 +4021,7 @@ __global__ __launch_bounds__(128) void k_adjb_body(FluidArgs a, BodyArgs b, AdjI
     }
     if (!lead) return;
     for (int r = 0; r < 3; r++)
-      for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * vv[r] + k, s.d[3 * r + k]);
+      for (int k = 0; k < 3; k++) atomicAdd(ib.LP + 3 * vv[r] + k, ds[3 * r + k]);
     return;
   }
   const long long idx = grp - nfg;
