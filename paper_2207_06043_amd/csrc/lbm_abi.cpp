@@ -259,6 +259,19 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   G.Np = (long long)G.px * G.ny * G.nz;
   G.plane = (G.Np + 64 + 63) / 64 * 64;
   G.guard = ((long long)G.px * G.ny + G.px + 16 + 63) / 64 * 64;
+  {
+    auto magic = [](unsigned int d, unsigned int& m, int& s) {
+      int l = 0;
+      while ((1ull << l) < d) l++;
+      s = 31 + l;
+      m = (unsigned int)(((1ull << s) + d - 1) / d);
+    };
+    magic((unsigned int)G.px, G.mpx, G.spx);
+    magic((unsigned int)G.ny, G.mny, G.sny);
+  }
+  // the kernels take padded indices, the guard rows of both sides included,
+  // as int
+  if ((long long)G.px * G.ny * (G.nz + 2) + 2LL * G.px + 1024 >= (1LL << 31)) return bad("grid too large");
   const long long N = (long long)d->nx * d->ny * d->nz;
   const int nx = d->nx, ny = d->ny, nz = d->nz;
   auto lin = [&](int x, int y, int z) { return x + (long long)nx * (y + (long long)ny * z); };

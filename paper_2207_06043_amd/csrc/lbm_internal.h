@@ -59,6 +59,11 @@ struct Grid {
   long long Np;    // px*ny*nz
   long long plane; // distance between population planes (elements)
   long long guard; // elements allocated before plane 0 and after plane 18
+  // division of a padded index (< 2^31) by px and by ny as a multiply and a
+  // shift: q = (u m) >> s with m = ceil(2^s / d), s = 31 + ceil(log2 d)
+  // (exact for every u < 2^31, since m d - 2^s < d <= 2^(s - 31))
+  unsigned int mpx, mny;
+  int spx, sny;
 };
 
 // Everything the fluid and IB kernels need (passed by value).

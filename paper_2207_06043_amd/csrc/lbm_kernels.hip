@@ -85,12 +85,44 @@ __device__ __forceinline__ long long nbr(const Grid& G, int x, int y, int z, int
   return x + (long long)G.px * (y + (long long)G.ny * z);
 }
 
+__device__ __forceinline__ unsigned int udiv31(unsigned int u, unsigned int m, int s) {
+  return (unsigned int)(((unsigned long long)u * m) >> s);
+}
 __device__ __forceinline__ void coords(const Grid& G, long long n, int& x, int& y, int& z) {
   const unsigned int u = (unsigned int)n;  // padded index < 2^31
   const unsigned int t = u / (unsigned int)G.px;
   x = (int)(u - t * (unsigned int)G.px);
   z = (int)(t / (unsigned int)G.ny);
   y = (int)(t - (unsigned int)z * (unsigned int)G.ny);
+}
+// The same with the divisions as multiply-shifts (fewer instructions; the
+// fluid kernels, where the instruction count bounds the FP16S sweep).
+__device__ __forceinline__ void coords_ms(const Grid& G, long long n, int& x, int& y, int& z) {
+  const unsigned int u = (unsigned int)n;
+  const unsigned int t = udiv31(u, G.mpx, G.spx);
+  x = (int)(u - t * (unsigned int)G.px);
+  z = (int)udiv31(t, G.mny, G.sny);
+  y = (int)(t - (unsigned int)z * (unsigned int)G.ny);
+}
+
+// The wrapped neighbourhood of a node for offsets -2..2 on each axis, as the
+// three terms of a padded index (x, px y, px ny z): at() gives the same index
+// as nbr(), with the wraps done once per node instead of once per neighbour.
+struct Hood {
+  int tx[5], ty[5], tz[5];
+  __device__ __forceinline__ int at(int dx, int dy, int dz) const {
+    return tx[dx + 2] + ty[dy + 2] + tz[dz + 2];
+  }
+};
+__device__ __forceinline__ Hood hood(const Grid& G, int x, int y, int z) {
+  Hood h;
+#pragma unroll
+  for (int d = 0; d < 5; d++) {
+    h.tx[d] = wrap2(x + d - 2, G.nx);
+    h.ty[d] = G.px * wrap2(y + d - 2, G.ny);
+    h.tz[d] = G.px * G.ny * wrap2(z + d - 2, G.nz);
+  }
+  return h;
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; give every XCD a
@@ -126,6 +158,16 @@ __device__ __forceinline__ C dev_sum(const C (&g)[19]) {
   return g[0] + ((ax + d1) + d2);
 }
 
+// e v for a lattice velocity component e in {-1, 0, 1}.  The zero term is
+// -0, which an addition drops exactly, so the unrolled dot products below
+// keep only their non-zero terms: the same values as the full products
+// (0 v + w = w), without the multiplications by zero that IEEE arithmetic
+// would otherwise have to carry out.
+template <class C>
+__device__ __forceinline__ C eterm(int e, C v) {
+  return e == 0 ? C(-0.0) : (e > 0 ? v : -v);
+}
+
 // BGK with the forcing term on deviations g = f - w (Eqs. evoleq, eqfunc,
 // forcing): rho = 1 + sum g, rho u = sum g e + F/2,
 // g^eq_i = w_i (drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)),
@@ -148,8 +190,8 @@ __device__ __forceinline__ void collide(C (&g)[19], C Fx, C Fy, C Fz, C omega, C
   C kf = C(1) - C(0.5) * omega;
 #pragma unroll
   for (int i = 0; i < 19; i++) {
-    C eu = C(EX[i]) * ux + C(EY[i]) * uy + C(EZ[i]) * uz;
-    C eF = C(EX[i]) * Fx + C(EY[i]) * Fy + C(EZ[i]) * Fz;
+    C eu = eterm(EX[i], ux) + eterm(EY[i], uy) + eterm(EZ[i], uz);
+    C eF = eterm(EX[i], Fx) + eterm(EY[i], Fy) + eterm(EZ[i], Fz);
     C w = C(WD[i]);
     C geq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * usq));
     C Gi = kf * w * (C(3) * (eF - uF) + C(9) * eu * eF);
@@ -249,7 +291,31 @@ struct Bfl {
 
 template <class S>
 __device__ __forceinline__ Bfl<S> bfl_load(const FluidArgs& a, int j, bool linked, int lk, bool hq,
-                                           long long node, int x, int y, int z) {
+                                           int node, const Hood& h) {
+  typedef typename Store<S>::C C;
+  const Grid& G = a.g;
+  const C* lc = (const C*)a.lk_c;
+  const S* A = (const S*)a.A;
+  const long long nl = a.nlinks;
+  const int i = OPP[j];
+  const int l = linked ? lk : 0;
+  const int n1 = linked ? h.at(EX[j], EY[j], EZ[j]) : node;  // x - e_i
+  const int n2 = linked ? h.at(2 * EX[j], 2 * EY[j], 2 * EZ[j]) : node;
+  Bfl<S> r;
+  r.k0 = lc[l];
+  r.k1 = lc[nl + l];
+  r.k2 = lc[2 * nl + l];
+  r.s = ldA<S>(a, i, node);
+  r.t1 = to_c(A[hq ? (long long)j * G.plane + node : (long long)i * G.plane + n1]);
+  r.t2 = to_c(A[hq ? (long long)j * G.plane + n1 : (long long)i * G.plane + n2]);
+  return r;
+}
+
+// The same loads with each neighbour index formed on its own (fewer values
+// live at once: used where registers are scarce, in the IB kernels).
+template <class S>
+__device__ __forceinline__ Bfl<S> bfl_load_nb(const FluidArgs& a, int j, bool linked, int lk, bool hq,
+                                              long long node, int x, int y, int z) {
   typedef typename Store<S>::C C;
   const Grid& G = a.g;
   const C* lc = (const C*)a.lk_c;
@@ -284,13 +350,15 @@ template <class S>
 __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g)[19], bool zh = true) {
   typedef typename Store<S>::C C;
   const Grid& G = a.g;
-  const long long node = a.rec_node[r];
+  const S* A = (const S*)a.A;
+  const int node = a.rec_node[r];
   const uint32_t mask = a.rec_mask[r];
   const uint32_t hqm = a.rec_mb[r];
   const int lk0 = a.rec_link0[r];
   const int fc = a.rec_face[r];
   int x, y, z;
   coords(G, node, x, y, z);
+  const Hood h = hood(G, x, y, z);
   const int face = fc & 7, kind = (fc >> 4) & 1;
   const int ax = face >> 1, s = (face & 1) ? -1 : 1;
   C pl[19];
@@ -302,8 +370,8 @@ __device__ void pull_general(const FluidArgs& a, int r, typename Store<S>::C (&g
     const bool linked = (mask >> j) & 1u;
     const bool unknown = fc != 0xff && s * (ax == 0 ? e[0] : (ax == 1 ? e[1] : e[2])) == 1;
     const bool plain = !linked && !unknown;
-    pl[j] = ldA<S>(a, plain ? j : 0, plain ? nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]) : node);
-    bb[j] = bfl_load<S>(a, j, linked, lk0 + __popc(mask & ((1u << j) - 1u)), (hqm >> j) & 1u, node, x, y, z);
+    pl[j] = to_c(A[plain ? (long long)j * G.plane + h.at(-EX[j], -EY[j], -EZ[j]) : (long long)node]);
+    bb[j] = bfl_load<S>(a, j, linked, lk0 + __popc(mask & ((1u << j) - 1u)), (hqm >> j) & 1u, node, h);
   }
   g[0] = pl[0];
 #pragma unroll
@@ -352,7 +420,7 @@ __device__ __forceinline__ Moments streamed_moments(const FluidArgs& a, long lon
       const bool linked = (mask >> j) & 1u;
       const bool plain = !linked && !(fc != 0xff && en == 1);
       pl[j] = ldA<S>(a, plain ? j : 0, plain ? nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]) : node);
-      bb[j] = bfl_load<S>(a, j, linked, lk0 + __popc(mask & ((1u << j) - 1u)), (hqm >> j) & 1u, node, x, y, z);
+      bb[j] = bfl_load_nb<S>(a, j, linked, lk0 + __popc(mask & ((1u << j) - 1u)), (hqm >> j) & 1u, node, x, y, z);
     }
     g[0] = (double)pl[0];
 #pragma unroll
@@ -403,8 +471,9 @@ __device__ __forceinline__ void pull_node(const FluidArgs& a, long long node,
     const Grid& G = a.g;
     int x, y, z;
     coords(G, node, x, y, z);
+    const Hood h = hood(G, x, y, z);
 #pragma unroll
-    for (int j = 0; j < 19; j++) g[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
+    for (int j = 0; j < 19; j++) g[j] = ldA<S>(a, j, h.at(-EX[j], -EY[j], -EZ[j]));
   } else {
     pull_general<S>(a, a.rec_of[node], g);
   }
@@ -497,21 +566,42 @@ __device__ void fluid_bulk(const FluidArgs& a, int blk) {
   S* B = (S*)a.B;
   const C omega = (C)a.omega;
   int x0, y, z;
-  coords(G, base, x0, y, z);
+  coords_ms(G, base, x0, y, z);
+  // The nine source rows (y - e_y, z - e_z), wrapped once on periodic axes
+  // (on closed ones the guard rows take the discarded pulls), as element
+  // offsets from the start of a plane: padded indices, guards included,
+  // stay inside int range (checked when the lattice is created).
+  int rows[3][3];
+  {
+    const int pxy = G.px * G.ny;
+    int ty[3], tz[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      ty[d] = G.px * (G.per[1] ? wrap2(y + d - 1, G.ny) : y + d - 1);
+      tz[d] = pxy * (G.per[2] ? wrap2(z + d - 1, G.nz) : z + d - 1);
+    }
+#pragma unroll
+    for (int dz = 0; dz < 3; dz++)
+#pragma unroll
+      for (int dy = 0; dy < 3; dy++) rows[dz][dy] = (ty[dy] + x0) + tz[dz];
+  }
   // periodic x: groups touching x = 0 or x = nx-1 gather element by element
   const bool xedge = PERX && (x0 == 0 || x0 + V > G.nx - 1);
   vec in[19];
+  if (!PERX || !xedge) {
 #pragma unroll
-  for (int j = 0; j < 19; j++) {
-    const int sy = (G.per[1] ? wrap2(y - EY[j], G.ny) : y - EY[j]);
-    const int sz = (G.per[2] ? wrap2(z - EZ[j], G.nz) : z - EZ[j]);
-    const long long row = (long long)G.px * (sy + (long long)G.ny * sz);
-    const S* pl = A + (long long)j * G.plane + row;
-    if (EX[j] == 0) {
-      in[j] = *(const vec*)(pl + x0);
-    } else if (!PERX || !xedge) {
-      in[j] = *(const vecu*)(pl + x0 - EX[j]);
-    } else {
+    for (int j = 0; j < 19; j++) {
+      const S* pl = A + (long long)j * G.plane;
+      const int o = rows[1 - EZ[j]][1 - EY[j]];
+      if (EX[j] == 0)
+        in[j] = *(const vec*)(pl + o);
+      else
+        in[j] = *(const vecu*)(pl + (o - EX[j]));
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 19; j++) {
+      const S* pl = A + (long long)j * G.plane + (rows[1 - EZ[j]][1 - EY[j]] - x0);
 #pragma unroll
       for (int k = 0; k < V; k++) in[j][k] = pl[wrap2(x0 + k - EX[j], G.nx)];
     }
@@ -530,15 +620,16 @@ __device__ void fluid_bulk(const FluidArgs& a, int blk) {
 #pragma unroll
     for (int j = 0; j < 19; j++) in[j][k] = (S)g[j];
   }
+  const int b32 = (int)base;
   if (all) {
 #pragma unroll
-    for (int j = 0; j < 19; j++) *(vec*)(B + (long long)j * G.plane + base) = in[j];
+    for (int j = 0; j < 19; j++) *(vec*)(B + (long long)j * G.plane + b32) = in[j];
   } else {
 #pragma unroll
     for (int j = 0; j < 19; j++)
 #pragma unroll
       for (int k = 0; k < V; k++)
-        if (isb[k]) B[(long long)j * G.plane + base + k] = in[j][k];
+        if (isb[k]) B[(long long)j * G.plane + (b32 + k)] = in[j][k];
   }
   if (bad) raise_pending(a.flags, ST_UNSTABLE);
 }
@@ -2789,8 +2880,9 @@ __device__ __forceinline__ void adj_fwd_bulk_one(const FluidArgs& a, int t) {
   int x, y, z;
   coords(G, n, x, y, z);
   C g[19], dr, ux, uy, uz, Fx, Fy, Fz;
+  const Hood h = hood(G, x, y, z);
 #pragma unroll
-  for (int j = 0; j < 19; j++) g[j] = ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
+  for (int j = 0; j < 19; j++) g[j] = ldA<S>(a, j, h.at(-EX[j], -EY[j], -EZ[j]));
   node_force<C>(a, n, a.tflag && a.tflag[n >> TILE_SHIFT], Fx, Fy, Fz);
   collide<C>(g, Fx, Fy, Fz, (C)a.omega, dr, ux, uy, uz);
   if (a.mac) store_mac<C>(a, n, dr, ux, uy, uz);
@@ -2995,14 +3087,15 @@ __device__ __forceinline__ void adj_links_one(const FluidArgs& a, int r, long lo
   const long long nl = a.nlinks;
   int x, y, z;
   coords(G, node, x, y, z);
+  const Hood hd = hood(G, x, y, z);
 #pragma unroll
   for (int j = 1; j < 19; j++) {
     if (!((mask >> j) & 1u)) continue;
     const int l = lk0 + __popc(mask & ((1u << j) - 1u));
     const int i = OPP[j];
     const bool hq = (hqm >> j) & 1u;
-    const long long n1 = nbr(G, x, y, z, EX[j], EY[j], EZ[j]);  // x - e_i
-    const long long n2 = nbr(G, x, y, z, 2 * EX[j], 2 * EY[j], 2 * EZ[j]);
+    const long long n1 = hd.at(EX[j], EY[j], EZ[j]);  // x - e_i
+    const long long n2 = hd.at(2 * EX[j], 2 * EY[j], 2 * EZ[j]);
     const double k0 = (double)lc[l], k1 = (double)lc[nl + l], k2 = (double)lc[2 * nl + l];
     if (k0 != 0.0) atomicAdd(acc + (long long)i * G.plane + node, k0 * m[j]);
     if (k1 != 0.0) atomicAdd(acc + (long long)(hq ? j : i) * G.plane + (hq ? node : n1), k1 * m[j]);
@@ -3039,9 +3132,10 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
   if (st.mode == 1 && !fflag && !(st.etf && st.etf[n >> TILE_SHIFT])) return;
   int x, y, z;
   coords(G, n, x, y, z);
+  const Hood hd = hood(G, x, y, z);
   if (!REC) {
 #pragma unroll
-    for (int j = 0; j < 19; j++) h[j] = (double)ldA<S>(a, j, nbr(G, x, y, z, -EX[j], -EY[j], -EZ[j]));
+    for (int j = 0; j < 19; j++) h[j] = (double)ldA<S>(a, j, hd.at(-EX[j], -EY[j], -EZ[j]));
   }
   const int q = REC ? a.nbulk_nodes + t : t;
   const uint32_t am = st.amask[q];
@@ -3052,7 +3146,7 @@ __device__ __forceinline__ void adj_reverse_one(const FluidArgs& a, const AdjSte
     const uint32_t pm = st.pmask[q];
 #pragma unroll
     for (int j = 0; j < 19; j++) {
-      const long long src = j == 0 ? n : nbr(G, x, y, z, EX[j], EY[j], EZ[j]);
+      const long long src = j == 0 ? n : hd.at(EX[j], EY[j], EZ[j]);
       double v = ((pm >> j) & 1u) ? st.mu_next[(long long)j * G.plane + src] : 0.0;
       if ((am >> j) & 1u) {
         double* pa = st.acc_in + (long long)j * G.plane + n;
