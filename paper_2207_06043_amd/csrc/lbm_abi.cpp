@@ -228,9 +228,10 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   }
   const bool large = n_open >= (4LL << 20);
   // measured on MI355X: FP16S runs 2 nodes per thread in 128-thread blocks
-  // on large grids (8 per thread: 1.5-1.6x slower) and the list form on
-  // small ones (24% faster than 2 per thread on the precision form)
-  ctx->bulk_v = large ? (d->precision == 0 ? 2 : (d->precision == 1 ? 4 : 2)) : (d->precision == 2 ? 0 : 1);
+  // on large grids (8 per thread: 1.6x slower) and the list form on small
+  // ones (24% faster than 2 per thread on the precision form); FP32 one
+  // node per thread (the D = 96 pipe 3% faster than 4, the 256^3 box the same)
+  ctx->bulk_v = large ? (d->precision == 0 ? 2 : (d->precision == 1 ? 1 : 2)) : (d->precision == 2 ? 0 : 1);
   ctx->bulk_block = large ? (d->precision == 2 ? 128 : 256) : 64;
   // small grids: one fluid launch (no fork/join between streams) with the
   // record blocks in the same 64-thread shape as the bulk tiles
