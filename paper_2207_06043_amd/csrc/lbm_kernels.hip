@@ -2384,13 +2384,26 @@ __global__ __launch_bounds__(256) void k_body_post(BodyArgs b, DevFlags* flags, 
 // step is one launch over the work units of all of them.  Block g of a
 // phase takes unit map[g] = (instance, block of that instance's own launch);
 // the instance's arguments are read from a device table (per step parity).
+// The tables are read through the constant address space: with a uniform
+// address such a load is a scalar load into SGPRs, and the compiler may
+// reload a field where it is used instead of holding it (a plain global
+// pointer gets vector loads, and every field then held in a VGPR).
+typedef const __attribute__((address_space(4))) BatchItem CBatchItem;
+typedef const __attribute__((address_space(4))) int CInt;
+__device__ __forceinline__ int2 batch_unit_at(const int2* map, int u) {
+  const CInt* p = (const CInt*)map;
+  return make_int2(p[2 * u], p[2 * u + 1]);
+}
+__device__ __forceinline__ int2 batch_unit(const int2* map) { return batch_unit_at(map, blockIdx.x); }
+__device__ __forceinline__ const BatchItem& batch_item(const BatchItem* items, int k) {
+  return *(const BatchItem*)&((CBatchItem*)items)[k];
+}
+
 template <class S>
 __global__ __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) void kb_ib_force(const BatchItem* items,
                                                                           const int2* map) {
-  const int2 m = map[blockIdx.x];
-  // the tables are read in place (uniform addresses: scalar loads), not
-  // copied into registers
-  const BatchItem& it = items[m.x];
+  const int2 m = batch_unit(map);
+  const BatchItem& it = batch_item(items, m.x);
   if (it.a.flags->stop) return;
   ib_force_block<S>(it.a, it.b, it.fxc, it.tfc, it.fxp, it.tfp, it.counter, m.y);
 }
@@ -2403,10 +2416,10 @@ __global__ __launch_bounds__(256, sizeof(S) == 8 ? 1 : 2) void kb_ib_force(const
 // each XCD takes a contiguous run of units (whole instances where possible).
 template <class S, int V, bool PERX>
 __global__ __launch_bounds__(256) void kb_fluid_all(const BatchItem* items, const int2* map) {
-  const int2 m = map[blockIdx.x];
-  const FluidArgs a = items[m.x].a;
+  const int2 m = batch_unit(map);
+  const FluidArgs a = batch_item(items, m.x).a;
   if (a.flags->stop) return;
-  fluid_unit<S, V, PERX>(a, items[m.x].nrb, m.y);
+  fluid_unit<S, V, PERX>(a, batch_item(items, m.x).nrb, m.y);
 }
 
 // Persistent form (its own kernel: holding an instance's arguments across
@@ -2422,11 +2435,11 @@ __global__ __launch_bounds__(256) void kb_fluid_all_persist(const BatchItem* ite
   bool stop = true;
   FluidArgs a;
   for (int u = u0 + j; u < u1; u += per_xcd) {
-    const int2 m = map[u];
+    const int2 m = batch_unit_at(map, u);
     if (m.x != cur) {
       cur = m.x;
-      a = items[m.x].a;
-      nrb = items[m.x].nrb;
+      a = batch_item(items, m.x).a;
+      nrb = batch_item(items, m.x).nrb;
       stop = a.flags->stop != 0u;
     }
     if (!stop) fluid_unit<S, V, PERX>(a, nrb, m.y);
@@ -2435,8 +2448,8 @@ __global__ __launch_bounds__(256) void kb_fluid_all_persist(const BatchItem* ite
 
 template <class S>
 __global__ __launch_bounds__(256) void kb_fluid_rec(const BatchItem* items, const int2* map) {
-  const int2 m = map[blockIdx.x];
-  const FluidArgs a = items[m.x].a;
+  const int2 m = batch_unit(map);
+  const FluidArgs a = batch_item(items, m.x).a;
   if (a.flags->stop) return;
   const int r = m.y * blockDim.x + threadIdx.x;
   if (r < a.nrec) fluid_record_thread<S>(a, r);
@@ -2447,8 +2460,8 @@ __global__ __launch_bounds__(256) void kb_fluid_rec(const BatchItem* items, cons
 // per_xcd.
 template <class S, int V, bool PERX>
 __global__ __launch_bounds__(256) void kb_fluid_bulk(const BatchItem* items, const int2* map) {
-  const int2 m = map[blockIdx.x];
-  const FluidArgs a = items[m.x].a;
+  const int2 m = batch_unit(map);
+  const FluidArgs a = batch_item(items, m.x).a;
   if (a.flags->stop) return;
   fluid_bulk<S, V, PERX>(a, m.y);
 }
@@ -2462,10 +2475,10 @@ __global__ __launch_bounds__(256) void kb_fluid_bulk_persist(const BatchItem* it
   bool stop = true;
   FluidArgs a;
   for (int u = u0 + j; u < u1; u += per_xcd) {
-    const int2 m = map[u];
+    const int2 m = batch_unit_at(map, u);
     if (m.x != cur) {  // an instance's arguments once per run of its units
       cur = m.x;
-      a = items[m.x].a;
+      a = batch_item(items, m.x).a;
       stop = a.flags->stop != 0u;
     }
     if (!stop) fluid_bulk<S, V, PERX>(a, m.y);
@@ -2474,20 +2487,17 @@ __global__ __launch_bounds__(256) void kb_fluid_bulk_persist(const BatchItem* it
 
 template <class S>
 __global__ __launch_bounds__(256) void kb_mls_post(const BatchItem* items, const int2* map) {
-  const int2 m = map[blockIdx.x];
-  const BatchItem& it = items[m.x];
-  const FluidArgs a = it.a;
-  if (a.flags->stop) return;
-  const BodyArgs b = it.b;
-  mls_post_unit<S>(a, b, it.fxp, it.tfp, m.y);
+  const int2 m = batch_unit(map);
+  const BatchItem& it = batch_item(items, m.x);
+  if (it.a.flags->stop) return;
+  mls_post_unit<S>(it.a, it.b, it.fxp, it.tfp, m.y);
 }
 
 __global__ __launch_bounds__(256) void kb_body_post(const BatchItem* items, const int2* map) {
-  const int2 m = map[blockIdx.x];
-  const BatchItem& it = items[m.x];
+  const int2 m = batch_unit(map);
+  const BatchItem& it = batch_item(items, m.x);
   if (it.a.flags->stop) return;
-  const BodyArgs b = it.b;
-  body_post_block(b, m.y);
+  body_post_block(it.b, m.y);
 }
 
 // Closes a step of every instance (one thread each).
