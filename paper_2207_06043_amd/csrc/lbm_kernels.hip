@@ -1373,11 +1373,12 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
   axis_weights(cen[1], bs[1], wy);
   axis_weights(cen[2], bs[2], wz);
   double A[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, bu[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  // The support loops run rolled: each marker block runs this code once per
+  // step on its CU, so its length costs instruction fetch (measured: the
+  // seven-fold unrolled loops took longer than their arithmetic).
   if (mk && fits) {
-#pragma unroll
-    for (int i = 0; i < 7; i++) {
-      const int k = sub + 4 * i;
-      if (k >= 27) break;
+#pragma unroll 1
+    for (int k = sub; k < 27; k += 4) {
       const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
       const int cx = bs[0] + kx - 1, cy = bs[1] + ky - 1, cz = bs[2] + kz - 1;
       const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
@@ -1426,33 +1427,37 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
 #pragma unroll
     for (int q = 0; q < 3; q++)
       F[q] = Ub[q] - (cc[0] * bu[q][0] + cc[1] * bu[q][1] + cc[2] * bu[q][2] + cc[3] * bu[q][3]);
+    if (fits) {
+#pragma unroll 1
+      for (int k = sub; k < 27; k += 4) {
+        const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        const int cx = bs[0] + kx - 1, cy = bs[1] + ky - 1, cz = bs[2] + kz - 1;
+        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+        const int c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
+        const double phi = sel3(kx, wx) * sel3(ky, wy) * sel3(kz, wz) * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
+        if (s_node[c] >= 0 && phi != 0.0) {
+          const double cp = area * phi;
 #pragma unroll
-    for (int i = 0; i < 7; i++) {
-      const int k = sub + 4 * i;
-      if (k >= 27) break;
-      const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
-      const int cx = bs[0] + kx - 1, cy = bs[1] + ky - 1, cz = bs[2] + kz - 1;
-      const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
-      long long node;
-      int c = 0;
-      bool ok;
-      if (fits) {
-        c = (cx - x0) + ex * ((cy - y0) + ey * (cz - z0));
-        node = s_node[c];
-        ok = node >= 0;
-      } else {
-        ok = support_node(G, a.ncls, cx, cy, cz, node);
-      }
-      const double phi = sel3(kx, wx) * sel3(ky, wy) * sel3(kz, wz) * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
-      if (ok && phi != 0.0) {
-        const double cp = area * phi;
-#pragma unroll
-        for (int q = 0; q < 3; q++) {
-          const long long v = fx_quant(cp * F[q], a.flags);
-          if (fits) atomicAdd((unsigned long long*)&s_acc[q][c], (unsigned long long)v);
-          else atomicAdd((unsigned long long*)(fxc + q * G.Np + node), (unsigned long long)v);
+          for (int q = 0; q < 3; q++)
+            atomicAdd((unsigned long long*)&s_acc[q][c], (unsigned long long)fx_quant(cp * F[q], a.flags));
         }
-        if (!fits) tfc[node >> TILE_SHIFT] = 1;
+      }
+    } else {
+#pragma unroll 1
+      for (int k = sub; k < 27; k += 4) {
+        const int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+        const int cx = bs[0] + kx - 1, cy = bs[1] + ky - 1, cz = bs[2] + kz - 1;
+        const double dx = cx - cen[0], dy = cy - cen[1], dz = cz - cen[2];
+        long long node;
+        const bool ok = support_node(G, a.ncls, cx, cy, cz, node);
+        const double phi = sel3(kx, wx) * sel3(ky, wy) * sel3(kz, wz) * (cc[0] + cc[1] * dx + cc[2] * dy + cc[3] * dz);
+        if (ok && phi != 0.0) {
+          const double cp = area * phi;
+#pragma unroll
+          for (int q = 0; q < 3; q++)
+            atomicAdd((unsigned long long*)(fxc + q * G.Np + node), (unsigned long long)fx_quant(cp * F[q], a.flags));
+          tfc[node >> TILE_SHIFT] = 1;
+        }
       }
     }
   }
