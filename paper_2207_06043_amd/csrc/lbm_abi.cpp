@@ -785,8 +785,12 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   // marker order: identity until k_bin_faces runs (below, and every
   // BIN_EVERY steps); sort space in global memory for bodies above the LDS
   // capacity of the binning kernel
-  std::vector<int32_t> ident(f0);
-  for (int f = 0; f < f0; f++) ident[f] = f;
+  std::vector<int32_t> ident(f0), slot_f(4 * (size_t)f0);
+  for (int f = 0; f < f0; f++) {
+    ident[f] = f;
+    for (int k = 0; k < 3; k++) slot_f[4 * (size_t)f + k] = faces[3 * (size_t)f + k];
+    slot_f[4 * (size_t)f + 3] = face_body[f];
+  }
   std::vector<long long> key0(nb, 0);
   long long nkeys = 0;
   for (int b = 0; b < nb; b++) {
@@ -799,6 +803,8 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
   long long* d_key0;
   unsigned long long* d_bkeys;
   CHK(up(&d_perm, ident));
+  int32_t* d_slotf;
+  CHK(up(&d_slotf, slot_f));
   CHK(up(&d_key0, key0));
   CHK(up(&d_bkeys, std::vector<unsigned long long>(std::max<long long>(nkeys, 1), 0ull)));
   int32_t *d_chs0, *d_chn, *d_bch0;
@@ -817,6 +823,7 @@ static lbm_status build_body_arrays(lbm_ctx* ctx, int cur, const std::vector<dou
     B.stage_node = d_snode;
   }
   B.perm = d_perm;
+  B.slot_f = d_slotf;
   B.b_key0 = d_key0;
   B.bin_keys = d_bkeys;
   B.centroid = d_cen;

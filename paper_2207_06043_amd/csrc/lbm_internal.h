@@ -138,14 +138,17 @@ struct BodyArgs {
   int n_marker_blocks, n_elem_blocks, n_diag_blocks;
   // Marker order: the marker blocks take the faces in slot order, slot s
   // holding face perm[s].  perm keeps each body's faces in its own slot
-  // range (that of its face indices), sorted by the Morton code of their
+  // range (that of its face indices), sorted by the Hilbert key of their
   // stencil bases (k_bin_faces), so that a block's 64 faces are neighbours
   // whatever order the caller gave.  Results do not depend on it.
+  // slot_f[s] = (the three vertex ids, body) of face perm[s], written with
+  // perm, so that a marker reaches its vertices in one load instead of two.
   // The marker blocks take chunks of at most 64 consecutive slots: block c
   // the slots chunk_s0[c] .. + chunk_n[c] (0 for an unused chunk); body b
   // owns chunks b_chunk0[b] .. b_chunk0[b + 1] - 1 (CHUNK_CAP chunks per
   // 64 faces), cut by k_bin_faces where the sorted faces jump apart.
   int* perm;                   // [nf]
+  int* slot_f;                 // [nf][4]
   int* chunk_s0;               // [n_marker_blocks]
   int* chunk_n;                // [n_marker_blocks]
   const int32_t* b_chunk0;     // [nbody + 1]

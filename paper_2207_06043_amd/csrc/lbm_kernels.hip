@@ -1294,12 +1294,12 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
   double cen[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0}, area = 0.0;
   int bs[3] = {0, 0, 0};
   if (mk) {
-    // three rounds of loads: the slot's face, its vertices and body, then
-    // everything that depends on them at once (positions, vertex
-    // velocities, rigid state; the unused of the last two are discarded)
-    const int fm = b.perm[m];
-    const int v0 = b.faces[3 * fm], v1 = b.faces[3 * fm + 1], v2 = b.faces[3 * fm + 2];
-    const int body = b.face_body[fm];
+    // two rounds of loads: the slot's vertex ids and body, then everything
+    // that depends on them at once (positions, vertex velocities, rigid
+    // state; the unused of the last two are discarded)
+    const int4 sf = *(const int4*)(b.slot_f + 4 * (long long)m);
+    const int v0 = sf.x, v1 = sf.y, v2 = sf.z;
+    const int body = sf.w;
     double pa[3], pb[3], pd[3], va[3], vb[3], vd[3], rs[12];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -1710,6 +1710,13 @@ __device__ __forceinline__ T block_scan(T v, T* s_tmp, T& total) {
 
 // Chunks of at most 64 consecutive slots, in order: nrun runs of 64 (the
 // last one shorter), the rest of the body's chunks unused.
+// Slot s takes face f: the permutation and the face's vertex ids and body.
+__device__ __forceinline__ void set_slot(const BodyArgs& b, int s, int f) {
+  b.perm[s] = f;
+  const int4 v = make_int4(b.faces[3 * f], b.faces[3 * f + 1], b.faces[3 * f + 2], b.face_body[f]);
+  *(int4*)(b.slot_f + 4 * (long long)s) = v;
+}
+
 __device__ __forceinline__ void fixed_chunks(const BodyArgs& b, int f0, int nf, int c0, int cap) {
   const int nrun = (nf + MARKERS_PER_BLOCK - 1) / MARKERS_PER_BLOCK;
   for (int c = threadIdx.x; c < cap; c += blockDim.x) {
@@ -1744,7 +1751,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_faces(BodyArgs b) {
     // large body: sorted in global memory, cut in runs of 64
     unsigned long long* K = b.bin_keys + b.b_key0[body];
     hilbert_sort(b, f0, nf, n2, mn, K);
-    for (int i = t; i < nf; i += blockDim.x) b.perm[f0 + i] = f0 + (int)(K[i] & 0xffffffffull);
+    for (int i = t; i < nf; i += blockDim.x) set_slot(b, f0 + i, f0 + (int)(K[i] & 0xffffffffull));
     fixed_chunks(b, f0, nf, c0, cap);
     return;
   }
@@ -1764,7 +1771,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_faces(BodyArgs b) {
       const int i = i0 + r;
       if (i >= nf) break;
       const unsigned long long key = s_keys[i];
-      b.perm[f0 + i] = f0 + (int)(key & 0xffffffffull);
+      set_slot(b, f0 + i, f0 + (int)(key & 0xffffffffull));
       int c[3];
       hilbert10_point((unsigned int)(key >> 32), c);
       const int d = max(abs(c[0] - prev[0]), max(abs(c[1] - prev[1]), abs(c[2] - prev[2])));
