@@ -131,7 +131,10 @@ typedef struct {
 
 /* Create a context on the current HIP device; work is enqueued on
  * hip_stream (a hipStream_t; NULL = the default stream).  Validates the
- * geometry (LBM_E_INVAL with a message on failure). */
+ * geometry (LBM_E_INVAL with a message on failure).  The kernels index
+ * nodes with 32-bit integers: a grid whose padded node count with one guard
+ * plane on each side, px ny (nz + 2) with px = nx rounded up to a multiple
+ * of 8, reaches 2^31 is refused with LBM_E_INVAL ("grid too large"). */
 lbm_status lbm_create(const lbm_desc *desc, void *hip_stream, lbm_ctx **out);
 lbm_status lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(const lbm_ctx *ctx);
