@@ -2,18 +2,24 @@
 // step (Coclite, de Tullio, Pascazio, Politi, arXiv 2207.06043, section
 // "Numerical method and computational procedure").
 //
-// One step is five launches on one stream:
-//   k_ib_force   MLS interpolation of the streamed (pre-force) velocity at the
-//                face centroids, direct forcing and spreading (fixed-point
-//                atomics, deterministic), clearing of the previous step's
-//                spread buffer;
-//   k_fluid      fused pull-stream + wall links (interpolated bounce-back) +
-//                Zou-He + moments + forced BGK collision; bulk tiles use
-//                128-bit SoA loads/stores, boundary nodes use compact records;
+// One coupled step is four launches on one stream (a step without bodies:
+// the fluid launch and k_close):
+//   k_ib_force   marker blocks: MLS interpolation of the streamed (pre-force)
+//                velocity at the face centroids, direct forcing and spreading
+//                (fixed-point atomics, deterministic); element blocks:
+//                stretching and bending forces; diagnostics blocks: volume,
+//                area, bounding box and damage check of the positions;
+//   k_fluid_all  (k_fluid_bulk and k_fluid_rec on two streams for large
+//                grids) fused pull-stream + wall links (interpolated
+//                bounce-back) + Zou-He + moments + forced BGK collision; bulk
+//                nodes as SoA loads/stores of V consecutive nodes (or one node
+//                per thread from a list), boundary nodes from compact records;
 //   k_mls_post   hydrodynamic probes (pressure and viscous stress from MLS
-//                fits at +-1.2 dx), repulsion, MLS velocity at the vertices;
-//   k_body_post  membrane forces and Verlet (soft) / Newton-Euler (rigid);
-//   k_diag       volume, area, bounding box, damage and the step bookkeeping.
+//                fits at +-1.2 dx), repulsion, MLS velocity at the vertices,
+//                clearing of the previous step's spread buffer;
+//   k_body_post  vertex forces and Verlet (soft) / Newton-Euler (rigid); its
+//                last block closes the step (with many bodies a k_close
+//                launch follows instead).
 // Populations are stored as deviations g_i = f_i - w_i from the rest
 // equilibrium; the collision is written for g (algebraically identical to the
 // BGK rule on f, with smaller rounding).
