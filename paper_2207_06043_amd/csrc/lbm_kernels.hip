@@ -1293,8 +1293,15 @@ __device__ void marker_block(const FluidArgs& a, const BodyArgs& b, int blk, lon
   __shared__ int s_box[6];
   const Grid& G = a.g;
   const int t = threadIdx.x, sub = t & 3;
+  const int nchunk = b.chunk_n[blk];
+  if (nchunk == 0) {
+    // an unused chunk: its box stays empty (the repulsion and the owner
+    // pass skip it), and nothing else is done
+    if (t < 6) b.chunk_box[6 * blk + t] = t < 3 ? INT_MAX : INT_MIN;
+    return;
+  }
   const int m = b.chunk_s0[blk] + (t >> 2);  // slot
-  const bool mk = (t >> 2) < b.chunk_n[blk];
+  const bool mk = (t >> 2) < nchunk;
   if (t < 6) s_box[t] = t < 3 ? INT_MAX : INT_MIN;
   __syncthreads();
   double cen[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0}, area = 0.0;
