@@ -232,9 +232,13 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
   // ones (24% faster than 2 per thread on the precision form); FP32 one
   // node per thread (the D = 96 pipe 3% faster than 4, the 256^3 box the same)
   ctx->bulk_v = large ? (d->precision == 0 ? 2 : (d->precision == 1 ? 1 : 2)) : (d->precision == 2 ? 0 : 1);
-  ctx->bulk_block = large ? (d->precision == 2 ? 128 : 256) : 64;
+  // small grids: 128-thread tiles in FP32 (the bifurcation with its capsule:
+  // 15.0 us per fluid launch against 15.6 with 64), 64-thread tiles in FP64
+  // (the pipe with a sphere: 9.1 against 9.7 us with 128), the list form in
+  // 64-thread blocks in FP16S
+  ctx->bulk_block = large ? (d->precision == 2 ? 128 : 256) : (d->precision == 1 ? 128 : 64);
   // small grids: one fluid launch (no fork/join between streams) with the
-  // record blocks in the same 64-thread shape as the bulk tiles
+  // record blocks in the same shape as the bulk tiles
   ctx->fluid_merged = !large;
   if (const char* ev = getenv("LBM_RECORD_BLOCK")) ctx->rec_block = atoi(ev);
   if (const char* ev = getenv("LBM_BULK_V")) ctx->bulk_v = atoi(ev);
