@@ -217,10 +217,10 @@ extern "C" lbm_status lbm_create(const lbm_desc* d, void* hip_stream, lbm_ctx** 
     long long* scr = nullptr;
     if (noalloc_scratch(ctx->device, &scr) != hipSuccess) return bad("device scratch not addressable");
   }
-  // launch shape (defaults; overridable for tuning)
-  // few non-solid nodes (cache-resident, latency-bound; or a sparse box,
-  // where big tiles would mostly cover solid nodes): one node per thread and
-  // 64-thread blocks; many (HBM-bound): 16-byte accesses per thread
+  // launch shape (defaults; overridable for tuning): few non-solid nodes
+  // (cache-resident, latency-bound; or a sparse box, where big tiles would
+  // mostly cover solid nodes): one merged launch, one node per thread (the
+  // list form in FP16S); many (HBM-bound): split launches, vector accesses
   long long n_open = 0;
   {
     const long long Nb = (long long)d->nx * d->ny * d->nz;
